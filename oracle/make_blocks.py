@@ -1,0 +1,69 @@
+"""Write the frozen block files of the truncated workloads (test infrastructure).
+
+Runs the oracle's infinite-system growth (float64, CPU) and stores the final
+blocks 1 and 4 under ``workloads/blocks/<name>.npz`` together with a JSON log
+of every growth step.  Calls nothing outside ``oracle/`` and ``workloads``.
+
+    python -m oracle.make_blocks --config 2
+    python -m oracle.make_blocks --config 5 --problems 0-7
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+import workloads as W
+
+from .blockio import save_block_pair
+from .dmrg import infinite_system
+from .local import Model
+
+
+def build(wl: W.Workload, tol=1e-10, verbose=True):
+    model = Model(wl.kind, wl.legs, t=wl.t, U=wl.U, J=wl.J)
+    t0 = time.time()
+
+    def log(info):
+        if verbose:
+            print(wl.name, {k: (float(f"{v:.12g}") if isinstance(v, float) else v)
+                            for k, v in info.items()}, f"{time.time() - t0:.1f}s", flush=True)
+
+    L, R, hist = infinite_system(model, wl.block_cols, wl.m, wl.target_of_sites, seed=0, tol=tol, log=log)
+    os.makedirs(W.BLOCK_DIR, exist_ok=True)
+    path = W.block_path(wl.name)
+    save_block_pair(path, L, R)
+    meta = {"name": wl.name, "block_cols": wl.block_cols, "m": wl.m, "dims": [L.dim, R.dim],
+            "sectors": [len(L.sectors()), len(R.sectors())], "hash": W.block_file_hash(wl.name),
+            "history": [{k: (float(v) if isinstance(v, (float, np.floating)) else v)
+                         for k, v in h.items()} for h in hist],
+            "seconds": time.time() - t0}
+    with open(path.replace(".npz", ".json"), "w") as f:
+        json.dump(meta, f, indent=1)
+    return meta
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--config", type=int, required=True)
+    ap.add_argument("--problems", default=None, help="config 5 only: a-b range")
+    ap.add_argument("--tol", type=float, default=1e-10)
+    args = ap.parse_args()
+    if args.config == 5:
+        probs = W.config5()
+        if args.problems:
+            a, b = (int(x) for x in args.problems.split("-"))
+            probs = probs[a:b + 1]
+        for wl in probs:
+            if os.path.exists(W.block_path(wl.name)):
+                continue
+            build(wl, tol=args.tol)
+    else:
+        print(build(W.CONFIGS[args.config], tol=args.tol))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,169 @@
+"""Seeded synthetic workloads shared by the oracle side and the HIP side.
+
+This module holds *no arithmetic of the method*: it names the workloads
+(model, lattice, kept states, target quantum numbers), draws seeded random
+vectors, and loads the frozen block files as raw arrays.  Both the oracle
+(``oracle/``) and the HIP binding read their inputs from here; neither
+imports the other.
+
+The paper's workloads are model Hamiltonians fixed by a few parameters; no
+dataset is involved.  The frozen block files under ``workloads/blocks`` are
+written once by ``oracle/make_blocks.py`` (infinite-system growth in float64
+on the CPU) and never by the HIP path.
+
+Block file layout (``numpy.savez``; ``P`` is ``"L_"`` or ``"R_"``):
+
+* ``P+kind``    int: 0 Heisenberg, 1 Hubbard;  ``P+legs``, ``P+ncols``,
+  ``P+side`` (0 left block, 1 right block); ``P+t``, ``P+U``, ``P+J``.
+* ``P+sec_qn``  int64 ``(nsec, 2)``: ``(n_up, n_dn)`` of each sector, ascending.
+* ``P+sec_dim`` int64 ``(nsec,)``.
+* ``P+H``       float64: block Hamiltonian, one dense column-major
+  ``d x d`` block per sector, in sector order.
+* ``P+op_key``  int64 ``(nops, 3)``: edge operator names,
+  ``(0, y, sigma)`` = annihilator c_{y,sigma} (Jordan-Wigner string over the
+  block's earlier modes folded in), ``(1, y, 0)`` = S^z_y,
+  ``(2, y, 0)`` = S^+_y.
+* ``P+op_blk``  int64 ``(nblk, 3)``: ``(op index, sector from, sector to)``.
+* ``P+op_off``  int64 ``(nblk,)``: offset of each block in ``P+op_data``.
+* ``P+op_data`` float64: dense column-major ``d_to x d_from`` blocks.
+"""
+from __future__ import annotations
+
+import hashlib
+import math
+import os
+from dataclasses import dataclass, field
+from typing import Callable
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+BLOCK_DIR = os.path.join(HERE, "blocks")
+
+KIND_HEISENBERG = 0
+KIND_HUBBARD = 1
+
+
+def _half_filling(legs):
+    def f(nsites):
+        return (nsites // 2, nsites // 2)
+    return f
+
+
+def _sz_zero(legs):
+    def f(nsites):
+        return (nsites // 2, 0)
+    return f
+
+
+def _doped_11_12(nsites):
+    """N = round-half-even(11/12 * sites), N_up = ceil(N/2)."""
+    N = int(round(11 * nsites / 12))          # Python's round is half-even
+    nup = (N + 1) // 2
+    return (nup, N - nup)
+
+
+@dataclass
+class Workload:
+    """One superblock problem: model, lattice, kept states, target sector."""
+
+    name: str
+    kind: str                 # "heisenberg" | "hubbard"
+    legs: int
+    length: int               # columns of the full lattice
+    m: int                    # states kept in blocks 1 and 4
+    t: float = 1.0
+    U: float = 0.0
+    J: float = 1.0
+    target_of_sites: Callable = field(default=None, repr=False)
+    seed: int = 0             # Lanczos start-vector seed
+    description: str = ""
+
+    @property
+    def block_cols(self) -> int:
+        return (self.length - 2) // 2
+
+    @property
+    def nsites(self) -> int:
+        return self.legs * self.length
+
+    @property
+    def target(self):
+        return self.target_of_sites(self.nsites)
+
+    @property
+    def kind_id(self) -> int:
+        return KIND_HUBBARD if self.kind == "hubbard" else KIND_HEISENBERG
+
+    @property
+    def column_dim(self) -> int:
+        return (4 if self.kind == "hubbard" else 2) ** self.legs
+
+
+def _config5_problems():
+    """64 uneven superblocks: one default_rng(5) stream, drawn problem by problem."""
+    rng = np.random.default_rng(5)
+    out = []
+    for i in range(64):
+        legs = int(rng.choice([2, 3]))
+        kind = str(rng.choice(["hubbard", "heisenberg"]))
+        m = int(rng.choice([64, 128, 256, 512]))
+        U = float(rng.uniform(2.0, 10.0)) if kind == "hubbard" else 0.0
+        tgt = _half_filling(legs) if kind == "hubbard" else _sz_zero(legs)
+        out.append(Workload(f"batch{i:02d}_{kind}_{legs}x{CONFIG5_LENGTH}_m{m}", kind, legs,
+                            CONFIG5_LENGTH, m, t=1.0, U=U, J=1.0, target_of_sites=tgt,
+                            seed=100 + i))
+    return out
+
+
+CONFIG5_LENGTH = 10
+
+CONFIGS = {
+    1: Workload("heisenberg_2x6_m16", "heisenberg", 2, 6, 16, J=1.0, target_of_sites=_sz_zero(2),
+                description="2-leg Heisenberg ladder 2x6, exact blocks of two rungs (m=16), "
+                            "columns of dim 4, superblock dim 4096"),
+    2: Workload("hubbard_2x16_U8_m256", "hubbard", 2, 16, 256, t=1.0, U=8.0,
+                target_of_sites=_half_filling(2),
+                description="2-leg Hubbard ladder 2x16, t=1, U=8, half filling, m=256"),
+    3: Workload("hubbard_3x12_U4_N33_m400", "hubbard", 3, 12, 400, t=1.0, U=4.0,
+                target_of_sites=_doped_11_12,
+                description="3-leg Hubbard ladder 3x12, t=1, U=4, 33 electrons (17 up, 16 down), m=400"),
+    4: Workload("heisenberg_4x16_m1000", "heisenberg", 4, 16, 1000, J=1.0,
+                target_of_sites=_sz_zero(4),
+                description="4-leg Heisenberg ladder 4x16, J=1, S_z=0, m=1000"),
+}
+
+
+def config5():
+    return _config5_problems()
+
+
+def block_path(name: str) -> str:
+    return os.path.join(BLOCK_DIR, f"{name}.npz")
+
+
+def load_blocks(name: str):
+    """Raw arrays of a frozen block file: ``{"L": {...}, "R": {...}}``."""
+    with np.load(block_path(name), allow_pickle=False) as z:
+        out = {"L": {}, "R": {}}
+        for k in z.files:
+            side, key = k[0], k[2:]
+            out[side][key] = z[k]
+    return out
+
+
+def block_file_hash(name: str) -> str:
+    h = hashlib.sha256()
+    with open(block_path(name), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def random_vector(n: int, seed: int) -> np.ndarray:
+    """Seeded N(0,1) vector (the start vectors and the Hv test vectors)."""
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+def unit_vector(n: int, seed: int) -> np.ndarray:
+    v = random_vector(n, seed)
+    return v / math.sqrt(float(v @ v))
