@@ -1,0 +1,284 @@
+/*
+ * d2d.h -- C ABI of libd2d, the MI355X (gfx950) superblock Hamiltonian-vector
+ * product of the direct two-dimensional DMRG and the Lanczos ground-state
+ * solve built on it.
+ *
+ * The method (Yamada, Okumura, Machida, "Direct Extension of DMRG toward
+ * 2-Dimensional Quantum Lattice Systems"): a superblock of four blocks, left
+ * to right block 1 (m states, index i1), column 2 (n states, i2), column 3
+ * (n states, i3) and block 4 (m states, i4), Fig. 2.  Its Hamiltonian splits
+ * as in Eq. (1) into H_l on (i1,i2), H_r on (i3,i4) and H_c on (i2,i3).  The
+ * superblock vector, reshaped into the matrix V with row (i2-1)m+i1 and
+ * column (i3-1)m+i4, turns Hv into H_l V + V H_r^T + (central term), the
+ * matrix form given right after Eq. (1).  The central term is applied as
+ * sum_k A_k V B_k^T with A_k acting on column 2 and B_k on column 3 (the same
+ * operator as the paper's H_c V_c).  Every term is split into quantum-number
+ * sectors: (N_up, N_dn) for the Hubbard model, N_up (i.e. S_z) for the
+ * Heisenberg model.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns a d2d_status; nothing aborts or throws across the ABI.
+ *   d2d_last_error() returns a thread-local message for the last failure.
+ * - "host" pointers are read during the call only and copied when kept.
+ *   "device" pointers must point to memory of the context's device; they are
+ *   borrowed for the duration of the call and work is ordered on the
+ *   context's stream.  The library keeps no caller pointer after a return.
+ * - Every *_create has a matching *_destroy owned by the caller.  Objects may
+ *   be destroyed in any order except that a context must outlive everything
+ *   made from it; d2d_ctx_destroy() with live children returns D2D_ESTATE and
+ *   destroys nothing.
+ * - Quantum numbers are int64 pairs (n_up, n_dn); for the Heisenberg model
+ *   n_dn is 0 and n_up counts up spins.
+ *
+ * Packed superblock-vector layout (used by d2d_hv, d2d_lanczos, ...)
+ * -----------------------------------------------------------------
+ * For a target total quantum number Q the vector is block sparse: nonzero only
+ * where q(i1)+q(i2) = q_L and q(i3)+q(i4) = Q - q_L.  The packed vector lists
+ * the sector pairs in ascending q_L (lexicographic (n_up, n_dn)), each pair as
+ * a dense d_L x d_R column-major block.  Rows are the left-half states with
+ * quantum number q_L in ascending i2*m + i1 (i2 slow, i1 fast); columns are the
+ * right-half states with Q - q_L in ascending i3*m + i4 (i3 slow, i4 fast).
+ * This is the paper's element ((i2-1)m+i1, (i3-1)m+i4) of V restricted to the
+ * sector.  Block states are ordered by quantum number (each sector a
+ * contiguous range), column states by their occupation bits.
+ */
+#ifndef D2D_H
+#define D2D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int d2d_status;
+#define D2D_OK       0
+#define D2D_EINVAL  -1   /* bad argument (null, size, NaN input, empty target)  */
+#define D2D_ENOMEM  -2   /* device allocation failed or context memory cap hit */
+#define D2D_EDEVICE -3   /* HIP runtime error                                  */
+#define D2D_ENOCONV -4   /* Lanczos did not reach the tolerance                */
+#define D2D_ESTATE  -5   /* object in the wrong state (live children, ...)     */
+
+/* Precision of one Hv.  Inputs v: double / float / bfloat16 (uint16 bits);
+ * output w: double for D2D_FP64, float otherwise.  Products accumulate in the
+ * output precision (FP32 accumulation for BF16 inputs). */
+#define D2D_FP64 0
+#define D2D_FP32 1
+#define D2D_BF16 2
+
+#define D2D_HEISENBERG 0
+#define D2D_HUBBARD    1
+
+typedef struct d2d_ctx d2d_ctx;
+typedef struct d2d_block d2d_block;
+typedef struct d2d_sb d2d_sb;
+typedef struct d2d_batch d2d_batch;
+
+/* Model of the ladder.  Hubbard: -t on every nearest-neighbour bond, +U n_up
+ * n_dn on every site.  Heisenberg: J (S^z S^z + (S^+S^- + S^-S^+)/2) on every
+ * bond (J_z = J_xy, as in the paper's spin model).  legs = sites per column. */
+typedef struct {
+    int kind;          /* D2D_HEISENBERG or D2D_HUBBARD */
+    int legs;          /* 1..4 for Hubbard (column dim 4^legs), 1..8 Heisenberg */
+    double t, U, J;
+} d2d_model;
+
+/* Last error message of the calling thread ("" if none). */
+const char* d2d_last_error(void);
+
+/* Version string of the library. */
+const char* d2d_version(void);
+
+/* ------------------------------------------------------------------ context
+ * device     HIP device ordinal.
+ * hip_stream hipStream_t to order all work on (NULL = the null stream).
+ * mem_cap    upper bound in bytes on what the context allocates (0 = none);
+ *            an allocation beyond it fails with D2D_ENOMEM. */
+d2d_status d2d_ctx_create(int device, void* hip_stream, size_t mem_cap, d2d_ctx** out);
+d2d_status d2d_ctx_destroy(d2d_ctx* ctx);
+/* Bytes currently allocated by the context. */
+d2d_status d2d_ctx_bytes(const d2d_ctx* ctx, size_t* bytes);
+
+/* ------------------------------------------------------------------- blocks
+ * A block (Fig. 1a: block 1 or block 4) of m states, all host FP64 arrays,
+ * copied by d2d_block_import.  Layout:
+ *   sec_qn[2*nsec], sec_dim[nsec]: sectors in ascending (n_up, n_dn).
+ *   H: block Hamiltonian, per sector one dense column-major d x d block.
+ *   op_key[3*nops]: edge-column operators that enter bonds with the next
+ *     column: (0, y, sigma) annihilator c_{y,sigma} with the Jordan-Wigner
+ *     string over the block's own earlier modes folded in (mode order: columns
+ *     left to right, inside a column leg by leg, up before down);
+ *     (1, y, 0) S^z_y; (2, y, 0) S^+_y.
+ *   op_blk[3*nblk] = (op index, sector from, sector to), op_off[nblk] offsets
+ *     into op_data of dense column-major d_to x d_from blocks.
+ *   side: 0 = left block (block 1, edge = rightmost column), 1 = right block
+ *     (block 4, edge = leftmost column). */
+typedef struct {
+    int side;
+    int ncols;
+    int nsec;
+    const int64_t* sec_qn;
+    const int64_t* sec_dim;
+    const double* H;
+    int nops;
+    const int64_t* op_key;
+    int nblk;
+    const int64_t* op_blk;
+    const int64_t* op_off;
+    const double* op_data;
+    int64_t op_data_len;   /* number of doubles in op_data (bounds check) */
+} d2d_block_desc;
+
+d2d_status d2d_block_import(d2d_ctx* ctx, const d2d_model* model, const d2d_block_desc* desc,
+                            d2d_block** out);
+/* Exact block of ncols columns grown by Kronecker products (Fig. 1a), no
+ * truncation: m = (column dim)^ncols.  side as in d2d_block_desc. */
+d2d_status d2d_block_exact(d2d_ctx* ctx, const d2d_model* model, int ncols, int side,
+                           d2d_block** out);
+/* Number of states and sectors of a block. */
+d2d_status d2d_block_dims(const d2d_block* b, int* m, int* nsec);
+/* Copy a block out in the d2d_block_desc layout.  Caller buffers; pass the
+ * sizes it has (nsec, H length, nblk, op_data length) in *_cap.  With
+ * H == NULL only the sizes are written (size query). */
+d2d_status d2d_block_export(const d2d_block* b, int64_t* sec_qn, int64_t* sec_dim, double* H,
+                            int64_t* op_key, int64_t* op_blk, int64_t* op_off, double* op_data,
+                            int64_t sizes[5] /* out: nsec, H len, nops, nblk, op_data len */);
+d2d_status d2d_block_destroy(d2d_block* b);
+
+/* --------------------------------------------------------------- superblock
+ * Superblock block1 (x) column (x) column (x) block4 restricted to the target
+ * quantum number target_q[2] (Eq. (1)).  Both blocks must be of the model
+ * given and of equal size m (the index maps of the paper assume it).  The
+ * superblock copies what it needs; the blocks may be destroyed afterwards.
+ * prec_mask: bit (1<<D2D_FP64 | 1<<D2D_FP32 | 1<<D2D_BF16) of the precisions
+ * whose operator copies are kept on the device.  Fails with D2D_EINVAL when
+ * the target space is empty. */
+d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d_block* b4,
+                         const d2d_model* model, const int64_t target_q[2], unsigned prec_mask,
+                         d2d_sb** out);
+d2d_status d2d_sb_destroy(d2d_sb* sb);
+
+typedef struct {
+    int64_t n;              /* packed vector length N_sb                         */
+    int32_t npairs;         /* sector pairs                                      */
+    int32_t m, ncol;        /* block and column dimension                        */
+    int32_t nterms;         /* central terms K                                   */
+    int32_t max_dl, max_dr; /* largest sector dimensions                        */
+    double flops_exec;      /* dense-sector flops of one Hv: sum 2dL^2dR+2dLdR^2 */
+    double flops_nnz;       /* same with the nonzeros of H_l, H_r sectors        */
+    double flops_central;   /* 2 x nonzero central gathers                       */
+    double bytes_min_fp64;  /* minimal HBM bytes of one FP64 Hv                  */
+    double bytes_min_fp32;  /* same, FP32 operators and vectors                  */
+    double bytes_min_bf16;  /* same, BF16 operators and inputs, FP32 output      */
+    int64_t op_entries;     /* sum dL^2 + sum dR^2                               */
+} d2d_sb_info_t;
+
+d2d_status d2d_sb_info(const d2d_sb* sb, d2d_sb_info_t* info);
+/* Sector table in packed order: qL[2*npairs], dL[npairs], dR[npairs],
+ * offset[npairs] (host buffers of npairs entries). */
+d2d_status d2d_sb_sectors(const d2d_sb* sb, int64_t* qL, int64_t* dL, int64_t* dR, int64_t* offset);
+
+/* --------------------------------------------------------------------- Hv
+ * w = H v in the packed layout, on the context stream, asynchronous.
+ * prec D2D_FP64: v, w double.  D2D_FP32: v float, w float.  D2D_BF16: v
+ * bfloat16 (uint16 storage), w float.  v and w must not overlap. */
+d2d_status d2d_hv(d2d_sb* sb, int prec, const void* v, void* w);
+
+/* Kernel timing of Hv: runs `reps` products w = H v back to back on the
+ * context stream with HIP events between the launches and returns the average
+ * duration in milliseconds of the grouped-GEMM launch (ms_gemm) and of the
+ * central-term launch (ms_central).  Synchronous. */
+d2d_status d2d_hv_profile(d2d_sb* sb, int prec, const void* v, void* w, int reps, double* ms_gemm,
+                          double* ms_central);
+
+/* Number of Hv launches the superblock has issued per precision (counters). */
+d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[3]);
+
+/* Tile shape of the grouped-GEMM launch used for one precision: index into
+ * the library's table of tile shapes (see d2d_tile_shapes), or -1 to let the
+ * library choose by problem size.  Returns D2D_EINVAL for an index out of
+ * range or a shape not built for that precision. */
+d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile);
+/* Number of tile shapes and, if desc != NULL, for each shape i: desc[4*i..] =
+ * (precision, BM, BN, BK). */
+d2d_status d2d_tile_shapes(int* count, int* desc);
+
+/* ------------------------------------------------------------------ Lanczos
+ * Ground state of the superblock in its target sector by FP64
+ * residual-corrected restarted Lanczos:
+ *   restart j: w = H_64 x_j, theta_j = x_j.w, r = w - theta_j x_j,
+ *   rho_j = |r|; stop if converged; else an inner Lanczos started from x_j
+ *   (alpha_0 = theta_j, beta_1 = rho_j, q_1 = r/rho_j) runs k_in - 1 more
+ *   steps with Hv in precision prec_j, full reorthogonalisation (classical
+ *   Gram-Schmidt twice, FP64), the tridiagonal lowest eigenpair on the
+ *   device, and x_{j+1} = Q y.
+ * All recurrences, dot products, the tridiagonal solve and the Ritz vector
+ * are FP64 on the device; the host reads (theta_j, rho_j) once per restart.
+ * Precision schedule: start in opts.prec; if rho_{j+1} > escalate * rho_j the
+ * precision is raised (BF16 -> FP32 -> FP64).
+ * Convergence: rho_j <= tol_res * |theta_j|.
+ * v0: device FP64 start vector of length n (required, need not be normalised).
+ * energy: host out, the last theta.  psi: device out (nullable), the unit
+ * Ritz vector.  Returns D2D_ENOCONV (with energy/psi/stats filled) when
+ * max_restarts is reached. */
+typedef struct {
+    int prec;            /* Hv precision of the inner steps                    */
+    int k_in;            /* Krylov dimension per restart (2..128)              */
+    int max_restarts;
+    double tol_res;      /* relative residual |r|/|theta|                      */
+    double escalate;     /* precision raise threshold on rho_{j+1}/rho_j        */
+    int use_graph;       /* capture the inner loop in a hipGraph and replay it */
+} d2d_lanczos_opts;
+
+#define D2D_LOG_MAX 256
+typedef struct {
+    int restarts;
+    int64_t hv_count[3];      /* Hv applications per precision                 */
+    double residual;          /* last rho                                      */
+    double seconds;           /* wall time of the call                         */
+    int nlog;                 /* entries in the per-restart log                */
+    double log_t[D2D_LOG_MAX];      /* seconds since the call started           */
+    double log_theta[D2D_LOG_MAX];
+    double log_rho[D2D_LOG_MAX];
+    int log_prec[D2D_LOG_MAX];      /* precision used after this restart        */
+} d2d_lanczos_stats;
+
+d2d_status d2d_lanczos(d2d_sb* sb, const d2d_lanczos_opts* opts, const double* v0, double* energy,
+                       double* psi, d2d_lanczos_stats* stats);
+
+/* ----------------------------------------------------------- density matrix
+ * Reduced density matrix of one half of the packed state psi (device, FP64,
+ * unit norm): side 0 -> rho_L[q_L] = V[q] V[q]^T (block 1 (x) column 2),
+ * side 1 -> rho_R[q_R] = V[q]^T V[q] (column 3 (x) block 4); the paper's
+ * density-matrix formation.  Each sector is diagonalised (density-matrix
+ * diagonalisation) and the m_keep eigenvectors of largest weight are kept
+ * (ties: sector ascending, index ascending); the enlarged half's operators are
+ * projected onto them, giving the block of the next, one column longer,
+ * superblock.  trunc_err (host out) = 1 - kept weight.  spectrum (host,
+ * nullable) receives all eigenvalues in descending order; spectrum_len (in:
+ * capacity, out: count). */
+d2d_status d2d_density_matrix(d2d_sb* sb, const double* psi, int side, int m_keep,
+                              d2d_block** new_block, double* trunc_err, double* spectrum,
+                              int64_t* spectrum_len);
+
+/* -------------------------------------------------------------------- batch
+ * Many independent superblocks advanced together: one grouped launch per
+ * Lanczos step covers every sector tile of every problem.  The superblocks
+ * are borrowed and must outlive the batch. */
+d2d_status d2d_batch_create(d2d_ctx* ctx, d2d_sb* const* sbs, int n, d2d_batch** out);
+d2d_status d2d_batch_destroy(d2d_batch* b);
+/* One batched Hv: v[i], w[i] device pointers of problem i (precision prec). */
+d2d_status d2d_batch_hv(d2d_batch* b, int prec, const void* const* v, void* const* w);
+/* Batched restarted Lanczos; v0[i] device start vectors; energies host out
+ * [n]; psi[i] device out (nullable array or entries); per_problem (nullable)
+ * stats [n].  Converged problems leave the launch at the next restart. */
+d2d_status d2d_batch_lanczos(d2d_batch* b, const d2d_lanczos_opts* opts, const double* const* v0,
+                             double* energies, double* const* psi, d2d_lanczos_stats* per_problem);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* D2D_H */

@@ -1,0 +1,80 @@
+"""Reference ground energies of the frozen workloads (test infrastructure).
+
+For each workload: load the frozen blocks, build the superblock of Eq. (1)
+with the oracle, and find its lowest eigenvalue in the target sector to about
+1e-13 relative:
+
+* small targets (N <= 2e6): the oracle Lanczos with full reorthogonalisation,
+  checked against ARPACK (``eigsh``, tol=0) on the same operator;
+* large targets: ARPACK on the mode-F product, tol=0.
+
+Writes ``tests/golden/reference_energies.json`` (merging with what is there).
+Calls only ``oracle/`` and ``workloads``.
+
+    python -m oracle.make_reference --config 1 2
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+import workloads as W
+
+from .blockio import block_from_arrays
+from .lanczos import ground_state, ground_state_arpack
+from .lattice import lattice_hamiltonian
+from .superblock import Superblock
+
+GOLDEN = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden",
+                      "reference_energies.json")
+
+
+def superblock_of(wl: W.Workload) -> Superblock:
+    raw = W.load_blocks(wl.name)
+    return Superblock(block_from_arrays(raw["L"]), block_from_arrays(raw["R"]), wl.target)
+
+
+def reference(wl: W.Workload, ncv=32):
+    t0 = time.time()
+    sb = superblock_of(wl)
+    rec = {"name": wl.name, "target": list(wl.target), "N": int(sb.N), "npairs": len(sb.sectors),
+           "block_hash": W.block_file_hash(wl.name)}
+    v0 = W.random_vector(sb.N, wl.seed)
+    if sb.N <= 2_000_000:
+        e1, x1, i1 = ground_state(sb.hv_factored, sb.N, v0=v0, tol=1e-15, max_iter=1500)
+        e2, x2, i2 = ground_state_arpack(sb.hv_factored, sb.N, v0=v0, ncv=ncv)
+        rec.update(E0=float(e2), E0_lanczos=float(e1), lanczos_iters=i1["iterations"],
+                   residual=float(i2["residual"]), agree=float(abs(e1 - e2)))
+    else:
+        e2, x2, i2 = ground_state_arpack(sb.hv_factored, sb.N, v0=v0, ncv=ncv)
+        rec.update(E0=float(e2), residual=float(i2["residual"]))
+    if wl.nsites <= 16 and wl.kind == "heisenberg":
+        H, _ = lattice_hamiltonian(sb.model, wl.length, wl.target)
+        rec["E0_lattice_ed"] = float(np.linalg.eigvalsh(H.toarray())[0]) if H.shape[0] <= 6000 else None
+    rec["seconds"] = time.time() - t0
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--config", type=int, nargs="+", required=True)
+    args = ap.parse_args()
+    data = {}
+    if os.path.exists(GOLDEN):
+        with open(GOLDEN) as f:
+            data = json.load(f)
+    for c in args.config:
+        wl = W.CONFIGS[c]
+        rec = reference(wl)
+        print(rec, flush=True)
+        data[wl.name] = rec
+        with open(GOLDEN, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main()

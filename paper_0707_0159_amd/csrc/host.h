@@ -1,0 +1,127 @@
+// Host-side objects of libd2d (not part of the ABI).
+#pragma once
+
+#include <map>
+#include <memory>
+#include <utility>
+
+#include "internal.h"
+
+namespace d2d {
+
+typedef std::pair<int64_t, int64_t> QN;
+
+// Dense column-major FP64 matrix on the host.
+struct Mat {
+    int rows = 0, cols = 0;
+    std::vector<double> a;
+    Mat() = default;
+    Mat(int r, int c) : rows(r), cols(c), a((size_t)r * c, 0.0) {}
+    double& operator()(int i, int j) { return a[(size_t)j * rows + i]; }
+    double operator()(int i, int j) const { return a[(size_t)j * rows + i]; }
+};
+
+Mat mat_transpose(const Mat& x);
+Mat mat_mul(const Mat& x, const Mat& y);
+Mat mat_add(const Mat& x, const Mat& y, double cy = 1.0);
+Mat mat_kron(const Mat& slow, const Mat& fast);
+Mat mat_identity(int n);
+Mat mat_scale_rows(const Mat& x, const std::vector<double>& d);   // diag(d) x
+Mat mat_scale_cols(const Mat& x, const std::vector<double>& d);   // x diag(d)
+
+// Operator name: (kind, leg, spin); kind 0 annihilator, 1 S^z, 2 S^+.
+typedef std::array<int64_t, 3> OpKey;
+
+// One column (rung of `legs` sites) in the occupation basis.
+struct Column {
+    int n = 0;
+    std::vector<QN> qn;
+    std::vector<double> parity;
+    Mat H;
+    std::vector<OpKey> keys;
+    std::vector<Mat> ops;
+    const Mat& op(const OpKey& k) const;
+};
+Column make_column(const d2d_model& m);
+
+// A bond term coef * (A on the part whose modes come first) (x) (B on the other).
+struct BondTerm {
+    double coef;
+    Mat A, B;
+};
+// Leg bonds between part X (earlier modes; ops_x, parity px) and part Y.
+std::vector<BondTerm> bond_terms(const d2d_model& model, const std::vector<OpKey>& keys_x,
+                                 const std::vector<Mat>& ops_x, const std::vector<double>& px,
+                                 const std::vector<OpKey>& keys_y, const std::vector<Mat>& ops_y);
+std::vector<OpKey> edge_keys(const d2d_model& model);
+
+}  // namespace d2d
+
+struct d2d_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t mem_cap = 0;
+    size_t bytes = 0;
+    int children = 0;
+    d2d_status alloc(void** p, size_t bytes);
+    void free(void* p, size_t bytes);
+};
+
+struct d2d_block {
+    d2d_ctx* ctx = nullptr;
+    d2d_model model{};
+    int side = 0, ncols = 0, m = 0;
+    std::vector<d2d::QN> qn;           // per state, sorted
+    std::vector<d2d::QN> sec_qn;
+    std::vector<int64_t> sec_dim, sec_start;
+    d2d::Mat H;
+    std::vector<d2d::OpKey> keys;
+    std::vector<d2d::Mat> ops;
+    std::vector<double> parity() const;
+};
+
+struct LanczosWork;
+
+struct d2d_sb {
+    d2d_ctx* ctx = nullptr;
+    d2d_model model{};
+    int m = 0, n = 0;
+    int64_t Q[2] = {0, 0};
+    unsigned prec_mask = 0;
+    // sector pairs
+    std::vector<d2d::QN> pair_q;
+    std::vector<d2d::SectorDev> pairs;
+    std::vector<std::vector<int32_t>> rowsL, colsR;   // half indices per pair
+    int64_t N = 0, Drows = 0, Dcols = 0;
+    int max_dl = 0, max_dr = 0;
+    int64_t hl_len = 0, hr_len = 0;
+    double flops_exec = 0, flops_nnz = 0, flops_central = 0;
+    // device tables
+    d2d::SectorDev* d_sec = nullptr;
+    void* HL[3] = {nullptr, nullptr, nullptr};
+    void* HR[3] = {nullptr, nullptr, nullptr};
+    int K = 0;
+    int32_t* d_src = nullptr;
+    int32_t* d_rmap = nullptr;
+    int32_t* d_cmap = nullptr;
+    double* d_rcoef64 = nullptr;
+    double* d_ccoef64 = nullptr;
+    float* d_rcoef32 = nullptr;
+    float* d_ccoef32 = nullptr;
+    int64_t max_elems = 0;
+    // work lists per tile shape
+    std::map<int, std::pair<d2d::WorkItem*, int>> work;
+    int tile_sel[3] = {-1, -1, -1};
+    int64_t hv_count[3] = {0, 0, 0};
+    LanczosWork* lz = nullptr;          // owned; freed by free_lanczos
+    ~d2d_sb();
+};
+
+namespace d2d {
+d2d_status sb_hv(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s);
+d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s, hipEvent_t mid);
+int sb_auto_tile(const d2d_sb* sb, int prec);
+d2d_status sb_work(d2d_sb* sb, int shape, WorkItem** w, int* nwork);
+void free_lanczos(d2d_sb* sb);
+}  // namespace d2d

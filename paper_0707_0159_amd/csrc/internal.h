@@ -1,0 +1,158 @@
+// Internal declarations of libd2d (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "d2d.h"
+
+namespace d2d {
+
+void set_error(const char* fmt, ...);
+
+#define D2D_HIP(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            d2d::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),       \
+                           __FILE__, __LINE__);                                         \
+            return D2D_EDEVICE;                                                         \
+        }                                                                               \
+    } while (0)
+
+#define D2D_CHECK(st)                          \
+    do {                                       \
+        d2d_status s_ = (st);                  \
+        if (s_ != D2D_OK) return s_;           \
+    } while (0)
+
+typedef uint16_t bf16_t;   // bfloat16 bits
+
+// ---------------------------------------------------------------- device tables
+// One sector pair (q_L, Q - q_L) of the packed vector.
+struct SectorDev {
+    int32_t dL, dR;
+    int64_t off;        // packed offset of the d_L x d_R block
+    int64_t hl_off;     // offset of H_l[q_L] (d_L x d_L, column-major)
+    int64_t hr_off;     // offset of H_r[Q - q_L] (d_R x d_R)
+    int64_t row_base;   // first global row slot of this pair
+    int64_t col_base;   // first global column slot
+};
+
+// One output tile of the grouped GEMM: pair, tile row, tile column.
+struct WorkItem {
+    int32_t p, tm, tn, cost;
+};
+
+// Tile shapes built into the library.
+struct TileShape {
+    int prec, BM, BN, BK;
+};
+int tile_shape_count();
+const TileShape& tile_shape(int i);
+
+// ---------------------------------------------------------------- launchers
+// Grouped GEMM W = H_l V + V H_r^T over a work list.  Returns false on a bad
+// shape index.  problem tables are device pointers.
+struct HvGemmArgs {
+    const WorkItem* work;
+    int nwork;
+    const SectorDev* sec;
+    const void* HL;
+    const void* HR;
+    const void* V;
+    void* W;
+};
+hipError_t launch_hv_gemm(int shape, const HvGemmArgs& a, hipStream_t s);
+
+// Central term W += sum_k c_k a_k V b_k^T by gather tables.
+struct CentralArgs {
+    const SectorDev* sec;
+    int npairs;
+    int K;
+    int max_elems;             // largest d_L*d_R
+    const int32_t* src;        // [npairs*K] source pair or -1
+    const int32_t* rmap;       // [K*Drows]
+    const int32_t* cmap;       // [K*Dcols]
+    const void* rcoef;         // [K*Drows] (double for FP64, float otherwise)
+    const void* ccoef;         // [K*Dcols]
+    int64_t Drows, Dcols;
+    const void* V;
+    void* W;
+};
+hipError_t launch_central(int prec, const CentralArgs& a, hipStream_t s);
+
+// Assembly of dense half Hamiltonian sectors on the device:
+// out[s](r,c) = d(a,a') F0(b,b') + S0(a,a') d(b,b') + sum_t coef_t S_t(a,a') F_t(b,b')
+// with half index h = a*m + b (a: column state, b: block state).
+struct AssembleArgs {
+    int nsec;
+    const int64_t* rows_off;   // [nsec+1] into rows
+    const int32_t* rows;       // half indices
+    const int64_t* out_off;    // [nsec]
+    int m, n, T;
+    const double* F0;          // m x m
+    const double* S0;          // n x n
+    const double* S;           // T x n x n
+    const double* F;           // T x m x m
+    const double* coef;        // T
+    double* out;
+    int64_t max_d2;
+    int transpose;             // 1: store the transposed block
+};
+hipError_t launch_assemble(const AssembleArgs& a, hipStream_t s);
+
+hipError_t launch_cast_f64_f32(const double* x, float* y, int64_t n, hipStream_t s);
+hipError_t launch_cast_f64_bf16(const double* x, bf16_t* y, int64_t n, hipStream_t s);
+hipError_t launch_cast_f32_bf16(const float* x, bf16_t* y, int64_t n, hipStream_t s);
+hipError_t launch_check_finite(const void* x, int prec, int64_t n, int* flag, hipStream_t s);
+
+// ---------------------------------------------------------------- Lanczos kernels
+int lz_nblocks(int64_t n);
+// partial[j*NB + b] = sum over block b of Q[j][e]*w[e], j < nq; if Tw is float the
+// FP32 input is upcast and written to w64 as well.
+hipError_t launch_dots_f64(const double* Q, int64_t ldq, int nq, const double* w, int64_t n,
+                           double* partial, hipStream_t s);
+hipError_t launch_upcast_dots(const double* Q, int64_t ldq, int nq, const float* w32, double* w64,
+                              int64_t n, double* partial, hipStream_t s);
+// out[j] = sum_b partial[j*NB + b]
+hipError_t launch_reduce(const double* partial, int nq, int nb, double* out, hipStream_t s);
+// w -= sum_j c[j] Q[j]; if partial != null: partial sums of |w|^2 (one vector).
+hipError_t launch_update(const double* Q, int64_t ldq, int nq, const double* c, double* w, int64_t n,
+                         double* partial_norm, hipStream_t s);
+// scal ops (single thread)
+hipError_t launch_step_scalars(int i, const double* c1, const double* c2, const double* nrm2,
+                               double* alpha, double* beta, double* flags, hipStream_t s);
+// Qnext = w / beta[i+1]; lo = cast(Qnext) in prec (FP32 or BF16; none for FP64)
+hipError_t launch_scale_store(const double* w, const double* beta_ip1, double* qnext, void* lo,
+                              int lo_prec, int64_t n, hipStream_t s);
+// x = sum_j y[j] Q[j]; partial |x|^2
+hipError_t launch_ritz(const double* Q, int64_t ldq, int k, const double* y, double* x, int64_t n,
+                       double* partial_norm, hipStream_t s);
+// x *= 1/sqrt(nrm2[0])
+hipError_t launch_normalize(double* x, const double* nrm2, int64_t n, hipStream_t s);
+// r = w - theta x (theta = dots[0]), in place in w; partial |r|^2
+hipError_t launch_residual(const double* x, const double* theta, double* w, int64_t n,
+                           double* partial_norm, hipStream_t s);
+// lowest eigenpair of the k x k tridiagonal (alpha[0..k-1], beta[1..k-1])
+hipError_t launch_tridiag(const double* alpha, const double* beta, int k, double* theta,
+                          double* y, double* work, hipStream_t s);
+// res[0] = theta, res[1] = sqrt(nrm2), alpha[0] = theta, beta[1] = sqrt(nrm2)
+hipError_t launch_restart_scalars(const double* theta, const double* nrm2, double* alpha, double* beta,
+                                  double* res, hipStream_t s);
+hipError_t launch_copy_f64(const double* x, double* y, int64_t n, hipStream_t s);
+// y = x / |x| with |x|^2 in nrm2 (device scalar)
+hipError_t launch_scale_copy(const double* x, const double* nrm2, double* y, int64_t n, hipStream_t s);
+
+// density matrix: rho = V V^T (side 0) or V^T V (side 1) of a dL x dR block
+hipError_t launch_syrk_f64(const double* V, int dL, int dR, int side, double* rho, hipStream_t s);
+// out (rows x k) = A (rows x rows, col-major) * B (rows x k)
+hipError_t launch_gemm_nn_f64(const double* A, int lda, const double* B, int ldb, double* C, int ldc,
+                              int M, int N, int K, int transA, hipStream_t s);
+
+}  // namespace d2d

@@ -1,0 +1,373 @@
+// Superblock Hv kernels for gfx950 (CDNA4).
+//
+// W = H_l V + V H_r^T + sum_k c_k A_k V B_k^T, sector by sector (the matrix
+// form of Eq. (1) with V the reshaped superblock vector).  Per sector pair the
+// two products are dense GEMMs that share one output tile: the tile's
+// accumulator first runs the K-loop of H_l[q_L] V[q] (K = d_L), then the
+// K-loop of V[q] H_r[q_R]^T (K = d_R), so no atomics and no second pass over
+// W are needed.  All tiles of all sector pairs are one grouped launch driven by
+// a work list.  The central term is a signed gather from neighbouring sector
+// pairs (every A_k, B_k has at most one nonzero per row).
+#include "internal.h"
+
+namespace d2d {
+
+// ------------------------------------------------------------------ MFMA shapes
+// Operand layouts of the gfx950 matrix instructions used (wave64):
+//  16x16x4 (f64): lane l holds A[l%16][l/16], B[l/16][l%16]; result value v
+//                 of lane l is D[4*v+l/16][l%16] (checked on the device: the
+//                 four results of a lane are rows l/16, l/16+4, l/16+8, l/16+12).
+//  32x32x2 (f32): lane l holds A[l%32][l/32], B[l/32][l%32]; result value v
+//                 of lane l is D[8*(v/4)+4*(l/32)+v%4][l%32].
+// The kernels feed the MFMA "A" operand from the B tile and the "B" operand
+// from the A tile, i.e. they compute the transposed tile D = (A B)^T, so that a
+// lane's results run down a column of the column-major output (coalesced
+// stores).
+template <typename T>
+struct Mf;
+
+template <>
+struct Mf<double> {
+    static constexpr int MN = 16, MK = 4, NV = 4;
+    typedef double vec __attribute__((ext_vector_type(4)));
+    __device__ static inline vec op(double a, double b, vec c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int col_of(int lane, int v) { return 4 * v + (lane >> 4); }
+    static constexpr int PA_MOD = 32, PA_RES = 16;   // row stride = 16 (mod 32) doubles
+};
+
+template <>
+struct Mf<float> {
+    static constexpr int MN = 32, MK = 2, NV = 16;
+    typedef float vec __attribute__((ext_vector_type(16)));
+    __device__ static inline vec op(float a, float b, vec c) {
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int col_of(int lane, int v) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
+    static constexpr int PA_MOD = 64, PA_RES = 32;   // row stride = 32 (mod 64) floats
+};
+
+template <typename T, int BM, int BN, int BK, int WGM, int WGN>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+k_hv_gemm(const WorkItem* __restrict__ work, const SectorDev* __restrict__ sec,
+          const T* __restrict__ HL, const T* __restrict__ HRt, const T* __restrict__ V,
+          T* __restrict__ W) {
+    using M = Mf<T>;
+    constexpr int NT = 64 * WGM * WGN;
+    constexpr int WM = BM / WGM, WN = BN / WGN;
+    constexpr int FM = WM / M::MN, FN = WN / M::MN;
+    static_assert(FM >= 1 && FN >= 1 && WM % M::MN == 0 && WN % M::MN == 0, "wave tile");
+    static_assert(BK % M::MK == 0, "BK");
+    constexpr int EA = BK * BM / NT, EB = BK * BN / NT;
+    static_assert(EA * NT == BK * BM && EB * NT == BK * BN, "load split");
+    constexpr int PA = ((M::PA_RES - BM % M::PA_MOD) % M::PA_MOD + M::PA_MOD) % M::PA_MOD;
+    constexpr int PB = 1;
+    __shared__ T As[2][BK][BM + PA];
+    __shared__ T Bs[2][BN][BK + PB];
+
+    const WorkItem wi = work[blockIdx.x];
+    const SectorDev s = sec[wi.p];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave % WGM, wn = wave / WGM;
+    const int row0 = wi.tm * BM, col0 = wi.tn * BN;
+    const int dL = s.dL, dR = s.dR;
+
+    typename M::vec acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int v = 0; v < M::NV; ++v) acc[i][j][v] = T(0);
+
+    T ra[EA], rb[EB];
+#pragma unroll 1
+    for (int phase = 0; phase < 2; ++phase) {
+        // phase 0: A = H_l[q_L] (dL x dL), B = V (dL x dR), K = dL
+        // phase 1: A = V (dL x dR), B = H_r^T (dR x dR), K = dR
+        const T* A = phase == 0 ? HL + s.hl_off : V + s.off;
+        const T* B = phase == 0 ? V + s.off : HRt + s.hr_off;
+        const int64_t lda = dL;
+        const int64_t ldb = phase == 0 ? dL : dR;
+        const int K = phase == 0 ? dL : dR;
+
+        auto gload = [&](int k0) {
+#pragma unroll
+            for (int e = 0; e < EA; ++e) {
+                const int idx = t + NT * e, i = idx % BM, k = idx / BM;
+                const int r = row0 + i, kk = k0 + k;
+                ra[e] = (r < dL && kk < K) ? A[r + kk * lda] : T(0);
+            }
+#pragma unroll
+            for (int e = 0; e < EB; ++e) {
+                const int idx = t + NT * e, k = idx % BK, j = idx / BK;
+                const int c = col0 + j, kk = k0 + k;
+                rb[e] = (c < dR && kk < K) ? B[kk + c * ldb] : T(0);
+            }
+        };
+
+        gload(0);
+        int buf = 0;
+#pragma unroll 1
+        for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+            for (int e = 0; e < EA; ++e) {
+                const int idx = t + NT * e;
+                As[buf][idx / BM][idx % BM] = ra[e];
+            }
+#pragma unroll
+            for (int e = 0; e < EB; ++e) {
+                const int idx = t + NT * e;
+                Bs[buf][idx / BK][idx % BK] = rb[e];
+            }
+            __syncthreads();
+            if (k0 + BK < K) gload(k0 + BK);
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += M::MK) {
+                T a[FM], b[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+                    a[i] = As[buf][kk + lane / M::MN][wm * WM + i * M::MN + lane % M::MN];
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    b[j] = Bs[buf][wn * WN + j * M::MN + lane % M::MN][kk + lane / M::MN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) acc[i][j] = M::op(b[j], a[i], acc[i][j]);
+            }
+            buf ^= 1;
+        }
+        __syncthreads();
+    }
+
+    T* Wp = W + s.off;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+        const int r = row0 + wm * WM + i * M::MN + lane % M::MN;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+#pragma unroll
+            for (int v = 0; v < M::NV; ++v) {
+                const int c = col0 + wn * WN + j * M::MN + M::col_of(lane, v);
+                if (r < dL && c < dR) Wp[r + (int64_t)c * dL] = acc[i][j][v];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ tile table
+static const TileShape kShapes[] = {
+    {D2D_FP64, 32, 32, 16},    // 0: 4 waves of 16x16
+    {D2D_FP64, 64, 64, 16},    // 1: 4 waves of 32x32
+    {D2D_FP64, 128, 128, 16},  // 2: 4 waves of 64x64
+    {D2D_FP32, 32, 32, 16},    // 3: 1 wave of 32x32
+    {D2D_FP32, 64, 64, 16},    // 4: 4 waves of 32x32
+    {D2D_FP32, 128, 128, 16},  // 5: 4 waves of 64x64
+};
+
+int tile_shape_count() { return (int)(sizeof(kShapes) / sizeof(kShapes[0])); }
+const TileShape& tile_shape(int i) { return kShapes[i]; }
+
+hipError_t launch_hv_gemm(int shape, const HvGemmArgs& a, hipStream_t st) {
+    if (a.nwork <= 0) return hipSuccess;
+    dim3 grid(a.nwork);
+    switch (shape) {
+        case 0:
+            hipLaunchKernelGGL((k_hv_gemm<double, 32, 32, 16, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec,
+                               (const double*)a.HL, (const double*)a.HR, (const double*)a.V, (double*)a.W);
+            break;
+        case 1:
+            hipLaunchKernelGGL((k_hv_gemm<double, 64, 64, 16, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec,
+                               (const double*)a.HL, (const double*)a.HR, (const double*)a.V, (double*)a.W);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_hv_gemm<double, 128, 128, 16, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec,
+                               (const double*)a.HL, (const double*)a.HR, (const double*)a.V, (double*)a.W);
+            break;
+        case 3:
+            hipLaunchKernelGGL((k_hv_gemm<float, 32, 32, 16, 1, 1>), grid, dim3(64), 0, st, a.work, a.sec,
+                               (const float*)a.HL, (const float*)a.HR, (const float*)a.V, (float*)a.W);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_hv_gemm<float, 64, 64, 16, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec,
+                               (const float*)a.HL, (const float*)a.HR, (const float*)a.V, (float*)a.W);
+            break;
+        case 5:
+            hipLaunchKernelGGL((k_hv_gemm<float, 128, 128, 16, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec,
+                               (const float*)a.HL, (const float*)a.HR, (const float*)a.V, (float*)a.W);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ central term
+__device__ inline float bf16_to_f32(bf16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+template <typename TI>
+__device__ inline float load_as_float(const TI* p, int64_t i);
+template <>
+__device__ inline float load_as_float<float>(const float* p, int64_t i) { return p[i]; }
+template <>
+__device__ inline float load_as_float<bf16_t>(const bf16_t* p, int64_t i) { return bf16_to_f32(p[i]); }
+
+// One thread per output element of pair blockIdx.y: r fastest, so the
+// gathered source rows (same i1 run) are read coalesced.
+template <typename TI, typename TO, typename TC>
+__global__ void __launch_bounds__(256)
+k_central(const SectorDev* __restrict__ sec, int K, const int32_t* __restrict__ src,
+          const int32_t* __restrict__ rmap, const int32_t* __restrict__ cmap, const TC* __restrict__ rcoef,
+          const TC* __restrict__ ccoef, int64_t Drows, int64_t Dcols, const TI* __restrict__ V,
+          TO* __restrict__ W) {
+    const int p = blockIdx.y;
+    const SectorDev s = sec[p];
+    const int64_t n = (int64_t)s.dL * s.dR;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e % s.dL), c = (int)(e / s.dL);
+        TC acc = TC(0);
+        for (int k = 0; k < K; ++k) {
+            const int p2 = src[p * K + k];
+            if (p2 < 0) continue;
+            const int rm = rmap[k * Drows + s.row_base + r];
+            const int cm = cmap[k * Dcols + s.col_base + c];
+            if (rm < 0 || cm < 0) continue;
+            const SectorDev s2 = sec[p2];
+            TC x;
+            if constexpr (sizeof(TI) == sizeof(TC)) x = (TC)V[s2.off + rm + (int64_t)cm * s2.dL];
+            else x = (TC)load_as_float<TI>(V, s2.off + rm + (int64_t)cm * s2.dL);
+            acc += rcoef[k * Drows + s.row_base + r] * ccoef[k * Dcols + s.col_base + c] * x;
+        }
+        W[s.off + e] += (TO)acc;
+    }
+}
+
+hipError_t launch_central(int prec, const CentralArgs& a, hipStream_t st) {
+    if (a.K == 0 || a.npairs == 0) return hipSuccess;
+    int gx = (int)((a.max_elems + 255) / 256);
+    if (gx > 1024) gx = 1024;
+    if (gx < 1) gx = 1;
+    dim3 grid(gx, a.npairs);
+    if (prec == D2D_FP64)
+        hipLaunchKernelGGL((k_central<double, double, double>), grid, dim3(256), 0, st, a.sec, a.K, a.src, a.rmap,
+                           a.cmap, (const double*)a.rcoef, (const double*)a.ccoef, a.Drows, a.Dcols,
+                           (const double*)a.V, (double*)a.W);
+    else if (prec == D2D_FP32)
+        hipLaunchKernelGGL((k_central<float, float, float>), grid, dim3(256), 0, st, a.sec, a.K, a.src, a.rmap,
+                           a.cmap, (const float*)a.rcoef, (const float*)a.ccoef, a.Drows, a.Dcols,
+                           (const float*)a.V, (float*)a.W);
+    else
+        hipLaunchKernelGGL((k_central<bf16_t, float, float>), grid, dim3(256), 0, st, a.sec, a.K, a.src, a.rmap,
+                           a.cmap, (const float*)a.rcoef, (const float*)a.ccoef, a.Drows, a.Dcols,
+                           (const bf16_t*)a.V, (float*)a.W);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ assembly
+// transpose_out != 0 writes the transposed block (used for H_r^T).
+__global__ void __launch_bounds__(256)
+k_assemble(const int64_t* __restrict__ rows_off, const int32_t* __restrict__ rows,
+           const int64_t* __restrict__ out_off, int m, int n, int T, const double* __restrict__ F0,
+           const double* __restrict__ S0, const double* __restrict__ S, const double* __restrict__ F,
+           const double* __restrict__ coef, double* __restrict__ out, int transpose) {
+    const int sidx = blockIdx.y;
+    const int64_t r0 = rows_off[sidx];
+    const int d = (int)(rows_off[sidx + 1] - r0);
+    const int64_t dd = (int64_t)d * d;
+    const int64_t nn = (int64_t)n * n, mm = (int64_t)m * m;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < dd; e += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e % d), c = (int)(e / d);
+        const int hr = rows[r0 + (transpose ? c : r)], hc = rows[r0 + (transpose ? r : c)];
+        const int a = hr / m, b = hr % m, a2 = hc / m, b2 = hc % m;
+        double v = 0.0;
+        if (a == a2) v += F0[b + (int64_t)b2 * m];
+        if (b == b2) v += S0[a + (int64_t)a2 * n];
+        for (int tt = 0; tt < T; ++tt) {
+            const double sv = S[tt * nn + a + (int64_t)a2 * n];
+            if (sv != 0.0) v += coef[tt] * sv * F[tt * mm + b + (int64_t)b2 * m];
+        }
+        out[out_off[sidx] + e] = v;
+    }
+}
+
+hipError_t launch_assemble(const AssembleArgs& a, hipStream_t st) {
+    if (a.nsec == 0) return hipSuccess;
+    int gx = (int)((a.max_d2 + 255) / 256);
+    if (gx > 4096) gx = 4096;
+    if (gx < 1) gx = 1;
+    hipLaunchKernelGGL(k_assemble, dim3(gx, a.nsec), dim3(256), 0, st, a.rows_off, a.rows, a.out_off, a.m, a.n,
+                       a.T, a.F0, a.S0, a.S, a.F, a.coef, a.out, a.transpose);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ casts
+__device__ inline bf16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (bf16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (bf16_t)(u >> 16);
+}
+
+__global__ void k_cast_f64_f32(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (float)x[i];
+}
+__global__ void k_cast_f64_bf16(const double* __restrict__ x, bf16_t* __restrict__ y, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = f32_to_bf16_rne((float)x[i]);
+}
+__global__ void k_cast_f32_bf16(const float* __restrict__ x, bf16_t* __restrict__ y, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = f32_to_bf16_rne(x[i]);
+}
+
+static int grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_cast_f64_f32(const double* x, float* y, int64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cast_f64_f32, dim3(grid_for(n)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+hipError_t launch_cast_f64_bf16(const double* x, bf16_t* y, int64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cast_f64_bf16, dim3(grid_for(n)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+hipError_t launch_cast_f32_bf16(const float* x, bf16_t* y, int64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cast_f32_bf16, dim3(grid_for(n)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
+// flag[0] set to 1 if any element is NaN or Inf
+template <typename T>
+__global__ void k_check_finite(const T* __restrict__ x, int64_t n, int* flag) {
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float f;
+        if constexpr (sizeof(T) == 2) f = bf16_to_f32(x[i]);
+        else f = (float)x[i];
+        if constexpr (sizeof(T) == 8) { if (!isfinite((double)x[i])) bad = 1; }
+        else if (!isfinite(f)) bad = 1;
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+hipError_t launch_check_finite(const void* x, int prec, int64_t n, int* flag, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    int g = grid_for(n);
+    if (g > 1024) g = 1024;
+    if (prec == D2D_FP64) hipLaunchKernelGGL(k_check_finite<double>, dim3(g), dim3(256), 0, s, (const double*)x, n, flag);
+    else if (prec == D2D_FP32) hipLaunchKernelGGL(k_check_finite<float>, dim3(g), dim3(256), 0, s, (const float*)x, n, flag);
+    else hipLaunchKernelGGL(k_check_finite<bf16_t>, dim3(g), dim3(256), 0, s, (const bf16_t*)x, n, flag);
+    return hipGetLastError();
+}
+
+}  // namespace d2d

@@ -1,0 +1,554 @@
+// Superblock of the direct 2-D DMRG (Eq. (1)): sector enumeration, packed
+// layout, device assembly of the dense sector operators, central-term gather
+// tables, grouped-GEMM work lists and the Hv entry point.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "host.h"
+
+using namespace d2d;
+
+namespace {
+
+template <typename T>
+d2d_status upload(d2d_ctx* ctx, const std::vector<T>& h, T** d) {
+    *d = nullptr;
+    if (h.empty()) return D2D_OK;
+    D2D_CHECK(ctx->alloc((void**)d, h.size() * sizeof(T)));
+    hipError_t e = hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        ctx->free(*d, h.size() * sizeof(T));
+        *d = nullptr;
+        set_error("hipMemcpy H2D failed: %s", hipGetErrorString(e));
+        return D2D_EDEVICE;
+    }
+    return D2D_OK;
+}
+
+template <typename T>
+void release(d2d_ctx* ctx, T*& p, size_t count) {
+    if (p) ctx->free((void*)p, count * sizeof(T));
+    p = nullptr;
+}
+
+// Assemble one half (slow = column state a, fast = block state b) for every
+// pair's sector into dense blocks at out (+offsets), optionally transposed.
+d2d_status assemble_half(d2d_sb* sb, const d2d_block* blk, const Column& col, const std::vector<BondTerm>& terms,
+                         bool left, double* out) {
+    d2d_ctx* ctx = sb->ctx;
+    const int m = blk->m, n = col.n, T = (int)terms.size();
+    const auto& rows = left ? sb->rowsL : sb->colsR;
+    const int np = (int)rows.size();
+    std::vector<int64_t> rows_off(np + 1, 0), out_off(np);
+    std::vector<int32_t> rows_cat;
+    int64_t max_d2 = 0;
+    for (int p = 0; p < np; ++p) {
+        rows_off[p + 1] = rows_off[p] + (int64_t)rows[p].size();
+        out_off[p] = left ? sb->pairs[p].hl_off : sb->pairs[p].hr_off;
+        rows_cat.insert(rows_cat.end(), rows[p].begin(), rows[p].end());
+        max_d2 = std::max<int64_t>(max_d2, (int64_t)rows[p].size() * rows[p].size());
+    }
+    std::vector<double> S((size_t)T * n * n), F((size_t)T * m * m), coef(T);
+    for (int t = 0; t < T; ++t) {
+        // left: S_t = column factor B, F_t = block factor A; right: S_t = A (column), F_t = B (block)
+        const Mat& sm = left ? terms[t].B : terms[t].A;
+        const Mat& fm = left ? terms[t].A : terms[t].B;
+        std::copy(sm.a.begin(), sm.a.end(), S.begin() + (size_t)t * n * n);
+        std::copy(fm.a.begin(), fm.a.end(), F.begin() + (size_t)t * m * m);
+        coef[t] = terms[t].coef;
+    }
+    int64_t *d_rows_off = nullptr, *d_out_off = nullptr;
+    int32_t* d_rows = nullptr;
+    double *d_F0 = nullptr, *d_S0 = nullptr, *d_S = nullptr, *d_F = nullptr, *d_coef = nullptr;
+    d2d_status st = D2D_OK;
+    if ((st = upload(ctx, rows_off, &d_rows_off)) == D2D_OK && (st = upload(ctx, out_off, &d_out_off)) == D2D_OK &&
+        (st = upload(ctx, rows_cat, &d_rows)) == D2D_OK && (st = upload(ctx, blk->H.a, &d_F0)) == D2D_OK &&
+        (st = upload(ctx, col.H.a, &d_S0)) == D2D_OK && (st = upload(ctx, S, &d_S)) == D2D_OK &&
+        (st = upload(ctx, F, &d_F)) == D2D_OK && (st = upload(ctx, coef, &d_coef)) == D2D_OK) {
+        AssembleArgs a{np, d_rows_off, d_rows, d_out_off, m, n, T, d_F0, d_S0, d_S, d_F, d_coef, out, max_d2};
+        a.transpose = left ? 0 : 1;
+        hipError_t e = launch_assemble(a, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) {
+            set_error("operator assembly failed: %s", hipGetErrorString(e));
+            st = D2D_EDEVICE;
+        }
+    }
+    release(ctx, d_rows_off, rows_off.size());
+    release(ctx, d_out_off, out_off.size());
+    release(ctx, d_rows, rows_cat.size());
+    release(ctx, d_F0, blk->H.a.size());
+    release(ctx, d_S0, col.H.a.size());
+    release(ctx, d_S, S.size());
+    release(ctx, d_F, F.size());
+    release(ctx, d_coef, coef.size());
+    return st;
+}
+
+bool same_model(const d2d_model& a, const d2d_model& b) {
+    return a.kind == b.kind && a.legs == b.legs && a.t == b.t && a.U == b.U && a.J == b.J;
+}
+
+}  // namespace
+
+d2d_sb::~d2d_sb() {
+    free_lanczos(this);
+    if (!ctx) return;
+    const size_t np = pairs.size();
+    release(ctx, d_sec, np);
+    const size_t esz[3] = {8, 4, 2};
+    for (int p = 0; p < 3; ++p) {
+        if (HL[p]) ctx->free(HL[p], (size_t)hl_len * esz[p]);
+        if (HR[p]) ctx->free(HR[p], (size_t)hr_len * esz[p]);
+        HL[p] = HR[p] = nullptr;
+    }
+    release(ctx, d_src, np * K);
+    release(ctx, d_rmap, (size_t)K * Drows);
+    release(ctx, d_cmap, (size_t)K * Dcols);
+    release(ctx, d_rcoef64, (size_t)K * Drows);
+    release(ctx, d_ccoef64, (size_t)K * Dcols);
+    release(ctx, d_rcoef32, (size_t)K * Drows);
+    release(ctx, d_ccoef32, (size_t)K * Dcols);
+    for (auto& kv : work) {
+        WorkItem* w = kv.second.first;
+        release(ctx, w, (size_t)kv.second.second);
+    }
+    work.clear();
+}
+
+namespace d2d {
+
+int sb_auto_tile(const d2d_sb* sb, int prec) {
+    const int D = std::max(sb->max_dl, sb->max_dr);
+    if (prec == D2D_FP64) return D <= 64 ? 0 : (D <= 768 ? 1 : 2);
+    if (prec == D2D_FP32) return D <= 64 ? 3 : (D <= 768 ? 4 : 5);
+    return -1;
+}
+
+d2d_status sb_work(d2d_sb* sb, int shape, WorkItem** out, int* nwork) {
+    auto it = sb->work.find(shape);
+    if (it != sb->work.end()) {
+        *out = it->second.first;
+        *nwork = it->second.second;
+        return D2D_OK;
+    }
+    const TileShape& ts = tile_shape(shape);
+    std::vector<WorkItem> w;
+    for (size_t p = 0; p < sb->pairs.size(); ++p) {
+        const int dL = sb->pairs[p].dL, dR = sb->pairs[p].dR;
+        const int tm = (dL + ts.BM - 1) / ts.BM, tn = (dR + ts.BN - 1) / ts.BN;
+        for (int j = 0; j < tn; ++j)
+            for (int i = 0; i < tm; ++i) w.push_back({(int32_t)p, i, j, dL + dR});
+    }
+    // longest tiles first (their K-loops are d_L + d_R long)
+    std::stable_sort(w.begin(), w.end(), [](const WorkItem& a, const WorkItem& b) { return a.cost > b.cost; });
+    WorkItem* d = nullptr;
+    D2D_CHECK(upload(sb->ctx, w, &d));
+    sb->work[shape] = {d, (int)w.size()};
+    *out = d;
+    *nwork = (int)w.size();
+    return D2D_OK;
+}
+
+d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s, hipEvent_t mid) {
+    if (prec < 0 || prec > 2 || !(sb->prec_mask & (1u << prec)) || !sb->HL[prec]) {
+        set_error("precision %d not available on this superblock", prec);
+        return D2D_EINVAL;
+    }
+    if (prec == D2D_BF16) {
+        set_error("BF16 Hv kernels are not built in this library version");
+        return D2D_EINVAL;
+    }
+    const int shape = sb->tile_sel[prec] >= 0 ? sb->tile_sel[prec] : sb_auto_tile(sb, prec);
+    WorkItem* work = nullptr;
+    int nwork = 0;
+    D2D_CHECK(sb_work(sb, shape, &work, &nwork));
+    HvGemmArgs g{work, nwork, sb->d_sec, sb->HL[prec], sb->HR[prec], v, w};
+    D2D_HIP(launch_hv_gemm(shape, g, s));
+    if (mid) D2D_HIP(hipEventRecord(mid, s));
+    CentralArgs c{};
+    c.sec = sb->d_sec;
+    c.npairs = (int)sb->pairs.size();
+    c.K = sb->K;
+    c.max_elems = (int)std::min<int64_t>(sb->max_elems, 1 << 30);
+    c.src = sb->d_src;
+    c.rmap = sb->d_rmap;
+    c.cmap = sb->d_cmap;
+    c.rcoef = prec == D2D_FP64 ? (const void*)sb->d_rcoef64 : (const void*)sb->d_rcoef32;
+    c.ccoef = prec == D2D_FP64 ? (const void*)sb->d_ccoef64 : (const void*)sb->d_ccoef32;
+    c.Drows = sb->Drows;
+    c.Dcols = sb->Dcols;
+    c.V = v;
+    c.W = w;
+    D2D_HIP(launch_central(prec, c, s));
+    sb->hv_count[prec]++;
+    return D2D_OK;
+}
+
+d2d_status sb_hv(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s) {
+    return sb_hv_parts(sb, prec, v, w, s, nullptr);
+}
+
+}  // namespace d2d
+
+extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d_block* b4, const d2d_model* model,
+                                    const int64_t target_q[2], unsigned prec_mask, d2d_sb** out) {
+    if (!ctx || !b1 || !b4 || !model || !target_q || !out) {
+        set_error("d2d_sb_create: NULL argument");
+        return D2D_EINVAL;
+    }
+    *out = nullptr;
+    if (!same_model(b1->model, *model) || !same_model(b4->model, *model)) {
+        set_error("d2d_sb_create: blocks were built for a different model");
+        return D2D_EINVAL;
+    }
+    if (b1->side != 0 || b4->side != 1) {
+        set_error("d2d_sb_create: block 1 must be a left block and block 4 a right block");
+        return D2D_EINVAL;
+    }
+    if (b1->m != b4->m) {
+        set_error("d2d_sb_create: blocks 1 and 4 must have the same number of states (%d vs %d)", b1->m, b4->m);
+        return D2D_EINVAL;
+    }
+    if (prec_mask & ~7u) {
+        set_error("d2d_sb_create: unknown precision bits 0x%x", prec_mask);
+        return D2D_EINVAL;
+    }
+    prec_mask |= 1u << D2D_FP64;   // the FP64 operators are always kept (residuals, restarts)
+    D2D_HIP(hipSetDevice(ctx->device));
+    const Column col = make_column(*model);
+    const int m = b1->m, n = col.n;
+    const int64_t mn = (int64_t)m * n;
+    if (mn > (1ll << 30)) {
+        set_error("half dimension m*n = %lld too large", (long long)mn);
+        return D2D_EINVAL;
+    }
+    auto sb = std::make_unique<d2d_sb>();
+    sb->ctx = ctx;
+    sb->model = *model;
+    sb->m = m;
+    sb->n = n;
+    sb->Q[0] = target_q[0];
+    sb->Q[1] = target_q[1];
+    sb->prec_mask = prec_mask;
+    ctx->children++;   // undone by the destructor path below on failure
+    struct Guard {
+        std::unique_ptr<d2d_sb>* p;
+        d2d_ctx* c;
+        ~Guard() {
+            if (*p) c->children--;
+        }
+    } guard{&sb, ctx};
+
+    // a1: sectors of the two enlarged halves, half index = column state * m + block state
+    std::map<QN, std::vector<int32_t>> left, right;
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < m; ++b) {
+            left[{col.qn[a].first + b1->qn[b].first, col.qn[a].second + b1->qn[b].second}].push_back(a * m + b);
+            right[{col.qn[a].first + b4->qn[b].first, col.qn[a].second + b4->qn[b].second}].push_back(a * m + b);
+        }
+    std::map<QN, int> pair_of;
+    int64_t off = 0, hl = 0, hr = 0, rb = 0, cb = 0;
+    for (auto& kv : left) {
+        const QN qr{target_q[0] - kv.first.first, target_q[1] - kv.first.second};
+        auto it = right.find(qr);
+        if (it == right.end()) continue;
+        SectorDev s{};
+        s.dL = (int32_t)kv.second.size();
+        s.dR = (int32_t)it->second.size();
+        s.off = off;
+        s.hl_off = hl;
+        s.hr_off = hr;
+        s.row_base = rb;
+        s.col_base = cb;
+        off += (int64_t)s.dL * s.dR;
+        hl += (int64_t)s.dL * s.dL;
+        hr += (int64_t)s.dR * s.dR;
+        rb += s.dL;
+        cb += s.dR;
+        pair_of[kv.first] = (int)sb->pairs.size();
+        sb->pairs.push_back(s);
+        sb->pair_q.push_back(kv.first);
+        sb->rowsL.push_back(kv.second);
+        sb->colsR.push_back(it->second);
+        sb->max_dl = std::max(sb->max_dl, (int)s.dL);
+        sb->max_dr = std::max(sb->max_dr, (int)s.dR);
+        sb->max_elems = std::max<int64_t>(sb->max_elems, (int64_t)s.dL * s.dR);
+        sb->flops_exec += 2.0 * s.dL * (double)s.dL * s.dR + 2.0 * s.dL * (double)s.dR * s.dR;
+    }
+    if (sb->pairs.empty()) {
+        set_error("d2d_sb_create: the target sector (%lld,%lld) is empty", (long long)target_q[0],
+                  (long long)target_q[1]);
+        return D2D_EINVAL;
+    }
+    sb->N = off;
+    sb->hl_len = hl;
+    sb->hr_len = hr;
+    sb->Drows = rb;
+    sb->Dcols = cb;
+    D2D_CHECK(upload(ctx, sb->pairs, &sb->d_sec));
+
+    // a2: dense sector operators, FP64 master copies
+    D2D_CHECK(ctx->alloc(&sb->HL[D2D_FP64], (size_t)hl * 8));
+    D2D_CHECK(ctx->alloc(&sb->HR[D2D_FP64], (size_t)hr * 8));
+    const std::vector<BondTerm> tl = bond_terms(*model, b1->keys, b1->ops, b1->parity(), col.keys, col.ops);
+    const std::vector<BondTerm> tr = bond_terms(*model, col.keys, col.ops, col.parity, b4->keys, b4->ops);
+    D2D_CHECK(assemble_half(sb.get(), b1, col, tl, true, (double*)sb->HL[D2D_FP64]));
+    D2D_CHECK(assemble_half(sb.get(), b4, col, tr, false, (double*)sb->HR[D2D_FP64]));
+    // nonzero count of the sector operators (the method's sparse flop count)
+    {
+        std::vector<double> h(hl), r(hr);
+        D2D_HIP(hipMemcpy(h.data(), sb->HL[D2D_FP64], hl * 8, hipMemcpyDeviceToHost));
+        D2D_HIP(hipMemcpy(r.data(), sb->HR[D2D_FP64], hr * 8, hipMemcpyDeviceToHost));
+        for (size_t p = 0; p < sb->pairs.size(); ++p) {
+            const SectorDev& s = sb->pairs[p];
+            int64_t nl = 0, nr = 0;
+            for (int64_t i = 0; i < (int64_t)s.dL * s.dL; ++i) nl += h[s.hl_off + i] != 0.0;
+            for (int64_t i = 0; i < (int64_t)s.dR * s.dR; ++i) nr += r[s.hr_off + i] != 0.0;
+            sb->flops_nnz += 2.0 * nl * s.dR + 2.0 * nr * s.dL;
+        }
+    }
+    if (prec_mask & (1u << D2D_FP32)) {
+        D2D_CHECK(ctx->alloc(&sb->HL[D2D_FP32], (size_t)hl * 4));
+        D2D_CHECK(ctx->alloc(&sb->HR[D2D_FP32], (size_t)hr * 4));
+        D2D_HIP(launch_cast_f64_f32((const double*)sb->HL[0], (float*)sb->HL[1], hl, ctx->stream));
+        D2D_HIP(launch_cast_f64_f32((const double*)sb->HR[0], (float*)sb->HR[1], hr, ctx->stream));
+    }
+    if (prec_mask & (1u << D2D_BF16)) {
+        D2D_CHECK(ctx->alloc(&sb->HL[D2D_BF16], (size_t)hl * 2));
+        D2D_CHECK(ctx->alloc(&sb->HR[D2D_BF16], (size_t)hr * 2));
+        D2D_HIP(launch_cast_f64_bf16((const double*)sb->HL[0], (bf16_t*)sb->HL[2], hl, ctx->stream));
+        D2D_HIP(launch_cast_f64_bf16((const double*)sb->HR[0], (bf16_t*)sb->HR[2], hr, ctx->stream));
+    }
+
+    // a5: central bond terms sum_k c_k A_k (x) B_k, A_k on column 2, B_k on column 3
+    const std::vector<BondTerm> tc = bond_terms(*model, col.keys, col.ops, col.parity, col.keys, col.ops);
+    sb->K = (int)tc.size();
+    const int K = sb->K, np = (int)sb->pairs.size();
+    // position of every half index inside its sector
+    std::vector<int32_t> posL(mn, -1), posR(mn, -1);
+    for (auto& kv : left)
+        for (size_t i = 0; i < kv.second.size(); ++i) posL[kv.second[i]] = (int32_t)i;
+    for (auto& kv : right)
+        for (size_t i = 0; i < kv.second.size(); ++i) posR[kv.second[i]] = (int32_t)i;
+    std::vector<int32_t> src((size_t)np * K, -1), rmap((size_t)K * rb, -1), cmap((size_t)K * cb, -1);
+    std::vector<double> rc((size_t)K * rb, 0.0), cc((size_t)K * cb, 0.0);
+    int64_t gathers = 0;
+    for (int k = 0; k < K; ++k) {
+        const Mat& A = tc[k].A;
+        const Mat& B = tc[k].B;
+        std::vector<int> ra(n, -1), rbm(n, -1);
+        std::vector<double> av(n, 0.0), bv(n, 0.0);
+        QN dA{0, 0}, dB{0, 0};
+        bool seenA = false, seenB = false;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                if (A(i, j) != 0.0) {
+                    if (ra[i] >= 0) {
+                        set_error("central operator with two nonzeros in a row");
+                        return D2D_EINVAL;
+                    }
+                    ra[i] = j;
+                    av[i] = A(i, j);
+                    dA = {col.qn[i].first - col.qn[j].first, col.qn[i].second - col.qn[j].second};
+                    seenA = true;
+                }
+                if (B(i, j) != 0.0) {
+                    if (rbm[i] >= 0) {
+                        set_error("central operator with two nonzeros in a row");
+                        return D2D_EINVAL;
+                    }
+                    rbm[i] = j;
+                    bv[i] = B(i, j);
+                    dB = {col.qn[i].first - col.qn[j].first, col.qn[i].second - col.qn[j].second};
+                    seenB = true;
+                }
+            }
+        if (!seenA || !seenB) continue;
+        if (dA.first + dB.first != 0 || dA.second + dB.second != 0) {
+            set_error("central term does not conserve the quantum numbers");
+            return D2D_EINVAL;
+        }
+        for (int p = 0; p < np; ++p) {
+            const QN qs{sb->pair_q[p].first - dA.first, sb->pair_q[p].second - dA.second};
+            auto it = pair_of.find(qs);
+            if (it == pair_of.end()) continue;
+            const int p2 = it->second;
+            src[(size_t)p * K + k] = p2;
+            const SectorDev& s = sb->pairs[p];
+            int64_t nr = 0, nc = 0;
+            for (int r = 0; r < s.dL; ++r) {
+                const int h = sb->rowsL[p][r], a = h / m, b = h % m;
+                if (ra[a] < 0) continue;
+                const int32_t pos = posL[(int64_t)ra[a] * m + b];
+                rmap[(size_t)k * rb + s.row_base + r] = pos;
+                rc[(size_t)k * rb + s.row_base + r] = tc[k].coef * av[a];
+                ++nr;
+            }
+            for (int c = 0; c < s.dR; ++c) {
+                const int h = sb->colsR[p][c], a = h / m, b = h % m;
+                if (rbm[a] < 0) continue;
+                const int32_t pos = posR[(int64_t)rbm[a] * m + b];
+                cmap[(size_t)k * cb + s.col_base + c] = pos;
+                cc[(size_t)k * cb + s.col_base + c] = bv[a];
+                ++nc;
+            }
+            gathers += nr * nc;
+        }
+    }
+    sb->flops_central = 2.0 * (double)gathers;
+    std::vector<float> rc32(rc.begin(), rc.end()), cc32(cc.begin(), cc.end());
+    D2D_CHECK(upload(ctx, src, &sb->d_src));
+    D2D_CHECK(upload(ctx, rmap, &sb->d_rmap));
+    D2D_CHECK(upload(ctx, cmap, &sb->d_cmap));
+    D2D_CHECK(upload(ctx, rc, &sb->d_rcoef64));
+    D2D_CHECK(upload(ctx, cc, &sb->d_ccoef64));
+    D2D_CHECK(upload(ctx, rc32, &sb->d_rcoef32));
+    D2D_CHECK(upload(ctx, cc32, &sb->d_ccoef32));
+    D2D_HIP(hipStreamSynchronize(ctx->stream));
+    *out = sb.release();
+    return D2D_OK;
+}
+
+extern "C" d2d_status d2d_sb_destroy(d2d_sb* sb) {
+    if (!sb) return D2D_OK;
+    d2d_ctx* c = sb->ctx;
+    if (c) (void)hipStreamSynchronize(c->stream);
+    delete sb;
+    if (c) c->children--;
+    return D2D_OK;
+}
+
+extern "C" d2d_status d2d_sb_info(const d2d_sb* sb, d2d_sb_info_t* info) {
+    if (!sb || !info) {
+        set_error("d2d_sb_info: NULL argument");
+        return D2D_EINVAL;
+    }
+    std::memset(info, 0, sizeof(*info));
+    info->n = sb->N;
+    info->npairs = (int32_t)sb->pairs.size();
+    info->m = sb->m;
+    info->ncol = sb->n;
+    info->nterms = sb->K;
+    info->max_dl = sb->max_dl;
+    info->max_dr = sb->max_dr;
+    info->flops_exec = sb->flops_exec;
+    info->flops_nnz = sb->flops_nnz + sb->flops_central;
+    info->flops_central = sb->flops_central;
+    const double ops = (double)(sb->hl_len + sb->hr_len);
+    info->op_entries = sb->hl_len + sb->hr_len;
+    const double N = (double)sb->N;
+    info->bytes_min_fp64 = 3.0 * N * 8 + ops * 8;
+    info->bytes_min_fp32 = 3.0 * N * 4 + ops * 4;
+    info->bytes_min_bf16 = 2.0 * N * 2 + N * 4 + ops * 2;
+    return D2D_OK;
+}
+
+extern "C" d2d_status d2d_sb_sectors(const d2d_sb* sb, int64_t* qL, int64_t* dL, int64_t* dR, int64_t* offset) {
+    if (!sb || !qL || !dL || !dR || !offset) {
+        set_error("d2d_sb_sectors: NULL argument");
+        return D2D_EINVAL;
+    }
+    for (size_t p = 0; p < sb->pairs.size(); ++p) {
+        qL[2 * p] = sb->pair_q[p].first;
+        qL[2 * p + 1] = sb->pair_q[p].second;
+        dL[p] = sb->pairs[p].dL;
+        dR[p] = sb->pairs[p].dR;
+        offset[p] = sb->pairs[p].off;
+    }
+    return D2D_OK;
+}
+
+extern "C" d2d_status d2d_hv(d2d_sb* sb, int prec, const void* v, void* w) {
+    if (!sb || !v || !w) {
+        set_error("d2d_hv: NULL argument");
+        return D2D_EINVAL;
+    }
+    if (v == w) {
+        set_error("d2d_hv: v and w must not overlap");
+        return D2D_EINVAL;
+    }
+    return sb_hv(sb, prec, v, w, sb->ctx->stream);
+}
+
+extern "C" d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[3]) {
+    if (!sb || !counts) {
+        set_error("d2d_hv_count: NULL argument");
+        return D2D_EINVAL;
+    }
+    for (int i = 0; i < 3; ++i) counts[i] = sb->hv_count[i];
+    return D2D_OK;
+}
+
+extern "C" d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile) {
+    if (!sb || prec < 0 || prec > 2) {
+        set_error("d2d_sb_set_tile: bad argument");
+        return D2D_EINVAL;
+    }
+    if (tile >= tile_shape_count() || (tile >= 0 && tile_shape(tile).prec != prec)) {
+        set_error("d2d_sb_set_tile: tile %d is not a shape of precision %d", tile, prec);
+        return D2D_EINVAL;
+    }
+    sb->tile_sel[prec] = tile < 0 ? -1 : tile;
+    return D2D_OK;
+}
+
+extern "C" d2d_status d2d_tile_shapes(int* count, int* desc) {
+    if (!count) {
+        set_error("d2d_tile_shapes: NULL count");
+        return D2D_EINVAL;
+    }
+    *count = tile_shape_count();
+    if (desc)
+        for (int i = 0; i < *count; ++i) {
+            const TileShape& t = tile_shape(i);
+            desc[4 * i] = t.prec;
+            desc[4 * i + 1] = t.BM;
+            desc[4 * i + 2] = t.BN;
+            desc[4 * i + 3] = t.BK;
+        }
+    return D2D_OK;
+}
+
+extern "C" d2d_status d2d_hv_profile(d2d_sb* sb, int prec, const void* v, void* w, int reps, double* ms_gemm,
+                                     double* ms_central) {
+    if (!sb || !v || !w || !ms_gemm || !ms_central || reps < 1 || reps > 100000) {
+        set_error("d2d_hv_profile: bad argument");
+        return D2D_EINVAL;
+    }
+    hipStream_t s = sb->ctx->stream;
+    std::vector<hipEvent_t> ev(3 * (size_t)reps, nullptr);
+    d2d_status st = D2D_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            set_error("hipEventCreate failed");
+            st = D2D_EDEVICE;
+            break;
+        }
+    for (int r = 0; r < reps && st == D2D_OK; ++r) {
+        if (hipEventRecord(ev[3 * r], s) != hipSuccess) st = D2D_EDEVICE;
+        if (st == D2D_OK) st = sb_hv_parts(sb, prec, v, w, s, ev[3 * r + 1]);
+        if (st == D2D_OK && hipEventRecord(ev[3 * r + 2], s) != hipSuccess) st = D2D_EDEVICE;
+    }
+    double g = 0.0, c = 0.0;
+    if (st == D2D_OK && hipStreamSynchronize(s) != hipSuccess) st = D2D_EDEVICE;
+    for (int r = 0; r < reps && st == D2D_OK; ++r) {
+        float a = 0.f, b = 0.f;
+        if (hipEventElapsedTime(&a, ev[3 * r], ev[3 * r + 1]) != hipSuccess ||
+            hipEventElapsedTime(&b, ev[3 * r + 1], ev[3 * r + 2]) != hipSuccess) {
+            set_error("hipEventElapsedTime failed");
+            st = D2D_EDEVICE;
+            break;
+        }
+        g += a;
+        c += b;
+    }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (st != D2D_OK) return st;
+    *ms_gemm = g / reps;
+    *ms_central = c / reps;
+    return D2D_OK;
+}

@@ -1,0 +1,109 @@
+"""Hv parity: the HIP grouped-GEMM path against the oracle, element by element.
+
+Bars (agreement of w = Hv with the FP64 oracle, ||w - w_ref|| / ||w_ref||):
+FP64 <= 1e-12, FP32 <= 1e-5 (inputs rounded to FP32 once, FP32 accumulation).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from helpers import GpuProblem, oracle_superblock, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_0707_0159_amd import d2d
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    c = d2d.d2d_ctx_create(0)
+    yield c
+    torch.cuda.synchronize()
+    d2d.d2d_ctx_destroy(c)
+
+
+def gpu_hv(ctx, prob, prec, v):
+    from paper_0707_0159_amd import d2d
+    dt = torch.float64 if prec == d2d.D2D_FP64 else torch.float32
+    with torch.cuda.stream(ctx.stream):
+        vd = torch.as_tensor(v, dtype=dt).to("cuda")
+        wd = torch.full_like(vd, float("nan"))
+        d2d.d2d_hv(prob.sb, prec, vd, wd)
+    ctx.stream.synchronize()
+    return wd.double().cpu().numpy()
+
+
+def test_config1_all_sectors_fp64_and_fp32(ctx):
+    """2x6 Heisenberg, exact m=16 blocks, every S_z sector of the 4096 space."""
+    from paper_0707_0159_amd import d2d
+    wl = W.CONFIGS[1]
+    worst = {0: 0.0, 1: 0.0}
+    total = 0
+    for nup in range(0, 13):
+        osb = oracle_superblock(wl, (nup, 0))
+        prob = GpuProblem(ctx, wl, (nup, 0))
+        assert prob.info["n"] == osb.N
+        qL, dL, dR, off = d2d.d2d_sb_sectors(prob.sb)
+        assert [tuple(q) for q in qL] == [s[0] for s in osb.sectors]
+        assert list(off) == [s[3] for s in osb.sectors]
+        H = osb.explicit()
+        nvec = 1000 // 13 + 1
+        for i in range(nvec):
+            v = W.random_vector(osb.N, 1000 + total + i)
+            ref = H @ v
+            for prec in (0, 1):
+                worst[prec] = max(worst[prec], rel_err(gpu_hv(ctx, prob, prec, v), ref))
+        total += nvec
+        prob.close()
+    print("config1 worst rel err", worst)
+    assert worst[0] <= 1e-12
+    assert worst[1] <= 1e-5
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)])
+def test_config2_every_tile_shape(ctx, prec, tol):
+    """2x16 Hubbard m=256: 47 sector pairs of ragged size, every tile shape."""
+    from paper_0707_0159_amd import d2d
+    wl = W.CONFIGS[2]
+    osb = oracle_superblock(wl)
+    prob = GpuProblem(ctx, wl)
+    assert prob.info["n"] == osb.N
+    shapes = [i for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == prec]
+    for k in range(3):
+        v = W.random_vector(osb.N, 1000 + k)
+        ref = osb.hv_factored(v)
+        for sh in shapes:
+            d2d.d2d_sb_set_tile(prob.sb, prec, sh)
+            w = gpu_hv(ctx, prob, prec, v)
+            err = rel_err(w, ref)
+            print(f"prec {prec} shape {sh} vec {k}: rel err {err:.3e}")
+            assert np.all(np.isfinite(w))
+            assert err <= tol
+    prob.close()
+
+
+def test_sector_table_matches_oracle(ctx):
+    from paper_0707_0159_amd import d2d
+    wl = W.CONFIGS[2]
+    osb = oracle_superblock(wl)
+    prob = GpuProblem(ctx, wl)
+    qL, dL, dR, off = d2d.d2d_sb_sectors(prob.sb)
+    assert [tuple(q) for q in qL] == [s[0] for s in osb.sectors]
+    assert list(dL) == [s[1].size for s in osb.sectors]
+    assert list(dR) == [s[2].size for s in osb.sectors]
+    assert list(off) == [s[3] for s in osb.sectors]
+    prob.close()
+
+
+def test_repeatable_bitwise(ctx):
+    """No atomics in the accumulation: repeated products are bit-identical."""
+    wl = W.CONFIGS[2]
+    prob = GpuProblem(ctx, wl)
+    v = W.random_vector(prob.info["n"], 7)
+    for prec in (0, 1):
+        a = gpu_hv(ctx, prob, prec, v)
+        for _ in range(5):
+            assert np.array_equal(a, gpu_hv(ctx, prob, prec, v))
+    prob.close()
