@@ -88,6 +88,10 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile", choices=["hv", "copy"], default=None,
+                    help="profiling runs for rocprofv3: 'hv' = only Hv launches of --prec, "
+                         "'copy' = a plain device copy of known size (counter calibration)")
+    ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp32")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -99,6 +103,16 @@ def main():
 
     import workloads as W
     from paper_0707_0159_amd import d2d
+
+    if args.profile == "copy":
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": "copy", "bytes_read_per_launch": nbytes, "bytes_written_per_launch": nbytes}))
+        return
 
     wl = W.CONFIGS[args.config]
     ref_path = os.path.join(ROOT, "tests", "golden", "reference_energies.json")
@@ -120,6 +134,19 @@ def main():
         v0 = torch.as_tensor(W.random_vector(N, wl.seed), device="cuda")
         psi = torch.zeros_like(v0)
     s.synchronize()
+
+    if args.profile == "hv":
+        prec = d2d.D2D_FP32 if args.prec == "fp32" else d2d.D2D_FP64
+        with torch.cuda.stream(s):
+            x = torch.as_tensor(W.random_vector(N, 1000), device="cuda")
+            x = x.float() if prec == d2d.D2D_FP32 else x
+            w = torch.empty_like(x)
+        for _ in range(args.steps):
+            d2d.d2d_hv(sb, prec, x, w)
+        s.synchronize()
+        print(json.dumps({"profile": "hv", "prec": args.prec, "workload": wl.name, "launches": args.steps,
+                          "flops_exec": info["flops_exec"], "bytes_min": info["bytes_min_" + args.prec]}))
+        return
 
     def solve(prec):
         opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol, use_graph=1)
