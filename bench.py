@@ -130,6 +130,11 @@ def main():
     info = d2d.d2d_sb_info(sb)
     N = info["n"]
     s = ctx.stream
+    shapes = d2d.d2d_tile_shapes()
+    tuned = {}
+    for name, prec in (("fp64", d2d.D2D_FP64), ("fp32", d2d.D2D_FP32)):
+        t, ms_t = d2d.d2d_sb_autotune(sb, prec, reps=10)
+        tuned[name] = {"tile": t, "BMxBNxBK": "x".join(str(x) for x in shapes[t][1:]), "ms": ms_t}
     with torch.cuda.stream(s):
         v0 = torch.as_tensor(W.random_vector(N, wl.seed), device="cuda")
         psi = torch.zeros_like(v0)
@@ -212,7 +217,7 @@ def main():
     achieved = F / g32
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK["fp32"], "traffic": traffic_record(wl.name, "fp32"),
-                "kernel": "k_hv_gemm<float> (grouped GEMM H_l V + V H_r^T, FP32 MFMA 32x32x2)",
+                "kernel": f"k_hv_gemm<float,{tuned['fp32']['BMxBNxBK']}> (grouped GEMM H_l V + V H_r^T, FP32 MFMA 32x32x2)",
                 "flops_per_launch": F, "launch_ms": ms["fp32"]["gemm_ms"]}
 
     line = {
@@ -231,6 +236,7 @@ def main():
         "config": {"workload": wl.name, "description": wl.description, "N_sb": N,
                    "sector_pairs": info["npairs"], "m": info["m"], "column_dim": info["ncol"],
                    "central_terms": info["nterms"], "k_in": args.k_in, "tol_res": args.tol,
+                   "tiles": tuned,
                    "parallelism": "none (1 GPU)"},
         "time_to_energy": {
             "mixed_s": st_mixed["seconds"], "fp64_s": wall64,

@@ -201,6 +201,15 @@ d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[3]);
  * library choose by problem size.  Returns D2D_EINVAL for an index out of
  * range or a shape not built for that precision. */
 d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile);
+/* Autotuner: times every grouped-GEMM tile shape of precision prec on this
+ * superblock (reps launches each, on internal scratch vectors, HIP events on
+ * the context stream), selects the fastest for later d2d_hv / d2d_lanczos
+ * calls and returns its index and average milliseconds.  If the environment
+ * variable D2D_TUNE_CACHE names a file, results are looked up there first
+ * (key: precision and the list of sector dimensions) and appended after a
+ * measurement.  Synchronous. */
+d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_tile, double* best_ms);
+
 /* Number of tile shapes and, if desc != NULL, for each shape i: desc[4*i..] =
  * (precision, BM, BN, BK). */
 d2d_status d2d_tile_shapes(int* count, int* desc);

@@ -110,6 +110,8 @@ struct d2d_sb {
     float* d_rcoef32 = nullptr;
     float* d_ccoef32 = nullptr;
     int64_t max_elems = 0;
+    int4* d_cblocks = nullptr;         // central-term launch table
+    int n_cblocks = 0;
     // work lists per tile shape
     std::map<int, std::pair<d2d::WorkItem*, int>> work;
     int tile_sel[3] = {-1, -1, -1};

@@ -67,15 +67,24 @@ struct HvGemmArgs {
     const void* HR;
     const void* V;
     void* W;
+    // central term, fused into the GEMM epilogue
+    int K;
+    const int32_t* src;
+    const int32_t* rmap;
+    const int32_t* cmap;
+    const void* rcoef;     // element type of the precision (double / float)
+    const void* ccoef;
+    int64_t Drows, Dcols;
 };
 hipError_t launch_hv_gemm(int shape, const HvGemmArgs& a, hipStream_t s);
 
 // Central term W += sum_k c_k a_k V b_k^T by gather tables.
 struct CentralArgs {
+    const int4* blocks;        // [nblocks] (pair, 64-row tile, 8-column tile, 0)
+    int nblocks;
     const SectorDev* sec;
     int npairs;
     int K;
-    int max_elems;             // largest d_L*d_R
     const int32_t* src;        // [npairs*K] source pair or -1
     const int32_t* rmap;       // [K*Drows]
     const int32_t* cmap;       // [K*Dcols]
@@ -110,6 +119,7 @@ hipError_t launch_assemble(const AssembleArgs& a, hipStream_t s);
 hipError_t launch_cast_f64_f32(const double* x, float* y, int64_t n, hipStream_t s);
 hipError_t launch_cast_f64_bf16(const double* x, bf16_t* y, int64_t n, hipStream_t s);
 hipError_t launch_cast_f32_bf16(const float* x, bf16_t* y, int64_t n, hipStream_t s);
+hipError_t launch_fill(void* x, int prec, int64_t n, double v, hipStream_t s);
 hipError_t launch_check_finite(const void* x, int prec, int64_t n, int* flag, hipStream_t s);
 
 // ---------------------------------------------------------------- Lanczos kernels
@@ -148,6 +158,33 @@ hipError_t launch_restart_scalars(const double* theta, const double* nrm2, doubl
 hipError_t launch_copy_f64(const double* x, double* y, int64_t n, hipStream_t s);
 // y = x / |x| with |x|^2 in nrm2 (device scalar)
 hipError_t launch_scale_copy(const double* x, const double* nrm2, double* y, int64_t n, hipStream_t s);
+
+// Fused Lanczos step i (nq = i+1 <= 32 basis vectors), three kernels:
+// c1 = Q^T w (w upcast from w32 first if upcast), w -= Q c1, c2 = Q^T w,
+// alpha[i] = c1[i] + c2[i], beta[i+1] = sqrt(|w|^2 - |c2|^2), and if
+// qnext != null: qnext = (w - [need2] Q c2) / beta[i+1], lo = cast(qnext).
+struct LzStepArgs {
+    const double* Q;
+    int64_t n;
+    int nq, i;
+    bool upcast;
+    const float* w32;
+    double* w;
+    double* partial;     // two partial-sum buffers of (33 x 256) doubles
+    double* partial2;
+    double *alpha, *beta;
+    double* qnext;
+    void* lo;
+    int lo_prec;
+};
+int lz_step_blocks(int64_t n);
+hipError_t launch_lz_step(const LzStepArgs& a, hipStream_t s);
+// theta = x.w, w -= theta x, rho = |w|; alpha[0] = theta, beta[1] = rho, res[0..1] = (theta, rho)
+hipError_t launch_lz_residual(const double* x, double* w, int64_t n, double* partial, double* partial2,
+                              double* alpha, double* beta, double* res, hipStream_t s);
+// x = Q y / |Q y|
+hipError_t launch_lz_ritz(const double* Q, int64_t ldq, int k, const double* y, double* x, int64_t n,
+                          double* partial, hipStream_t s);
 
 // density matrix: rho = V V^T (side 0) or V^T V (side 1) of a dL x dR block
 hipError_t launch_syrk_f64(const double* V, int dL, int dR, int side, double* rho, hipStream_t s);

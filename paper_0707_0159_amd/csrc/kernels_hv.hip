@@ -48,12 +48,36 @@ struct Mf<float> {
     static constexpr int PA_MOD = 64, PA_RES = 32;   // row stride = 32 (mod 64) floats
 };
 
+// Kernel arguments (by value).  Central term: for output row r (column c) of
+// pair p and bond term k, rmap/cmap give the row (column) of the source pair
+// src[p*K+k] or -1, rcoef/ccoef the signed coefficients.
+template <typename T>
+struct HvK {
+    const WorkItem* work;
+    const SectorDev* sec;
+    const T* HL;
+    const T* HRt;
+    const T* V;
+    T* W;
+    int K;
+    const int32_t* src;
+    const int32_t* rmap;
+    const int32_t* cmap;
+    const T* rcoef;
+    const T* ccoef;
+    int64_t Drows, Dcols;
+};
+
 template <typename T, int BM, int BN, int BK, int WGM, int WGN>
 __global__ void __launch_bounds__(64 * WGM * WGN)
-k_hv_gemm(const WorkItem* __restrict__ work, const SectorDev* __restrict__ sec,
-          const T* __restrict__ HL, const T* __restrict__ HRt, const T* __restrict__ V,
-          T* __restrict__ W) {
+k_hv_gemm(const HvK<T> g) {
     using M = Mf<T>;
+    const WorkItem* __restrict__ work = g.work;
+    const SectorDev* __restrict__ sec = g.sec;
+    const T* __restrict__ HL = g.HL;
+    const T* __restrict__ HRt = g.HRt;
+    const T* __restrict__ V = g.V;
+    T* __restrict__ W = g.W;
     constexpr int NT = 64 * WGM * WGN;
     constexpr int WM = BM / WGM, WN = BN / WGN;
     constexpr int FM = WM / M::MN, FN = WN / M::MN;
@@ -165,38 +189,84 @@ static const TileShape kShapes[] = {
     {D2D_FP32, 32, 32, 16},    // 3: 1 wave of 32x32
     {D2D_FP32, 64, 64, 16},    // 4: 4 waves of 32x32
     {D2D_FP32, 128, 128, 16},  // 5: 4 waves of 64x64
+    {D2D_FP64, 64, 64, 32},    // 6: 4 waves of 32x32, deeper K step
+    {D2D_FP32, 64, 64, 32},    // 7
+    {D2D_FP32, 128, 128, 32},  // 8
+    {D2D_FP64, 128, 64, 16},   // 9: 4 waves of 64x32
+    {D2D_FP32, 128, 64, 16},   // 10: 4 waves of 64x32
+    {D2D_FP32, 64, 64, 64},    // 11: long K step for small, latency-bound sectors
+    {D2D_FP64, 32, 32, 32},    // 12
+    {D2D_FP64, 64, 64, 64},    // 13
 };
 
 int tile_shape_count() { return (int)(sizeof(kShapes) / sizeof(kShapes[0])); }
 const TileShape& tile_shape(int i) { return kShapes[i]; }
+
+template <typename T>
+static HvK<T> make_args(const HvGemmArgs& a) {
+    HvK<T> g;
+    g.work = a.work;
+    g.sec = a.sec;
+    g.HL = (const T*)a.HL;
+    g.HRt = (const T*)a.HR;
+    g.V = (const T*)a.V;
+    g.W = (T*)a.W;
+    g.K = a.K;
+    g.src = a.src;
+    g.rmap = a.rmap;
+    g.cmap = a.cmap;
+    g.rcoef = (const T*)a.rcoef;
+    g.ccoef = (const T*)a.ccoef;
+    g.Drows = a.Drows;
+    g.Dcols = a.Dcols;
+    return g;
+}
 
 hipError_t launch_hv_gemm(int shape, const HvGemmArgs& a, hipStream_t st) {
     if (a.nwork <= 0) return hipSuccess;
     dim3 grid(a.nwork);
     switch (shape) {
         case 0:
-            hipLaunchKernelGGL((k_hv_gemm<double, 32, 32, 16, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec,
-                               (const double*)a.HL, (const double*)a.HR, (const double*)a.V, (double*)a.W);
+            hipLaunchKernelGGL((k_hv_gemm<double, 32, 32, 16, 2, 2>), grid, dim3(256), 0, st, make_args<double>(a));
             break;
         case 1:
-            hipLaunchKernelGGL((k_hv_gemm<double, 64, 64, 16, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec,
-                               (const double*)a.HL, (const double*)a.HR, (const double*)a.V, (double*)a.W);
+            hipLaunchKernelGGL((k_hv_gemm<double, 64, 64, 16, 2, 2>), grid, dim3(256), 0, st, make_args<double>(a));
             break;
         case 2:
-            hipLaunchKernelGGL((k_hv_gemm<double, 128, 128, 16, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec,
-                               (const double*)a.HL, (const double*)a.HR, (const double*)a.V, (double*)a.W);
+            hipLaunchKernelGGL((k_hv_gemm<double, 128, 128, 16, 2, 2>), grid, dim3(256), 0, st, make_args<double>(a));
             break;
         case 3:
-            hipLaunchKernelGGL((k_hv_gemm<float, 32, 32, 16, 1, 1>), grid, dim3(64), 0, st, a.work, a.sec,
-                               (const float*)a.HL, (const float*)a.HR, (const float*)a.V, (float*)a.W);
+            hipLaunchKernelGGL((k_hv_gemm<float, 32, 32, 16, 1, 1>), grid, dim3(64), 0, st, make_args<float>(a));
             break;
         case 4:
-            hipLaunchKernelGGL((k_hv_gemm<float, 64, 64, 16, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec,
-                               (const float*)a.HL, (const float*)a.HR, (const float*)a.V, (float*)a.W);
+            hipLaunchKernelGGL((k_hv_gemm<float, 64, 64, 16, 2, 2>), grid, dim3(256), 0, st, make_args<float>(a));
             break;
         case 5:
-            hipLaunchKernelGGL((k_hv_gemm<float, 128, 128, 16, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec,
-                               (const float*)a.HL, (const float*)a.HR, (const float*)a.V, (float*)a.W);
+            hipLaunchKernelGGL((k_hv_gemm<float, 128, 128, 16, 2, 2>), grid, dim3(256), 0, st, make_args<float>(a));
+            break;
+        case 6:
+            hipLaunchKernelGGL((k_hv_gemm<double, 64, 64, 32, 2, 2>), grid, dim3(256), 0, st, make_args<double>(a));
+            break;
+        case 7:
+            hipLaunchKernelGGL((k_hv_gemm<float, 64, 64, 32, 2, 2>), grid, dim3(256), 0, st, make_args<float>(a));
+            break;
+        case 8:
+            hipLaunchKernelGGL((k_hv_gemm<float, 128, 128, 32, 2, 2>), grid, dim3(256), 0, st, make_args<float>(a));
+            break;
+        case 9:
+            hipLaunchKernelGGL((k_hv_gemm<double, 128, 64, 16, 2, 2>), grid, dim3(256), 0, st, make_args<double>(a));
+            break;
+        case 10:
+            hipLaunchKernelGGL((k_hv_gemm<float, 128, 64, 16, 2, 2>), grid, dim3(256), 0, st, make_args<float>(a));
+            break;
+        case 11:
+            hipLaunchKernelGGL((k_hv_gemm<float, 64, 64, 64, 2, 2>), grid, dim3(256), 0, st, make_args<float>(a));
+            break;
+        case 12:
+            hipLaunchKernelGGL((k_hv_gemm<double, 32, 32, 32, 2, 2>), grid, dim3(256), 0, st, make_args<double>(a));
+            break;
+        case 13:
+            hipLaunchKernelGGL((k_hv_gemm<double, 64, 64, 64, 2, 2>), grid, dim3(256), 0, st, make_args<double>(a));
             break;
         default:
             return hipErrorInvalidValue;
@@ -214,53 +284,99 @@ __device__ inline float load_as_float<float>(const float* p, int64_t i) { return
 template <>
 __device__ inline float load_as_float<bf16_t>(const bf16_t* p, int64_t i) { return bf16_to_f32(p[i]); }
 
-// One thread per output element of pair blockIdx.y: r fastest, so the
-// gathered source rows (same i1 run) are read coalesced.
+// Central term.  One wave per output tile of 64 rows x CT columns of one pair
+// (compact launch table).  Each lane owns one row r: it loads the row maps and
+// coefficients of all K terms once; the column maps of the tile's CT columns
+// are staged in shared memory; then all K x CT gathers of the lane are issued
+// together (runs of consecutive i1 map to consecutive source rows, so a
+// wave's gathers are coalesced) and W is updated once per element.
+static constexpr int CT = 8;
+static constexpr int KMAX = 16;
+
 template <typename TI, typename TO, typename TC>
-__global__ void __launch_bounds__(256)
-k_central(const SectorDev* __restrict__ sec, int K, const int32_t* __restrict__ src,
+__global__ void __launch_bounds__(64)
+k_central(const int4* __restrict__ tiles, const SectorDev* __restrict__ sec, int K, const int32_t* __restrict__ src,
           const int32_t* __restrict__ rmap, const int32_t* __restrict__ cmap, const TC* __restrict__ rcoef,
           const TC* __restrict__ ccoef, int64_t Drows, int64_t Dcols, const TI* __restrict__ V,
           TO* __restrict__ W) {
-    const int p = blockIdx.y;
+    __shared__ int64_t s_off2[KMAX];
+    __shared__ int s_dl2[KMAX];
+    __shared__ int s_cm[KMAX][CT];
+    __shared__ TC s_cc[KMAX][CT];
+    const int4 t = tiles[blockIdx.x];
+    const int p = t.x, r0 = t.y * 64, c0 = t.z * CT;
     const SectorDev s = sec[p];
-    const int64_t n = (int64_t)s.dL * s.dR;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const int r = (int)(e % s.dL), c = (int)(e / s.dL);
-        TC acc = TC(0);
-        for (int k = 0; k < K; ++k) {
-            const int p2 = src[p * K + k];
-            if (p2 < 0) continue;
-            const int rm = rmap[k * Drows + s.row_base + r];
-            const int cm = cmap[k * Dcols + s.col_base + c];
-            if (rm < 0 || cm < 0) continue;
-            const SectorDev s2 = sec[p2];
-            TC x;
-            if constexpr (sizeof(TI) == sizeof(TC)) x = (TC)V[s2.off + rm + (int64_t)cm * s2.dL];
-            else x = (TC)load_as_float<TI>(V, s2.off + rm + (int64_t)cm * s2.dL);
-            acc += rcoef[k * Drows + s.row_base + r] * ccoef[k * Dcols + s.col_base + c] * x;
-        }
-        W[s.off + e] += (TO)acc;
+    const int lane = threadIdx.x;
+    if (lane < K) {
+        const int p2 = src[p * K + lane];
+        s_off2[lane] = p2 >= 0 ? sec[p2].off : -1;
+        s_dl2[lane] = p2 >= 0 ? sec[p2].dL : 0;
     }
+    for (int q = lane; q < K * CT; q += 64) {
+        const int k = q / CT, cc = q % CT, c = c0 + cc;
+        const bool ok = c < s.dR;
+        s_cm[k][cc] = ok ? cmap[k * Dcols + s.col_base + c] : -1;
+        s_cc[k][cc] = ok ? ccoef[k * Dcols + s.col_base + c] : TC(0);
+    }
+    __syncthreads();
+    const int r = r0 + lane;
+    if (r >= s.dL) return;
+    TC acc[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[c] = TC(0);
+    // terms in groups of KG: all row-map loads of a group first, then all its gathers
+    constexpr int KG = 4;
+    for (int k0 = 0; k0 < K; k0 += KG) {
+        int rm[KG];
+        TC rc[KG];
+#pragma unroll
+        for (int q = 0; q < KG; ++q) {
+            const int k = k0 + q;
+            const bool ok = k < K && s_off2[k < K ? k : 0] >= 0;
+            rm[q] = ok ? rmap[k * Drows + s.row_base + r] : -1;
+            rc[q] = ok ? rcoef[k * Drows + s.row_base + r] : TC(0);
+        }
+        TC x[KG][CT];
+#pragma unroll
+        for (int q = 0; q < KG; ++q) {
+            const int k = k0 + q < K ? k0 + q : 0;
+            const int64_t base = s_off2[k] + rm[q];
+            const int64_t dl2 = s_dl2[k];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const int cm = s_cm[k][c];
+                const bool ok = rm[q] >= 0 && cm >= 0;
+                if constexpr (sizeof(TI) == sizeof(TC)) x[q][c] = ok ? (TC)V[base + cm * dl2] : TC(0);
+                else x[q][c] = ok ? (TC)load_as_float<TI>(V, base + cm * dl2) : TC(0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < KG; ++q) {
+            const int k = k0 + q < K ? k0 + q : 0;
+#pragma unroll
+            for (int c = 0; c < CT; ++c) acc[c] += rc[q] * s_cc[k][c] * x[q][c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+        if (c0 + c < s.dR) W[s.off + r + (int64_t)(c0 + c) * s.dL] += (TO)acc[c];
 }
 
 hipError_t launch_central(int prec, const CentralArgs& a, hipStream_t st) {
-    if (a.K == 0 || a.npairs == 0) return hipSuccess;
-    int gx = (int)((a.max_elems + 255) / 256);
-    if (gx > 1024) gx = 1024;
-    if (gx < 1) gx = 1;
-    dim3 grid(gx, a.npairs);
+    if (a.K == 0 || a.nblocks == 0) return hipSuccess;
+    if (a.K > KMAX) return hipErrorInvalidValue;
+    dim3 grid(a.nblocks);
     if (prec == D2D_FP64)
-        hipLaunchKernelGGL((k_central<double, double, double>), grid, dim3(256), 0, st, a.sec, a.K, a.src, a.rmap,
-                           a.cmap, (const double*)a.rcoef, (const double*)a.ccoef, a.Drows, a.Dcols,
+        hipLaunchKernelGGL((k_central<double, double, double>), grid, dim3(64), 0, st, a.blocks, a.sec, a.K, a.src,
+                           a.rmap, a.cmap, (const double*)a.rcoef, (const double*)a.ccoef, a.Drows, a.Dcols,
                            (const double*)a.V, (double*)a.W);
     else if (prec == D2D_FP32)
-        hipLaunchKernelGGL((k_central<float, float, float>), grid, dim3(256), 0, st, a.sec, a.K, a.src, a.rmap,
-                           a.cmap, (const float*)a.rcoef, (const float*)a.ccoef, a.Drows, a.Dcols,
+        hipLaunchKernelGGL((k_central<float, float, float>), grid, dim3(64), 0, st, a.blocks, a.sec, a.K, a.src,
+                           a.rmap, a.cmap, (const float*)a.rcoef, (const float*)a.ccoef, a.Drows, a.Dcols,
                            (const float*)a.V, (float*)a.W);
     else
-        hipLaunchKernelGGL((k_central<bf16_t, float, float>), grid, dim3(256), 0, st, a.sec, a.K, a.src, a.rmap,
-                           a.cmap, (const float*)a.rcoef, (const float*)a.ccoef, a.Drows, a.Dcols,
+        hipLaunchKernelGGL((k_central<bf16_t, float, float>), grid, dim3(64), 0, st, a.blocks, a.sec, a.K, a.src,
+                           a.rmap, a.cmap, (const float*)a.rcoef, (const float*)a.ccoef, a.Drows, a.Dcols,
                            (const bf16_t*)a.V, (float*)a.W);
     return hipGetLastError();
 }
@@ -343,6 +459,20 @@ hipError_t launch_cast_f64_bf16(const double* x, bf16_t* y, int64_t n, hipStream
 hipError_t launch_cast_f32_bf16(const float* x, bf16_t* y, int64_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_cast_f32_bf16, dim3(grid_for(n)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
+__global__ void k_fill(void* x, int prec, int64_t n, double v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (prec == D2D_FP64) ((double*)x)[i] = v;
+        else if (prec == D2D_FP32) ((float*)x)[i] = (float)v;
+        else ((bf16_t*)x)[i] = f32_to_bf16_rne((float)v);
+    }
+}
+
+hipError_t launch_fill(void* x, int prec, int64_t n, double v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, s, x, prec, n, v);
     return hipGetLastError();
 }
 

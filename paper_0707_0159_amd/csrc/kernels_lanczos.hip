@@ -488,3 +488,316 @@ hipError_t launch_gemm_nn_f64(const double* A, int lda, const double* B, int ldb
 }
 
 }  // namespace d2d
+
+// ====================================================================== fused step
+// Kernels of one Lanczos step with full reorthogonalisation.  A kernel that
+// needs a global sum produced by the previous kernel adds that kernel's
+// per-block partial sums itself (every block redundantly, in a fixed order),
+// so no separate reduction launches and no inter-block fences are needed: the
+// kernel boundary orders the partial sums before their use.  The number of
+// blocks of these kernels is capped at LZ_STEP_NB to bound that re-reading.
+namespace d2d {
+
+static constexpr int LZ_STEP_NB = 256;
+
+int lz_step_blocks(int64_t n) {
+    int64_t nb = (n + 1023) / 1024;
+    if (nb > LZ_STEP_NB) nb = LZ_STEP_NB;
+    if (nb < 1) nb = 1;
+    return (int)nb;
+}
+
+// out_sh[j] = sum_b partial[j*nb + b] for j < rows (shared memory result).
+__device__ inline void reduce_rows(const double* __restrict__ partial, int rows, int nb, double* out_sh) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int j = wv; j < rows; j += LZ_THREADS / 64) {
+        double s = 0.0;
+        for (int b = lane; b < nb; b += 64) s += partial[(int64_t)j * nb + b];
+        s = wave_sum(s);
+        if (lane == 0) out_sh[j] = s;
+    }
+    __syncthreads();
+}
+
+// Per-block sums of acc[0..rows) (rows <= R) written to partial[j*nb + b].
+template <int R>
+__device__ inline void write_partials(const double (&acc)[R], int rows, double* __restrict__ partial, int nb,
+                                      int b) {
+    __shared__ double sh[LZ_THREADS / 64][R];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        if (j < rows) {
+            const double s = wave_sum(acc[j]);
+            if (lane == 0) sh[wv][j] = s;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < rows) {
+        double s = 0.0;
+        for (int w = 0; w < LZ_THREADS / 64; ++w) s += sh[w][threadIdx.x];
+        partial[(int64_t)threadIdx.x * nb + b] = s;
+    }
+}
+
+// Step kernel 1: partials of c1 = Q[0..nq)^T w (w upcast from FP32 first when UPCAST).
+template <int NQ, bool UPCAST>
+__global__ void __launch_bounds__(LZ_THREADS)
+k_lz_dots(const double* __restrict__ Q, int64_t ldq, int nq, const double* __restrict__ w64in,
+          const float* __restrict__ w32, double* __restrict__ w64out, int64_t n, double* __restrict__ partial) {
+    const int nb = gridDim.x, b = blockIdx.x;
+    int64_t lo, hi;
+    chunk(n, b, nb, &lo, &hi);
+    double acc[NQ];
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) acc[j] = 0.0;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+        double x;
+        if constexpr (UPCAST) {
+            x = (double)w32[e];
+            w64out[e] = x;
+        } else {
+            x = w64in[e];
+        }
+        double q[NQ];
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) q[j] = j < nq ? Q[j * ldq + e] : 0.0;
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) acc[j] += q[j] * x;
+    }
+    write_partials<NQ>(acc, nq, partial, nb, b);
+}
+
+// Step kernel 2: c1 from partial_in; w <- w - Q c1; partials of c2 = Q^T w
+// (rows 0..nq-1) and |w|^2 (row nq) into partial_out; alpha[i] = c1[i].
+template <int NQ>
+__global__ void __launch_bounds__(LZ_THREADS)
+k_lz_update_dots(const double* __restrict__ Q, int64_t ldq, int nq, const double* __restrict__ partial_in,
+                 int nb_in, double* __restrict__ w, int64_t n, double* __restrict__ partial_out,
+                 double* __restrict__ alpha, int i) {
+    __shared__ double cs[NQ];
+    if ((int)threadIdx.x < NQ) cs[threadIdx.x] = 0.0;
+    __syncthreads();
+    reduce_rows(partial_in, nq, nb_in, cs);
+    if (blockIdx.x == 0 && threadIdx.x == 0) alpha[i] = cs[i];
+    const int nb = gridDim.x, b = blockIdx.x;
+    int64_t lo, hi;
+    chunk(n, b, nb, &lo, &hi);
+    double acc[NQ + 1];
+#pragma unroll
+    for (int j = 0; j <= NQ; ++j) acc[j] = 0.0;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+        double q[NQ];
+        double x = w[e];
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) {
+            q[j] = j < nq ? Q[j * ldq + e] : 0.0;
+            x -= cs[j] * q[j];
+        }
+        w[e] = x;
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) acc[j] += q[j] * x;
+        acc[NQ] += x * x;
+    }
+    // rows 0..nq-1: projections; row nq: |w|^2
+    __shared__ double sh[LZ_THREADS / 64][NQ + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+        if (j < nq) {
+            const double t = wave_sum(acc[j]);
+            if (lane == 0) sh[wv][j] = t;
+        }
+    }
+    {
+        const double t = wave_sum(acc[NQ]);
+        if (lane == 0) sh[wv][nq] = t;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x <= nq) {
+        double t = 0.0;
+        for (int ww = 0; ww < LZ_THREADS / 64; ++ww) t += sh[ww][threadIdx.x];
+        partial_out[(int64_t)threadIdx.x * nb + b] = t;
+    }
+}
+
+// Step kernel 3: c2 and |w|^2 from partial_in; beta = sqrt(|w|^2 - |c2|^2);
+// q_next = (w - [need2] Q c2) / beta with need2 = |c2| > 1e-13 |w|;
+// lo = cast(q_next); block 0 writes alpha[i] += c2[i], beta[i+1].
+template <int NQ>
+__global__ void __launch_bounds__(LZ_THREADS)
+k_lz_next(const double* __restrict__ Q, int64_t ldq, int nq, const double* __restrict__ partial_in, int nb_in,
+          const double* __restrict__ w, double* __restrict__ qnext, void* __restrict__ lo, int lo_prec, int64_t n,
+          double* __restrict__ alpha, double* __restrict__ beta, int i) {
+    __shared__ double cs[NQ + 1];
+    reduce_rows(partial_in, nq + 1, nb_in, cs);
+    double s2 = 0.0;
+    for (int j = 0; j < nq; ++j) s2 += cs[j] * cs[j];
+    const double w2 = cs[nq];
+    const double b2 = w2 - s2;
+    const double bb = sqrt(b2 > 0.0 ? b2 : 0.0);
+    const bool corr = sqrt(s2) > 1e-13 * sqrt(w2 > 0.0 ? w2 : 0.0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        alpha[i] += cs[i];
+        beta[i + 1] = bb;
+    }
+    if (!qnext) return;
+    const double inv = bb > 0.0 ? 1.0 / bb : 0.0;
+    // four independent elements per thread and iteration (memory-level parallelism)
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < n; e0 += 4 * stride) {
+        double x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t e = e0 + u * stride;
+            x[u] = e < n ? w[e] : 0.0;
+        }
+        if (corr)
+            for (int j = 0; j < nq; ++j)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t e = e0 + u * stride;
+                    if (e < n) x[u] -= cs[j] * Q[j * ldq + e];
+                }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t e = e0 + u * stride;
+            if (e >= n) break;
+            const double q = x[u] * inv;
+            qnext[e] = q;
+            if (lo_prec == D2D_FP32) ((float*)lo)[e] = (float)q;
+            else if (lo_prec == D2D_BF16) ((uint16_t*)lo)[e] = f32_bf16_rne((float)q);
+        }
+    }
+}
+
+template <int NQ>
+static hipError_t lz_step_nq(const LzStepArgs& a, hipStream_t s) {
+    const int nb = lz_step_blocks(a.n);
+    double* p1 = a.partial;
+    double* p2 = a.partial2;
+    if (a.upcast)
+        hipLaunchKernelGGL((k_lz_dots<NQ, true>), dim3(nb), dim3(LZ_THREADS), 0, s, a.Q, a.n, a.nq,
+                           (const double*)nullptr, a.w32, a.w, a.n, p1);
+    else
+        hipLaunchKernelGGL((k_lz_dots<NQ, false>), dim3(nb), dim3(LZ_THREADS), 0, s, a.Q, a.n, a.nq, a.w,
+                           (const float*)nullptr, (double*)nullptr, a.n, p1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_lz_update_dots<NQ>), dim3(nb), dim3(LZ_THREADS), 0, s, a.Q, a.n, a.nq, p1, nb, a.w, a.n,
+                       p2, a.alpha, a.i);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int gn = a.qnext ? nb : 1;
+    hipLaunchKernelGGL((k_lz_next<NQ>), dim3(gn), dim3(LZ_THREADS), 0, s, a.Q, a.n, a.nq, p2, nb, a.w, a.qnext,
+                       a.lo, a.lo ? a.lo_prec : -1, a.n, a.alpha, a.beta, a.i);
+    return hipGetLastError();
+}
+
+hipError_t launch_lz_step(const LzStepArgs& a, hipStream_t s) {
+    if (a.nq <= 8) return lz_step_nq<8>(a, s);
+    if (a.nq <= 16) return lz_step_nq<16>(a, s);
+    if (a.nq <= 32) return lz_step_nq<32>(a, s);
+    return hipErrorInvalidValue;
+}
+
+// Residual of the restart: partials of theta = x.w; then r = w - theta x with
+// partials of |r|^2; then one block finishes alpha[0] = theta, beta[1] = rho
+// and res = (theta, rho).
+__global__ void __launch_bounds__(LZ_THREADS)
+k_lz_theta(const double* __restrict__ x, const double* __restrict__ w, int64_t n, double* __restrict__ partial) {
+    double acc[1] = {0.0};
+    const int nb = gridDim.x, b = blockIdx.x;
+    int64_t lo, hi;
+    chunk(n, b, nb, &lo, &hi);
+    for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) acc[0] += x[e] * w[e];
+    write_partials<1>(acc, 1, partial, nb, b);
+}
+
+__global__ void __launch_bounds__(LZ_THREADS)
+k_lz_resid(const double* __restrict__ x, const double* __restrict__ partial_in, int nb_in, double* __restrict__ w,
+           int64_t n, double* __restrict__ partial_out) {
+    __shared__ double th[1];
+    reduce_rows(partial_in, 1, nb_in, th);
+    const double t = th[0];
+    double acc[1] = {0.0};
+    const int nb = gridDim.x, b = blockIdx.x;
+    int64_t lo, hi;
+    chunk(n, b, nb, &lo, &hi);
+    for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+        const double r = w[e] - t * x[e];
+        w[e] = r;
+        acc[0] += r * r;
+    }
+    write_partials<1>(acc, 1, partial_out, nb, b);
+}
+
+__global__ void __launch_bounds__(LZ_THREADS)
+k_lz_restart_finish(const double* __restrict__ p_theta, const double* __restrict__ p_rho, int nb,
+                    double* __restrict__ alpha, double* __restrict__ beta, double* __restrict__ res) {
+    __shared__ double v[2];
+    reduce_rows(p_theta, 1, nb, v);
+    reduce_rows(p_rho, 1, nb, v + 1);
+    if (threadIdx.x == 0) {
+        const double rho = sqrt(v[1] > 0.0 ? v[1] : 0.0);
+        alpha[0] = v[0];
+        beta[1] = rho;
+        res[0] = v[0];
+        res[1] = rho;
+    }
+}
+
+hipError_t launch_lz_residual(const double* x, double* w, int64_t n, double* partial, double* partial2,
+                              double* alpha, double* beta, double* res, hipStream_t s) {
+    const int nb = lz_step_blocks(n);
+    hipLaunchKernelGGL(k_lz_theta, dim3(nb), dim3(LZ_THREADS), 0, s, x, w, n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lz_resid, dim3(nb), dim3(LZ_THREADS), 0, s, x, partial, nb, w, n, partial2);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lz_restart_finish, dim3(1), dim3(LZ_THREADS), 0, s, partial, partial2, nb, alpha, beta, res);
+    return hipGetLastError();
+}
+
+// x = Q y with partials of |x|^2; then x /= |x|.
+__global__ void __launch_bounds__(LZ_THREADS)
+k_lz_ritz(const double* __restrict__ Q, int64_t ldq, int k, const double* __restrict__ y, double* __restrict__ x,
+          int64_t n, double* __restrict__ partial) {
+    __shared__ double ys[128];
+    for (int j = threadIdx.x; j < k && j < 128; j += blockDim.x) ys[j] = y[j];
+    __syncthreads();
+    double acc[1] = {0.0};
+    const int nb = gridDim.x, b = blockIdx.x;
+    int64_t lo, hi;
+    chunk(n, b, nb, &lo, &hi);
+    for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+        double v = 0.0;
+        for (int j = 0; j < k; ++j) v += ys[j] * Q[j * ldq + e];
+        x[e] = v;
+        acc[0] += v * v;
+    }
+    write_partials<1>(acc, 1, partial, nb, b);
+}
+
+__global__ void __launch_bounds__(LZ_THREADS)
+k_lz_normalize(double* __restrict__ x, const double* __restrict__ partial, int nb, int64_t n) {
+    __shared__ double v[1];
+    reduce_rows(partial, 1, nb, v);
+    const double inv = v[0] > 0.0 ? 1.0 / sqrt(v[0]) : 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        x[e] *= inv;
+}
+
+hipError_t launch_lz_ritz(const double* Q, int64_t ldq, int k, const double* y, double* x, int64_t n,
+                          double* partial, hipStream_t s) {
+    if (k > 128) return hipErrorInvalidValue;
+    const int nb = lz_step_blocks(n);
+    hipLaunchKernelGGL(k_lz_ritz, dim3(nb), dim3(LZ_THREADS), 0, s, Q, ldq, k, y, x, n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lz_normalize, dim3(nb), dim3(LZ_THREADS), 0, s, x, partial, nb, n);
+    return hipGetLastError();
+}
+
+}  // namespace d2d

@@ -40,7 +40,17 @@ namespace {
 constexpr int S_ALPHA = 0, S_BETA = 130, S_C1 = 260, S_C2 = 390, S_NRM = 520, S_THETA = 524, S_Y = 528,
               S_TWORK = 660, S_RES = 1300, S_FLAGS = 1304, S_LEN = 1400;
 constexpr int PARTIAL_ROWS = 130;
+// second partial-sum buffer of the fused step kernels (33 rows x 256 blocks), after the first
+constexpr int64_t PARTIAL2_ROWS = 34;
 }  // namespace
+
+// partial-sum area: PARTIAL_ROWS x nb for the general kernels, of which the
+// first 34 x 256 also serve the fused step kernels, then a second 34 x 256 buffer
+static size_t partial_len(int nb) {
+    const size_t a = (size_t)PARTIAL_ROWS * (nb > 256 ? nb : 256);
+    return a + (size_t)PARTIAL2_ROWS * 256;
+}
+#define PARTIAL2 ((int64_t)PARTIAL_ROWS * (w->nb > 256 ? w->nb : 256))
 
 namespace d2d {
 
@@ -57,7 +67,7 @@ void free_lanczos(d2d_sb* sb) {
     c->free(lw->W, (size_t)lw->N * 8);
     c->free(lw->wlo, (size_t)lw->N * 4);
     c->free(lw->vlo, (size_t)lw->N * 4);
-    c->free(lw->partial, (size_t)PARTIAL_ROWS * lw->nb * 8);
+    c->free(lw->partial, partial_len(lw->nb) * 8);
     c->free(lw->scal, (size_t)S_LEN * 8);
     if (lw->host_res) (void)hipHostFree(lw->host_res);
     delete lw;
@@ -80,8 +90,9 @@ static d2d_status ensure_work(d2d_sb* sb, int kmax) {
     D2D_CHECK(c->alloc((void**)&w->W, (size_t)w->N * 8));
     D2D_CHECK(c->alloc((void**)&w->wlo, (size_t)w->N * 4));
     D2D_CHECK(c->alloc((void**)&w->vlo, (size_t)w->N * 4));
-    D2D_CHECK(c->alloc((void**)&w->partial, (size_t)PARTIAL_ROWS * w->nb * 8));
+    D2D_CHECK(c->alloc((void**)&w->partial, partial_len(w->nb) * 8));
     D2D_CHECK(c->alloc((void**)&w->scal, (size_t)S_LEN * 8));
+    D2D_HIP(hipMemset(w->scal, 0, (size_t)S_LEN * 8));
     D2D_HIP(hipHostMalloc((void**)&w->host_res, 8 * sizeof(double), hipHostMallocDefault));
     return D2D_OK;
 }
@@ -92,11 +103,8 @@ static d2d_status residual_step(d2d_sb* sb, hipStream_t s) {
     LanczosWork* w = sb->lz;
     double* sc = w->scal;
     D2D_CHECK(sb_hv(sb, D2D_FP64, w->X, w->W, s));
-    D2D_HIP(launch_dots_f64(w->X, w->N, 1, w->W, w->N, w->partial, s));
-    D2D_HIP(launch_reduce(w->partial, 1, w->nb, sc + S_THETA, s));
-    D2D_HIP(launch_residual(w->X, sc + S_THETA, w->W, w->N, w->partial, s));
-    D2D_HIP(launch_reduce(w->partial, 1, w->nb, sc + S_NRM, s));
-    D2D_HIP(launch_restart_scalars(sc + S_THETA, sc + S_NRM, sc + S_ALPHA, sc + S_BETA, sc + S_RES, s));
+    D2D_HIP(launch_lz_residual(w->X, w->W, w->N, w->partial, w->partial + PARTIAL2, sc + S_ALPHA, sc + S_BETA,
+                               sc + S_RES, s));
     D2D_HIP(hipMemcpyAsync(w->host_res, sc + S_RES, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     return D2D_OK;
 }
@@ -113,6 +121,28 @@ static d2d_status inner_loop(d2d_sb* sb, int prec, int k, hipStream_t s) {
     for (int i = 1; i < k; ++i) {
         double* qi = w->Q + (int64_t)i * N;
         const int nq = i + 1;
+        if (nq <= 32) {
+            // fused step: three kernels with in-kernel reductions
+            if (prec == D2D_FP64) D2D_CHECK(sb_hv(sb, D2D_FP64, qi, w->W, s));
+            else D2D_CHECK(sb_hv(sb, prec, w->vlo, w->wlo, s));
+            LzStepArgs a{};
+            a.Q = w->Q;
+            a.n = N;
+            a.nq = nq;
+            a.i = i;
+            a.upcast = prec != D2D_FP64;
+            a.w32 = w->wlo;
+            a.w = w->W;
+            a.partial = w->partial;
+            a.partial2 = w->partial + PARTIAL2;
+            a.alpha = sc + S_ALPHA;
+            a.beta = sc + S_BETA;
+            a.qnext = i + 1 < k ? w->Q + (int64_t)(i + 1) * N : nullptr;
+            a.lo = lo;
+            a.lo_prec = prec;
+            D2D_HIP(launch_lz_step(a, s));
+            continue;
+        }
         if (prec == D2D_FP64) {
             D2D_CHECK(sb_hv(sb, D2D_FP64, qi, w->W, s));
             D2D_HIP(launch_dots_f64(w->Q, N, nq, w->W, N, w->partial, s));
@@ -130,9 +160,7 @@ static d2d_status inner_loop(d2d_sb* sb, int prec, int k, hipStream_t s) {
         if (i + 1 < k) D2D_HIP(launch_scale_store(w->W, sc + S_BETA + i + 1, w->Q + (int64_t)(i + 1) * N, lo, prec, N, s));
     }
     D2D_HIP(launch_tridiag(sc + S_ALPHA, sc + S_BETA, k, sc + S_THETA + 1, sc + S_Y, sc + S_TWORK, s));
-    D2D_HIP(launch_ritz(w->Q, N, k, sc + S_Y, w->X, N, w->partial, s));
-    D2D_HIP(launch_reduce(w->partial, 1, w->nb, sc + S_NRM, s));
-    D2D_HIP(launch_normalize(w->X, sc + S_NRM, N, s));
+    D2D_HIP(launch_lz_ritz(w->Q, N, k, sc + S_Y, w->X, N, w->partial, s));
     return D2D_OK;
 }
 

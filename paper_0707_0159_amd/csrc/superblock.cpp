@@ -111,6 +111,7 @@ d2d_sb::~d2d_sb() {
     release(ctx, d_ccoef64, (size_t)K * Dcols);
     release(ctx, d_rcoef32, (size_t)K * Drows);
     release(ctx, d_ccoef32, (size_t)K * Dcols);
+    release(ctx, d_cblocks, (size_t)n_cblocks);
     for (auto& kv : work) {
         WorkItem* w = kv.second.first;
         release(ctx, w, (size_t)kv.second.second);
@@ -166,13 +167,22 @@ d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t
     int nwork = 0;
     D2D_CHECK(sb_work(sb, shape, &work, &nwork));
     HvGemmArgs g{work, nwork, sb->d_sec, sb->HL[prec], sb->HR[prec], v, w};
+    g.K = sb->K;
+    g.src = sb->d_src;
+    g.rmap = sb->d_rmap;
+    g.cmap = sb->d_cmap;
+    g.rcoef = prec == D2D_FP64 ? (const void*)sb->d_rcoef64 : (const void*)sb->d_rcoef32;
+    g.ccoef = prec == D2D_FP64 ? (const void*)sb->d_ccoef64 : (const void*)sb->d_ccoef32;
+    g.Drows = sb->Drows;
+    g.Dcols = sb->Dcols;
     D2D_HIP(launch_hv_gemm(shape, g, s));
     if (mid) D2D_HIP(hipEventRecord(mid, s));
     CentralArgs c{};
+    c.blocks = sb->d_cblocks;
+    c.nblocks = sb->n_cblocks;
     c.sec = sb->d_sec;
     c.npairs = (int)sb->pairs.size();
     c.K = sb->K;
-    c.max_elems = (int)std::min<int64_t>(sb->max_elems, 1 << 30);
     c.src = sb->d_src;
     c.rmap = sb->d_rmap;
     c.cmap = sb->d_cmap;
@@ -407,6 +417,21 @@ extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d
     D2D_CHECK(upload(ctx, cc, &sb->d_ccoef64));
     D2D_CHECK(upload(ctx, rc32, &sb->d_rcoef32));
     D2D_CHECK(upload(ctx, cc32, &sb->d_ccoef32));
+    // launch table of the central term: (pair, 64-row tile, 8-column tile)
+    if (K > 16) {
+        set_error("more than 16 central bond terms are not supported");
+        return D2D_EINVAL;
+    }
+    {
+        std::vector<int4> cb;
+        for (int p = 0; p < np; ++p) {
+            const int tr = (sb->pairs[p].dL + 63) / 64, tc = (sb->pairs[p].dR + 7) / 8;
+            for (int j = 0; j < tc; ++j)
+                for (int i = 0; i < tr; ++i) cb.push_back(make_int4(p, i, j, 0));
+        }
+        sb->n_cblocks = (int)cb.size();
+        D2D_CHECK(upload(ctx, cb, &sb->d_cblocks));
+    }
     D2D_HIP(hipStreamSynchronize(ctx->stream));
     *out = sb.release();
     return D2D_OK;
@@ -550,5 +575,109 @@ extern "C" d2d_status d2d_hv_profile(d2d_sb* sb, int prec, const void* v, void* 
     if (st != D2D_OK) return st;
     *ms_gemm = g / reps;
     *ms_central = c / reps;
+    return D2D_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+static uint64_t sector_key(const d2d_sb* sb, int prec) {
+    uint64_t h = 1469598103934665603ull ^ (uint64_t)prec;
+    auto mix = [&](uint64_t v) {
+        h ^= v;
+        h *= 1099511628211ull;
+    };
+    mix(sb->pairs.size());
+    for (const auto& p : sb->pairs) {
+        mix((uint64_t)p.dL);
+        mix((uint64_t)p.dR);
+    }
+    return h;
+}
+
+extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_tile, double* best_ms) {
+    if (!sb || !best_tile || !best_ms || prec < 0 || prec > 2 || reps < 1 || reps > 10000) {
+        set_error("d2d_sb_autotune: bad argument");
+        return D2D_EINVAL;
+    }
+    if (!(sb->prec_mask & (1u << prec)) || !sb->HL[prec]) {
+        set_error("d2d_sb_autotune: precision %d not kept by this superblock", prec);
+        return D2D_EINVAL;
+    }
+    const uint64_t key = sector_key(sb, prec);
+    const char* cache = getenv("D2D_TUNE_CACHE");
+    if (cache && *cache) {
+        FILE* f = fopen(cache, "r");
+        if (f) {
+            unsigned long long k;
+            int t;
+            double ms;
+            while (fscanf(f, "%llx %d %lf", &k, &t, &ms) == 3)
+                if (k == key && t >= 0 && t < tile_shape_count() && tile_shape(t).prec == prec) {
+                    sb->tile_sel[prec] = t;
+                    *best_tile = t;
+                    *best_ms = ms;
+                    fclose(f);
+                    return D2D_OK;
+                }
+            fclose(f);
+        }
+    }
+    d2d_ctx* ctx = sb->ctx;
+    hipStream_t s = ctx->stream;
+    const size_t in_sz = prec == D2D_FP64 ? 8 : (prec == D2D_FP32 ? 4 : 2);
+    const size_t out_sz = prec == D2D_FP64 ? 8 : 4;
+    void *v = nullptr, *w = nullptr;
+    D2D_CHECK(ctx->alloc(&v, (size_t)sb->N * in_sz));
+    d2d_status st = ctx->alloc(&w, (size_t)sb->N * out_sz);
+    if (st != D2D_OK) {
+        ctx->free(v, (size_t)sb->N * in_sz);
+        return st;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int best = -1;
+    double bms = 1e300;
+    const int saved = sb->tile_sel[prec];
+    if (launch_fill(v, prec, sb->N, 0.5, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+        set_error("d2d_sb_autotune: HIP setup failed");
+        st = D2D_EDEVICE;
+    }
+    for (int t = 0; t < tile_shape_count() && st == D2D_OK; ++t) {
+        if (tile_shape(t).prec != prec) continue;
+        sb->tile_sel[prec] = t;
+        st = sb_hv(sb, prec, v, w, s);   // warm-up (also builds the work list)
+        if (st != D2D_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) st = D2D_EDEVICE;
+        for (int r = 0; r < reps && st == D2D_OK; ++r) st = sb_hv(sb, prec, v, w, s);
+        float ms = 0.f;
+        if (st == D2D_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = D2D_EDEVICE;
+        if (st == D2D_OK && ms / reps < bms) {
+            bms = ms / reps;
+            best = t;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    ctx->free(v, (size_t)sb->N * in_sz);
+    ctx->free(w, (size_t)sb->N * out_sz);
+    if (st != D2D_OK || best < 0) {
+        sb->tile_sel[prec] = saved;
+        if (st == D2D_OK) {
+            set_error("d2d_sb_autotune: no tile shape for precision %d", prec);
+            st = D2D_EINVAL;
+        }
+        return st;
+    }
+    sb->tile_sel[prec] = best;
+    *best_tile = best;
+    *best_ms = bms;
+    if (cache && *cache) {
+        FILE* f = fopen(cache, "a");
+        if (f) {
+            fprintf(f, "%llx %d %.6f\n", (unsigned long long)key, best, bms);
+            fclose(f);
+        }
+    }
     return D2D_OK;
 }

@@ -79,6 +79,7 @@ _SIGS = {
     "d2d_hv_count": (C.c_int, [P, i64p]),
     "d2d_hv_profile": (C.c_int, [P, C.c_int, P, P, C.c_int, f64p, f64p]),
     "d2d_sb_set_tile": (C.c_int, [P, C.c_int, C.c_int]),
+    "d2d_sb_autotune": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(C.c_int), f64p]),
     "d2d_tile_shapes": (C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "d2d_lanczos": (C.c_int, [P, C.POINTER(d2d_lanczos_opts), P, f64p, P, C.POINTER(d2d_lanczos_stats)]),
     "d2d_density_matrix": (C.c_int, [P, P, C.c_int, C.c_int, C.POINTER(P), f64p, f64p, i64p]),
@@ -279,6 +280,14 @@ def d2d_hv_count(sb: int):
 
 def d2d_sb_set_tile(sb: int, prec: int, tile: int):
     _check(load().d2d_sb_set_tile(P(sb), int(prec), int(tile)))
+
+
+def d2d_sb_autotune(sb: int, prec: int, reps: int = 20):
+    """Time every tile shape of prec, keep the fastest; returns (tile index, ms)."""
+    t = C.c_int()
+    ms = C.c_double()
+    _check(load().d2d_sb_autotune(P(sb), int(prec), int(reps), C.byref(t), C.byref(ms)))
+    return t.value, ms.value
 
 
 def d2d_tile_shapes():
