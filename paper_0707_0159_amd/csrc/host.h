@@ -111,6 +111,12 @@ struct d2d_sb {
     float* d_ccoef32 = nullptr;
     int64_t max_elems = 0;
     int4* d_cblocks = nullptr;         // central-term launch table
+    // BF16 operands and per-Hv padded copies of the input vector
+    int64_t hl16_len = 0, hr16_len = 0, vp_len = 0, vt_len = 0;
+    d2d::bf16_t* d_vp = nullptr;
+    d2d::bf16_t* d_vt = nullptr;
+    int4* d_ptiles = nullptr;          // pack launch table (pair, 64-row tile, 64-column tile)
+    int n_ptiles = 0;
     int n_cblocks = 0;
     // work lists per tile shape
     std::map<int, std::pair<d2d::WorkItem*, int>> work;

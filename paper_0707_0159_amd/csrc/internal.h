@@ -42,6 +42,12 @@ struct SectorDev {
     int64_t hr_off;     // offset of H_r[Q - q_L] (d_R x d_R)
     int64_t row_base;   // first global row slot of this pair
     int64_t col_base;   // first global column slot
+    // BF16 operands, K-major with leading dimensions padded to a multiple of 8
+    int32_t dLp, dRp;   // padded d_L, d_R
+    int64_t hl16_off;   // H_l row-major: dL rows of dLp (sum dLp*dL)
+    int64_t hr16_off;   // H_r^T column-major: dR columns of dRp (sum dRp*dR)
+    int64_t vp_off;     // V column-major, ld dLp (sum dLp*dR)
+    int64_t vt_off;     // V^T column-major, ld dRp (sum dRp*dL)
 };
 
 // One output tile of the grouped GEMM: pair, tile row, tile column.
@@ -77,6 +83,15 @@ struct HvGemmArgs {
     int64_t Drows, Dcols;
 };
 hipError_t launch_hv_gemm(int shape, const HvGemmArgs& a, hipStream_t s);
+// BF16: HvGemmArgs.V is the padded copy VP, VT its padded transpose.
+hipError_t launch_hv_gemm_bf16(int shape, const HvGemmArgs& a, const void* VT, hipStream_t s);
+// VP / VT of a packed BF16 vector (padding stays as it was: zero).
+hipError_t launch_pack_bf16(const int4* tiles, int ntiles, const SectorDev* sec, const bf16_t* v, bf16_t* vp,
+                            bf16_t* vt, hipStream_t s);
+// BF16 operator copies from the FP64 masters: HL (column-major dL x dL) ->
+// row-major padded; HRt (column-major H_r^T) -> padded; two-step RNE rounding.
+hipError_t launch_op_bf16(const int64_t* src_off, const int64_t* dst_off, const int32_t* d, const int32_t* dp,
+                          int nsec, int transpose, const double* src, bf16_t* dst, int64_t max_d2, hipStream_t s);
 
 // Central term W += sum_k c_k a_k V b_k^T by gather tables.
 struct CentralArgs {

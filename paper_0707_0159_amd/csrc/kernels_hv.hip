@@ -181,6 +181,216 @@ k_hv_gemm(const HvK<T> g) {
     }
 }
 
+// ------------------------------------------------------------------ BF16 GEMM
+// Same tile algorithm with v_mfma_f32_32x32x16_bf16 (lane l holds A[l%32][8(l/32)..+7]
+// and B[8(l/32)..+7][l%32]; results as the 32x32x2 f32 form, checked on the
+// device).  Both operands are K-major so a lane's eight K values are one
+// 16-byte load from global memory and from LDS:
+//   phase 0: A = H_l (row-major, ld dLp), B = V (column-major, ld dLp)
+//   phase 1: A = V^T (column-major dR x dL, ld dRp), B = H_r^T (ld dRp)
+// K runs over the padded length; the padding of every operand is zero.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+__device__ inline bf16_t f32_to_bf16_rne(float f);
+
+template <int BM, int BN, int BK, int WGM, int WGN>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+k_hv_gemm_bf16(const WorkItem* __restrict__ work, const SectorDev* __restrict__ sec, const bf16_t* __restrict__ HL,
+               const bf16_t* __restrict__ HRt, const bf16_t* __restrict__ VP, const bf16_t* __restrict__ VT,
+               float* __restrict__ W) {
+    using M = Mf<float>;
+    constexpr int NT = 64 * WGM * WGN;
+    constexpr int WM = BM / WGM, WN = BN / WGN;
+    constexpr int FM = WM / 32, FN = WN / 32;
+    static_assert(FM >= 1 && FN >= 1 && BK % 16 == 0, "tile");
+    constexpr int KV = BK / 8;                       // 16-byte vectors per row of a tile
+    constexpr int EA = BM * KV / NT, EB = BN * KV / NT;
+    static_assert(EA * NT == BM * KV && EB * NT == BN * KV, "load split");
+    constexpr int LD = BK + 8;                       // row stride in LDS (bf16), 16-byte aligned
+    __shared__ __attribute__((aligned(16))) bf16_t As[2][BM][LD];
+    __shared__ __attribute__((aligned(16))) bf16_t Bs[2][BN][LD];
+
+    const WorkItem wi = work[blockIdx.x];
+    const SectorDev s = sec[wi.p];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave % WGM, wn = wave / WGM;
+    const int row0 = wi.tm * BM, col0 = wi.tn * BN;
+    const int dL = s.dL, dR = s.dR;
+
+    typename M::vec acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int v = 0; v < M::NV; ++v) acc[i][j][v] = 0.0f;
+
+    uint4 ra[EA], rb[EB];
+#pragma unroll 1
+    for (int phase = 0; phase < 2; ++phase) {
+        const bf16_t* A = phase == 0 ? HL + s.hl16_off : VT + s.vt_off;
+        const bf16_t* B = phase == 0 ? VP + s.vp_off : HRt + s.hr16_off;
+        const int64_t ld = phase == 0 ? s.dLp : s.dRp;     // both operands share the K stride
+        const int Kp = phase == 0 ? s.dLp : s.dRp;
+
+        auto gload = [&](int k0) {
+#pragma unroll
+            for (int e = 0; e < EA; ++e) {
+                const int idx = t + NT * e, r = idx / KV, kv = idx % KV;
+                const int gr = row0 + r, kk = k0 + 8 * kv;
+                ra[e] = (gr < dL && kk < Kp) ? *(const uint4*)(A + gr * ld + kk) : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int e = 0; e < EB; ++e) {
+                const int idx = t + NT * e, c = idx / KV, kv = idx % KV;
+                const int gc = col0 + c, kk = k0 + 8 * kv;
+                rb[e] = (gc < dR && kk < Kp) ? *(const uint4*)(B + gc * ld + kk) : make_uint4(0, 0, 0, 0);
+            }
+        };
+        gload(0);
+        int buf = 0;
+#pragma unroll 1
+        for (int k0 = 0; k0 < Kp; k0 += BK) {
+#pragma unroll
+            for (int e = 0; e < EA; ++e) {
+                const int idx = t + NT * e;
+                *(uint4*)&As[buf][idx / KV][8 * (idx % KV)] = ra[e];
+            }
+#pragma unroll
+            for (int e = 0; e < EB; ++e) {
+                const int idx = t + NT * e;
+                *(uint4*)&Bs[buf][idx / KV][8 * (idx % KV)] = rb[e];
+            }
+            __syncthreads();
+            if (k0 + BK < Kp) gload(k0 + BK);
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 16) {
+                bf16x8 a[FM], b[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+                    a[i] = *(const bf16x8*)&As[buf][wm * WM + i * 32 + (lane & 31)][kk + 8 * (lane >> 5)];
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    b[j] = *(const bf16x8*)&Bs[buf][wn * WN + j * 32 + (lane & 31)][kk + 8 * (lane >> 5)];
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[j], a[i], acc[i][j], 0, 0, 0);
+            }
+            buf ^= 1;
+        }
+        __syncthreads();
+    }
+
+    float* Wp = W + s.off;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+        const int r = row0 + wm * WM + i * 32 + (lane & 31);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+#pragma unroll
+            for (int v = 0; v < M::NV; ++v) {
+                const int c = col0 + wn * WN + j * 32 + M::col_of(lane, v);
+                if (r < dL && c < dR) Wp[r + (int64_t)c * dL] = acc[i][j][v];
+            }
+        }
+    }
+}
+
+hipError_t launch_hv_gemm_bf16(int shape, const HvGemmArgs& a, const void* VT, hipStream_t st) {
+    if (a.nwork <= 0) return hipSuccess;
+    dim3 grid(a.nwork);
+    const bf16_t* HL = (const bf16_t*)a.HL;
+    const bf16_t* HR = (const bf16_t*)a.HR;
+    const bf16_t* VP = (const bf16_t*)a.V;
+    const bf16_t* V2 = (const bf16_t*)VT;
+    float* W = (float*)a.W;
+    switch (shape) {
+        case 14:
+            hipLaunchKernelGGL((k_hv_gemm_bf16<64, 64, 32, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec, HL, HR, VP,
+                               V2, W);
+            break;
+        case 15:
+            hipLaunchKernelGGL((k_hv_gemm_bf16<128, 128, 32, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec, HL, HR,
+                               VP, V2, W);
+            break;
+        case 16:
+            hipLaunchKernelGGL((k_hv_gemm_bf16<128, 128, 64, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec, HL, HR,
+                               VP, V2, W);
+            break;
+        case 17:
+            hipLaunchKernelGGL((k_hv_gemm_bf16<32, 32, 64, 1, 1>), grid, dim3(64), 0, st, a.work, a.sec, HL, HR, VP,
+                               V2, W);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Padded copies of a packed BF16 vector: 64x64 tiles through LDS so that both
+// the column-major copy and the transposed copy are written coalesced.
+__global__ void __launch_bounds__(256)
+k_pack_bf16(const int4* __restrict__ tiles, const SectorDev* __restrict__ sec, const bf16_t* __restrict__ v,
+            bf16_t* __restrict__ vp, bf16_t* __restrict__ vt) {
+    __shared__ bf16_t sh[64][66];
+    const int4 ti = tiles[blockIdx.x];
+    const SectorDev s = sec[ti.x];
+    const int r0 = ti.y * 64, c0 = ti.z * 64;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int rr = t & 63, cc = (t >> 6) + 4 * q;
+        const int r = r0 + rr, c = c0 + cc;
+        if (r < s.dL && c < s.dR) {
+            const bf16_t x = v[s.off + r + (int64_t)c * s.dL];
+            sh[cc][rr] = x;
+            vp[s.vp_off + r + (int64_t)c * s.dLp] = x;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int cc = t & 63, rr = (t >> 6) + 4 * q;
+        const int r = r0 + rr, c = c0 + cc;
+        if (r < s.dL && c < s.dR) vt[s.vt_off + c + (int64_t)r * s.dRp] = sh[cc][rr];
+    }
+}
+
+hipError_t launch_pack_bf16(const int4* tiles, int ntiles, const SectorDev* sec, const bf16_t* v, bf16_t* vp,
+                            bf16_t* vt, hipStream_t st) {
+    if (ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_bf16, dim3(ntiles), dim3(256), 0, st, tiles, sec, v, vp, vt);
+    return hipGetLastError();
+}
+
+// dst (padded, K-major) from an FP64 column-major d x d block; transpose=1
+// stores the transposed block (row-major H_l), 0 stores it as is (H_r^T).
+__global__ void __launch_bounds__(256)
+k_op_bf16(const int64_t* __restrict__ src_off, const int64_t* __restrict__ dst_off, const int32_t* __restrict__ dd,
+          const int32_t* __restrict__ ddp, int transpose, const double* __restrict__ src, bf16_t* __restrict__ dst) {
+    const int si = blockIdx.y;
+    const int d = dd[si], dp = ddp[si];
+    const int64_t n = (int64_t)d * d;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % d), j = (int)(e / d);     // element (i, j) of the source
+        const float f = (float)src[src_off[si] + e];
+        const bf16_t h = f32_to_bf16_rne(f);
+        if (transpose) dst[dst_off[si] + j + (int64_t)i * dp] = h;   // row i of the source, K = j
+        else dst[dst_off[si] + i + (int64_t)j * dp] = h;
+    }
+}
+
+hipError_t launch_op_bf16(const int64_t* src_off, const int64_t* dst_off, const int32_t* d, const int32_t* dp,
+                          int nsec, int transpose, const double* src, bf16_t* dst, int64_t max_d2, hipStream_t st) {
+    if (nsec == 0) return hipSuccess;
+    int gx = (int)((max_d2 + 255) / 256);
+    if (gx > 4096) gx = 4096;
+    if (gx < 1) gx = 1;
+    hipLaunchKernelGGL(k_op_bf16, dim3(gx, nsec), dim3(256), 0, st, src_off, dst_off, d, dp, transpose, src, dst);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ tile table
 static const TileShape kShapes[] = {
     {D2D_FP64, 32, 32, 16},    // 0: 4 waves of 16x16
@@ -197,6 +407,10 @@ static const TileShape kShapes[] = {
     {D2D_FP32, 64, 64, 64},    // 11: long K step for small, latency-bound sectors
     {D2D_FP64, 32, 32, 32},    // 12
     {D2D_FP64, 64, 64, 64},    // 13
+    {D2D_BF16, 64, 64, 32},    // 14: 4 waves of 32x32 (bf16 32x32x16)
+    {D2D_BF16, 128, 128, 32},  // 15: 4 waves of 64x64
+    {D2D_BF16, 128, 128, 64},  // 16
+    {D2D_BF16, 32, 32, 64},    // 17: 1 wave
 };
 
 int tile_shape_count() { return (int)(sizeof(kShapes) / sizeof(kShapes[0])); }

@@ -223,10 +223,6 @@ extern "C" d2d_status d2d_lanczos(d2d_sb* sb, const d2d_lanczos_opts* opts, cons
         set_error("d2d_lanczos: precision %d not kept by this superblock", opts->prec);
         return D2D_EINVAL;
     }
-    if (opts->prec == D2D_BF16) {
-        set_error("BF16 Hv kernels are not built in this library version");
-        return D2D_EINVAL;
-    }
     hipStream_t s = sb->ctx->stream;
     const int k = (int)std::min<int64_t>(opts->k_in, sb->N);
     D2D_CHECK(ensure_work(sb, std::max(k, 2)));
@@ -257,8 +253,12 @@ extern "C" d2d_status d2d_lanczos(d2d_sb* sb, const d2d_lanczos_opts* opts, cons
             result = D2D_EDEVICE;
             break;
         }
-        if (rho_prev >= 0.0 && prec != D2D_FP64 && opts->escalate > 0.0 && rho > opts->escalate * rho_prev)
-            prec = prec == D2D_BF16 ? D2D_FP32 : D2D_FP64;
+        if (rho_prev >= 0.0 && prec != D2D_FP64 && opts->escalate > 0.0 && rho > opts->escalate * rho_prev) {
+            // raise to the next precision this superblock keeps
+            int np = prec == D2D_BF16 ? D2D_FP32 : D2D_FP64;
+            if (!(sb->prec_mask & (1u << np)) || !sb->HL[np]) np = D2D_FP64;
+            prec = np;
+        }
         if (st.nlog < D2D_LOG_MAX) {
             st.log_t[st.nlog] = tsec;
             st.log_theta[st.nlog] = theta;

@@ -98,12 +98,16 @@ d2d_sb::~d2d_sb() {
     if (!ctx) return;
     const size_t np = pairs.size();
     release(ctx, d_sec, np);
-    const size_t esz[3] = {8, 4, 2};
+    const size_t hls[3] = {(size_t)hl_len * 8, (size_t)hl_len * 4, (size_t)hl16_len * 2};
+    const size_t hrs[3] = {(size_t)hr_len * 8, (size_t)hr_len * 4, (size_t)hr16_len * 2};
     for (int p = 0; p < 3; ++p) {
-        if (HL[p]) ctx->free(HL[p], (size_t)hl_len * esz[p]);
-        if (HR[p]) ctx->free(HR[p], (size_t)hr_len * esz[p]);
+        if (HL[p]) ctx->free(HL[p], hls[p]);
+        if (HR[p]) ctx->free(HR[p], hrs[p]);
         HL[p] = HR[p] = nullptr;
     }
+    release(ctx, d_vp, (size_t)vp_len);
+    release(ctx, d_vt, (size_t)vt_len);
+    release(ctx, d_ptiles, (size_t)n_ptiles);
     release(ctx, d_src, np * K);
     release(ctx, d_rmap, (size_t)K * Drows);
     release(ctx, d_cmap, (size_t)K * Dcols);
@@ -125,6 +129,7 @@ int sb_auto_tile(const d2d_sb* sb, int prec) {
     const int D = std::max(sb->max_dl, sb->max_dr);
     if (prec == D2D_FP64) return D <= 64 ? 0 : (D <= 768 ? 1 : 2);
     if (prec == D2D_FP32) return D <= 64 ? 3 : (D <= 768 ? 4 : 5);
+    if (prec == D2D_BF16) return D <= 64 ? 17 : (D <= 512 ? 14 : 15);
     return -1;
 }
 
@@ -158,15 +163,16 @@ d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t
         set_error("precision %d not available on this superblock", prec);
         return D2D_EINVAL;
     }
-    if (prec == D2D_BF16) {
-        set_error("BF16 Hv kernels are not built in this library version");
-        return D2D_EINVAL;
-    }
     const int shape = sb->tile_sel[prec] >= 0 ? sb->tile_sel[prec] : sb_auto_tile(sb, prec);
     WorkItem* work = nullptr;
     int nwork = 0;
     D2D_CHECK(sb_work(sb, shape, &work, &nwork));
     HvGemmArgs g{work, nwork, sb->d_sec, sb->HL[prec], sb->HR[prec], v, w};
+    if (prec == D2D_BF16) {
+        D2D_HIP(launch_pack_bf16(sb->d_ptiles, sb->n_ptiles, sb->d_sec, (const bf16_t*)v, sb->d_vp, sb->d_vt, s));
+        g.V = sb->d_vp;
+        D2D_HIP(launch_hv_gemm_bf16(shape, g, sb->d_vt, s));
+    } else {
     g.K = sb->K;
     g.src = sb->d_src;
     g.rmap = sb->d_rmap;
@@ -176,6 +182,7 @@ d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t
     g.Drows = sb->Drows;
     g.Dcols = sb->Dcols;
     D2D_HIP(launch_hv_gemm(shape, g, s));
+    }
     if (mid) D2D_HIP(hipEventRecord(mid, s));
     CentralArgs c{};
     c.blocks = sb->d_cblocks;
@@ -190,7 +197,7 @@ d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t
     c.ccoef = prec == D2D_FP64 ? (const void*)sb->d_ccoef64 : (const void*)sb->d_ccoef32;
     c.Drows = sb->Drows;
     c.Dcols = sb->Dcols;
-    c.V = v;
+    c.V = v;   // the unpadded input in every precision
     c.W = w;
     D2D_HIP(launch_central(prec, c, s));
     sb->hv_count[prec]++;
@@ -273,6 +280,16 @@ extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d
         s.hr_off = hr;
         s.row_base = rb;
         s.col_base = cb;
+        s.dLp = (s.dL + 7) / 8 * 8;
+        s.dRp = (s.dR + 7) / 8 * 8;
+        s.hl16_off = sb->hl16_len;
+        s.hr16_off = sb->hr16_len;
+        s.vp_off = sb->vp_len;
+        s.vt_off = sb->vt_len;
+        sb->hl16_len += (int64_t)s.dLp * s.dL;
+        sb->hr16_len += (int64_t)s.dRp * s.dR;
+        sb->vp_len += (int64_t)s.dLp * s.dR;
+        sb->vt_len += (int64_t)s.dRp * s.dL;
         off += (int64_t)s.dL * s.dR;
         hl += (int64_t)s.dL * s.dL;
         hr += (int64_t)s.dR * s.dR;
@@ -327,10 +344,57 @@ extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d
         D2D_HIP(launch_cast_f64_f32((const double*)sb->HR[0], (float*)sb->HR[1], hr, ctx->stream));
     }
     if (prec_mask & (1u << D2D_BF16)) {
-        D2D_CHECK(ctx->alloc(&sb->HL[D2D_BF16], (size_t)hl * 2));
-        D2D_CHECK(ctx->alloc(&sb->HR[D2D_BF16], (size_t)hr * 2));
-        D2D_HIP(launch_cast_f64_bf16((const double*)sb->HL[0], (bf16_t*)sb->HL[2], hl, ctx->stream));
-        D2D_HIP(launch_cast_f64_bf16((const double*)sb->HR[0], (bf16_t*)sb->HR[2], hr, ctx->stream));
+        const size_t h16 = (size_t)sb->hl16_len * 2, r16 = (size_t)sb->hr16_len * 2;
+        D2D_CHECK(ctx->alloc(&sb->HL[D2D_BF16], h16));
+        D2D_CHECK(ctx->alloc(&sb->HR[D2D_BF16], r16));
+        D2D_CHECK(ctx->alloc((void**)&sb->d_vp, (size_t)sb->vp_len * 2));
+        D2D_CHECK(ctx->alloc((void**)&sb->d_vt, (size_t)sb->vt_len * 2));
+        // padding of every K-major operand is zero and stays zero
+        D2D_HIP(hipMemset(sb->HL[D2D_BF16], 0, h16));
+        D2D_HIP(hipMemset(sb->HR[D2D_BF16], 0, r16));
+        D2D_HIP(hipMemset(sb->d_vp, 0, (size_t)sb->vp_len * 2));
+        D2D_HIP(hipMemset(sb->d_vt, 0, (size_t)sb->vt_len * 2));
+        const int npp = (int)sb->pairs.size();
+        std::vector<int64_t> so_l(npp), so_r(npp), do_l(npp), do_r(npp);
+        std::vector<int32_t> dl(npp), dlp(npp), dr(npp), drp(npp);
+        int64_t mx = 0;
+        for (int p = 0; p < npp; ++p) {
+            const SectorDev& q = sb->pairs[p];
+            so_l[p] = q.hl_off; so_r[p] = q.hr_off; do_l[p] = q.hl16_off; do_r[p] = q.hr16_off;
+            dl[p] = q.dL; dlp[p] = q.dLp; dr[p] = q.dR; drp[p] = q.dRp;
+            mx = std::max<int64_t>(mx, std::max<int64_t>((int64_t)q.dL * q.dL, (int64_t)q.dR * q.dR));
+        }
+        int64_t *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *a4 = nullptr;
+        int32_t *b1 = nullptr, *b2 = nullptr, *b3 = nullptr, *b4 = nullptr;
+        d2d_status st = D2D_OK;
+        if ((st = upload(ctx, so_l, &a1)) == D2D_OK && (st = upload(ctx, so_r, &a2)) == D2D_OK &&
+            (st = upload(ctx, do_l, &a3)) == D2D_OK && (st = upload(ctx, do_r, &a4)) == D2D_OK &&
+            (st = upload(ctx, dl, &b1)) == D2D_OK && (st = upload(ctx, dlp, &b2)) == D2D_OK &&
+            (st = upload(ctx, dr, &b3)) == D2D_OK && (st = upload(ctx, drp, &b4)) == D2D_OK) {
+            hipError_t e = launch_op_bf16(a1, a3, b1, b2, npp, 1, (const double*)sb->HL[0], (bf16_t*)sb->HL[2], mx,
+                                          ctx->stream);
+            if (e == hipSuccess)
+                e = launch_op_bf16(a2, a4, b3, b4, npp, 0, (const double*)sb->HR[0], (bf16_t*)sb->HR[2], mx,
+                                   ctx->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+            if (e != hipSuccess) {
+                set_error("BF16 operator conversion failed: %s", hipGetErrorString(e));
+                st = D2D_EDEVICE;
+            }
+        }
+        release(ctx, a1, so_l.size()); release(ctx, a2, so_r.size());
+        release(ctx, a3, do_l.size()); release(ctx, a4, do_r.size());
+        release(ctx, b1, dl.size()); release(ctx, b2, dlp.size());
+        release(ctx, b3, dr.size()); release(ctx, b4, drp.size());
+        D2D_CHECK(st);
+        std::vector<int4> pt;
+        for (int p = 0; p < npp; ++p) {
+            const int tr = (sb->pairs[p].dL + 63) / 64, tc = (sb->pairs[p].dR + 63) / 64;
+            for (int j = 0; j < tc; ++j)
+                for (int i = 0; i < tr; ++i) pt.push_back(make_int4(p, i, j, 0));
+        }
+        sb->n_ptiles = (int)pt.size();
+        D2D_CHECK(upload(ctx, pt, &sb->d_ptiles));
     }
 
     // a5: central bond terms sum_k c_k A_k (x) B_k, A_k on column 2, B_k on column 3

@@ -107,3 +107,65 @@ def test_repeatable_bitwise(ctx):
         for _ in range(5):
             assert np.array_equal(a, gpu_hv(ctx, prob, prec, v))
     prob.close()
+
+
+def bf16_round(x):
+    """float64 -> float32 (RNE) -> bfloat16 (RNE), returned as float64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def bf16_bits(x):
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+def oracle_hv_bf16_operands(osb, v):
+    """The oracle's matrix form with H_l, H_r sectors and v rounded to bfloat16."""
+    vb = bf16_round(v)
+    w = np.zeros_like(vb)
+    for (q, r, c, o), (hl, hr) in zip(osb.sectors, osb.dense_sectors()):
+        dL, dR = r.size, c.size
+        V = vb[o:o + dL * dR].reshape(dR, dL).T
+        W = bf16_round(hl) @ V + V @ bf16_round(hr).T
+        w[o:o + dL * dR] = W.T.reshape(-1)
+    for hc, pidx in osb.central_groups():
+        w[pidx] += hc @ vb[pidx]
+    return w
+
+
+def gpu_hv_bf16(ctx, prob, v):
+    from paper_0707_0159_amd import d2d
+    with torch.cuda.stream(ctx.stream):
+        vd = torch.as_tensor(bf16_bits(v).view(np.int16)).to("cuda")
+        wd = torch.full((v.size,), float("nan"), dtype=torch.float32, device="cuda")
+        d2d.d2d_hv(prob.sb, d2d.D2D_BF16, vd, wd)
+    ctx.stream.synchronize()
+    return wd.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_bf16_every_tile_shape(ctx, cfg):
+    """BF16 operands, FP32 accumulation: equal to the oracle on bf16-rounded
+    operands up to FP32 accumulation (<= 1e-5), and within 2e-2 of the exact product."""
+    from paper_0707_0159_amd import d2d
+    wl = W.CONFIGS[cfg]
+    osb = oracle_superblock(wl)
+    prob = GpuProblem(ctx, wl, prec_mask=7)
+    shapes = [i for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == d2d.D2D_BF16]
+    assert shapes
+    for k in range(2):
+        v = W.random_vector(osb.N, 1000 + k)
+        ref_b = oracle_hv_bf16_operands(osb, v)
+        ref = osb.hv_factored(v)
+        for sh in shapes:
+            d2d.d2d_sb_set_tile(prob.sb, d2d.D2D_BF16, sh)
+            w = gpu_hv_bf16(ctx, prob, v)
+            e1, e2 = rel_err(w, ref_b), rel_err(w, ref)
+            print(f"config {cfg} bf16 shape {sh}: vs bf16-operand oracle {e1:.3e}, vs exact {e2:.3e}")
+            assert e1 <= 1e-5
+            assert e2 <= 2e-2
+    prob.close()

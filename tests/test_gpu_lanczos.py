@@ -50,10 +50,10 @@ def test_config1_energy(ctx, prec, graph):
     prob.close()
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_config2_energy(ctx, prec):
     wl = W.CONFIGS[2]
-    prob = GpuProblem(ctx, wl)
+    prob = GpuProblem(ctx, wl, prec_mask=7)
     st, e, stats, psi = run(ctx, prob, prec, wl.seed)
     E0 = reference_energy(wl.name)
     print("config2", prec, e, E0, (e - E0) / abs(E0), stats["restarts"], stats["hv_count"], stats["seconds"])
