@@ -89,6 +89,8 @@ struct d2d_sb {
     int m = 0, n = 0;
     int64_t Q[2] = {0, 0};
     unsigned prec_mask = 0;
+    std::vector<d2d::QN> qn1, qn4;     // block-state quantum numbers (block 1, block 4)
+    int ncols1 = 0, ncols4 = 0;
     // sector pairs
     std::vector<d2d::QN> pair_q;
     std::vector<d2d::SectorDev> pairs;

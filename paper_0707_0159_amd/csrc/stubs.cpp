@@ -3,14 +3,6 @@
 
 using namespace d2d;
 
-extern "C" d2d_status d2d_density_matrix(d2d_sb* sb, const double* psi, int side, int m_keep, d2d_block** new_block,
-                                         double* trunc_err, double* spectrum, int64_t* spectrum_len) {
-    (void)sb; (void)psi; (void)side; (void)m_keep; (void)new_block; (void)trunc_err; (void)spectrum;
-    (void)spectrum_len;
-    set_error("d2d_density_matrix is not built in this library version");
-    return D2D_EINVAL;
-}
-
 extern "C" d2d_status d2d_batch_create(d2d_ctx* ctx, d2d_sb* const* sbs, int n, d2d_batch** out) {
     (void)ctx; (void)sbs; (void)n;
     if (out) *out = nullptr;

@@ -250,6 +250,10 @@ extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d
     sb->Q[0] = target_q[0];
     sb->Q[1] = target_q[1];
     sb->prec_mask = prec_mask;
+    sb->qn1 = b1->qn;
+    sb->qn4 = b4->qn;
+    sb->ncols1 = b1->ncols;
+    sb->ncols4 = b4->ncols;
     ctx->children++;   // undone by the destructor path below on failure
     struct Guard {
         std::unique_ptr<d2d_sb>* p;

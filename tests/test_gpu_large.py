@@ -1,0 +1,91 @@
+"""Full-size parity on the large workloads (3-leg Hubbard m=400, 4-leg Heisenberg m=1000).
+
+Every element of w = Hv is compared with the oracle's matrix-form product at the
+real superblock size (N = 3e7 .. 4e7), in the launch configuration the
+benchmark uses (autotuned tiles); ground energies against the reference
+energies written by the oracle.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from helpers import GpuProblem, oracle_superblock, reference_energy, rel_err
+from test_gpu_hv import bf16_bits, oracle_hv_bf16_operands
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(1200)]
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_0707_0159_amd import d2d
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    c = d2d.d2d_ctx_create(0)
+    yield c
+    torch.cuda.synchronize()
+    d2d.d2d_ctx_destroy(c)
+
+
+@pytest.fixture(scope="module", params=[3, 4])
+def problem(request, ctx):
+    wl = W.CONFIGS[request.param]
+    print(f"building {wl.name}", flush=True)
+    osb = oracle_superblock(wl)
+    prob = GpuProblem(ctx, wl, prec_mask=7)
+    yield wl, osb, prob
+    prob.close()
+
+
+def hv(ctx, prob, prec, v):
+    from paper_0707_0159_amd import d2d
+    with torch.cuda.stream(ctx.stream):
+        if prec == d2d.D2D_BF16:
+            vd = torch.as_tensor(bf16_bits(v).view(np.int16)).to("cuda")
+            wd = torch.empty(v.size, dtype=torch.float32, device="cuda")
+        else:
+            vd = torch.as_tensor(v, dtype=torch.float64 if prec == 0 else torch.float32).to("cuda")
+            wd = torch.empty_like(vd)
+        d2d.d2d_hv(prob.sb, prec, vd, wd)
+    ctx.stream.synchronize()
+    out = wd.double().cpu().numpy()
+    del vd, wd
+    return out
+
+
+def test_full_size_hv(ctx, problem):
+    from paper_0707_0159_amd import d2d
+    wl, osb, prob = problem
+    assert prob.info["n"] == osb.N
+    qL, dL, dR, off = d2d.d2d_sb_sectors(prob.sb)
+    assert [tuple(q) for q in qL] == [s[0] for s in osb.sectors]
+    for prec in (0, 1, 2):
+        d2d.d2d_sb_autotune(prob.sb, prec, reps=3)
+    v = W.random_vector(osb.N, 1000)
+    ref = osb.hv_factored(v)
+    e64 = rel_err(hv(ctx, prob, 0, v), ref)
+    e32 = rel_err(hv(ctx, prob, 1, v), ref)
+    w16 = hv(ctx, prob, 2, v)
+    e16 = rel_err(w16, ref)
+    e16b = rel_err(w16, oracle_hv_bf16_operands(osb, v))
+    print(f"{wl.name}: N={osb.N} fp64 {e64:.3e} fp32 {e32:.3e} bf16 {e16:.3e} (vs bf16-operand oracle {e16b:.3e})")
+    assert e64 <= 1e-12
+    assert e32 <= 1e-5
+    assert e16b <= 1e-5
+    assert e16 <= 2e-2
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_full_size_energy(ctx, problem, prec):
+    from paper_0707_0159_amd import d2d
+    wl, osb, prob = problem
+    E0 = reference_energy(wl.name)
+    n = prob.info["n"]
+    with torch.cuda.stream(ctx.stream):
+        v0 = torch.as_tensor(W.random_vector(n, wl.seed)).to("cuda")
+    ctx.stream.synchronize()
+    opts = d2d.lanczos_opts(prec=prec, k_in=24, max_restarts=400, tol_res=1e-8, use_graph=1)
+    st, e, stats = d2d.d2d_lanczos(prob.sb, opts, v0)
+    print(f"{wl.name} prec {prec}: E={e:.14f} ref {E0:.14f} dE {(e - E0) / abs(E0):.2e} "
+          f"restarts {stats['restarts']} hv {stats['hv_count']} {stats['seconds']:.3f}s")
+    assert st == 0
+    assert abs(e - E0) <= 1e-10 * abs(E0)
