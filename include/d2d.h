@@ -226,7 +226,8 @@ d2d_status d2d_tile_shapes(int* count, int* desc);
  * All recurrences, dot products, the tridiagonal solve and the Ritz vector
  * are FP64 on the device; the host reads (theta_j, rho_j) once per restart.
  * Precision schedule: start in opts.prec; if rho_{j+1} > escalate * rho_j the
- * precision is raised (BF16 -> FP32 -> FP64).
+ * precision is raised (BF16 -> FP32 -> FP64).  k_in is capped at the problem
+ * dimension.
  * Convergence: rho_j <= tol_res * |theta_j|.
  * v0: device FP64 start vector of length n (required, need not be normalised).
  * energy: host out, the last theta.  psi: device out (nullable), the unit
@@ -234,7 +235,7 @@ d2d_status d2d_tile_shapes(int* count, int* desc);
  * max_restarts is reached. */
 typedef struct {
     int prec;            /* Hv precision of the inner steps                    */
-    int k_in;            /* Krylov dimension per restart (2..128)              */
+    int k_in;            /* Krylov dimension per restart (2..33)               */
     int max_restarts;
     double tol_res;      /* relative residual |r|/|theta|                      */
     double escalate;     /* precision raise threshold on rho_{j+1}/rho_j        */

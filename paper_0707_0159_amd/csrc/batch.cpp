@@ -1,0 +1,402 @@
+// Batches of independent superblocks of uneven size.  The sector tables,
+// operators and central-term tables of all problems are concatenated, so one
+// grouped-GEMM launch (work list sorted longest-first across problems) and one
+// central-term launch cover every sector of every problem; the Lanczos vector
+// kernels are segmented per problem.  Converged problems leave the work lists
+// at the next restart.
+#include <algorithm>
+#include <cstring>
+
+#include "host.h"
+
+using namespace d2d;
+
+struct d2d_batch {
+    d2d_ctx* ctx = nullptr;
+    std::vector<d2d_sb*> sbs;
+    unsigned prec_mask = 0;
+    std::vector<SectorDev> pairs;       // rebased
+    std::vector<int> pair_prob;
+    std::vector<int64_t> voff, len;
+    int64_t ntot = 0;
+    int max_dl = 0, max_dr = 0;
+    SectorDev* d_sec = nullptr;
+    void* HL[3] = {nullptr, nullptr, nullptr};
+    void* HR[3] = {nullptr, nullptr, nullptr};
+    size_t hl_bytes[3] = {0, 0, 0}, hr_bytes[3] = {0, 0, 0};
+    int K = 0;
+    int64_t Drows = 0, Dcols = 0;
+    int32_t *d_src = nullptr, *d_rmap = nullptr, *d_cmap = nullptr;
+    double *d_rc64 = nullptr, *d_cc64 = nullptr;
+    float *d_rc32 = nullptr, *d_cc32 = nullptr;
+    int4* d_ctiles = nullptr;
+    int n_ctiles = 0, cap_ctiles = 0;
+    int4* d_ptiles = nullptr;
+    int n_ptiles = 0, cap_ptiles = 0;
+    bf16_t *d_vp = nullptr, *d_vt = nullptr;
+    int64_t vp_len = 0, vt_len = 0;
+    std::map<int, std::pair<WorkItem*, int>> work;   // shape -> (table, count), active problems only
+    std::map<int, int> work_cap;
+    std::vector<int> active;
+    int64_t hv_count[3] = {0, 0, 0};
+    void* stage_v = nullptr;
+    void* stage_w = nullptr;
+    LanczosWork* lz = nullptr;
+    ~d2d_batch();
+};
+
+namespace {
+
+template <typename T>
+void dfree(d2d_ctx* c, T*& p, size_t count) {
+    if (p) c->free((void*)p, count * sizeof(T));
+    p = nullptr;
+}
+
+template <typename T>
+d2d_status dupload(d2d_ctx* c, const std::vector<T>& h, T** d) {
+    *d = nullptr;
+    if (h.empty()) return D2D_OK;
+    D2D_CHECK(c->alloc((void**)d, h.size() * sizeof(T)));
+    D2D_HIP(hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return D2D_OK;
+}
+
+int batch_auto_tile(const d2d_batch* b, int prec) {
+    const int D = std::max(b->max_dl, b->max_dr);
+    if (prec == D2D_FP64) return D <= 64 ? 0 : (D <= 768 ? 1 : 2);
+    if (prec == D2D_FP32) return D <= 64 ? 3 : (D <= 768 ? 4 : 5);
+    return D <= 64 ? 17 : (D <= 512 ? 14 : 15);
+}
+
+// Launch tables of the active problems (work list of one shape, central and pack tiles).
+d2d_status build_work(d2d_batch* b, int shape) {
+    const TileShape& ts = tile_shape(shape);
+    std::vector<WorkItem> w;
+    for (size_t p = 0; p < b->pairs.size(); ++p) {
+        if (!b->active[b->pair_prob[p]]) continue;
+        const int dL = b->pairs[p].dL, dR = b->pairs[p].dR;
+        const int tm = (dL + ts.BM - 1) / ts.BM, tn = (dR + ts.BN - 1) / ts.BN;
+        for (int j = 0; j < tn; ++j)
+            for (int i = 0; i < tm; ++i) w.push_back({(int32_t)p, i, j, dL + dR});
+    }
+    std::stable_sort(w.begin(), w.end(), [](const WorkItem& x, const WorkItem& y) { return x.cost > y.cost; });
+    auto it = b->work.find(shape);
+    if (it != b->work.end() && b->work_cap[shape] < (int)w.size()) {
+        dfree(b->ctx, it->second.first, (size_t)b->work_cap[shape]);
+        b->work.erase(it);
+        it = b->work.end();
+    }
+    if (it == b->work.end()) {
+        WorkItem* d = nullptr;
+        const size_t cap = std::max<size_t>(w.size(), 1);
+        D2D_CHECK(b->ctx->alloc((void**)&d, cap * sizeof(WorkItem)));
+        b->work[shape] = {d, 0};
+        b->work_cap[shape] = (int)cap;
+    }
+    auto& e = b->work[shape];
+    if (!w.empty()) D2D_HIP(hipMemcpy(e.first, w.data(), w.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+    e.second = (int)w.size();
+    return D2D_OK;
+}
+
+d2d_status build_tiles(d2d_batch* b) {
+    std::vector<int4> ct, pt;
+    for (size_t p = 0; p < b->pairs.size(); ++p) {
+        if (!b->active[b->pair_prob[p]]) continue;
+        const int dL = b->pairs[p].dL, dR = b->pairs[p].dR;
+        for (int j = 0; j < (dR + 7) / 8; ++j)
+            for (int i = 0; i < (dL + 63) / 64; ++i) ct.push_back(make_int4((int)p, i, j, 0));
+        for (int j = 0; j < (dR + 63) / 64; ++j)
+            for (int i = 0; i < (dL + 63) / 64; ++i) pt.push_back(make_int4((int)p, i, j, 0));
+    }
+    if ((int)ct.size() > b->cap_ctiles) {
+        dfree(b->ctx, b->d_ctiles, (size_t)b->cap_ctiles);
+        b->cap_ctiles = (int)std::max<size_t>(ct.size(), 1);
+        D2D_CHECK(b->ctx->alloc((void**)&b->d_ctiles, (size_t)b->cap_ctiles * sizeof(int4)));
+    }
+    if ((int)pt.size() > b->cap_ptiles) {
+        dfree(b->ctx, b->d_ptiles, (size_t)b->cap_ptiles);
+        b->cap_ptiles = (int)std::max<size_t>(pt.size(), 1);
+        D2D_CHECK(b->ctx->alloc((void**)&b->d_ptiles, (size_t)b->cap_ptiles * sizeof(int4)));
+    }
+    if (!ct.empty()) D2D_HIP(hipMemcpy(b->d_ctiles, ct.data(), ct.size() * sizeof(int4), hipMemcpyHostToDevice));
+    if (!pt.empty()) D2D_HIP(hipMemcpy(b->d_ptiles, pt.data(), pt.size() * sizeof(int4), hipMemcpyHostToDevice));
+    b->n_ctiles = (int)ct.size();
+    b->n_ptiles = (int)pt.size();
+    return D2D_OK;
+}
+
+HvTables tables_of(d2d_batch* b) {
+    HvTables t{};
+    t.sec = b->d_sec;
+    t.npairs = (int)b->pairs.size();
+    for (int p = 0; p < 3; ++p) {
+        t.HL[p] = b->HL[p];
+        t.HR[p] = b->HR[p];
+    }
+    t.K = b->K;
+    t.src = b->d_src;
+    t.rmap = b->d_rmap;
+    t.cmap = b->d_cmap;
+    t.rcoef64 = b->d_rc64;
+    t.ccoef64 = b->d_cc64;
+    t.rcoef32 = b->d_rc32;
+    t.ccoef32 = b->d_cc32;
+    t.Drows = b->Drows;
+    t.Dcols = b->Dcols;
+    t.ctiles = b->d_ctiles;
+    t.n_ctiles = b->n_ctiles;
+    t.ptiles = b->d_ptiles;
+    t.n_ptiles = b->n_ptiles;
+    t.vp = b->d_vp;
+    t.vt = b->d_vt;
+    return t;
+}
+
+d2d_status batch_hv(d2d_batch* b, int prec, const void* v, void* w, hipStream_t s) {
+    if (prec < 0 || prec > 2 || !(b->prec_mask & (1u << prec)) || !b->HL[prec]) {
+        set_error("precision %d not kept by every superblock of the batch", prec);
+        return D2D_EINVAL;
+    }
+    const int shape = batch_auto_tile(b, prec);
+    if (b->work.find(shape) == b->work.end()) D2D_CHECK(build_work(b, shape));
+    auto& wl = b->work[shape];
+    return hv_launch(tables_of(b), prec, shape, wl.first, wl.second, v, w, s, nullptr);
+}
+
+struct BatchHv : HvOps {
+    d2d_batch* b;
+    explicit BatchHv(d2d_batch* x) : b(x) {}
+    d2d_status hv(int prec, const void* v, void* w, hipStream_t s) override { return batch_hv(b, prec, v, w, s); }
+    d2d_status prepare(int prec) override {
+        const int shape = batch_auto_tile(b, prec);
+        if (b->work.find(shape) == b->work.end()) return build_work(b, shape);
+        return D2D_OK;
+    }
+    d2d_status set_active(const std::vector<int>& a, bool* rebuilt) override {
+        if (rebuilt) *rebuilt = false;
+        if (a == b->active) return D2D_OK;
+        b->active = a;
+        std::vector<int> shapes;
+        for (auto& kv : b->work) shapes.push_back(kv.first);
+        for (int sh : shapes) D2D_CHECK(build_work(b, sh));
+        D2D_CHECK(build_tiles(b));
+        if (rebuilt) *rebuilt = true;
+        return D2D_OK;
+    }
+    bool has(int prec) override { return (b->prec_mask & (1u << prec)) && b->HL[prec]; }
+    void count(int prec, int64_t n) override { b->hv_count[prec] += n; }
+    int64_t counter(int prec) override { return b->hv_count[prec]; }
+};
+
+}  // namespace
+
+d2d_batch::~d2d_batch() {
+    free_lanczos_work(ctx, lz);
+    const size_t np = pairs.size();
+    dfree(ctx, d_sec, np);
+    for (int p = 0; p < 3; ++p) {
+        if (HL[p]) ctx->free(HL[p], hl_bytes[p]);
+        if (HR[p]) ctx->free(HR[p], hr_bytes[p]);
+    }
+    dfree(ctx, d_src, np * K);
+    dfree(ctx, d_rmap, (size_t)K * Drows);
+    dfree(ctx, d_cmap, (size_t)K * Dcols);
+    dfree(ctx, d_rc64, (size_t)K * Drows);
+    dfree(ctx, d_cc64, (size_t)K * Dcols);
+    dfree(ctx, d_rc32, (size_t)K * Drows);
+    dfree(ctx, d_cc32, (size_t)K * Dcols);
+    dfree(ctx, d_ctiles, (size_t)cap_ctiles);
+    dfree(ctx, d_ptiles, (size_t)cap_ptiles);
+    dfree(ctx, d_vp, (size_t)vp_len);
+    dfree(ctx, d_vt, (size_t)vt_len);
+    for (auto& kv : work) dfree(ctx, kv.second.first, (size_t)work_cap[kv.first]);
+    if (stage_v) ctx->free(stage_v, (size_t)ntot * 8);
+    if (stage_w) ctx->free(stage_w, (size_t)ntot * 8);
+}
+
+extern "C" d2d_status d2d_batch_create(d2d_ctx* ctx, d2d_sb* const* sbs, int n, d2d_batch** out) {
+    if (!ctx || !sbs || !out || n < 1) {
+        set_error("d2d_batch_create: bad argument");
+        return D2D_EINVAL;
+    }
+    *out = nullptr;
+    auto b = std::make_unique<d2d_batch>();
+    b->ctx = ctx;
+    b->prec_mask = 7u;
+    for (int i = 0; i < n; ++i) {
+        if (!sbs[i] || sbs[i]->ctx != ctx) {
+            set_error("d2d_batch_create: superblock %d is NULL or of another context", i);
+            return D2D_EINVAL;
+        }
+        b->sbs.push_back(sbs[i]);
+        b->prec_mask &= sbs[i]->prec_mask;
+        b->K = std::max(b->K, sbs[i]->K);
+    }
+    // concatenation offsets
+    int64_t voff = 0, hl = 0, hr = 0, h16 = 0, r16 = 0, vp = 0, vt = 0, rb = 0, cb = 0;
+    std::vector<int> pbase(n);
+    for (int i = 0; i < n; ++i) {
+        const d2d_sb* s = sbs[i];
+        pbase[i] = (int)b->pairs.size();
+        for (const SectorDev& q0 : s->pairs) {
+            SectorDev q = q0;
+            q.off += voff;
+            q.hl_off += hl;
+            q.hr_off += hr;
+            q.row_base += rb;
+            q.col_base += cb;
+            q.hl16_off += h16;
+            q.hr16_off += r16;
+            q.vp_off += vp;
+            q.vt_off += vt;
+            b->pairs.push_back(q);
+            b->pair_prob.push_back(i);
+        }
+        b->voff.push_back(voff);
+        b->len.push_back(s->N);
+        b->max_dl = std::max(b->max_dl, s->max_dl);
+        b->max_dr = std::max(b->max_dr, s->max_dr);
+        voff += s->N;
+        hl += s->hl_len;
+        hr += s->hr_len;
+        h16 += s->hl16_len;
+        r16 += s->hr16_len;
+        vp += s->vp_len;
+        vt += s->vt_len;
+        rb += s->Drows;
+        cb += s->Dcols;
+    }
+    b->ntot = voff;
+    b->Drows = rb;
+    b->Dcols = cb;
+    b->vp_len = vp;
+    b->vt_len = vt;
+    D2D_CHECK(dupload(ctx, b->pairs, &b->d_sec));
+    // operators: device-to-device concatenation
+    const size_t esz[3] = {8, 4, 2};
+    for (int p = 0; p < 3; ++p) {
+        if (!(b->prec_mask & (1u << p))) continue;
+        b->hl_bytes[p] = (size_t)(p == 2 ? h16 : hl) * esz[p];
+        b->hr_bytes[p] = (size_t)(p == 2 ? r16 : hr) * esz[p];
+        D2D_CHECK(ctx->alloc(&b->HL[p], b->hl_bytes[p]));
+        D2D_CHECK(ctx->alloc(&b->HR[p], b->hr_bytes[p]));
+        size_t ol = 0, orr = 0;
+        for (int i = 0; i < n; ++i) {
+            const d2d_sb* s = sbs[i];
+            const size_t bl = (size_t)(p == 2 ? s->hl16_len : s->hl_len) * esz[p];
+            const size_t br = (size_t)(p == 2 ? s->hr16_len : s->hr_len) * esz[p];
+            D2D_HIP(hipMemcpy((char*)b->HL[p] + ol, s->HL[p], bl, hipMemcpyDeviceToDevice));
+            D2D_HIP(hipMemcpy((char*)b->HR[p] + orr, s->HR[p], br, hipMemcpyDeviceToDevice));
+            ol += bl;
+            orr += br;
+        }
+    }
+    if (b->prec_mask & (1u << D2D_BF16)) {
+        D2D_CHECK(ctx->alloc((void**)&b->d_vp, (size_t)vp * 2));
+        D2D_CHECK(ctx->alloc((void**)&b->d_vt, (size_t)vt * 2));
+        D2D_HIP(hipMemset(b->d_vp, 0, (size_t)vp * 2));
+        D2D_HIP(hipMemset(b->d_vt, 0, (size_t)vt * 2));
+    }
+    // central tables padded to K terms, source pairs rebased
+    const int K = b->K;
+    const size_t np = b->pairs.size();
+    std::vector<int32_t> src(np * K, -1), rmap((size_t)K * rb, -1), cmap((size_t)K * cb, -1);
+    std::vector<double> rc((size_t)K * rb, 0.0), cc((size_t)K * cb, 0.0);
+    int64_t rbase = 0, cbase = 0;
+    for (int i = 0; i < n; ++i) {
+        const d2d_sb* s = sbs[i];
+        const int Ki = s->K;
+        for (size_t p = 0; p < s->pairs.size(); ++p)
+            for (int k = 0; k < Ki; ++k) {
+                const int32_t q = s->h_src[p * Ki + k];
+                src[(pbase[i] + p) * K + k] = q >= 0 ? q + pbase[i] : -1;
+            }
+        for (int k = 0; k < Ki; ++k) {
+            for (int64_t r = 0; r < s->Drows; ++r) {
+                rmap[(size_t)k * rb + rbase + r] = s->h_rmap[(size_t)k * s->Drows + r];
+                rc[(size_t)k * rb + rbase + r] = s->h_rc[(size_t)k * s->Drows + r];
+            }
+            for (int64_t c = 0; c < s->Dcols; ++c) {
+                cmap[(size_t)k * cb + cbase + c] = s->h_cmap[(size_t)k * s->Dcols + c];
+                cc[(size_t)k * cb + cbase + c] = s->h_cc[(size_t)k * s->Dcols + c];
+            }
+        }
+        rbase += s->Drows;
+        cbase += s->Dcols;
+    }
+    std::vector<float> rc32(rc.begin(), rc.end()), cc32(cc.begin(), cc.end());
+    D2D_CHECK(dupload(ctx, src, &b->d_src));
+    D2D_CHECK(dupload(ctx, rmap, &b->d_rmap));
+    D2D_CHECK(dupload(ctx, cmap, &b->d_cmap));
+    D2D_CHECK(dupload(ctx, rc, &b->d_rc64));
+    D2D_CHECK(dupload(ctx, cc, &b->d_cc64));
+    D2D_CHECK(dupload(ctx, rc32, &b->d_rc32));
+    D2D_CHECK(dupload(ctx, cc32, &b->d_cc32));
+    b->active.assign(n, 1);
+    D2D_CHECK(build_tiles(b.get()));
+    D2D_CHECK(ctx->alloc(&b->stage_v, (size_t)b->ntot * 8));
+    D2D_CHECK(ctx->alloc(&b->stage_w, (size_t)b->ntot * 8));
+    ctx->children++;
+    *out = b.release();
+    return D2D_OK;
+}
+
+extern "C" d2d_status d2d_batch_destroy(d2d_batch* b) {
+    if (!b) return D2D_OK;
+    d2d_ctx* c = b->ctx;
+    (void)hipStreamSynchronize(c->stream);
+    delete b;
+    c->children--;
+    return D2D_OK;
+}
+
+extern "C" d2d_status d2d_batch_hv(d2d_batch* b, int prec, const void* const* v, void* const* w) {
+    if (!b || !v || !w || prec < 0 || prec > 2) {
+        set_error("d2d_batch_hv: bad argument");
+        return D2D_EINVAL;
+    }
+    const int n = (int)b->sbs.size();
+    const size_t in_sz = prec == D2D_FP64 ? 8 : (prec == D2D_FP32 ? 4 : 2);
+    const size_t out_sz = prec == D2D_FP64 ? 8 : 4;
+    hipStream_t s = b->ctx->stream;
+    std::vector<int> all(n, 1);
+    BatchHv ops(b);
+    bool rebuilt = false;
+    D2D_CHECK(ops.set_active(all, &rebuilt));
+    for (int i = 0; i < n; ++i) {
+        if (!v[i] || !w[i]) {
+            set_error("d2d_batch_hv: NULL vector of problem %d", i);
+            return D2D_EINVAL;
+        }
+        D2D_HIP(hipMemcpyAsync((char*)b->stage_v + b->voff[i] * in_sz, v[i], (size_t)b->len[i] * in_sz,
+                               hipMemcpyDeviceToDevice, s));
+    }
+    D2D_CHECK(batch_hv(b, prec, b->stage_v, b->stage_w, s));
+    b->hv_count[prec]++;
+    for (int i = 0; i < n; ++i)
+        D2D_HIP(hipMemcpyAsync(w[i], (char*)b->stage_w + b->voff[i] * out_sz, (size_t)b->len[i] * out_sz,
+                               hipMemcpyDeviceToDevice, s));
+    return D2D_OK;
+}
+
+extern "C" d2d_status d2d_batch_lanczos(d2d_batch* b, const d2d_lanczos_opts* opts, const double* const* v0,
+                                        double* energies, double* const* psi, d2d_lanczos_stats* per_problem) {
+    if (!b || !opts || !v0 || !energies) {
+        set_error("d2d_batch_lanczos: NULL argument");
+        return D2D_EINVAL;
+    }
+    D2D_CHECK(check_lanczos_opts(opts));
+    if (!(b->prec_mask & (1u << opts->prec))) {
+        set_error("d2d_batch_lanczos: precision %d not kept by every superblock", opts->prec);
+        return D2D_EINVAL;
+    }
+    for (size_t i = 0; i < b->sbs.size(); ++i)
+        if (!v0[i]) {
+            set_error("d2d_batch_lanczos: NULL start vector %zu", i);
+            return D2D_EINVAL;
+        }
+    BatchHv ops(b);
+    return run_lanczos(b->ctx, b->lz, ops, opts, b->len, v0, energies, psi, per_problem);
+}

@@ -81,7 +81,66 @@ struct d2d_block {
     std::vector<double> parity() const;
 };
 
-struct LanczosWork;
+// Workspace of a restarted Lanczos over a set of problems (vectors concatenated).
+struct LanczosWork {
+    int kmax = 0, nprob = 0, NB = 0;
+    int64_t ntot = 0;
+    std::vector<int64_t> seg_off, seg_len;
+    double* Q = nullptr;         // (kmax+1) x ntot
+    double* X = nullptr;
+    double* W = nullptr;
+    float* wlo = nullptr;
+    float* vlo = nullptr;        // FP32 input (BF16 uses it as uint16 storage)
+    double* partial = nullptr;   // 2 x 34 x NB
+    double* scal = nullptr;      // nprob x S_LEN
+    double* res = nullptr;       // 2 x nprob
+    double* res_host = nullptr;  // pinned copy of res
+    d2d::LzSeg* bt = nullptr;
+    int2* prange = nullptr;
+    int* active = nullptr;
+    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+    hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+    int graph_k[3] = {0, 0, 0};
+};
+
+namespace d2d {
+// Device tables of one grouped Hv launch sequence (one superblock or a batch).
+struct HvTables {
+    const SectorDev* sec;
+    int npairs;
+    const void* HL[3];
+    const void* HR[3];
+    int K;
+    const int32_t* src;
+    const int32_t* rmap;
+    const int32_t* cmap;
+    const double* rcoef64;
+    const double* ccoef64;
+    const float* rcoef32;
+    const float* ccoef32;
+    int64_t Drows, Dcols;
+    const int4* ctiles;
+    int n_ctiles;
+    const int4* ptiles;
+    int n_ptiles;
+    bf16_t* vp;
+    bf16_t* vt;
+};
+// pack (BF16) + grouped GEMM + central term; `mid` (nullable) is recorded after the GEMM
+d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkItem* work, int nwork, const void* v,
+                     void* w, hipStream_t s, hipEvent_t mid);
+
+// Hv of a set of problems on concatenated vectors (one superblock or a batch).
+struct HvOps {
+    virtual ~HvOps() = default;
+    virtual d2d_status hv(int prec, const void* v, void* w, hipStream_t s) = 0;   // no counting
+    virtual d2d_status prepare(int prec) = 0;                                      // before graph capture
+    virtual d2d_status set_active(const std::vector<int>& active, bool* rebuilt) = 0;
+    virtual bool has(int prec) = 0;
+    virtual void count(int prec, int64_t n) = 0;
+    virtual int64_t counter(int prec) = 0;
+};
+}  // namespace d2d
 
 struct d2d_sb {
     d2d_ctx* ctx = nullptr;
@@ -120,6 +179,9 @@ struct d2d_sb {
     int4* d_ptiles = nullptr;          // pack launch table (pair, 64-row tile, 64-column tile)
     int n_ptiles = 0;
     int n_cblocks = 0;
+    // host copies of the central tables (used to build batches)
+    std::vector<int32_t> h_src, h_rmap, h_cmap;
+    std::vector<double> h_rc, h_cc;
     // work lists per tile shape
     std::map<int, std::pair<d2d::WorkItem*, int>> work;
     int tile_sel[3] = {-1, -1, -1};
@@ -130,6 +192,13 @@ struct d2d_sb {
 
 namespace d2d {
 d2d_status sb_hv(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s);
+d2d_status sb_hv_nocount(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s);
+void free_lanczos_work(d2d_ctx* c, LanczosWork*& lw);
+d2d_status ensure_lanczos_work(d2d_ctx* c, LanczosWork*& lw, const std::vector<int64_t>& len, int kmax);
+d2d_status check_lanczos_opts(const d2d_lanczos_opts* o);
+d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanczos_opts* opts,
+                       const std::vector<int64_t>& len, const double* const* v0, double* energies,
+                       double* const* psi, d2d_lanczos_stats* stats);
 d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s, hipEvent_t mid);
 int sb_auto_tile(const d2d_sb* sb, int prec);
 d2d_status sb_work(d2d_sb* sb, int shape, WorkItem** w, int* nwork);

@@ -138,68 +138,70 @@ hipError_t launch_fill(void* x, int prec, int64_t n, double v, hipStream_t s);
 hipError_t launch_check_finite(const void* x, int prec, int64_t n, int* flag, hipStream_t s);
 
 // ---------------------------------------------------------------- Lanczos kernels
-int lz_nblocks(int64_t n);
-// partial[j*NB + b] = sum over block b of Q[j][e]*w[e], j < nq; if Tw is float the
-// FP32 input is upcast and written to w64 as well.
-hipError_t launch_dots_f64(const double* Q, int64_t ldq, int nq, const double* w, int64_t n,
-                           double* partial, hipStream_t s);
-hipError_t launch_upcast_dots(const double* Q, int64_t ldq, int nq, const float* w32, double* w64,
-                              int64_t n, double* partial, hipStream_t s);
-// out[j] = sum_b partial[j*NB + b]
-hipError_t launch_reduce(const double* partial, int nq, int nb, double* out, hipStream_t s);
-// w -= sum_j c[j] Q[j]; if partial != null: partial sums of |w|^2 (one vector).
-hipError_t launch_update(const double* Q, int64_t ldq, int nq, const double* c, double* w, int64_t n,
-                         double* partial_norm, hipStream_t s);
-// scal ops (single thread)
-hipError_t launch_step_scalars(int i, const double* c1, const double* c2, const double* nrm2,
-                               double* alpha, double* beta, double* flags, hipStream_t s);
-// Qnext = w / beta[i+1]; lo = cast(Qnext) in prec (FP32 or BF16; none for FP64)
-hipError_t launch_scale_store(const double* w, const double* beta_ip1, double* qnext, void* lo,
-                              int lo_prec, int64_t n, hipStream_t s);
-// x = sum_j y[j] Q[j]; partial |x|^2
-hipError_t launch_ritz(const double* Q, int64_t ldq, int k, const double* y, double* x, int64_t n,
-                       double* partial_norm, hipStream_t s);
-// x *= 1/sqrt(nrm2[0])
-hipError_t launch_normalize(double* x, const double* nrm2, int64_t n, hipStream_t s);
-// r = w - theta x (theta = dots[0]), in place in w; partial |r|^2
-hipError_t launch_residual(const double* x, const double* theta, double* w, int64_t n,
-                           double* partial_norm, hipStream_t s);
 // lowest eigenpair of the k x k tridiagonal (alpha[0..k-1], beta[1..k-1])
 hipError_t launch_tridiag(const double* alpha, const double* beta, int k, double* theta,
                           double* y, double* work, hipStream_t s);
-// res[0] = theta, res[1] = sqrt(nrm2), alpha[0] = theta, beta[1] = sqrt(nrm2)
-hipError_t launch_restart_scalars(const double* theta, const double* nrm2, double* alpha, double* beta,
-                                  double* res, hipStream_t s);
-hipError_t launch_copy_f64(const double* x, double* y, int64_t n, hipStream_t s);
-// y = x / |x| with |x|^2 in nrm2 (device scalar)
-hipError_t launch_scale_copy(const double* x, const double* nrm2, double* y, int64_t n, hipStream_t s);
 
-// Fused Lanczos step i (nq = i+1 <= 32 basis vectors), three kernels:
-// c1 = Q^T w (w upcast from w32 first if upcast), w -= Q c1, c2 = Q^T w,
-// alpha[i] = c1[i] + c2[i], beta[i+1] = sqrt(|w|^2 - |c2|^2), and if
-// qnext != null: qnext = (w - [need2] Q c2) / beta[i+1], lo = cast(qnext).
+// ------------------------------------------------------------------ Lanczos sets
+// Scalar layout per problem (doubles), at scal + prob * S_LEN.
+constexpr int S_ALPHA = 0, S_BETA = 130, S_THETA = 524, S_Y = 528, S_TWORK = 660, S_LEN = 1400;
+
+// Block of a segmented kernel: problem, its block range [pb0, pb1), chunk [lo, hi).
+struct LzSeg {
+    int prob, pb0, pb1, pad;
+    int64_t lo, hi;
+};
+
+// A set of problems whose vectors are concatenated (offsets in the block table).
+struct LzSet {
+    int nprob;
+    int NB;                 // blocks of the segmented kernels
+    int64_t ntot;           // total vector length (leading dimension of Q)
+    const LzSeg* bt;        // [NB]
+    const int2* prange;     // [nprob] block range of each problem
+    const int* active;      // [nprob] 1 while the problem iterates
+    double* partial;        // two partial-sum buffers of 33 x NB
+    double* partial2;
+    double* scal;           // [nprob * S_LEN]
+    double* res;            // [2 nprob] (theta, rho) of the last residual
+};
+
+// Lanczos step i (nq = i+1 <= 32): c1 = Q^T w (w upcast from w32 first if
+// upcast), w -= Q c1, c2 = Q^T w, alpha_i = c1[i] + c2[i],
+// beta_{i+1} = sqrt(|w|^2 - |c2|^2), and if qnext != null:
+// qnext = (w - [need2] Q c2) / beta_{i+1}, lo = cast(qnext).
 struct LzStepArgs {
+    const LzSeg* bt;
+    const int* active;
     const double* Q;
-    int64_t n;
+    int64_t ldq;
     int nq, i;
     bool upcast;
     const float* w32;
     double* w;
-    double* partial;     // two partial-sum buffers of (33 x 256) doubles
+    double* partial;
     double* partial2;
-    double *alpha, *beta;
+    int NB;
+    double* scal;
     double* qnext;
     void* lo;
     int lo_prec;
 };
 int lz_step_blocks(int64_t n);
 hipError_t launch_lz_step(const LzStepArgs& a, hipStream_t s);
-// theta = x.w, w -= theta x, rho = |w|; alpha[0] = theta, beta[1] = rho, res[0..1] = (theta, rho)
-hipError_t launch_lz_residual(const double* x, double* w, int64_t n, double* partial, double* partial2,
-                              double* alpha, double* beta, double* res, hipStream_t s);
-// x = Q y / |Q y|
-hipError_t launch_lz_ritz(const double* Q, int64_t ldq, int k, const double* y, double* x, int64_t n,
-                          double* partial, hipStream_t s);
+// theta = x.w, w -= theta x, rho = |w|; alpha_0 = theta, beta_1 = rho, res = (theta, rho)
+hipError_t launch_lz_residual(const LzSet& z, const double* x, double* w, hipStream_t s);
+// x = Q y / |Q y| per problem
+hipError_t launch_lz_ritz(const LzSet& z, const double* Q, int k, double* x, hipStream_t s);
+// x = v / |v| per problem
+hipError_t launch_lz_normalize_into(const LzSet& z, const double* v, double* x, hipStream_t s);
+// res[2p] = |v_p|^2
+hipError_t launch_lz_norms(const LzSet& z, const double* v, hipStream_t s);
+// Q[0] = x, Q[1] = w / beta_1, lo = cast(Q[1])
+hipError_t launch_lz_first(const LzSet& z, const double* x, const double* w, double* Q, void* lo, int lo_prec,
+                           hipStream_t s);
+// lowest eigenpair of each problem's k x k tridiagonal (theta at S_THETA+1, y at S_Y)
+hipError_t launch_lz_tridiag(const LzSet& z, int k, hipStream_t s);
 
 // density matrix: rho = V V^T (side 0) or V^T V (side 1) of a dL x dR block
 hipError_t launch_syrk_f64(const double* V, int dL, int dR, int side, double* rho, hipStream_t s);

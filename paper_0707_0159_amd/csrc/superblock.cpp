@@ -158,6 +158,71 @@ d2d_status sb_work(d2d_sb* sb, int shape, WorkItem** out, int* nwork) {
     return D2D_OK;
 }
 
+d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkItem* work, int nwork, const void* v,
+                     void* w, hipStream_t s, hipEvent_t mid) {
+    HvGemmArgs g{work, nwork, t.sec, t.HL[prec], t.HR[prec], v, w};
+    g.K = t.K;
+    g.src = t.src;
+    g.rmap = t.rmap;
+    g.cmap = t.cmap;
+    g.rcoef = prec == D2D_FP64 ? (const void*)t.rcoef64 : (const void*)t.rcoef32;
+    g.ccoef = prec == D2D_FP64 ? (const void*)t.ccoef64 : (const void*)t.ccoef32;
+    g.Drows = t.Drows;
+    g.Dcols = t.Dcols;
+    if (prec == D2D_BF16) {
+        D2D_HIP(launch_pack_bf16(t.ptiles, t.n_ptiles, t.sec, (const bf16_t*)v, t.vp, t.vt, s));
+        g.V = t.vp;
+        D2D_HIP(launch_hv_gemm_bf16(shape, g, t.vt, s));
+    } else {
+        D2D_HIP(launch_hv_gemm(shape, g, s));
+    }
+    if (mid) D2D_HIP(hipEventRecord(mid, s));
+    CentralArgs c{};
+    c.blocks = t.ctiles;
+    c.nblocks = t.n_ctiles;
+    c.sec = t.sec;
+    c.npairs = t.npairs;
+    c.K = t.K;
+    c.src = t.src;
+    c.rmap = t.rmap;
+    c.cmap = t.cmap;
+    c.rcoef = g.rcoef;
+    c.ccoef = g.ccoef;
+    c.Drows = t.Drows;
+    c.Dcols = t.Dcols;
+    c.V = v;   // the unpadded input in every precision
+    c.W = w;
+    D2D_HIP(launch_central(prec, c, s));
+    return D2D_OK;
+}
+
+static HvTables tables_of(d2d_sb* sb) {
+    HvTables t{};
+    t.sec = sb->d_sec;
+    t.npairs = (int)sb->pairs.size();
+    for (int p = 0; p < 3; ++p) {
+        t.HL[p] = sb->HL[p];
+        t.HR[p] = sb->HR[p];
+    }
+    t.K = sb->K;
+    t.src = sb->d_src;
+    t.rmap = sb->d_rmap;
+    t.cmap = sb->d_cmap;
+    t.rcoef64 = sb->d_rcoef64;
+    t.ccoef64 = sb->d_ccoef64;
+    t.rcoef32 = sb->d_rcoef32;
+    t.ccoef32 = sb->d_ccoef32;
+    t.Drows = sb->Drows;
+    t.Dcols = sb->Dcols;
+    t.ctiles = sb->d_cblocks;
+    t.n_ctiles = sb->n_cblocks;
+    t.ptiles = sb->d_ptiles;
+    t.n_ptiles = sb->n_ptiles;
+    t.vp = sb->d_vp;
+    t.vt = sb->d_vt;
+    return t;
+}
+
 d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s, hipEvent_t mid) {
     if (prec < 0 || prec > 2 || !(sb->prec_mask & (1u << prec)) || !sb->HL[prec]) {
         set_error("precision %d not available on this superblock", prec);
@@ -167,45 +232,17 @@ d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t
     WorkItem* work = nullptr;
     int nwork = 0;
     D2D_CHECK(sb_work(sb, shape, &work, &nwork));
-    HvGemmArgs g{work, nwork, sb->d_sec, sb->HL[prec], sb->HR[prec], v, w};
-    if (prec == D2D_BF16) {
-        D2D_HIP(launch_pack_bf16(sb->d_ptiles, sb->n_ptiles, sb->d_sec, (const bf16_t*)v, sb->d_vp, sb->d_vt, s));
-        g.V = sb->d_vp;
-        D2D_HIP(launch_hv_gemm_bf16(shape, g, sb->d_vt, s));
-    } else {
-    g.K = sb->K;
-    g.src = sb->d_src;
-    g.rmap = sb->d_rmap;
-    g.cmap = sb->d_cmap;
-    g.rcoef = prec == D2D_FP64 ? (const void*)sb->d_rcoef64 : (const void*)sb->d_rcoef32;
-    g.ccoef = prec == D2D_FP64 ? (const void*)sb->d_ccoef64 : (const void*)sb->d_ccoef32;
-    g.Drows = sb->Drows;
-    g.Dcols = sb->Dcols;
-    D2D_HIP(launch_hv_gemm(shape, g, s));
-    }
-    if (mid) D2D_HIP(hipEventRecord(mid, s));
-    CentralArgs c{};
-    c.blocks = sb->d_cblocks;
-    c.nblocks = sb->n_cblocks;
-    c.sec = sb->d_sec;
-    c.npairs = (int)sb->pairs.size();
-    c.K = sb->K;
-    c.src = sb->d_src;
-    c.rmap = sb->d_rmap;
-    c.cmap = sb->d_cmap;
-    c.rcoef = prec == D2D_FP64 ? (const void*)sb->d_rcoef64 : (const void*)sb->d_rcoef32;
-    c.ccoef = prec == D2D_FP64 ? (const void*)sb->d_ccoef64 : (const void*)sb->d_ccoef32;
-    c.Drows = sb->Drows;
-    c.Dcols = sb->Dcols;
-    c.V = v;   // the unpadded input in every precision
-    c.W = w;
-    D2D_HIP(launch_central(prec, c, s));
-    sb->hv_count[prec]++;
-    return D2D_OK;
+    return hv_launch(tables_of(sb), prec, shape, work, nwork, v, w, s, mid);
+}
+
+d2d_status sb_hv_nocount(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s) {
+    return sb_hv_parts(sb, prec, v, w, s, nullptr);
 }
 
 d2d_status sb_hv(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s) {
-    return sb_hv_parts(sb, prec, v, w, s, nullptr);
+    D2D_CHECK(sb_hv_parts(sb, prec, v, w, s, nullptr));
+    sb->hv_count[prec]++;
+    return D2D_OK;
 }
 
 }  // namespace d2d
@@ -478,6 +515,11 @@ extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d
     }
     sb->flops_central = 2.0 * (double)gathers;
     std::vector<float> rc32(rc.begin(), rc.end()), cc32(cc.begin(), cc.end());
+    sb->h_src = src;
+    sb->h_rmap = rmap;
+    sb->h_cmap = cmap;
+    sb->h_rc = rc;
+    sb->h_cc = cc;
     D2D_CHECK(upload(ctx, src, &sb->d_src));
     D2D_CHECK(upload(ctx, rmap, &sb->d_rmap));
     D2D_CHECK(upload(ctx, cmap, &sb->d_cmap));
@@ -623,6 +665,7 @@ extern "C" d2d_status d2d_hv_profile(d2d_sb* sb, int prec, const void* v, void* 
     for (int r = 0; r < reps && st == D2D_OK; ++r) {
         if (hipEventRecord(ev[3 * r], s) != hipSuccess) st = D2D_EDEVICE;
         if (st == D2D_OK) st = sb_hv_parts(sb, prec, v, w, s, ev[3 * r + 1]);
+        if (st == D2D_OK) sb->hv_count[prec]++;
         if (st == D2D_OK && hipEventRecord(ev[3 * r + 2], s) != hipSuccess) st = D2D_EDEVICE;
     }
     double g = 0.0, c = 0.0;
