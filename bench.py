@@ -3,15 +3,18 @@
 
 One step = one complete ground-state solve of the superblock (every row of the
 hot path: the grouped-GEMM Hv H_l V + V H_r^T, the central term, the FP64
-Lanczos recurrence with full reorthogonalisation, the tridiagonal eigensolve
-and the FP64 residual-corrected restarts) from the seeded start vector to the
-solver's convergence, with FP32-MFMA inner products (mixed precision).
-value = Hv applications of the K timed solves (FP32 + FP64) / wall time.
+Lanczos recurrence with reorthogonalisation, the tridiagonal eigensolve and
+the FP64 residual-corrected restarts) from the seeded start vector to the
+solver's convergence.  The headline path runs its inner Hv in FP32 on the
+matrix cores (mixed precision); value = Hv applications of the K timed solves
+(FP32 + FP64) / wall time.
 
-Also reported: the same solve on the pure FP64 path, time to energy (the
-solver's own stop, and the first restart within 1e-10 of the oracle energy),
-Hv-only rates per precision, the roofline of the dominant kernel (grouped
-GEMM, timed with HIP events on its stream), and the CPU oracle's Hv rate.
+Also reported, on the same algorithm: the BF16-input path (escalating to FP32
+if it stalls) and the pure FP64 path; time to energy of each (the solver's own
+stop, and the first restart within 1e-10 of the oracle energy); Hv-only rates
+per precision; the roofline of the dominant kernel (the grouped GEMM, timed
+with HIP events on the stream it runs on) and of the BF16 GEMM; and the CPU
+oracle's Hv rate on the host cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2]
 """
@@ -38,8 +41,8 @@ def kernel_source_hash() -> str:
 
 
 def traffic_record(workload: str, prec: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    """HBM bytes per launch of the grouped GEMM from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "hv_gemm_traffic.json")
     if not os.path.exists(path):
         return None
@@ -53,7 +56,6 @@ def traffic_record(workload: str, prec: str):
 
 def cpu_baseline(wl, seconds: float):
     """The oracle's Hv (the paper's matrix form, float64, numpy/scipy) on the host."""
-    import numpy as np
     from threadpoolctl import threadpool_info
 
     import workloads as W
@@ -85,13 +87,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--k-in", type=int, default=24)
+    ap.add_argument("--window", type=int, default=3, help="reorthogonalisation window (0 = full)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", choices=["hv", "copy"], default=None,
                     help="profiling runs for rocprofv3: 'hv' = only Hv launches of --prec, "
                          "'copy' = a plain device copy of known size (counter calibration)")
-    ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp32")
+    ap.add_argument("--prec", choices=["fp64", "fp32", "bf16"], default="fp32")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -126,35 +129,42 @@ def main():
     model = d2d.make_model(wl.kind, wl.legs, wl.t, wl.U, wl.J)
     b1 = d2d.d2d_block_import(ctx, model, raw["L"])
     b4 = d2d.d2d_block_import(ctx, model, raw["R"])
-    sb = d2d.d2d_sb_create(ctx, b1, b4, model, wl.target, (1 << d2d.D2D_FP64) | (1 << d2d.D2D_FP32))
+    sb = d2d.d2d_sb_create(ctx, b1, b4, model, wl.target, 7)
     info = d2d.d2d_sb_info(sb)
     N = info["n"]
     s = ctx.stream
     shapes = d2d.d2d_tile_shapes()
+    names = {d2d.D2D_FP64: "fp64", d2d.D2D_FP32: "fp32", d2d.D2D_BF16: "bf16"}
     tuned = {}
-    for name, prec in (("fp64", d2d.D2D_FP64), ("fp32", d2d.D2D_FP32)):
+    for prec, name in names.items():
         t, ms_t = d2d.d2d_sb_autotune(sb, prec, reps=10)
-        tuned[name] = {"tile": t, "BMxBNxBK": "x".join(str(x) for x in shapes[t][1:]), "ms": ms_t}
+        tuned[name] = {"tile": t & 0xFFFF, "split_k_loops": bool(t & d2d.D2D_TILE_SPLIT),
+                       "BMxBNxBK": "x".join(str(x) for x in shapes[t & 0xFFFF][1:]), "ms": ms_t}
     with torch.cuda.stream(s):
         v0 = torch.as_tensor(W.random_vector(N, wl.seed), device="cuda")
         psi = torch.zeros_like(v0)
     s.synchronize()
 
     if args.profile == "hv":
-        prec = d2d.D2D_FP32 if args.prec == "fp32" else d2d.D2D_FP64
+        prec = {"fp64": d2d.D2D_FP64, "fp32": d2d.D2D_FP32, "bf16": d2d.D2D_BF16}[args.prec]
         with torch.cuda.stream(s):
             x = torch.as_tensor(W.random_vector(N, 1000), device="cuda")
-            x = x.float() if prec == d2d.D2D_FP32 else x
-            w = torch.empty_like(x)
+            if prec == d2d.D2D_FP32:
+                x = x.float()
+            elif prec == d2d.D2D_BF16:
+                x = x.to(torch.bfloat16)
+            w = torch.empty(N, dtype=torch.float64 if prec == d2d.D2D_FP64 else torch.float32, device="cuda")
         for _ in range(args.steps):
             d2d.d2d_hv(sb, prec, x, w)
         s.synchronize()
         print(json.dumps({"profile": "hv", "prec": args.prec, "workload": wl.name, "launches": args.steps,
-                          "flops_exec": info["flops_exec"], "bytes_min": info["bytes_min_" + args.prec]}))
+                          "tile": tuned[args.prec], "flops_exec": info["flops_exec"],
+                          "bytes_min": info["bytes_min_" + args.prec]}))
         return
 
     def solve(prec):
-        opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol, use_graph=1)
+        opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol, use_graph=1,
+                                reorth_window=args.window)
         st, e, stats = d2d.d2d_lanczos(sb, opts, v0, psi)
         if st != 0:
             raise RuntimeError(f"Lanczos did not converge: {stats['residual']}")
@@ -168,66 +178,71 @@ def main():
                 return t
         return None
 
-    # ---------------------------------------------------------------- timed: mixed precision
-    for _ in range(args.warmup):
-        solve(d2d.D2D_FP32)
-    torch.cuda.synchronize()
-    hv = 0
-    t0 = time.perf_counter()
-    last = None
-    for _ in range(args.steps):
-        e, stats = solve(d2d.D2D_FP32)
-        hv += sum(stats["hv_count"])
-        last = (e, stats)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    e_mixed, st_mixed = last
+    def timed(prec, steps, warmup):
+        for _ in range(warmup):
+            solve(prec)
+        torch.cuda.synchronize()
+        hv = 0
+        t0 = time.perf_counter()
+        last = None
+        for _ in range(steps):
+            last = solve(prec)
+            hv += sum(last[1]["hv_count"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        e, st = last
+        return {"hv_per_s": hv / wall, "s_per_solve": wall / steps, "E": e,
+                "dE_rel": None if E0 is None else abs(e - E0) / abs(E0),
+                "first_within_1e-10_s": first_within(st), "restarts": st["restarts"],
+                "hv_count": st["hv_count"], "precision_log": st["log_prec"]}
 
-    # ---------------------------------------------------------------- FP64 path, same algorithm
-    solve(d2d.D2D_FP64)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    reps64 = max(1, min(args.steps, 5))
-    for _ in range(reps64):
-        e64, st64 = solve(d2d.D2D_FP64)
-    torch.cuda.synchronize()
-    wall64 = (time.perf_counter() - t1) / reps64
+    # ---------------------------------------------------------------- timed: headline mixed path (FP32 MFMA)
+    head = timed(d2d.D2D_FP32, args.steps, args.warmup)
+    # ---------------------------------------------------------------- same algorithm, BF16 inputs / FP64
+    reps = max(1, min(args.steps, 5))
+    bf16 = timed(d2d.D2D_BF16, reps, 1)
+    fp64 = timed(d2d.D2D_FP64, reps, 1)
 
     # ---------------------------------------------------------------- Hv-only and kernel timing
     with torch.cuda.stream(s):
         x64 = torch.as_tensor(W.random_vector(N, 1000), device="cuda")
-        x32 = x64.float()
-        w64 = torch.empty_like(x64)
-        w32 = torch.empty_like(x32)
+        xs = {"fp64": x64, "fp32": x64.float(), "bf16": x64.to(torch.bfloat16)}
+        ws = {"fp64": torch.empty_like(x64), "fp32": torch.empty(N, dtype=torch.float32, device="cuda"),
+              "bf16": torch.empty(N, dtype=torch.float32, device="cuda")}
     s.synchronize()
     ms = {}
-    for name, prec, x, w in (("fp64", d2d.D2D_FP64, x64, w64), ("fp32", d2d.D2D_FP32, x32, w32)):
-        d2d.d2d_hv_profile(sb, prec, x, w, reps=5)
-        g, c = d2d.d2d_hv_profile(sb, prec, x, w, reps=50)
+    for prec, name in names.items():
+        d2d.d2d_hv_profile(sb, prec, xs[name], ws[name], reps=5)
+        g, c = d2d.d2d_hv_profile(sb, prec, xs[name], ws[name], reps=50)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(s)
         for _ in range(50):
-            d2d.d2d_hv(sb, prec, x, w)
+            d2d.d2d_hv(sb, prec, xs[name], ws[name])
         ev1.record(s)
         s.synchronize()
         ms[name] = {"gemm_ms": g, "central_ms": c, "hv_ms": ev0.elapsed_time(ev1) / 50}
 
     F = info["flops_exec"]
-    g32 = ms["fp32"]["gemm_ms"] * 1e-3
-    achieved = F / g32
-    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK["fp32"], "traffic": traffic_record(wl.name, "fp32"),
-                "kernel": f"k_hv_gemm<float,{tuned['fp32']['BMxBNxBK']}> (grouped GEMM H_l V + V H_r^T, FP32 MFMA 32x32x2)",
-                "flops_per_launch": F, "launch_ms": ms["fp32"]["gemm_ms"]}
+
+    def roofline(name):
+        sec = ms[name]["gemm_ms"] * 1e-3
+        achieved = F / sec
+        return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[name] / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK[name], "traffic": traffic_record(wl.name, name),
+                "kernel": f"grouped GEMM H_l V + V H_r^T ({name}, tile {tuned[name]['BMxBNxBK']}"
+                          f"{', split K-loops' if tuned[name]['split_k_loops'] else ''})",
+                "flops_per_launch": F, "launch_ms": ms[name]["gemm_ms"],
+                "hbm_bytes_min_per_launch": info["bytes_min_" + name],
+                "hbm_frac_at_min_bytes": info["bytes_min_" + name] / sec / PEAK["hbm"]}
 
     line = {
         "metric": "Hv/sec + Lanczos time to |dE|<=1e-10: mixed-precision vs FP64, 1 GPU",
-        "value": hv / wall,
+        "value": head["hv_per_s"],
         "unit": "Hv/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": head["s_per_solve"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -235,23 +250,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "description": wl.description, "N_sb": N,
                    "sector_pairs": info["npairs"], "m": info["m"], "column_dim": info["ncol"],
-                   "central_terms": info["nterms"], "k_in": args.k_in, "tol_res": args.tol,
-                   "tiles": tuned,
-                   "parallelism": "none (1 GPU)"},
+                   "central_terms": info["nterms"], "k_in": args.k_in, "reorth_window": args.window,
+                   "tol_res": args.tol, "tiles": tuned, "parallelism": "none (1 GPU)"},
+        "precision_schedule": "inner Hv FP32 MFMA (FP32 accumulate); FP64 Lanczos scalars, reorthogonalisation, "
+                              "tridiagonal solve and FP64-Hv residual at every restart",
         "time_to_energy": {
-            "mixed_s": st_mixed["seconds"], "fp64_s": wall64,
-            "speedup_vs_fp64": wall64 / st_mixed["seconds"],
-            "mixed_first_within_1e-10_s": first_within(st_mixed),
-            "fp64_first_within_1e-10_s": first_within(st64),
-            "E_mixed": e_mixed, "E_fp64": e64, "E_oracle": E0,
-            "dE_rel_mixed": None if E0 is None else abs(e_mixed - E0) / abs(E0),
-            "dE_rel_fp64": None if E0 is None else abs(e64 - E0) / abs(E0),
-            "restarts_mixed": st_mixed["restarts"], "hv_count_mixed": st_mixed["hv_count"],
-            "restarts_fp64": st64["restarts"], "hv_count_fp64": st64["hv_count"],
+            "E_oracle": E0,
+            "mixed_fp32": head, "mixed_bf16": bf16, "fp64": fp64,
+            "speedup_fp32_vs_fp64": fp64["s_per_solve"] / head["s_per_solve"],
+            "speedup_bf16_vs_fp64": fp64["s_per_solve"] / bf16["s_per_solve"],
         },
         "hv_only": {k: {"hv_per_s": 1e3 / v["hv_ms"], **v} for k, v in ms.items()},
         "flops_exec_per_hv": F, "flops_nnz_per_hv": info["flops_nnz"],
-        "roofline": roofline,
+        "roofline": roofline("fp32"),
+        "roofline_bf16": roofline("bf16"),
+        "roofline_fp64": roofline("fp64"),
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

@@ -198,13 +198,18 @@ d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[3]);
 
 /* Tile shape of the grouped-GEMM launch used for one precision: index into
  * the library's table of tile shapes (see d2d_tile_shapes), or -1 to let the
- * library choose by problem size.  Returns D2D_EINVAL for an index out of
+ * library choose by problem size.  OR-ing D2D_TILE_SPLIT runs the two K-loops
+ * of every output tile (H_l V and V H_r^T) as separate work items into two
+ * partial outputs, which the central-term launch adds (shorter critical path
+ * for small, latency-bound sectors).  Returns D2D_EINVAL for an index out of
  * range or a shape not built for that precision. */
+#define D2D_TILE_SPLIT (1 << 16)
 d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile);
 /* Autotuner: times every grouped-GEMM tile shape of precision prec on this
- * superblock (reps launches each, on internal scratch vectors, HIP events on
- * the context stream), selects the fastest for later d2d_hv / d2d_lanczos
- * calls and returns its index and average milliseconds.  If the environment
+ * superblock, each with and without D2D_TILE_SPLIT (reps launches each, on
+ * internal scratch vectors, HIP events on the context stream), selects the
+ * fastest for later d2d_hv / d2d_lanczos calls and returns it (shape index,
+ * OR-ed with D2D_TILE_SPLIT when split) and its average milliseconds.  If the environment
  * variable D2D_TUNE_CACHE names a file, results are looked up there first
  * (key: precision and the list of sector dimensions) and appended after a
  * measurement.  Synchronous. */
@@ -220,9 +225,10 @@ d2d_status d2d_tile_shapes(int* count, int* desc);
  *   restart j: w = H_64 x_j, theta_j = x_j.w, r = w - theta_j x_j,
  *   rho_j = |r|; stop if converged; else an inner Lanczos started from x_j
  *   (alpha_0 = theta_j, beta_1 = rho_j, q_1 = r/rho_j) runs k_in - 1 more
- *   steps with Hv in precision prec_j, full reorthogonalisation (classical
- *   Gram-Schmidt twice, FP64), the tridiagonal lowest eigenpair on the
- *   device, and x_{j+1} = Q y.
+ *   steps with Hv in precision prec_j, reorthogonalisation by classical
+ *   Gram-Schmidt twice in FP64 (against all basis vectors, or the last
+ *   reorth_window ones), the tridiagonal lowest eigenpair on the device, and
+ *   x_{j+1} = Q y.
  * All recurrences, dot products, the tridiagonal solve and the Ritz vector
  * are FP64 on the device; the host reads (theta_j, rho_j) once per restart.
  * Precision schedule: start in opts.prec; if rho_{j+1} > escalate * rho_j the
@@ -240,6 +246,9 @@ typedef struct {
     double tol_res;      /* relative residual |r|/|theta|                      */
     double escalate;     /* precision raise threshold on rho_{j+1}/rho_j        */
     int use_graph;       /* capture the inner loop in a hipGraph and replay it */
+    int reorth_window;   /* 0: reorthogonalise against every basis vector (full);
+                            w >= 2: only against the last w vectors (the FP64
+                            restarts keep the fixed point exact either way)   */
 } d2d_lanczos_opts;
 
 #define D2D_LOG_MAX 256

@@ -39,6 +39,8 @@ struct d2d_batch {
     std::map<int, int> work_cap;
     std::vector<int> active;
     int64_t hv_count[3] = {0, 0, 0};
+    int split = 0;                      // split K-loops (small, latency-bound sectors)
+    void* d_w1 = nullptr;               // ntot doubles
     void* stage_v = nullptr;
     void* stage_w = nullptr;
     LanczosWork* lz = nullptr;
@@ -71,16 +73,10 @@ int batch_auto_tile(const d2d_batch* b, int prec) {
 
 // Launch tables of the active problems (work list of one shape, central and pack tiles).
 d2d_status build_work(d2d_batch* b, int shape) {
-    const TileShape& ts = tile_shape(shape);
+    std::vector<int> keep(b->pairs.size());
+    for (size_t p = 0; p < b->pairs.size(); ++p) keep[p] = b->active[b->pair_prob[p]];
     std::vector<WorkItem> w;
-    for (size_t p = 0; p < b->pairs.size(); ++p) {
-        if (!b->active[b->pair_prob[p]]) continue;
-        const int dL = b->pairs[p].dL, dR = b->pairs[p].dR;
-        const int tm = (dL + ts.BM - 1) / ts.BM, tn = (dR + ts.BN - 1) / ts.BN;
-        for (int j = 0; j < tn; ++j)
-            for (int i = 0; i < tm; ++i) w.push_back({(int32_t)p, i, j, dL + dR});
-    }
-    std::stable_sort(w.begin(), w.end(), [](const WorkItem& x, const WorkItem& y) { return x.cost > y.cost; });
+    make_work(b->pairs, &keep, tile_shape(shape), b->split, w);
     auto it = b->work.find(shape);
     if (it != b->work.end() && b->work_cap[shape] < (int)w.size()) {
         dfree(b->ctx, it->second.first, (size_t)b->work_cap[shape]);
@@ -151,6 +147,7 @@ HvTables tables_of(d2d_batch* b) {
     t.n_ptiles = b->n_ptiles;
     t.vp = b->d_vp;
     t.vt = b->d_vt;
+    t.w1 = b->split ? b->d_w1 : nullptr;
     return t;
 }
 
@@ -212,6 +209,7 @@ d2d_batch::~d2d_batch() {
     dfree(ctx, d_vp, (size_t)vp_len);
     dfree(ctx, d_vt, (size_t)vt_len);
     for (auto& kv : work) dfree(ctx, kv.second.first, (size_t)work_cap[kv.first]);
+    if (d_w1) ctx->free(d_w1, (size_t)ntot * 8);
     if (stage_v) ctx->free(stage_v, (size_t)ntot * 8);
     if (stage_w) ctx->free(stage_w, (size_t)ntot * 8);
 }
@@ -335,6 +333,9 @@ extern "C" d2d_status d2d_batch_create(d2d_ctx* ctx, d2d_sb* const* sbs, int n, 
     D2D_CHECK(dupload(ctx, rc32, &b->d_rc32));
     D2D_CHECK(dupload(ctx, cc32, &b->d_cc32));
     b->active.assign(n, 1);
+    // every sector small: the GEMM is latency-bound, split its two K-loops
+    b->split = std::max(b->max_dl, b->max_dr) <= 768 ? 1 : 0;
+    if (b->split) D2D_CHECK(ctx->alloc(&b->d_w1, (size_t)b->ntot * 8));
     D2D_CHECK(build_tiles(b.get()));
     D2D_CHECK(ctx->alloc(&b->stage_v, (size_t)b->ntot * 8));
     D2D_CHECK(ctx->alloc(&b->stage_w, (size_t)b->ntot * 8));

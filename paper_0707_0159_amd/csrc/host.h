@@ -108,6 +108,7 @@ namespace d2d {
 struct HvTables {
     const SectorDev* sec;
     int npairs;
+    void* w1;                 // scratch partial output of split K-loops (ntot doubles)
     const void* HL[3];
     const void* HR[3];
     int K;
@@ -184,7 +185,9 @@ struct d2d_sb {
     std::vector<double> h_rc, h_cc;
     // work lists per tile shape
     std::map<int, std::pair<d2d::WorkItem*, int>> work;
-    int tile_sel[3] = {-1, -1, -1};
+    int tile_sel[3] = {-1, -1, -1};     // shape index, or -1 = by size
+    int split[3] = {0, 0, 0};
+    void* d_w1 = nullptr;               // N doubles, allocated on first split launch
     int64_t hv_count[3] = {0, 0, 0};
     LanczosWork* lz = nullptr;          // owned; freed by free_lanczos
     ~d2d_sb();
@@ -201,6 +204,9 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
                        double* const* psi, d2d_lanczos_stats* stats);
 d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s, hipEvent_t mid);
 int sb_auto_tile(const d2d_sb* sb, int prec);
-d2d_status sb_work(d2d_sb* sb, int shape, WorkItem** w, int* nwork);
+d2d_status sb_work(d2d_sb* sb, int shape, int split, WorkItem** w, int* nwork);
+// work items of the pairs [0, npairs) for a tile shape; split = two items per tile
+void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep, const TileShape& ts, int split,
+               std::vector<WorkItem>& out);
 void free_lanczos(d2d_sb* sb);
 }  // namespace d2d

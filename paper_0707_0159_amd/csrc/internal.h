@@ -51,8 +51,10 @@ struct SectorDev {
 };
 
 // One output tile of the grouped GEMM: pair, tile row, tile column.
+// part: 0 = both K-loops into W; 1 = H_l V only into W; 2 = V H_r^T only into W1
+// (split K-loops: the central-term kernel adds W1 into W).
 struct WorkItem {
-    int32_t p, tm, tn, cost;
+    int32_t p, tm, tn, part;
 };
 
 // Tile shapes built into the library.
@@ -73,7 +75,8 @@ struct HvGemmArgs {
     const void* HR;
     const void* V;
     void* W;
-    // central term, fused into the GEMM epilogue
+    void* W1;              // second partial output of split work items (nullable)
+    // central term arguments (used by the central-term kernel)
     int K;
     const int32_t* src;
     const int32_t* rmap;
@@ -108,6 +111,7 @@ struct CentralArgs {
     int64_t Drows, Dcols;
     const void* V;
     void* W;
+    const void* W1;            // partial output of split K-loops added into W (nullable)
 };
 hipError_t launch_central(int prec, const CentralArgs& a, hipStream_t s);
 

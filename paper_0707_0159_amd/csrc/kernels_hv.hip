@@ -59,6 +59,7 @@ struct HvK {
     const T* HRt;
     const T* V;
     T* W;
+    T* W1;
     int K;
     const int32_t* src;
     const int32_t* rmap;
@@ -77,7 +78,6 @@ k_hv_gemm(const HvK<T> g) {
     const T* __restrict__ HL = g.HL;
     const T* __restrict__ HRt = g.HRt;
     const T* __restrict__ V = g.V;
-    T* __restrict__ W = g.W;
     constexpr int NT = 64 * WGM * WGN;
     constexpr int WM = BM / WGM, WN = BN / WGN;
     constexpr int FM = WM / M::MN, FN = WN / M::MN;
@@ -106,8 +106,9 @@ k_hv_gemm(const HvK<T> g) {
             for (int v = 0; v < M::NV; ++v) acc[i][j][v] = T(0);
 
     T ra[EA], rb[EB];
+    const int ph_lo = wi.part == 2 ? 1 : 0, ph_hi = wi.part == 1 ? 1 : 2;
 #pragma unroll 1
-    for (int phase = 0; phase < 2; ++phase) {
+    for (int phase = ph_lo; phase < ph_hi; ++phase) {
         // phase 0: A = H_l[q_L] (dL x dL), B = V (dL x dR), K = dL
         // phase 1: A = V (dL x dR), B = H_r^T (dR x dR), K = dR
         const T* A = phase == 0 ? HL + s.hl_off : V + s.off;
@@ -166,7 +167,7 @@ k_hv_gemm(const HvK<T> g) {
         __syncthreads();
     }
 
-    T* Wp = W + s.off;
+    T* Wp = (wi.part == 2 ? g.W1 : g.W) + s.off;
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
         const int r = row0 + wm * WM + i * M::MN + lane % M::MN;
@@ -196,7 +197,7 @@ template <int BM, int BN, int BK, int WGM, int WGN>
 __global__ void __launch_bounds__(64 * WGM * WGN)
 k_hv_gemm_bf16(const WorkItem* __restrict__ work, const SectorDev* __restrict__ sec, const bf16_t* __restrict__ HL,
                const bf16_t* __restrict__ HRt, const bf16_t* __restrict__ VP, const bf16_t* __restrict__ VT,
-               float* __restrict__ W) {
+               float* __restrict__ W, float* __restrict__ W1) {
     using M = Mf<float>;
     constexpr int NT = 64 * WGM * WGN;
     constexpr int WM = BM / WGM, WN = BN / WGN;
@@ -225,8 +226,9 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, const SectorDev* __restrict__ 
             for (int v = 0; v < M::NV; ++v) acc[i][j][v] = 0.0f;
 
     uint4 ra[EA], rb[EB];
+    const int ph_lo = wi.part == 2 ? 1 : 0, ph_hi = wi.part == 1 ? 1 : 2;
 #pragma unroll 1
-    for (int phase = 0; phase < 2; ++phase) {
+    for (int phase = ph_lo; phase < ph_hi; ++phase) {
         const bf16_t* A = phase == 0 ? HL + s.hl16_off : VT + s.vt_off;
         const bf16_t* B = phase == 0 ? VP + s.vp_off : HRt + s.hr16_off;
         const int64_t ld = phase == 0 ? s.dLp : s.dRp;     // both operands share the K stride
@@ -282,7 +284,7 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, const SectorDev* __restrict__ 
         __syncthreads();
     }
 
-    float* Wp = W + s.off;
+    float* Wp = (wi.part == 2 ? W1 : W) + s.off;
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
         const int r = row0 + wm * WM + i * 32 + (lane & 31);
@@ -305,22 +307,21 @@ hipError_t launch_hv_gemm_bf16(int shape, const HvGemmArgs& a, const void* VT, h
     const bf16_t* VP = (const bf16_t*)a.V;
     const bf16_t* V2 = (const bf16_t*)VT;
     float* W = (float*)a.W;
+    float* W1 = (float*)a.W1;
     switch (shape) {
         case 14:
-            hipLaunchKernelGGL((k_hv_gemm_bf16<64, 64, 32, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec, HL, HR, VP,
-                               V2, W);
+            hipLaunchKernelGGL((k_hv_gemm_bf16<64, 64, 32, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec, HL, HR, VP, V2, W, W1);
             break;
         case 15:
             hipLaunchKernelGGL((k_hv_gemm_bf16<128, 128, 32, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec, HL, HR,
-                               VP, V2, W);
+                               VP, V2, W, W1);
             break;
         case 16:
             hipLaunchKernelGGL((k_hv_gemm_bf16<128, 128, 64, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec, HL, HR,
-                               VP, V2, W);
+                               VP, V2, W, W1);
             break;
         case 17:
-            hipLaunchKernelGGL((k_hv_gemm_bf16<32, 32, 64, 1, 1>), grid, dim3(64), 0, st, a.work, a.sec, HL, HR, VP,
-                               V2, W);
+            hipLaunchKernelGGL((k_hv_gemm_bf16<32, 32, 64, 1, 1>), grid, dim3(64), 0, st, a.work, a.sec, HL, HR, VP, V2, W, W1);
             break;
         default:
             return hipErrorInvalidValue;
@@ -425,6 +426,7 @@ static HvK<T> make_args(const HvGemmArgs& a) {
     g.HRt = (const T*)a.HR;
     g.V = (const T*)a.V;
     g.W = (T*)a.W;
+    g.W1 = (T*)a.W1;
     g.K = a.K;
     g.src = a.src;
     g.rmap = a.rmap;
@@ -512,7 +514,7 @@ __global__ void __launch_bounds__(64)
 k_central(const int4* __restrict__ tiles, const SectorDev* __restrict__ sec, int K, const int32_t* __restrict__ src,
           const int32_t* __restrict__ rmap, const int32_t* __restrict__ cmap, const TC* __restrict__ rcoef,
           const TC* __restrict__ ccoef, int64_t Drows, int64_t Dcols, const TI* __restrict__ V,
-          TO* __restrict__ W) {
+          TO* __restrict__ W, const TO* __restrict__ W1) {
     __shared__ int64_t s_off2[KMAX];
     __shared__ int s_dl2[KMAX];
     __shared__ int s_cm[KMAX][CT];
@@ -573,7 +575,10 @@ k_central(const int4* __restrict__ tiles, const SectorDev* __restrict__ sec, int
     }
 #pragma unroll
     for (int c = 0; c < CT; ++c)
-        if (c0 + c < s.dR) W[s.off + r + (int64_t)(c0 + c) * s.dL] += (TO)acc[c];
+        if (c0 + c < s.dR) {
+            const int64_t e = s.off + r + (int64_t)(c0 + c) * s.dL;
+            W[e] += (W1 ? W1[e] : TO(0)) + (TO)acc[c];
+        }
 }
 
 hipError_t launch_central(int prec, const CentralArgs& a, hipStream_t st) {
@@ -583,15 +588,15 @@ hipError_t launch_central(int prec, const CentralArgs& a, hipStream_t st) {
     if (prec == D2D_FP64)
         hipLaunchKernelGGL((k_central<double, double, double>), grid, dim3(64), 0, st, a.blocks, a.sec, a.K, a.src,
                            a.rmap, a.cmap, (const double*)a.rcoef, (const double*)a.ccoef, a.Drows, a.Dcols,
-                           (const double*)a.V, (double*)a.W);
+                           (const double*)a.V, (double*)a.W, (const double*)a.W1);
     else if (prec == D2D_FP32)
         hipLaunchKernelGGL((k_central<float, float, float>), grid, dim3(64), 0, st, a.blocks, a.sec, a.K, a.src,
                            a.rmap, a.cmap, (const float*)a.rcoef, (const float*)a.ccoef, a.Drows, a.Dcols,
-                           (const float*)a.V, (float*)a.W);
+                           (const float*)a.V, (float*)a.W, (const float*)a.W1);
     else
         hipLaunchKernelGGL((k_central<bf16_t, float, float>), grid, dim3(64), 0, st, a.blocks, a.sec, a.K, a.src,
                            a.rmap, a.cmap, (const float*)a.rcoef, (const float*)a.ccoef, a.Drows, a.Dcols,
-                           (const bf16_t*)a.V, (float*)a.W);
+                           (const bf16_t*)a.V, (float*)a.W, (const float*)a.W1);
     return hipGetLastError();
 }
 

@@ -316,7 +316,7 @@ k_lz_update_dots(const LzSeg* __restrict__ bt, const int* __restrict__ active, c
     if ((int)threadIdx.x < NQ) cs[threadIdx.x] = 0.0;
     __syncthreads();
     reduce_rows(partial_in, nq, NB, sg.pb0, sg.pb1, cs);
-    if ((int)blockIdx.x == sg.pb0 && threadIdx.x == 0) scal[(int64_t)sg.prob * S_LEN + S_ALPHA + i] = cs[i];
+    if ((int)blockIdx.x == sg.pb0 && threadIdx.x == 0) scal[(int64_t)sg.prob * S_LEN + S_ALPHA + i] = cs[nq - 1];
     double acc[NQ + 1];
 #pragma unroll
     for (int j = 0; j <= NQ; ++j) acc[j] = 0.0;
@@ -375,7 +375,7 @@ k_lz_next(const LzSeg* __restrict__ bt, const int* __restrict__ active, const do
     const bool corr = sqrt(s2) > 1e-13 * sqrt(w2 > 0.0 ? w2 : 0.0);
     if ((int)blockIdx.x == sg.pb0 && threadIdx.x == 0) {
         double* sc = scal + (int64_t)sg.prob * S_LEN;
-        sc[S_ALPHA + i] += cs[i];
+        sc[S_ALPHA + i] += cs[nq - 1];
         sc[S_BETA + i + 1] = bb;
     }
     if (!qnext) return;

@@ -139,7 +139,7 @@ d2d_status residual_step(LanczosWork* w, HvOps& hv, hipStream_t s) {
 }
 
 // One inner Lanczos of k vectors from X (after residual_step); X <- Ritz vector.
-d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, hipStream_t s) {
+d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, hipStream_t s) {
     const LzSet z = set_of(w);
     const int64_t N = w->ntot;
     void* lo = prec == D2D_FP64 ? nullptr : (void*)w->vlo;
@@ -151,9 +151,11 @@ d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, hipStream_t s)
         LzStepArgs a{};
         a.bt = z.bt;
         a.active = z.active;
-        a.Q = w->Q;
+        // projection against q_{i-nq+1} .. q_i (all of them for full reorthogonalisation)
+        const int nq = window >= 2 ? std::min(i + 1, window) : i + 1;
+        a.Q = w->Q + (int64_t)(i + 1 - nq) * N;
         a.ldq = N;
-        a.nq = i + 1;
+        a.nq = nq;
         a.i = i;
         a.upcast = prec != D2D_FP64;
         a.w32 = w->wlo;
@@ -181,9 +183,9 @@ void drop_graphs(LanczosWork* w) {
     }
 }
 
-d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, bool use_graph, hipStream_t s) {
+d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool use_graph, hipStream_t s) {
     if (!use_graph || s == nullptr) {
-        D2D_CHECK(inner_loop(w, hv, prec, k, s));
+        D2D_CHECK(inner_loop(w, hv, prec, k, window, s));
         D2D_CHECK(residual_step(w, hv, s));
         hv.count(prec, k - 1);
         hv.count(D2D_FP64, 1);
@@ -197,7 +199,7 @@ d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, bool use_graph, h
         D2D_CHECK(hv.prepare(prec));          // launch tables exist before capture
         D2D_CHECK(hv.prepare(D2D_FP64));
         D2D_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        d2d_status st = inner_loop(w, hv, prec, k, s);
+        d2d_status st = inner_loop(w, hv, prec, k, window, s);
         if (st == D2D_OK) st = residual_step(w, hv, s);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s, &g);
@@ -225,8 +227,8 @@ namespace d2d {
 
 d2d_status check_lanczos_opts(const d2d_lanczos_opts* o) {
     if (!o || o->k_in < 2 || o->k_in > 33 || o->max_restarts < 0 || !(o->tol_res > 0.0) || o->prec < 0 ||
-        o->prec > 2) {
-        set_error("Lanczos options: k_in 2..33, max_restarts >= 0, tol_res > 0, prec 0..2");
+        o->prec > 2 || o->reorth_window < 0 || o->reorth_window == 1) {
+        set_error("Lanczos options: k_in 2..33, max_restarts >= 0, tol_res > 0, prec 0..2, reorth_window 0 or >= 2");
         return D2D_EINVAL;
     }
     return D2D_OK;
@@ -330,7 +332,7 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
             D2D_CHECK(hv.set_active(a, &rebuilt));
             if (rebuilt) drop_graphs(w);
         }
-        D2D_CHECK(restart(w, hv, prec, k, opts->use_graph != 0, s));
+        D2D_CHECK(restart(w, hv, prec, k, opts->reorth_window, opts->use_graph != 0, s));
         D2D_HIP(hipStreamSynchronize(s));
         ++j;
         for (int p = 0; p < np; ++p) {
@@ -370,7 +372,8 @@ struct SbHv : HvOps {
         WorkItem* d;
         int n;
         const int shape = sb->tile_sel[prec] >= 0 ? sb->tile_sel[prec] : sb_auto_tile(sb, prec);
-        return sb_work(sb, shape, &d, &n);
+        if (sb->split[prec] && !sb->d_w1) D2D_CHECK(sb->ctx->alloc(&sb->d_w1, (size_t)sb->N * 8));
+        return sb_work(sb, shape, sb->split[prec], &d, &n);
     }
     d2d_status set_active(const std::vector<int>&, bool* rebuilt) override {
         if (rebuilt) *rebuilt = false;

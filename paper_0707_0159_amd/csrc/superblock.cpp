@@ -105,6 +105,8 @@ d2d_sb::~d2d_sb() {
         if (HR[p]) ctx->free(HR[p], hrs[p]);
         HL[p] = HR[p] = nullptr;
     }
+    if (d_w1) ctx->free(d_w1, (size_t)N * 8);
+    d_w1 = nullptr;
     release(ctx, d_vp, (size_t)vp_len);
     release(ctx, d_vt, (size_t)vt_len);
     release(ctx, d_ptiles, (size_t)n_ptiles);
@@ -133,26 +135,44 @@ int sb_auto_tile(const d2d_sb* sb, int prec) {
     return -1;
 }
 
-d2d_status sb_work(d2d_sb* sb, int shape, WorkItem** out, int* nwork) {
-    auto it = sb->work.find(shape);
+void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep, const TileShape& ts, int split,
+               std::vector<WorkItem>& out) {
+    std::vector<std::pair<int, WorkItem>> w;
+    for (size_t p = 0; p < pairs.size(); ++p) {
+        if (keep && !(*keep)[p]) continue;
+        const int dL = pairs[p].dL, dR = pairs[p].dR;
+        const int tm = (dL + ts.BM - 1) / ts.BM, tn = (dR + ts.BN - 1) / ts.BN;
+        for (int j = 0; j < tn; ++j)
+            for (int i = 0; i < tm; ++i) {
+                if (split) {
+                    w.push_back({dL, {(int32_t)p, i, j, 1}});
+                    w.push_back({dR, {(int32_t)p, i, j, 2}});
+                } else {
+                    w.push_back({dL + dR, {(int32_t)p, i, j, 0}});
+                }
+            }
+    }
+    // longest K-loops first
+    std::stable_sort(w.begin(), w.end(), [](const std::pair<int, WorkItem>& a, const std::pair<int, WorkItem>& b) {
+        return a.first > b.first;
+    });
+    out.clear();
+    for (auto& x : w) out.push_back(x.second);
+}
+
+d2d_status sb_work(d2d_sb* sb, int shape, int split, WorkItem** out, int* nwork) {
+    const int key = shape | (split ? D2D_TILE_SPLIT : 0);
+    auto it = sb->work.find(key);
     if (it != sb->work.end()) {
         *out = it->second.first;
         *nwork = it->second.second;
         return D2D_OK;
     }
-    const TileShape& ts = tile_shape(shape);
     std::vector<WorkItem> w;
-    for (size_t p = 0; p < sb->pairs.size(); ++p) {
-        const int dL = sb->pairs[p].dL, dR = sb->pairs[p].dR;
-        const int tm = (dL + ts.BM - 1) / ts.BM, tn = (dR + ts.BN - 1) / ts.BN;
-        for (int j = 0; j < tn; ++j)
-            for (int i = 0; i < tm; ++i) w.push_back({(int32_t)p, i, j, dL + dR});
-    }
-    // longest tiles first (their K-loops are d_L + d_R long)
-    std::stable_sort(w.begin(), w.end(), [](const WorkItem& a, const WorkItem& b) { return a.cost > b.cost; });
+    make_work(sb->pairs, nullptr, tile_shape(shape), split, w);
     WorkItem* d = nullptr;
     D2D_CHECK(upload(sb->ctx, w, &d));
-    sb->work[shape] = {d, (int)w.size()};
+    sb->work[key] = {d, (int)w.size()};
     *out = d;
     *nwork = (int)w.size();
     return D2D_OK;
@@ -160,7 +180,13 @@ d2d_status sb_work(d2d_sb* sb, int shape, WorkItem** out, int* nwork) {
 
 d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkItem* work, int nwork, const void* v,
                      void* w, hipStream_t s, hipEvent_t mid) {
-    HvGemmArgs g{work, nwork, t.sec, t.HL[prec], t.HR[prec], v, w};
+    // a split work list writes the second K-loop into w1; the central term adds it
+    bool split = false;
+    {
+        // the caller passes split work lists only together with a scratch w1
+        split = t.w1 != nullptr;
+    }
+    HvGemmArgs g{work, nwork, t.sec, t.HL[prec], t.HR[prec], v, w, split ? t.w1 : nullptr};
     g.K = t.K;
     g.src = t.src;
     g.rmap = t.rmap;
@@ -192,6 +218,7 @@ d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkItem* wor
     c.Dcols = t.Dcols;
     c.V = v;   // the unpadded input in every precision
     c.W = w;
+    c.W1 = split ? t.w1 : nullptr;
     D2D_HIP(launch_central(prec, c, s));
     return D2D_OK;
 }
@@ -229,10 +256,16 @@ d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t
         return D2D_EINVAL;
     }
     const int shape = sb->tile_sel[prec] >= 0 ? sb->tile_sel[prec] : sb_auto_tile(sb, prec);
+    const int split = sb->split[prec];
     WorkItem* work = nullptr;
     int nwork = 0;
-    D2D_CHECK(sb_work(sb, shape, &work, &nwork));
-    return hv_launch(tables_of(sb), prec, shape, work, nwork, v, w, s, mid);
+    D2D_CHECK(sb_work(sb, shape, split, &work, &nwork));
+    HvTables t = tables_of(sb);
+    if (split) {
+        if (!sb->d_w1) D2D_CHECK(sb->ctx->alloc(&sb->d_w1, (size_t)sb->N * 8));
+        t.w1 = sb->d_w1;
+    }
+    return hv_launch(t, prec, shape, work, nwork, v, w, s, mid);
 }
 
 d2d_status sb_hv_nocount(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s) {
@@ -622,11 +655,14 @@ extern "C" d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile) {
         set_error("d2d_sb_set_tile: bad argument");
         return D2D_EINVAL;
     }
-    if (tile >= tile_shape_count() || (tile >= 0 && tile_shape(tile).prec != prec)) {
+    const int split = tile >= 0 && (tile & D2D_TILE_SPLIT) ? 1 : 0;
+    const int shape = tile < 0 ? -1 : (tile & ~D2D_TILE_SPLIT);
+    if (shape >= tile_shape_count() || (shape >= 0 && tile_shape(shape).prec != prec)) {
         set_error("d2d_sb_set_tile: tile %d is not a shape of precision %d", tile, prec);
         return D2D_EINVAL;
     }
-    sb->tile_sel[prec] = tile < 0 ? -1 : tile;
+    sb->tile_sel[prec] = shape;
+    sb->split[prec] = split;
     return D2D_OK;
 }
 
@@ -721,14 +757,17 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
             unsigned long long k;
             int t;
             double ms;
-            while (fscanf(f, "%llx %d %lf", &k, &t, &ms) == 3)
-                if (k == key && t >= 0 && t < tile_shape_count() && tile_shape(t).prec == prec) {
-                    sb->tile_sel[prec] = t;
+            while (fscanf(f, "%llx %d %lf", &k, &t, &ms) == 3) {
+                const int sh = t & ~D2D_TILE_SPLIT;
+                if (k == key && sh >= 0 && sh < tile_shape_count() && tile_shape(sh).prec == prec) {
+                    sb->tile_sel[prec] = sh;
+                    sb->split[prec] = (t & D2D_TILE_SPLIT) ? 1 : 0;
                     *best_tile = t;
                     *best_ms = ms;
                     fclose(f);
                     return D2D_OK;
                 }
+            }
             fclose(f);
         }
     }
@@ -746,15 +785,17 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int best = -1;
     double bms = 1e300;
-    const int saved = sb->tile_sel[prec];
+    const int saved = sb->tile_sel[prec], saved_split = sb->split[prec];
     if (launch_fill(v, prec, sb->N, 0.5, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
         hipEventCreate(&e1) != hipSuccess) {
         set_error("d2d_sb_autotune: HIP setup failed");
         st = D2D_EDEVICE;
     }
-    for (int t = 0; t < tile_shape_count() && st == D2D_OK; ++t) {
+    for (int tt = 0; tt < 2 * tile_shape_count() && st == D2D_OK; ++tt) {
+        const int t = tt % tile_shape_count(), sp = tt / tile_shape_count();
         if (tile_shape(t).prec != prec) continue;
         sb->tile_sel[prec] = t;
+        sb->split[prec] = sp;
         st = sb_hv(sb, prec, v, w, s);   // warm-up (also builds the work list)
         if (st != D2D_OK) break;
         if (hipEventRecord(e0, s) != hipSuccess) st = D2D_EDEVICE;
@@ -765,7 +806,7 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
             st = D2D_EDEVICE;
         if (st == D2D_OK && ms / reps < bms) {
             bms = ms / reps;
-            best = t;
+            best = t | (sp ? D2D_TILE_SPLIT : 0);
         }
     }
     if (e0) (void)hipEventDestroy(e0);
@@ -774,13 +815,15 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
     ctx->free(w, (size_t)sb->N * out_sz);
     if (st != D2D_OK || best < 0) {
         sb->tile_sel[prec] = saved;
+        sb->split[prec] = saved_split;
         if (st == D2D_OK) {
             set_error("d2d_sb_autotune: no tile shape for precision %d", prec);
             st = D2D_EINVAL;
         }
         return st;
     }
-    sb->tile_sel[prec] = best;
+    sb->tile_sel[prec] = best & ~D2D_TILE_SPLIT;
+    sb->split[prec] = (best & D2D_TILE_SPLIT) ? 1 : 0;
     *best_tile = best;
     *best_ms = bms;
     if (cache && *cache) {

@@ -48,6 +48,8 @@ def test_batch_hv_equals_single(ctx, prec):
     ctx.stream.synchronize()
     max_d = max(max(p.info["max_dl"], p.info["max_dr"]) for p in probs)
     shape = (1 if max_d <= 768 else 2) if prec == 0 else (4 if max_d <= 768 else 5)
+    if max_d <= 768:
+        shape |= d2d.D2D_TILE_SPLIT      # the batch splits the K-loops of small sectors
     for p, v, r in zip(probs, vs, refs):
         d2d.d2d_sb_set_tile(p.sb, prec, shape)
         d2d.d2d_hv(p.sb, prec, v, r)

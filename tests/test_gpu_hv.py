@@ -70,7 +70,8 @@ def test_config2_every_tile_shape(ctx, prec, tol):
     osb = oracle_superblock(wl)
     prob = GpuProblem(ctx, wl)
     assert prob.info["n"] == osb.N
-    shapes = [i for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == prec]
+    shapes = [i | sp for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == prec
+              for sp in (0, d2d.D2D_TILE_SPLIT)]
     for k in range(3):
         v = W.random_vector(osb.N, 1000 + k)
         ref = osb.hv_factored(v)
@@ -103,9 +104,12 @@ def test_repeatable_bitwise(ctx):
     prob = GpuProblem(ctx, wl)
     v = W.random_vector(prob.info["n"], 7)
     for prec in (0, 1):
-        a = gpu_hv(ctx, prob, prec, v)
-        for _ in range(5):
-            assert np.array_equal(a, gpu_hv(ctx, prob, prec, v))
+        for sp in (0, 1 << 16):
+            d2d_set = __import__("paper_0707_0159_amd.d2d", fromlist=["d2d"])
+            d2d_set.d2d_sb_set_tile(prob.sb, prec, (4 if prec else 1) | sp)
+            a = gpu_hv(ctx, prob, prec, v)
+            for _ in range(5):
+                assert np.array_equal(a, gpu_hv(ctx, prob, prec, v))
     prob.close()
 
 
@@ -155,7 +159,8 @@ def test_bf16_every_tile_shape(ctx, cfg):
     wl = W.CONFIGS[cfg]
     osb = oracle_superblock(wl)
     prob = GpuProblem(ctx, wl, prec_mask=7)
-    shapes = [i for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == d2d.D2D_BF16]
+    shapes = [i | sp for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == d2d.D2D_BF16
+              for sp in (0, d2d.D2D_TILE_SPLIT)]
     assert shapes
     for k in range(2):
         v = W.random_vector(osb.N, 1000 + k)

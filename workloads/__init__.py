@@ -116,7 +116,7 @@ def _config5_problems():
     return out
 
 
-CONFIG5_LENGTH = 10
+CONFIG5_LENGTH = 6
 
 CONFIGS = {
     1: Workload("heisenberg_2x6_m16", "heisenberg", 2, 6, 16, J=1.0, target_of_sites=_sz_zero(2),
