@@ -74,9 +74,25 @@ def main():
                 continue
             rec = reference(wl)
             print(rec, flush=True)
-            data[wl.name] = rec
-            with open(GOLDEN, "w") as f:
-                json.dump(data, f, indent=1, sort_keys=True)
+            store(wl.name, rec)
+
+
+def store(name: str, rec: dict):
+    """Merge one record into the golden file under an exclusive lock (several
+    runs of this script may write it at once)."""
+    import fcntl
+    with open(GOLDEN + ".lock", "w") as lk:
+        fcntl.flock(lk, fcntl.LOCK_EX)
+        data = {}
+        if os.path.exists(GOLDEN):
+            with open(GOLDEN) as f:
+                data = json.load(f)
+        data[name] = rec
+        tmp = GOLDEN + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, GOLDEN)
+        fcntl.flock(lk, fcntl.LOCK_UN)
 
 
 if __name__ == "__main__":
