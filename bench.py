@@ -139,6 +139,7 @@ def main():
     for prec, name in names.items():
         t, ms_t = d2d.d2d_sb_autotune(sb, prec, reps=10)
         tuned[name] = {"tile": t & 0xFFFF, "split_k_loops": bool(t & d2d.D2D_TILE_SPLIT),
+                       "central_in_gemm_launch": bool(t & d2d.D2D_TILE_FUSED),
                        "BMxBNxBK": "x".join(str(x) for x in shapes[t & 0xFFFF][1:]), "ms": ms_t}
     with torch.cuda.stream(s):
         v0 = torch.as_tensor(W.random_vector(N, wl.seed), device="cuda")

@@ -201,18 +201,25 @@ d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[3]);
  * library choose by problem size.  OR-ing D2D_TILE_SPLIT runs the two K-loops
  * of every output tile (H_l V and V H_r^T) as separate work items into two
  * partial outputs, which the central-term launch adds (shorter critical path
- * for small, latency-bound sectors).  Returns D2D_EINVAL for an index out of
- * range or a shape not built for that precision. */
+ * for small, latency-bound sectors).  OR-ing D2D_TILE_FUSED makes the inner
+ * Lanczos steps evaluate the central term inside the grouped-GEMM launch (its
+ * tiles as extra blocks after the GEMM work items, into an output of its own
+ * that the first vector kernel of the step adds: same result bit for bit, one
+ * launch less, the central term overlapping the GEMM's tail); d2d_hv always
+ * returns the whole product.  Without a call (or after tile -1) FP32 and BF16
+ * are fused, FP64 is not.  Returns D2D_EINVAL for an index out of range or a
+ * shape not built for that precision. */
 #define D2D_TILE_SPLIT (1 << 16)
+#define D2D_TILE_FUSED (1 << 17)
 d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile);
 /* Autotuner: times every grouped-GEMM tile shape of precision prec on this
- * superblock, each with and without D2D_TILE_SPLIT (reps launches each, on
- * internal scratch vectors, HIP events on the context stream), selects the
- * fastest for later d2d_hv / d2d_lanczos calls and returns it (shape index,
- * OR-ed with D2D_TILE_SPLIT when split) and its average milliseconds.  If the environment
- * variable D2D_TUNE_CACHE names a file, results are looked up there first
- * (key: precision and the list of sector dimensions) and appended after a
- * measurement.  Synchronous. */
+ * superblock, with and without D2D_TILE_SPLIT and with and without
+ * D2D_TILE_FUSED (reps launches each, on internal scratch vectors, HIP events
+ * on the context stream), selects the fastest for later d2d_hv / d2d_lanczos
+ * calls and returns it (shape index OR-ed with the flags) and its average
+ * milliseconds.  If the environment variable D2D_TUNE_CACHE names a file,
+ * results are looked up there first (key: precision and the list of sector
+ * dimensions) and appended after a measurement.  Synchronous. */
 d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_tile, double* best_ms);
 
 /* Number of tile shapes and, if desc != NULL, for each shape i: desc[4*i..] =
@@ -249,6 +256,10 @@ typedef struct {
     int reorth_window;   /* 0: reorthogonalise against every basis vector (full);
                             w >= 2: only against the last w vectors (the FP64
                             restarts keep the fixed point exact either way)   */
+    int separate_central; /* 0: inner-step Hv is one launch (GEMM work items and
+                            central-term tiles together, the parts added by the
+                            first step kernel); 1: the central term as a launch
+                            of its own after the GEMM.  Same result bit for bit */
 } d2d_lanczos_opts;
 
 #define D2D_LOG_MAX 256

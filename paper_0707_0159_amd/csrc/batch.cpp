@@ -29,8 +29,10 @@ struct d2d_batch {
     int32_t *d_src = nullptr, *d_rmap = nullptr, *d_cmap = nullptr;
     double *d_rc64 = nullptr, *d_cc64 = nullptr;
     float *d_rc32 = nullptr, *d_cc32 = nullptr;
-    int4* d_ctiles = nullptr;
+    CentralTile* d_ctiles = nullptr;
     int n_ctiles = 0, cap_ctiles = 0;
+    int64_t* d_srcoff = nullptr;
+    int32_t* d_srcdl = nullptr;
     int4* d_ptiles = nullptr;
     int n_ptiles = 0, cap_ptiles = 0;
     bf16_t *d_vp = nullptr, *d_vt = nullptr;
@@ -41,6 +43,7 @@ struct d2d_batch {
     int64_t hv_count[3] = {0, 0, 0};
     int split = 0;                      // split K-loops (small, latency-bound sectors)
     void* d_w1 = nullptr;               // ntot doubles
+    void* d_w2 = nullptr;               // ntot doubles, central-term part of fused launches
     void* stage_v = nullptr;
     void* stage_w = nullptr;
     LanczosWork* lz = nullptr;
@@ -97,26 +100,29 @@ d2d_status build_work(d2d_batch* b, int shape) {
 }
 
 d2d_status build_tiles(d2d_batch* b) {
-    std::vector<int4> ct, pt;
+    std::vector<CentralTile> ct;
+    std::vector<int4> pt;
+    std::vector<int> keep(b->pairs.size());
+    for (size_t p = 0; p < b->pairs.size(); ++p) keep[p] = b->active[b->pair_prob[p]];
+    central_tiles(b->pairs, &keep, ct);
     for (size_t p = 0; p < b->pairs.size(); ++p) {
-        if (!b->active[b->pair_prob[p]]) continue;
+        if (!keep[p]) continue;
         const int dL = b->pairs[p].dL, dR = b->pairs[p].dR;
-        for (int j = 0; j < (dR + 7) / 8; ++j)
-            for (int i = 0; i < (dL + 63) / 64; ++i) ct.push_back(make_int4((int)p, i, j, 0));
         for (int j = 0; j < (dR + 63) / 64; ++j)
             for (int i = 0; i < (dL + 63) / 64; ++i) pt.push_back(make_int4((int)p, i, j, 0));
     }
     if ((int)ct.size() > b->cap_ctiles) {
         dfree(b->ctx, b->d_ctiles, (size_t)b->cap_ctiles);
         b->cap_ctiles = (int)std::max<size_t>(ct.size(), 1);
-        D2D_CHECK(b->ctx->alloc((void**)&b->d_ctiles, (size_t)b->cap_ctiles * sizeof(int4)));
+        D2D_CHECK(b->ctx->alloc((void**)&b->d_ctiles, (size_t)b->cap_ctiles * sizeof(CentralTile)));
     }
     if ((int)pt.size() > b->cap_ptiles) {
         dfree(b->ctx, b->d_ptiles, (size_t)b->cap_ptiles);
         b->cap_ptiles = (int)std::max<size_t>(pt.size(), 1);
         D2D_CHECK(b->ctx->alloc((void**)&b->d_ptiles, (size_t)b->cap_ptiles * sizeof(int4)));
     }
-    if (!ct.empty()) D2D_HIP(hipMemcpy(b->d_ctiles, ct.data(), ct.size() * sizeof(int4), hipMemcpyHostToDevice));
+    if (!ct.empty())
+        D2D_HIP(hipMemcpy(b->d_ctiles, ct.data(), ct.size() * sizeof(CentralTile), hipMemcpyHostToDevice));
     if (!pt.empty()) D2D_HIP(hipMemcpy(b->d_ptiles, pt.data(), pt.size() * sizeof(int4), hipMemcpyHostToDevice));
     b->n_ctiles = (int)ct.size();
     b->n_ptiles = (int)pt.size();
@@ -143,6 +149,8 @@ HvTables tables_of(d2d_batch* b) {
     t.Dcols = b->Dcols;
     t.ctiles = b->d_ctiles;
     t.n_ctiles = b->n_ctiles;
+    t.srcoff = b->d_srcoff;
+    t.srcdl = b->d_srcdl;
     t.ptiles = b->d_ptiles;
     t.n_ptiles = b->n_ptiles;
     t.vp = b->d_vp;
@@ -151,7 +159,7 @@ HvTables tables_of(d2d_batch* b) {
     return t;
 }
 
-d2d_status batch_hv(d2d_batch* b, int prec, const void* v, void* w, hipStream_t s) {
+d2d_status batch_hv(d2d_batch* b, int prec, const void* v, void* w, hipStream_t s, HvParts* parts = nullptr) {
     if (prec < 0 || prec > 2 || !(b->prec_mask & (1u << prec)) || !b->HL[prec]) {
         set_error("precision %d not kept by every superblock of the batch", prec);
         return D2D_EINVAL;
@@ -159,13 +167,27 @@ d2d_status batch_hv(d2d_batch* b, int prec, const void* v, void* w, hipStream_t 
     const int shape = batch_auto_tile(b, prec);
     if (b->work.find(shape) == b->work.end()) D2D_CHECK(build_work(b, shape));
     auto& wl = b->work[shape];
-    return hv_launch(tables_of(b), prec, shape, wl.first, wl.second, v, w, s, nullptr);
+    HvTables t = tables_of(b);
+    if (parts && prec == D2D_FP64) {
+        // FP64: the central term's register demand lowers the GEMM's occupancy
+        parts->w1 = parts->w2 = nullptr;
+        parts = nullptr;
+    }
+    if (parts) {
+        t.w2 = b->d_w2;
+        parts->w1 = t.w1;
+        parts->w2 = t.w2;
+    }
+    return hv_launch(t, prec, shape, wl.first, wl.second, v, w, s, nullptr);
 }
 
 struct BatchHv : HvOps {
     d2d_batch* b;
     explicit BatchHv(d2d_batch* x) : b(x) {}
     d2d_status hv(int prec, const void* v, void* w, hipStream_t s) override { return batch_hv(b, prec, v, w, s); }
+    d2d_status hv_fused(int prec, const void* v, void* w, hipStream_t s, HvParts* parts) override {
+        return batch_hv(b, prec, v, w, s, parts);
+    }
     d2d_status prepare(int prec) override {
         const int shape = batch_auto_tile(b, prec);
         if (b->work.find(shape) == b->work.end()) return build_work(b, shape);
@@ -198,6 +220,8 @@ d2d_batch::~d2d_batch() {
         if (HR[p]) ctx->free(HR[p], hr_bytes[p]);
     }
     dfree(ctx, d_src, np * K);
+    dfree(ctx, d_srcoff, np * K);
+    dfree(ctx, d_srcdl, np * K);
     dfree(ctx, d_rmap, (size_t)K * Drows);
     dfree(ctx, d_cmap, (size_t)K * Dcols);
     dfree(ctx, d_rc64, (size_t)K * Drows);
@@ -210,6 +234,7 @@ d2d_batch::~d2d_batch() {
     dfree(ctx, d_vt, (size_t)vt_len);
     for (auto& kv : work) dfree(ctx, kv.second.first, (size_t)work_cap[kv.first]);
     if (d_w1) ctx->free(d_w1, (size_t)ntot * 8);
+    if (d_w2) ctx->free(d_w2, (size_t)ntot * 8);
     if (stage_v) ctx->free(stage_v, (size_t)ntot * 8);
     if (stage_w) ctx->free(stage_w, (size_t)ntot * 8);
 }
@@ -326,6 +351,13 @@ extern "C" d2d_status d2d_batch_create(d2d_ctx* ctx, d2d_sb* const* sbs, int n, 
     }
     std::vector<float> rc32(rc.begin(), rc.end()), cc32(cc.begin(), cc.end());
     D2D_CHECK(dupload(ctx, src, &b->d_src));
+    {
+        std::vector<int64_t> so;
+        std::vector<int32_t> sd;
+        central_sources(b->pairs, src, K, so, sd);
+        D2D_CHECK(dupload(ctx, so, &b->d_srcoff));
+        D2D_CHECK(dupload(ctx, sd, &b->d_srcdl));
+    }
     D2D_CHECK(dupload(ctx, rmap, &b->d_rmap));
     D2D_CHECK(dupload(ctx, cmap, &b->d_cmap));
     D2D_CHECK(dupload(ctx, rc, &b->d_rc64));
@@ -336,6 +368,7 @@ extern "C" d2d_status d2d_batch_create(d2d_ctx* ctx, d2d_sb* const* sbs, int n, 
     // every sector small: the GEMM is latency-bound, split its two K-loops
     b->split = std::max(b->max_dl, b->max_dr) <= 768 ? 1 : 0;
     if (b->split) D2D_CHECK(ctx->alloc(&b->d_w1, (size_t)b->ntot * 8));
+    D2D_CHECK(ctx->alloc(&b->d_w2, (size_t)b->ntot * 8));
     D2D_CHECK(build_tiles(b.get()));
     D2D_CHECK(ctx->alloc(&b->stage_v, (size_t)b->ntot * 8));
     D2D_CHECK(ctx->alloc(&b->stage_w, (size_t)b->ntot * 8));

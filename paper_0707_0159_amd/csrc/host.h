@@ -109,6 +109,7 @@ struct HvTables {
     const SectorDev* sec;
     int npairs;
     void* w1;                 // scratch partial output of split K-loops (ntot doubles)
+    void* w2;                 // central-term output of a fused launch (ntot doubles; null = unfused)
     const void* HL[3];
     const void* HR[3];
     int K;
@@ -120,8 +121,10 @@ struct HvTables {
     const float* rcoef32;
     const float* ccoef32;
     int64_t Drows, Dcols;
-    const int4* ctiles;
+    const CentralTile* ctiles;
     int n_ctiles;
+    const int64_t* srcoff;
+    const int32_t* srcdl;
     const int4* ptiles;
     int n_ptiles;
     bf16_t* vp;
@@ -131,10 +134,19 @@ struct HvTables {
 d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkItem* work, int nwork, const void* v,
                      void* w, hipStream_t s, hipEvent_t mid);
 
+// Output of a fused Hv left in parts: the product is (w + w1) + w2, added in
+// that order by the consumer (w1 null when the K-loops are not split).
+struct HvParts {
+    const void* w1;
+    const void* w2;
+};
+
 // Hv of a set of problems on concatenated vectors (one superblock or a batch).
 struct HvOps {
     virtual ~HvOps() = default;
     virtual d2d_status hv(int prec, const void* v, void* w, hipStream_t s) = 0;   // no counting
+    // one launch for GEMMs and central term; the result stays in parts
+    virtual d2d_status hv_fused(int prec, const void* v, void* w, hipStream_t s, HvParts* parts) = 0;
     virtual d2d_status prepare(int prec) = 0;                                      // before graph capture
     virtual d2d_status set_active(const std::vector<int>& active, bool* rebuilt) = 0;
     virtual bool has(int prec) = 0;
@@ -172,7 +184,9 @@ struct d2d_sb {
     float* d_rcoef32 = nullptr;
     float* d_ccoef32 = nullptr;
     int64_t max_elems = 0;
-    int4* d_cblocks = nullptr;         // central-term launch table
+    d2d::CentralTile* d_cblocks = nullptr;   // central-term launch table
+    int64_t* d_srcoff = nullptr;             // central source blocks per (pair, term)
+    int32_t* d_srcdl = nullptr;
     // BF16 operands and per-Hv padded copies of the input vector
     int64_t hl16_len = 0, hr16_len = 0, vp_len = 0, vt_len = 0;
     d2d::bf16_t* d_vp = nullptr;
@@ -187,7 +201,9 @@ struct d2d_sb {
     std::map<int, std::pair<d2d::WorkItem*, int>> work;
     int tile_sel[3] = {-1, -1, -1};     // shape index, or -1 = by size
     int split[3] = {0, 0, 0};
+    int fuse[3] = {0, 1, 1};            // inner Lanczos steps: central term inside the GEMM launch
     void* d_w1 = nullptr;               // N doubles, allocated on first split launch
+    void* d_w2 = nullptr;               // N doubles, central-term part of fused launches
     int64_t hv_count[3] = {0, 0, 0};
     LanczosWork* lz = nullptr;          // owned; freed by free_lanczos
     ~d2d_sb();
@@ -202,9 +218,18 @@ d2d_status check_lanczos_opts(const d2d_lanczos_opts* o);
 d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanczos_opts* opts,
                        const std::vector<int64_t>& len, const double* const* v0, double* energies,
                        double* const* psi, d2d_lanczos_stats* stats);
-d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s, hipEvent_t mid);
+// Hv of a superblock; with parts non-null the launch is fused and the result
+// is left in parts (see HvParts), else w holds the whole product.
+d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s, hipEvent_t mid,
+                       HvParts* parts = nullptr);
 int sb_auto_tile(const d2d_sb* sb, int prec);
 d2d_status sb_work(d2d_sb* sb, int shape, int split, WorkItem** w, int* nwork);
+// central-term launch table of the pairs with keep[p] != 0 (all when keep is null)
+void central_tiles(const std::vector<SectorDev>& pairs, const std::vector<int>* keep,
+                   std::vector<CentralTile>& out);
+// packed offset and row count of the source block of every (pair, term); -1 / 0 when none
+void central_sources(const std::vector<SectorDev>& pairs, const std::vector<int32_t>& src, int K,
+                     std::vector<int64_t>& off, std::vector<int32_t>& dl);
 // work items of the pairs [0, npairs) for a tile shape; split = two items per tile
 void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep, const TileShape& ts, int split,
                std::vector<WorkItem>& out);

@@ -65,8 +65,38 @@ int tile_shape_count();
 const TileShape& tile_shape(int i);
 
 // ---------------------------------------------------------------- launchers
-// Grouped GEMM W = H_l V + V H_r^T over a work list.  Returns false on a bad
-// shape index.  problem tables are device pointers.
+// Central term W += sum_k c_k a_k V b_k^T by gather tables.
+// One launch-table entry per output tile of 64 rows x 8 columns of one pair,
+// carrying everything the tile needs about its pair.
+struct CentralTile {
+    int64_t off;                 // packed offset of the output block
+    int64_t row_base, col_base;  // offsets of the pair's rows / columns in the map tables
+    int p;                       // sector pair
+    int r0, c0;                  // first row and column of the tile
+    int dL, dR;                  // dimensions of the output block
+    int pad;
+};
+struct CentralArgs {
+    const CentralTile* tiles;  // [ntiles]
+    int ntiles;
+    int K;
+    const int64_t* srcoff;     // [npairs*K] packed offset of the source block of term k, or -1
+    const int32_t* srcdl;      // [npairs*K] row count of that source block
+    const int32_t* rmap;       // [K*Drows]
+    const int32_t* cmap;       // [K*Dcols]
+    const void* rcoef;         // [K*Drows] (double for FP64, float otherwise)
+    const void* ccoef;         // [K*Dcols]
+    int64_t Drows, Dcols;
+    const void* V;
+    void* W;
+    const void* W1;            // partial output of split K-loops added into W (nullable)
+};
+hipError_t launch_central(int prec, const CentralArgs& a, hipStream_t s);
+
+// Grouped GEMM W = H_l V + V H_r^T over a work list (split work items write
+// their second K-loop to W1).  With fuse set, the same launch also evaluates
+// the central term into fuse->W (a separate output: the caller adds
+// (W + W1) + fuse->W).
 struct HvGemmArgs {
     const WorkItem* work;
     int nwork;
@@ -75,15 +105,8 @@ struct HvGemmArgs {
     const void* HR;
     const void* V;
     void* W;
-    void* W1;              // second partial output of split work items (nullable)
-    // central term arguments (used by the central-term kernel)
-    int K;
-    const int32_t* src;
-    const int32_t* rmap;
-    const int32_t* cmap;
-    const void* rcoef;     // element type of the precision (double / float)
-    const void* ccoef;
-    int64_t Drows, Dcols;
+    void* W1;                  // second partial output of split work items (nullable)
+    const CentralArgs* fuse;   // nullable
 };
 hipError_t launch_hv_gemm(int shape, const HvGemmArgs& a, hipStream_t s);
 // BF16: HvGemmArgs.V is the padded copy VP, VT its padded transpose.
@@ -96,24 +119,7 @@ hipError_t launch_pack_bf16(const int4* tiles, int ntiles, const SectorDev* sec,
 hipError_t launch_op_bf16(const int64_t* src_off, const int64_t* dst_off, const int32_t* d, const int32_t* dp,
                           int nsec, int transpose, const double* src, bf16_t* dst, int64_t max_d2, hipStream_t s);
 
-// Central term W += sum_k c_k a_k V b_k^T by gather tables.
-struct CentralArgs {
-    const int4* blocks;        // [nblocks] (pair, 64-row tile, 8-column tile, 0)
-    int nblocks;
-    const SectorDev* sec;
-    int npairs;
-    int K;
-    const int32_t* src;        // [npairs*K] source pair or -1
-    const int32_t* rmap;       // [K*Drows]
-    const int32_t* cmap;       // [K*Dcols]
-    const void* rcoef;         // [K*Drows] (double for FP64, float otherwise)
-    const void* ccoef;         // [K*Dcols]
-    int64_t Drows, Dcols;
-    const void* V;
-    void* W;
-    const void* W1;            // partial output of split K-loops added into W (nullable)
-};
-hipError_t launch_central(int prec, const CentralArgs& a, hipStream_t s);
+
 
 // Assembly of dense half Hamiltonian sectors on the device:
 // out[s](r,c) = d(a,a') F0(b,b') + S0(a,a') d(b,b') + sum_t coef_t S_t(a,a') F_t(b,b')
@@ -142,13 +148,10 @@ hipError_t launch_fill(void* x, int prec, int64_t n, double v, hipStream_t s);
 hipError_t launch_check_finite(const void* x, int prec, int64_t n, int* flag, hipStream_t s);
 
 // ---------------------------------------------------------------- Lanczos kernels
-// lowest eigenpair of the k x k tridiagonal (alpha[0..k-1], beta[1..k-1])
-hipError_t launch_tridiag(const double* alpha, const double* beta, int k, double* theta,
-                          double* y, double* work, hipStream_t s);
 
 // ------------------------------------------------------------------ Lanczos sets
 // Scalar layout per problem (doubles), at scal + prob * S_LEN.
-constexpr int S_ALPHA = 0, S_BETA = 130, S_THETA = 524, S_Y = 528, S_TWORK = 660, S_LEN = 1400;
+constexpr int S_ALPHA = 0, S_BETA = 130, S_THETA = 524, S_Y = 528, S_LEN = 660;
 
 // Block of a segmented kernel: problem, its block range [pb0, pb1), chunk [lo, hi).
 struct LzSeg {
@@ -183,6 +186,10 @@ struct LzStepArgs {
     bool upcast;
     const float* w32;
     double* w;
+    // parts of a fused Hv: the product is (w32 or w) + wp1 + wp2 in the Hv's
+    // own precision (FP32 when upcast, else FP64); each nullable
+    const void* wp1;
+    const void* wp2;
     double* partial;
     double* partial2;
     int NB;

@@ -48,30 +48,241 @@ struct Mf<float> {
     static constexpr int PA_MOD = 64, PA_RES = 32;   // row stride = 32 (mod 64) floats
 };
 
-// Kernel arguments (by value).  Central term: for output row r (column c) of
-// pair p and bond term k, rmap/cmap give the row (column) of the source pair
-// src[p*K+k] or -1, rcoef/ccoef the signed coefficients.
+// ------------------------------------------------------------------ central term
+__device__ inline float bf16_to_f32(bf16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+
+static constexpr int CT = 8;
+static constexpr int KMAX = 16;
+
+// Central-term arguments in the element types of one precision.
+template <typename TI, typename TO, typename TC>
+struct CentralK {
+    const CentralTile* tiles;
+    int ntiles;
+    int K;
+    const int64_t* srcoff;
+    const int32_t* srcdl;
+    const int32_t* rmap;
+    const int32_t* cmap;
+    const TC* rcoef;
+    const TC* ccoef;
+    int64_t Drows, Dcols;
+    const TI* V;
+    TO* W;
+    const TO* W1;
+};
+
+// Central term.  One wave per output tile of 64 rows x CT columns of one pair;
+// the NW waves of a block take tiles i0 .. i0+NW-1 (every wave of the block
+// must call this: it holds a block barrier).  The launch-table entry carries
+// the pair's offsets and dimensions, and the source block of every term comes
+// from a per-(pair, term) table, so all the loads the gathers depend on
+// (column maps and coefficients into shared memory; each lane's row maps and
+// coefficients of all K terms; the old W and the split-K partial W1) are
+// issued in one round.  Each lane owns one row r; runs of consecutive i1 map
+// to consecutive source rows, so a wave's gathers are coalesced.
+// ACCUM: W = (W + W1) + central.  Otherwise W is a separate output that
+// receives the central term alone, for a consumer that adds (W + W1) + it.
+template <typename TI, typename TO, typename TC, int NW, bool ACCUM>
+__device__ inline void central_tiles_block(const CentralK<TI, TO, TC>& c, int i0) {
+    __shared__ int64_t s_off2[NW][KMAX];
+    __shared__ int s_dl2[NW][KMAX];
+    __shared__ int s_cm[NW][KMAX][CT];
+    __shared__ TC s_cc[NW][KMAX][CT];
+    const int wv = NW == 1 ? 0 : (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int ti = i0 + wv;
+    const bool live = ti < c.ntiles;
+    const CentralTile t = c.tiles[live ? ti : 0];
+    const int K = live ? c.K : 0;
+    if (lane < K) {
+        s_off2[wv][lane] = c.srcoff[(int64_t)t.p * K + lane];
+        s_dl2[wv][lane] = c.srcdl[(int64_t)t.p * K + lane];
+    }
+    for (int q = lane; q < K * CT; q += 64) {
+        const int k = q / CT, cc = q % CT, col = t.c0 + cc;
+        const bool ok = col < t.dR;
+        s_cm[wv][k][cc] = ok ? c.cmap[k * c.Dcols + t.col_base + col] : -1;
+        s_cc[wv][k][cc] = ok ? c.ccoef[k * c.Dcols + t.col_base + col] : TC(0);
+    }
+    const int r = t.r0 + lane;
+    const bool rok = live && r < t.dL;
+    // Loads below are unconditional, at an index clamped into the tables (the
+    // element of row 0, or of column 0, of this tile's own block), and the
+    // out-of-range values are masked afterwards: a load under a condition whose
+    // value is selected right at the join would make every load wait for the
+    // previous one.
+    int rm[KMAX];
+    TC rc[KMAX];
+    TO wo[CT];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        rm[k] = -1;
+        rc[k] = TC(0);
+    }
+#pragma unroll
+    for (int j = 0; j < CT; ++j) wo[j] = TO(0);
+    if (K > 0) {
+        const int rr = rok ? r : 0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const int64_t i = (k < K ? k : 0) * c.Drows + t.row_base + rr;
+            rm[k] = c.rmap[i];
+            rc[k] = c.rcoef[i];
+        }
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (!(rok && k < K)) {
+                rm[k] = -1;
+                rc[k] = TC(0);
+            }
+    }
+    if constexpr (ACCUM) {
+        if (live) {
+            const int rr = rok ? r : 0;
+#pragma unroll
+            for (int j = 0; j < CT; ++j) {
+                const int cc = t.c0 + j < t.dR ? t.c0 + j : 0;
+                const int64_t e = t.off + rr + (int64_t)cc * t.dL;
+                wo[j] = c.W[e] + (c.W1 ? c.W1[e] : TO(0));
+            }
+        }
+    }
+    __syncthreads();
+    if (!rok) return;
+    TC acc[CT];
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[j] = TC(0);
+    // Gather addressing: for term k and tile column j the source column
+    // V + so + cm * dl2 is the same for the whole wave, only the row map rm
+    // differs per lane, so a gather is a wave-uniform base plus a 32-bit
+    // per-lane byte offset (a source block is far below 4 GB), and the 8
+    // column gathers of one term share that offset.  bf16 input: a gather
+    // reads the aligned 32-bit word holding the element and keeps its half
+    // after all loads of the group are issued (16-bit loads into half
+    // registers, or converting right at the load, would make each gather wait
+    // for the previous one); an aligned word never crosses a page, so the
+    // wider read stays inside the allocation holding the element.
+    constexpr bool NARROW = sizeof(TI) == 2;
+    // gathers in groups of KG terms (all loads of a group, then its FMAs)
+    constexpr int KG = sizeof(TC) == 8 ? 4 : 8;
+#pragma unroll
+    for (int k0 = 0; k0 < KMAX; k0 += KG) {
+        if (k0 >= K) break;
+        TC x[KG][CT];
+        uint32_t raw[NARROW ? KG : 1][NARROW ? CT : 1];
+        uint64_t hi = 0;   // bit q*CT+j: the element is the word's upper half
+        static_assert(!NARROW || KG * CT <= 64, "half mask");
+#pragma unroll
+        for (int q = 0; q < KG; ++q) {
+            const int k = k0 + q < K ? k0 + q : 0;
+            const int64_t so = s_off2[wv][k];
+            const bool okr = k0 + q < K && rm[k0 + q] >= 0 && so >= 0;
+            const int64_t dl2 = s_dl2[wv][k];
+            const uint32_t rr = (uint32_t)rm[k0 + q];
+#pragma unroll
+            for (int j = 0; j < CT; ++j) {
+                const int cm = s_cm[wv][k][j];
+                const bool ok = okr && cm >= 0;
+                const TI* col = c.V + (so >= 0 ? so : 0) + (int64_t)(cm >= 0 ? cm : 0) * dl2;   // uniform
+                if constexpr (NARROW) {
+                    const uint32_t shc = (uint32_t)(((uintptr_t)col >> 1) & 1);
+                    const char* wb = (const char*)(col - shc);                                      // 4-byte aligned
+                    const uint32_t pe = rr + shc;
+                    raw[q][j] = ok ? *(const uint32_t*)(wb + ((pe >> 1) << 2)) : 0u;
+                    hi |= (uint64_t)(pe & 1) << (q * CT + j);
+                } else {
+                    x[q][j] = ok ? (TC) * (const TI*)((const char*)col + rr * (uint32_t)sizeof(TI)) : TC(0);
+                }
+            }
+        }
+        if constexpr (NARROW) {
+#pragma unroll
+            for (int q = 0; q < KG; ++q)
+#pragma unroll
+                for (int j = 0; j < CT; ++j)
+                    x[q][j] = __uint_as_float(((hi >> (q * CT + j)) & 1) ? (raw[q][j] & 0xffff0000u)
+                                                                        : (raw[q][j] << 16));
+        }
+#pragma unroll
+        for (int q = 0; q < KG; ++q) {
+            const int k = k0 + q < K ? k0 + q : 0;
+#pragma unroll
+            for (int j = 0; j < CT; ++j) acc[j] += rc[k0 + q] * s_cc[wv][k][j] * x[q][j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < CT; ++j)
+        if (t.c0 + j < t.dR) {
+            const int64_t e = t.off + r + (int64_t)(t.c0 + j) * t.dL;
+            c.W[e] = wo[j] + (TO)acc[j];
+        }
+}
+
+template <typename TI, typename TO, typename TC>
+__global__ void __launch_bounds__(64) k_central(const CentralK<TI, TO, TC> c) {
+    central_tiles_block<TI, TO, TC, 1, true>(c, blockIdx.x);
+}
+
+template <typename TI, typename TO, typename TC>
+static CentralK<TI, TO, TC> central_args(const CentralArgs& a) {
+    CentralK<TI, TO, TC> c;
+    c.tiles = a.tiles;
+    c.ntiles = a.ntiles;
+    c.K = a.K;
+    c.srcoff = a.srcoff;
+    c.srcdl = a.srcdl;
+    c.rmap = a.rmap;
+    c.cmap = a.cmap;
+    c.rcoef = (const TC*)a.rcoef;
+    c.ccoef = (const TC*)a.ccoef;
+    c.Drows = a.Drows;
+    c.Dcols = a.Dcols;
+    c.V = (const TI*)a.V;
+    c.W = (TO*)a.W;
+    c.W1 = (const TO*)a.W1;
+    return c;
+}
+
+hipError_t launch_central(int prec, const CentralArgs& a, hipStream_t st) {
+    if (a.ntiles == 0) return hipSuccess;
+    if (a.K > KMAX) return hipErrorInvalidValue;
+    dim3 grid(a.ntiles);
+    if (prec == D2D_FP64)
+        hipLaunchKernelGGL((k_central<double, double, double>), grid, dim3(64), 0, st,
+                           central_args<double, double, double>(a));
+    else if (prec == D2D_FP32)
+        hipLaunchKernelGGL((k_central<float, float, float>), grid, dim3(64), 0, st, central_args<float, float, float>(a));
+    else
+        hipLaunchKernelGGL((k_central<bf16_t, float, float>), grid, dim3(64), 0, st,
+                           central_args<bf16_t, float, float>(a));
+    return hipGetLastError();
+}
+
+// Kernel arguments (by value).  With CEN, the blocks past the nwork GEMM work
+// items evaluate the central term into its own output (cen.W).
 template <typename T>
 struct HvK {
     const WorkItem* work;
+    int nwork;
     const SectorDev* sec;
     const T* HL;
     const T* HRt;
     const T* V;
     T* W;
     T* W1;
-    int K;
-    const int32_t* src;
-    const int32_t* rmap;
-    const int32_t* cmap;
-    const T* rcoef;
-    const T* ccoef;
-    int64_t Drows, Dcols;
+    CentralK<T, T, T> cen;
 };
 
-template <typename T, int BM, int BN, int BK, int WGM, int WGN>
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, bool CEN>
 __global__ void __launch_bounds__(64 * WGM * WGN)
 k_hv_gemm(const HvK<T> g) {
+    if constexpr (CEN) {
+        if ((int)blockIdx.x >= g.nwork) {
+            central_tiles_block<T, T, T, WGM * WGN, false>(g.cen, ((int)blockIdx.x - g.nwork) * WGM * WGN);
+            return;
+        }
+    }
     using M = Mf<T>;
     const WorkItem* __restrict__ work = g.work;
     const SectorDev* __restrict__ sec = g.sec;
@@ -193,11 +404,18 @@ k_hv_gemm(const HvK<T> g) {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 __device__ inline bf16_t f32_to_bf16_rne(float f);
 
-template <int BM, int BN, int BK, int WGM, int WGN>
+template <int BM, int BN, int BK, int WGM, int WGN, bool CEN>
 __global__ void __launch_bounds__(64 * WGM * WGN)
-k_hv_gemm_bf16(const WorkItem* __restrict__ work, const SectorDev* __restrict__ sec, const bf16_t* __restrict__ HL,
-               const bf16_t* __restrict__ HRt, const bf16_t* __restrict__ VP, const bf16_t* __restrict__ VT,
-               float* __restrict__ W, float* __restrict__ W1) {
+k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __restrict__ sec,
+               const bf16_t* __restrict__ HL, const bf16_t* __restrict__ HRt, const bf16_t* __restrict__ VP,
+               const bf16_t* __restrict__ VT, float* __restrict__ W, float* __restrict__ W1,
+               const CentralK<bf16_t, float, float> cen) {
+    if constexpr (CEN) {
+        if ((int)blockIdx.x >= nwork) {
+            central_tiles_block<bf16_t, float, float, WGM * WGN, false>(cen, ((int)blockIdx.x - nwork) * WGM * WGN);
+            return;
+        }
+    }
     using M = Mf<float>;
     constexpr int NT = 64 * WGM * WGN;
     constexpr int WM = BM / WGM, WN = BN / WGN;
@@ -299,32 +517,34 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, const SectorDev* __restrict__ 
     }
 }
 
-hipError_t launch_hv_gemm_bf16(int shape, const HvGemmArgs& a, const void* VT, hipStream_t st) {
-    if (a.nwork <= 0) return hipSuccess;
-    dim3 grid(a.nwork);
+template <int BM, int BN, int BK, int WGM, int WGN>
+static void gemm_bf16_launch(const HvGemmArgs& a, const void* VT, hipStream_t st) {
+    constexpr int NW = WGM * WGN;
     const bf16_t* HL = (const bf16_t*)a.HL;
     const bf16_t* HR = (const bf16_t*)a.HR;
     const bf16_t* VP = (const bf16_t*)a.V;
     const bf16_t* V2 = (const bf16_t*)VT;
     float* W = (float*)a.W;
     float* W1 = (float*)a.W1;
+    if (a.fuse) {
+        const int extra = (a.fuse->ntiles + NW - 1) / NW;
+        hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, true>), dim3(a.nwork + extra), dim3(64 * NW), 0, st,
+                           a.work, a.nwork, a.sec, HL, HR, VP, V2, W, W1, central_args<bf16_t, float, float>(*a.fuse));
+    } else {
+        hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, false>), dim3(a.nwork), dim3(64 * NW), 0, st, a.work,
+                           a.nwork, a.sec, HL, HR, VP, V2, W, W1, CentralK<bf16_t, float, float>{});
+    }
+}
+
+hipError_t launch_hv_gemm_bf16(int shape, const HvGemmArgs& a, const void* VT, hipStream_t st) {
+    if (a.nwork <= 0) return hipSuccess;
+    if (a.fuse && a.fuse->K > KMAX) return hipErrorInvalidValue;
     switch (shape) {
-        case 14:
-            hipLaunchKernelGGL((k_hv_gemm_bf16<64, 64, 32, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec, HL, HR, VP, V2, W, W1);
-            break;
-        case 15:
-            hipLaunchKernelGGL((k_hv_gemm_bf16<128, 128, 32, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec, HL, HR,
-                               VP, V2, W, W1);
-            break;
-        case 16:
-            hipLaunchKernelGGL((k_hv_gemm_bf16<128, 128, 64, 2, 2>), grid, dim3(256), 0, st, a.work, a.sec, HL, HR,
-                               VP, V2, W, W1);
-            break;
-        case 17:
-            hipLaunchKernelGGL((k_hv_gemm_bf16<32, 32, 64, 1, 1>), grid, dim3(64), 0, st, a.work, a.sec, HL, HR, VP, V2, W, W1);
-            break;
-        default:
-            return hipErrorInvalidValue;
+        case 14: gemm_bf16_launch<64, 64, 32, 2, 2>(a, VT, st); break;
+        case 15: gemm_bf16_launch<128, 128, 32, 2, 2>(a, VT, st); break;
+        case 16: gemm_bf16_launch<128, 128, 64, 2, 2>(a, VT, st); break;
+        case 17: gemm_bf16_launch<32, 32, 64, 1, 1>(a, VT, st); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
@@ -339,14 +559,21 @@ k_pack_bf16(const int4* __restrict__ tiles, const SectorDev* __restrict__ sec, c
     const SectorDev s = sec[ti.x];
     const int r0 = ti.y * 64, c0 = ti.z * 64;
     const int t = threadIdx.x;
+    // all 16 loads first (index clamped into the block), then the stores
+    uint32_t x[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int rr = t & 63, cc = (t >> 6) + 4 * q;
+        const int r = min(r0 + rr, s.dL - 1), c = min(c0 + cc, s.dR - 1);
+        x[q] = v[s.off + r + (int64_t)c * s.dL];
+    }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int rr = t & 63, cc = (t >> 6) + 4 * q;
         const int r = r0 + rr, c = c0 + cc;
         if (r < s.dL && c < s.dR) {
-            const bf16_t x = v[s.off + r + (int64_t)c * s.dL];
-            sh[cc][rr] = x;
-            vp[s.vp_off + r + (int64_t)c * s.dLp] = x;
+            sh[cc][rr] = (bf16_t)x[q];
+            vp[s.vp_off + r + (int64_t)c * s.dLp] = (bf16_t)x[q];
         }
     }
     __syncthreads();
@@ -417,188 +644,51 @@ static const TileShape kShapes[] = {
 int tile_shape_count() { return (int)(sizeof(kShapes) / sizeof(kShapes[0])); }
 const TileShape& tile_shape(int i) { return kShapes[i]; }
 
-template <typename T>
-static HvK<T> make_args(const HvGemmArgs& a) {
+template <typename T, int BM, int BN, int BK, int WGM, int WGN>
+static void gemm_launch(const HvGemmArgs& a, hipStream_t st) {
+    constexpr int NW = WGM * WGN;
     HvK<T> g;
     g.work = a.work;
+    g.nwork = a.nwork;
     g.sec = a.sec;
     g.HL = (const T*)a.HL;
     g.HRt = (const T*)a.HR;
     g.V = (const T*)a.V;
     g.W = (T*)a.W;
     g.W1 = (T*)a.W1;
-    g.K = a.K;
-    g.src = a.src;
-    g.rmap = a.rmap;
-    g.cmap = a.cmap;
-    g.rcoef = (const T*)a.rcoef;
-    g.ccoef = (const T*)a.ccoef;
-    g.Drows = a.Drows;
-    g.Dcols = a.Dcols;
-    return g;
+    if (a.fuse) {
+        g.cen = central_args<T, T, T>(*a.fuse);
+        const int extra = (a.fuse->ntiles + NW - 1) / NW;
+        hipLaunchKernelGGL((k_hv_gemm<T, BM, BN, BK, WGM, WGN, true>), dim3(a.nwork + extra), dim3(64 * NW), 0, st, g);
+    } else {
+        g.cen = CentralK<T, T, T>{};
+        hipLaunchKernelGGL((k_hv_gemm<T, BM, BN, BK, WGM, WGN, false>), dim3(a.nwork), dim3(64 * NW), 0, st, g);
+    }
 }
 
 hipError_t launch_hv_gemm(int shape, const HvGemmArgs& a, hipStream_t st) {
     if (a.nwork <= 0) return hipSuccess;
-    dim3 grid(a.nwork);
+    if (a.fuse && a.fuse->K > KMAX) return hipErrorInvalidValue;
     switch (shape) {
-        case 0:
-            hipLaunchKernelGGL((k_hv_gemm<double, 32, 32, 16, 2, 2>), grid, dim3(256), 0, st, make_args<double>(a));
-            break;
-        case 1:
-            hipLaunchKernelGGL((k_hv_gemm<double, 64, 64, 16, 2, 2>), grid, dim3(256), 0, st, make_args<double>(a));
-            break;
-        case 2:
-            hipLaunchKernelGGL((k_hv_gemm<double, 128, 128, 16, 2, 2>), grid, dim3(256), 0, st, make_args<double>(a));
-            break;
-        case 3:
-            hipLaunchKernelGGL((k_hv_gemm<float, 32, 32, 16, 1, 1>), grid, dim3(64), 0, st, make_args<float>(a));
-            break;
-        case 4:
-            hipLaunchKernelGGL((k_hv_gemm<float, 64, 64, 16, 2, 2>), grid, dim3(256), 0, st, make_args<float>(a));
-            break;
-        case 5:
-            hipLaunchKernelGGL((k_hv_gemm<float, 128, 128, 16, 2, 2>), grid, dim3(256), 0, st, make_args<float>(a));
-            break;
-        case 6:
-            hipLaunchKernelGGL((k_hv_gemm<double, 64, 64, 32, 2, 2>), grid, dim3(256), 0, st, make_args<double>(a));
-            break;
-        case 7:
-            hipLaunchKernelGGL((k_hv_gemm<float, 64, 64, 32, 2, 2>), grid, dim3(256), 0, st, make_args<float>(a));
-            break;
-        case 8:
-            hipLaunchKernelGGL((k_hv_gemm<float, 128, 128, 32, 2, 2>), grid, dim3(256), 0, st, make_args<float>(a));
-            break;
-        case 9:
-            hipLaunchKernelGGL((k_hv_gemm<double, 128, 64, 16, 2, 2>), grid, dim3(256), 0, st, make_args<double>(a));
-            break;
-        case 10:
-            hipLaunchKernelGGL((k_hv_gemm<float, 128, 64, 16, 2, 2>), grid, dim3(256), 0, st, make_args<float>(a));
-            break;
-        case 11:
-            hipLaunchKernelGGL((k_hv_gemm<float, 64, 64, 64, 2, 2>), grid, dim3(256), 0, st, make_args<float>(a));
-            break;
-        case 12:
-            hipLaunchKernelGGL((k_hv_gemm<double, 32, 32, 32, 2, 2>), grid, dim3(256), 0, st, make_args<double>(a));
-            break;
-        case 13:
-            hipLaunchKernelGGL((k_hv_gemm<double, 64, 64, 64, 2, 2>), grid, dim3(256), 0, st, make_args<double>(a));
-            break;
-        default:
-            return hipErrorInvalidValue;
+        case 0: gemm_launch<double, 32, 32, 16, 2, 2>(a, st); break;
+        case 1: gemm_launch<double, 64, 64, 16, 2, 2>(a, st); break;
+        case 2: gemm_launch<double, 128, 128, 16, 2, 2>(a, st); break;
+        case 3: gemm_launch<float, 32, 32, 16, 1, 1>(a, st); break;
+        case 4: gemm_launch<float, 64, 64, 16, 2, 2>(a, st); break;
+        case 5: gemm_launch<float, 128, 128, 16, 2, 2>(a, st); break;
+        case 6: gemm_launch<double, 64, 64, 32, 2, 2>(a, st); break;
+        case 7: gemm_launch<float, 64, 64, 32, 2, 2>(a, st); break;
+        case 8: gemm_launch<float, 128, 128, 32, 2, 2>(a, st); break;
+        case 9: gemm_launch<double, 128, 64, 16, 2, 2>(a, st); break;
+        case 10: gemm_launch<float, 128, 64, 16, 2, 2>(a, st); break;
+        case 11: gemm_launch<float, 64, 64, 64, 2, 2>(a, st); break;
+        case 12: gemm_launch<double, 32, 32, 32, 2, 2>(a, st); break;
+        case 13: gemm_launch<double, 64, 64, 64, 2, 2>(a, st); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ central term
-__device__ inline float bf16_to_f32(bf16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
-
-template <typename TI>
-__device__ inline float load_as_float(const TI* p, int64_t i);
-template <>
-__device__ inline float load_as_float<float>(const float* p, int64_t i) { return p[i]; }
-template <>
-__device__ inline float load_as_float<bf16_t>(const bf16_t* p, int64_t i) { return bf16_to_f32(p[i]); }
-
-// Central term.  One wave per output tile of 64 rows x CT columns of one pair
-// (compact launch table).  Each lane owns one row r: it loads the row maps and
-// coefficients of all K terms once; the column maps of the tile's CT columns
-// are staged in shared memory; then all K x CT gathers of the lane are issued
-// together (runs of consecutive i1 map to consecutive source rows, so a
-// wave's gathers are coalesced) and W is updated once per element.
-static constexpr int CT = 8;
-static constexpr int KMAX = 16;
-
-template <typename TI, typename TO, typename TC>
-__global__ void __launch_bounds__(64)
-k_central(const int4* __restrict__ tiles, const SectorDev* __restrict__ sec, int K, const int32_t* __restrict__ src,
-          const int32_t* __restrict__ rmap, const int32_t* __restrict__ cmap, const TC* __restrict__ rcoef,
-          const TC* __restrict__ ccoef, int64_t Drows, int64_t Dcols, const TI* __restrict__ V,
-          TO* __restrict__ W, const TO* __restrict__ W1) {
-    __shared__ int64_t s_off2[KMAX];
-    __shared__ int s_dl2[KMAX];
-    __shared__ int s_cm[KMAX][CT];
-    __shared__ TC s_cc[KMAX][CT];
-    const int4 t = tiles[blockIdx.x];
-    const int p = t.x, r0 = t.y * 64, c0 = t.z * CT;
-    const SectorDev s = sec[p];
-    const int lane = threadIdx.x;
-    if (lane < K) {
-        const int p2 = src[p * K + lane];
-        s_off2[lane] = p2 >= 0 ? sec[p2].off : -1;
-        s_dl2[lane] = p2 >= 0 ? sec[p2].dL : 0;
-    }
-    for (int q = lane; q < K * CT; q += 64) {
-        const int k = q / CT, cc = q % CT, c = c0 + cc;
-        const bool ok = c < s.dR;
-        s_cm[k][cc] = ok ? cmap[k * Dcols + s.col_base + c] : -1;
-        s_cc[k][cc] = ok ? ccoef[k * Dcols + s.col_base + c] : TC(0);
-    }
-    __syncthreads();
-    const int r = r0 + lane;
-    if (r >= s.dL) return;
-    TC acc[CT];
-#pragma unroll
-    for (int c = 0; c < CT; ++c) acc[c] = TC(0);
-    // terms in groups of KG: all row-map loads of a group first, then all its gathers
-    constexpr int KG = 4;
-    for (int k0 = 0; k0 < K; k0 += KG) {
-        int rm[KG];
-        TC rc[KG];
-#pragma unroll
-        for (int q = 0; q < KG; ++q) {
-            const int k = k0 + q;
-            const bool ok = k < K && s_off2[k < K ? k : 0] >= 0;
-            rm[q] = ok ? rmap[k * Drows + s.row_base + r] : -1;
-            rc[q] = ok ? rcoef[k * Drows + s.row_base + r] : TC(0);
-        }
-        TC x[KG][CT];
-#pragma unroll
-        for (int q = 0; q < KG; ++q) {
-            const int k = k0 + q < K ? k0 + q : 0;
-            const int64_t base = s_off2[k] + rm[q];
-            const int64_t dl2 = s_dl2[k];
-#pragma unroll
-            for (int c = 0; c < CT; ++c) {
-                const int cm = s_cm[k][c];
-                const bool ok = rm[q] >= 0 && cm >= 0;
-                if constexpr (sizeof(TI) == sizeof(TC)) x[q][c] = ok ? (TC)V[base + cm * dl2] : TC(0);
-                else x[q][c] = ok ? (TC)load_as_float<TI>(V, base + cm * dl2) : TC(0);
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < KG; ++q) {
-            const int k = k0 + q < K ? k0 + q : 0;
-#pragma unroll
-            for (int c = 0; c < CT; ++c) acc[c] += rc[q] * s_cc[k][c] * x[q][c];
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < CT; ++c)
-        if (c0 + c < s.dR) {
-            const int64_t e = s.off + r + (int64_t)(c0 + c) * s.dL;
-            W[e] += (W1 ? W1[e] : TO(0)) + (TO)acc[c];
-        }
-}
-
-hipError_t launch_central(int prec, const CentralArgs& a, hipStream_t st) {
-    if (a.K == 0 || a.nblocks == 0) return hipSuccess;
-    if (a.K > KMAX) return hipErrorInvalidValue;
-    dim3 grid(a.nblocks);
-    if (prec == D2D_FP64)
-        hipLaunchKernelGGL((k_central<double, double, double>), grid, dim3(64), 0, st, a.blocks, a.sec, a.K, a.src,
-                           a.rmap, a.cmap, (const double*)a.rcoef, (const double*)a.ccoef, a.Drows, a.Dcols,
-                           (const double*)a.V, (double*)a.W, (const double*)a.W1);
-    else if (prec == D2D_FP32)
-        hipLaunchKernelGGL((k_central<float, float, float>), grid, dim3(64), 0, st, a.blocks, a.sec, a.K, a.src,
-                           a.rmap, a.cmap, (const float*)a.rcoef, (const float*)a.ccoef, a.Drows, a.Dcols,
-                           (const float*)a.V, (float*)a.W, (const float*)a.W1);
-    else
-        hipLaunchKernelGGL((k_central<bf16_t, float, float>), grid, dim3(64), 0, st, a.blocks, a.sec, a.K, a.src,
-                           a.rmap, a.cmap, (const float*)a.rcoef, (const float*)a.ccoef, a.Drows, a.Dcols,
-                           (const bf16_t*)a.V, (float*)a.W, (const float*)a.W1);
-    return hipGetLastError();
-}
 
 // ------------------------------------------------------------------ assembly
 // transpose_out != 0 writes the transposed block (used for H_r^T).

@@ -52,8 +52,10 @@ __device__ int sturm_count(const double* a, const double* b, int k, double x) {
 }
 
 __device__ void tridiag_body(const double* __restrict__ alpha, const double* __restrict__ beta, int k,
-                             double* __restrict__ theta_out, double* __restrict__ y, double* __restrict__ work) {
+                             double* __restrict__ theta_out, double* __restrict__ y_out) {
     __shared__ double a[128], b[128];
+    __shared__ double dl[128], d[128], du[128], du2[128], y[128];
+    __shared__ int piv[128];
     __shared__ double lo_s, hi_s;
     const int l = threadIdx.x;
     for (int i = l; i < k; i += 64) {
@@ -73,9 +75,14 @@ __device__ void tridiag_body(const double* __restrict__ alpha, const double* __r
         hi_s = hi + pad;
     }
     __syncthreads();
+    double plo = 0.0, phi = 0.0;
     for (int it = 0; it < 40; ++it) {
         const double lo = lo_s, hi = hi_s;
         if (hi - lo <= 4.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) || hi <= lo) break;
+        // a bracket of a few ulps can stop shrinking (the 65 points round onto its ends)
+        if (it > 0 && lo == plo && hi == phi) break;
+        plo = lo;
+        phi = hi;
         const double x = lo + (hi - lo) * (double)(l + 1) / 65.0;
         const int c = sturm_count(a, b, k, x);
         // first lane whose point has at least one eigenvalue below it
@@ -92,16 +99,11 @@ __device__ void tridiag_body(const double* __restrict__ alpha, const double* __r
         }
         __syncthreads();
     }
+    // inverse iteration (T - theta I) z = y on lane 0, all in shared memory:
+    // LU with partial pivoting in the LAPACK dgttrf layout (dl, d, du, du2, piv)
     if (l == 0) {
         const double th = 0.5 * (lo_s + hi_s);
         theta_out[0] = th;
-        // inverse iteration: (T - th I) z = y, Gaussian elimination with partial pivoting.
-        // work: dl[k], d[k], du[k], du2[k], z[k]
-        double* dl = work;
-        double* d = work + 128;
-        double* du = work + 256;
-        double* du2 = work + 384;
-        int* piv = (int*)(work + 512);
         const double eps = 2.220446049250313e-16 * fmax(1.0, fabs(th));
         for (int i = 0; i < k; ++i) {
             d[i] = a[i] - th;
@@ -109,7 +111,6 @@ __device__ void tridiag_body(const double* __restrict__ alpha, const double* __r
             dl[i] = i + 1 < k ? b[i + 1] : 0.0;
             du2[i] = 0.0;
         }
-        // LU with partial pivoting (LAPACK dgttrf scheme)
         for (int i = 0; i < k - 1; ++i) {
             if (fabs(d[i]) >= fabs(dl[i])) {
                 piv[i] = i;
@@ -157,19 +158,8 @@ __device__ void tridiag_body(const double* __restrict__ alpha, const double* __r
         if (y[0] < 0.0)
             for (int i = 0; i < k; ++i) y[i] = -y[i];
     }
-}
-
-__global__ void __launch_bounds__(64)
-k_tridiag(const double* __restrict__ alpha, const double* __restrict__ beta, int k, double* __restrict__ theta_out,
-          double* __restrict__ y, double* __restrict__ work) {
-    tridiag_body(alpha, beta, k, theta_out, y, work);
-}
-
-hipError_t launch_tridiag(const double* alpha, const double* beta, int k, double* theta, double* y, double* work,
-                          hipStream_t s) {
-    if (k < 1 || k > 128) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(64), 0, s, alpha, beta, k, theta, y, work);
-    return hipGetLastError();
+    __syncthreads();
+    for (int i = l; i < k; i += 64) y_out[i] = y[i];
 }
 
 // ------------------------------------------------------------------ density matrix helpers
@@ -232,10 +222,14 @@ hipError_t launch_gemm_nn_f64(const double* A, int lda, const double* B, int ldb
 // Scalars live per problem at scal + prob * S_LEN (layout in lz_layout.h).
 namespace d2d {
 
-static constexpr int LZ_STEP_NB = 256;
+static constexpr int LZ_STEP_NB = 1024;
 
+// About 2048 elements per block: with the U-way unrolled element loops below a
+// block covers its segment in one or two rounds of loads, so a step kernel
+// costs about one memory latency on mid-sized problems and is bandwidth-bound
+// on large ones.
 int lz_step_blocks(int64_t n) {
-    int64_t nb = (n + 1023) / 1024;
+    int64_t nb = (n + 2047) / 2048;
     if (nb > LZ_STEP_NB) nb = LZ_STEP_NB;
     if (nb < 1) nb = 1;
     return (int)nb;
@@ -275,30 +269,58 @@ __device__ inline void write_partials(const double (&acc)[R], int rows, double* 
     }
 }
 
-// Step kernel 1: partials of c1 = Q[0..nq)^T w (w upcast from FP32 first when UPCAST).
+// Elements a thread keeps in flight per round in the step kernels (bounded
+// so that the U x NQ loaded values stay in registers).
+template <int NQ>
+struct StepUnroll {
+    static constexpr int U = NQ <= 4 ? 4 : (NQ <= 8 ? 2 : 1);
+};
+
+// Step kernel 1: w = (w + p1) + p2 in the Hv's precision (the parts of a
+// fused Hv, each nullable), upcast from FP32 when UPCAST, stored as FP64 when
+// it changed; partials of c1 = Q[0..nq)^T w.
 template <int NQ, bool UPCAST>
 __global__ void __launch_bounds__(LZ_THREADS)
 k_lz_dots(const LzSeg* __restrict__ bt, const int* __restrict__ active, const double* __restrict__ Q,
-          int64_t ldq, int nq, const double* __restrict__ w64in, const float* __restrict__ w32,
-          double* __restrict__ w64out, double* __restrict__ partial, int NB) {
+          int64_t ldq, int nq, const double* w64in, const float* __restrict__ w32,
+          const void* __restrict__ p1, const void* __restrict__ p2, double* w64out,
+          double* __restrict__ partial, int NB) {
+    constexpr int U = StepUnroll<NQ>::U;
     const LzSeg sg = bt[blockIdx.x];
     if (!active[sg.prob]) return;
     double acc[NQ];
 #pragma unroll
     for (int j = 0; j < NQ; ++j) acc[j] = 0.0;
-    for (int64_t e = sg.lo + threadIdx.x; e < sg.hi; e += blockDim.x) {
-        double x;
-        if constexpr (UPCAST) {
-            x = (double)w32[e];
-            w64out[e] = x;
-        } else {
-            x = w64in[e];
+    const int64_t st = blockDim.x;
+    for (int64_t e0 = sg.lo + threadIdx.x; e0 < sg.hi; e0 += U * st) {
+        double x[U], q[U][NQ];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = e0 + u * st;
+            const bool ok = e < sg.hi;
+            if constexpr (UPCAST) {
+                float f = ok ? w32[e] : 0.0f;
+                if (p1) f = f + (ok ? ((const float*)p1)[e] : 0.0f);
+                if (p2) f = f + (ok ? ((const float*)p2)[e] : 0.0f);
+                x[u] = (double)f;
+            } else {
+                double d = ok ? w64in[e] : 0.0;
+                if (p1) d = d + (ok ? ((const double*)p1)[e] : 0.0);
+                if (p2) d = d + (ok ? ((const double*)p2)[e] : 0.0);
+                x[u] = d;
+            }
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) q[u][j] = (ok && j < nq) ? Q[j * ldq + e] : 0.0;
         }
-        double q[NQ];
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) q[j] = j < nq ? Q[j * ldq + e] : 0.0;
+        for (int u = 0; u < U; ++u) {
+            if (UPCAST || p1 || p2) {
+                const int64_t e = e0 + u * st;
+                if (e < sg.hi) w64out[e] = x[u];
+            }
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) acc[j] += q[j] * x;
+            for (int j = 0; j < NQ; ++j) acc[j] += q[u][j] * x[u];
+        }
     }
     write_partials<NQ>(acc, nq, partial, NB, blockIdx.x);
 }
@@ -317,21 +339,31 @@ k_lz_update_dots(const LzSeg* __restrict__ bt, const int* __restrict__ active, c
     __syncthreads();
     reduce_rows(partial_in, nq, NB, sg.pb0, sg.pb1, cs);
     if ((int)blockIdx.x == sg.pb0 && threadIdx.x == 0) scal[(int64_t)sg.prob * S_LEN + S_ALPHA + i] = cs[nq - 1];
+    constexpr int U = StepUnroll<NQ>::U;
     double acc[NQ + 1];
 #pragma unroll
     for (int j = 0; j <= NQ; ++j) acc[j] = 0.0;
-    for (int64_t e = sg.lo + threadIdx.x; e < sg.hi; e += blockDim.x) {
-        double q[NQ];
-        double x = w[e];
+    const int64_t st = blockDim.x;
+    for (int64_t e0 = sg.lo + threadIdx.x; e0 < sg.hi; e0 += U * st) {
+        double x[U], q[U][NQ];
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) {
-            q[j] = j < nq ? Q[j * ldq + e] : 0.0;
-            x -= cs[j] * q[j];
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = e0 + u * st;
+            const bool ok = e < sg.hi;
+            x[u] = ok ? w[e] : 0.0;
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) q[u][j] = (ok && j < nq) ? Q[j * ldq + e] : 0.0;
         }
-        w[e] = x;
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) acc[j] += q[j] * x;
-        acc[NQ] += x * x;
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) x[u] -= cs[j] * q[u][j];
+            const int64_t e = e0 + u * st;
+            if (e < sg.hi) w[e] = x[u];
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) acc[j] += q[u][j] * x[u];
+            acc[NQ] += x[u] * x[u];
+        }
     }
     // rows 0..nq-1: projections; row nq: |w|^2
     __shared__ double sh[LZ_THREADS / 64][NQ + 1];
@@ -412,10 +444,10 @@ static hipError_t lz_step_nq(const LzStepArgs& a, hipStream_t s) {
     const int NB = a.NB;
     if (a.upcast)
         hipLaunchKernelGGL((k_lz_dots<NQ, true>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.active, a.Q, a.ldq, a.nq,
-                           (const double*)nullptr, a.w32, a.w, a.partial, NB);
+                           (const double*)nullptr, a.w32, a.wp1, a.wp2, a.w, a.partial, NB);
     else
         hipLaunchKernelGGL((k_lz_dots<NQ, false>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.active, a.Q, a.ldq,
-                           a.nq, a.w, (const float*)nullptr, (double*)nullptr, a.partial, NB);
+                           a.nq, a.w, (const float*)nullptr, a.wp1, a.wp2, a.w, a.partial, NB);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_lz_update_dots<NQ>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.active, a.Q, a.ldq, a.nq,
@@ -428,6 +460,7 @@ static hipError_t lz_step_nq(const LzStepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_lz_step(const LzStepArgs& a, hipStream_t s) {
+    if (a.nq <= 4) return lz_step_nq<4>(a, s);
     if (a.nq <= 8) return lz_step_nq<8>(a, s);
     if (a.nq <= 16) return lz_step_nq<16>(a, s);
     if (a.nq <= 32) return lz_step_nq<32>(a, s);
@@ -606,7 +639,7 @@ __global__ void __launch_bounds__(64)
 k_lz_tridiag(const int* __restrict__ active, int k, double* __restrict__ scal) {
     if (!active[blockIdx.x]) return;
     double* sc = scal + (int64_t)blockIdx.x * S_LEN;
-    tridiag_body(sc + S_ALPHA, sc + S_BETA, k, sc + S_THETA + 1, sc + S_Y, sc + S_TWORK);
+    tridiag_body(sc + S_ALPHA, sc + S_BETA, k, sc + S_THETA + 1, sc + S_Y);
 }
 
 hipError_t launch_lz_tridiag(const LzSet& z, int k, hipStream_t s) {

@@ -139,15 +139,19 @@ d2d_status residual_step(LanczosWork* w, HvOps& hv, hipStream_t s) {
 }
 
 // One inner Lanczos of k vectors from X (after residual_step); X <- Ritz vector.
-d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, hipStream_t s) {
+d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool fused, hipStream_t s) {
     const LzSet z = set_of(w);
     const int64_t N = w->ntot;
     void* lo = prec == D2D_FP64 ? nullptr : (void*)w->vlo;
     D2D_HIP(launch_lz_first(z, w->X, w->W, w->Q, lo, prec, s));
     for (int i = 1; i < k; ++i) {
         double* qi = w->Q + (int64_t)i * N;
-        if (prec == D2D_FP64) D2D_CHECK(hv.hv(D2D_FP64, qi, w->W, s));
-        else D2D_CHECK(hv.hv(prec, w->vlo, w->wlo, s));
+        // fused GEMM + central launch; the step's first kernel adds the parts
+        HvParts parts{};
+        const void* hin = prec == D2D_FP64 ? (const void*)qi : (const void*)w->vlo;
+        void* hout = prec == D2D_FP64 ? (void*)w->W : (void*)w->wlo;
+        if (fused) D2D_CHECK(hv.hv_fused(prec, hin, hout, s, &parts));
+        else D2D_CHECK(hv.hv(prec, hin, hout, s));
         LzStepArgs a{};
         a.bt = z.bt;
         a.active = z.active;
@@ -160,6 +164,8 @@ d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, hi
         a.upcast = prec != D2D_FP64;
         a.w32 = w->wlo;
         a.w = w->W;
+        a.wp1 = parts.w1;
+        a.wp2 = parts.w2;
         a.partial = z.partial;
         a.partial2 = z.partial2;
         a.NB = z.NB;
@@ -183,9 +189,10 @@ void drop_graphs(LanczosWork* w) {
     }
 }
 
-d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool use_graph, hipStream_t s) {
+d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool fused, bool use_graph,
+                   hipStream_t s) {
     if (!use_graph || s == nullptr) {
-        D2D_CHECK(inner_loop(w, hv, prec, k, window, s));
+        D2D_CHECK(inner_loop(w, hv, prec, k, window, fused, s));
         D2D_CHECK(residual_step(w, hv, s));
         hv.count(prec, k - 1);
         hv.count(D2D_FP64, 1);
@@ -199,7 +206,7 @@ d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool 
         D2D_CHECK(hv.prepare(prec));          // launch tables exist before capture
         D2D_CHECK(hv.prepare(D2D_FP64));
         D2D_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        d2d_status st = inner_loop(w, hv, prec, k, window, s);
+        d2d_status st = inner_loop(w, hv, prec, k, window, fused, s);
         if (st == D2D_OK) st = residual_step(w, hv, s);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s, &g);
@@ -227,8 +234,10 @@ namespace d2d {
 
 d2d_status check_lanczos_opts(const d2d_lanczos_opts* o) {
     if (!o || o->k_in < 2 || o->k_in > 33 || o->max_restarts < 0 || !(o->tol_res > 0.0) || o->prec < 0 ||
-        o->prec > 2 || o->reorth_window < 0 || o->reorth_window == 1) {
-        set_error("Lanczos options: k_in 2..33, max_restarts >= 0, tol_res > 0, prec 0..2, reorth_window 0 or >= 2");
+        o->prec > 2 || o->reorth_window < 0 || o->reorth_window == 1 || o->separate_central < 0 ||
+        o->separate_central > 1) {
+        set_error("Lanczos options: k_in 2..33, max_restarts >= 0, tol_res > 0, prec 0..2, reorth_window 0 or >= 2, "
+                  "separate_central 0 or 1");
         return D2D_EINVAL;
     }
     return D2D_OK;
@@ -332,7 +341,7 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
             D2D_CHECK(hv.set_active(a, &rebuilt));
             if (rebuilt) drop_graphs(w);
         }
-        D2D_CHECK(restart(w, hv, prec, k, opts->reorth_window, opts->use_graph != 0, s));
+        D2D_CHECK(restart(w, hv, prec, k, opts->reorth_window, opts->separate_central == 0, opts->use_graph != 0, s));
         D2D_HIP(hipStreamSynchronize(s));
         ++j;
         for (int p = 0; p < np; ++p) {
@@ -368,11 +377,19 @@ struct SbHv : HvOps {
     d2d_status hv(int prec, const void* v, void* w, hipStream_t s) override {
         return sb_hv_nocount(sb, prec, v, w, s);
     }
+    d2d_status hv_fused(int prec, const void* v, void* w, hipStream_t s, HvParts* parts) override {
+        if (!sb->fuse[prec]) {
+            parts->w1 = parts->w2 = nullptr;
+            return sb_hv_nocount(sb, prec, v, w, s);
+        }
+        return sb_hv_parts(sb, prec, v, w, s, nullptr, parts);
+    }
     d2d_status prepare(int prec) override {
         WorkItem* d;
         int n;
         const int shape = sb->tile_sel[prec] >= 0 ? sb->tile_sel[prec] : sb_auto_tile(sb, prec);
         if (sb->split[prec] && !sb->d_w1) D2D_CHECK(sb->ctx->alloc(&sb->d_w1, (size_t)sb->N * 8));
+        if (!sb->d_w2) D2D_CHECK(sb->ctx->alloc(&sb->d_w2, (size_t)sb->N * 8));
         return sb_work(sb, shape, sb->split[prec], &d, &n);
     }
     d2d_status set_active(const std::vector<int>&, bool* rebuilt) override {

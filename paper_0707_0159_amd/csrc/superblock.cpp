@@ -107,6 +107,8 @@ d2d_sb::~d2d_sb() {
     }
     if (d_w1) ctx->free(d_w1, (size_t)N * 8);
     d_w1 = nullptr;
+    if (d_w2) ctx->free(d_w2, (size_t)N * 8);
+    d_w2 = nullptr;
     release(ctx, d_vp, (size_t)vp_len);
     release(ctx, d_vt, (size_t)vt_len);
     release(ctx, d_ptiles, (size_t)n_ptiles);
@@ -118,6 +120,8 @@ d2d_sb::~d2d_sb() {
     release(ctx, d_rcoef32, (size_t)K * Drows);
     release(ctx, d_ccoef32, (size_t)K * Dcols);
     release(ctx, d_cblocks, (size_t)n_cblocks);
+    release(ctx, d_srcoff, np * K);
+    release(ctx, d_srcdl, np * K);
     for (auto& kv : work) {
         WorkItem* w = kv.second.first;
         release(ctx, w, (size_t)kv.second.second);
@@ -133,6 +137,41 @@ int sb_auto_tile(const d2d_sb* sb, int prec) {
     if (prec == D2D_FP32) return D <= 64 ? 3 : (D <= 768 ? 4 : 5);
     if (prec == D2D_BF16) return D <= 64 ? 17 : (D <= 512 ? 14 : 15);
     return -1;
+}
+
+void central_tiles(const std::vector<SectorDev>& pairs, const std::vector<int>* keep,
+                   std::vector<CentralTile>& out) {
+    out.clear();
+    for (size_t p = 0; p < pairs.size(); ++p) {
+        if (keep && !(*keep)[p]) continue;
+        const SectorDev& s = pairs[p];
+        for (int c0 = 0; c0 < s.dR; c0 += 8)
+            for (int r0 = 0; r0 < s.dL; r0 += 64) {
+                CentralTile t{};
+                t.off = s.off;
+                t.p = (int)p;
+                t.r0 = r0;
+                t.c0 = c0;
+                t.dL = s.dL;
+                t.dR = s.dR;
+                t.row_base = s.row_base;
+                t.col_base = s.col_base;
+                out.push_back(t);
+            }
+    }
+}
+
+void central_sources(const std::vector<SectorDev>& pairs, const std::vector<int32_t>& src, int K,
+                     std::vector<int64_t>& off, std::vector<int32_t>& dl) {
+    off.assign(pairs.size() * K, -1);
+    dl.assign(pairs.size() * K, 0);
+    for (size_t p = 0; p < pairs.size(); ++p)
+        for (int k = 0; k < K; ++k) {
+            const int32_t q = src[p * K + k];
+            if (q < 0) continue;
+            off[p * K + k] = pairs[q].off;
+            dl[p * K + k] = pairs[q].dL;
+        }
 }
 
 void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep, const TileShape& ts, int split,
@@ -180,21 +219,31 @@ d2d_status sb_work(d2d_sb* sb, int shape, int split, WorkItem** out, int* nwork)
 
 d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkItem* work, int nwork, const void* v,
                      void* w, hipStream_t s, hipEvent_t mid) {
-    // a split work list writes the second K-loop into w1; the central term adds it
-    bool split = false;
-    {
-        // the caller passes split work lists only together with a scratch w1
-        split = t.w1 != nullptr;
+    // a split work list (passed together with a scratch w1) writes the second
+    // K-loop into w1; the central term adds it, or, fused, leaves it to the consumer
+    const bool split = t.w1 != nullptr;
+    HvGemmArgs g{work, nwork, t.sec, t.HL[prec], t.HR[prec], v, w, split ? t.w1 : nullptr, nullptr};
+    CentralArgs c{};
+    c.tiles = t.ctiles;
+    c.ntiles = t.n_ctiles;
+    c.K = t.K;
+    c.srcoff = t.srcoff;
+    c.srcdl = t.srcdl;
+    c.rmap = t.rmap;
+    c.cmap = t.cmap;
+    c.rcoef = prec == D2D_FP64 ? (const void*)t.rcoef64 : (const void*)t.rcoef32;
+    c.ccoef = prec == D2D_FP64 ? (const void*)t.ccoef64 : (const void*)t.ccoef32;
+    c.Drows = t.Drows;
+    c.Dcols = t.Dcols;
+    c.V = v;   // the unpadded input in every precision
+    if (t.w2) {
+        c.W = t.w2;
+        c.W1 = nullptr;
+        g.fuse = &c;
+    } else {
+        c.W = w;
+        c.W1 = split ? t.w1 : nullptr;
     }
-    HvGemmArgs g{work, nwork, t.sec, t.HL[prec], t.HR[prec], v, w, split ? t.w1 : nullptr};
-    g.K = t.K;
-    g.src = t.src;
-    g.rmap = t.rmap;
-    g.cmap = t.cmap;
-    g.rcoef = prec == D2D_FP64 ? (const void*)t.rcoef64 : (const void*)t.rcoef32;
-    g.ccoef = prec == D2D_FP64 ? (const void*)t.ccoef64 : (const void*)t.ccoef32;
-    g.Drows = t.Drows;
-    g.Dcols = t.Dcols;
     if (prec == D2D_BF16) {
         D2D_HIP(launch_pack_bf16(t.ptiles, t.n_ptiles, t.sec, (const bf16_t*)v, t.vp, t.vt, s));
         g.V = t.vp;
@@ -203,23 +252,7 @@ d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkItem* wor
         D2D_HIP(launch_hv_gemm(shape, g, s));
     }
     if (mid) D2D_HIP(hipEventRecord(mid, s));
-    CentralArgs c{};
-    c.blocks = t.ctiles;
-    c.nblocks = t.n_ctiles;
-    c.sec = t.sec;
-    c.npairs = t.npairs;
-    c.K = t.K;
-    c.src = t.src;
-    c.rmap = t.rmap;
-    c.cmap = t.cmap;
-    c.rcoef = g.rcoef;
-    c.ccoef = g.ccoef;
-    c.Drows = t.Drows;
-    c.Dcols = t.Dcols;
-    c.V = v;   // the unpadded input in every precision
-    c.W = w;
-    c.W1 = split ? t.w1 : nullptr;
-    D2D_HIP(launch_central(prec, c, s));
+    if (!t.w2) D2D_HIP(launch_central(prec, c, s));
     return D2D_OK;
 }
 
@@ -243,6 +276,8 @@ static HvTables tables_of(d2d_sb* sb) {
     t.Dcols = sb->Dcols;
     t.ctiles = sb->d_cblocks;
     t.n_ctiles = sb->n_cblocks;
+    t.srcoff = sb->d_srcoff;
+    t.srcdl = sb->d_srcdl;
     t.ptiles = sb->d_ptiles;
     t.n_ptiles = sb->n_ptiles;
     t.vp = sb->d_vp;
@@ -250,7 +285,8 @@ static HvTables tables_of(d2d_sb* sb) {
     return t;
 }
 
-d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s, hipEvent_t mid) {
+d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s, hipEvent_t mid,
+                       HvParts* parts) {
     if (prec < 0 || prec > 2 || !(sb->prec_mask & (1u << prec)) || !sb->HL[prec]) {
         set_error("precision %d not available on this superblock", prec);
         return D2D_EINVAL;
@@ -264,6 +300,12 @@ d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t
     if (split) {
         if (!sb->d_w1) D2D_CHECK(sb->ctx->alloc(&sb->d_w1, (size_t)sb->N * 8));
         t.w1 = sb->d_w1;
+    }
+    if (parts) {
+        if (!sb->d_w2) D2D_CHECK(sb->ctx->alloc(&sb->d_w2, (size_t)sb->N * 8));
+        t.w2 = sb->d_w2;
+        parts->w1 = t.w1;
+        parts->w2 = t.w2;
     }
     return hv_launch(t, prec, shape, work, nwork, v, w, s, mid);
 }
@@ -566,14 +608,15 @@ extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d
         return D2D_EINVAL;
     }
     {
-        std::vector<int4> cb;
-        for (int p = 0; p < np; ++p) {
-            const int tr = (sb->pairs[p].dL + 63) / 64, tc = (sb->pairs[p].dR + 7) / 8;
-            for (int j = 0; j < tc; ++j)
-                for (int i = 0; i < tr; ++i) cb.push_back(make_int4(p, i, j, 0));
-        }
+        std::vector<CentralTile> cb;
+        central_tiles(sb->pairs, nullptr, cb);
         sb->n_cblocks = (int)cb.size();
         D2D_CHECK(upload(ctx, cb, &sb->d_cblocks));
+        std::vector<int64_t> so;
+        std::vector<int32_t> sd;
+        central_sources(sb->pairs, src, K, so, sd);
+        D2D_CHECK(upload(ctx, so, &sb->d_srcoff));
+        D2D_CHECK(upload(ctx, sd, &sb->d_srcdl));
     }
     D2D_HIP(hipStreamSynchronize(ctx->stream));
     *out = sb.release();
@@ -656,13 +699,16 @@ extern "C" d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile) {
         return D2D_EINVAL;
     }
     const int split = tile >= 0 && (tile & D2D_TILE_SPLIT) ? 1 : 0;
-    const int shape = tile < 0 ? -1 : (tile & ~D2D_TILE_SPLIT);
-    if (shape >= tile_shape_count() || (shape >= 0 && tile_shape(shape).prec != prec)) {
+    const int fused = tile >= 0 ? ((tile & D2D_TILE_FUSED) ? 1 : 0) : (prec != D2D_FP64 ? 1 : 0);
+    const int shape = tile < 0 ? -1 : (tile & 0xFFFF);
+    if (shape >= tile_shape_count() || (shape >= 0 && tile_shape(shape).prec != prec) ||
+        (tile >= 0 && (tile & ~(0xFFFF | D2D_TILE_SPLIT | D2D_TILE_FUSED)))) {
         set_error("d2d_sb_set_tile: tile %d is not a shape of precision %d", tile, prec);
         return D2D_EINVAL;
     }
     sb->tile_sel[prec] = shape;
     sb->split[prec] = split;
+    sb->fuse[prec] = fused;
     return D2D_OK;
 }
 
@@ -758,10 +804,11 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
             int t;
             double ms;
             while (fscanf(f, "%llx %d %lf", &k, &t, &ms) == 3) {
-                const int sh = t & ~D2D_TILE_SPLIT;
-                if (k == key && sh >= 0 && sh < tile_shape_count() && tile_shape(sh).prec == prec) {
+                const int sh = t & 0xFFFF;
+                if (k == key && t >= 0 && sh < tile_shape_count() && tile_shape(sh).prec == prec) {
                     sb->tile_sel[prec] = sh;
                     sb->split[prec] = (t & D2D_TILE_SPLIT) ? 1 : 0;
+                    sb->fuse[prec] = (t & D2D_TILE_FUSED) ? 1 : 0;
                     *best_tile = t;
                     *best_ms = ms;
                     fclose(f);
@@ -785,28 +832,31 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int best = -1;
     double bms = 1e300;
-    const int saved = sb->tile_sel[prec], saved_split = sb->split[prec];
+    const int saved = sb->tile_sel[prec], saved_split = sb->split[prec], saved_fuse = sb->fuse[prec];
     if (launch_fill(v, prec, sb->N, 0.5, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
         hipEventCreate(&e1) != hipSuccess) {
         set_error("d2d_sb_autotune: HIP setup failed");
         st = D2D_EDEVICE;
     }
-    for (int tt = 0; tt < 2 * tile_shape_count() && st == D2D_OK; ++tt) {
-        const int t = tt % tile_shape_count(), sp = tt / tile_shape_count();
+    const int nsh = tile_shape_count();
+    for (int tt = 0; tt < 4 * nsh && st == D2D_OK; ++tt) {
+        const int t = tt % nsh, sp = (tt / nsh) & 1, fu = tt / (2 * nsh);
         if (tile_shape(t).prec != prec) continue;
         sb->tile_sel[prec] = t;
         sb->split[prec] = sp;
-        st = sb_hv(sb, prec, v, w, s);   // warm-up (also builds the work list)
+        HvParts parts{};
+        HvParts* pp = fu ? &parts : nullptr;
+        st = sb_hv_parts(sb, prec, v, w, s, nullptr, pp);   // warm-up (also builds the work list)
         if (st != D2D_OK) break;
         if (hipEventRecord(e0, s) != hipSuccess) st = D2D_EDEVICE;
-        for (int r = 0; r < reps && st == D2D_OK; ++r) st = sb_hv(sb, prec, v, w, s);
+        for (int r = 0; r < reps && st == D2D_OK; ++r) st = sb_hv_parts(sb, prec, v, w, s, nullptr, pp);
         float ms = 0.f;
         if (st == D2D_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
             st = D2D_EDEVICE;
         if (st == D2D_OK && ms / reps < bms) {
             bms = ms / reps;
-            best = t | (sp ? D2D_TILE_SPLIT : 0);
+            best = t | (sp ? D2D_TILE_SPLIT : 0) | (fu ? D2D_TILE_FUSED : 0);
         }
     }
     if (e0) (void)hipEventDestroy(e0);
@@ -816,14 +866,16 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
     if (st != D2D_OK || best < 0) {
         sb->tile_sel[prec] = saved;
         sb->split[prec] = saved_split;
+        sb->fuse[prec] = saved_fuse;
         if (st == D2D_OK) {
             set_error("d2d_sb_autotune: no tile shape for precision %d", prec);
             st = D2D_EINVAL;
         }
         return st;
     }
-    sb->tile_sel[prec] = best & ~D2D_TILE_SPLIT;
+    sb->tile_sel[prec] = best & 0xFFFF;
     sb->split[prec] = (best & D2D_TILE_SPLIT) ? 1 : 0;
+    sb->fuse[prec] = (best & D2D_TILE_FUSED) ? 1 : 0;
     *best_tile = best;
     *best_ms = bms;
     if (cache && *cache) {

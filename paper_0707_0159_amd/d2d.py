@@ -21,6 +21,7 @@ D2D_FP64, D2D_FP32, D2D_BF16 = 0, 1, 2
 D2D_HEISENBERG, D2D_HUBBARD = 0, 1
 D2D_LOG_MAX = 256
 D2D_TILE_SPLIT = 1 << 16
+D2D_TILE_FUSED = 1 << 17
 
 _STATUS = {0: "D2D_OK", -1: "D2D_EINVAL", -2: "D2D_ENOMEM", -3: "D2D_EDEVICE", -4: "D2D_ENOCONV",
            -5: "D2D_ESTATE"}
@@ -50,7 +51,8 @@ class d2d_sb_info_t(C.Structure):
 
 class d2d_lanczos_opts(C.Structure):
     _fields_ = [("prec", C.c_int), ("k_in", C.c_int), ("max_restarts", C.c_int), ("tol_res", C.c_double),
-                ("escalate", C.c_double), ("use_graph", C.c_int), ("reorth_window", C.c_int)]
+                ("escalate", C.c_double), ("use_graph", C.c_int), ("reorth_window", C.c_int),
+                ("separate_central", C.c_int)]
 
 
 class d2d_lanczos_stats(C.Structure):
@@ -300,9 +302,9 @@ def d2d_tile_shapes():
 
 
 def lanczos_opts(prec=D2D_FP64, k_in=24, max_restarts=200, tol_res=1e-9, escalate=0.5, use_graph=1,
-                 reorth_window=0):
+                 reorth_window=0, separate_central=0):
     return d2d_lanczos_opts(int(prec), int(k_in), int(max_restarts), float(tol_res), float(escalate),
-                            int(use_graph), int(reorth_window))
+                            int(use_graph), int(reorth_window), int(separate_central))
 
 
 def d2d_lanczos(sb: int, opts: d2d_lanczos_opts, v0, psi=None):

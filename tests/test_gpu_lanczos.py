@@ -20,14 +20,15 @@ def ctx():
     d2d.d2d_ctx_destroy(c)
 
 
-def run(ctx, prob, prec, seed, k_in=24, graph=1, tol=1e-9):
+def run(ctx, prob, prec, seed, k_in=24, graph=1, tol=1e-9, window=0, separate=0):
     from paper_0707_0159_amd import d2d
     n = prob.info["n"]
     with torch.cuda.stream(ctx.stream):
         v0 = torch.as_tensor(W.random_vector(n, seed)).to("cuda")
         psi = torch.zeros_like(v0)
     ctx.stream.synchronize()
-    opts = d2d.lanczos_opts(prec=prec, k_in=k_in, max_restarts=300, tol_res=tol, use_graph=graph)
+    opts = d2d.lanczos_opts(prec=prec, k_in=k_in, max_restarts=300, tol_res=tol, use_graph=graph,
+                            reorth_window=window, separate_central=separate)
     st, e, stats = d2d.d2d_lanczos(prob.sb, opts, v0, psi)
     ctx.stream.synchronize()
     return st, e, stats, psi.cpu().numpy()
@@ -60,6 +61,23 @@ def test_config2_energy(ctx, prec):
     assert st == 0
     assert abs(e - E0) <= 1e-10 * abs(E0)
     assert e >= E0 - 1e-10 * abs(E0)          # Rayleigh quotient is variational
+    prob.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_fused_central_is_bitwise_separate(ctx, prec):
+    """One launch for GEMM + central term (parts added by the first step kernel)
+    gives the same iterates bit for bit as the central term launched after the
+    GEMM: same energies, restart logs and Ritz vector."""
+    wl = W.CONFIGS[2]
+    prob = GpuProblem(ctx, wl, prec_mask=7)
+    out = [run(ctx, prob, prec, wl.seed, window=3, tol=1e-8, separate=sep) for sep in (0, 1)]
+    (s0, e0, st0, p0), (s1, e1, st1, p1) = out
+    assert s0 == 0 and s1 == 0
+    assert e0 == e1
+    assert st0["restarts"] == st1["restarts"]
+    assert np.array_equal(np.asarray(st0["log_theta"]), np.asarray(st1["log_theta"]))
+    assert np.array_equal(p0, p1)
     prob.close()
 
 
