@@ -17,6 +17,10 @@ with HIP events on the stream it runs on) and of the BF16 GEMM; and the CPU
 oracle's Hv rate on the host cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2]
+
+--config 5 runs the batch of 64 uneven superblocks instead (one grouped
+launch per Lanczos step over every problem; value = problem Hv applications
+per second, summed over the batch).
 """
 from __future__ import annotations
 
@@ -80,6 +84,151 @@ def cpu_baseline(wl, seconds: float):
                       f"N={sb.N}, {dt:.1f} s, BLAS threads {threads}, host cpus {len(os.sched_getaffinity(0))}"}
 
 
+def cpu_baseline_batch(wls, seconds: float):
+    """The oracle's Hv over the problems of a batch, in turn, on the host."""
+    from threadpoolctl import threadpool_info
+
+    import workloads as W
+    from oracle.blockio import block_from_arrays
+    from oracle.superblock import Superblock
+
+    n = 0
+    t0 = time.perf_counter()
+    dt = 0.0
+    names = []
+    while dt < seconds and n < len(wls):
+        wl = wls[n]
+        raw = W.load_blocks(wl.name)
+        sb = Superblock(block_from_arrays(raw["L"]), block_from_arrays(raw["R"]), wl.target)
+        v = W.random_vector(sb.N, 1000)
+        t1 = time.perf_counter()
+        sb.hv_factored(v)
+        dt += time.perf_counter() - t1     # the product only, not the set-up of each problem
+        names.append(wl.name)
+        n += 1
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return {"value": n / dt, "unit": "problem-Hv/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one oracle Hv (mode F, float64) on each of the first {n} problems of the batch, "
+                      f"{dt:.1f} s of products, BLAS threads {threads}, host cpus {len(os.sched_getaffinity(0))}"}
+
+
+def bench_batch(args):
+    """64 uneven superblocks in one batch: one grouped launch per Lanczos step."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_0707_0159_amd import d2d
+
+    wls = W.config5()
+    ref_path = os.path.join(ROOT, "tests", "golden", "reference_energies.json")
+    refs = {}
+    if os.path.exists(ref_path):
+        with open(ref_path) as f:
+            g = json.load(f)
+        refs = {wl.name: g[wl.name]["E0"] for wl in wls if wl.name in g}
+    ctx = d2d.d2d_ctx_create(0)
+    s = ctx.stream
+    blocks, sbs = [], []
+    for wl in wls:
+        raw = W.load_blocks(wl.name)
+        model = d2d.make_model(wl.kind, wl.legs, wl.t, wl.U, wl.J)
+        b1 = d2d.d2d_block_import(ctx, model, raw["L"])
+        b4 = d2d.d2d_block_import(ctx, model, raw["R"])
+        blocks += [b1, b4]
+        sbs.append(d2d.d2d_sb_create(ctx, b1, b4, model, wl.target, 7))
+    infos = [d2d.d2d_sb_info(sb) for sb in sbs]
+    b = d2d.d2d_batch_create(ctx, sbs)
+    with torch.cuda.stream(s):
+        v0 = [torch.as_tensor(W.random_vector(i["n"], wl.seed), device="cuda") for i, wl in zip(infos, wls)]
+    s.synchronize()
+
+    def solve(prec):
+        opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol, use_graph=1,
+                                reorth_window=args.window)
+        st, e, per = d2d.d2d_batch_lanczos(b, opts, v0)
+        if st != 0:
+            raise RuntimeError("batched Lanczos did not converge")
+        return e, per
+
+    def timed(prec, steps, warmup):
+        for _ in range(warmup):
+            solve(prec)
+        torch.cuda.synchronize()
+        hv = 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            e, per = solve(prec)
+            hv += sum(sum(p["hv_count"]) for p in per)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        dE = [abs(x - refs[wl.name]) / abs(refs[wl.name]) for x, wl in zip(e, wls) if wl.name in refs]
+        firsts = []
+        for p, wl in zip(per, wls):
+            E0 = refs.get(wl.name)
+            if E0 is None:
+                continue
+            ft = next((t for t, th in zip(p["log_t"], p["log_theta"]) if abs(th - E0) <= 1e-10 * abs(E0)), None)
+            firsts.append(ft)
+        return {"hv_per_s": hv / wall, "s_per_solve": wall / steps,
+                "max_dE_rel": max(dE) if dE else None, "problems_with_reference": len(dE),
+                "all_within_1e-10_s": (max(firsts) if firsts and None not in firsts else None),
+                "restarts_max": max(p["restarts"] for p in per),
+                "hv_per_problem_mean": hv / steps / len(per)}
+
+    head = timed(d2d.D2D_FP32, args.steps, args.warmup)
+    reps = max(1, min(args.steps, 3))
+    bf16 = timed(d2d.D2D_BF16, reps, 1)
+    fp64 = timed(d2d.D2D_FP64, reps, 1)
+
+    # one batched Hv (pack + grouped GEMM + central term) per precision, HIP events on the context stream
+    hv_ms = {}
+    F = sum(i["flops_exec"] for i in infos)
+    for prec, name, dt in ((d2d.D2D_FP64, "fp64", torch.float64), (d2d.D2D_FP32, "fp32", torch.float32),
+                           (d2d.D2D_BF16, "bf16", torch.bfloat16)):
+        with torch.cuda.stream(s):
+            xs = [v.to(dt) for v in v0]
+            ws = [torch.empty(v.numel(), dtype=torch.float64 if prec == 0 else torch.float32, device="cuda")
+                  for v in v0]
+        s.synchronize()
+        d2d.d2d_batch_hv(b, prec, xs, ws)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(s)
+        for _ in range(20):
+            d2d.d2d_batch_hv(b, prec, xs, ws)
+        ev1.record(s)
+        s.synchronize()
+        hv_ms[name] = ev0.elapsed_time(ev1) / 20
+    line = {
+        "metric": "Hv/sec + Lanczos time to |dE|<=1e-10: mixed-precision vs FP64, 1 GPU",
+        "value": head["hv_per_s"], "unit": "Hv/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["s_per_solve"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": f"batch of {len(wls)} uneven superblocks (2/3-leg Heisenberg and Hubbard, "
+                               f"{len(wls)} problems, 6 columns, m 64..512)",
+                   "N_sb_total": sum(i["n"] for i in infos), "N_sb_max": max(i["n"] for i in infos),
+                   "k_in": args.k_in, "reorth_window": args.window, "tol_res": args.tol,
+                   "parallelism": "none (1 GPU)"},
+        "time_to_energy": {"mixed_fp32": head, "mixed_bf16": bf16, "fp64": fp64,
+                           "speedup_fp32_vs_fp64": fp64["s_per_solve"] / head["s_per_solve"],
+                           "speedup_bf16_vs_fp64": fp64["s_per_solve"] / bf16["s_per_solve"]},
+        "batched_hv_ms": hv_ms,
+        "flops_exec_per_batched_hv": F,
+        "roofline": {"bound": "mfma", "achieved": F / (hv_ms["fp32"] * 1e-3) / 1e12, "peak": PEAK["fp32"] / 1e12,
+                     "unit": "TFLOP/s", "frac": F / (hv_ms["fp32"] * 1e-3) / PEAK["fp32"], "traffic": None,
+                     "kernel": "batched Hv launch sequence (fp32 grouped GEMM + central term), latency-bound"},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_batch(wls, args.cpu_seconds)
+    d2d.d2d_batch_destroy(b)
+    for sb in sbs:
+        d2d.d2d_sb_destroy(sb)
+    for bl in blocks:
+        d2d.d2d_block_destroy(bl)
+    d2d.d2d_ctx_destroy(ctx)
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +266,9 @@ def main():
         print(json.dumps({"profile": "copy", "bytes_read_per_launch": nbytes, "bytes_written_per_launch": nbytes}))
         return
 
+    if args.config == 5:
+        bench_batch(args)
+        return
     wl = W.CONFIGS[args.config]
     ref_path = os.path.join(ROOT, "tests", "golden", "reference_energies.json")
     E0 = None

@@ -180,6 +180,17 @@ d2d_status d2d_sb_info(const d2d_sb* sb, d2d_sb_info_t* info);
  * offset[npairs] (host buffers of npairs entries). */
 d2d_status d2d_sb_sectors(const d2d_sb* sb, int64_t* qL, int64_t* dL, int64_t* dR, int64_t* offset);
 
+/* Conversion between the packed sector layout (length n) and the full
+ * superblock space of Eq. (1) (length D^2, D = m*ncol), whose element
+ * (i1, i2, i3, i4) (block 1, column 2, column 3, block 4 states) sits at
+ * (i2*m + i1) + D*(i3*m + i4), i.e. the superblock vector in the paper's
+ * index order, or the column-major D x D matrix V.  Device FP64 buffers,
+ * asynchronous on the context stream.  d2d_pack keeps the target-sector
+ * elements of full; d2d_unpack writes every element of full (zero outside the
+ * target sector).  Buffers must not overlap. */
+d2d_status d2d_pack(d2d_sb* sb, const double* full, double* packed);
+d2d_status d2d_unpack(d2d_sb* sb, const double* packed, double* full);
+
 /* --------------------------------------------------------------------- Hv
  * w = H v in the packed layout, on the context stream, asynchronous.
  * prec D2D_FP64: v, w double.  D2D_FP32: v float, w float.  D2D_BF16: v
@@ -241,8 +252,14 @@ d2d_status d2d_tile_shapes(int* count, int* desc);
  * Precision schedule: start in opts.prec; if rho_{j+1} > escalate * rho_j the
  * precision is raised (BF16 -> FP32 -> FP64).  k_in is capped at the problem
  * dimension.
- * Convergence: rho_j <= tol_res * |theta_j|.
- * v0: device FP64 start vector of length n (required, need not be normalised).
+ * Convergence: rho_j <= tol_res * |theta_j|, or, when tol_rel_e > 0, two
+ * successive FP64 Rayleigh quotients with |theta_j - theta_{j-1}| <=
+ * tol_rel_e * |theta_j|.
+ * v0: device FP64 start vector of length n (need not be normalised), or NULL
+ * for a seeded N(0,1) vector: element i is the Box-Muller normal
+ * sqrt(-2 ln u1) cos(2 pi u2) of u1, u2 from outputs 2i and 2i+1 of the
+ * SplitMix64 stream (Steele, Lea and Flood 2014) seeded with opts.seed (a
+ * batch adds the problem index to the seed).
  * energy: host out, the last theta.  psi: device out (nullable), the unit
  * Ritz vector.  Returns D2D_ENOCONV (with energy/psi/stats filled) when
  * max_restarts is reached. */
@@ -256,10 +273,11 @@ typedef struct {
     int reorth_window;   /* 0: reorthogonalise against every basis vector (full);
                             w >= 2: only against the last w vectors (the FP64
                             restarts keep the fixed point exact either way)   */
-    int separate_central; /* 0: inner-step Hv is one launch (GEMM work items and
-                            central-term tiles together, the parts added by the
-                            first step kernel); 1: the central term as a launch
-                            of its own after the GEMM.  Same result bit for bit */
+    int separate_central; /* 0: inner-step Hv is one launch where the tile choice
+                            says so (D2D_TILE_FUSED); 1: the central term always
+                            as a launch of its own.  Same result bit for bit  */
+    double tol_rel_e;    /* energy-change stop (0: off)                         */
+    uint64_t seed;       /* seed of the start vector when v0 is NULL            */
 } d2d_lanczos_opts;
 
 #define D2D_LOG_MAX 256
@@ -301,7 +319,8 @@ d2d_status d2d_batch_create(d2d_ctx* ctx, d2d_sb* const* sbs, int n, d2d_batch**
 d2d_status d2d_batch_destroy(d2d_batch* b);
 /* One batched Hv: v[i], w[i] device pointers of problem i (precision prec). */
 d2d_status d2d_batch_hv(d2d_batch* b, int prec, const void* const* v, void* const* w);
-/* Batched restarted Lanczos; v0[i] device start vectors; energies host out
+/* Batched restarted Lanczos; v0[i] device start vectors (array or entries
+ * nullable: seeded as for d2d_lanczos with seed opts.seed + i); energies host out
  * [n]; psi[i] device out (nullable array or entries); per_problem (nullable)
  * stats [n].  Converged problems leave the launch at the next restart. */
 d2d_status d2d_batch_lanczos(d2d_batch* b, const d2d_lanczos_opts* opts, const double* const* v0,

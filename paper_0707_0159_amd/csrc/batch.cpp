@@ -417,7 +417,7 @@ extern "C" d2d_status d2d_batch_hv(d2d_batch* b, int prec, const void* const* v,
 
 extern "C" d2d_status d2d_batch_lanczos(d2d_batch* b, const d2d_lanczos_opts* opts, const double* const* v0,
                                         double* energies, double* const* psi, d2d_lanczos_stats* per_problem) {
-    if (!b || !opts || !v0 || !energies) {
+    if (!b || !opts || !energies) {
         set_error("d2d_batch_lanczos: NULL argument");
         return D2D_EINVAL;
     }
@@ -426,11 +426,6 @@ extern "C" d2d_status d2d_batch_lanczos(d2d_batch* b, const d2d_lanczos_opts* op
         set_error("d2d_batch_lanczos: precision %d not kept by every superblock", opts->prec);
         return D2D_EINVAL;
     }
-    for (size_t i = 0; i < b->sbs.size(); ++i)
-        if (!v0[i]) {
-            set_error("d2d_batch_lanczos: NULL start vector %zu", i);
-            return D2D_EINVAL;
-        }
     BatchHv ops(b);
     return run_lanczos(b->ctx, b->lz, ops, opts, b->len, v0, energies, psi, per_problem);
 }

@@ -186,6 +186,8 @@ struct d2d_sb {
     int64_t max_elems = 0;
     d2d::CentralTile* d_cblocks = nullptr;   // central-term launch table
     int64_t* d_srcoff = nullptr;             // central source blocks per (pair, term)
+    int32_t* d_rowsL = nullptr;              // [Drows] left half index of every packed row
+    int32_t* d_colsR = nullptr;              // [Dcols] right half index of every packed column
     int32_t* d_srcdl = nullptr;
     // BF16 operands and per-Hv padded copies of the input vector
     int64_t hl16_len = 0, hr16_len = 0, vp_len = 0, vt_len = 0;

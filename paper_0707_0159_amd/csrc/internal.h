@@ -93,6 +93,10 @@ struct CentralArgs {
 };
 hipError_t launch_central(int prec, const CentralArgs& a, hipStream_t s);
 
+// packed <-> full space (dir 0: dst packed from full src; dir 1: dst full from packed src)
+hipError_t launch_full_pack(const SectorDev* sec, int npairs, int64_t max_elems, const int32_t* rows,
+                            const int32_t* cols, int64_t D, int dir, const double* src, double* dst, hipStream_t s);
+
 // Grouped GEMM W = H_l V + V H_r^T over a work list (split work items write
 // their second K-loop to W1).  With fuse set, the same launch also evaluates
 // the central term into fuse->W (a separate output: the caller adds
@@ -199,6 +203,8 @@ struct LzStepArgs {
     int lo_prec;
 };
 int lz_step_blocks(int64_t n);
+// x[i] = N(0,1) sample i of the SplitMix64 stream seeded with seed (Box-Muller)
+hipError_t launch_seeded_normal(double* x, int64_t n, uint64_t seed, hipStream_t s);
 hipError_t launch_lz_step(const LzStepArgs& a, hipStream_t s);
 // theta = x.w, w -= theta x, rho = |w|; alpha_0 = theta, beta_1 = rho, res = (theta, rho)
 hipError_t launch_lz_residual(const LzSet& z, const double* x, double* w, hipStream_t s);

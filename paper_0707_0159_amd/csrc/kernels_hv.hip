@@ -619,6 +619,33 @@ hipError_t launch_op_bf16(const int64_t* src_off, const int64_t* dst_off, const 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ full space
+// Packed element (r, c) of pair p sits at full-space index rows[row_base + r]
+// + D * cols[col_base + c] (left half index i2*m + i1, right half index
+// i3*m + i4, D = m*n).  dir 0: packed <- full; dir 1: full <- packed.
+__global__ void __launch_bounds__(256)
+k_full_pack(const SectorDev* __restrict__ sec, const int32_t* __restrict__ rows, const int32_t* __restrict__ cols,
+            int64_t D, int dir, const double* __restrict__ src, double* __restrict__ dst) {
+    const SectorDev s = sec[blockIdx.y];
+    const int64_t n = (int64_t)s.dL * s.dR;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e % s.dL), c = (int)(e / s.dL);
+        const int64_t f = (int64_t)rows[s.row_base + r] + D * cols[s.col_base + c];
+        if (dir == 0) dst[s.off + e] = src[f];
+        else dst[f] = src[s.off + e];
+    }
+}
+
+hipError_t launch_full_pack(const SectorDev* sec, int npairs, int64_t max_elems, const int32_t* rows,
+                            const int32_t* cols, int64_t D, int dir, const double* src, double* dst, hipStream_t st) {
+    if (npairs == 0) return hipSuccess;
+    int64_t gx = (max_elems + 255) / 256;
+    if (gx > 1024) gx = 1024;
+    if (gx < 1) gx = 1;
+    hipLaunchKernelGGL(k_full_pack, dim3((unsigned)gx, npairs), dim3(256), 0, st, sec, rows, cols, D, dir, src, dst);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ tile table
 static const TileShape kShapes[] = {
     {D2D_FP64, 32, 32, 16},    // 0: 4 waves of 16x16

@@ -615,6 +615,32 @@ k_lz_first(const LzSeg* __restrict__ bt, const int* __restrict__ active, const d
     }
 }
 
+// Seeded start vector.  SplitMix64 (Steele, Lea and Flood, "Fast splittable
+// pseudorandom number generators", 2014) is counter-based: output c of the
+// stream seeded with s is mix(s + (c + 1) * 0x9E3779B97F4A7C15).  Element i
+// takes outputs 2i and 2i+1 as u1, u2 in (0, 1) (53-bit mantissas, offset by
+// half an ulp) and the Box-Muller normal sqrt(-2 ln u1) cos(2 pi u2).
+__device__ inline uint64_t splitmix64_out(uint64_t seed, uint64_t c) {
+    uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(LZ_THREADS) k_seeded_normal(double* __restrict__ x, int64_t n, uint64_t seed) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double u1 = ((double)(splitmix64_out(seed, 2 * (uint64_t)i) >> 11) + 0.5) * 0x1.0p-53;
+        const double u2 = ((double)(splitmix64_out(seed, 2 * (uint64_t)i + 1) >> 11) + 0.5) * 0x1.0p-53;
+        x[i] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    }
+}
+
+hipError_t launch_seeded_normal(double* x, int64_t n, uint64_t seed, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seeded_normal, dim3(ew_grid(n)), dim3(LZ_THREADS), 0, s, x, n, seed);
+    return hipGetLastError();
+}
+
 // copy of the active problems' segments
 __global__ void __launch_bounds__(LZ_THREADS)
 k_lz_copy(const LzSeg* __restrict__ bt, const int* __restrict__ active, const double* __restrict__ x,

@@ -235,9 +235,9 @@ namespace d2d {
 d2d_status check_lanczos_opts(const d2d_lanczos_opts* o) {
     if (!o || o->k_in < 2 || o->k_in > 33 || o->max_restarts < 0 || !(o->tol_res > 0.0) || o->prec < 0 ||
         o->prec > 2 || o->reorth_window < 0 || o->reorth_window == 1 || o->separate_central < 0 ||
-        o->separate_central > 1) {
+        o->separate_central > 1 || !(o->tol_rel_e >= 0.0)) {
         set_error("Lanczos options: k_in 2..33, max_restarts >= 0, tol_res > 0, prec 0..2, reorth_window 0 or >= 2, "
-                  "separate_central 0 or 1");
+                  "separate_central 0 or 1, tol_rel_e >= 0");
         return D2D_EINVAL;
     }
     return D2D_OK;
@@ -261,8 +261,12 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
     D2D_HIP(hipMemcpy(w->active, act.data(), np * sizeof(int), hipMemcpyHostToDevice));
     D2D_CHECK(hv.set_active(act, nullptr));
     const int64_t cnt0[3] = {hv.counter(0), hv.counter(1), hv.counter(2)};
-    for (int p = 0; p < np; ++p)
-        D2D_HIP(hipMemcpyAsync(w->X + w->seg_off[p], v0[p], (size_t)len[p] * 8, hipMemcpyDeviceToDevice, s));
+    for (int p = 0; p < np; ++p) {
+        if (v0 && v0[p])
+            D2D_HIP(hipMemcpyAsync(w->X + w->seg_off[p], v0[p], (size_t)len[p] * 8, hipMemcpyDeviceToDevice, s));
+        else
+            D2D_HIP(launch_seeded_normal(w->X + w->seg_off[p], len[p], opts->seed + (uint64_t)p, s));
+    }
     D2D_HIP(launch_lz_norms(z, w->X, s));
     D2D_HIP(hipMemcpyAsync(w->res_host, w->res, (size_t)2 * np * 8, hipMemcpyDeviceToHost, s));
     D2D_HIP(hipStreamSynchronize(s));
@@ -277,7 +281,8 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
     D2D_CHECK(residual_step(w, hv, s));
     hv.count(D2D_FP64, 1);
     D2D_HIP(hipStreamSynchronize(s));
-    std::vector<double> theta(np), rho(np), rho_prev(np, -1.0);
+    std::vector<double> theta(np), rho(np), rho_prev(np, -1.0), theta_prev(np, 0.0);
+    std::vector<int> have_prev(np, 0);
     std::vector<d2d_lanczos_stats> st(np);
     std::memset(st.data(), 0, sizeof(d2d_lanczos_stats) * np);
     std::vector<int> done(np, 0), restarts(np, 0);
@@ -306,7 +311,9 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
                 sp.log_prec[sp.nlog] = prec;
                 sp.nlog++;
             }
-            if (rho[p] <= opts->tol_res * std::fabs(theta[p]) || rho[p] == 0.0 || k < 2) {
+            const bool e_stop = opts->tol_rel_e > 0.0 && have_prev[p] &&
+                                std::fabs(theta[p] - theta_prev[p]) <= opts->tol_rel_e * std::fabs(theta[p]);
+            if (rho[p] <= opts->tol_res * std::fabs(theta[p]) || rho[p] == 0.0 || k < 2 || e_stop) {
                 done[p] = 1;
                 changed = true;
                 sp.seconds = tsec;
@@ -347,6 +354,8 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
         for (int p = 0; p < np; ++p) {
             if (done[p]) continue;
             rho_prev[p] = rho[p];
+            theta_prev[p] = theta[p];
+            have_prev[p] = 1;
             theta[p] = w->res_host[2 * p];
             rho[p] = w->res_host[2 * p + 1];
             restarts[p] = j;
@@ -405,7 +414,7 @@ struct SbHv : HvOps {
 
 extern "C" d2d_status d2d_lanczos(d2d_sb* sb, const d2d_lanczos_opts* opts, const double* v0, double* energy,
                                   double* psi, d2d_lanczos_stats* stats) {
-    if (!sb || !opts || !v0 || !energy) {
+    if (!sb || !opts || !energy) {
         set_error("d2d_lanczos: NULL argument");
         return D2D_EINVAL;
     }

@@ -121,6 +121,8 @@ d2d_sb::~d2d_sb() {
     release(ctx, d_ccoef32, (size_t)K * Dcols);
     release(ctx, d_cblocks, (size_t)n_cblocks);
     release(ctx, d_srcoff, np * K);
+    release(ctx, d_rowsL, (size_t)Drows);
+    release(ctx, d_colsR, (size_t)Dcols);
     release(ctx, d_srcdl, np * K);
     for (auto& kv : work) {
         WorkItem* w = kv.second.first;
@@ -618,6 +620,16 @@ extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d
         D2D_CHECK(upload(ctx, so, &sb->d_srcoff));
         D2D_CHECK(upload(ctx, sd, &sb->d_srcdl));
     }
+    {
+        // half indices of the packed rows and columns (full-space conversion)
+        std::vector<int32_t> hr, hc;
+        for (size_t p = 0; p < sb->pairs.size(); ++p) {
+            hr.insert(hr.end(), sb->rowsL[p].begin(), sb->rowsL[p].end());
+            hc.insert(hc.end(), sb->colsR[p].begin(), sb->colsR[p].end());
+        }
+        D2D_CHECK(upload(ctx, hr, &sb->d_rowsL));
+        D2D_CHECK(upload(ctx, hc, &sb->d_colsR));
+    }
     D2D_HIP(hipStreamSynchronize(ctx->stream));
     *out = sb.release();
     return D2D_OK;
@@ -670,6 +682,27 @@ extern "C" d2d_status d2d_sb_sectors(const d2d_sb* sb, int64_t* qL, int64_t* dL,
         offset[p] = sb->pairs[p].off;
     }
     return D2D_OK;
+}
+
+static d2d_status full_pack(d2d_sb* sb, int dir, const double* src, double* dst, const char* who) {
+    if (!sb || !src || !dst) {
+        set_error("%s: NULL argument", who);
+        return D2D_EINVAL;
+    }
+    const int64_t D = (int64_t)sb->m * sb->n;
+    hipStream_t s = sb->ctx->stream;
+    if (dir == 1) D2D_HIP(launch_fill(dst, D2D_FP64, D * D, 0.0, s));
+    D2D_HIP(launch_full_pack(sb->d_sec, (int)sb->pairs.size(), sb->max_elems, sb->d_rowsL, sb->d_colsR, D, dir, src,
+                             dst, s));
+    return D2D_OK;
+}
+
+extern "C" d2d_status d2d_pack(d2d_sb* sb, const double* full, double* packed) {
+    return full_pack(sb, 0, full, packed, "d2d_pack");
+}
+
+extern "C" d2d_status d2d_unpack(d2d_sb* sb, const double* packed, double* full) {
+    return full_pack(sb, 1, packed, full, "d2d_unpack");
 }
 
 extern "C" d2d_status d2d_hv(d2d_sb* sb, int prec, const void* v, void* w) {

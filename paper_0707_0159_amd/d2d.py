@@ -52,7 +52,7 @@ class d2d_sb_info_t(C.Structure):
 class d2d_lanczos_opts(C.Structure):
     _fields_ = [("prec", C.c_int), ("k_in", C.c_int), ("max_restarts", C.c_int), ("tol_res", C.c_double),
                 ("escalate", C.c_double), ("use_graph", C.c_int), ("reorth_window", C.c_int),
-                ("separate_central", C.c_int)]
+                ("separate_central", C.c_int), ("tol_rel_e", C.c_double), ("seed", C.c_uint64)]
 
 
 class d2d_lanczos_stats(C.Structure):
@@ -78,6 +78,8 @@ _SIGS = {
     "d2d_sb_destroy": (C.c_int, [P]),
     "d2d_sb_info": (C.c_int, [P, C.POINTER(d2d_sb_info_t)]),
     "d2d_sb_sectors": (C.c_int, [P, i64p, i64p, i64p, i64p]),
+    "d2d_pack": (C.c_int, [P, P, P]),
+    "d2d_unpack": (C.c_int, [P, P, P]),
     "d2d_hv": (C.c_int, [P, C.c_int, P, P]),
     "d2d_hv_count": (C.c_int, [P, i64p]),
     "d2d_hv_profile": (C.c_int, [P, C.c_int, P, P, C.c_int, f64p, f64p]),
@@ -262,6 +264,18 @@ def d2d_sb_sectors(sb: int):
     return qL.reshape(-1, 2), dL, dR, off
 
 
+def d2d_pack(sb: int, full, packed):
+    """packed <- target-sector elements of the full-space vector (device FP64 tensors)."""
+    _check(load().d2d_pack(P(sb), P(_ptr(full)), P(_ptr(packed))))
+    return packed
+
+
+def d2d_unpack(sb: int, packed, full):
+    """full-space vector (zero outside the target sector) <- packed (device FP64 tensors)."""
+    _check(load().d2d_unpack(P(sb), P(_ptr(packed)), P(_ptr(full))))
+    return full
+
+
 def d2d_hv(sb: int, prec: int, v, w):
     """w = H v on the context stream; v, w torch tensors on the device."""
     _check(load().d2d_hv(P(sb), int(prec), P(_ptr(v)), P(_ptr(w))))
@@ -302,9 +316,10 @@ def d2d_tile_shapes():
 
 
 def lanczos_opts(prec=D2D_FP64, k_in=24, max_restarts=200, tol_res=1e-9, escalate=0.5, use_graph=1,
-                 reorth_window=0, separate_central=0):
+                 reorth_window=0, separate_central=0, tol_rel_e=0.0, seed=0):
     return d2d_lanczos_opts(int(prec), int(k_in), int(max_restarts), float(tol_res), float(escalate),
-                            int(use_graph), int(reorth_window), int(separate_central))
+                            int(use_graph), int(reorth_window), int(separate_central), float(tol_rel_e),
+                            int(seed))
 
 
 def d2d_lanczos(sb: int, opts: d2d_lanczos_opts, v0, psi=None):
@@ -348,9 +363,10 @@ def d2d_batch_hv(b: int, prec: int, vs, ws):
     _check(load().d2d_batch_hv(P(b), int(prec), va, wa))
 
 
-def d2d_batch_lanczos(b: int, opts: d2d_lanczos_opts, v0s, psis=None):
-    n = len(v0s)
-    va = (P * n)(*[P(_ptr(v)) for v in v0s])
+def d2d_batch_lanczos(b: int, opts: d2d_lanczos_opts, v0s, psis=None, n=None):
+    """v0s: device start vectors, or None (seeded start vectors; then n = number of problems)."""
+    n = len(v0s) if v0s is not None else int(n)
+    va = (P * n)(*[P(_ptr(v)) for v in v0s]) if v0s is not None else None
     pa = (P * n)(*[P(_ptr(p)) for p in psis]) if psis is not None else None
     e = np.zeros(n)
     stats = (d2d_lanczos_stats * n)()

@@ -41,3 +41,25 @@ def test_binding_loads_and_reports_errors():
     # error path without a GPU: NULL out pointer is rejected before any device call
     assert lib.d2d_ctx_create(0, None, 0, None) == d2d.D2D_EINVAL
     assert "NULL" in d2d.d2d_last_error()
+
+
+def test_splitmix64_known_answers():
+    """The seeded start-vector generator against the SplitMix64 reference
+    outputs for seed 1234567 (the published test vector of the generator)."""
+    import numpy as np
+    import workloads as W
+    assert [int(x) for x in W.splitmix64(1234567, 5)] == [
+        6457827717110365317, 3203168211198807973, 9817491932198370423, 4593380528125082431,
+        16408922859458223821]
+    z = W.splitmix_normal(200000, 7)
+    assert abs(z.mean()) < 0.01 and abs(z.std() - 1.0) < 0.01
+
+
+def test_lanczos_opts_layout():
+    """The binding's options struct has the C layout (offsets of the tail fields)."""
+    import ctypes as C
+    from paper_0707_0159_amd import d2d
+    o = d2d.d2d_lanczos_opts
+    assert o.tol_res.offset == 16 and o.escalate.offset == 24
+    assert o.separate_central.offset == 40 and o.tol_rel_e.offset == 48 and o.seed.offset == 56
+    assert C.sizeof(o) == 64

@@ -86,3 +86,57 @@ def test_batch_lanczos_energies(ctx, prec):
     d2d.d2d_batch_destroy(b)
     for p in probs:
         p.close()
+
+
+def config5_or_skip():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "reference_energies.json")
+    with open(path) as f:
+        g = json.load(f)
+    wls = W.config5()
+    missing = [wl.name for wl in wls if wl.name not in g]
+    if missing:
+        pytest.skip(f"reference energies not yet written for {len(missing)} batch problems")
+    return wls, {wl.name: float(g[wl.name]["E0"]) for wl in wls}
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_config5_batch_energies(ctx, prec):
+    """64 uneven superblocks (2/3-leg Heisenberg and Hubbard, m 64..512) in one
+    batch: every problem's ground energy within 1e-10 of the oracle's."""
+    from paper_0707_0159_amd import d2d
+    wls, refs = config5_or_skip()
+    probs = [GpuProblem(ctx, wl, prec_mask=7) for wl in wls]
+    b = d2d.d2d_batch_create(ctx, [p.sb for p in probs])
+    with torch.cuda.stream(ctx.stream):
+        v0 = [torch.as_tensor(W.random_vector(p.info["n"], wl.seed)).to("cuda") for p, wl in zip(probs, wls)]
+    ctx.stream.synchronize()
+    opts = d2d.lanczos_opts(prec=prec, k_in=24, max_restarts=400, tol_res=1e-8, reorth_window=3)
+    st, e, per = d2d.d2d_batch_lanczos(b, opts, v0)
+    dE = [abs(ei - refs[wl.name]) / abs(refs[wl.name]) for ei, wl in zip(e, wls)]
+    print(f"config5 prec {prec}: max dE {max(dE):.2e}, restarts max {max(q['restarts'] for q in per)}")
+    assert st == 0
+    assert max(dE) <= 1e-10
+    d2d.d2d_batch_destroy(b)
+    for p in probs:
+        p.close()
+
+
+def test_config5_sampled_hv_against_oracle(ctx):
+    """Single-problem Hv of the smaller batch problems against the oracle (FP64 <= 1e-12)."""
+    from test_gpu_hv import gpu_hv
+    wls = W.config5()
+    done = 0
+    for wl in wls:
+        osb = oracle_superblock(wl)
+        if osb.N > 300_000:
+            continue
+        prob = GpuProblem(ctx, wl)
+        v = W.random_vector(osb.N, 900)
+        err = rel_err(gpu_hv(ctx, prob, 0, v), osb.hv_factored(v))
+        assert err <= 1e-12, (wl.name, err)
+        prob.close()
+        done += 1
+    print("config5 problems checked", done)
+    assert done >= 16

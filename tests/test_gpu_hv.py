@@ -174,3 +174,28 @@ def test_bf16_every_tile_shape(ctx, cfg):
             assert e1 <= 1e-5
             assert e2 <= 2e-2
     prob.close()
+
+
+@pytest.mark.parametrize("cfg,target", [(1, (6, 0)), (1, (3, 0)), (2, None)])
+def test_pack_unpack_full_space(ctx, cfg, target):
+    """d2d_pack / d2d_unpack against the oracle's index map of the paper's
+    vector order (pure data movement: equal bit for bit; unpack zero-fills
+    outside the target sector)."""
+    from paper_0707_0159_amd import d2d
+    wl = W.CONFIGS[cfg]
+    osb = oracle_superblock(wl, target)
+    prob = GpuProblem(ctx, wl, target)
+    D = osb.m * osb.n
+    x = W.random_vector(D * D, 77)
+    with torch.cuda.stream(ctx.stream):
+        xd = torch.as_tensor(x).to("cuda")
+        pd = torch.full((osb.N,), float("nan"), dtype=torch.float64, device="cuda")
+        fd = torch.full((D * D,), float("nan"), dtype=torch.float64, device="cuda")
+        d2d.d2d_pack(prob.sb, xd, pd)
+        d2d.d2d_unpack(prob.sb, pd, fd)
+    ctx.stream.synchronize()
+    packed = osb.pack(x)
+    assert np.array_equal(pd.cpu().numpy(), packed)
+    assert np.array_equal(fd.cpu().numpy(), osb.unpack(packed))
+    del xd, pd, fd
+    prob.close()

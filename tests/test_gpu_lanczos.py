@@ -81,6 +81,49 @@ def test_fused_central_is_bitwise_separate(ctx, prec):
     prob.close()
 
 
+def test_seeded_start_vector(ctx):
+    """v0 = NULL: the device draws the SplitMix64 / Box-Muller start vector; the
+    same vector generated on the host gives the same solve (same restarts,
+    energies within rounding of the two log/cos implementations)."""
+    from paper_0707_0159_amd import d2d
+    wl = W.CONFIGS[2]
+    prob = GpuProblem(ctx, wl)
+    n = prob.info["n"]
+    E0 = reference_energy(wl.name)
+    opts = d2d.lanczos_opts(prec=1, k_in=24, max_restarts=300, tol_res=1e-8, reorth_window=3, seed=11)
+    st0, e0, s0 = d2d.d2d_lanczos(prob.sb, opts, None)
+    with torch.cuda.stream(ctx.stream):
+        v0 = torch.as_tensor(W.splitmix_normal(n, 11)).to("cuda")
+    ctx.stream.synchronize()
+    st1, e1, s1 = d2d.d2d_lanczos(prob.sb, opts, v0)
+    print("seeded", e0, e1, s0["restarts"], s1["restarts"])
+    assert st0 == 0 and st1 == 0
+    assert abs(e0 - E0) <= 1e-10 * abs(E0)
+    assert abs(e0 - e1) <= 1e-12 * abs(E0)
+    assert abs(s0["log_theta"][0] - s1["log_theta"][0]) <= 1e-12 * abs(s1["log_theta"][0])
+    prob.close()
+
+
+def test_energy_change_stop(ctx):
+    """tol_rel_e: stop on successive FP64 Rayleigh quotients (residual bar out of reach)."""
+    from paper_0707_0159_amd import d2d
+    wl = W.CONFIGS[2]
+    prob = GpuProblem(ctx, wl)
+    E0 = reference_energy(wl.name)
+    n = prob.info["n"]
+    with torch.cuda.stream(ctx.stream):
+        v0 = torch.as_tensor(W.random_vector(n, wl.seed)).to("cuda")
+    ctx.stream.synchronize()
+    opts = d2d.lanczos_opts(prec=1, k_in=24, max_restarts=300, tol_res=1e-300, reorth_window=3, tol_rel_e=1e-13)
+    st, e, stats = d2d.d2d_lanczos(prob.sb, opts, v0)
+    th = stats["log_theta"]
+    print("tol_rel_e", e, stats["restarts"], th[-2:], stats["residual"])
+    assert st == 0
+    assert abs(th[-1] - th[-2]) <= 1e-13 * abs(th[-1])
+    assert abs(e - E0) <= 1e-10 * abs(E0)
+    prob.close()
+
+
 def test_ferromagnetic_sector_breakdown(ctx):
     """1-dimensional sector: the start vector is an eigenvector, rho = 0 at once."""
     wl = W.CONFIGS[1]

@@ -164,6 +164,25 @@ def random_vector(n: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal(n)
 
 
+def splitmix64(seed: int, n: int) -> np.ndarray:
+    """Outputs 0..n-1 of the SplitMix64 stream seeded with ``seed`` (Steele,
+    Lea and Flood 2014): output c is mix(seed + (c+1) * 0x9E3779B97F4A7C15)."""
+    c = np.arange(n, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (c + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def splitmix_normal(n: int, seed: int) -> np.ndarray:
+    """The library's seeded start vector: element i is the Box-Muller normal
+    sqrt(-2 ln u1) cos(2 pi u2) of u = (out >> 11 + 1/2) 2^-53 for SplitMix64
+    outputs 2i and 2i+1."""
+    u = ((splitmix64(seed, 2 * n) >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53
+    return np.sqrt(-2.0 * np.log(u[0::2])) * np.cos(2.0 * np.pi * u[1::2])
+
+
 def unit_vector(n: int, seed: int) -> np.ndarray:
     v = random_vector(n, seed)
     return v / math.sqrt(float(v @ v))
