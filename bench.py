@@ -290,7 +290,8 @@ def main():
     tuned = {}
     for prec, name in names.items():
         t, ms_t = d2d.d2d_sb_autotune(sb, prec, reps=10)
-        tuned[name] = {"tile": t & 0xFFFF, "split_k_loops": bool(t & d2d.D2D_TILE_SPLIT),
+        tuned[name] = {"tile": t & 0xFFFF,
+                       "split_k_loops": "halves" if t & d2d.D2D_TILE_SPLIT4 else bool(t & d2d.D2D_TILE_SPLIT),
                        "central_in_gemm_launch": bool(t & d2d.D2D_TILE_FUSED),
                        "BMxBNxBK": "x".join(str(x) for x in shapes[t & 0xFFFF][1:]), "ms": ms_t}
     with torch.cuda.stream(s):
@@ -383,7 +384,8 @@ def main():
         return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[name] / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK[name], "traffic": traffic_record(wl.name, name),
                 "kernel": f"grouped GEMM H_l V + V H_r^T ({name}, tile {tuned[name]['BMxBNxBK']}"
-                          f"{', split K-loops' if tuned[name]['split_k_loops'] else ''})",
+                          f"{', split K-loops' if tuned[name]['split_k_loops'] else ''}"
+                          f"{' (halved)' if tuned[name]['split_k_loops'] == 'halves' else ''})",
                 "flops_per_launch": F, "launch_ms": ms[name]["gemm_ms"],
                 "hbm_bytes_min_per_launch": info["bytes_min_" + name],
                 "hbm_frac_at_min_bytes": info["bytes_min_" + name] / sec / PEAK["hbm"]}

@@ -212,7 +212,9 @@ d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[3]);
  * library choose by problem size.  OR-ing D2D_TILE_SPLIT runs the two K-loops
  * of every output tile (H_l V and V H_r^T) as separate work items into two
  * partial outputs, which the central-term launch adds (shorter critical path
- * for small, latency-bound sectors).  OR-ing D2D_TILE_FUSED makes the inner
+ * for small, latency-bound sectors); D2D_TILE_SPLIT4 also halves each K-loop
+ * (four work items and four partial outputs per tile, added in a fixed order,
+ * so results stay deterministic).  OR-ing D2D_TILE_FUSED makes the inner
  * Lanczos steps evaluate the central term inside the grouped-GEMM launch (its
  * tiles as extra blocks after the GEMM work items, into an output of its own
  * that the first vector kernel of the step adds: same result bit for bit, one
@@ -222,10 +224,11 @@ d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[3]);
  * shape not built for that precision. */
 #define D2D_TILE_SPLIT (1 << 16)
 #define D2D_TILE_FUSED (1 << 17)
+#define D2D_TILE_SPLIT4 (1 << 18)
 d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile);
 /* Autotuner: times every grouped-GEMM tile shape of precision prec on this
- * superblock, with and without D2D_TILE_SPLIT and with and without
- * D2D_TILE_FUSED (reps launches each, on internal scratch vectors, HIP events
+ * superblock, unsplit, with D2D_TILE_SPLIT and with D2D_TILE_SPLIT4, each with
+ * and without D2D_TILE_FUSED (reps launches each, on internal scratch vectors, HIP events
  * on the context stream), selects the fastest for later d2d_hv / d2d_lanczos
  * calls and returns it (shape index OR-ed with the flags) and its average
  * milliseconds.  If the environment variable D2D_TUNE_CACHE names a file,

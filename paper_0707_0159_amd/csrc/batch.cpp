@@ -155,7 +155,7 @@ HvTables tables_of(d2d_batch* b) {
     t.n_ptiles = b->n_ptiles;
     t.vp = b->d_vp;
     t.vt = b->d_vt;
-    t.w1 = b->split ? b->d_w1 : nullptr;
+    if (b->split) t.x[0] = b->d_w1;
     return t;
 }
 
@@ -170,13 +170,13 @@ d2d_status batch_hv(d2d_batch* b, int prec, const void* v, void* w, hipStream_t 
     HvTables t = tables_of(b);
     if (parts && prec == D2D_FP64) {
         // FP64: the central term's register demand lowers the GEMM's occupancy
-        parts->w1 = parts->w2 = nullptr;
+        *parts = HvParts{};
         parts = nullptr;
     }
     if (parts) {
         t.w2 = b->d_w2;
-        parts->w1 = t.w1;
-        parts->w2 = t.w2;
+        for (int i = 0; i < 3; ++i) parts->x[i] = t.x[i];
+        parts->central = t.w2;
     }
     return hv_launch(t, prec, shape, wl.first, wl.second, v, w, s, nullptr);
 }

@@ -96,6 +96,7 @@ struct LanczosWork {
     double* res = nullptr;       // 2 x nprob
     double* res_host = nullptr;  // pinned copy of res
     d2d::LzSeg* bt = nullptr;
+    std::vector<d2d::LzSeg> h_bt;   // host copy (its act flags follow the active set)
     int2* prange = nullptr;
     int* active = nullptr;
     hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
@@ -108,7 +109,7 @@ namespace d2d {
 struct HvTables {
     const SectorDev* sec;
     int npairs;
-    void* w1;                 // scratch partial output of split K-loops (ntot doubles)
+    void* x[3];               // partial outputs of split K-loops (ntot doubles each; null = unused)
     void* w2;                 // central-term output of a fused launch (ntot doubles; null = unfused)
     const void* HL[3];
     const void* HR[3];
@@ -134,11 +135,12 @@ struct HvTables {
 d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkItem* work, int nwork, const void* v,
                      void* w, hipStream_t s, hipEvent_t mid);
 
-// Output of a fused Hv left in parts: the product is (w + w1) + w2, added in
-// that order by the consumer (w1 null when the K-loops are not split).
+// Output of a fused Hv left in parts: the product is
+// (((w + x0) + x1) + x2) + central, added in that order by the consumer (the
+// x present depend on how the K-loops are split; central null when unfused).
 struct HvParts {
-    const void* w1;
-    const void* w2;
+    const void* x[3];
+    const void* central;
 };
 
 // Hv of a set of problems on concatenated vectors (one superblock or a batch).
@@ -202,9 +204,9 @@ struct d2d_sb {
     // work lists per tile shape
     std::map<int, std::pair<d2d::WorkItem*, int>> work;
     int tile_sel[3] = {-1, -1, -1};     // shape index, or -1 = by size
-    int split[3] = {0, 0, 0};
+    int split[3] = {0, 0, 0};          // 0 none, 1 two K-loops apart, 2 each K-loop halved too
     int fuse[3] = {0, 1, 1};            // inner Lanczos steps: central term inside the GEMM launch
-    void* d_w1 = nullptr;               // N doubles, allocated on first split launch
+    void* d_x[3] = {nullptr, nullptr, nullptr};   // split-K partial outputs, N doubles each, on demand
     void* d_w2 = nullptr;               // N doubles, central-term part of fused launches
     int64_t hv_count[3] = {0, 0, 0};
     LanczosWork* lz = nullptr;          // owned; freed by free_lanczos
@@ -224,6 +226,8 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
 // is left in parts (see HvParts), else w holds the whole product.
 d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s, hipEvent_t mid,
                        HvParts* parts = nullptr);
+// partial outputs of a split level (and the central part) allocated on demand
+d2d_status sb_ensure_parts(d2d_sb* sb, int split, bool central);
 int sb_auto_tile(const d2d_sb* sb, int prec);
 d2d_status sb_work(d2d_sb* sb, int shape, int split, WorkItem** w, int* nwork);
 // central-term launch table of the pairs with keep[p] != 0 (all when keep is null)
@@ -232,7 +236,10 @@ void central_tiles(const std::vector<SectorDev>& pairs, const std::vector<int>* 
 // packed offset and row count of the source block of every (pair, term); -1 / 0 when none
 void central_sources(const std::vector<SectorDev>& pairs, const std::vector<int32_t>& src, int K,
                      std::vector<int64_t>& off, std::vector<int32_t>& dl);
-// work items of the pairs [0, npairs) for a tile shape; split = two items per tile
+// number of partial outputs of a split level (0, 1, 3)
+inline int split_parts(int split) { return split == 0 ? 0 : (split == 1 ? 1 : 3); }
+// work items of the pairs with keep[p] != 0 for a tile shape; split level 0:
+// one item per output tile, 1: one per K-loop, 2: one per half K-loop
 void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep, const TileShape& ts, int split,
                std::vector<WorkItem>& out);
 void free_lanczos(d2d_sb* sb);

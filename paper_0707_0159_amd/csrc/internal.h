@@ -53,6 +53,9 @@ struct SectorDev {
 // One output tile of the grouped GEMM: pair, tile row, tile column.
 // part: 0 = both K-loops into W; 1 = H_l V only into W; 2 = V H_r^T only into W1
 // (split K-loops: the central-term kernel adds W1 into W).
+// part: bits 0-1 K-loops (0 both, 1 H_l V only, 2 V H_r^T only); bits 2-3
+// output slot (0 W, s partial X[s-1]); bit 4 one half of the K-loop only,
+// bit 5 which half.
 struct WorkItem {
     int32_t p, tm, tn, part;
 };
@@ -89,7 +92,7 @@ struct CentralArgs {
     int64_t Drows, Dcols;
     const void* V;
     void* W;
-    const void* W1;            // partial output of split K-loops added into W (nullable)
+    const void* X[3];          // split-K partial outputs added into W first, in order (nullable)
 };
 hipError_t launch_central(int prec, const CentralArgs& a, hipStream_t s);
 
@@ -97,10 +100,11 @@ hipError_t launch_central(int prec, const CentralArgs& a, hipStream_t s);
 hipError_t launch_full_pack(const SectorDev* sec, int npairs, int64_t max_elems, const int32_t* rows,
                             const int32_t* cols, int64_t D, int dir, const double* src, double* dst, hipStream_t s);
 
-// Grouped GEMM W = H_l V + V H_r^T over a work list (split work items write
-// their second K-loop to W1).  With fuse set, the same launch also evaluates
-// the central term into fuse->W (a separate output: the caller adds
-// (W + W1) + fuse->W).
+// Grouped GEMM W = H_l V + V H_r^T over a work list; split work items write
+// their share of the K-loops to the partial outputs X (the product is
+// ((W + X0) + X1) + X2, added by the central term).  With fuse set, the same
+// launch also evaluates the central term into fuse->W (a separate output: the
+// consumer adds the GEMM parts in order and then fuse->W).
 struct HvGemmArgs {
     const WorkItem* work;
     int nwork;
@@ -109,7 +113,7 @@ struct HvGemmArgs {
     const void* HR;
     const void* V;
     void* W;
-    void* W1;                  // second partial output of split work items (nullable)
+    void* X[3];                // partial outputs of split work items (slot s -> X[s-1]; nullable)
     const CentralArgs* fuse;   // nullable
 };
 hipError_t launch_hv_gemm(int shape, const HvGemmArgs& a, hipStream_t s);
@@ -159,7 +163,8 @@ constexpr int S_ALPHA = 0, S_BETA = 130, S_THETA = 524, S_Y = 528, S_LEN = 660;
 
 // Block of a segmented kernel: problem, its block range [pb0, pb1), chunk [lo, hi).
 struct LzSeg {
-    int prob, pb0, pb1, pad;
+    int prob, pb0, pb1;
+    int act;     // the problem is still iterating (kept equal to the active flags)
     int64_t lo, hi;
 };
 
@@ -183,17 +188,15 @@ struct LzSet {
 // qnext = (w - [need2] Q c2) / beta_{i+1}, lo = cast(qnext).
 struct LzStepArgs {
     const LzSeg* bt;
-    const int* active;
     const double* Q;
     int64_t ldq;
     int nq, i;
     bool upcast;
     const float* w32;
     double* w;
-    // parts of a fused Hv: the product is (w32 or w) + wp1 + wp2 in the Hv's
-    // own precision (FP32 when upcast, else FP64); each nullable
-    const void* wp1;
-    const void* wp2;
+    // parts of a fused Hv: the product is (((w32 or w) + P0) + P1) + P2 + P3
+    // in the Hv's own precision (FP32 when upcast, else FP64); each nullable
+    const void* wpart[4];
     double* partial;
     double* partial2;
     int NB;

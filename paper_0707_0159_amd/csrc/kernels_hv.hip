@@ -12,6 +12,36 @@
 
 namespace d2d {
 
+// ------------------------------------------------------------------ work items
+// WorkItem.part: bits 0-1 the K-loops it runs (0 both, 1 only H_l V, 2 only
+// V H_r^T); bits 2-3 its output slot (0: W, s: X[s-1]); bit 4 set: it runs
+// only one half of its K-loop, bit 5 which half.  A half is cut at a multiple
+// of BK, so no K step straddles the cut.
+struct ItemK {
+    int ph_lo, ph_hi, slot, halved, half;
+};
+__device__ inline ItemK decode_item(int part) {
+    ItemK d;
+    const int ph = part & 3;
+    d.ph_lo = ph == 2 ? 1 : 0;
+    d.ph_hi = ph == 1 ? 1 : 2;
+    d.slot = (part >> 2) & 3;
+    d.halved = (part >> 4) & 1;
+    d.half = (part >> 5) & 1;
+    return d;
+}
+template <int BK>
+__device__ inline void k_range(const ItemK& d, int K, int& k_lo, int& k_hi) {
+    if (!d.halved) {
+        k_lo = 0;
+        k_hi = K;
+        return;
+    }
+    const int cut = ((K + 1) / 2 + BK - 1) / BK * BK;
+    k_lo = d.half ? (cut < K ? cut : K) : 0;
+    k_hi = d.half ? K : (cut < K ? cut : K);
+}
+
 // ------------------------------------------------------------------ MFMA shapes
 // Operand layouts of the gfx950 matrix instructions used (wave64):
 //  16x16x4 (f64): lane l holds A[l%16][l/16], B[l/16][l%16]; result value v
@@ -70,7 +100,7 @@ struct CentralK {
     int64_t Drows, Dcols;
     const TI* V;
     TO* W;
-    const TO* W1;
+    const TO* X[3];   // split-K partial outputs added to W before the central term (nullable)
 };
 
 // Central term.  One wave per output tile of 64 rows x CT columns of one pair;
@@ -82,8 +112,9 @@ struct CentralK {
 // coefficients of all K terms; the old W and the split-K partial W1) are
 // issued in one round.  Each lane owns one row r; runs of consecutive i1 map
 // to consecutive source rows, so a wave's gathers are coalesced.
-// ACCUM: W = (W + W1) + central.  Otherwise W is a separate output that
-// receives the central term alone, for a consumer that adds (W + W1) + it.
+// ACCUM: W = (((W + X0) + X1) + X2) + central (the split-K partials that
+// are present).  Otherwise W is a separate output that receives the central
+// term alone, for a consumer that adds the parts in that order.
 template <typename TI, typename TO, typename TC, int NW, bool ACCUM>
 __device__ inline void central_tiles_block(const CentralK<TI, TO, TC>& c, int i0) {
     __shared__ int64_t s_off2[NW][KMAX];
@@ -144,7 +175,11 @@ __device__ inline void central_tiles_block(const CentralK<TI, TO, TC>& c, int i0
             for (int j = 0; j < CT; ++j) {
                 const int cc = t.c0 + j < t.dR ? t.c0 + j : 0;
                 const int64_t e = t.off + rr + (int64_t)cc * t.dL;
-                wo[j] = c.W[e] + (c.W1 ? c.W1[e] : TO(0));
+                TO x = c.W[e];
+                if (c.X[0]) x = x + c.X[0][e];
+                if (c.X[1]) x = x + c.X[1][e];
+                if (c.X[2]) x = x + c.X[2][e];
+                wo[j] = x;
             }
         }
     }
@@ -240,7 +275,7 @@ static CentralK<TI, TO, TC> central_args(const CentralArgs& a) {
     c.Dcols = a.Dcols;
     c.V = (const TI*)a.V;
     c.W = (TO*)a.W;
-    c.W1 = (const TO*)a.W1;
+    for (int i = 0; i < 3; ++i) c.X[i] = (const TO*)a.X[i];
     return c;
 }
 
@@ -270,7 +305,7 @@ struct HvK {
     const T* HRt;
     const T* V;
     T* W;
-    T* W1;
+    T* X[3];
     CentralK<T, T, T> cen;
 };
 
@@ -317,9 +352,9 @@ k_hv_gemm(const HvK<T> g) {
             for (int v = 0; v < M::NV; ++v) acc[i][j][v] = T(0);
 
     T ra[EA], rb[EB];
-    const int ph_lo = wi.part == 2 ? 1 : 0, ph_hi = wi.part == 1 ? 1 : 2;
+    const ItemK it = decode_item(wi.part);
 #pragma unroll 1
-    for (int phase = ph_lo; phase < ph_hi; ++phase) {
+    for (int phase = it.ph_lo; phase < it.ph_hi; ++phase) {
         // phase 0: A = H_l[q_L] (dL x dL), B = V (dL x dR), K = dL
         // phase 1: A = V (dL x dR), B = H_r^T (dR x dR), K = dR
         const T* A = phase == 0 ? HL + s.hl_off : V + s.off;
@@ -327,6 +362,8 @@ k_hv_gemm(const HvK<T> g) {
         const int64_t lda = dL;
         const int64_t ldb = phase == 0 ? dL : dR;
         const int K = phase == 0 ? dL : dR;
+        int k_lo, k_hi;
+        k_range<BK>(it, K, k_lo, k_hi);
 
         auto gload = [&](int k0) {
 #pragma unroll
@@ -343,10 +380,10 @@ k_hv_gemm(const HvK<T> g) {
             }
         };
 
-        gload(0);
+        if (k_lo < k_hi) gload(k_lo);
         int buf = 0;
 #pragma unroll 1
-        for (int k0 = 0; k0 < K; k0 += BK) {
+        for (int k0 = k_lo; k0 < k_hi; k0 += BK) {
 #pragma unroll
             for (int e = 0; e < EA; ++e) {
                 const int idx = t + NT * e;
@@ -358,7 +395,7 @@ k_hv_gemm(const HvK<T> g) {
                 Bs[buf][idx / BK][idx % BK] = rb[e];
             }
             __syncthreads();
-            if (k0 + BK < K) gload(k0 + BK);
+            if (k0 + BK < k_hi) gload(k0 + BK);
 #pragma unroll
             for (int kk = 0; kk < BK; kk += M::MK) {
                 T a[FM], b[FN];
@@ -378,7 +415,7 @@ k_hv_gemm(const HvK<T> g) {
         __syncthreads();
     }
 
-    T* Wp = (wi.part == 2 ? g.W1 : g.W) + s.off;
+    T* Wp = (it.slot == 0 ? g.W : g.X[it.slot - 1]) + s.off;
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
         const int r = row0 + wm * WM + i * M::MN + lane % M::MN;
@@ -402,14 +439,17 @@ k_hv_gemm(const HvK<T> g) {
 //   phase 1: A = V^T (column-major dR x dL, ld dRp), B = H_r^T (ld dRp)
 // K runs over the padded length; the padding of every operand is zero.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+struct OutPtrs {
+    float* W;
+    float* X[3];
+};
 __device__ inline bf16_t f32_to_bf16_rne(float f);
 
 template <int BM, int BN, int BK, int WGM, int WGN, bool CEN>
 __global__ void __launch_bounds__(64 * WGM * WGN)
 k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __restrict__ sec,
                const bf16_t* __restrict__ HL, const bf16_t* __restrict__ HRt, const bf16_t* __restrict__ VP,
-               const bf16_t* __restrict__ VT, float* __restrict__ W, float* __restrict__ W1,
-               const CentralK<bf16_t, float, float> cen) {
+               const bf16_t* __restrict__ VT, const OutPtrs out, const CentralK<bf16_t, float, float> cen) {
     if constexpr (CEN) {
         if ((int)blockIdx.x >= nwork) {
             central_tiles_block<bf16_t, float, float, WGM * WGN, false>(cen, ((int)blockIdx.x - nwork) * WGM * WGN);
@@ -444,13 +484,15 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __
             for (int v = 0; v < M::NV; ++v) acc[i][j][v] = 0.0f;
 
     uint4 ra[EA], rb[EB];
-    const int ph_lo = wi.part == 2 ? 1 : 0, ph_hi = wi.part == 1 ? 1 : 2;
+    const ItemK it = decode_item(wi.part);
 #pragma unroll 1
-    for (int phase = ph_lo; phase < ph_hi; ++phase) {
+    for (int phase = it.ph_lo; phase < it.ph_hi; ++phase) {
         const bf16_t* A = phase == 0 ? HL + s.hl16_off : VT + s.vt_off;
         const bf16_t* B = phase == 0 ? VP + s.vp_off : HRt + s.hr16_off;
         const int64_t ld = phase == 0 ? s.dLp : s.dRp;     // both operands share the K stride
         const int Kp = phase == 0 ? s.dLp : s.dRp;
+        int k_lo, k_hi;
+        k_range<BK>(it, Kp, k_lo, k_hi);
 
         auto gload = [&](int k0) {
 #pragma unroll
@@ -466,10 +508,10 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __
                 rb[e] = (gc < dR && kk < Kp) ? *(const uint4*)(B + gc * ld + kk) : make_uint4(0, 0, 0, 0);
             }
         };
-        gload(0);
+        if (k_lo < k_hi) gload(k_lo);
         int buf = 0;
 #pragma unroll 1
-        for (int k0 = 0; k0 < Kp; k0 += BK) {
+        for (int k0 = k_lo; k0 < k_hi; k0 += BK) {
 #pragma unroll
             for (int e = 0; e < EA; ++e) {
                 const int idx = t + NT * e;
@@ -481,7 +523,7 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __
                 *(uint4*)&Bs[buf][idx / KV][8 * (idx % KV)] = rb[e];
             }
             __syncthreads();
-            if (k0 + BK < Kp) gload(k0 + BK);
+            if (k0 + BK < k_hi) gload(k0 + BK);
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 16) {
                 bf16x8 a[FM], b[FN];
@@ -502,7 +544,7 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __
         __syncthreads();
     }
 
-    float* Wp = (wi.part == 2 ? W1 : W) + s.off;
+    float* Wp = (it.slot == 0 ? out.W : out.X[it.slot - 1]) + s.off;
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
         const int r = row0 + wm * WM + i * 32 + (lane & 31);
@@ -524,15 +566,16 @@ static void gemm_bf16_launch(const HvGemmArgs& a, const void* VT, hipStream_t st
     const bf16_t* HR = (const bf16_t*)a.HR;
     const bf16_t* VP = (const bf16_t*)a.V;
     const bf16_t* V2 = (const bf16_t*)VT;
-    float* W = (float*)a.W;
-    float* W1 = (float*)a.W1;
+    OutPtrs out;
+    out.W = (float*)a.W;
+    for (int i = 0; i < 3; ++i) out.X[i] = (float*)a.X[i];
     if (a.fuse) {
         const int extra = (a.fuse->ntiles + NW - 1) / NW;
         hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, true>), dim3(a.nwork + extra), dim3(64 * NW), 0, st,
-                           a.work, a.nwork, a.sec, HL, HR, VP, V2, W, W1, central_args<bf16_t, float, float>(*a.fuse));
+                           a.work, a.nwork, a.sec, HL, HR, VP, V2, out, central_args<bf16_t, float, float>(*a.fuse));
     } else {
         hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, false>), dim3(a.nwork), dim3(64 * NW), 0, st, a.work,
-                           a.nwork, a.sec, HL, HR, VP, V2, W, W1, CentralK<bf16_t, float, float>{});
+                           a.nwork, a.sec, HL, HR, VP, V2, out, CentralK<bf16_t, float, float>{});
     }
 }
 
@@ -682,7 +725,7 @@ static void gemm_launch(const HvGemmArgs& a, hipStream_t st) {
     g.HRt = (const T*)a.HR;
     g.V = (const T*)a.V;
     g.W = (T*)a.W;
-    g.W1 = (T*)a.W1;
+    for (int i = 0; i < 3; ++i) g.X[i] = (T*)a.X[i];
     if (a.fuse) {
         g.cen = central_args<T, T, T>(*a.fuse);
         const int extra = (a.fuse->ntiles + NW - 1) / NW;

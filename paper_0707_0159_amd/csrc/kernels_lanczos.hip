@@ -236,12 +236,25 @@ int lz_step_blocks(int64_t n) {
 }
 
 // out_sh[j] = sum_{b in [b0,b1)} partial[j*NB + b], j < rows (shared result).
+// A problem has at most LZ_STEP_NB blocks, so a lane adds at most
+// LZ_STEP_NB / 64 partials of a row; all of them are loaded at once (index
+// clamped into the problem's range, the extra values masked afterwards), so
+// the sum costs one memory latency, not one per partial.
 __device__ inline void reduce_rows(const double* __restrict__ partial, int rows, int NB, int b0, int b1,
                                    double* out_sh) {
+    constexpr int R = LZ_STEP_NB / 64;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int j = wv; j < rows; j += LZ_THREADS / 64) {
+        double v[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int b = b0 + lane + 64 * q;
+            v[q] = partial[(int64_t)j * NB + (b < b1 ? b : b0)];
+        }
         double s = 0.0;
-        for (int b = b0 + lane; b < b1; b += 64) s += partial[(int64_t)j * NB + b];
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (b0 + lane + 64 * q < b1) s += v[q];
         s = wave_sum(s);
         if (lane == 0) out_sh[j] = s;
     }
@@ -276,45 +289,57 @@ struct StepUnroll {
     static constexpr int U = NQ <= 4 ? 4 : (NQ <= 8 ? 2 : 1);
 };
 
-// Step kernel 1: w = (w + p1) + p2 in the Hv's precision (the parts of a
-// fused Hv, each nullable), upcast from FP32 when UPCAST, stored as FP64 when
-// it changed; partials of c1 = Q[0..nq)^T w.
+struct HvPartPtrs {
+    const void* p[4];
+};
+
+// Step kernel 1: w = (((w + P0) + P1) + P2) + P3 in the Hv's precision (the
+// parts of a split or fused Hv, each nullable), upcast from FP32 when UPCAST,
+// stored as FP64 when it changed; partials of c1 = Q[0..nq)^T w.
 template <int NQ, bool UPCAST>
 __global__ void __launch_bounds__(LZ_THREADS)
-k_lz_dots(const LzSeg* __restrict__ bt, const int* __restrict__ active, const double* __restrict__ Q,
-          int64_t ldq, int nq, const double* w64in, const float* __restrict__ w32,
-          const void* __restrict__ p1, const void* __restrict__ p2, double* w64out,
-          double* __restrict__ partial, int NB) {
+k_lz_dots(const LzSeg* __restrict__ bt, const double* __restrict__ Q,
+          int64_t ldq, int nq, const double* w64in, const float* __restrict__ w32, const HvPartPtrs P,
+          double* w64out, double* __restrict__ partial, int NB) {
+    const bool any = P.p[0] || P.p[1] || P.p[2] || P.p[3];
     constexpr int U = StepUnroll<NQ>::U;
     const LzSeg sg = bt[blockIdx.x];
-    if (!active[sg.prob]) return;
+    if (!sg.act) return;
     double acc[NQ];
 #pragma unroll
     for (int j = 0; j < NQ; ++j) acc[j] = 0.0;
     const int64_t st = blockDim.x;
+    using TW = typename std::conditional<UPCAST, float, double>::type;
+    const TW* win = UPCAST ? (const TW*)w32 : (const TW*)w64in;
     for (int64_t e0 = sg.lo + threadIdx.x; e0 < sg.hi; e0 += U * st) {
+        // loads at an index clamped into the segment, issued together; the
+        // lanes past the end are masked afterwards
         double x[U], q[U][NQ];
+        TW wv[U], pv[4][U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t e = e0 + u * st;
-            const bool ok = e < sg.hi;
-            if constexpr (UPCAST) {
-                float f = ok ? w32[e] : 0.0f;
-                if (p1) f = f + (ok ? ((const float*)p1)[e] : 0.0f);
-                if (p2) f = f + (ok ? ((const float*)p2)[e] : 0.0f);
-                x[u] = (double)f;
-            } else {
-                double d = ok ? w64in[e] : 0.0;
-                if (p1) d = d + (ok ? ((const double*)p1)[e] : 0.0);
-                if (p2) d = d + (ok ? ((const double*)p2)[e] : 0.0);
-                x[u] = d;
-            }
+            const int64_t ec = e < sg.hi ? e : sg.lo;
+            wv[u] = win[ec];
 #pragma unroll
-            for (int j = 0; j < NQ; ++j) q[u][j] = (ok && j < nq) ? Q[j * ldq + e] : 0.0;
+            for (int i = 0; i < 4; ++i) pv[i][u] = P.p[i] ? ((const TW*)P.p[i])[ec] : TW(0);
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? Q[j * ldq + ec] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (UPCAST || p1 || p2) {
+            const bool ok = e0 + u * st < sg.hi;
+            TW f = wv[u];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (P.p[i]) f = f + pv[i][u];
+            x[u] = ok ? (double)f : 0.0;
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) q[u][j] = ok ? q[u][j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (UPCAST || any) {
                 const int64_t e = e0 + u * st;
                 if (e < sg.hi) w64out[e] = x[u];
             }
@@ -329,11 +354,11 @@ k_lz_dots(const LzSeg* __restrict__ bt, const int* __restrict__ active, const do
 // (rows 0..nq-1) and |w|^2 (row nq) into partial_out; alpha_i = c1[i].
 template <int NQ>
 __global__ void __launch_bounds__(LZ_THREADS)
-k_lz_update_dots(const LzSeg* __restrict__ bt, const int* __restrict__ active, const double* __restrict__ Q,
+k_lz_update_dots(const LzSeg* __restrict__ bt, const double* __restrict__ Q,
                  int64_t ldq, int nq, const double* __restrict__ partial_in, double* __restrict__ w,
                  double* __restrict__ partial_out, int NB, double* __restrict__ scal, int i) {
     const LzSeg sg = bt[blockIdx.x];
-    if (!active[sg.prob]) return;
+    if (!sg.act) return;
     __shared__ double cs[NQ];
     if ((int)threadIdx.x < NQ) cs[threadIdx.x] = 0.0;
     __syncthreads();
@@ -349,11 +374,18 @@ k_lz_update_dots(const LzSeg* __restrict__ bt, const int* __restrict__ active, c
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t e = e0 + u * st;
-            const bool ok = e < sg.hi;
-            x[u] = ok ? w[e] : 0.0;
+            const int64_t ec = e < sg.hi ? e : sg.lo;
+            x[u] = w[ec];
 #pragma unroll
-            for (int j = 0; j < NQ; ++j) q[u][j] = (ok && j < nq) ? Q[j * ldq + e] : 0.0;
+            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? Q[j * ldq + ec] : 0.0;
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e0 + u * st >= sg.hi) {
+                x[u] = 0.0;
+#pragma unroll
+                for (int j = 0; j < NQ; ++j) q[u][j] = 0.0;
+            }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -392,11 +424,11 @@ k_lz_update_dots(const LzSeg* __restrict__ bt, const int* __restrict__ active, c
 // lo = cast(q_next); the problem's first block writes alpha_i += c2[i], beta_{i+1}.
 template <int NQ>
 __global__ void __launch_bounds__(LZ_THREADS)
-k_lz_next(const LzSeg* __restrict__ bt, const int* __restrict__ active, const double* __restrict__ Q,
+k_lz_next(const LzSeg* __restrict__ bt, const double* __restrict__ Q,
           int64_t ldq, int nq, const double* __restrict__ partial_in, int NB, const double* __restrict__ w,
           double* __restrict__ qnext, void* __restrict__ lo, int lo_prec, double* __restrict__ scal, int i) {
     const LzSeg sg = bt[blockIdx.x];
-    if (!active[sg.prob]) return;
+    if (!sg.act) return;
     __shared__ double cs[NQ + 1];
     reduce_rows(partial_in, nq + 1, NB, sg.pb0, sg.pb1, cs);
     double s2 = 0.0;
@@ -414,19 +446,22 @@ k_lz_next(const LzSeg* __restrict__ bt, const int* __restrict__ active, const do
     const double inv = bb > 0.0 ? 1.0 / bb : 0.0;
     const int64_t st = blockDim.x;
     for (int64_t e0 = sg.lo + threadIdx.x; e0 < sg.hi; e0 += 4 * st) {
-        double x[4];
+        // loads at an index clamped into the segment, issued together
+        double x[4], q[4][NQ];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t e = e0 + u * st;
-            x[u] = e < sg.hi ? w[e] : 0.0;
+            const int64_t ec = e < sg.hi ? e : sg.lo;
+            x[u] = w[ec];
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) q[u][j] = (corr && j < nq) ? Q[j * ldq + ec] : 0.0;
         }
         if (corr)
-            for (int j = 0; j < nq; ++j)
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int64_t e = e0 + u * st;
-                    if (e < sg.hi) x[u] -= cs[j] * Q[j * ldq + e];
-                }
+            for (int j = 0; j < NQ; ++j)
+                if (j < nq)   // cs[nq] holds |w|^2, and entries past it are not written
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) x[u] -= cs[j] * q[u][j];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t e = e0 + u * st;
@@ -442,19 +477,21 @@ k_lz_next(const LzSeg* __restrict__ bt, const int* __restrict__ active, const do
 template <int NQ>
 static hipError_t lz_step_nq(const LzStepArgs& a, hipStream_t s) {
     const int NB = a.NB;
+    HvPartPtrs P;
+    for (int i = 0; i < 4; ++i) P.p[i] = a.wpart[i];
     if (a.upcast)
-        hipLaunchKernelGGL((k_lz_dots<NQ, true>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.active, a.Q, a.ldq, a.nq,
-                           (const double*)nullptr, a.w32, a.wp1, a.wp2, a.w, a.partial, NB);
+        hipLaunchKernelGGL((k_lz_dots<NQ, true>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq,
+                           (const double*)nullptr, a.w32, P, a.w, a.partial, NB);
     else
-        hipLaunchKernelGGL((k_lz_dots<NQ, false>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.active, a.Q, a.ldq,
-                           a.nq, a.w, (const float*)nullptr, a.wp1, a.wp2, a.w, a.partial, NB);
+        hipLaunchKernelGGL((k_lz_dots<NQ, false>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq,
+                           a.nq, a.w, (const float*)nullptr, P, a.w, a.partial, NB);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_lz_update_dots<NQ>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.active, a.Q, a.ldq, a.nq,
+    hipLaunchKernelGGL((k_lz_update_dots<NQ>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq,
                        a.partial, a.w, a.partial2, NB, a.scal, a.i);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_lz_next<NQ>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.active, a.Q, a.ldq, a.nq,
+    hipLaunchKernelGGL((k_lz_next<NQ>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq,
                        a.partial2, NB, a.w, a.qnext, a.lo, a.lo ? a.lo_prec : -1, a.scal, a.i);
     return hipGetLastError();
 }
@@ -469,10 +506,10 @@ hipError_t launch_lz_step(const LzStepArgs& a, hipStream_t s) {
 
 // partials of x.w (row 0)
 __global__ void __launch_bounds__(LZ_THREADS)
-k_lz_dot1(const LzSeg* __restrict__ bt, const int* __restrict__ active, const double* __restrict__ x,
+k_lz_dot1(const LzSeg* __restrict__ bt, const double* __restrict__ x,
           const double* __restrict__ w, double* __restrict__ partial, int NB) {
     const LzSeg sg = bt[blockIdx.x];
-    if (!active[sg.prob]) return;
+    if (!sg.act) return;
     double acc[1] = {0.0};
     for (int64_t e = sg.lo + threadIdx.x; e < sg.hi; e += blockDim.x) acc[0] += x[e] * w[e];
     write_partials<1>(acc, 1, partial, NB, blockIdx.x);
@@ -480,10 +517,10 @@ k_lz_dot1(const LzSeg* __restrict__ bt, const int* __restrict__ active, const do
 
 // theta from partial_in; w <- w - theta x; partials of |w|^2
 __global__ void __launch_bounds__(LZ_THREADS)
-k_lz_resid(const LzSeg* __restrict__ bt, const int* __restrict__ active, const double* __restrict__ x,
+k_lz_resid(const LzSeg* __restrict__ bt, const double* __restrict__ x,
            const double* __restrict__ partial_in, double* __restrict__ w, double* __restrict__ partial_out, int NB) {
     const LzSeg sg = bt[blockIdx.x];
-    if (!active[sg.prob]) return;
+    if (!sg.act) return;
     __shared__ double th[1];
     reduce_rows(partial_in, 1, NB, sg.pb0, sg.pb1, th);
     const double t = th[0];
@@ -518,10 +555,10 @@ k_lz_restart_finish(const int2* __restrict__ prange, const int* __restrict__ act
 }
 
 hipError_t launch_lz_residual(const LzSet& z, const double* x, double* w, hipStream_t s) {
-    hipLaunchKernelGGL(k_lz_dot1, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, z.active, x, w, z.partial, z.NB);
+    hipLaunchKernelGGL(k_lz_dot1, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, x, w, z.partial, z.NB);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lz_resid, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, z.active, x, z.partial, w, z.partial2,
+    hipLaunchKernelGGL(k_lz_resid, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, x, z.partial, w, z.partial2,
                        z.NB);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -532,10 +569,10 @@ hipError_t launch_lz_residual(const LzSet& z, const double* x, double* w, hipStr
 
 // x = Q y (y of the problem); partials of |x|^2
 __global__ void __launch_bounds__(LZ_THREADS)
-k_lz_ritz(const LzSeg* __restrict__ bt, const int* __restrict__ active, const double* __restrict__ Q, int64_t ldq,
+k_lz_ritz(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int64_t ldq,
           int k, const double* __restrict__ scal, double* __restrict__ x, double* __restrict__ partial, int NB) {
     const LzSeg sg = bt[blockIdx.x];
-    if (!active[sg.prob]) return;
+    if (!sg.act) return;
     __shared__ double ys[128];
     const double* y = scal + (int64_t)sg.prob * S_LEN + S_Y;
     for (int j = threadIdx.x; j < k && j < 128; j += blockDim.x) ys[j] = y[j];
@@ -552,10 +589,10 @@ k_lz_ritz(const LzSeg* __restrict__ bt, const int* __restrict__ active, const do
 
 // dst = src / |src| per problem (|src|^2 from the partials of its blocks)
 __global__ void __launch_bounds__(LZ_THREADS)
-k_lz_normalize(const LzSeg* __restrict__ bt, const int* __restrict__ active, const double* __restrict__ partial,
+k_lz_normalize(const LzSeg* __restrict__ bt, const double* __restrict__ partial,
                int NB, const double* __restrict__ src, double* __restrict__ dst) {
     const LzSeg sg = bt[blockIdx.x];
-    if (!active[sg.prob]) return;
+    if (!sg.act) return;
     __shared__ double v[1];
     reduce_rows(partial, 1, NB, sg.pb0, sg.pb1, v);
     const double inv = v[0] > 0.0 ? 1.0 / sqrt(v[0]) : 0.0;
@@ -564,21 +601,21 @@ k_lz_normalize(const LzSeg* __restrict__ bt, const int* __restrict__ active, con
 
 hipError_t launch_lz_ritz(const LzSet& z, const double* Q, int k, double* x, hipStream_t s) {
     if (k > 128) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_lz_ritz, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, z.active, Q, z.ntot, k, z.scal, x,
+    hipLaunchKernelGGL(k_lz_ritz, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, Q, z.ntot, k, z.scal, x,
                        z.partial, z.NB);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lz_normalize, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, z.active, z.partial, z.NB,
+    hipLaunchKernelGGL(k_lz_normalize, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, z.partial, z.NB,
                        (const double*)x, x);
     return hipGetLastError();
 }
 
 // x = v / |v| per problem (start vectors)
 hipError_t launch_lz_normalize_into(const LzSet& z, const double* v, double* x, hipStream_t s) {
-    hipLaunchKernelGGL(k_lz_dot1, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, z.active, v, v, z.partial, z.NB);
+    hipLaunchKernelGGL(k_lz_dot1, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, v, v, z.partial, z.NB);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lz_normalize, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, z.active, z.partial, z.NB, v, x);
+    hipLaunchKernelGGL(k_lz_normalize, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, z.partial, z.NB, v, x);
     return hipGetLastError();
 }
 
@@ -592,7 +629,7 @@ k_lz_norms(const int2* __restrict__ prange, const double* __restrict__ partial, 
 }
 
 hipError_t launch_lz_norms(const LzSet& z, const double* v, hipStream_t s) {
-    hipLaunchKernelGGL(k_lz_dot1, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, z.active, v, v, z.partial, z.NB);
+    hipLaunchKernelGGL(k_lz_dot1, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, v, v, z.partial, z.NB);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_lz_norms, dim3(z.nprob), dim3(LZ_THREADS), 0, s, z.prange, z.partial, z.NB, z.res);
@@ -601,10 +638,10 @@ hipError_t launch_lz_norms(const LzSet& z, const double* v, hipStream_t s) {
 
 // q_1 = r / beta_1 of each problem; lo = cast(q_1)
 __global__ void __launch_bounds__(LZ_THREADS)
-k_lz_first(const LzSeg* __restrict__ bt, const int* __restrict__ active, const double* __restrict__ w,
+k_lz_first(const LzSeg* __restrict__ bt, const double* __restrict__ w,
            const double* __restrict__ scal, double* __restrict__ q1, void* __restrict__ lo, int lo_prec) {
     const LzSeg sg = bt[blockIdx.x];
-    if (!active[sg.prob]) return;
+    if (!sg.act) return;
     const double b = scal[(int64_t)sg.prob * S_LEN + S_BETA + 1];
     const double inv = b > 0.0 ? 1.0 / b : 0.0;
     for (int64_t e = sg.lo + threadIdx.x; e < sg.hi; e += blockDim.x) {
@@ -643,19 +680,19 @@ hipError_t launch_seeded_normal(double* x, int64_t n, uint64_t seed, hipStream_t
 
 // copy of the active problems' segments
 __global__ void __launch_bounds__(LZ_THREADS)
-k_lz_copy(const LzSeg* __restrict__ bt, const int* __restrict__ active, const double* __restrict__ x,
+k_lz_copy(const LzSeg* __restrict__ bt, const double* __restrict__ x,
           double* __restrict__ y) {
     const LzSeg sg = bt[blockIdx.x];
-    if (!active[sg.prob]) return;
+    if (!sg.act) return;
     for (int64_t e = sg.lo + threadIdx.x; e < sg.hi; e += blockDim.x) y[e] = x[e];
 }
 
 hipError_t launch_lz_first(const LzSet& z, const double* x, const double* w, double* Q, void* lo, int lo_prec,
                            hipStream_t s) {
-    hipLaunchKernelGGL(k_lz_copy, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, z.active, x, Q);
+    hipLaunchKernelGGL(k_lz_copy, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, x, Q);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lz_first, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, z.active, w, z.scal, Q + z.ntot, lo,
+    hipLaunchKernelGGL(k_lz_first, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, w, z.scal, Q + z.ntot, lo,
                        lo ? lo_prec : -1);
     return hipGetLastError();
 }

@@ -74,6 +74,7 @@ d2d_status ensure_lanczos_work(d2d_ctx* c, LanczosWork*& lw, const std::vector<i
         for (int b = 0; b < nb; ++b) {
             LzSeg sg{};
             sg.prob = p;
+            sg.act = 1;
             sg.pb0 = b0;
             sg.pb1 = b0 + nb;
             sg.lo = off + std::min<int64_t>((int64_t)b * per, len[p]);
@@ -84,6 +85,7 @@ d2d_status ensure_lanczos_work(d2d_ctx* c, LanczosWork*& lw, const std::vector<i
         off += len[p];
     }
     w->NB = (int)bt.size();
+    w->h_bt = bt;
     w->seg_off.resize(w->nprob);
     w->seg_len = len;
     off = 0;
@@ -113,6 +115,14 @@ d2d_status ensure_lanczos_work(d2d_ctx* c, LanczosWork*& lw, const std::vector<i
 }  // namespace d2d
 
 namespace {
+
+// active flags per problem, and the same flags in every block-table entry
+d2d_status set_active_flags(LanczosWork* w, const std::vector<int>& act) {
+    for (auto& sg : w->h_bt) sg.act = act[sg.prob] ? 1 : 0;
+    D2D_HIP(hipMemcpy(w->active, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice));
+    D2D_HIP(hipMemcpy(w->bt, w->h_bt.data(), w->h_bt.size() * sizeof(LzSeg), hipMemcpyHostToDevice));
+    return D2D_OK;
+}
 
 LzSet set_of(LanczosWork* w) {
     LzSet z{};
@@ -154,7 +164,6 @@ d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bo
         else D2D_CHECK(hv.hv(prec, hin, hout, s));
         LzStepArgs a{};
         a.bt = z.bt;
-        a.active = z.active;
         // projection against q_{i-nq+1} .. q_i (all of them for full reorthogonalisation)
         const int nq = window >= 2 ? std::min(i + 1, window) : i + 1;
         a.Q = w->Q + (int64_t)(i + 1 - nq) * N;
@@ -164,8 +173,8 @@ d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bo
         a.upcast = prec != D2D_FP64;
         a.w32 = w->wlo;
         a.w = w->W;
-        a.wp1 = parts.w1;
-        a.wp2 = parts.w2;
+        for (int q = 0; q < 3; ++q) a.wpart[q] = parts.x[q];
+        a.wpart[3] = parts.central;
         a.partial = z.partial;
         a.partial2 = z.partial2;
         a.NB = z.NB;
@@ -258,7 +267,7 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
     drop_graphs(w);
     const LzSet z = set_of(w);
     std::vector<int> act(np, 1);
-    D2D_HIP(hipMemcpy(w->active, act.data(), np * sizeof(int), hipMemcpyHostToDevice));
+    D2D_CHECK(set_active_flags(w, act));
     D2D_CHECK(hv.set_active(act, nullptr));
     const int64_t cnt0[3] = {hv.counter(0), hv.counter(1), hv.counter(2)};
     for (int p = 0; p < np; ++p) {
@@ -343,7 +352,7 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
             std::vector<int> a(np);
             for (int p = 0; p < np; ++p) a[p] = done[p] ? 0 : 1;
             D2D_HIP(hipStreamSynchronize(s));
-            D2D_HIP(hipMemcpy(w->active, a.data(), np * sizeof(int), hipMemcpyHostToDevice));
+            D2D_CHECK(set_active_flags(w, a));
             bool rebuilt = false;
             D2D_CHECK(hv.set_active(a, &rebuilt));
             if (rebuilt) drop_graphs(w);
@@ -388,7 +397,7 @@ struct SbHv : HvOps {
     }
     d2d_status hv_fused(int prec, const void* v, void* w, hipStream_t s, HvParts* parts) override {
         if (!sb->fuse[prec]) {
-            parts->w1 = parts->w2 = nullptr;
+            *parts = HvParts{};
             return sb_hv_nocount(sb, prec, v, w, s);
         }
         return sb_hv_parts(sb, prec, v, w, s, nullptr, parts);
@@ -397,8 +406,7 @@ struct SbHv : HvOps {
         WorkItem* d;
         int n;
         const int shape = sb->tile_sel[prec] >= 0 ? sb->tile_sel[prec] : sb_auto_tile(sb, prec);
-        if (sb->split[prec] && !sb->d_w1) D2D_CHECK(sb->ctx->alloc(&sb->d_w1, (size_t)sb->N * 8));
-        if (!sb->d_w2) D2D_CHECK(sb->ctx->alloc(&sb->d_w2, (size_t)sb->N * 8));
+        D2D_CHECK(sb_ensure_parts(sb, sb->split[prec], true));
         return sb_work(sb, shape, sb->split[prec], &d, &n);
     }
     d2d_status set_active(const std::vector<int>&, bool* rebuilt) override {

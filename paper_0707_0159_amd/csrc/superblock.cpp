@@ -105,8 +105,10 @@ d2d_sb::~d2d_sb() {
         if (HR[p]) ctx->free(HR[p], hrs[p]);
         HL[p] = HR[p] = nullptr;
     }
-    if (d_w1) ctx->free(d_w1, (size_t)N * 8);
-    d_w1 = nullptr;
+    for (int i = 0; i < 3; ++i) {
+        if (d_x[i]) ctx->free(d_x[i], (size_t)N * 8);
+        d_x[i] = nullptr;
+    }
     if (d_w2) ctx->free(d_w2, (size_t)N * 8);
     d_w2 = nullptr;
     release(ctx, d_vp, (size_t)vp_len);
@@ -183,11 +185,18 @@ void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep
         if (keep && !(*keep)[p]) continue;
         const int dL = pairs[p].dL, dR = pairs[p].dR;
         const int tm = (dL + ts.BM - 1) / ts.BM, tn = (dR + ts.BN - 1) / ts.BN;
+        const int hL = (dL + 1) / 2, hR = (dR + 1) / 2;
         for (int j = 0; j < tn; ++j)
             for (int i = 0; i < tm; ++i) {
-                if (split) {
-                    w.push_back({dL, {(int32_t)p, i, j, 1}});
-                    w.push_back({dR, {(int32_t)p, i, j, 2}});
+                if (split == 2) {
+                    // slots: W (H_l V, 1st half), X0 (2nd half), X1 (V H_r^T, 1st half), X2 (2nd half)
+                    w.push_back({hL, {(int32_t)p, i, j, 1 | (0 << 2) | (1 << 4) | (0 << 5)}});
+                    w.push_back({dL - hL, {(int32_t)p, i, j, 1 | (1 << 2) | (1 << 4) | (1 << 5)}});
+                    w.push_back({hR, {(int32_t)p, i, j, 2 | (2 << 2) | (1 << 4) | (0 << 5)}});
+                    w.push_back({dR - hR, {(int32_t)p, i, j, 2 | (3 << 2) | (1 << 4) | (1 << 5)}});
+                } else if (split == 1) {
+                    w.push_back({dL, {(int32_t)p, i, j, 1 | (0 << 2)}});
+                    w.push_back({dR, {(int32_t)p, i, j, 2 | (1 << 2)}});
                 } else {
                     w.push_back({dL + dR, {(int32_t)p, i, j, 0}});
                 }
@@ -202,7 +211,7 @@ void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep
 }
 
 d2d_status sb_work(d2d_sb* sb, int shape, int split, WorkItem** out, int* nwork) {
-    const int key = shape | (split ? D2D_TILE_SPLIT : 0);
+    const int key = shape | (split << 16);
     auto it = sb->work.find(key);
     if (it != sb->work.end()) {
         *out = it->second.first;
@@ -221,10 +230,10 @@ d2d_status sb_work(d2d_sb* sb, int shape, int split, WorkItem** out, int* nwork)
 
 d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkItem* work, int nwork, const void* v,
                      void* w, hipStream_t s, hipEvent_t mid) {
-    // a split work list (passed together with a scratch w1) writes the second
-    // K-loop into w1; the central term adds it, or, fused, leaves it to the consumer
-    const bool split = t.w1 != nullptr;
-    HvGemmArgs g{work, nwork, t.sec, t.HL[prec], t.HR[prec], v, w, split ? t.w1 : nullptr, nullptr};
+    // a split work list (passed together with its partial outputs x) writes
+    // shares of the K-loops there; the central term adds them, or, fused,
+    // leaves them to the consumer
+    HvGemmArgs g{work, nwork, t.sec, t.HL[prec], t.HR[prec], v, w, {t.x[0], t.x[1], t.x[2]}, nullptr};
     CentralArgs c{};
     c.tiles = t.ctiles;
     c.ntiles = t.n_ctiles;
@@ -240,11 +249,10 @@ d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkItem* wor
     c.V = v;   // the unpadded input in every precision
     if (t.w2) {
         c.W = t.w2;
-        c.W1 = nullptr;
         g.fuse = &c;
     } else {
         c.W = w;
-        c.W1 = split ? t.w1 : nullptr;
+        for (int i = 0; i < 3; ++i) c.X[i] = t.x[i];
     }
     if (prec == D2D_BF16) {
         D2D_HIP(launch_pack_bf16(t.ptiles, t.n_ptiles, t.sec, (const bf16_t*)v, t.vp, t.vt, s));
@@ -287,6 +295,13 @@ static HvTables tables_of(d2d_sb* sb) {
     return t;
 }
 
+d2d_status sb_ensure_parts(d2d_sb* sb, int split, bool central) {
+    for (int i = 0; i < split_parts(split); ++i)
+        if (!sb->d_x[i]) D2D_CHECK(sb->ctx->alloc(&sb->d_x[i], (size_t)sb->N * 8));
+    if (central && !sb->d_w2) D2D_CHECK(sb->ctx->alloc(&sb->d_w2, (size_t)sb->N * 8));
+    return D2D_OK;
+}
+
 d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s, hipEvent_t mid,
                        HvParts* parts) {
     if (prec < 0 || prec > 2 || !(sb->prec_mask & (1u << prec)) || !sb->HL[prec]) {
@@ -299,15 +314,12 @@ d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t
     int nwork = 0;
     D2D_CHECK(sb_work(sb, shape, split, &work, &nwork));
     HvTables t = tables_of(sb);
-    if (split) {
-        if (!sb->d_w1) D2D_CHECK(sb->ctx->alloc(&sb->d_w1, (size_t)sb->N * 8));
-        t.w1 = sb->d_w1;
-    }
+    D2D_CHECK(sb_ensure_parts(sb, split, parts != nullptr));
+    for (int i = 0; i < split_parts(split); ++i) t.x[i] = sb->d_x[i];
     if (parts) {
-        if (!sb->d_w2) D2D_CHECK(sb->ctx->alloc(&sb->d_w2, (size_t)sb->N * 8));
         t.w2 = sb->d_w2;
-        parts->w1 = t.w1;
-        parts->w2 = t.w2;
+        for (int i = 0; i < 3; ++i) parts->x[i] = t.x[i];
+        parts->central = t.w2;
     }
     return hv_launch(t, prec, shape, work, nwork, v, w, s, mid);
 }
@@ -731,11 +743,12 @@ extern "C" d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile) {
         set_error("d2d_sb_set_tile: bad argument");
         return D2D_EINVAL;
     }
-    const int split = tile >= 0 && (tile & D2D_TILE_SPLIT) ? 1 : 0;
+    const int split = tile < 0 ? 0 : ((tile & D2D_TILE_SPLIT4) ? 2 : ((tile & D2D_TILE_SPLIT) ? 1 : 0));
     const int fused = tile >= 0 ? ((tile & D2D_TILE_FUSED) ? 1 : 0) : (prec != D2D_FP64 ? 1 : 0);
     const int shape = tile < 0 ? -1 : (tile & 0xFFFF);
     if (shape >= tile_shape_count() || (shape >= 0 && tile_shape(shape).prec != prec) ||
-        (tile >= 0 && (tile & ~(0xFFFF | D2D_TILE_SPLIT | D2D_TILE_FUSED)))) {
+        (tile >= 0 && (tile & ~(0xFFFF | D2D_TILE_SPLIT | D2D_TILE_SPLIT4 | D2D_TILE_FUSED))) ||
+        (tile >= 0 && (tile & D2D_TILE_SPLIT) && (tile & D2D_TILE_SPLIT4))) {
         set_error("d2d_sb_set_tile: tile %d is not a shape of precision %d", tile, prec);
         return D2D_EINVAL;
     }
@@ -840,7 +853,7 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
                 const int sh = t & 0xFFFF;
                 if (k == key && t >= 0 && sh < tile_shape_count() && tile_shape(sh).prec == prec) {
                     sb->tile_sel[prec] = sh;
-                    sb->split[prec] = (t & D2D_TILE_SPLIT) ? 1 : 0;
+                    sb->split[prec] = (t & D2D_TILE_SPLIT4) ? 2 : ((t & D2D_TILE_SPLIT) ? 1 : 0);
                     sb->fuse[prec] = (t & D2D_TILE_FUSED) ? 1 : 0;
                     *best_tile = t;
                     *best_ms = ms;
@@ -872,8 +885,8 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
         st = D2D_EDEVICE;
     }
     const int nsh = tile_shape_count();
-    for (int tt = 0; tt < 4 * nsh && st == D2D_OK; ++tt) {
-        const int t = tt % nsh, sp = (tt / nsh) & 1, fu = tt / (2 * nsh);
+    for (int tt = 0; tt < 6 * nsh && st == D2D_OK; ++tt) {
+        const int t = tt % nsh, sp = (tt / nsh) % 3, fu = tt / (3 * nsh);
         if (tile_shape(t).prec != prec) continue;
         sb->tile_sel[prec] = t;
         sb->split[prec] = sp;
@@ -889,7 +902,7 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
             st = D2D_EDEVICE;
         if (st == D2D_OK && ms / reps < bms) {
             bms = ms / reps;
-            best = t | (sp ? D2D_TILE_SPLIT : 0) | (fu ? D2D_TILE_FUSED : 0);
+            best = t | (sp == 1 ? D2D_TILE_SPLIT : 0) | (sp == 2 ? D2D_TILE_SPLIT4 : 0) | (fu ? D2D_TILE_FUSED : 0);
         }
     }
     if (e0) (void)hipEventDestroy(e0);
@@ -907,7 +920,7 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
         return st;
     }
     sb->tile_sel[prec] = best & 0xFFFF;
-    sb->split[prec] = (best & D2D_TILE_SPLIT) ? 1 : 0;
+    sb->split[prec] = (best & D2D_TILE_SPLIT4) ? 2 : ((best & D2D_TILE_SPLIT) ? 1 : 0);
     sb->fuse[prec] = (best & D2D_TILE_FUSED) ? 1 : 0;
     *best_tile = best;
     *best_ms = bms;

@@ -65,12 +65,18 @@ def test_config2_energy(ctx, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_fused_central_is_bitwise_separate(ctx, prec):
+@pytest.mark.parametrize("split", [0, 1, 2])
+def test_fused_central_is_bitwise_separate(ctx, prec, split):
     """One launch for GEMM + central term (parts added by the first step kernel)
     gives the same iterates bit for bit as the central term launched after the
-    GEMM: same energies, restart logs and Ritz vector."""
+    GEMM: same energies, restart logs and Ritz vector; for unsplit, split and
+    halved K-loops."""
+    from paper_0707_0159_amd import d2d
     wl = W.CONFIGS[2]
     prob = GpuProblem(ctx, wl, prec_mask=7)
+    shape = next(i for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == prec)
+    flag = [0, d2d.D2D_TILE_SPLIT, d2d.D2D_TILE_SPLIT4][split]
+    d2d.d2d_sb_set_tile(prob.sb, prec, shape | flag | d2d.D2D_TILE_FUSED)
     out = [run(ctx, prob, prec, wl.seed, window=3, tol=1e-8, separate=sep) for sep in (0, 1)]
     (s0, e0, st0, p0), (s1, e1, st1, p1) = out
     assert s0 == 0 and s1 == 0
