@@ -293,7 +293,8 @@ def main():
         tuned[name] = {"tile": t & 0xFFFF,
                        "split_k_loops": "halves" if t & d2d.D2D_TILE_SPLIT4 else bool(t & d2d.D2D_TILE_SPLIT),
                        "central_in_gemm_launch": bool(t & d2d.D2D_TILE_FUSED),
-                       "BMxBNxBK": "x".join(str(x) for x in shapes[t & 0xFFFF][1:]), "ms": ms_t}
+                       "BMxBNxBK": "x".join(str(x) for x in shapes[t & 0xFFFF][1:4]),
+                       "prefetch_depth": shapes[t & 0xFFFF][4], "ms": ms_t}
     with torch.cuda.stream(s):
         v0 = torch.as_tensor(W.random_vector(N, wl.seed), device="cuda")
         psi = torch.zeros_like(v0)

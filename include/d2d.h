@@ -236,8 +236,9 @@ d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile);
  * dimensions) and appended after a measurement.  Synchronous. */
 d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_tile, double* best_ms);
 
-/* Number of tile shapes and, if desc != NULL, for each shape i: desc[4*i..] =
- * (precision, BM, BN, BK). */
+/* Number of tile shapes and, if desc != NULL, for each shape i: desc[5*i..] =
+ * (precision, BM, BN, BK, prefetch depth: K steps whose loads are in flight
+ * while a step's MFMAs run). */
 d2d_status d2d_tile_shapes(int* count, int* desc);
 
 /* ------------------------------------------------------------------ Lanczos

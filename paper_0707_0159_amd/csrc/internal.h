@@ -63,6 +63,7 @@ struct WorkItem {
 // Tile shapes built into the library.
 struct TileShape {
     int prec, BM, BN, BK;
+    int PF = 1;   // K steps whose loads are in flight during a step's MFMAs
 };
 int tile_shape_count();
 const TileShape& tile_shape(int i);

@@ -309,7 +309,9 @@ struct HvK {
     CentralK<T, T, T> cen;
 };
 
-template <typename T, int BM, int BN, int BK, int WGM, int WGN, bool CEN>
+// PF: K steps whose global loads are in flight while a step is computed (1 or
+// 2; two register sets for 2, the loop unrolled by two so the sets stay static).
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int PF, bool CEN>
 __global__ void __launch_bounds__(64 * WGM * WGN)
 k_hv_gemm(const HvK<T> g) {
     if constexpr (CEN) {
@@ -365,37 +367,33 @@ k_hv_gemm(const HvK<T> g) {
         int k_lo, k_hi;
         k_range<BK>(it, K, k_lo, k_hi);
 
-        auto gload = [&](int k0) {
+        auto gload = [&](int k0, T (&xa)[EA], T (&xb)[EB]) {
 #pragma unroll
             for (int e = 0; e < EA; ++e) {
                 const int idx = t + NT * e, i = idx % BM, k = idx / BM;
                 const int r = row0 + i, kk = k0 + k;
-                ra[e] = (r < dL && kk < K) ? A[r + kk * lda] : T(0);
+                xa[e] = (r < dL && kk < K) ? A[r + kk * lda] : T(0);
             }
 #pragma unroll
             for (int e = 0; e < EB; ++e) {
                 const int idx = t + NT * e, k = idx % BK, j = idx / BK;
                 const int c = col0 + j, kk = k0 + k;
-                rb[e] = (c < dR && kk < K) ? B[kk + c * ldb] : T(0);
+                xb[e] = (c < dR && kk < K) ? B[kk + c * ldb] : T(0);
             }
         };
-
-        if (k_lo < k_hi) gload(k_lo);
-        int buf = 0;
-#pragma unroll 1
-        for (int k0 = k_lo; k0 < k_hi; k0 += BK) {
+        auto stage = [&](const T (&xa)[EA], const T (&xb)[EB], int buf) {
 #pragma unroll
             for (int e = 0; e < EA; ++e) {
                 const int idx = t + NT * e;
-                As[buf][idx / BM][idx % BM] = ra[e];
+                As[buf][idx / BM][idx % BM] = xa[e];
             }
 #pragma unroll
             for (int e = 0; e < EB; ++e) {
                 const int idx = t + NT * e;
-                Bs[buf][idx / BK][idx % BK] = rb[e];
+                Bs[buf][idx / BK][idx % BK] = xb[e];
             }
-            __syncthreads();
-            if (k0 + BK < k_hi) gload(k0 + BK);
+        };
+        auto compute = [&](int buf) {
 #pragma unroll
             for (int kk = 0; kk < BK; kk += M::MK) {
                 T a[FM], b[FN];
@@ -410,7 +408,40 @@ k_hv_gemm(const HvK<T> g) {
 #pragma unroll
                     for (int j = 0; j < FN; ++j) acc[i][j] = M::op(b[j], a[i], acc[i][j]);
             }
-            buf ^= 1;
+        };
+
+        // LDS is double-buffered: a step stores into one buffer while the
+        // other was computed in the previous step, and the barrier after the
+        // stores orders both.
+        int buf = 0;
+        if constexpr (PF == 1) {
+            if (k_lo < k_hi) gload(k_lo, ra, rb);
+#pragma unroll 1
+            for (int k0 = k_lo; k0 < k_hi; k0 += BK) {
+                stage(ra, rb, buf);
+                __syncthreads();
+                if (k0 + BK < k_hi) gload(k0 + BK, ra, rb);
+                compute(buf);
+                buf ^= 1;
+            }
+        } else {
+            T ra1[EA], rb1[EB];
+            if (k_lo < k_hi) gload(k_lo, ra, rb);
+            if (k_lo + BK < k_hi) gload(k_lo + BK, ra1, rb1);
+#pragma unroll 1
+            for (int k0 = k_lo; k0 < k_hi; k0 += 2 * BK) {
+                stage(ra, rb, buf);
+                __syncthreads();
+                if (k0 + 2 * BK < k_hi) gload(k0 + 2 * BK, ra, rb);
+                compute(buf);
+                buf ^= 1;
+                if (k0 + BK >= k_hi) break;
+                stage(ra1, rb1, buf);
+                __syncthreads();
+                if (k0 + 3 * BK < k_hi) gload(k0 + 3 * BK, ra1, rb1);
+                compute(buf);
+                buf ^= 1;
+            }
         }
         __syncthreads();
     }
@@ -445,7 +476,7 @@ struct OutPtrs {
 };
 __device__ inline bf16_t f32_to_bf16_rne(float f);
 
-template <int BM, int BN, int BK, int WGM, int WGN, bool CEN>
+template <int BM, int BN, int BK, int WGM, int WGN, int PF, bool CEN>
 __global__ void __launch_bounds__(64 * WGM * WGN)
 k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __restrict__ sec,
                const bf16_t* __restrict__ HL, const bf16_t* __restrict__ HRt, const bf16_t* __restrict__ VP,
@@ -494,36 +525,33 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __
         int k_lo, k_hi;
         k_range<BK>(it, Kp, k_lo, k_hi);
 
-        auto gload = [&](int k0) {
+        auto gload = [&](int k0, uint4 (&xa)[EA], uint4 (&xb)[EB]) {
 #pragma unroll
             for (int e = 0; e < EA; ++e) {
                 const int idx = t + NT * e, r = idx / KV, kv = idx % KV;
                 const int gr = row0 + r, kk = k0 + 8 * kv;
-                ra[e] = (gr < dL && kk < Kp) ? *(const uint4*)(A + gr * ld + kk) : make_uint4(0, 0, 0, 0);
+                xa[e] = (gr < dL && kk < Kp) ? *(const uint4*)(A + gr * ld + kk) : make_uint4(0, 0, 0, 0);
             }
 #pragma unroll
             for (int e = 0; e < EB; ++e) {
                 const int idx = t + NT * e, c = idx / KV, kv = idx % KV;
                 const int gc = col0 + c, kk = k0 + 8 * kv;
-                rb[e] = (gc < dR && kk < Kp) ? *(const uint4*)(B + gc * ld + kk) : make_uint4(0, 0, 0, 0);
+                xb[e] = (gc < dR && kk < Kp) ? *(const uint4*)(B + gc * ld + kk) : make_uint4(0, 0, 0, 0);
             }
         };
-        if (k_lo < k_hi) gload(k_lo);
-        int buf = 0;
-#pragma unroll 1
-        for (int k0 = k_lo; k0 < k_hi; k0 += BK) {
+        auto stage = [&](const uint4 (&xa)[EA], const uint4 (&xb)[EB], int buf) {
 #pragma unroll
             for (int e = 0; e < EA; ++e) {
                 const int idx = t + NT * e;
-                *(uint4*)&As[buf][idx / KV][8 * (idx % KV)] = ra[e];
+                *(uint4*)&As[buf][idx / KV][8 * (idx % KV)] = xa[e];
             }
 #pragma unroll
             for (int e = 0; e < EB; ++e) {
                 const int idx = t + NT * e;
-                *(uint4*)&Bs[buf][idx / KV][8 * (idx % KV)] = rb[e];
+                *(uint4*)&Bs[buf][idx / KV][8 * (idx % KV)] = xb[e];
             }
-            __syncthreads();
-            if (k0 + BK < k_hi) gload(k0 + BK);
+        };
+        auto compute = [&](int buf) {
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 16) {
                 bf16x8 a[FM], b[FN];
@@ -539,7 +567,36 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __
                     for (int j = 0; j < FN; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[j], a[i], acc[i][j], 0, 0, 0);
             }
-            buf ^= 1;
+        };
+        int buf = 0;
+        if constexpr (PF == 1) {
+            if (k_lo < k_hi) gload(k_lo, ra, rb);
+#pragma unroll 1
+            for (int k0 = k_lo; k0 < k_hi; k0 += BK) {
+                stage(ra, rb, buf);
+                __syncthreads();
+                if (k0 + BK < k_hi) gload(k0 + BK, ra, rb);
+                compute(buf);
+                buf ^= 1;
+            }
+        } else {
+            uint4 ra1[EA], rb1[EB];
+            if (k_lo < k_hi) gload(k_lo, ra, rb);
+            if (k_lo + BK < k_hi) gload(k_lo + BK, ra1, rb1);
+#pragma unroll 1
+            for (int k0 = k_lo; k0 < k_hi; k0 += 2 * BK) {
+                stage(ra, rb, buf);
+                __syncthreads();
+                if (k0 + 2 * BK < k_hi) gload(k0 + 2 * BK, ra, rb);
+                compute(buf);
+                buf ^= 1;
+                if (k0 + BK >= k_hi) break;
+                stage(ra1, rb1, buf);
+                __syncthreads();
+                if (k0 + 3 * BK < k_hi) gload(k0 + 3 * BK, ra1, rb1);
+                compute(buf);
+                buf ^= 1;
+            }
         }
         __syncthreads();
     }
@@ -559,7 +616,7 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __
     }
 }
 
-template <int BM, int BN, int BK, int WGM, int WGN>
+template <int BM, int BN, int BK, int WGM, int WGN, int PF>
 static void gemm_bf16_launch(const HvGemmArgs& a, const void* VT, hipStream_t st) {
     constexpr int NW = WGM * WGN;
     const bf16_t* HL = (const bf16_t*)a.HL;
@@ -571,10 +628,10 @@ static void gemm_bf16_launch(const HvGemmArgs& a, const void* VT, hipStream_t st
     for (int i = 0; i < 3; ++i) out.X[i] = (float*)a.X[i];
     if (a.fuse) {
         const int extra = (a.fuse->ntiles + NW - 1) / NW;
-        hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, true>), dim3(a.nwork + extra), dim3(64 * NW), 0, st,
+        hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, PF, true>), dim3(a.nwork + extra), dim3(64 * NW), 0, st,
                            a.work, a.nwork, a.sec, HL, HR, VP, V2, out, central_args<bf16_t, float, float>(*a.fuse));
     } else {
-        hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, false>), dim3(a.nwork), dim3(64 * NW), 0, st, a.work,
+        hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, PF, false>), dim3(a.nwork), dim3(64 * NW), 0, st, a.work,
                            a.nwork, a.sec, HL, HR, VP, V2, out, CentralK<bf16_t, float, float>{});
     }
 }
@@ -583,10 +640,13 @@ hipError_t launch_hv_gemm_bf16(int shape, const HvGemmArgs& a, const void* VT, h
     if (a.nwork <= 0) return hipSuccess;
     if (a.fuse && a.fuse->K > KMAX) return hipErrorInvalidValue;
     switch (shape) {
-        case 14: gemm_bf16_launch<64, 64, 32, 2, 2>(a, VT, st); break;
-        case 15: gemm_bf16_launch<128, 128, 32, 2, 2>(a, VT, st); break;
-        case 16: gemm_bf16_launch<128, 128, 64, 2, 2>(a, VT, st); break;
-        case 17: gemm_bf16_launch<32, 32, 64, 1, 1>(a, VT, st); break;
+        case 14: gemm_bf16_launch<64, 64, 32, 2, 2, 1>(a, VT, st); break;
+        case 15: gemm_bf16_launch<128, 128, 32, 2, 2, 1>(a, VT, st); break;
+        case 16: gemm_bf16_launch<128, 128, 64, 2, 2, 1>(a, VT, st); break;
+        case 17: gemm_bf16_launch<32, 32, 64, 1, 1, 1>(a, VT, st); break;
+        case 25: gemm_bf16_launch<64, 64, 32, 2, 2, 2>(a, VT, st); break;
+        case 26: gemm_bf16_launch<32, 32, 64, 1, 1, 2>(a, VT, st); break;
+        case 27: gemm_bf16_launch<128, 128, 64, 2, 2, 2>(a, VT, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -709,12 +769,23 @@ static const TileShape kShapes[] = {
     {D2D_BF16, 128, 128, 32},  // 15: 4 waves of 64x64
     {D2D_BF16, 128, 128, 64},  // 16
     {D2D_BF16, 32, 32, 64},    // 17: 1 wave
+    // prefetch depth 2: the loads of the next two K steps in flight (latency-bound sectors)
+    {D2D_FP32, 64, 64, 32, 2},    // 18
+    {D2D_FP32, 64, 64, 16, 2},    // 19
+    {D2D_FP64, 32, 32, 32, 2},    // 20
+    {D2D_FP64, 32, 32, 16, 2},    // 21
+    {D2D_FP32, 32, 32, 16, 2},    // 22: 1 wave
+    {D2D_FP64, 64, 64, 16, 2},    // 23
+    {D2D_FP32, 128, 64, 16, 2},   // 24
+    {D2D_BF16, 64, 64, 32, 2},    // 25
+    {D2D_BF16, 32, 32, 64, 2},    // 26: 1 wave
+    {D2D_BF16, 128, 128, 64, 2},  // 27
 };
 
 int tile_shape_count() { return (int)(sizeof(kShapes) / sizeof(kShapes[0])); }
 const TileShape& tile_shape(int i) { return kShapes[i]; }
 
-template <typename T, int BM, int BN, int BK, int WGM, int WGN>
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int PF>
 static void gemm_launch(const HvGemmArgs& a, hipStream_t st) {
     constexpr int NW = WGM * WGN;
     HvK<T> g;
@@ -729,10 +800,10 @@ static void gemm_launch(const HvGemmArgs& a, hipStream_t st) {
     if (a.fuse) {
         g.cen = central_args<T, T, T>(*a.fuse);
         const int extra = (a.fuse->ntiles + NW - 1) / NW;
-        hipLaunchKernelGGL((k_hv_gemm<T, BM, BN, BK, WGM, WGN, true>), dim3(a.nwork + extra), dim3(64 * NW), 0, st, g);
+        hipLaunchKernelGGL((k_hv_gemm<T, BM, BN, BK, WGM, WGN, PF, true>), dim3(a.nwork + extra), dim3(64 * NW), 0, st, g);
     } else {
         g.cen = CentralK<T, T, T>{};
-        hipLaunchKernelGGL((k_hv_gemm<T, BM, BN, BK, WGM, WGN, false>), dim3(a.nwork), dim3(64 * NW), 0, st, g);
+        hipLaunchKernelGGL((k_hv_gemm<T, BM, BN, BK, WGM, WGN, PF, false>), dim3(a.nwork), dim3(64 * NW), 0, st, g);
     }
 }
 
@@ -740,20 +811,27 @@ hipError_t launch_hv_gemm(int shape, const HvGemmArgs& a, hipStream_t st) {
     if (a.nwork <= 0) return hipSuccess;
     if (a.fuse && a.fuse->K > KMAX) return hipErrorInvalidValue;
     switch (shape) {
-        case 0: gemm_launch<double, 32, 32, 16, 2, 2>(a, st); break;
-        case 1: gemm_launch<double, 64, 64, 16, 2, 2>(a, st); break;
-        case 2: gemm_launch<double, 128, 128, 16, 2, 2>(a, st); break;
-        case 3: gemm_launch<float, 32, 32, 16, 1, 1>(a, st); break;
-        case 4: gemm_launch<float, 64, 64, 16, 2, 2>(a, st); break;
-        case 5: gemm_launch<float, 128, 128, 16, 2, 2>(a, st); break;
-        case 6: gemm_launch<double, 64, 64, 32, 2, 2>(a, st); break;
-        case 7: gemm_launch<float, 64, 64, 32, 2, 2>(a, st); break;
-        case 8: gemm_launch<float, 128, 128, 32, 2, 2>(a, st); break;
-        case 9: gemm_launch<double, 128, 64, 16, 2, 2>(a, st); break;
-        case 10: gemm_launch<float, 128, 64, 16, 2, 2>(a, st); break;
-        case 11: gemm_launch<float, 64, 64, 64, 2, 2>(a, st); break;
-        case 12: gemm_launch<double, 32, 32, 32, 2, 2>(a, st); break;
-        case 13: gemm_launch<double, 64, 64, 64, 2, 2>(a, st); break;
+        case 0: gemm_launch<double, 32, 32, 16, 2, 2, 1>(a, st); break;
+        case 1: gemm_launch<double, 64, 64, 16, 2, 2, 1>(a, st); break;
+        case 2: gemm_launch<double, 128, 128, 16, 2, 2, 1>(a, st); break;
+        case 3: gemm_launch<float, 32, 32, 16, 1, 1, 1>(a, st); break;
+        case 4: gemm_launch<float, 64, 64, 16, 2, 2, 1>(a, st); break;
+        case 5: gemm_launch<float, 128, 128, 16, 2, 2, 1>(a, st); break;
+        case 6: gemm_launch<double, 64, 64, 32, 2, 2, 1>(a, st); break;
+        case 7: gemm_launch<float, 64, 64, 32, 2, 2, 1>(a, st); break;
+        case 8: gemm_launch<float, 128, 128, 32, 2, 2, 1>(a, st); break;
+        case 9: gemm_launch<double, 128, 64, 16, 2, 2, 1>(a, st); break;
+        case 10: gemm_launch<float, 128, 64, 16, 2, 2, 1>(a, st); break;
+        case 11: gemm_launch<float, 64, 64, 64, 2, 2, 1>(a, st); break;
+        case 12: gemm_launch<double, 32, 32, 32, 2, 2, 1>(a, st); break;
+        case 13: gemm_launch<double, 64, 64, 64, 2, 2, 1>(a, st); break;
+        case 18: gemm_launch<float, 64, 64, 32, 2, 2, 2>(a, st); break;
+        case 19: gemm_launch<float, 64, 64, 16, 2, 2, 2>(a, st); break;
+        case 20: gemm_launch<double, 32, 32, 32, 2, 2, 2>(a, st); break;
+        case 21: gemm_launch<double, 32, 32, 16, 2, 2, 2>(a, st); break;
+        case 22: gemm_launch<float, 32, 32, 16, 1, 1, 2>(a, st); break;
+        case 23: gemm_launch<double, 64, 64, 16, 2, 2, 2>(a, st); break;
+        case 24: gemm_launch<float, 128, 64, 16, 2, 2, 2>(a, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

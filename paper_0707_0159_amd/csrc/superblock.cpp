@@ -767,10 +767,11 @@ extern "C" d2d_status d2d_tile_shapes(int* count, int* desc) {
     if (desc)
         for (int i = 0; i < *count; ++i) {
             const TileShape& t = tile_shape(i);
-            desc[4 * i] = t.prec;
-            desc[4 * i + 1] = t.BM;
-            desc[4 * i + 2] = t.BN;
-            desc[4 * i + 3] = t.BK;
+            desc[5 * i] = t.prec;
+            desc[5 * i + 1] = t.BM;
+            desc[5 * i + 2] = t.BN;
+            desc[5 * i + 3] = t.BK;
+            desc[5 * i + 4] = t.PF;
         }
     return D2D_OK;
 }

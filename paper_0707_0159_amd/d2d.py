@@ -311,9 +311,9 @@ def d2d_sb_autotune(sb: int, prec: int, reps: int = 20):
 def d2d_tile_shapes():
     n = C.c_int()
     _check(load().d2d_tile_shapes(C.byref(n), None))
-    desc = (C.c_int * (4 * n.value))()
+    desc = (C.c_int * (5 * n.value))()
     _check(load().d2d_tile_shapes(C.byref(n), desc))
-    return [tuple(desc[4 * i:4 * i + 4]) for i in range(n.value)]
+    return [tuple(desc[5 * i:5 * i + 5]) for i in range(n.value)]
 
 
 def lanczos_opts(prec=D2D_FP64, k_in=24, max_restarts=200, tol_res=1e-9, escalate=0.5, use_graph=1,
