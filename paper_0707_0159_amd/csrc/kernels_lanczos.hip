@@ -31,36 +31,36 @@ static int ew_grid(int64_t n) {
 
 // ------------------------------------------------------------------ tridiagonal
 // Lowest eigenpair of the symmetric tridiagonal T (diagonal alpha[0..k-1],
-// off-diagonal beta[1..k-1]), one wave:
-//  - eigenvalue: Sturm-sequence bisection, each round splitting the bracket
-//    into 65 pieces evaluated by the 64 lanes (count of eigenvalues below x);
-//  - eigenvector: two steps of inverse iteration with (T - theta I), solved by
-//    Gaussian elimination with partial pivoting on lane 0 (k <= 128).
-__device__ int sturm_count(const double* a, const double* b, int k, double x) {
-    // number of eigenvalues < x
-    int cnt = 0;
-    double d = a[0] - x;
-    const double tiny = 1e-300;
-    if (d == 0.0) d = -tiny;
-    if (d < 0.0) ++cnt;
-    for (int i = 1; i < k; ++i) {
-        d = (a[i] - x) - b[i] * b[i] / d;
-        if (d == 0.0) d = -tiny;
-        if (d < 0.0) ++cnt;
-    }
-    return cnt;
+// off-diagonal beta[1..k-1]), k <= 128, one wave:
+//  - eigenvalue: Sturm-sequence multisection.  The count of eigenvalues below
+//    x is the number of sign changes of the leading principal minors
+//    p_i = (a_i - x) p_{i-1} - b_i^2 p_{i-2} (p_0 = 1): two multiply-adds
+//    per step and no division (one wave issues every instruction, so the
+//    instruction count is the cost); a zero minor counts as a change (as a
+//    zero pivot taken as slightly negative would); rescaled when large (a
+//    tiny pivot is always followed by a large one, so the minors do not
+//    underflow).  The 64 lanes split the bracket into 65 pieces per round.
+//  - eigenvector: twisted factorization (T - theta I = N_r D_r N_r^T, Dhillon
+//    and Parlett): the forward pivots D+ (lane 0) and backward pivots D-
+//    (lane 1) run in parallel; the twist index r minimises
+//    |D+_i + D-_i - (a_i - theta)|; from y_r = 1 the components below r
+//    (lane 0) and above r (lane 1) follow from the pivots, then the vector
+//    is normalised with y[0] >= 0.
+__device__ inline double sturm_pivot(double d) {
+    // a zero pivot is replaced by a tiny negative one (the count treats it as below)
+    return d == 0.0 ? -1e-290 : d;
 }
 
 __device__ void tridiag_body(const double* __restrict__ alpha, const double* __restrict__ beta, int k,
                              double* __restrict__ theta_out, double* __restrict__ y_out) {
-    __shared__ double a[128], b[128];
-    __shared__ double dl[128], d[128], du[128], du2[128], y[128];
-    __shared__ int piv[128];
-    __shared__ double lo_s, hi_s;
+    __shared__ double a[128], b[128], b2[128], dp[128], dm[128], y[128];
+    __shared__ double lo_s, hi_s, scale_s;
+    __shared__ int r_s;
     const int l = threadIdx.x;
     for (int i = l; i < k; i += 64) {
         a[i] = alpha[i];
         b[i] = i > 0 ? beta[i] : 0.0;
+        b2[i] = b[i] * b[i];
     }
     __syncthreads();
     if (l == 0) {
@@ -75,91 +75,130 @@ __device__ void tridiag_body(const double* __restrict__ alpha, const double* __r
         hi_s = hi + pad;
     }
     __syncthreads();
+    constexpr int P = 1;                     // points per lane
+    constexpr double NP1 = 64.0 * P + 1.0;   // pieces per round
     double plo = 0.0, phi = 0.0;
     for (int it = 0; it < 40; ++it) {
         const double lo = lo_s, hi = hi_s;
         if (hi - lo <= 4.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) || hi <= lo) break;
-        // a bracket of a few ulps can stop shrinking (the 65 points round onto its ends)
+        // a bracket of a few ulps can stop shrinking (the points round onto its ends)
         if (it > 0 && lo == plo && hi == phi) break;
         plo = lo;
         phi = hi;
-        const double x = lo + (hi - lo) * (double)(l + 1) / 65.0;
-        const int c = sturm_count(a, b, k, x);
-        // first lane whose point has at least one eigenvalue below it
-        const unsigned long long mask = __ballot(c >= 1);
+        double x[P], pm[P], pc[P];
+        int c[P];
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            x[u] = lo + (hi - lo) * (double)(P * l + u + 1) / NP1;
+            pm[u] = 1.0;
+            pc[u] = sturm_pivot(a[0] - x[u]);
+            c[u] = pc[u] < 0.0 ? 1 : 0;
+        }
+        for (int i = 1; i < k; ++i) {
+            const double ai = a[i], bi2 = b2[i];
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                double pn = (ai - x[u]) * pc[u] - bi2 * pm[u];
+                if (pn == 0.0) pn = pc[u] < 0.0 ? 1e-290 : -1e-290;
+                c[u] += (pn < 0.0) != (pc[u] < 0.0) ? 1 : 0;
+                pm[u] = pc[u];
+                pc[u] = pn;
+                if (fabs(pn) > 1e150) {
+                    pm[u] *= 1e-150;
+                    pc[u] *= 1e-150;
+                }
+            }
+        }
+        // smallest point index (over the wave) with at least one eigenvalue below it
+        int q = 1 << 30;
+#pragma unroll
+        for (int u = P - 1; u >= 0; --u)
+            if (c[u] >= 1) q = P * l + u;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) q = min(q, __shfl_xor(q, o, 64));
         __syncthreads();
         if (l == 0) {
-            if (mask == 0ull) {
-                lo_s = lo + (hi - lo) * 64.0 / 65.0;
+            if (q >= (1 << 30)) {
+                lo_s = lo + (hi - lo) * (NP1 - 1.0) / NP1;
             } else {
-                const int f = __ffsll((long long)mask) - 1;
-                hi_s = lo + (hi - lo) * (double)(f + 1) / 65.0;
-                if (f > 0) lo_s = lo + (hi - lo) * (double)f / 65.0;
+                hi_s = lo + (hi - lo) * (double)(q + 1) / NP1;
+                if (q > 0) lo_s = lo + (hi - lo) * (double)q / NP1;
             }
         }
         __syncthreads();
     }
-    // inverse iteration (T - theta I) z = y on lane 0, all in shared memory:
-    // LU with partial pivoting in the LAPACK dgttrf layout (dl, d, du, du2, piv)
+    const double th = 0.5 * (lo_s + hi_s);
+    if (l == 0) theta_out[0] = th;
+    // twisted factorization: pivots from both ends in parallel
     if (l == 0) {
-        const double th = 0.5 * (lo_s + hi_s);
-        theta_out[0] = th;
-        const double eps = 2.220446049250313e-16 * fmax(1.0, fabs(th));
-        for (int i = 0; i < k; ++i) {
-            d[i] = a[i] - th;
-            du[i] = i + 1 < k ? b[i + 1] : 0.0;
-            dl[i] = i + 1 < k ? b[i + 1] : 0.0;
-            du2[i] = 0.0;
+        double d = sturm_pivot(a[0] - th);
+        dp[0] = d;
+        for (int i = 1; i < k; ++i) {
+            d = sturm_pivot((a[i] - th) - b2[i] / d);
+            dp[i] = d;
         }
-        for (int i = 0; i < k - 1; ++i) {
-            if (fabs(d[i]) >= fabs(dl[i])) {
-                piv[i] = i;
-                const double piv_v = d[i] != 0.0 ? d[i] : eps;
-                d[i] = piv_v;
-                const double f = dl[i] / piv_v;
-                dl[i] = f;
-                d[i + 1] -= f * du[i];
-                du2[i] = 0.0;
-            } else {
-                piv[i] = i + 1;
-                const double f = d[i] / dl[i];
-                d[i] = dl[i];
-                dl[i] = f;
-                const double tmp = du[i];
-                du[i] = d[i + 1];
-                d[i + 1] = tmp - f * d[i + 1];
-                if (i + 1 < k - 1) {
-                    du2[i] = du[i + 1];
-                    du[i + 1] = -f * du[i + 1];
-                }
-            }
+    } else if (l == 1) {
+        double d = sturm_pivot(a[k - 1] - th);
+        dm[k - 1] = d;
+        for (int i = k - 2; i >= 0; --i) {
+            d = sturm_pivot((a[i] - th) - b2[i + 1] / d);
+            dm[i] = d;
         }
-        if (d[k - 1] == 0.0) d[k - 1] = eps;
-        for (int i = 0; i < k; ++i) y[i] = 1.0 / sqrt((double)k);
-        for (int rep = 0; rep < 3; ++rep) {
-            // solve L U z = y (forward with pivots, then back substitution)
-            for (int i = 0; i < k - 1; ++i) {
-                if (piv[i] == i) {
-                    y[i + 1] -= dl[i] * y[i];
-                } else {
-                    const double t = y[i];
-                    y[i] = y[i + 1];
-                    y[i + 1] = t - dl[i] * y[i];
-                }
-            }
-            y[k - 1] /= d[k - 1];
-            if (k > 1) y[k - 2] = (y[k - 2] - du[k - 2] * y[k - 1]) / d[k - 2];
-            for (int i = k - 3; i >= 0; --i) y[i] = (y[i] - du[i] * y[i + 1] - du2[i] * y[i + 2]) / d[i];
-            double nrm = 0.0;
-            for (int i = 0; i < k; ++i) nrm += y[i] * y[i];
-            nrm = sqrt(nrm);
-            for (int i = 0; i < k; ++i) y[i] /= nrm;
-        }
-        if (y[0] < 0.0)
-            for (int i = 0; i < k; ++i) y[i] = -y[i];
     }
     __syncthreads();
-    for (int i = l; i < k; i += 64) y_out[i] = y[i];
+    {
+        // twist index: argmin |gamma_i|, ties to the smallest i
+        double best = 1e308;
+        int bi = 0;
+        for (int i = l; i < k; i += 64) {
+            const double g = fabs(dp[i] + dm[i] - (a[i] - th));
+            if (g < best) {
+                best = g;
+                bi = i;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o, 64);
+            const int oi = __shfl_xor(bi, o, 64);
+            if (ob < best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+            }
+        }
+        if (l == 0) r_s = bi;
+    }
+    __syncthreads();
+    const int r = r_s;
+    if (l == 0) {
+        double v = 1.0;
+        y[r] = 1.0;
+        for (int i = r - 1; i >= 0; --i) {
+            v = -b[i + 1] * v / dp[i];
+            y[i] = v;
+        }
+    } else if (l == 1) {
+        double v = 1.0;
+        for (int i = r + 1; i < k; ++i) {
+            v = -b[i] * v / dm[i];
+            y[i] = v;
+        }
+    }
+    __syncthreads();
+    // normalise: scale by the largest modulus first (the recurrences can grow large)
+    double mx = 0.0;
+    for (int i = l; i < k; i += 64) mx = fmax(mx, fabs(y[i]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    double ss = 0.0;
+    for (int i = l; i < k; i += 64) {
+        const double t = y[i] / mx;
+        ss += t * t;
+    }
+    ss = wave_sum(ss);
+    if (l == 0) scale_s = (y[0] < 0.0 ? -1.0 : 1.0) / (mx * sqrt(ss));   // lane 0 holds the sum
+    __syncthreads();
+    for (int i = l; i < k; i += 64) y_out[i] = y[i] * scale_s;
 }
 
 // ------------------------------------------------------------------ density matrix helpers
