@@ -282,6 +282,10 @@ typedef struct {
                             as a launch of its own.  Same result bit for bit  */
     double tol_rel_e;    /* energy-change stop (0: off)                         */
     uint64_t seed;       /* seed of the start vector when v0 is NULL            */
+    int plain_cgs2;      /* 0: with a window of 2..4 each step is two kernels: the
+                            second Gram-Schmidt pass and the norm follow from the
+                            first pass's sums and the window's Gram matrix;
+                            1: always two explicit passes (three kernels)     */
 } d2d_lanczos_opts;
 
 #define D2D_LOG_MAX 256

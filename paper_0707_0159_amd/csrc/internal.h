@@ -193,6 +193,7 @@ struct LzStepArgs {
     int64_t ldq;
     int nq, i;
     bool upcast;
+    bool gram;              // two-kernel Gram form of the step (nq <= 4)
     const float* w32;
     double* w;
     // parts of a fused Hv: the product is (((w32 or w) + P0) + P1) + P2 + P3

@@ -279,11 +279,41 @@ int lz_step_blocks(int64_t n) {
 // LZ_STEP_NB / 64 partials of a row; all of them are loaded at once (index
 // clamped into the problem's range, the extra values masked afterwards), so
 // the sum costs one memory latency, not one per partial.
+// When the problem has at most 512 blocks, a wave loads the partials of up to
+// four of its rows together (8 per lane and row) before adding any.
 __device__ inline void reduce_rows(const double* __restrict__ partial, int rows, int NB, int b0, int b1,
                                    double* out_sh) {
     constexpr int R = LZ_STEP_NB / 64;
+    constexpr int NW = LZ_THREADS / 64;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int j = wv; j < rows; j += LZ_THREADS / 64) {
+    if (b1 - b0 <= 512) {
+        constexpr int L = 8, MR = 4;
+        for (int j0 = wv; j0 < rows; j0 += NW * MR) {
+            double v[MR][L];
+#pragma unroll
+            for (int r = 0; r < MR; ++r) {
+                const int j = j0 + NW * r;
+#pragma unroll
+                for (int q = 0; q < L; ++q) {
+                    const int b = b0 + lane + 64 * q;
+                    v[r][q] = j < rows ? partial[(int64_t)j * NB + (b < b1 ? b : b0)] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < MR; ++r) {
+                const int j = j0 + NW * r;
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < L; ++q)
+                    if (b0 + lane + 64 * q < b1) s += v[r][q];
+                s = wave_sum(s);
+                if (lane == 0 && j < rows) out_sh[j] = s;
+            }
+        }
+        __syncthreads();
+        return;
+    }
+    for (int j = wv; j < rows; j += NW) {
         double v[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -513,6 +543,156 @@ k_lz_next(const LzSeg* __restrict__ bt, const double* __restrict__ Q,
     }
 }
 
+// ---- Gram form of the step for a short window (nq <= 4): two kernels.
+// The second classical Gram-Schmidt pass and the norm follow from the first
+// pass's sums and the window's Gram matrix G = Q^T Q, gathered in the same
+// read of the window: c2 = c1 - G c1, d = c1 + c2, and
+// |w - Q d|^2 = |w|^2 - 2 d.c1 + d^T G d.  Partial rows (fixed layout):
+// c1 in 0..NQ-1, |w|^2 in NQ, G_jl (j <= l) from NQ+1 on.
+template <int NQ>
+struct GramLayout {
+    static constexpr int NG = NQ * (NQ + 1) / 2;
+    static constexpr int ROWS = NQ + 1 + NG;
+    __host__ __device__ static constexpr int g(int j, int l) { return NQ + 1 + j * NQ - j * (j - 1) / 2 + (l - j); }
+};
+
+template <int NQ, bool UPCAST>
+__global__ void __launch_bounds__(LZ_THREADS)
+k_lz_dots_gram(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int64_t ldq, int nq,
+               const double* w64in, const float* __restrict__ w32, const HvPartPtrs P, double* w64out,
+               double* __restrict__ partial, int NB) {
+    using GL = GramLayout<NQ>;
+    constexpr int U = StepUnroll<NQ>::U;
+    const LzSeg sg = bt[blockIdx.x];
+    if (!sg.act) return;
+    const bool any = P.p[0] || P.p[1] || P.p[2] || P.p[3];
+    double acc[GL::ROWS];
+#pragma unroll
+    for (int j = 0; j < GL::ROWS; ++j) acc[j] = 0.0;
+    const int64_t st = blockDim.x;
+    using TW = typename std::conditional<UPCAST, float, double>::type;
+    const TW* win = UPCAST ? (const TW*)w32 : (const TW*)w64in;
+    for (int64_t e0 = sg.lo + threadIdx.x; e0 < sg.hi; e0 += U * st) {
+        double x[U], q[U][NQ];
+        TW wv[U], pv[4][U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = e0 + u * st;
+            const int64_t ec = e < sg.hi ? e : sg.lo;
+            wv[u] = win[ec];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) pv[i][u] = P.p[i] ? ((const TW*)P.p[i])[ec] : TW(0);
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? Q[j * ldq + ec] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = e0 + u * st;
+            const bool ok = e < sg.hi;
+            TW f = wv[u];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (P.p[i]) f = f + pv[i][u];
+            x[u] = ok ? (double)f : 0.0;
+            if ((UPCAST || any) && ok) w64out[e] = x[u];
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) q[u][j] = ok ? q[u][j] : 0.0;
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) acc[j] += q[u][j] * x[u];
+            acc[NQ] += x[u] * x[u];
+#pragma unroll
+            for (int j = 0; j < NQ; ++j)
+#pragma unroll
+                for (int l = j; l < NQ; ++l) acc[GL::g(j, l)] += q[u][j] * q[u][l];
+        }
+    }
+    write_partials<GL::ROWS>(acc, GL::ROWS, partial, NB, blockIdx.x);
+}
+
+// Second kernel: d, alpha_i = d[nq-1], beta = |w - Q d| from the sums;
+// q_next = (w - Q d) / beta and its low-precision copy.
+template <int NQ>
+__global__ void __launch_bounds__(LZ_THREADS)
+k_lz_update_gram(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int64_t ldq, int nq,
+                 const double* __restrict__ partial_in, int NB, const double* __restrict__ w,
+                 double* __restrict__ qnext, void* __restrict__ lo, int lo_prec, double* __restrict__ scal, int i) {
+    using GL = GramLayout<NQ>;
+    const LzSeg sg = bt[blockIdx.x];
+    if (!sg.act) return;
+    __shared__ double cs[GL::ROWS];
+    reduce_rows(partial_in, GL::ROWS, NB, sg.pb0, sg.pb1, cs);
+    double c1[NQ], d[NQ];
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) c1[j] = j < nq ? cs[j] : 0.0;
+    auto gram = [&](int j, int l) { return j <= l ? cs[GL::g(j, l)] : cs[GL::g(l, j)]; };
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+        double gc = 0.0;
+#pragma unroll
+        for (int l = 0; l < NQ; ++l) gc += gram(j, l) * c1[l];
+        d[j] = j < nq ? c1[j] + (c1[j] - gc) : 0.0;
+    }
+    double dc = 0.0, dgd = 0.0;
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+        dc += d[j] * c1[j];
+        double gd = 0.0;
+#pragma unroll
+        for (int l = 0; l < NQ; ++l) gd += gram(j, l) * d[l];
+        dgd += d[j] * gd;
+    }
+    const double b2 = cs[NQ] - 2.0 * dc + dgd;
+    const double bb = sqrt(b2 > 0.0 ? b2 : 0.0);
+    if ((int)blockIdx.x == sg.pb0 && threadIdx.x == 0) {
+        double* sc = scal + (int64_t)sg.prob * S_LEN;
+        sc[S_ALPHA + i] = d[nq - 1];
+        sc[S_BETA + i + 1] = bb;
+    }
+    if (!qnext) return;
+    const double inv = bb > 0.0 ? 1.0 / bb : 0.0;
+    const int64_t st = blockDim.x;
+    for (int64_t e0 = sg.lo + threadIdx.x; e0 < sg.hi; e0 += 4 * st) {
+        double x[4], q[4][NQ];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t e = e0 + u * st;
+            const int64_t ec = e < sg.hi ? e : sg.lo;
+            x[u] = w[ec];
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? Q[j * ldq + ec] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t e = e0 + u * st;
+            if (e >= sg.hi) break;
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) x[u] -= d[j] * q[u][j];
+            const double qv = x[u] * inv;
+            qnext[e] = qv;
+            if (lo_prec == D2D_FP32) ((float*)lo)[e] = (float)qv;
+            else if (lo_prec == D2D_BF16) ((uint16_t*)lo)[e] = f32_bf16_rne((float)qv);
+        }
+    }
+}
+
+static hipError_t lz_step_gram(const LzStepArgs& a, hipStream_t s) {
+    constexpr int NQ = 4;
+    const int NB = a.NB;
+    HvPartPtrs P;
+    for (int i = 0; i < 4; ++i) P.p[i] = a.wpart[i];
+    if (a.upcast)
+        hipLaunchKernelGGL((k_lz_dots_gram<NQ, true>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq,
+                           (const double*)nullptr, a.w32, P, a.w, a.partial, NB);
+    else
+        hipLaunchKernelGGL((k_lz_dots_gram<NQ, false>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq,
+                           a.w, (const float*)nullptr, P, a.w, a.partial, NB);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_lz_update_gram<NQ>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq, a.partial,
+                       NB, a.w, a.qnext, a.lo, a.lo ? a.lo_prec : -1, a.scal, a.i);
+    return hipGetLastError();
+}
+
 template <int NQ>
 static hipError_t lz_step_nq(const LzStepArgs& a, hipStream_t s) {
     const int NB = a.NB;
@@ -536,6 +716,7 @@ static hipError_t lz_step_nq(const LzStepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_lz_step(const LzStepArgs& a, hipStream_t s) {
+    if (a.gram && a.nq <= 4) return lz_step_gram(a, s);
     if (a.nq <= 4) return lz_step_nq<4>(a, s);
     if (a.nq <= 8) return lz_step_nq<8>(a, s);
     if (a.nq <= 16) return lz_step_nq<16>(a, s);

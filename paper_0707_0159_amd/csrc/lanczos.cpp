@@ -149,7 +149,8 @@ d2d_status residual_step(LanczosWork* w, HvOps& hv, hipStream_t s) {
 }
 
 // One inner Lanczos of k vectors from X (after residual_step); X <- Ritz vector.
-d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool fused, hipStream_t s) {
+d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool fused, bool plain_cgs2,
+                      hipStream_t s) {
     const LzSet z = set_of(w);
     const int64_t N = w->ntot;
     void* lo = prec == D2D_FP64 ? nullptr : (void*)w->vlo;
@@ -171,6 +172,7 @@ d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bo
         a.nq = nq;
         a.i = i;
         a.upcast = prec != D2D_FP64;
+        a.gram = !plain_cgs2 && window >= 2 && window <= 4;
         a.w32 = w->wlo;
         a.w = w->W;
         for (int q = 0; q < 3; ++q) a.wpart[q] = parts.x[q];
@@ -198,10 +200,10 @@ void drop_graphs(LanczosWork* w) {
     }
 }
 
-d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool fused, bool use_graph,
-                   hipStream_t s) {
+d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool fused, bool plain_cgs2,
+                   bool use_graph, hipStream_t s) {
     if (!use_graph || s == nullptr) {
-        D2D_CHECK(inner_loop(w, hv, prec, k, window, fused, s));
+        D2D_CHECK(inner_loop(w, hv, prec, k, window, fused, plain_cgs2, s));
         D2D_CHECK(residual_step(w, hv, s));
         hv.count(prec, k - 1);
         hv.count(D2D_FP64, 1);
@@ -215,7 +217,7 @@ d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool 
         D2D_CHECK(hv.prepare(prec));          // launch tables exist before capture
         D2D_CHECK(hv.prepare(D2D_FP64));
         D2D_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        d2d_status st = inner_loop(w, hv, prec, k, window, fused, s);
+        d2d_status st = inner_loop(w, hv, prec, k, window, fused, plain_cgs2, s);
         if (st == D2D_OK) st = residual_step(w, hv, s);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s, &g);
@@ -244,9 +246,9 @@ namespace d2d {
 d2d_status check_lanczos_opts(const d2d_lanczos_opts* o) {
     if (!o || o->k_in < 2 || o->k_in > 33 || o->max_restarts < 0 || !(o->tol_res > 0.0) || o->prec < 0 ||
         o->prec > 2 || o->reorth_window < 0 || o->reorth_window == 1 || o->separate_central < 0 ||
-        o->separate_central > 1 || !(o->tol_rel_e >= 0.0)) {
+        o->separate_central > 1 || !(o->tol_rel_e >= 0.0) || o->plain_cgs2 < 0 || o->plain_cgs2 > 1) {
         set_error("Lanczos options: k_in 2..33, max_restarts >= 0, tol_res > 0, prec 0..2, reorth_window 0 or >= 2, "
-                  "separate_central 0 or 1, tol_rel_e >= 0");
+                  "separate_central 0 or 1, tol_rel_e >= 0, plain_cgs2 0 or 1");
         return D2D_EINVAL;
     }
     return D2D_OK;
@@ -357,7 +359,8 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
             D2D_CHECK(hv.set_active(a, &rebuilt));
             if (rebuilt) drop_graphs(w);
         }
-        D2D_CHECK(restart(w, hv, prec, k, opts->reorth_window, opts->separate_central == 0, opts->use_graph != 0, s));
+        D2D_CHECK(restart(w, hv, prec, k, opts->reorth_window, opts->separate_central == 0, opts->plain_cgs2 != 0,
+                          opts->use_graph != 0, s));
         D2D_HIP(hipStreamSynchronize(s));
         ++j;
         for (int p = 0; p < np; ++p) {

@@ -62,4 +62,5 @@ def test_lanczos_opts_layout():
     o = d2d.d2d_lanczos_opts
     assert o.tol_res.offset == 16 and o.escalate.offset == 24
     assert o.separate_central.offset == 40 and o.tol_rel_e.offset == 48 and o.seed.offset == 56
-    assert C.sizeof(o) == 64
+    assert o.plain_cgs2.offset == 64
+    assert C.sizeof(o) == 72

@@ -20,7 +20,7 @@ def ctx():
     d2d.d2d_ctx_destroy(c)
 
 
-def run(ctx, prob, prec, seed, k_in=24, graph=1, tol=1e-9, window=0, separate=0):
+def run(ctx, prob, prec, seed, k_in=24, graph=1, tol=1e-9, window=0, separate=0, plain=0):
     from paper_0707_0159_amd import d2d
     n = prob.info["n"]
     with torch.cuda.stream(ctx.stream):
@@ -28,7 +28,7 @@ def run(ctx, prob, prec, seed, k_in=24, graph=1, tol=1e-9, window=0, separate=0)
         psi = torch.zeros_like(v0)
     ctx.stream.synchronize()
     opts = d2d.lanczos_opts(prec=prec, k_in=k_in, max_restarts=300, tol_res=tol, use_graph=graph,
-                            reorth_window=window, separate_central=separate)
+                            reorth_window=window, separate_central=separate, plain_cgs2=plain)
     st, e, stats = d2d.d2d_lanczos(prob.sb, opts, v0, psi)
     ctx.stream.synchronize()
     return st, e, stats, psi.cpu().numpy()
@@ -52,12 +52,16 @@ def test_config1_energy(ctx, prec, graph):
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_config2_energy(ctx, prec):
+@pytest.mark.parametrize("window,plain", [(0, 0), (3, 0), (3, 1), (2, 0), (4, 0)])
+def test_config2_energy(ctx, prec, window, plain):
+    """Full reorthogonalisation, and windows of 2..4 in the two-kernel Gram form
+    and the three-kernel two-pass form."""
     wl = W.CONFIGS[2]
     prob = GpuProblem(ctx, wl, prec_mask=7)
-    st, e, stats, psi = run(ctx, prob, prec, wl.seed)
+    st, e, stats, psi = run(ctx, prob, prec, wl.seed, window=window, plain=plain)
     E0 = reference_energy(wl.name)
-    print("config2", prec, e, E0, (e - E0) / abs(E0), stats["restarts"], stats["hv_count"], stats["seconds"])
+    print("config2", prec, window, plain, e, E0, (e - E0) / abs(E0), stats["restarts"], stats["hv_count"],
+          stats["seconds"])
     assert st == 0
     assert abs(e - E0) <= 1e-10 * abs(E0)
     assert e >= E0 - 1e-10 * abs(E0)          # Rayleigh quotient is variational
