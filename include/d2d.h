@@ -197,10 +197,12 @@ d2d_status d2d_unpack(d2d_sb* sb, const double* packed, double* full);
  * bfloat16 (uint16 storage), w float.  v and w must not overlap. */
 d2d_status d2d_hv(d2d_sb* sb, int prec, const void* v, void* w);
 
-/* Kernel timing of Hv: runs `reps` products w = H v back to back on the
- * context stream with HIP events between the launches and returns the average
- * duration in milliseconds of the grouped-GEMM launch (ms_gemm) and of the
- * central-term launch (ms_central).  Synchronous. */
+/* Kernel timing of Hv on the context stream: after one product, `reps`
+ * grouped-GEMM launches back to back and then `reps` central-term launches
+ * back to back, each group between two HIP events; returns the average
+ * duration in milliseconds of one grouped-GEMM launch (ms_gemm; for BF16 the
+ * pack kernel that precedes it is not included) and of one central-term
+ * launch (ms_central).  A last product leaves w = H v.  Synchronous. */
 d2d_status d2d_hv_profile(d2d_sb* sb, int prec, const void* v, void* w, int reps, double* ms_gemm,
                           double* ms_central);
 

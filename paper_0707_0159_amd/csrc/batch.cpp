@@ -178,7 +178,7 @@ d2d_status batch_hv(d2d_batch* b, int prec, const void* v, void* w, hipStream_t 
         for (int i = 0; i < 3; ++i) parts->x[i] = t.x[i];
         parts->central = t.w2;
     }
-    return hv_launch(t, prec, shape, wl.first, wl.second, v, w, s, nullptr);
+    return hv_launch(t, prec, shape, wl.first, wl.second, v, w, s);
 }
 
 struct BatchHv : HvOps {

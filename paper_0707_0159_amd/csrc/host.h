@@ -131,9 +131,11 @@ struct HvTables {
     bf16_t* vp;
     bf16_t* vt;
 };
-// pack (BF16) + grouped GEMM + central term; `mid` (nullable) is recorded after the GEMM
+// stages of one Hv launch sequence (a whole product is all three)
+constexpr int HV_PACK = 1, HV_GEMM = 2, HV_CENTRAL = 4, HV_ALL = 7;
+// pack (BF16) + grouped GEMM + central term, the stages selected
 d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkItem* work, int nwork, const void* v,
-                     void* w, hipStream_t s, hipEvent_t mid);
+                     void* w, hipStream_t s, int stages = HV_ALL);
 
 // Output of a fused Hv left in parts: the product is
 // (((w + x0) + x1) + x2) + central, added in that order by the consumer (the
@@ -224,7 +226,7 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
                        double* const* psi, d2d_lanczos_stats* stats);
 // Hv of a superblock; with parts non-null the launch is fused and the result
 // is left in parts (see HvParts), else w holds the whole product.
-d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s, hipEvent_t mid,
+d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s, int stages = HV_ALL,
                        HvParts* parts = nullptr);
 // partial outputs of a split level (and the central part) allocated on demand
 d2d_status sb_ensure_parts(d2d_sb* sb, int split, bool central);

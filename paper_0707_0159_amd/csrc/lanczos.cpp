@@ -403,7 +403,7 @@ struct SbHv : HvOps {
             *parts = HvParts{};
             return sb_hv_nocount(sb, prec, v, w, s);
         }
-        return sb_hv_parts(sb, prec, v, w, s, nullptr, parts);
+        return sb_hv_parts(sb, prec, v, w, s, HV_ALL, parts);
     }
     d2d_status prepare(int prec) override {
         WorkItem* d;

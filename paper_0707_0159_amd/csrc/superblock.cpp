@@ -229,7 +229,7 @@ d2d_status sb_work(d2d_sb* sb, int shape, int split, WorkItem** out, int* nwork)
 }
 
 d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkItem* work, int nwork, const void* v,
-                     void* w, hipStream_t s, hipEvent_t mid) {
+                     void* w, hipStream_t s, int stages) {
     // a split work list (passed together with its partial outputs x) writes
     // shares of the K-loops there; the central term adds them, or, fused,
     // leaves them to the consumer
@@ -255,14 +255,13 @@ d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkItem* wor
         for (int i = 0; i < 3; ++i) c.X[i] = t.x[i];
     }
     if (prec == D2D_BF16) {
-        D2D_HIP(launch_pack_bf16(t.ptiles, t.n_ptiles, t.sec, (const bf16_t*)v, t.vp, t.vt, s));
+        if (stages & HV_PACK) D2D_HIP(launch_pack_bf16(t.ptiles, t.n_ptiles, t.sec, (const bf16_t*)v, t.vp, t.vt, s));
         g.V = t.vp;
-        D2D_HIP(launch_hv_gemm_bf16(shape, g, t.vt, s));
+        if (stages & HV_GEMM) D2D_HIP(launch_hv_gemm_bf16(shape, g, t.vt, s));
     } else {
-        D2D_HIP(launch_hv_gemm(shape, g, s));
+        if (stages & HV_GEMM) D2D_HIP(launch_hv_gemm(shape, g, s));
     }
-    if (mid) D2D_HIP(hipEventRecord(mid, s));
-    if (!t.w2) D2D_HIP(launch_central(prec, c, s));
+    if (!t.w2 && (stages & HV_CENTRAL)) D2D_HIP(launch_central(prec, c, s));
     return D2D_OK;
 }
 
@@ -302,7 +301,7 @@ d2d_status sb_ensure_parts(d2d_sb* sb, int split, bool central) {
     return D2D_OK;
 }
 
-d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s, hipEvent_t mid,
+d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s, int stages,
                        HvParts* parts) {
     if (prec < 0 || prec > 2 || !(sb->prec_mask & (1u << prec)) || !sb->HL[prec]) {
         set_error("precision %d not available on this superblock", prec);
@@ -321,15 +320,15 @@ d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t
         for (int i = 0; i < 3; ++i) parts->x[i] = t.x[i];
         parts->central = t.w2;
     }
-    return hv_launch(t, prec, shape, work, nwork, v, w, s, mid);
+    return hv_launch(t, prec, shape, work, nwork, v, w, s, stages);
 }
 
 d2d_status sb_hv_nocount(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s) {
-    return sb_hv_parts(sb, prec, v, w, s, nullptr);
+    return sb_hv_parts(sb, prec, v, w, s);
 }
 
 d2d_status sb_hv(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s) {
-    D2D_CHECK(sb_hv_parts(sb, prec, v, w, s, nullptr));
+    D2D_CHECK(sb_hv_parts(sb, prec, v, w, s));
     sb->hv_count[prec]++;
     return D2D_OK;
 }
@@ -783,7 +782,7 @@ extern "C" d2d_status d2d_hv_profile(d2d_sb* sb, int prec, const void* v, void* 
         return D2D_EINVAL;
     }
     hipStream_t s = sb->ctx->stream;
-    std::vector<hipEvent_t> ev(3 * (size_t)reps, nullptr);
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     d2d_status st = D2D_OK;
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) {
@@ -791,29 +790,26 @@ extern "C" d2d_status d2d_hv_profile(d2d_sb* sb, int prec, const void* v, void* 
             st = D2D_EDEVICE;
             break;
         }
-    for (int r = 0; r < reps && st == D2D_OK; ++r) {
-        if (hipEventRecord(ev[3 * r], s) != hipSuccess) st = D2D_EDEVICE;
-        if (st == D2D_OK) st = sb_hv_parts(sb, prec, v, w, s, ev[3 * r + 1]);
-        if (st == D2D_OK) sb->hv_count[prec]++;
-        if (st == D2D_OK && hipEventRecord(ev[3 * r + 2], s) != hipSuccess) st = D2D_EDEVICE;
-    }
-    double g = 0.0, c = 0.0;
-    if (st == D2D_OK && hipStreamSynchronize(s) != hipSuccess) st = D2D_EDEVICE;
-    for (int r = 0; r < reps && st == D2D_OK; ++r) {
-        float a = 0.f, b = 0.f;
-        if (hipEventElapsedTime(&a, ev[3 * r], ev[3 * r + 1]) != hipSuccess ||
-            hipEventElapsedTime(&b, ev[3 * r + 1], ev[3 * r + 2]) != hipSuccess) {
-            set_error("hipEventElapsedTime failed");
-            st = D2D_EDEVICE;
-            break;
-        }
-        g += a;
-        c += b;
+    // one whole product (work list, BF16 copies of v), the GEMM launches back
+    // to back, the central-term launches back to back, and a last whole
+    // product so that w = H v on return
+    if (st == D2D_OK) st = sb_hv(sb, prec, v, w, s);
+    if (st == D2D_OK && hipEventRecord(ev[0], s) != hipSuccess) st = D2D_EDEVICE;
+    for (int r = 0; r < reps && st == D2D_OK; ++r) st = sb_hv_parts(sb, prec, v, w, s, HV_GEMM);
+    if (st == D2D_OK && hipEventRecord(ev[1], s) != hipSuccess) st = D2D_EDEVICE;
+    for (int r = 0; r < reps && st == D2D_OK; ++r) st = sb_hv_parts(sb, prec, v, w, s, HV_CENTRAL);
+    if (st == D2D_OK && hipEventRecord(ev[2], s) != hipSuccess) st = D2D_EDEVICE;
+    if (st == D2D_OK) st = sb_hv(sb, prec, v, w, s);
+    float a = 0.f, c = 0.f;
+    if (st == D2D_OK && (hipStreamSynchronize(s) != hipSuccess || hipEventElapsedTime(&a, ev[0], ev[1]) != hipSuccess ||
+                         hipEventElapsedTime(&c, ev[1], ev[2]) != hipSuccess)) {
+        set_error("d2d_hv_profile: HIP event timing failed");
+        st = D2D_EDEVICE;
     }
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
     if (st != D2D_OK) return st;
-    *ms_gemm = g / reps;
+    *ms_gemm = a / reps;
     *ms_central = c / reps;
     return D2D_OK;
 }
@@ -893,10 +889,10 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
         sb->split[prec] = sp;
         HvParts parts{};
         HvParts* pp = fu ? &parts : nullptr;
-        st = sb_hv_parts(sb, prec, v, w, s, nullptr, pp);   // warm-up (also builds the work list)
+        st = sb_hv_parts(sb, prec, v, w, s, HV_ALL, pp);   // warm-up (also builds the work list)
         if (st != D2D_OK) break;
         if (hipEventRecord(e0, s) != hipSuccess) st = D2D_EDEVICE;
-        for (int r = 0; r < reps && st == D2D_OK; ++r) st = sb_hv_parts(sb, prec, v, w, s, nullptr, pp);
+        for (int r = 0; r < reps && st == D2D_OK; ++r) st = sb_hv_parts(sb, prec, v, w, s, HV_ALL, pp);
         float ms = 0.f;
         if (st == D2D_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
