@@ -293,6 +293,7 @@ def main():
         tuned[name] = {"tile": t & 0xFFFF,
                        "split_k_loops": "halves" if t & d2d.D2D_TILE_SPLIT4 else bool(t & d2d.D2D_TILE_SPLIT),
                        "central_in_gemm_launch": bool(t & d2d.D2D_TILE_FUSED),
+                       "xcd_order": bool(t & d2d.D2D_TILE_XCD),
                        "BMxBNxBK": "x".join(str(x) for x in shapes[t & 0xFFFF][1:4]),
                        "prefetch_depth": shapes[t & 0xFFFF][4], "ms": ms_t}
     with torch.cuda.stream(s):

@@ -216,7 +216,10 @@ d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[3]);
  * partial outputs, which the central-term launch adds (shorter critical path
  * for small, latency-bound sectors); D2D_TILE_SPLIT4 also halves each K-loop
  * (four work items and four partial outputs per tile, added in a fixed order,
- * so results stay deterministic).  OR-ing D2D_TILE_FUSED makes the inner
+ * so results stay deterministic).  D2D_TILE_XCD orders the work items so that
+ * each of the 8 XCDs (work-groups go to them round-robin, each has its own L2)
+ * works on one rectangle of every sector's tiles, cutting L2 misses on large
+ * sectors.  OR-ing D2D_TILE_FUSED makes the inner
  * Lanczos steps evaluate the central term inside the grouped-GEMM launch (its
  * tiles as extra blocks after the GEMM work items, into an output of its own
  * that the first vector kernel of the step adds: same result bit for bit, one
@@ -227,10 +230,11 @@ d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[3]);
 #define D2D_TILE_SPLIT (1 << 16)
 #define D2D_TILE_FUSED (1 << 17)
 #define D2D_TILE_SPLIT4 (1 << 18)
+#define D2D_TILE_XCD (1 << 19)
 d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile);
 /* Autotuner: times every grouped-GEMM tile shape of precision prec on this
  * superblock, unsplit, with D2D_TILE_SPLIT and with D2D_TILE_SPLIT4, each with
- * and without D2D_TILE_FUSED (reps launches each, on internal scratch vectors, HIP events
+ * and without D2D_TILE_FUSED and D2D_TILE_XCD (reps launches each, on internal scratch vectors, HIP events
  * on the context stream), selects the fastest for later d2d_hv / d2d_lanczos
  * calls and returns it (shape index OR-ed with the flags) and its average
  * milliseconds.  If the environment variable D2D_TUNE_CACHE names a file,

@@ -79,7 +79,7 @@ d2d_status build_work(d2d_batch* b, int shape) {
     std::vector<int> keep(b->pairs.size());
     for (size_t p = 0; p < b->pairs.size(); ++p) keep[p] = b->active[b->pair_prob[p]];
     std::vector<WorkItem> w;
-    make_work(b->pairs, &keep, tile_shape(shape), b->split, w);
+    make_work(b->pairs, &keep, tile_shape(shape), b->split, 0, w);
     auto it = b->work.find(shape);
     if (it != b->work.end() && b->work_cap[shape] < (int)w.size()) {
         dfree(b->ctx, it->second.first, (size_t)b->work_cap[shape]);

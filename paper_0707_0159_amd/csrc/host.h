@@ -208,6 +208,7 @@ struct d2d_sb {
     int tile_sel[3] = {-1, -1, -1};     // shape index, or -1 = by size
     int split[3] = {0, 0, 0};          // 0 none, 1 two K-loops apart, 2 each K-loop halved too
     int fuse[3] = {0, 1, 1};            // inner Lanczos steps: central term inside the GEMM launch
+    int xcd[3] = {0, 0, 0};             // XCD-aware work order
     void* d_x[3] = {nullptr, nullptr, nullptr};   // split-K partial outputs, N doubles each, on demand
     void* d_w2 = nullptr;               // N doubles, central-term part of fused launches
     int64_t hv_count[3] = {0, 0, 0};
@@ -231,7 +232,7 @@ d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t
 // partial outputs of a split level (and the central part) allocated on demand
 d2d_status sb_ensure_parts(d2d_sb* sb, int split, bool central);
 int sb_auto_tile(const d2d_sb* sb, int prec);
-d2d_status sb_work(d2d_sb* sb, int shape, int split, WorkItem** w, int* nwork);
+d2d_status sb_work(d2d_sb* sb, int shape, int split, int xcd, WorkItem** w, int* nwork);
 // central-term launch table of the pairs with keep[p] != 0 (all when keep is null)
 void central_tiles(const std::vector<SectorDev>& pairs, const std::vector<int>* keep,
                    std::vector<CentralTile>& out);
@@ -242,7 +243,8 @@ void central_sources(const std::vector<SectorDev>& pairs, const std::vector<int3
 inline int split_parts(int split) { return split == 0 ? 0 : (split == 1 ? 1 : 3); }
 // work items of the pairs with keep[p] != 0 for a tile shape; split level 0:
 // one item per output tile, 1: one per K-loop, 2: one per half K-loop
-void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep, const TileShape& ts, int split,
+// xcd: the XCD-aware order (rectangles of each pair's tiles per XCD, interleaved, padded with p = -1)
+void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep, const TileShape& ts, int split, int xcd,
                std::vector<WorkItem>& out);
 void free_lanczos(d2d_sb* sb);
 }  // namespace d2d

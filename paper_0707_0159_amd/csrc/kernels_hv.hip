@@ -339,6 +339,7 @@ k_hv_gemm(const HvK<T> g) {
     __shared__ T Bs[2][BN][BK + PB];
 
     const WorkItem wi = work[blockIdx.x];
+    if (wi.p < 0) return;   // padding of an XCD-ordered work list
     const SectorDev s = sec[wi.p];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave % WGM, wn = wave / WGM;
@@ -500,6 +501,7 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __
     __shared__ __attribute__((aligned(16))) bf16_t Bs[2][BN][LD];
 
     const WorkItem wi = work[blockIdx.x];
+    if (wi.p < 0) return;   // padding of an XCD-ordered work list
     const SectorDev s = sec[wi.p];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave % WGM, wn = wave / WGM;

@@ -410,7 +410,7 @@ struct SbHv : HvOps {
         int n;
         const int shape = sb->tile_sel[prec] >= 0 ? sb->tile_sel[prec] : sb_auto_tile(sb, prec);
         D2D_CHECK(sb_ensure_parts(sb, sb->split[prec], true));
-        return sb_work(sb, shape, sb->split[prec], &d, &n);
+        return sb_work(sb, shape, sb->split[prec], sb->xcd[prec], &d, &n);
     }
     d2d_status set_active(const std::vector<int>&, bool* rebuilt) override {
         if (rebuilt) *rebuilt = false;

@@ -178,40 +178,91 @@ void central_sources(const std::vector<SectorDev>& pairs, const std::vector<int3
         }
 }
 
-void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep, const TileShape& ts, int split,
-               std::vector<WorkItem>& out) {
-    std::vector<std::pair<int, WorkItem>> w;
-    for (size_t p = 0; p < pairs.size(); ++p) {
-        if (keep && !(*keep)[p]) continue;
-        const int dL = pairs[p].dL, dR = pairs[p].dR;
-        const int tm = (dL + ts.BM - 1) / ts.BM, tn = (dR + ts.BN - 1) / ts.BN;
-        const int hL = (dL + 1) / 2, hR = (dR + 1) / 2;
-        for (int j = 0; j < tn; ++j)
-            for (int i = 0; i < tm; ++i) {
+// Items of one pair: for every K-loop variant of the split level, the tiles in
+// raster order (rows fastest), with their K extents as costs.
+static void pair_items(int p, const SectorDev& sd, const TileShape& ts, int split, int i0, int i1, int j0, int j1,
+                       std::vector<std::pair<int, WorkItem>>& w) {
+    const int dL = sd.dL, dR = sd.dR;
+    const int hL = (dL + 1) / 2, hR = (dR + 1) / 2;
+    const int nv = split == 2 ? 4 : (split == 1 ? 2 : 1);
+    for (int v = 0; v < nv; ++v)
+        for (int j = j0; j < j1; ++j)
+            for (int i = i0; i < i1; ++i) {
                 if (split == 2) {
                     // slots: W (H_l V, 1st half), X0 (2nd half), X1 (V H_r^T, 1st half), X2 (2nd half)
-                    w.push_back({hL, {(int32_t)p, i, j, 1 | (0 << 2) | (1 << 4) | (0 << 5)}});
-                    w.push_back({dL - hL, {(int32_t)p, i, j, 1 | (1 << 2) | (1 << 4) | (1 << 5)}});
-                    w.push_back({hR, {(int32_t)p, i, j, 2 | (2 << 2) | (1 << 4) | (0 << 5)}});
-                    w.push_back({dR - hR, {(int32_t)p, i, j, 2 | (3 << 2) | (1 << 4) | (1 << 5)}});
+                    const int cost[4] = {hL, dL - hL, hR, dR - hR};
+                    const int part[4] = {1 | (0 << 2) | (1 << 4) | (0 << 5), 1 | (1 << 2) | (1 << 4) | (1 << 5),
+                                         2 | (2 << 2) | (1 << 4) | (0 << 5), 2 | (3 << 2) | (1 << 4) | (1 << 5)};
+                    w.push_back({cost[v], {(int32_t)p, i, j, part[v]}});
                 } else if (split == 1) {
-                    w.push_back({dL, {(int32_t)p, i, j, 1 | (0 << 2)}});
-                    w.push_back({dR, {(int32_t)p, i, j, 2 | (1 << 2)}});
+                    w.push_back({v == 0 ? dL : dR, {(int32_t)p, i, j, v == 0 ? (1 | (0 << 2)) : (2 | (1 << 2))}});
                 } else {
                     w.push_back({dL + dR, {(int32_t)p, i, j, 0}});
                 }
             }
+}
+
+void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep, const TileShape& ts, int split,
+               int xcd, std::vector<WorkItem>& out) {
+    out.clear();
+    if (xcd) {
+        // XCD-aware order.  Work-groups go to the 8 XCDs round-robin by index,
+        // and each XCD has its own L2: cut every pair's tile grid into 8
+        // rectangles (2 row bands x 4 column bands when the grid allows, else
+        // 8 runs of its raster order), give rectangle x to XCD x, and
+        // interleave the 8 lists so that item b runs on XCD b mod 8.  An XCD
+        // then re-reads the operator panels of its own rows and the input
+        // panels of its own columns only.  Pairs go in order of decreasing
+        // work; the lists are padded with empty items (p = -1) to one length.
+        constexpr int NX = 8;
+        std::vector<int> order;
+        for (size_t p = 0; p < pairs.size(); ++p)
+            if (!keep || (*keep)[p]) order.push_back((int)p);
+        auto work_of = [&](int p) {
+            const double a = pairs[p].dL, b = pairs[p].dR;
+            return a * a * b + a * b * b;
+        };
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work_of(a) > work_of(b); });
+        std::vector<std::vector<WorkItem>> bins(NX);
+        for (int p : order) {
+            const SectorDev& sd = pairs[p];
+            const int tm = (sd.dL + ts.BM - 1) / ts.BM, tn = (sd.dR + ts.BN - 1) / ts.BN;
+            if (tm >= 2 && tn >= 4) {
+                for (int x = 0; x < NX; ++x) {
+                    const int rb = x / 4, cb = x % 4;
+                    std::vector<std::pair<int, WorkItem>> w;
+                    pair_items(p, sd, ts, split, rb * tm / 2, (rb + 1) * tm / 2, cb * tn / 4, (cb + 1) * tn / 4, w);
+                    for (auto& e : w) bins[x].push_back(e.second);
+                }
+            } else {
+                std::vector<std::pair<int, WorkItem>> w;
+                pair_items(p, sd, ts, split, 0, tm, 0, tn, w);
+                const size_t n = w.size();
+                for (int x = 0; x < NX; ++x)
+                    for (size_t q = x * n / NX; q < (x + 1) * n / NX; ++q) bins[x].push_back(w[q].second);
+            }
+        }
+        size_t len = 0;
+        for (auto& b : bins) len = std::max(len, b.size());
+        for (size_t j = 0; j < len; ++j)
+            for (int x = 0; x < NX; ++x) out.push_back(j < bins[x].size() ? bins[x][j] : WorkItem{-1, 0, 0, 0});
+        return;
+    }
+    std::vector<std::pair<int, WorkItem>> w;
+    for (size_t p = 0; p < pairs.size(); ++p) {
+        if (keep && !(*keep)[p]) continue;
+        const int tm = (pairs[p].dL + ts.BM - 1) / ts.BM, tn = (pairs[p].dR + ts.BN - 1) / ts.BN;
+        pair_items((int)p, pairs[p], ts, split, 0, tm, 0, tn, w);
     }
     // longest K-loops first
     std::stable_sort(w.begin(), w.end(), [](const std::pair<int, WorkItem>& a, const std::pair<int, WorkItem>& b) {
         return a.first > b.first;
     });
-    out.clear();
     for (auto& x : w) out.push_back(x.second);
 }
 
-d2d_status sb_work(d2d_sb* sb, int shape, int split, WorkItem** out, int* nwork) {
-    const int key = shape | (split << 16);
+d2d_status sb_work(d2d_sb* sb, int shape, int split, int xcd, WorkItem** out, int* nwork) {
+    const int key = shape | (split << 16) | (xcd << 18);
     auto it = sb->work.find(key);
     if (it != sb->work.end()) {
         *out = it->second.first;
@@ -219,7 +270,7 @@ d2d_status sb_work(d2d_sb* sb, int shape, int split, WorkItem** out, int* nwork)
         return D2D_OK;
     }
     std::vector<WorkItem> w;
-    make_work(sb->pairs, nullptr, tile_shape(shape), split, w);
+    make_work(sb->pairs, nullptr, tile_shape(shape), split, xcd, w);
     WorkItem* d = nullptr;
     D2D_CHECK(upload(sb->ctx, w, &d));
     sb->work[key] = {d, (int)w.size()};
@@ -311,7 +362,7 @@ d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t
     const int split = sb->split[prec];
     WorkItem* work = nullptr;
     int nwork = 0;
-    D2D_CHECK(sb_work(sb, shape, split, &work, &nwork));
+    D2D_CHECK(sb_work(sb, shape, split, sb->xcd[prec], &work, &nwork));
     HvTables t = tables_of(sb);
     D2D_CHECK(sb_ensure_parts(sb, split, parts != nullptr));
     for (int i = 0; i < split_parts(split); ++i) t.x[i] = sb->d_x[i];
@@ -744,9 +795,10 @@ extern "C" d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile) {
     }
     const int split = tile < 0 ? 0 : ((tile & D2D_TILE_SPLIT4) ? 2 : ((tile & D2D_TILE_SPLIT) ? 1 : 0));
     const int fused = tile >= 0 ? ((tile & D2D_TILE_FUSED) ? 1 : 0) : (prec != D2D_FP64 ? 1 : 0);
+    const int xcd = tile >= 0 && (tile & D2D_TILE_XCD) ? 1 : 0;
     const int shape = tile < 0 ? -1 : (tile & 0xFFFF);
     if (shape >= tile_shape_count() || (shape >= 0 && tile_shape(shape).prec != prec) ||
-        (tile >= 0 && (tile & ~(0xFFFF | D2D_TILE_SPLIT | D2D_TILE_SPLIT4 | D2D_TILE_FUSED))) ||
+        (tile >= 0 && (tile & ~(0xFFFF | D2D_TILE_SPLIT | D2D_TILE_SPLIT4 | D2D_TILE_FUSED | D2D_TILE_XCD))) ||
         (tile >= 0 && (tile & D2D_TILE_SPLIT) && (tile & D2D_TILE_SPLIT4))) {
         set_error("d2d_sb_set_tile: tile %d is not a shape of precision %d", tile, prec);
         return D2D_EINVAL;
@@ -754,6 +806,7 @@ extern "C" d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile) {
     sb->tile_sel[prec] = shape;
     sb->split[prec] = split;
     sb->fuse[prec] = fused;
+    sb->xcd[prec] = xcd;
     return D2D_OK;
 }
 
@@ -852,6 +905,7 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
                     sb->tile_sel[prec] = sh;
                     sb->split[prec] = (t & D2D_TILE_SPLIT4) ? 2 : ((t & D2D_TILE_SPLIT) ? 1 : 0);
                     sb->fuse[prec] = (t & D2D_TILE_FUSED) ? 1 : 0;
+                    sb->xcd[prec] = (t & D2D_TILE_XCD) ? 1 : 0;
                     *best_tile = t;
                     *best_ms = ms;
                     fclose(f);
@@ -875,18 +929,20 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int best = -1;
     double bms = 1e300;
-    const int saved = sb->tile_sel[prec], saved_split = sb->split[prec], saved_fuse = sb->fuse[prec];
+    const int saved = sb->tile_sel[prec], saved_split = sb->split[prec], saved_fuse = sb->fuse[prec],
+              saved_xcd = sb->xcd[prec];
     if (launch_fill(v, prec, sb->N, 0.5, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
         hipEventCreate(&e1) != hipSuccess) {
         set_error("d2d_sb_autotune: HIP setup failed");
         st = D2D_EDEVICE;
     }
     const int nsh = tile_shape_count();
-    for (int tt = 0; tt < 6 * nsh && st == D2D_OK; ++tt) {
-        const int t = tt % nsh, sp = (tt / nsh) % 3, fu = tt / (3 * nsh);
+    for (int tt = 0; tt < 12 * nsh && st == D2D_OK; ++tt) {
+        const int t = tt % nsh, sp = (tt / nsh) % 3, fu = (tt / (3 * nsh)) % 2, xo = tt / (6 * nsh);
         if (tile_shape(t).prec != prec) continue;
         sb->tile_sel[prec] = t;
         sb->split[prec] = sp;
+        sb->xcd[prec] = xo;
         HvParts parts{};
         HvParts* pp = fu ? &parts : nullptr;
         st = sb_hv_parts(sb, prec, v, w, s, HV_ALL, pp);   // warm-up (also builds the work list)
@@ -899,7 +955,8 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
             st = D2D_EDEVICE;
         if (st == D2D_OK && ms / reps < bms) {
             bms = ms / reps;
-            best = t | (sp == 1 ? D2D_TILE_SPLIT : 0) | (sp == 2 ? D2D_TILE_SPLIT4 : 0) | (fu ? D2D_TILE_FUSED : 0);
+            best = t | (sp == 1 ? D2D_TILE_SPLIT : 0) | (sp == 2 ? D2D_TILE_SPLIT4 : 0) | (fu ? D2D_TILE_FUSED : 0) |
+                   (xo ? D2D_TILE_XCD : 0);
         }
     }
     if (e0) (void)hipEventDestroy(e0);
@@ -910,6 +967,7 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
         sb->tile_sel[prec] = saved;
         sb->split[prec] = saved_split;
         sb->fuse[prec] = saved_fuse;
+        sb->xcd[prec] = saved_xcd;
         if (st == D2D_OK) {
             set_error("d2d_sb_autotune: no tile shape for precision %d", prec);
             st = D2D_EINVAL;
@@ -919,6 +977,7 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
     sb->tile_sel[prec] = best & 0xFFFF;
     sb->split[prec] = (best & D2D_TILE_SPLIT4) ? 2 : ((best & D2D_TILE_SPLIT) ? 1 : 0);
     sb->fuse[prec] = (best & D2D_TILE_FUSED) ? 1 : 0;
+    sb->xcd[prec] = (best & D2D_TILE_XCD) ? 1 : 0;
     *best_tile = best;
     *best_ms = bms;
     if (cache && *cache) {

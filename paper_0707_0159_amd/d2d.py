@@ -23,6 +23,7 @@ D2D_LOG_MAX = 256
 D2D_TILE_SPLIT = 1 << 16
 D2D_TILE_FUSED = 1 << 17
 D2D_TILE_SPLIT4 = 1 << 18
+D2D_TILE_XCD = 1 << 19
 
 _STATUS = {0: "D2D_OK", -1: "D2D_EINVAL", -2: "D2D_ENOMEM", -3: "D2D_EDEVICE", -4: "D2D_ENOCONV",
            -5: "D2D_ESTATE"}

@@ -71,7 +71,9 @@ def test_config2_every_tile_shape(ctx, prec, tol):
     prob = GpuProblem(ctx, wl)
     assert prob.info["n"] == osb.N
     shapes = [i | sp for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == prec
-              for sp in (0, d2d.D2D_TILE_SPLIT, d2d.D2D_TILE_SPLIT4)]
+              for sp in (0, d2d.D2D_TILE_SPLIT, d2d.D2D_TILE_SPLIT4,
+                         d2d.D2D_TILE_XCD, d2d.D2D_TILE_SPLIT | d2d.D2D_TILE_XCD,
+                         d2d.D2D_TILE_SPLIT4 | d2d.D2D_TILE_XCD)]
     for k in range(3):
         v = W.random_vector(osb.N, 1000 + k)
         ref = osb.hv_factored(v)
@@ -160,7 +162,9 @@ def test_bf16_every_tile_shape(ctx, cfg):
     osb = oracle_superblock(wl)
     prob = GpuProblem(ctx, wl, prec_mask=7)
     shapes = [i | sp for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == d2d.D2D_BF16
-              for sp in (0, d2d.D2D_TILE_SPLIT, d2d.D2D_TILE_SPLIT4)]
+              for sp in (0, d2d.D2D_TILE_SPLIT, d2d.D2D_TILE_SPLIT4,
+                         d2d.D2D_TILE_XCD, d2d.D2D_TILE_SPLIT | d2d.D2D_TILE_XCD,
+                         d2d.D2D_TILE_SPLIT4 | d2d.D2D_TILE_XCD)]
     assert shapes
     for k in range(2):
         v = W.random_vector(osb.N, 1000 + k)
