@@ -139,9 +139,14 @@ d2d_status d2d_block_exact(d2d_ctx* ctx, const d2d_model* model, int ncols, int 
                            d2d_block** out);
 /* Number of states and sectors of a block. */
 d2d_status d2d_block_dims(const d2d_block* b, int* m, int* nsec);
-/* Copy a block out in the d2d_block_desc layout.  Caller buffers; pass the
- * sizes it has (nsec, H length, nblk, op_data length) in *_cap.  With
- * H == NULL only the sizes are written (size query). */
+/* Copy a block out in the d2d_block_desc layout (host buffers owned by the
+ * caller; sec_qn holds 2 entries per sector, op_key 3 per operator, op_blk 3
+ * per nonzero operator block).  sizes[5] = (number of sectors, length of H,
+ * number of operators, number of nonzero operator blocks, length of
+ * op_data).  With H == NULL the call only writes the needed sizes into sizes
+ * (size query); otherwise sizes holds the capacities of the caller's
+ * buffers, and a capacity below the need returns D2D_EINVAL with nothing
+ * written. */
 d2d_status d2d_block_export(const d2d_block* b, int64_t* sec_qn, int64_t* sec_dim, double* H,
                             int64_t* op_key, int64_t* op_blk, int64_t* op_off, double* op_data,
                             int64_t sizes[5] /* out: nsec, H len, nops, nblk, op_data len */);
