@@ -34,7 +34,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12}
+# BF16x3 forms three bf16 products per product: its peak in useful flops is a third of BF16's
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "bf16x3": 2.5e15 / 3, "hbm": 8.0e12}
 
 
 def kernel_source_hash() -> str:
@@ -243,7 +244,7 @@ def main():
     ap.add_argument("--profile", choices=["hv", "copy"], default=None,
                     help="profiling runs for rocprofv3: 'hv' = only Hv launches of --prec, "
                          "'copy' = a plain device copy of known size (counter calibration)")
-    ap.add_argument("--prec", choices=["fp64", "fp32", "bf16"], default="fp32")
+    ap.add_argument("--prec", choices=["fp64", "fp32", "bf16", "bf16x3"], default="fp32")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -281,12 +282,12 @@ def main():
     model = d2d.make_model(wl.kind, wl.legs, wl.t, wl.U, wl.J)
     b1 = d2d.d2d_block_import(ctx, model, raw["L"])
     b4 = d2d.d2d_block_import(ctx, model, raw["R"])
-    sb = d2d.d2d_sb_create(ctx, b1, b4, model, wl.target, 7)
+    sb = d2d.d2d_sb_create(ctx, b1, b4, model, wl.target, 15)
     info = d2d.d2d_sb_info(sb)
     N = info["n"]
     s = ctx.stream
     shapes = d2d.d2d_tile_shapes()
-    names = {d2d.D2D_FP64: "fp64", d2d.D2D_FP32: "fp32", d2d.D2D_BF16: "bf16"}
+    names = {d2d.D2D_FP64: "fp64", d2d.D2D_FP32: "fp32", d2d.D2D_BF16: "bf16", d2d.D2D_BF16X3: "bf16x3"}
     tuned = {}
     for prec, name in names.items():
         t, ms_t = d2d.d2d_sb_autotune(sb, prec, reps=10)
@@ -302,10 +303,11 @@ def main():
     s.synchronize()
 
     if args.profile == "hv":
-        prec = {"fp64": d2d.D2D_FP64, "fp32": d2d.D2D_FP32, "bf16": d2d.D2D_BF16}[args.prec]
+        prec = {"fp64": d2d.D2D_FP64, "fp32": d2d.D2D_FP32, "bf16": d2d.D2D_BF16,
+                "bf16x3": d2d.D2D_BF16X3}[args.prec]
         with torch.cuda.stream(s):
             x = torch.as_tensor(W.random_vector(N, 1000), device="cuda")
-            if prec == d2d.D2D_FP32:
+            if prec in (d2d.D2D_FP32, d2d.D2D_BF16X3):
                 x = x.float()
             elif prec == d2d.D2D_BF16:
                 x = x.to(torch.bfloat16)
@@ -357,14 +359,16 @@ def main():
     # ---------------------------------------------------------------- same algorithm, BF16 inputs / FP64
     reps = max(1, min(args.steps, 5))
     bf16 = timed(d2d.D2D_BF16, reps, 1)
+    bf16x3 = timed(d2d.D2D_BF16X3, reps, 1)
     fp64 = timed(d2d.D2D_FP64, reps, 1)
 
     # ---------------------------------------------------------------- Hv-only and kernel timing
     with torch.cuda.stream(s):
         x64 = torch.as_tensor(W.random_vector(N, 1000), device="cuda")
-        xs = {"fp64": x64, "fp32": x64.float(), "bf16": x64.to(torch.bfloat16)}
+        xs = {"fp64": x64, "fp32": x64.float(), "bf16": x64.to(torch.bfloat16), "bf16x3": x64.float()}
         ws = {"fp64": torch.empty_like(x64), "fp32": torch.empty(N, dtype=torch.float32, device="cuda"),
-              "bf16": torch.empty(N, dtype=torch.float32, device="cuda")}
+              "bf16": torch.empty(N, dtype=torch.float32, device="cuda"),
+              "bf16x3": torch.empty(N, dtype=torch.float32, device="cuda")}
     s.synchronize()
     ms = {}
     for prec, name in names.items():
@@ -413,14 +417,16 @@ def main():
                               "tridiagonal solve and FP64-Hv residual at every restart",
         "time_to_energy": {
             "E_oracle": E0,
-            "mixed_fp32": head, "mixed_bf16": bf16, "fp64": fp64,
+            "mixed_fp32": head, "mixed_bf16": bf16, "mixed_bf16x3": bf16x3, "fp64": fp64,
             "speedup_fp32_vs_fp64": fp64["s_per_solve"] / head["s_per_solve"],
             "speedup_bf16_vs_fp64": fp64["s_per_solve"] / bf16["s_per_solve"],
+            "speedup_bf16x3_vs_fp64": fp64["s_per_solve"] / bf16x3["s_per_solve"],
         },
         "hv_only": {k: {"hv_per_s": 1e3 / v["hv_ms"], **v} for k, v in ms.items()},
         "flops_exec_per_hv": F, "flops_nnz_per_hv": info["flops_nnz"],
         "roofline": roofline("fp32"),
         "roofline_bf16": roofline("bf16"),
+        "roofline_bf16x3": roofline("bf16x3"),
         "roofline_fp64": roofline("fp64"),
     }
     if not args.no_cpu_baseline:

@@ -61,12 +61,17 @@ typedef int d2d_status;
 #define D2D_ENOCONV -4   /* Lanczos did not reach the tolerance                */
 #define D2D_ESTATE  -5   /* object in the wrong state (live children, ...)     */
 
-/* Precision of one Hv.  Inputs v: double / float / bfloat16 (uint16 bits);
- * output w: double for D2D_FP64, float otherwise.  Products accumulate in the
- * output precision (FP32 accumulation for BF16 inputs). */
+/* Precision of one Hv.  Inputs v: double / float / bfloat16 (uint16 bits) /
+ * float; output w: double for D2D_FP64, float otherwise.  Products accumulate
+ * in the output precision (FP32 accumulation for BF16 inputs).  D2D_BF16X3
+ * splits every FP32 operand x into bf16 parts hi = bf16(x), lo = bf16(x - hi)
+ * and forms hi*hi + hi*lo + lo*hi on the BF16 matrix cores (the dropped lo*lo
+ * is about 2^-16 of a product): near-FP32 accuracy at BF16 matrix-core rate. */
 #define D2D_FP64 0
 #define D2D_FP32 1
 #define D2D_BF16 2
+#define D2D_BF16X3 3
+#define D2D_NPREC 4
 
 #define D2D_HEISENBERG 0
 #define D2D_HUBBARD    1
@@ -157,8 +162,8 @@ d2d_status d2d_block_destroy(d2d_block* b);
  * quantum number target_q[2] (Eq. (1)).  Both blocks must be of the model
  * given and of equal size m (the index maps of the paper assume it).  The
  * superblock copies what it needs; the blocks may be destroyed afterwards.
- * prec_mask: bit (1<<D2D_FP64 | 1<<D2D_FP32 | 1<<D2D_BF16) of the precisions
- * whose operator copies are kept on the device.  Fails with D2D_EINVAL when
+ * prec_mask: bits (1<<D2D_FP64 | 1<<D2D_FP32 | 1<<D2D_BF16 | 1<<D2D_BF16X3) of
+ * the precisions whose operator copies are kept on the device.  Fails with D2D_EINVAL when
  * the target space is empty. */
 d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d_block* b4,
                          const d2d_model* model, const int64_t target_q[2], unsigned prec_mask,
@@ -178,6 +183,7 @@ typedef struct {
     double bytes_min_fp32;  /* same, FP32 operators and vectors                  */
     double bytes_min_bf16;  /* same, BF16 operators and inputs, FP32 output      */
     int64_t op_entries;     /* sum dL^2 + sum dR^2                               */
+    double bytes_min_bf16x3; /* same, hi and lo BF16 operators, FP32 input/output */
 } d2d_sb_info_t;
 
 d2d_status d2d_sb_info(const d2d_sb* sb, d2d_sb_info_t* info);
@@ -212,7 +218,7 @@ d2d_status d2d_hv_profile(d2d_sb* sb, int prec, const void* v, void* w, int reps
                           double* ms_central);
 
 /* Number of Hv launches the superblock has issued per precision (counters). */
-d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[3]);
+d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[D2D_NPREC]);
 
 /* Tile shape of the grouped-GEMM launch used for one precision: index into
  * the library's table of tile shapes (see d2d_tile_shapes), or -1 to let the
@@ -265,7 +271,7 @@ d2d_status d2d_tile_shapes(int* count, int* desc);
  * All recurrences, dot products, the tridiagonal solve and the Ritz vector
  * are FP64 on the device; the host reads (theta_j, rho_j) once per restart.
  * Precision schedule: start in opts.prec; if rho_{j+1} > escalate * rho_j the
- * precision is raised (BF16 -> FP32 -> FP64).  k_in is capped at the problem
+ * precision is raised (BF16 -> BF16X3 when kept -> FP32 -> FP64).  k_in is capped at the problem
  * dimension.
  * Convergence: rho_j <= tol_res * |theta_j|, or, when tol_rel_e > 0, two
  * successive FP64 Rayleigh quotients with |theta_j - theta_{j-1}| <=
@@ -302,7 +308,7 @@ typedef struct {
 #define D2D_LOG_MAX 256
 typedef struct {
     int restarts;
-    int64_t hv_count[3];      /* Hv applications per precision                 */
+    int64_t hv_count[D2D_NPREC]; /* Hv applications per precision              */
     double residual;          /* last rho                                      */
     double seconds;           /* wall time of the call                         */
     int nlog;                 /* entries in the per-restart log                */

@@ -21,9 +21,11 @@ struct d2d_batch {
     int64_t ntot = 0;
     int max_dl = 0, max_dr = 0;
     SectorDev* d_sec = nullptr;
-    void* HL[3] = {nullptr, nullptr, nullptr};
-    void* HR[3] = {nullptr, nullptr, nullptr};
-    size_t hl_bytes[3] = {0, 0, 0}, hr_bytes[3] = {0, 0, 0};
+    void* HL[D2D_NPREC] = {nullptr, nullptr, nullptr, nullptr};
+    void* HR[D2D_NPREC] = {nullptr, nullptr, nullptr, nullptr};
+    size_t hl_bytes[D2D_NPREC] = {0, 0, 0, 0}, hr_bytes[D2D_NPREC] = {0, 0, 0, 0};
+    int64_t h16_len = 0, r16_len = 0;   // BF16 operator lengths (the BF16x3 lo parts follow the hi parts)
+    int vparts = 1;
     int K = 0;
     int64_t Drows = 0, Dcols = 0;
     int32_t *d_src = nullptr, *d_rmap = nullptr, *d_cmap = nullptr;
@@ -40,7 +42,7 @@ struct d2d_batch {
     std::map<int, std::pair<WorkItem*, int>> work;   // shape -> (table, count), active problems only
     std::map<int, int> work_cap;
     std::vector<int> active;
-    int64_t hv_count[3] = {0, 0, 0};
+    int64_t hv_count[D2D_NPREC] = {0, 0, 0, 0};
     int split = 0;                      // split K-loops (small, latency-bound sectors)
     void* d_w1 = nullptr;               // ntot doubles
     void* d_w2 = nullptr;               // ntot doubles, central-term part of fused launches
@@ -71,6 +73,7 @@ int batch_auto_tile(const d2d_batch* b, int prec) {
     const int D = std::max(b->max_dl, b->max_dr);
     if (prec == D2D_FP64) return D <= 64 ? 0 : (D <= 768 ? 1 : 2);
     if (prec == D2D_FP32) return D <= 64 ? 3 : (D <= 768 ? 4 : 5);
+    if (prec == D2D_BF16X3) return D <= 64 ? 30 : (D <= 512 ? 28 : 29);
     return D <= 64 ? 17 : (D <= 512 ? 14 : 15);
 }
 
@@ -133,10 +136,14 @@ HvTables tables_of(d2d_batch* b) {
     HvTables t{};
     t.sec = b->d_sec;
     t.npairs = (int)b->pairs.size();
-    for (int p = 0; p < 3; ++p) {
+    for (int p = 0; p < D2D_NPREC; ++p) {
         t.HL[p] = b->HL[p];
         t.HR[p] = b->HR[p];
     }
+    t.lo[0] = b->h16_len;
+    t.lo[1] = b->r16_len;
+    t.lo[2] = b->vp_len;
+    t.lo[3] = b->vt_len;
     t.K = b->K;
     t.src = b->d_src;
     t.rmap = b->d_rmap;
@@ -160,7 +167,7 @@ HvTables tables_of(d2d_batch* b) {
 }
 
 d2d_status batch_hv(d2d_batch* b, int prec, const void* v, void* w, hipStream_t s, HvParts* parts = nullptr) {
-    if (prec < 0 || prec > 2 || !(b->prec_mask & (1u << prec)) || !b->HL[prec]) {
+    if (prec < 0 || prec >= D2D_NPREC || !(b->prec_mask & (1u << prec)) || !b->HL[prec]) {
         set_error("precision %d not kept by every superblock of the batch", prec);
         return D2D_EINVAL;
     }
@@ -215,7 +222,7 @@ d2d_batch::~d2d_batch() {
     free_lanczos_work(ctx, lz);
     const size_t np = pairs.size();
     dfree(ctx, d_sec, np);
-    for (int p = 0; p < 3; ++p) {
+    for (int p = 0; p < D2D_NPREC; ++p) {
         if (HL[p]) ctx->free(HL[p], hl_bytes[p]);
         if (HR[p]) ctx->free(HR[p], hr_bytes[p]);
     }
@@ -230,8 +237,8 @@ d2d_batch::~d2d_batch() {
     dfree(ctx, d_cc32, (size_t)K * Dcols);
     dfree(ctx, d_ctiles, (size_t)cap_ctiles);
     dfree(ctx, d_ptiles, (size_t)cap_ptiles);
-    dfree(ctx, d_vp, (size_t)vp_len);
-    dfree(ctx, d_vt, (size_t)vt_len);
+    dfree(ctx, d_vp, (size_t)vp_len * vparts);
+    dfree(ctx, d_vt, (size_t)vt_len * vparts);
     for (auto& kv : work) dfree(ctx, kv.second.first, (size_t)work_cap[kv.first]);
     if (d_w1) ctx->free(d_w1, (size_t)ntot * 8);
     if (d_w2) ctx->free(d_w2, (size_t)ntot * 8);
@@ -247,7 +254,7 @@ extern "C" d2d_status d2d_batch_create(d2d_ctx* ctx, d2d_sb* const* sbs, int n, 
     *out = nullptr;
     auto b = std::make_unique<d2d_batch>();
     b->ctx = ctx;
-    b->prec_mask = 7u;
+    b->prec_mask = (1u << D2D_NPREC) - 1u;
     for (int i = 0; i < n; ++i) {
         if (!sbs[i] || sbs[i]->ctx != ctx) {
             set_error("d2d_batch_create: superblock %d is NULL or of another context", i);
@@ -298,29 +305,39 @@ extern "C" d2d_status d2d_batch_create(d2d_ctx* ctx, d2d_sb* const* sbs, int n, 
     b->vt_len = vt;
     D2D_CHECK(dupload(ctx, b->pairs, &b->d_sec));
     // operators: device-to-device concatenation
-    const size_t esz[3] = {8, 4, 2};
-    for (int p = 0; p < 3; ++p) {
+    // (BF16x3: every problem's hi parts, then every problem's lo parts)
+    const size_t esz[D2D_NPREC] = {8, 4, 2, 2};
+    b->h16_len = h16;
+    b->r16_len = r16;
+    for (int p = 0; p < D2D_NPREC; ++p) {
         if (!(b->prec_mask & (1u << p))) continue;
-        b->hl_bytes[p] = (size_t)(p == 2 ? h16 : hl) * esz[p];
-        b->hr_bytes[p] = (size_t)(p == 2 ? r16 : hr) * esz[p];
+        const bool b16 = p == D2D_BF16 || p == D2D_BF16X3;
+        const int parts = p == D2D_BF16X3 ? 2 : 1;
+        b->hl_bytes[p] = (size_t)(b16 ? h16 : hl) * esz[p] * parts;
+        b->hr_bytes[p] = (size_t)(b16 ? r16 : hr) * esz[p] * parts;
         D2D_CHECK(ctx->alloc(&b->HL[p], b->hl_bytes[p]));
         D2D_CHECK(ctx->alloc(&b->HR[p], b->hr_bytes[p]));
-        size_t ol = 0, orr = 0;
-        for (int i = 0; i < n; ++i) {
-            const d2d_sb* s = sbs[i];
-            const size_t bl = (size_t)(p == 2 ? s->hl16_len : s->hl_len) * esz[p];
-            const size_t br = (size_t)(p == 2 ? s->hr16_len : s->hr_len) * esz[p];
-            D2D_HIP(hipMemcpy((char*)b->HL[p] + ol, s->HL[p], bl, hipMemcpyDeviceToDevice));
-            D2D_HIP(hipMemcpy((char*)b->HR[p] + orr, s->HR[p], br, hipMemcpyDeviceToDevice));
-            ol += bl;
-            orr += br;
+        for (int part = 0; part < parts; ++part) {
+            size_t ol = (size_t)part * (b16 ? h16 : hl) * esz[p], orr = (size_t)part * (b16 ? r16 : hr) * esz[p];
+            for (int i = 0; i < n; ++i) {
+                const d2d_sb* s = sbs[i];
+                const size_t bl = (size_t)(b16 ? s->hl16_len : s->hl_len) * esz[p];
+                const size_t br = (size_t)(b16 ? s->hr16_len : s->hr_len) * esz[p];
+                D2D_HIP(hipMemcpy((char*)b->HL[p] + ol, (const char*)s->HL[p] + part * bl, bl,
+                                  hipMemcpyDeviceToDevice));
+                D2D_HIP(hipMemcpy((char*)b->HR[p] + orr, (const char*)s->HR[p] + part * br, br,
+                                  hipMemcpyDeviceToDevice));
+                ol += bl;
+                orr += br;
+            }
         }
     }
-    if (b->prec_mask & (1u << D2D_BF16)) {
-        D2D_CHECK(ctx->alloc((void**)&b->d_vp, (size_t)vp * 2));
-        D2D_CHECK(ctx->alloc((void**)&b->d_vt, (size_t)vt * 2));
-        D2D_HIP(hipMemset(b->d_vp, 0, (size_t)vp * 2));
-        D2D_HIP(hipMemset(b->d_vt, 0, (size_t)vt * 2));
+    if (b->prec_mask & ((1u << D2D_BF16) | (1u << D2D_BF16X3))) {
+        b->vparts = (b->prec_mask & (1u << D2D_BF16X3)) ? 2 : 1;
+        D2D_CHECK(ctx->alloc((void**)&b->d_vp, (size_t)vp * 2 * b->vparts));
+        D2D_CHECK(ctx->alloc((void**)&b->d_vt, (size_t)vt * 2 * b->vparts));
+        D2D_HIP(hipMemset(b->d_vp, 0, (size_t)vp * 2 * b->vparts));
+        D2D_HIP(hipMemset(b->d_vt, 0, (size_t)vt * 2 * b->vparts));
     }
     // central tables padded to K terms, source pairs rebased
     const int K = b->K;
@@ -387,12 +404,12 @@ extern "C" d2d_status d2d_batch_destroy(d2d_batch* b) {
 }
 
 extern "C" d2d_status d2d_batch_hv(d2d_batch* b, int prec, const void* const* v, void* const* w) {
-    if (!b || !v || !w || prec < 0 || prec > 2) {
+    if (!b || !v || !w || prec < 0 || prec >= D2D_NPREC) {
         set_error("d2d_batch_hv: bad argument");
         return D2D_EINVAL;
     }
     const int n = (int)b->sbs.size();
-    const size_t in_sz = prec == D2D_FP64 ? 8 : (prec == D2D_FP32 ? 4 : 2);
+    const size_t in_sz = prec == D2D_FP64 ? 8 : (prec == D2D_BF16 ? 2 : 4);
     const size_t out_sz = prec == D2D_FP64 ? 8 : 4;
     hipStream_t s = b->ctx->stream;
     std::vector<int> all(n, 1);

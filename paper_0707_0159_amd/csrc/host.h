@@ -99,9 +99,9 @@ struct LanczosWork {
     std::vector<d2d::LzSeg> h_bt;   // host copy (its act flags follow the active set)
     int2* prange = nullptr;
     int* active = nullptr;
-    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
-    hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
-    int graph_k[3] = {0, 0, 0};
+    hipGraphExec_t exec[D2D_NPREC] = {nullptr, nullptr, nullptr, nullptr};
+    hipGraph_t graph[D2D_NPREC] = {nullptr, nullptr, nullptr, nullptr};
+    int graph_k[D2D_NPREC] = {0, 0, 0, 0};
 };
 
 namespace d2d {
@@ -111,8 +111,9 @@ struct HvTables {
     int npairs;
     void* x[3];               // partial outputs of split K-loops (ntot doubles each; null = unused)
     void* w2;                 // central-term output of a fused launch (ntot doubles; null = unfused)
-    const void* HL[3];
-    const void* HR[3];
+    const void* HL[D2D_NPREC];
+    const void* HR[D2D_NPREC];
+    int64_t lo[4];            // BF16x3: elements from the hi to the lo parts of HL, HR, VP, VT
     int K;
     const int32_t* src;
     const int32_t* rmap;
@@ -177,8 +178,8 @@ struct d2d_sb {
     double flops_exec = 0, flops_nnz = 0, flops_central = 0;
     // device tables
     d2d::SectorDev* d_sec = nullptr;
-    void* HL[3] = {nullptr, nullptr, nullptr};
-    void* HR[3] = {nullptr, nullptr, nullptr};
+    void* HL[D2D_NPREC] = {nullptr, nullptr, nullptr, nullptr};
+    void* HR[D2D_NPREC] = {nullptr, nullptr, nullptr, nullptr};
     int K = 0;
     int32_t* d_src = nullptr;
     int32_t* d_rmap = nullptr;
@@ -197,6 +198,7 @@ struct d2d_sb {
     int64_t hl16_len = 0, hr16_len = 0, vp_len = 0, vt_len = 0;
     d2d::bf16_t* d_vp = nullptr;
     d2d::bf16_t* d_vt = nullptr;
+    int vparts = 1;                    // 2 when VP / VT also hold BF16x3 lo parts
     int4* d_ptiles = nullptr;          // pack launch table (pair, 64-row tile, 64-column tile)
     int n_ptiles = 0;
     int n_cblocks = 0;
@@ -205,13 +207,13 @@ struct d2d_sb {
     std::vector<double> h_rc, h_cc;
     // work lists per tile shape
     std::map<int, std::pair<d2d::WorkItem*, int>> work;
-    int tile_sel[3] = {-1, -1, -1};     // shape index, or -1 = by size
-    int split[3] = {0, 0, 0};          // 0 none, 1 two K-loops apart, 2 each K-loop halved too
-    int fuse[3] = {0, 1, 1};            // inner Lanczos steps: central term inside the GEMM launch
-    int xcd[3] = {0, 0, 0};             // XCD-aware work order
+    int tile_sel[D2D_NPREC] = {-1, -1, -1, -1};   // shape index, or -1 = by size
+    int split[D2D_NPREC] = {0, 0, 0, 0};          // 0 none, 1 two K-loops apart, 2 each K-loop halved too
+    int fuse[D2D_NPREC] = {0, 1, 1, 1};           // inner Lanczos steps: central term inside the GEMM launch
+    int xcd[D2D_NPREC] = {0, 0, 0, 0};            // XCD-aware work order
     void* d_x[3] = {nullptr, nullptr, nullptr};   // split-K partial outputs, N doubles each, on demand
     void* d_w2 = nullptr;               // N doubles, central-term part of fused launches
-    int64_t hv_count[3] = {0, 0, 0};
+    int64_t hv_count[D2D_NPREC] = {0, 0, 0, 0};
     LanczosWork* lz = nullptr;          // owned; freed by free_lanczos
     ~d2d_sb();
 };

@@ -116,6 +116,7 @@ struct HvGemmArgs {
     void* W;
     void* X[3];                // partial outputs of split work items (slot s -> X[s-1]; nullable)
     const CentralArgs* fuse;   // nullable
+    int64_t lo[4];             // BF16x3: element offsets of the lo parts of HL, HR, VP, VT
 };
 hipError_t launch_hv_gemm(int shape, const HvGemmArgs& a, hipStream_t s);
 // BF16: HvGemmArgs.V is the padded copy VP, VT its padded transpose.
@@ -126,7 +127,11 @@ hipError_t launch_pack_bf16(const int4* tiles, int ntiles, const SectorDev* sec,
 // BF16 operator copies from the FP64 masters: HL (column-major dL x dL) ->
 // row-major padded; HRt (column-major H_r^T) -> padded; two-step RNE rounding.
 hipError_t launch_op_bf16(const int64_t* src_off, const int64_t* dst_off, const int32_t* d, const int32_t* dp,
-                          int nsec, int transpose, const double* src, bf16_t* dst, int64_t max_d2, hipStream_t s);
+                          int nsec, int transpose, int lo, const double* src, bf16_t* dst, int64_t max_d2,
+                          hipStream_t s);
+// BF16x3 copies (hi and lo parts) of a packed FP32 vector
+hipError_t launch_pack_bf16x3(const int4* tiles, int ntiles, const SectorDev* sec, const float* v, bf16_t* vp,
+                              bf16_t* vt, int64_t lo_vp, int64_t lo_vt, hipStream_t s);
 
 
 

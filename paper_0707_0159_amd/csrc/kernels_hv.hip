@@ -286,7 +286,7 @@ hipError_t launch_central(int prec, const CentralArgs& a, hipStream_t st) {
     if (prec == D2D_FP64)
         hipLaunchKernelGGL((k_central<double, double, double>), grid, dim3(64), 0, st,
                            central_args<double, double, double>(a));
-    else if (prec == D2D_FP32)
+    else if (prec == D2D_FP32 || prec == D2D_BF16X3)
         hipLaunchKernelGGL((k_central<float, float, float>), grid, dim3(64), 0, st, central_args<float, float, float>(a));
     else
         hipLaunchKernelGGL((k_central<bf16_t, float, float>), grid, dim3(64), 0, st,
@@ -477,18 +477,30 @@ struct OutPtrs {
 };
 __device__ inline bf16_t f32_to_bf16_rne(float f);
 
-template <int BM, int BN, int BK, int WGM, int WGN, int PF, bool CEN>
+// X3 (BF16x3): every operand is an FP32 value split into bf16 parts
+// x = hi + lo (hi = bf16(x), lo = bf16(x - hi)); the lo copies sit at the
+// offsets lo.{hl, hr, vp, vt} (elements) from the hi ones, and each K slice
+// issues three MFMAs, hi*hi + hi*lo + lo*hi in that order (lo*lo, about
+// 2^-16 of the product, is dropped), accumulating in FP32.
+struct LoOffsets {
+    int64_t hl, hr, vp, vt;
+};
+
+template <int BM, int BN, int BK, int WGM, int WGN, int PF, bool X3, bool CEN>
 __global__ void __launch_bounds__(64 * WGM * WGN)
 k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __restrict__ sec,
                const bf16_t* __restrict__ HL, const bf16_t* __restrict__ HRt, const bf16_t* __restrict__ VP,
-               const bf16_t* __restrict__ VT, const OutPtrs out, const CentralK<bf16_t, float, float> cen) {
+               const bf16_t* __restrict__ VT, const OutPtrs out, const LoOffsets lo,
+               const CentralK<typename std::conditional<X3, float, bf16_t>::type, float, float> cen) {
+    using TIc = typename std::conditional<X3, float, bf16_t>::type;
     if constexpr (CEN) {
         if ((int)blockIdx.x >= nwork) {
-            central_tiles_block<bf16_t, float, float, WGM * WGN, false>(cen, ((int)blockIdx.x - nwork) * WGM * WGN);
+            central_tiles_block<TIc, float, float, WGM * WGN, false>(cen, ((int)blockIdx.x - nwork) * WGM * WGN);
             return;
         }
     }
     using M = Mf<float>;
+    constexpr int NP = X3 ? 2 : 1;                   // bf16 parts per operand
     constexpr int NT = 64 * WGM * WGN;
     constexpr int WM = BM / WGM, WN = BN / WGN;
     constexpr int FM = WM / 32, FN = WN / 32;
@@ -497,8 +509,8 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __
     constexpr int EA = BM * KV / NT, EB = BN * KV / NT;
     static_assert(EA * NT == BM * KV && EB * NT == BN * KV, "load split");
     constexpr int LD = BK + 8;                       // row stride in LDS (bf16), 16-byte aligned
-    __shared__ __attribute__((aligned(16))) bf16_t As[2][BM][LD];
-    __shared__ __attribute__((aligned(16))) bf16_t Bs[2][BN][LD];
+    __shared__ __attribute__((aligned(16))) bf16_t As[2][NP][BM][LD];
+    __shared__ __attribute__((aligned(16))) bf16_t Bs[2][NP][BN][LD];
 
     const WorkItem wi = work[blockIdx.x];
     if (wi.p < 0) return;   // padding of an XCD-ordered work list
@@ -516,58 +528,75 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __
 #pragma unroll
             for (int v = 0; v < M::NV; ++v) acc[i][j][v] = 0.0f;
 
-    uint4 ra[EA], rb[EB];
+    uint4 ra[NP][EA], rb[NP][EB];
     const ItemK it = decode_item(wi.part);
 #pragma unroll 1
     for (int phase = it.ph_lo; phase < it.ph_hi; ++phase) {
         const bf16_t* A = phase == 0 ? HL + s.hl16_off : VT + s.vt_off;
         const bf16_t* B = phase == 0 ? VP + s.vp_off : HRt + s.hr16_off;
+        const int64_t loA = phase == 0 ? lo.hl : lo.vt, loB = phase == 0 ? lo.vp : lo.hr;
         const int64_t ld = phase == 0 ? s.dLp : s.dRp;     // both operands share the K stride
         const int Kp = phase == 0 ? s.dLp : s.dRp;
         int k_lo, k_hi;
         k_range<BK>(it, Kp, k_lo, k_hi);
 
-        auto gload = [&](int k0, uint4 (&xa)[EA], uint4 (&xb)[EB]) {
+        auto gload = [&](int k0, uint4 (&xa)[NP][EA], uint4 (&xb)[NP][EB]) {
 #pragma unroll
-            for (int e = 0; e < EA; ++e) {
-                const int idx = t + NT * e, r = idx / KV, kv = idx % KV;
-                const int gr = row0 + r, kk = k0 + 8 * kv;
-                xa[e] = (gr < dL && kk < Kp) ? *(const uint4*)(A + gr * ld + kk) : make_uint4(0, 0, 0, 0);
-            }
+            for (int h = 0; h < NP; ++h) {
 #pragma unroll
-            for (int e = 0; e < EB; ++e) {
-                const int idx = t + NT * e, c = idx / KV, kv = idx % KV;
-                const int gc = col0 + c, kk = k0 + 8 * kv;
-                xb[e] = (gc < dR && kk < Kp) ? *(const uint4*)(B + gc * ld + kk) : make_uint4(0, 0, 0, 0);
+                for (int e = 0; e < EA; ++e) {
+                    const int idx = t + NT * e, r = idx / KV, kv = idx % KV;
+                    const int gr = row0 + r, kk = k0 + 8 * kv;
+                    xa[h][e] = (gr < dL && kk < Kp) ? *(const uint4*)(A + h * loA + gr * ld + kk)
+                                                    : make_uint4(0, 0, 0, 0);
+                }
+#pragma unroll
+                for (int e = 0; e < EB; ++e) {
+                    const int idx = t + NT * e, c = idx / KV, kv = idx % KV;
+                    const int gc = col0 + c, kk = k0 + 8 * kv;
+                    xb[h][e] = (gc < dR && kk < Kp) ? *(const uint4*)(B + h * loB + gc * ld + kk)
+                                                    : make_uint4(0, 0, 0, 0);
+                }
             }
         };
-        auto stage = [&](const uint4 (&xa)[EA], const uint4 (&xb)[EB], int buf) {
+        auto stage = [&](const uint4 (&xa)[NP][EA], const uint4 (&xb)[NP][EB], int buf) {
 #pragma unroll
-            for (int e = 0; e < EA; ++e) {
-                const int idx = t + NT * e;
-                *(uint4*)&As[buf][idx / KV][8 * (idx % KV)] = xa[e];
-            }
+            for (int h = 0; h < NP; ++h) {
 #pragma unroll
-            for (int e = 0; e < EB; ++e) {
-                const int idx = t + NT * e;
-                *(uint4*)&Bs[buf][idx / KV][8 * (idx % KV)] = xb[e];
+                for (int e = 0; e < EA; ++e) {
+                    const int idx = t + NT * e;
+                    *(uint4*)&As[buf][h][idx / KV][8 * (idx % KV)] = xa[h][e];
+                }
+#pragma unroll
+                for (int e = 0; e < EB; ++e) {
+                    const int idx = t + NT * e;
+                    *(uint4*)&Bs[buf][h][idx / KV][8 * (idx % KV)] = xb[h][e];
+                }
             }
         };
         auto compute = [&](int buf) {
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 16) {
-                bf16x8 a[FM], b[FN];
+                bf16x8 a[NP][FM], b[NP][FN];
 #pragma unroll
-                for (int i = 0; i < FM; ++i)
-                    a[i] = *(const bf16x8*)&As[buf][wm * WM + i * 32 + (lane & 31)][kk + 8 * (lane >> 5)];
+                for (int h = 0; h < NP; ++h) {
 #pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    b[j] = *(const bf16x8*)&Bs[buf][wn * WN + j * 32 + (lane & 31)][kk + 8 * (lane >> 5)];
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
+                    for (int i = 0; i < FM; ++i)
+                        a[h][i] = *(const bf16x8*)&As[buf][h][wm * WM + i * 32 + (lane & 31)][kk + 8 * (lane >> 5)];
 #pragma unroll
                     for (int j = 0; j < FN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[j], a[i], acc[i][j], 0, 0, 0);
+                        b[h][j] = *(const bf16x8*)&Bs[buf][h][wn * WN + j * 32 + (lane & 31)][kk + 8 * (lane >> 5)];
+                }
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[0][j], a[0][i], acc[i][j], 0, 0, 0);
+                        if constexpr (X3) {
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[NP - 1][j], a[0][i], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[0][j], a[NP - 1][i], acc[i][j], 0, 0, 0);
+                        }
+                    }
             }
         };
         int buf = 0;
@@ -582,7 +611,7 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __
                 buf ^= 1;
             }
         } else {
-            uint4 ra1[EA], rb1[EB];
+            uint4 ra1[NP][EA], rb1[NP][EB];
             if (k_lo < k_hi) gload(k_lo, ra, rb);
             if (k_lo + BK < k_hi) gload(k_lo + BK, ra1, rb1);
 #pragma unroll 1
@@ -618,8 +647,9 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __
     }
 }
 
-template <int BM, int BN, int BK, int WGM, int WGN, int PF>
+template <int BM, int BN, int BK, int WGM, int WGN, int PF, bool X3>
 static void gemm_bf16_launch(const HvGemmArgs& a, const void* VT, hipStream_t st) {
+    using TIc = typename std::conditional<X3, float, bf16_t>::type;
     constexpr int NW = WGM * WGN;
     const bf16_t* HL = (const bf16_t*)a.HL;
     const bf16_t* HR = (const bf16_t*)a.HR;
@@ -628,13 +658,15 @@ static void gemm_bf16_launch(const HvGemmArgs& a, const void* VT, hipStream_t st
     OutPtrs out;
     out.W = (float*)a.W;
     for (int i = 0; i < 3; ++i) out.X[i] = (float*)a.X[i];
+    const LoOffsets lo{a.lo[0], a.lo[1], a.lo[2], a.lo[3]};
     if (a.fuse) {
         const int extra = (a.fuse->ntiles + NW - 1) / NW;
-        hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, PF, true>), dim3(a.nwork + extra), dim3(64 * NW), 0, st,
-                           a.work, a.nwork, a.sec, HL, HR, VP, V2, out, central_args<bf16_t, float, float>(*a.fuse));
+        hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, PF, X3, true>), dim3(a.nwork + extra), dim3(64 * NW),
+                           0, st, a.work, a.nwork, a.sec, HL, HR, VP, V2, out, lo,
+                           central_args<TIc, float, float>(*a.fuse));
     } else {
-        hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, PF, false>), dim3(a.nwork), dim3(64 * NW), 0, st, a.work,
-                           a.nwork, a.sec, HL, HR, VP, V2, out, CentralK<bf16_t, float, float>{});
+        hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, PF, X3, false>), dim3(a.nwork), dim3(64 * NW), 0, st,
+                           a.work, a.nwork, a.sec, HL, HR, VP, V2, out, lo, CentralK<TIc, float, float>{});
     }
 }
 
@@ -642,13 +674,17 @@ hipError_t launch_hv_gemm_bf16(int shape, const HvGemmArgs& a, const void* VT, h
     if (a.nwork <= 0) return hipSuccess;
     if (a.fuse && a.fuse->K > KMAX) return hipErrorInvalidValue;
     switch (shape) {
-        case 14: gemm_bf16_launch<64, 64, 32, 2, 2, 1>(a, VT, st); break;
-        case 15: gemm_bf16_launch<128, 128, 32, 2, 2, 1>(a, VT, st); break;
-        case 16: gemm_bf16_launch<128, 128, 64, 2, 2, 1>(a, VT, st); break;
-        case 17: gemm_bf16_launch<32, 32, 64, 1, 1, 1>(a, VT, st); break;
-        case 25: gemm_bf16_launch<64, 64, 32, 2, 2, 2>(a, VT, st); break;
-        case 26: gemm_bf16_launch<32, 32, 64, 1, 1, 2>(a, VT, st); break;
-        case 27: gemm_bf16_launch<128, 128, 64, 2, 2, 2>(a, VT, st); break;
+        case 14: gemm_bf16_launch<64, 64, 32, 2, 2, 1, false>(a, VT, st); break;
+        case 15: gemm_bf16_launch<128, 128, 32, 2, 2, 1, false>(a, VT, st); break;
+        case 16: gemm_bf16_launch<128, 128, 64, 2, 2, 1, false>(a, VT, st); break;
+        case 17: gemm_bf16_launch<32, 32, 64, 1, 1, 1, false>(a, VT, st); break;
+        case 25: gemm_bf16_launch<64, 64, 32, 2, 2, 2, false>(a, VT, st); break;
+        case 26: gemm_bf16_launch<32, 32, 64, 1, 1, 2, false>(a, VT, st); break;
+        case 27: gemm_bf16_launch<128, 128, 64, 2, 2, 2, false>(a, VT, st); break;
+        case 28: gemm_bf16_launch<64, 64, 32, 2, 2, 1, true>(a, VT, st); break;
+        case 29: gemm_bf16_launch<128, 128, 32, 2, 2, 1, true>(a, VT, st); break;
+        case 30: gemm_bf16_launch<32, 32, 32, 1, 1, 2, true>(a, VT, st); break;
+        case 31: gemm_bf16_launch<64, 64, 32, 2, 2, 2, true>(a, VT, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -697,30 +733,85 @@ hipError_t launch_pack_bf16(const int4* tiles, int ntiles, const SectorDev* sec,
     return hipGetLastError();
 }
 
+// BF16x3 copies of a packed FP32 vector: hi = bf16(x), lo = bf16(x - hi), into
+// VP / VT and their lo halves at the element offsets lo_vp / lo_vt.
+__global__ void __launch_bounds__(256)
+k_pack_bf16x3(const int4* __restrict__ tiles, const SectorDev* __restrict__ sec, const float* __restrict__ v,
+              bf16_t* __restrict__ vp, bf16_t* __restrict__ vt, int64_t lo_vp, int64_t lo_vt) {
+    __shared__ uint32_t sh[64][65];
+    const int4 ti = tiles[blockIdx.x];
+    const SectorDev s = sec[ti.x];
+    const int r0 = ti.y * 64, c0 = ti.z * 64;
+    const int t = threadIdx.x;
+    float x[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int rr = t & 63, cc = (t >> 6) + 4 * q;
+        const int r = min(r0 + rr, s.dL - 1), c = min(c0 + cc, s.dR - 1);
+        x[q] = v[s.off + r + (int64_t)c * s.dL];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int rr = t & 63, cc = (t >> 6) + 4 * q;
+        const int r = r0 + rr, c = c0 + cc;
+        if (r < s.dL && c < s.dR) {
+            const bf16_t hi = f32_to_bf16_rne(x[q]);
+            const bf16_t lo = f32_to_bf16_rne(x[q] - bf16_to_f32(hi));
+            sh[cc][rr] = (uint32_t)hi | ((uint32_t)lo << 16);
+            const int64_t e = s.vp_off + r + (int64_t)c * s.dLp;
+            vp[e] = hi;
+            vp[e + lo_vp] = lo;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int cc = t & 63, rr = (t >> 6) + 4 * q;
+        const int r = r0 + rr, c = c0 + cc;
+        if (r < s.dL && c < s.dR) {
+            const uint32_t hl = sh[cc][rr];
+            const int64_t e = s.vt_off + c + (int64_t)r * s.dRp;
+            vt[e] = (bf16_t)(hl & 0xffffu);
+            vt[e + lo_vt] = (bf16_t)(hl >> 16);
+        }
+    }
+}
+
+hipError_t launch_pack_bf16x3(const int4* tiles, int ntiles, const SectorDev* sec, const float* v, bf16_t* vp,
+                              bf16_t* vt, int64_t lo_vp, int64_t lo_vt, hipStream_t st) {
+    if (ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_bf16x3, dim3(ntiles), dim3(256), 0, st, tiles, sec, v, vp, vt, lo_vp, lo_vt);
+    return hipGetLastError();
+}
+
 // dst (padded, K-major) from an FP64 column-major d x d block; transpose=1
 // stores the transposed block (row-major H_l), 0 stores it as is (H_r^T).
+// lo=1 stores the BF16x3 lo part bf16(f - hi) of f = fp32(x) instead of hi.
 __global__ void __launch_bounds__(256)
 k_op_bf16(const int64_t* __restrict__ src_off, const int64_t* __restrict__ dst_off, const int32_t* __restrict__ dd,
-          const int32_t* __restrict__ ddp, int transpose, const double* __restrict__ src, bf16_t* __restrict__ dst) {
+          const int32_t* __restrict__ ddp, int transpose, int lo, const double* __restrict__ src,
+          bf16_t* __restrict__ dst) {
     const int si = blockIdx.y;
     const int d = dd[si], dp = ddp[si];
     const int64_t n = (int64_t)d * d;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(e % d), j = (int)(e / d);     // element (i, j) of the source
         const float f = (float)src[src_off[si] + e];
-        const bf16_t h = f32_to_bf16_rne(f);
+        bf16_t h = f32_to_bf16_rne(f);
+        if (lo) h = f32_to_bf16_rne(f - bf16_to_f32(h));
         if (transpose) dst[dst_off[si] + j + (int64_t)i * dp] = h;   // row i of the source, K = j
         else dst[dst_off[si] + i + (int64_t)j * dp] = h;
     }
 }
 
 hipError_t launch_op_bf16(const int64_t* src_off, const int64_t* dst_off, const int32_t* d, const int32_t* dp,
-                          int nsec, int transpose, const double* src, bf16_t* dst, int64_t max_d2, hipStream_t st) {
+                          int nsec, int transpose, int lo, const double* src, bf16_t* dst, int64_t max_d2,
+                          hipStream_t st) {
     if (nsec == 0) return hipSuccess;
     int gx = (int)((max_d2 + 255) / 256);
     if (gx > 4096) gx = 4096;
     if (gx < 1) gx = 1;
-    hipLaunchKernelGGL(k_op_bf16, dim3(gx, nsec), dim3(256), 0, st, src_off, dst_off, d, dp, transpose, src, dst);
+    hipLaunchKernelGGL(k_op_bf16, dim3(gx, nsec), dim3(256), 0, st, src_off, dst_off, d, dp, transpose, lo, src, dst);
     return hipGetLastError();
 }
 
@@ -782,6 +873,11 @@ static const TileShape kShapes[] = {
     {D2D_BF16, 64, 64, 32, 2},    // 25
     {D2D_BF16, 32, 32, 64, 2},    // 26: 1 wave
     {D2D_BF16, 128, 128, 64, 2},  // 27
+    // BF16x3: hi/lo bf16 parts of FP32 operands, three MFMAs per K slice
+    {D2D_BF16X3, 64, 64, 32},     // 28
+    {D2D_BF16X3, 128, 128, 32},   // 29
+    {D2D_BF16X3, 32, 32, 32, 2},  // 30: 1 wave
+    {D2D_BF16X3, 64, 64, 32, 2},  // 31
 };
 
 int tile_shape_count() { return (int)(sizeof(kShapes) / sizeof(kShapes[0])); }
@@ -924,7 +1020,7 @@ hipError_t launch_cast_f32_bf16(const float* x, bf16_t* y, int64_t n, hipStream_
 __global__ void k_fill(void* x, int prec, int64_t n, double v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         if (prec == D2D_FP64) ((double*)x)[i] = v;
-        else if (prec == D2D_FP32) ((float*)x)[i] = (float)v;
+        else if (prec == D2D_FP32 || prec == D2D_BF16X3) ((float*)x)[i] = (float)v;
         else ((bf16_t*)x)[i] = f32_to_bf16_rne((float)v);
     }
 }

@@ -537,7 +537,7 @@ k_lz_next(const LzSeg* __restrict__ bt, const double* __restrict__ Q,
             if (e >= sg.hi) break;
             const double q = x[u] * inv;
             qnext[e] = q;
-            if (lo_prec == D2D_FP32) ((float*)lo)[e] = (float)q;
+            if (lo_prec == D2D_FP32 || lo_prec == D2D_BF16X3) ((float*)lo)[e] = (float)q;
             else if (lo_prec == D2D_BF16) ((uint16_t*)lo)[e] = f32_bf16_rne((float)q);
         }
     }
@@ -669,7 +669,7 @@ k_lz_update_gram(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int
             for (int j = 0; j < NQ; ++j) x[u] -= d[j] * q[u][j];
             const double qv = x[u] * inv;
             qnext[e] = qv;
-            if (lo_prec == D2D_FP32) ((float*)lo)[e] = (float)qv;
+            if (lo_prec == D2D_FP32 || lo_prec == D2D_BF16X3) ((float*)lo)[e] = (float)qv;
             else if (lo_prec == D2D_BF16) ((uint16_t*)lo)[e] = f32_bf16_rne((float)qv);
         }
     }
@@ -867,7 +867,7 @@ k_lz_first(const LzSeg* __restrict__ bt, const double* __restrict__ w,
     for (int64_t e = sg.lo + threadIdx.x; e < sg.hi; e += blockDim.x) {
         const double q = w[e] * inv;
         q1[e] = q;
-        if (lo_prec == D2D_FP32) ((float*)lo)[e] = (float)q;
+        if (lo_prec == D2D_FP32 || lo_prec == D2D_BF16X3) ((float*)lo)[e] = (float)q;
         else if (lo_prec == D2D_BF16) ((uint16_t*)lo)[e] = f32_bf16_rne((float)q);
     }
 }

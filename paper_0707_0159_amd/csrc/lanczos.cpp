@@ -29,7 +29,7 @@ namespace d2d {
 
 void free_lanczos_work(d2d_ctx* c, LanczosWork*& lw) {
     if (!lw) return;
-    for (int p = 0; p < 3; ++p) {
+    for (int p = 0; p < D2D_NPREC; ++p) {
         if (lw->exec[p]) (void)hipGraphExecDestroy(lw->exec[p]);
         if (lw->graph[p]) (void)hipGraphDestroy(lw->graph[p]);
     }
@@ -192,7 +192,7 @@ d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bo
 }
 
 void drop_graphs(LanczosWork* w) {
-    for (int p = 0; p < 3; ++p) {
+    for (int p = 0; p < D2D_NPREC; ++p) {
         if (w->exec[p]) (void)hipGraphExecDestroy(w->exec[p]);
         if (w->graph[p]) (void)hipGraphDestroy(w->graph[p]);
         w->exec[p] = nullptr;
@@ -245,9 +245,9 @@ namespace d2d {
 
 d2d_status check_lanczos_opts(const d2d_lanczos_opts* o) {
     if (!o || o->k_in < 2 || o->k_in > 33 || o->max_restarts < 0 || !(o->tol_res > 0.0) || o->prec < 0 ||
-        o->prec > 2 || o->reorth_window < 0 || o->reorth_window == 1 || o->separate_central < 0 ||
+        o->prec >= D2D_NPREC || o->reorth_window < 0 || o->reorth_window == 1 || o->separate_central < 0 ||
         o->separate_central > 1 || !(o->tol_rel_e >= 0.0) || o->plain_cgs2 < 0 || o->plain_cgs2 > 1) {
-        set_error("Lanczos options: k_in 2..33, max_restarts >= 0, tol_res > 0, prec 0..2, reorth_window 0 or >= 2, "
+        set_error("Lanczos options: k_in 2..33, max_restarts >= 0, tol_res > 0, prec 0..3, reorth_window 0 or >= 2, "
                   "separate_central 0 or 1, tol_rel_e >= 0, plain_cgs2 0 or 1");
         return D2D_EINVAL;
     }
@@ -271,7 +271,8 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
     std::vector<int> act(np, 1);
     D2D_CHECK(set_active_flags(w, act));
     D2D_CHECK(hv.set_active(act, nullptr));
-    const int64_t cnt0[3] = {hv.counter(0), hv.counter(1), hv.counter(2)};
+    int64_t cnt0[D2D_NPREC];
+    for (int i = 0; i < D2D_NPREC; ++i) cnt0[i] = hv.counter(i);
     for (int p = 0; p < np; ++p) {
         if (v0 && v0[p])
             D2D_HIP(hipMemcpyAsync(w->X + w->seg_off[p], v0[p], (size_t)len[p] * 8, hipMemcpyDeviceToDevice, s));
@@ -336,8 +337,10 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
             }
         }
         if (escalate && prec != D2D_FP64) {
-            int nxt = prec == D2D_BF16 ? D2D_FP32 : D2D_FP64;
-            if (!hv.has(nxt)) nxt = D2D_FP64;
+            // BF16 -> BF16x3 (when kept) -> FP32 (when kept) -> FP64
+            int nxt = D2D_FP64;
+            if (prec == D2D_BF16 && hv.has(D2D_BF16X3)) nxt = D2D_BF16X3;
+            else if ((prec == D2D_BF16 || prec == D2D_BF16X3) && hv.has(D2D_FP32)) nxt = D2D_FP32;
             prec = nxt;
         }
         if (!any) break;
@@ -380,7 +383,7 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
         st[p].restarts = restarts[p];
         st[p].residual = rho[p];
         if (!done[p]) st[p].seconds = total;
-        for (int i = 0; i < 3; ++i) st[p].hv_count[i] = hv.counter(i) - cnt0[i];
+        for (int i = 0; i < D2D_NPREC; ++i) st[p].hv_count[i] = hv.counter(i) - cnt0[i];
         if (stats) stats[p] = st[p];
     }
     if (np == 1 && stats) stats[0].seconds = total;

@@ -98,9 +98,11 @@ d2d_sb::~d2d_sb() {
     if (!ctx) return;
     const size_t np = pairs.size();
     release(ctx, d_sec, np);
-    const size_t hls[3] = {(size_t)hl_len * 8, (size_t)hl_len * 4, (size_t)hl16_len * 2};
-    const size_t hrs[3] = {(size_t)hr_len * 8, (size_t)hr_len * 4, (size_t)hr16_len * 2};
-    for (int p = 0; p < 3; ++p) {
+    const size_t hls[D2D_NPREC] = {(size_t)hl_len * 8, (size_t)hl_len * 4, (size_t)hl16_len * 2,
+                                   (size_t)hl16_len * 4};
+    const size_t hrs[D2D_NPREC] = {(size_t)hr_len * 8, (size_t)hr_len * 4, (size_t)hr16_len * 2,
+                                   (size_t)hr16_len * 4};
+    for (int p = 0; p < D2D_NPREC; ++p) {
         if (HL[p]) ctx->free(HL[p], hls[p]);
         if (HR[p]) ctx->free(HR[p], hrs[p]);
         HL[p] = HR[p] = nullptr;
@@ -111,8 +113,8 @@ d2d_sb::~d2d_sb() {
     }
     if (d_w2) ctx->free(d_w2, (size_t)N * 8);
     d_w2 = nullptr;
-    release(ctx, d_vp, (size_t)vp_len);
-    release(ctx, d_vt, (size_t)vt_len);
+    release(ctx, d_vp, (size_t)vp_len * vparts);
+    release(ctx, d_vt, (size_t)vt_len * vparts);
     release(ctx, d_ptiles, (size_t)n_ptiles);
     release(ctx, d_src, np * K);
     release(ctx, d_rmap, (size_t)K * Drows);
@@ -140,6 +142,7 @@ int sb_auto_tile(const d2d_sb* sb, int prec) {
     if (prec == D2D_FP64) return D <= 64 ? 0 : (D <= 768 ? 1 : 2);
     if (prec == D2D_FP32) return D <= 64 ? 3 : (D <= 768 ? 4 : 5);
     if (prec == D2D_BF16) return D <= 64 ? 17 : (D <= 512 ? 14 : 15);
+    if (prec == D2D_BF16X3) return D <= 64 ? 30 : (D <= 512 ? 28 : 29);
     return -1;
 }
 
@@ -305,9 +308,17 @@ d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkItem* wor
         c.W = w;
         for (int i = 0; i < 3; ++i) c.X[i] = t.x[i];
     }
-    if (prec == D2D_BF16) {
-        if (stages & HV_PACK) D2D_HIP(launch_pack_bf16(t.ptiles, t.n_ptiles, t.sec, (const bf16_t*)v, t.vp, t.vt, s));
+    if (prec == D2D_BF16 || prec == D2D_BF16X3) {
+        if (stages & HV_PACK) {
+            if (prec == D2D_BF16)
+                D2D_HIP(launch_pack_bf16(t.ptiles, t.n_ptiles, t.sec, (const bf16_t*)v, t.vp, t.vt, s));
+            else
+                D2D_HIP(launch_pack_bf16x3(t.ptiles, t.n_ptiles, t.sec, (const float*)v, t.vp, t.vt, t.lo[2],
+                                           t.lo[3], s));
+        }
         g.V = t.vp;
+        if (prec == D2D_BF16X3)
+            for (int i = 0; i < 4; ++i) g.lo[i] = t.lo[i];
         if (stages & HV_GEMM) D2D_HIP(launch_hv_gemm_bf16(shape, g, t.vt, s));
     } else {
         if (stages & HV_GEMM) D2D_HIP(launch_hv_gemm(shape, g, s));
@@ -320,10 +331,14 @@ static HvTables tables_of(d2d_sb* sb) {
     HvTables t{};
     t.sec = sb->d_sec;
     t.npairs = (int)sb->pairs.size();
-    for (int p = 0; p < 3; ++p) {
+    for (int p = 0; p < D2D_NPREC; ++p) {
         t.HL[p] = sb->HL[p];
         t.HR[p] = sb->HR[p];
     }
+    t.lo[0] = sb->hl16_len;
+    t.lo[1] = sb->hr16_len;
+    t.lo[2] = sb->vp_len;
+    t.lo[3] = sb->vt_len;
     t.K = sb->K;
     t.src = sb->d_src;
     t.rmap = sb->d_rmap;
@@ -354,7 +369,7 @@ d2d_status sb_ensure_parts(d2d_sb* sb, int split, bool central) {
 
 d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s, int stages,
                        HvParts* parts) {
-    if (prec < 0 || prec > 2 || !(sb->prec_mask & (1u << prec)) || !sb->HL[prec]) {
+    if (prec < 0 || prec >= D2D_NPREC || !(sb->prec_mask & (1u << prec)) || !sb->HL[prec]) {
         set_error("precision %d not available on this superblock", prec);
         return D2D_EINVAL;
     }
@@ -405,7 +420,7 @@ extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d
         set_error("d2d_sb_create: blocks 1 and 4 must have the same number of states (%d vs %d)", b1->m, b4->m);
         return D2D_EINVAL;
     }
-    if (prec_mask & ~7u) {
+    if (prec_mask & ~15u) {
         set_error("d2d_sb_create: unknown precision bits 0x%x", prec_mask);
         return D2D_EINVAL;
     }
@@ -523,17 +538,26 @@ extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d
         D2D_HIP(launch_cast_f64_f32((const double*)sb->HL[0], (float*)sb->HL[1], hl, ctx->stream));
         D2D_HIP(launch_cast_f64_f32((const double*)sb->HR[0], (float*)sb->HR[1], hr, ctx->stream));
     }
-    if (prec_mask & (1u << D2D_BF16)) {
+    const bool want16 = (prec_mask & (1u << D2D_BF16)) != 0, want3 = (prec_mask & (1u << D2D_BF16X3)) != 0;
+    if (want16 || want3) {
+        // BF16 operators: one copy (BF16) and / or hi and lo copies (BF16x3,
+        // lo at hl16_len / hr16_len elements after hi); the padded input
+        // copies VP / VT hold the lo parts after the hi parts when BF16x3 is kept
         const size_t h16 = (size_t)sb->hl16_len * 2, r16 = (size_t)sb->hr16_len * 2;
-        D2D_CHECK(ctx->alloc(&sb->HL[D2D_BF16], h16));
-        D2D_CHECK(ctx->alloc(&sb->HR[D2D_BF16], r16));
-        D2D_CHECK(ctx->alloc((void**)&sb->d_vp, (size_t)sb->vp_len * 2));
-        D2D_CHECK(ctx->alloc((void**)&sb->d_vt, (size_t)sb->vt_len * 2));
-        // padding of every K-major operand is zero and stays zero
-        D2D_HIP(hipMemset(sb->HL[D2D_BF16], 0, h16));
-        D2D_HIP(hipMemset(sb->HR[D2D_BF16], 0, r16));
-        D2D_HIP(hipMemset(sb->d_vp, 0, (size_t)sb->vp_len * 2));
-        D2D_HIP(hipMemset(sb->d_vt, 0, (size_t)sb->vt_len * 2));
+        sb->vparts = want3 ? 2 : 1;
+        for (int kind : {D2D_BF16, D2D_BF16X3}) {
+            if (!(prec_mask & (1u << kind))) continue;
+            const size_t np = kind == D2D_BF16X3 ? 2 : 1;
+            D2D_CHECK(ctx->alloc(&sb->HL[kind], h16 * np));
+            D2D_CHECK(ctx->alloc(&sb->HR[kind], r16 * np));
+            // padding of every K-major operand is zero and stays zero
+            D2D_HIP(hipMemset(sb->HL[kind], 0, h16 * np));
+            D2D_HIP(hipMemset(sb->HR[kind], 0, r16 * np));
+        }
+        D2D_CHECK(ctx->alloc((void**)&sb->d_vp, (size_t)sb->vp_len * 2 * sb->vparts));
+        D2D_CHECK(ctx->alloc((void**)&sb->d_vt, (size_t)sb->vt_len * 2 * sb->vparts));
+        D2D_HIP(hipMemset(sb->d_vp, 0, (size_t)sb->vp_len * 2 * sb->vparts));
+        D2D_HIP(hipMemset(sb->d_vt, 0, (size_t)sb->vt_len * 2 * sb->vparts));
         const int npp = (int)sb->pairs.size();
         std::vector<int64_t> so_l(npp), so_r(npp), do_l(npp), do_r(npp);
         std::vector<int32_t> dl(npp), dlp(npp), dr(npp), drp(npp);
@@ -551,11 +575,17 @@ extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d
             (st = upload(ctx, do_l, &a3)) == D2D_OK && (st = upload(ctx, do_r, &a4)) == D2D_OK &&
             (st = upload(ctx, dl, &b1)) == D2D_OK && (st = upload(ctx, dlp, &b2)) == D2D_OK &&
             (st = upload(ctx, dr, &b3)) == D2D_OK && (st = upload(ctx, drp, &b4)) == D2D_OK) {
-            hipError_t e = launch_op_bf16(a1, a3, b1, b2, npp, 1, (const double*)sb->HL[0], (bf16_t*)sb->HL[2], mx,
-                                          ctx->stream);
-            if (e == hipSuccess)
-                e = launch_op_bf16(a2, a4, b3, b4, npp, 0, (const double*)sb->HR[0], (bf16_t*)sb->HR[2], mx,
-                                   ctx->stream);
+            hipError_t e = hipSuccess;
+            for (int kind : {D2D_BF16, D2D_BF16X3}) {
+                if (!(prec_mask & (1u << kind))) continue;
+                for (int part = 0; part < (kind == D2D_BF16X3 ? 2 : 1) && e == hipSuccess; ++part) {
+                    e = launch_op_bf16(a1, a3, b1, b2, npp, 1, part, (const double*)sb->HL[0],
+                                       (bf16_t*)sb->HL[kind] + part * sb->hl16_len, mx, ctx->stream);
+                    if (e == hipSuccess)
+                        e = launch_op_bf16(a2, a4, b3, b4, npp, 0, part, (const double*)sb->HR[0],
+                                           (bf16_t*)sb->HR[kind] + part * sb->hr16_len, mx, ctx->stream);
+                }
+            }
             if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
             if (e != hipSuccess) {
                 set_error("BF16 operator conversion failed: %s", hipGetErrorString(e));
@@ -728,6 +758,7 @@ extern "C" d2d_status d2d_sb_info(const d2d_sb* sb, d2d_sb_info_t* info) {
     info->bytes_min_fp64 = 3.0 * N * 8 + ops * 8;
     info->bytes_min_fp32 = 3.0 * N * 4 + ops * 4;
     info->bytes_min_bf16 = 2.0 * N * 2 + N * 4 + ops * 2;
+    info->bytes_min_bf16x3 = 2.0 * N * 4 + N * 4 + ops * 4;
     return D2D_OK;
 }
 
@@ -779,17 +810,17 @@ extern "C" d2d_status d2d_hv(d2d_sb* sb, int prec, const void* v, void* w) {
     return sb_hv(sb, prec, v, w, sb->ctx->stream);
 }
 
-extern "C" d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[3]) {
+extern "C" d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[D2D_NPREC]) {
     if (!sb || !counts) {
         set_error("d2d_hv_count: NULL argument");
         return D2D_EINVAL;
     }
-    for (int i = 0; i < 3; ++i) counts[i] = sb->hv_count[i];
+    for (int i = 0; i < D2D_NPREC; ++i) counts[i] = sb->hv_count[i];
     return D2D_OK;
 }
 
 extern "C" d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile) {
-    if (!sb || prec < 0 || prec > 2) {
+    if (!sb || prec < 0 || prec >= D2D_NPREC) {
         set_error("d2d_sb_set_tile: bad argument");
         return D2D_EINVAL;
     }
@@ -883,7 +914,7 @@ static uint64_t sector_key(const d2d_sb* sb, int prec) {
 }
 
 extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_tile, double* best_ms) {
-    if (!sb || !best_tile || !best_ms || prec < 0 || prec > 2 || reps < 1 || reps > 10000) {
+    if (!sb || !best_tile || !best_ms || prec < 0 || prec >= D2D_NPREC || reps < 1 || reps > 10000) {
         set_error("d2d_sb_autotune: bad argument");
         return D2D_EINVAL;
     }
@@ -917,7 +948,7 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
     }
     d2d_ctx* ctx = sb->ctx;
     hipStream_t s = ctx->stream;
-    const size_t in_sz = prec == D2D_FP64 ? 8 : (prec == D2D_FP32 ? 4 : 2);
+    const size_t in_sz = prec == D2D_FP64 ? 8 : (prec == D2D_BF16 ? 2 : 4);
     const size_t out_sz = prec == D2D_FP64 ? 8 : 4;
     void *v = nullptr, *w = nullptr;
     D2D_CHECK(ctx->alloc(&v, (size_t)sb->N * in_sz));

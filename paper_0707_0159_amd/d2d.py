@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libd2d.so")
 
 D2D_OK, D2D_EINVAL, D2D_ENOMEM, D2D_EDEVICE, D2D_ENOCONV, D2D_ESTATE = 0, -1, -2, -3, -4, -5
-D2D_FP64, D2D_FP32, D2D_BF16 = 0, 1, 2
+D2D_FP64, D2D_FP32, D2D_BF16, D2D_BF16X3 = 0, 1, 2, 3
+D2D_NPREC = 4
 D2D_HEISENBERG, D2D_HUBBARD = 0, 1
 D2D_LOG_MAX = 256
 D2D_TILE_SPLIT = 1 << 16
@@ -48,7 +49,7 @@ class d2d_sb_info_t(C.Structure):
                 ("nterms", C.c_int32), ("max_dl", C.c_int32), ("max_dr", C.c_int32),
                 ("flops_exec", C.c_double), ("flops_nnz", C.c_double), ("flops_central", C.c_double),
                 ("bytes_min_fp64", C.c_double), ("bytes_min_fp32", C.c_double), ("bytes_min_bf16", C.c_double),
-                ("op_entries", C.c_int64)]
+                ("op_entries", C.c_int64), ("bytes_min_bf16x3", C.c_double)]
 
 
 class d2d_lanczos_opts(C.Structure):
@@ -59,7 +60,7 @@ class d2d_lanczos_opts(C.Structure):
 
 
 class d2d_lanczos_stats(C.Structure):
-    _fields_ = [("restarts", C.c_int), ("hv_count", C.c_int64 * 3), ("residual", C.c_double),
+    _fields_ = [("restarts", C.c_int), ("hv_count", C.c_int64 * D2D_NPREC), ("residual", C.c_double),
                 ("seconds", C.c_double), ("nlog", C.c_int), ("log_t", C.c_double * D2D_LOG_MAX),
                 ("log_theta", C.c_double * D2D_LOG_MAX), ("log_rho", C.c_double * D2D_LOG_MAX),
                 ("log_prec", C.c_int * D2D_LOG_MAX)]
@@ -293,7 +294,7 @@ def d2d_hv_profile(sb: int, prec: int, v, w, reps: int = 20):
 
 
 def d2d_hv_count(sb: int):
-    c = np.zeros(3, np.int64)
+    c = np.zeros(D2D_NPREC, np.int64)
     _check(load().d2d_hv_count(P(sb), c.ctypes.data_as(i64p)))
     return c
 

@@ -22,13 +22,13 @@ def ctx():
 
 
 def mixed_problems(ctx):
-    return [GpuProblem(ctx, W.CONFIGS[1], prec_mask=7),
-            GpuProblem(ctx, W.CONFIGS[2], prec_mask=7),
-            GpuProblem(ctx, W.CONFIGS[1], target=(7, 0), prec_mask=7),
-            GpuProblem(ctx, W.CONFIGS[1], target=(2, 0), prec_mask=7)]
+    return [GpuProblem(ctx, W.CONFIGS[1], prec_mask=15),
+            GpuProblem(ctx, W.CONFIGS[2], prec_mask=15),
+            GpuProblem(ctx, W.CONFIGS[1], target=(7, 0), prec_mask=15),
+            GpuProblem(ctx, W.CONFIGS[1], target=(2, 0), prec_mask=15)]
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 3])
 def test_batch_hv_equals_single(ctx, prec):
     from paper_0707_0159_amd import d2d
     probs = mixed_problems(ctx)
@@ -47,7 +47,10 @@ def test_batch_hv_equals_single(ctx, prec):
     d2d.d2d_batch_hv(b, prec, vs, ws)
     ctx.stream.synchronize()
     max_d = max(max(p.info["max_dl"], p.info["max_dr"]) for p in probs)
-    shape = (1 if max_d <= 768 else 2) if prec == 0 else (4 if max_d <= 768 else 5)
+    if prec == 3:
+        shape = 30 if max_d <= 64 else (28 if max_d <= 512 else 29)
+    else:
+        shape = (1 if max_d <= 768 else 2) if prec == 0 else (4 if max_d <= 768 else 5)
     if max_d <= 768:
         shape |= d2d.D2D_TILE_SPLIT      # the batch splits the K-loops of small sectors
     for p, v, r in zip(probs, vs, refs):
@@ -61,7 +64,7 @@ def test_batch_hv_equals_single(ctx, prec):
         p.close()
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_batch_lanczos_energies(ctx, prec):
     from paper_0707_0159_amd import d2d
     probs = mixed_problems(ctx)

@@ -143,6 +143,32 @@ def oracle_hv_bf16_operands(osb, v):
     return w
 
 
+def bf16x3_parts(x):
+    """float64 -> float32, then hi = bf16(x), lo = bf16(x - hi) (each RNE), as float64."""
+    f = np.asarray(x, dtype=np.float32).astype(np.float64)
+    hi = bf16_round(f)
+    return hi, bf16_round(f - hi)          # f - hi is exact in float32
+
+
+def oracle_hv_bf16x3_operands(osb, v):
+    """The oracle's matrix form with every GEMM product formed as hi*hi + hi*lo +
+    lo*hi of the bf16 parts (lo*lo dropped); the central term on float32(v)."""
+    vh, vl = bf16x3_parts(v)
+    vf = np.asarray(v, dtype=np.float32).astype(np.float64)
+    w = np.zeros_like(vf)
+    for (q, r, c, o), (hl, hr) in zip(osb.sectors, osb.dense_sectors()):
+        dL, dR = r.size, c.size
+        Vh = vh[o:o + dL * dR].reshape(dR, dL).T
+        Vl = vl[o:o + dL * dR].reshape(dR, dL).T
+        Lh, Ll = bf16x3_parts(hl)
+        Rh, Rl = bf16x3_parts(hr)
+        W = Lh @ Vh + Lh @ Vl + Ll @ Vh + Vh @ Rh.T + Vh @ Rl.T + Vl @ Rh.T
+        w[o:o + dL * dR] = W.T.reshape(-1)
+    for hc, pidx in osb.central_groups():
+        w[pidx] += hc @ vf[pidx]
+    return w
+
+
 def gpu_hv_bf16(ctx, prob, v):
     from paper_0707_0159_amd import d2d
     with torch.cuda.stream(ctx.stream):
@@ -202,4 +228,33 @@ def test_pack_unpack_full_space(ctx, cfg, target):
     assert np.array_equal(pd.cpu().numpy(), packed)
     assert np.array_equal(fd.cpu().numpy(), osb.unpack(packed))
     del xd, pd, fd
+    prob.close()
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_bf16x3_every_tile_shape(ctx, cfg):
+    """BF16x3 (hi/lo bf16 parts of FP32 operands, three products, FP32
+    accumulation): equal to the oracle computing the same three products in
+    float64 up to FP32 accumulation (<= 1e-5), and within 1e-4 of the exact product."""
+    from paper_0707_0159_amd import d2d
+    wl = W.CONFIGS[cfg]
+    osb = oracle_superblock(wl)
+    prob = GpuProblem(ctx, wl, prec_mask=15)
+    shapes = [i | sp for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == d2d.D2D_BF16X3
+              for sp in (0, d2d.D2D_TILE_SPLIT, d2d.D2D_TILE_SPLIT4, d2d.D2D_TILE_XCD)]
+    assert shapes
+    worst = 0.0
+    for k in range(2):
+        v = W.random_vector(osb.N, 1000 + k)
+        ref3 = oracle_hv_bf16x3_operands(osb, v)
+        ref = osb.hv_factored(v)
+        for sh in shapes:
+            d2d.d2d_sb_set_tile(prob.sb, d2d.D2D_BF16X3, sh)
+            w = gpu_hv(ctx, prob, d2d.D2D_BF16X3, v)
+            e1, e2 = rel_err(w, ref3), rel_err(w, ref)
+            print(f"config {cfg} bf16x3 shape {sh}: vs split-operand oracle {e1:.3e}, vs exact {e2:.3e}")
+            worst = max(worst, e2)
+            assert e1 <= 1e-5
+            assert e2 <= 1e-4
+    print("worst vs exact", worst)
     prob.close()

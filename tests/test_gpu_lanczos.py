@@ -51,13 +51,13 @@ def test_config1_energy(ctx, prec, graph):
     prob.close()
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 @pytest.mark.parametrize("window,plain", [(0, 0), (3, 0), (3, 1), (2, 0), (4, 0)])
 def test_config2_energy(ctx, prec, window, plain):
     """Full reorthogonalisation, and windows of 2..4 in the two-kernel Gram form
     and the three-kernel two-pass form."""
     wl = W.CONFIGS[2]
-    prob = GpuProblem(ctx, wl, prec_mask=7)
+    prob = GpuProblem(ctx, wl, prec_mask=15)
     st, e, stats, psi = run(ctx, prob, prec, wl.seed, window=window, plain=plain)
     E0 = reference_energy(wl.name)
     print("config2", prec, window, plain, e, E0, (e - E0) / abs(E0), stats["restarts"], stats["hv_count"],
@@ -68,7 +68,7 @@ def test_config2_energy(ctx, prec, window, plain):
     prob.close()
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 @pytest.mark.parametrize("split", [0, 1, 2])
 def test_fused_central_is_bitwise_separate(ctx, prec, split):
     """One launch for GEMM + central term (parts added by the first step kernel)
@@ -77,7 +77,7 @@ def test_fused_central_is_bitwise_separate(ctx, prec, split):
     halved K-loops."""
     from paper_0707_0159_amd import d2d
     wl = W.CONFIGS[2]
-    prob = GpuProblem(ctx, wl, prec_mask=7)
+    prob = GpuProblem(ctx, wl, prec_mask=15)
     shape = next(i for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == prec)
     flag = [0, d2d.D2D_TILE_SPLIT, d2d.D2D_TILE_SPLIT4][split]
     d2d.d2d_sb_set_tile(prob.sb, prec, shape | flag | d2d.D2D_TILE_FUSED)
@@ -131,6 +131,27 @@ def test_energy_change_stop(ctx):
     assert st == 0
     assert abs(th[-1] - th[-2]) <= 1e-13 * abs(th[-1])
     assert abs(e - E0) <= 1e-10 * abs(E0)
+    prob.close()
+
+
+def test_escalation_from_bf16_through_bf16x3(ctx):
+    """Precision schedule: a BF16 start escalates to BF16x3 when BF16 stalls (a
+    tiny escalate threshold forces it at the second restart), then to FP32 and
+    FP64; the energy still meets the bar."""
+    from paper_0707_0159_amd import d2d
+    wl = W.CONFIGS[2]
+    prob = GpuProblem(ctx, wl, prec_mask=15)
+    n = prob.info["n"]
+    with torch.cuda.stream(ctx.stream):
+        v0 = torch.as_tensor(W.random_vector(n, wl.seed)).to("cuda")
+    ctx.stream.synchronize()
+    opts = d2d.lanczos_opts(prec=2, k_in=24, max_restarts=300, tol_res=1e-8, reorth_window=3, escalate=1e-6)
+    st, e, stats = d2d.d2d_lanczos(prob.sb, opts, v0)
+    E0 = reference_energy(wl.name)
+    seen = list(dict.fromkeys(stats["log_prec"]))
+    print("escalation", seen, stats["hv_count"], e)
+    assert st == 0 and abs(e - E0) <= 1e-10 * abs(E0)
+    assert seen[:2] == [2, 3]
     prob.close()
 
 
