@@ -31,7 +31,7 @@ def problem(request, ctx):
     wl = W.CONFIGS[request.param]
     print(f"building {wl.name}", flush=True)
     osb = oracle_superblock(wl)
-    prob = GpuProblem(ctx, wl, prec_mask=7)
+    prob = GpuProblem(ctx, wl, prec_mask=15)
     yield wl, osb, prob
     prob.close()
 
@@ -58,7 +58,7 @@ def test_full_size_hv(ctx, problem):
     assert prob.info["n"] == osb.N
     qL, dL, dR, off = d2d.d2d_sb_sectors(prob.sb)
     assert [tuple(q) for q in qL] == [s[0] for s in osb.sectors]
-    for prec in (0, 1, 2):
+    for prec in (0, 1, 2, 3):
         d2d.d2d_sb_autotune(prob.sb, prec, reps=3)
     v = W.random_vector(osb.N, 1000)
     ref = osb.hv_factored(v)
@@ -67,14 +67,17 @@ def test_full_size_hv(ctx, problem):
     w16 = hv(ctx, prob, 2, v)
     e16 = rel_err(w16, ref)
     e16b = rel_err(w16, oracle_hv_bf16_operands(osb, v))
-    print(f"{wl.name}: N={osb.N} fp64 {e64:.3e} fp32 {e32:.3e} bf16 {e16:.3e} (vs bf16-operand oracle {e16b:.3e})")
+    e3 = rel_err(hv(ctx, prob, 3, v), ref)
+    print(f"{wl.name}: N={osb.N} fp64 {e64:.3e} fp32 {e32:.3e} bf16 {e16:.3e} (vs bf16-operand oracle {e16b:.3e}) "
+          f"bf16x3 {e3:.3e}")
     assert e64 <= 1e-12
     assert e32 <= 1e-5
     assert e16b <= 1e-5
     assert e16 <= 2e-2
+    assert e3 <= 1e-4
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_full_size_energy(ctx, problem, prec):
     from paper_0707_0159_amd import d2d
     wl, osb, prob = problem
