@@ -344,6 +344,23 @@ d2d_status d2d_batch_create(d2d_ctx* ctx, d2d_sb* const* sbs, int n, d2d_batch**
 d2d_status d2d_batch_destroy(d2d_batch* b);
 /* One batched Hv: v[i], w[i] device pointers of problem i (precision prec). */
 d2d_status d2d_batch_hv(d2d_batch* b, int prec, const void* const* v, void* const* w);
+/* Launch configuration of the batch's grouped launches in precision prec, as
+ * d2d_sb_set_tile for one superblock (shape index OR-ed with the D2D_TILE_*
+ * flags).  tile -1 restores the default: shape by the largest sector
+ * dimension, K-loops split when every sector dimension is at most 768, central
+ * term fused except in FP64, plain order.  The superblocks' own settings are
+ * not used by, nor changed by, the batch.  D2D_EINVAL for a shape not built
+ * for prec or unknown flags. */
+d2d_status d2d_batch_set_tile(d2d_batch* b, int prec, int tile);
+/* Autotuner of the batch, as d2d_sb_autotune: every shape of prec x split
+ * level x fused x XCD order timed over reps batched Hv with all problems
+ * active (on the batch's staging vectors, HIP events on the context stream);
+ * the fastest is kept for later d2d_batch_hv / d2d_batch_lanczos calls and
+ * returned (best_tile as for d2d_batch_set_tile, best_ms its average
+ * milliseconds per batched Hv).  D2D_TUNE_CACHE is consulted and appended as
+ * for a superblock (key: precision, problem count and every sector
+ * dimension).  Synchronous.  On an error the previous configuration stays. */
+d2d_status d2d_batch_autotune(d2d_batch* b, int prec, int reps, int* best_tile, double* best_ms);
 /* Batched restarted Lanczos; v0[i] device start vectors (array or entries
  * nullable: seeded as for d2d_lanczos with seed opts.seed + i); energies host out
  * [n]; psi[i] device out (nullable array or entries); per_problem (nullable)

@@ -39,12 +39,17 @@ struct d2d_batch {
     int n_ptiles = 0, cap_ptiles = 0;
     bf16_t *d_vp = nullptr, *d_vt = nullptr;
     int64_t vp_len = 0, vt_len = 0;
-    std::map<int, std::pair<WorkItem*, int>> work;   // shape -> (table, count), active problems only
+    // work_key(shape, split, xcd) -> (table, count), active problems only
+    std::map<int, std::pair<WorkItem*, int>> work;
     std::map<int, int> work_cap;
     std::vector<int> active;
     int64_t hv_count[D2D_NPREC] = {0, 0, 0, 0};
-    int split = 0;                      // split K-loops (small, latency-bound sectors)
-    void* d_w1 = nullptr;               // ntot doubles
+    // launch configuration per precision (as on a single superblock)
+    int tile_sel[D2D_NPREC] = {-1, -1, -1, -1};   // shape index, or -1 = by size
+    int split[D2D_NPREC] = {0, 0, 0, 0};          // K-loop split level
+    int fuse[D2D_NPREC] = {0, 1, 1, 1};           // central term inside the GEMM launch (inner steps)
+    int xcd[D2D_NPREC] = {0, 0, 0, 0};            // XCD-aware work order
+    void* d_x[3] = {nullptr, nullptr, nullptr};   // ntot doubles each, partial outputs of split K-loops
     void* d_w2 = nullptr;               // ntot doubles, central-term part of fused launches
     void* stage_v = nullptr;
     void* stage_w = nullptr;
@@ -77,15 +82,22 @@ int batch_auto_tile(const d2d_batch* b, int prec) {
     return D <= 64 ? 17 : (D <= 512 ? 14 : 15);
 }
 
-// Launch tables of the active problems (work list of one shape, central and pack tiles).
-d2d_status build_work(d2d_batch* b, int shape) {
+int work_key(int shape, int split, int xcd) { return shape | split << 16 | xcd << 18; }
+
+int batch_shape(const d2d_batch* b, int prec) {
+    return b->tile_sel[prec] >= 0 ? b->tile_sel[prec] : batch_auto_tile(b, prec);
+}
+
+// Launch tables of the active problems (work list of one shape, split level and
+// order; central and pack tiles).
+d2d_status build_work(d2d_batch* b, int key) {
     std::vector<int> keep(b->pairs.size());
     for (size_t p = 0; p < b->pairs.size(); ++p) keep[p] = b->active[b->pair_prob[p]];
     std::vector<WorkItem> w;
-    make_work(b->pairs, &keep, tile_shape(shape), b->split, 0, w);
-    auto it = b->work.find(shape);
-    if (it != b->work.end() && b->work_cap[shape] < (int)w.size()) {
-        dfree(b->ctx, it->second.first, (size_t)b->work_cap[shape]);
+    make_work(b->pairs, &keep, tile_shape(key & 0xFFFF), (key >> 16) & 3, (key >> 18) & 1, w);
+    auto it = b->work.find(key);
+    if (it != b->work.end() && b->work_cap[key] < (int)w.size()) {
+        dfree(b->ctx, it->second.first, (size_t)b->work_cap[key]);
         b->work.erase(it);
         it = b->work.end();
     }
@@ -93,10 +105,10 @@ d2d_status build_work(d2d_batch* b, int shape) {
         WorkItem* d = nullptr;
         const size_t cap = std::max<size_t>(w.size(), 1);
         D2D_CHECK(b->ctx->alloc((void**)&d, cap * sizeof(WorkItem)));
-        b->work[shape] = {d, 0};
-        b->work_cap[shape] = (int)cap;
+        b->work[key] = {d, 0};
+        b->work_cap[key] = (int)cap;
     }
-    auto& e = b->work[shape];
+    auto& e = b->work[key];
     if (!w.empty()) D2D_HIP(hipMemcpy(e.first, w.data(), w.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
     e.second = (int)w.size();
     return D2D_OK;
@@ -162,8 +174,16 @@ HvTables tables_of(d2d_batch* b) {
     t.n_ptiles = b->n_ptiles;
     t.vp = b->d_vp;
     t.vt = b->d_vt;
-    if (b->split) t.x[0] = b->d_w1;
     return t;
+}
+
+// Work list of the precision's current launch configuration (built on first use).
+d2d_status batch_work(d2d_batch* b, int prec, int* shape, std::pair<WorkItem*, int>** wl) {
+    *shape = batch_shape(b, prec);
+    const int key = work_key(*shape, b->split[prec], b->xcd[prec]);
+    if (b->work.find(key) == b->work.end()) D2D_CHECK(build_work(b, key));
+    *wl = &b->work[key];
+    return D2D_OK;
 }
 
 d2d_status batch_hv(d2d_batch* b, int prec, const void* v, void* w, hipStream_t s, HvParts* parts = nullptr) {
@@ -171,12 +191,15 @@ d2d_status batch_hv(d2d_batch* b, int prec, const void* v, void* w, hipStream_t 
         set_error("precision %d not kept by every superblock of the batch", prec);
         return D2D_EINVAL;
     }
-    const int shape = batch_auto_tile(b, prec);
-    if (b->work.find(shape) == b->work.end()) D2D_CHECK(build_work(b, shape));
-    auto& wl = b->work[shape];
+    int shape = 0;
+    std::pair<WorkItem*, int>* wl = nullptr;
+    D2D_CHECK(batch_work(b, prec, &shape, &wl));
     HvTables t = tables_of(b);
-    if (parts && prec == D2D_FP64) {
-        // FP64: the central term's register demand lowers the GEMM's occupancy
+    for (int i = 0; i < split_parts(b->split[prec]); ++i) {
+        if (!b->d_x[i]) D2D_CHECK(b->ctx->alloc(&b->d_x[i], (size_t)b->ntot * 8));
+        t.x[i] = b->d_x[i];
+    }
+    if (parts && !b->fuse[prec]) {
         *parts = HvParts{};
         parts = nullptr;
     }
@@ -185,7 +208,7 @@ d2d_status batch_hv(d2d_batch* b, int prec, const void* v, void* w, hipStream_t 
         for (int i = 0; i < 3; ++i) parts->x[i] = t.x[i];
         parts->central = t.w2;
     }
-    return hv_launch(t, prec, shape, wl.first, wl.second, v, w, s);
+    return hv_launch(t, prec, shape, wl->first, wl->second, v, w, s);
 }
 
 struct BatchHv : HvOps {
@@ -196,8 +219,11 @@ struct BatchHv : HvOps {
         return batch_hv(b, prec, v, w, s, parts);
     }
     d2d_status prepare(int prec) override {
-        const int shape = batch_auto_tile(b, prec);
-        if (b->work.find(shape) == b->work.end()) return build_work(b, shape);
+        int shape = 0;
+        std::pair<WorkItem*, int>* wl = nullptr;
+        D2D_CHECK(batch_work(b, prec, &shape, &wl));
+        for (int i = 0; i < split_parts(b->split[prec]); ++i)
+            if (!b->d_x[i]) D2D_CHECK(b->ctx->alloc(&b->d_x[i], (size_t)b->ntot * 8));
         return D2D_OK;
     }
     d2d_status set_active(const std::vector<int>& a, bool* rebuilt) override {
@@ -240,7 +266,8 @@ d2d_batch::~d2d_batch() {
     dfree(ctx, d_vp, (size_t)vp_len * vparts);
     dfree(ctx, d_vt, (size_t)vt_len * vparts);
     for (auto& kv : work) dfree(ctx, kv.second.first, (size_t)work_cap[kv.first]);
-    if (d_w1) ctx->free(d_w1, (size_t)ntot * 8);
+    for (auto& x : d_x)
+        if (x) ctx->free(x, (size_t)ntot * 8);
     if (d_w2) ctx->free(d_w2, (size_t)ntot * 8);
     if (stage_v) ctx->free(stage_v, (size_t)ntot * 8);
     if (stage_w) ctx->free(stage_w, (size_t)ntot * 8);
@@ -383,8 +410,8 @@ extern "C" d2d_status d2d_batch_create(d2d_ctx* ctx, d2d_sb* const* sbs, int n, 
     D2D_CHECK(dupload(ctx, cc32, &b->d_cc32));
     b->active.assign(n, 1);
     // every sector small: the GEMM is latency-bound, split its two K-loops
-    b->split = std::max(b->max_dl, b->max_dr) <= 768 ? 1 : 0;
-    if (b->split) D2D_CHECK(ctx->alloc(&b->d_w1, (size_t)b->ntot * 8));
+    const int split = std::max(b->max_dl, b->max_dr) <= 768 ? 1 : 0;
+    for (int p = 0; p < D2D_NPREC; ++p) b->split[p] = split;
     D2D_CHECK(ctx->alloc(&b->d_w2, (size_t)b->ntot * 8));
     D2D_CHECK(build_tiles(b.get()));
     D2D_CHECK(ctx->alloc(&b->stage_v, (size_t)b->ntot * 8));
@@ -445,4 +472,97 @@ extern "C" d2d_status d2d_batch_lanczos(d2d_batch* b, const d2d_lanczos_opts* op
     }
     BatchHv ops(b);
     return run_lanczos(b->ctx, b->lz, ops, opts, b->len, v0, energies, psi, per_problem);
+}
+
+extern "C" d2d_status d2d_batch_set_tile(d2d_batch* b, int prec, int tile) {
+    if (!b || prec < 0 || prec >= D2D_NPREC) {
+        set_error("d2d_batch_set_tile: bad argument");
+        return D2D_EINVAL;
+    }
+    TileSel t;
+    if (!decode_tile(prec, tile, &t)) {
+        set_error("d2d_batch_set_tile: tile %d is not a shape of precision %d", tile, prec);
+        return D2D_EINVAL;
+    }
+    b->tile_sel[prec] = t.shape;
+    b->split[prec] = tile < 0 ? (std::max(b->max_dl, b->max_dr) <= 768 ? 1 : 0) : t.split;
+    b->fuse[prec] = t.fuse;
+    b->xcd[prec] = t.xcd;
+    return D2D_OK;
+}
+
+namespace {
+uint64_t batch_key(const d2d_batch* b, int prec) {
+    uint64_t h = 0x9e3779b97f4a7c15ull ^ (uint64_t)prec;
+    auto mix = [&](uint64_t v) {
+        h ^= v;
+        h *= 1099511628211ull;
+    };
+    mix(b->sbs.size());
+    for (const auto& p : b->pairs) {
+        mix((uint64_t)p.dL);
+        mix((uint64_t)p.dR);
+    }
+    return h;
+}
+}  // namespace
+
+extern "C" d2d_status d2d_batch_autotune(d2d_batch* b, int prec, int reps, int* best_tile, double* best_ms) {
+    if (!b || !best_tile || !best_ms || prec < 0 || prec >= D2D_NPREC || reps < 1 || reps > 10000) {
+        set_error("d2d_batch_autotune: bad argument");
+        return D2D_EINVAL;
+    }
+    if (!(b->prec_mask & (1u << prec)) || !b->HL[prec]) {
+        set_error("d2d_batch_autotune: precision %d not kept by every superblock", prec);
+        return D2D_EINVAL;
+    }
+    auto apply = [&](const TileSel& c) {
+        b->tile_sel[prec] = c.shape;
+        b->split[prec] = c.split;
+        b->fuse[prec] = c.fuse;
+        b->xcd[prec] = c.xcd;
+    };
+    const uint64_t key = batch_key(b, prec);
+    TileSel sel;
+    if (tune_cache_lookup(key, prec, &sel, best_tile, best_ms)) {
+        apply(sel);
+        return D2D_OK;
+    }
+    hipStream_t s = b->ctx->stream;
+    const TileSel saved{b->tile_sel[prec], b->split[prec], b->fuse[prec], b->xcd[prec]};
+    // every problem active, as at the start of a solve
+    BatchHv ops(b);
+    D2D_CHECK(ops.set_active(std::vector<int>(b->sbs.size(), 1), nullptr));
+    if (launch_fill(b->stage_v, prec, b->ntot, 0.5, s) != hipSuccess) {
+        set_error("d2d_batch_autotune: HIP setup failed");
+        return D2D_EDEVICE;
+    }
+    double bms = 0;
+    const d2d_status st = tune_configs(s, prec, reps, [&](const TileSel& c) {
+        apply(c);
+        HvParts parts{};
+        return batch_hv(b, prec, b->stage_v, b->stage_w, s, c.fuse ? &parts : nullptr);
+    }, &sel, &bms);
+    if (st != D2D_OK) {
+        apply(saved);
+    } else {
+        apply(sel);
+        *best_tile = encode_tile(sel);
+        *best_ms = bms;
+        tune_cache_store(key, *best_tile, bms);
+    }
+    // keep only the work lists still selected (set_active rebuilds every list held)
+    std::vector<int> keys;
+    for (int p = 0; p < D2D_NPREC; ++p)
+        if (b->HL[p]) keys.push_back(work_key(batch_shape(b, p), b->split[p], b->xcd[p]));
+    for (auto it = b->work.begin(); it != b->work.end();) {
+        if (std::find(keys.begin(), keys.end(), it->first) == keys.end()) {
+            dfree(b->ctx, it->second.first, (size_t)b->work_cap[it->first]);
+            b->work_cap.erase(it->first);
+            it = b->work.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    return st;
 }

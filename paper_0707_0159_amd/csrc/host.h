@@ -1,6 +1,7 @@
 // Host-side objects of libd2d (not part of the ABI).
 #pragma once
 
+#include <functional>
 #include <map>
 #include <memory>
 #include <utility>
@@ -234,6 +235,23 @@ d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t
 // partial outputs of a split level (and the central part) allocated on demand
 d2d_status sb_ensure_parts(d2d_sb* sb, int split, bool central);
 int sb_auto_tile(const d2d_sb* sb, int prec);
+// a launch configuration: shape index (-1 = by size), K-loop split level, central
+// term fused into the GEMM launch, XCD-aware order
+struct TileSel {
+    int shape = -1, split = 0, fuse = 0, xcd = 0;
+};
+// d2d_sb_set_tile's tile argument (shape | D2D_TILE_* flags, or -1) for precision
+// prec; false when it names no shape of that precision or unknown flags
+bool decode_tile(int prec, int tile, TileSel* out);
+int encode_tile(const TileSel& t);
+// Autotuner core: for every shape of precision prec x split level x fused x XCD
+// order, run(c) once to warm up and reps times between HIP events on s; the
+// fastest configuration and its average milliseconds per run.
+d2d_status tune_configs(hipStream_t s, int prec, int reps, const std::function<d2d_status(const TileSel&)>& run,
+                        TileSel* best, double* best_ms);
+// D2D_TUNE_CACHE file (lines "key tile ms"): the first valid entry for key
+bool tune_cache_lookup(uint64_t key, int prec, TileSel* sel, int* tile, double* ms);
+void tune_cache_store(uint64_t key, int tile, double ms);
 d2d_status sb_work(d2d_sb* sb, int shape, int split, int xcd, WorkItem** w, int* nwork);
 // central-term launch table of the pairs with keep[p] != 0 (all when keep is null)
 void central_tiles(const std::vector<SectorDev>& pairs, const std::vector<int>* keep,

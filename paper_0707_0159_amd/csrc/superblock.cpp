@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <numeric>
 
 #include "host.h"
@@ -819,25 +820,43 @@ extern "C" d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[D2D_NPREC]) 
     return D2D_OK;
 }
 
+namespace d2d {
+
+bool decode_tile(int prec, int tile, TileSel* out) {
+    TileSel t;
+    t.split = tile < 0 ? 0 : ((tile & D2D_TILE_SPLIT4) ? 2 : ((tile & D2D_TILE_SPLIT) ? 1 : 0));
+    t.fuse = tile >= 0 ? ((tile & D2D_TILE_FUSED) ? 1 : 0) : (prec != D2D_FP64 ? 1 : 0);
+    t.xcd = tile >= 0 && (tile & D2D_TILE_XCD) ? 1 : 0;
+    t.shape = tile < 0 ? -1 : (tile & 0xFFFF);
+    if (t.shape >= tile_shape_count() || (t.shape >= 0 && tile_shape(t.shape).prec != prec) ||
+        (tile >= 0 && (tile & ~(0xFFFF | D2D_TILE_SPLIT | D2D_TILE_SPLIT4 | D2D_TILE_FUSED | D2D_TILE_XCD))) ||
+        (tile >= 0 && (tile & D2D_TILE_SPLIT) && (tile & D2D_TILE_SPLIT4)))
+        return false;
+    *out = t;
+    return true;
+}
+
+int encode_tile(const TileSel& t) {
+    return t.shape | (t.split == 1 ? D2D_TILE_SPLIT : 0) | (t.split == 2 ? D2D_TILE_SPLIT4 : 0) |
+           (t.fuse ? D2D_TILE_FUSED : 0) | (t.xcd ? D2D_TILE_XCD : 0);
+}
+
+}  // namespace d2d
+
 extern "C" d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile) {
     if (!sb || prec < 0 || prec >= D2D_NPREC) {
         set_error("d2d_sb_set_tile: bad argument");
         return D2D_EINVAL;
     }
-    const int split = tile < 0 ? 0 : ((tile & D2D_TILE_SPLIT4) ? 2 : ((tile & D2D_TILE_SPLIT) ? 1 : 0));
-    const int fused = tile >= 0 ? ((tile & D2D_TILE_FUSED) ? 1 : 0) : (prec != D2D_FP64 ? 1 : 0);
-    const int xcd = tile >= 0 && (tile & D2D_TILE_XCD) ? 1 : 0;
-    const int shape = tile < 0 ? -1 : (tile & 0xFFFF);
-    if (shape >= tile_shape_count() || (shape >= 0 && tile_shape(shape).prec != prec) ||
-        (tile >= 0 && (tile & ~(0xFFFF | D2D_TILE_SPLIT | D2D_TILE_SPLIT4 | D2D_TILE_FUSED | D2D_TILE_XCD))) ||
-        (tile >= 0 && (tile & D2D_TILE_SPLIT) && (tile & D2D_TILE_SPLIT4))) {
+    TileSel t;
+    if (!decode_tile(prec, tile, &t)) {
         set_error("d2d_sb_set_tile: tile %d is not a shape of precision %d", tile, prec);
         return D2D_EINVAL;
     }
-    sb->tile_sel[prec] = shape;
-    sb->split[prec] = split;
-    sb->fuse[prec] = fused;
-    sb->xcd[prec] = xcd;
+    sb->tile_sel[prec] = t.shape;
+    sb->split[prec] = t.split;
+    sb->fuse[prec] = t.fuse;
+    sb->xcd[prec] = t.xcd;
     return D2D_OK;
 }
 
@@ -913,6 +932,80 @@ static uint64_t sector_key(const d2d_sb* sb, int prec) {
     return h;
 }
 
+namespace d2d {
+
+bool tune_cache_lookup(uint64_t key, int prec, TileSel* sel, int* tile, double* ms) {
+    const char* cache = getenv("D2D_TUNE_CACHE");
+    if (!cache || !*cache) return false;
+    FILE* f = fopen(cache, "r");
+    if (!f) return false;
+    unsigned long long k;
+    int t;
+    double m;
+    bool found = false;
+    while (!found && fscanf(f, "%llx %d %lf", &k, &t, &m) == 3)
+        if (k == key && t >= 0 && decode_tile(prec, t, sel)) {
+            *tile = t;
+            *ms = m;
+            found = true;
+        }
+    fclose(f);
+    return found;
+}
+
+void tune_cache_store(uint64_t key, int tile, double ms) {
+    const char* cache = getenv("D2D_TUNE_CACHE");
+    if (!cache || !*cache) return;
+    FILE* f = fopen(cache, "a");
+    if (!f) return;
+    fprintf(f, "%llx %d %.6f\n", (unsigned long long)key, tile, ms);
+    fclose(f);
+}
+
+d2d_status tune_configs(hipStream_t s, int prec, int reps, const std::function<d2d_status(const TileSel&)>& run,
+                        TileSel* best, double* best_ms) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    d2d_status st = D2D_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        set_error("autotune: HIP event creation failed");
+        st = D2D_EDEVICE;
+    }
+    bool any = false;
+    double bms = 1e300;
+    const int nsh = tile_shape_count();
+    for (int tt = 0; tt < 12 * nsh && st == D2D_OK; ++tt) {
+        TileSel c;
+        c.shape = tt % nsh;
+        c.split = (tt / nsh) % 3;
+        c.fuse = (tt / (3 * nsh)) % 2;
+        c.xcd = tt / (6 * nsh);
+        if (tile_shape(c.shape).prec != prec) continue;
+        st = run(c);   // warm-up (also builds the work list)
+        if (st != D2D_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) st = D2D_EDEVICE;
+        for (int r = 0; r < reps && st == D2D_OK; ++r) st = run(c);
+        float ms = 0.f;
+        if (st == D2D_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = D2D_EDEVICE;
+        if (st == D2D_OK && ms / reps < bms) {
+            bms = ms / reps;
+            *best = c;
+            any = true;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st == D2D_OK && !any) {
+        set_error("autotune: no tile shape for precision %d", prec);
+        st = D2D_EINVAL;
+    }
+    if (st == D2D_OK) *best_ms = bms;
+    return st;
+}
+
+}  // namespace d2d
+
 extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_tile, double* best_ms) {
     if (!sb || !best_tile || !best_ms || prec < 0 || prec >= D2D_NPREC || reps < 1 || reps > 10000) {
         set_error("d2d_sb_autotune: bad argument");
@@ -922,29 +1015,17 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
         set_error("d2d_sb_autotune: precision %d not kept by this superblock", prec);
         return D2D_EINVAL;
     }
+    auto apply = [&](const TileSel& c) {
+        sb->tile_sel[prec] = c.shape;
+        sb->split[prec] = c.split;
+        sb->fuse[prec] = c.fuse;
+        sb->xcd[prec] = c.xcd;
+    };
     const uint64_t key = sector_key(sb, prec);
-    const char* cache = getenv("D2D_TUNE_CACHE");
-    if (cache && *cache) {
-        FILE* f = fopen(cache, "r");
-        if (f) {
-            unsigned long long k;
-            int t;
-            double ms;
-            while (fscanf(f, "%llx %d %lf", &k, &t, &ms) == 3) {
-                const int sh = t & 0xFFFF;
-                if (k == key && t >= 0 && sh < tile_shape_count() && tile_shape(sh).prec == prec) {
-                    sb->tile_sel[prec] = sh;
-                    sb->split[prec] = (t & D2D_TILE_SPLIT4) ? 2 : ((t & D2D_TILE_SPLIT) ? 1 : 0);
-                    sb->fuse[prec] = (t & D2D_TILE_FUSED) ? 1 : 0;
-                    sb->xcd[prec] = (t & D2D_TILE_XCD) ? 1 : 0;
-                    *best_tile = t;
-                    *best_ms = ms;
-                    fclose(f);
-                    return D2D_OK;
-                }
-            }
-            fclose(f);
-        }
+    TileSel sel;
+    if (tune_cache_lookup(key, prec, &sel, best_tile, best_ms)) {
+        apply(sel);
+        return D2D_OK;
     }
     d2d_ctx* ctx = sb->ctx;
     hipStream_t s = ctx->stream;
@@ -957,66 +1038,27 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
         ctx->free(v, (size_t)sb->N * in_sz);
         return st;
     }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    int best = -1;
-    double bms = 1e300;
-    const int saved = sb->tile_sel[prec], saved_split = sb->split[prec], saved_fuse = sb->fuse[prec],
-              saved_xcd = sb->xcd[prec];
-    if (launch_fill(v, prec, sb->N, 0.5, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
-        hipEventCreate(&e1) != hipSuccess) {
+    const TileSel saved{sb->tile_sel[prec], sb->split[prec], sb->fuse[prec], sb->xcd[prec]};
+    if (launch_fill(v, prec, sb->N, 0.5, s) != hipSuccess) {
         set_error("d2d_sb_autotune: HIP setup failed");
         st = D2D_EDEVICE;
     }
-    const int nsh = tile_shape_count();
-    for (int tt = 0; tt < 12 * nsh && st == D2D_OK; ++tt) {
-        const int t = tt % nsh, sp = (tt / nsh) % 3, fu = (tt / (3 * nsh)) % 2, xo = tt / (6 * nsh);
-        if (tile_shape(t).prec != prec) continue;
-        sb->tile_sel[prec] = t;
-        sb->split[prec] = sp;
-        sb->xcd[prec] = xo;
-        HvParts parts{};
-        HvParts* pp = fu ? &parts : nullptr;
-        st = sb_hv_parts(sb, prec, v, w, s, HV_ALL, pp);   // warm-up (also builds the work list)
-        if (st != D2D_OK) break;
-        if (hipEventRecord(e0, s) != hipSuccess) st = D2D_EDEVICE;
-        for (int r = 0; r < reps && st == D2D_OK; ++r) st = sb_hv_parts(sb, prec, v, w, s, HV_ALL, pp);
-        float ms = 0.f;
-        if (st == D2D_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-            st = D2D_EDEVICE;
-        if (st == D2D_OK && ms / reps < bms) {
-            bms = ms / reps;
-            best = t | (sp == 1 ? D2D_TILE_SPLIT : 0) | (sp == 2 ? D2D_TILE_SPLIT4 : 0) | (fu ? D2D_TILE_FUSED : 0) |
-                   (xo ? D2D_TILE_XCD : 0);
-        }
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
+    double bms = 0;
+    if (st == D2D_OK)
+        st = tune_configs(s, prec, reps, [&](const TileSel& c) {
+            apply(c);
+            HvParts parts{};
+            return sb_hv_parts(sb, prec, v, w, s, HV_ALL, c.fuse ? &parts : nullptr);
+        }, &sel, &bms);
     ctx->free(v, (size_t)sb->N * in_sz);
     ctx->free(w, (size_t)sb->N * out_sz);
-    if (st != D2D_OK || best < 0) {
-        sb->tile_sel[prec] = saved;
-        sb->split[prec] = saved_split;
-        sb->fuse[prec] = saved_fuse;
-        sb->xcd[prec] = saved_xcd;
-        if (st == D2D_OK) {
-            set_error("d2d_sb_autotune: no tile shape for precision %d", prec);
-            st = D2D_EINVAL;
-        }
+    if (st != D2D_OK) {
+        apply(saved);
         return st;
     }
-    sb->tile_sel[prec] = best & 0xFFFF;
-    sb->split[prec] = (best & D2D_TILE_SPLIT4) ? 2 : ((best & D2D_TILE_SPLIT) ? 1 : 0);
-    sb->fuse[prec] = (best & D2D_TILE_FUSED) ? 1 : 0;
-    sb->xcd[prec] = (best & D2D_TILE_XCD) ? 1 : 0;
-    *best_tile = best;
+    apply(sel);
+    *best_tile = encode_tile(sel);
     *best_ms = bms;
-    if (cache && *cache) {
-        FILE* f = fopen(cache, "a");
-        if (f) {
-            fprintf(f, "%llx %d %.6f\n", (unsigned long long)key, best, bms);
-            fclose(f);
-        }
-    }
+    tune_cache_store(key, *best_tile, bms);
     return D2D_OK;
 }

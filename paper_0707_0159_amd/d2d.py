@@ -95,6 +95,8 @@ _SIGS = {
     "d2d_batch_create": (C.c_int, [P, C.POINTER(P), C.c_int, C.POINTER(P)]),
     "d2d_batch_destroy": (C.c_int, [P]),
     "d2d_batch_hv": (C.c_int, [P, C.c_int, C.POINTER(P), C.POINTER(P)]),
+    "d2d_batch_set_tile": (C.c_int, [P, C.c_int, C.c_int]),
+    "d2d_batch_autotune": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(C.c_int), f64p]),
     "d2d_batch_lanczos": (C.c_int, [P, C.POINTER(d2d_lanczos_opts), C.POINTER(P), f64p, C.POINTER(P),
                                     C.POINTER(d2d_lanczos_stats)]),
 }
@@ -367,6 +369,19 @@ def d2d_batch_hv(b: int, prec: int, vs, ws):
     _check(load().d2d_batch_hv(P(b), int(prec), va, wa))
 
 
+def d2d_batch_set_tile(b: int, prec: int, tile: int):
+    _check(load().d2d_batch_set_tile(P(b), int(prec), int(tile)))
+
+
+def d2d_batch_autotune(b: int, prec: int, reps: int = 20):
+    """Time every launch configuration of prec on the batch, keep the fastest;
+    returns (tile with flags, ms per batched Hv)."""
+    t = C.c_int()
+    ms = C.c_double()
+    _check(load().d2d_batch_autotune(P(b), int(prec), int(reps), C.byref(t), C.byref(ms)))
+    return t.value, ms.value
+
+
 def d2d_batch_lanczos(b: int, opts: d2d_lanczos_opts, v0s, psis=None, n=None):
     """v0s: device start vectors, or None (seeded start vectors; then n = number of problems)."""
     n = len(v0s) if v0s is not None else int(n)
@@ -378,5 +393,6 @@ def d2d_batch_lanczos(b: int, opts: d2d_lanczos_opts, v0s, psis=None, n=None):
                allow=(D2D_ENOCONV,))
     per = [{"restarts": st.restarts, "hv_count": list(st.hv_count), "residual": st.residual,
             "seconds": st.seconds, "log_theta": list(st.log_theta[:st.nlog]),
-            "log_rho": list(st.log_rho[:st.nlog]), "log_t": list(st.log_t[:st.nlog])} for st in stats]
+            "log_rho": list(st.log_rho[:st.nlog]), "log_t": list(st.log_t[:st.nlog]),
+            "log_prec": list(st.log_prec[:st.nlog])} for st in stats]
     return s, e, per

@@ -28,24 +28,39 @@ def mixed_problems(ctx):
             GpuProblem(ctx, W.CONFIGS[1], target=(2, 0), prec_mask=15)]
 
 
+def batch_vectors(ctx, probs, prec, seed):
+    dt_in = {0: torch.float64, 2: torch.bfloat16}.get(prec, torch.float32)
+    dt_out = torch.float64 if prec == 0 else torch.float32
+    vs, ws, refs = [], [], []
+    for i, p in enumerate(probs):
+        v = W.random_vector(p.info["n"], seed + i)
+        with torch.cuda.stream(ctx.stream):
+            vs.append(torch.as_tensor(v).to("cuda").to(dt_in))
+            ws.append(torch.full((v.size,), float("nan"), dtype=dt_out, device="cuda"))
+            refs.append(torch.full((v.size,), float("nan"), dtype=dt_out, device="cuda"))
+    ctx.stream.synchronize()
+    return vs, ws, refs
+
+
+def assert_batch_equals_single(ctx, b, probs, prec, tile, seed):
+    """Batched Hv of every problem bit for bit equal to its own Hv under the
+    same launch configuration (each output tile is summed in the same order)."""
+    from paper_0707_0159_amd import d2d
+    vs, ws, refs = batch_vectors(ctx, probs, prec, seed)
+    d2d.d2d_batch_hv(b, prec, vs, ws)
+    for p, v, r in zip(probs, vs, refs):
+        d2d.d2d_sb_set_tile(p.sb, prec, tile)
+        d2d.d2d_hv(p.sb, prec, v, r)
+    ctx.stream.synchronize()
+    for w, r in zip(ws, refs):
+        assert torch.equal(w, r)
+
+
 @pytest.mark.parametrize("prec", [0, 1, 3])
 def test_batch_hv_equals_single(ctx, prec):
     from paper_0707_0159_amd import d2d
     probs = mixed_problems(ctx)
     b = d2d.d2d_batch_create(ctx, [p.sb for p in probs])
-    dt = torch.float64 if prec == 0 else torch.float32
-    vs, ws, refs = [], [], []
-    for i, p in enumerate(probs):
-        n = p.info["n"]
-        v = W.random_vector(n, 500 + i)
-        with torch.cuda.stream(ctx.stream):
-            vd = torch.as_tensor(v, dtype=dt).to("cuda")
-            vs.append(vd)
-            ws.append(torch.full_like(vd, float("nan")))
-            refs.append(torch.full_like(vd, float("nan")))
-    ctx.stream.synchronize()
-    d2d.d2d_batch_hv(b, prec, vs, ws)
-    ctx.stream.synchronize()
     max_d = max(max(p.info["max_dl"], p.info["max_dr"]) for p in probs)
     if prec == 3:
         shape = 30 if max_d <= 64 else (28 if max_d <= 512 else 29)
@@ -53,12 +68,53 @@ def test_batch_hv_equals_single(ctx, prec):
         shape = (1 if max_d <= 768 else 2) if prec == 0 else (4 if max_d <= 768 else 5)
     if max_d <= 768:
         shape |= d2d.D2D_TILE_SPLIT      # the batch splits the K-loops of small sectors
-    for p, v, r in zip(probs, vs, refs):
-        d2d.d2d_sb_set_tile(p.sb, prec, shape)
-        d2d.d2d_hv(p.sb, prec, v, r)
+    assert_batch_equals_single(ctx, b, probs, prec, shape, 500)
+    d2d.d2d_batch_destroy(b)
+    for p in probs:
+        p.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+def test_batch_set_tile_equals_single(ctx, prec):
+    """Every tile shape of the precision, with K-loops split in halves and the
+    XCD-aware order: batch and single problems agree bit for bit."""
+    from paper_0707_0159_amd import d2d
+    probs = mixed_problems(ctx)
+    b = d2d.d2d_batch_create(ctx, [p.sb for p in probs])
+    shapes = [i for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == prec]
+    for k, sh in enumerate(shapes):
+        flags = (d2d.D2D_TILE_SPLIT4 | d2d.D2D_TILE_XCD) if k % 2 else 0
+        d2d.d2d_batch_set_tile(b, prec, sh | flags)
+        assert_batch_equals_single(ctx, b, probs, prec, sh | flags, 600 + k)
+    with pytest.raises(RuntimeError):
+        d2d.d2d_batch_set_tile(b, prec, len(d2d.d2d_tile_shapes()))
+    with pytest.raises(RuntimeError):
+        d2d.d2d_batch_set_tile(b, prec, shapes[0] | d2d.D2D_TILE_SPLIT | d2d.D2D_TILE_SPLIT4)
+    d2d.d2d_batch_destroy(b)
+    for p in probs:
+        p.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_autotune(ctx, prec):
+    """The autotuner's choice is a valid configuration that keeps batched Hv
+    equal to single-problem Hv, and the batched Lanczos still converges to
+    every problem's energy."""
+    from paper_0707_0159_amd import d2d
+    probs = mixed_problems(ctx)
+    b = d2d.d2d_batch_create(ctx, [p.sb for p in probs])
+    tile, ms = d2d.d2d_batch_autotune(b, prec, 2)
+    print("batch autotune", prec, hex(tile), ms)
+    assert d2d.d2d_tile_shapes()[tile & 0xFFFF][0] == prec and ms > 0
+    assert_batch_equals_single(ctx, b, probs, prec, tile, 700)
+    refs = [reference_energy(W.CONFIGS[1].name), reference_energy(W.CONFIGS[2].name)]
+    with torch.cuda.stream(ctx.stream):
+        v0 = [torch.as_tensor(W.random_vector(p.info["n"], 100 + i)).to("cuda") for i, p in enumerate(probs)]
     ctx.stream.synchronize()
-    for w, r in zip(ws, refs):
-        assert torch.equal(w, r)
+    st, e, per = d2d.d2d_batch_lanczos(b, d2d.lanczos_opts(prec=prec, k_in=24, tol_res=1e-9), v0)
+    assert st == 0
+    for ei, ri in zip(e[:2], refs):
+        assert abs(ei - ri) <= 1e-10 * abs(ri)
     d2d.d2d_batch_destroy(b)
     for p in probs:
         p.close()
