@@ -137,9 +137,18 @@ def bench_batch(args):
         b1 = d2d.d2d_block_import(ctx, model, raw["L"])
         b4 = d2d.d2d_block_import(ctx, model, raw["R"])
         blocks += [b1, b4]
-        sbs.append(d2d.d2d_sb_create(ctx, b1, b4, model, wl.target, 7))
+        sbs.append(d2d.d2d_sb_create(ctx, b1, b4, model, wl.target, 15))
     infos = [d2d.d2d_sb_info(sb) for sb in sbs]
     b = d2d.d2d_batch_create(ctx, sbs)
+    # launch configuration of the batch's grouped launches, per precision
+    tiles = {}
+    for prec, name in ((d2d.D2D_FP64, "fp64"), (d2d.D2D_FP32, "fp32"), (d2d.D2D_BF16, "bf16"),
+                       (d2d.D2D_BF16X3, "bf16x3")):
+        t, ms_t = d2d.d2d_batch_autotune(b, prec, 2)
+        tiles[name] = {"shape": t & 0xFFFF, "split_k_loops": {0: False, 1: True, 2: "halves"}[
+            1 if t & d2d.D2D_TILE_SPLIT else (2 if t & d2d.D2D_TILE_SPLIT4 else 0)],
+            "central_in_gemm_launch": bool(t & d2d.D2D_TILE_FUSED), "xcd_order": bool(t & d2d.D2D_TILE_XCD),
+            "tuned_ms": ms_t}
     with torch.cuda.stream(s):
         v0 = [torch.as_tensor(W.random_vector(i["n"], wl.seed), device="cuda") for i, wl in zip(infos, wls)]
     s.synchronize()
@@ -175,18 +184,20 @@ def bench_batch(args):
                 "max_dE_rel": max(dE) if dE else None, "problems_with_reference": len(dE),
                 "all_within_1e-10_s": (max(firsts) if firsts and None not in firsts else None),
                 "restarts_max": max(p["restarts"] for p in per),
-                "hv_per_problem_mean": hv / steps / len(per)}
+                "hv_per_problem_mean": hv / steps / len(per),
+                "hv_per_precision_last_solve": [sum(p["hv_count"][q] for p in per) for q in range(4)]}
 
     head = timed(d2d.D2D_FP32, args.steps, args.warmup)
     reps = max(1, min(args.steps, 3))
     bf16 = timed(d2d.D2D_BF16, reps, 1)
+    bf16x3 = timed(d2d.D2D_BF16X3, reps, 1)
     fp64 = timed(d2d.D2D_FP64, reps, 1)
 
     # one batched Hv (pack + grouped GEMM + central term) per precision, HIP events on the context stream
     hv_ms = {}
     F = sum(i["flops_exec"] for i in infos)
     for prec, name, dt in ((d2d.D2D_FP64, "fp64", torch.float64), (d2d.D2D_FP32, "fp32", torch.float32),
-                           (d2d.D2D_BF16, "bf16", torch.bfloat16)):
+                           (d2d.D2D_BF16, "bf16", torch.bfloat16), (d2d.D2D_BF16X3, "bf16x3", torch.float32)):
         with torch.cuda.stream(s):
             xs = [v.to(dt) for v in v0]
             ws = [torch.empty(v.numel(), dtype=torch.float64 if prec == 0 else torch.float32, device="cuda")
@@ -210,9 +221,11 @@ def bench_batch(args):
                    "N_sb_total": sum(i["n"] for i in infos), "N_sb_max": max(i["n"] for i in infos),
                    "k_in": args.k_in, "reorth_window": args.window, "tol_res": args.tol,
                    "parallelism": "none (1 GPU)"},
-        "time_to_energy": {"mixed_fp32": head, "mixed_bf16": bf16, "fp64": fp64,
+        "time_to_energy": {"mixed_fp32": head, "mixed_bf16": bf16, "mixed_bf16x3": bf16x3, "fp64": fp64,
                            "speedup_fp32_vs_fp64": fp64["s_per_solve"] / head["s_per_solve"],
-                           "speedup_bf16_vs_fp64": fp64["s_per_solve"] / bf16["s_per_solve"]},
+                           "speedup_bf16_vs_fp64": fp64["s_per_solve"] / bf16["s_per_solve"],
+                           "speedup_bf16x3_vs_fp64": fp64["s_per_solve"] / bf16x3["s_per_solve"]},
+        "tiles": tiles,
         "batched_hv_ms": hv_ms,
         "flops_exec_per_batched_hv": F,
         "roofline": {"bound": "mfma", "achieved": F / (hv_ms["fp32"] * 1e-3) / 1e12, "peak": PEAK["fp32"] / 1e12,

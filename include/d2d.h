@@ -270,9 +270,14 @@ d2d_status d2d_tile_shapes(int* count, int* desc);
  *   x_{j+1} = Q y.
  * All recurrences, dot products, the tridiagonal solve and the Ritz vector
  * are FP64 on the device; the host reads (theta_j, rho_j) once per restart.
- * Precision schedule: start in opts.prec; if rho_{j+1} > escalate * rho_j the
- * precision is raised (BF16 -> BF16X3 when kept -> FP32 -> FP64).  k_in is capped at the problem
- * dimension.
+ * Precision schedule: start in opts.prec; the precision is raised (BF16 ->
+ * BF16X3 when kept -> FP32 -> FP64) after a restart with rho_{j+1} > escalate
+ * * rho_j whose shortfall is the low-precision products' doing: theta_{j+1} >
+ * theta_j (1e-13 relative; exact arithmetic never raises it) or rho_{j+1} > 4
+ * beta_k |y_k| (the true FP64 residual well above the one the Krylov
+ * recurrence predicts).  Slow convergence of the Krylov space itself keeps
+ * the precision.  A batch runs in one precision and raises it when any active
+ * problem meets the condition.  k_in is capped at the problem dimension.
  * Convergence: rho_j <= tol_res * |theta_j|, or, when tol_rel_e > 0, two
  * successive FP64 Rayleigh quotients with |theta_j - theta_{j-1}| <=
  * tol_rel_e * |theta_j|.
@@ -315,7 +320,11 @@ typedef struct {
     double log_t[D2D_LOG_MAX];      /* seconds since the call started           */
     double log_theta[D2D_LOG_MAX];
     double log_rho[D2D_LOG_MAX];
-    int log_prec[D2D_LOG_MAX];      /* precision used after this restart        */
+    int log_prec[D2D_LOG_MAX];      /* precision of the inner Lanczos that
+                                       produced this entry (opts.prec first)   */
+    double log_pred[D2D_LOG_MAX];   /* residual the previous inner Lanczos
+                                       predicted for its Ritz vector
+                                       (beta_k |y_k|; 0 for the first entry)     */
 } d2d_lanczos_stats;
 
 d2d_status d2d_lanczos(d2d_sb* sb, const d2d_lanczos_opts* opts, const double* v0, double* energy,

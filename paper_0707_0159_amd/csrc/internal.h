@@ -185,7 +185,8 @@ struct LzSet {
     double* partial;        // two partial-sum buffers of 33 x NB
     double* partial2;
     double* scal;           // [nprob * S_LEN]
-    double* res;            // [2 nprob] (theta, rho) of the last residual
+    double* res;            // [3 nprob] (theta, rho) of the last residual per problem, then the
+                            // Ritz residual estimate of the last inner Lanczos per problem
 };
 
 // Lanczos step i (nq = i+1 <= 32): c1 = Q^T w (w upcast from w32 first if

@@ -52,7 +52,8 @@ __device__ inline double sturm_pivot(double d) {
 }
 
 __device__ void tridiag_body(const double* __restrict__ alpha, const double* __restrict__ beta, int k,
-                             double* __restrict__ theta_out, double* __restrict__ y_out) {
+                             double* __restrict__ theta_out, double* __restrict__ y_out,
+                             double* __restrict__ pred_out) {
     __shared__ double a[128], b[128], b2[128], dp[128], dm[128], y[128];
     __shared__ double lo_s, hi_s, scale_s;
     __shared__ int r_s;
@@ -199,6 +200,8 @@ __device__ void tridiag_body(const double* __restrict__ alpha, const double* __r
     if (l == 0) scale_s = (y[0] < 0.0 ? -1.0 : 1.0) / (mx * sqrt(ss));   // lane 0 holds the sum
     __syncthreads();
     for (int i = l; i < k; i += 64) y_out[i] = y[i] * scale_s;
+    // residual norm of the Ritz vector by the recurrence: beta_k |y_{k-1}|
+    if (l == 0) *pred_out = fabs(beta[k] * y[k - 1] * scale_s);
 }
 
 // ------------------------------------------------------------------ density matrix helpers
@@ -917,17 +920,18 @@ hipError_t launch_lz_first(const LzSet& z, const double* x, const double* w, dou
     return hipGetLastError();
 }
 
-// tridiagonal eigenpairs, one block per problem
+// tridiagonal eigenpairs, one block per problem; the recurrence's residual
+// estimate of the Ritz vector at res[2 nprob + p]
 __global__ void __launch_bounds__(64)
-k_lz_tridiag(const int* __restrict__ active, int k, double* __restrict__ scal) {
+k_lz_tridiag(const int* __restrict__ active, int k, double* __restrict__ scal, double* __restrict__ res) {
     if (!active[blockIdx.x]) return;
     double* sc = scal + (int64_t)blockIdx.x * S_LEN;
-    tridiag_body(sc + S_ALPHA, sc + S_BETA, k, sc + S_THETA + 1, sc + S_Y);
+    tridiag_body(sc + S_ALPHA, sc + S_BETA, k, sc + S_THETA + 1, sc + S_Y, res + 2 * gridDim.x + blockIdx.x);
 }
 
 hipError_t launch_lz_tridiag(const LzSet& z, int k, hipStream_t s) {
     if (k < 1 || k > 128) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_lz_tridiag, dim3(z.nprob), dim3(64), 0, s, z.active, k, z.scal);
+    hipLaunchKernelGGL(k_lz_tridiag, dim3(z.nprob), dim3(64), 0, s, z.active, k, z.scal, z.res);
     return hipGetLastError();
 }
 

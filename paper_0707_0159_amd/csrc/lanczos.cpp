@@ -41,7 +41,7 @@ void free_lanczos_work(d2d_ctx* c, LanczosWork*& lw) {
     c->free(lw->vlo, nt * 4);
     c->free(lw->partial, (size_t)2 * 34 * lw->NB * 8);
     c->free(lw->scal, (size_t)lw->nprob * S_LEN * 8);
-    c->free(lw->res, (size_t)2 * lw->nprob * 8);
+    c->free(lw->res, (size_t)3 * lw->nprob * 8);
     c->free(lw->bt, (size_t)lw->NB * sizeof(LzSeg));
     c->free(lw->prange, (size_t)lw->nprob * sizeof(int2));
     c->free(lw->active, (size_t)lw->nprob * sizeof(int));
@@ -101,14 +101,15 @@ d2d_status ensure_lanczos_work(d2d_ctx* c, LanczosWork*& lw, const std::vector<i
     D2D_CHECK(c->alloc((void**)&w->vlo, nt * 4));
     D2D_CHECK(c->alloc((void**)&w->partial, (size_t)2 * 34 * w->NB * 8));
     D2D_CHECK(c->alloc((void**)&w->scal, (size_t)w->nprob * S_LEN * 8));
-    D2D_CHECK(c->alloc((void**)&w->res, (size_t)2 * w->nprob * 8));
+    D2D_CHECK(c->alloc((void**)&w->res, (size_t)3 * w->nprob * 8));
     D2D_CHECK(c->alloc((void**)&w->bt, bt.size() * sizeof(LzSeg)));
     D2D_CHECK(c->alloc((void**)&w->prange, pr.size() * sizeof(int2)));
     D2D_CHECK(c->alloc((void**)&w->active, (size_t)w->nprob * sizeof(int)));
     D2D_HIP(hipMemset(w->scal, 0, (size_t)w->nprob * S_LEN * 8));
     D2D_HIP(hipMemcpy(w->bt, bt.data(), bt.size() * sizeof(LzSeg), hipMemcpyHostToDevice));
     D2D_HIP(hipMemcpy(w->prange, pr.data(), pr.size() * sizeof(int2), hipMemcpyHostToDevice));
-    D2D_HIP(hipHostMalloc((void**)&w->res_host, (size_t)2 * w->nprob * 8, hipHostMallocDefault));
+    D2D_HIP(hipMemset(w->res, 0, (size_t)3 * w->nprob * 8));
+    D2D_HIP(hipHostMalloc((void**)&w->res_host, (size_t)3 * w->nprob * 8, hipHostMallocDefault));
     return D2D_OK;
 }
 
@@ -139,12 +140,13 @@ LzSet set_of(LanczosWork* w) {
     return z;
 }
 
-// FP64 residual of X; (theta, rho) of every problem copied to pinned host memory.
+// FP64 residual of X; (theta, rho) of every problem and the last Ritz residual
+// estimates copied to pinned host memory.
 d2d_status residual_step(LanczosWork* w, HvOps& hv, hipStream_t s) {
     const LzSet z = set_of(w);
     D2D_CHECK(hv.hv(D2D_FP64, w->X, w->W, s));
     D2D_HIP(launch_lz_residual(z, w->X, w->W, s));
-    D2D_HIP(hipMemcpyAsync(w->res_host, w->res, (size_t)2 * w->nprob * 8, hipMemcpyDeviceToHost, s));
+    D2D_HIP(hipMemcpyAsync(w->res_host, w->res, (size_t)3 * w->nprob * 8, hipMemcpyDeviceToHost, s));
     return D2D_OK;
 }
 
@@ -293,7 +295,7 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
     D2D_CHECK(residual_step(w, hv, s));
     hv.count(D2D_FP64, 1);
     D2D_HIP(hipStreamSynchronize(s));
-    std::vector<double> theta(np), rho(np), rho_prev(np, -1.0), theta_prev(np, 0.0);
+    std::vector<double> theta(np), rho(np), rho_prev(np, -1.0), theta_prev(np, 0.0), pred(np, 0.0);
     std::vector<int> have_prev(np, 0);
     std::vector<d2d_lanczos_stats> st(np);
     std::memset(st.data(), 0, sizeof(d2d_lanczos_stats) * np);
@@ -314,12 +316,20 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
                 set_error("Lanczos: non-finite Rayleigh quotient (problem %d, restart %d)", p, j);
                 return D2D_EDEVICE;
             }
-            if (rho_prev[p] >= 0.0 && opts->escalate > 0.0 && rho[p] > opts->escalate * rho_prev[p]) escalate = true;
+            // Raise the precision only when the restart both made poor progress and
+            // shows the inner products' error: the Rayleigh quotient rose (exact
+            // arithmetic never lets it), or the true residual is well above the
+            // one the Krylov recurrence predicted.  Slow convergence of the
+            // Krylov space itself (the estimate matches) is left alone.
+            if (rho_prev[p] >= 0.0 && opts->escalate > 0.0 && rho[p] > opts->escalate * rho_prev[p] &&
+                (theta[p] > theta_prev[p] + 1e-13 * std::fabs(theta_prev[p]) || rho[p] > 4.0 * pred[p]))
+                escalate = true;
             d2d_lanczos_stats& sp = st[p];
             if (sp.nlog < D2D_LOG_MAX) {
                 sp.log_t[sp.nlog] = tsec;
                 sp.log_theta[sp.nlog] = theta[p];
                 sp.log_rho[sp.nlog] = rho[p];
+                sp.log_pred[sp.nlog] = pred[p];
                 sp.log_prec[sp.nlog] = prec;
                 sp.nlog++;
             }
@@ -373,6 +383,7 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
             have_prev[p] = 1;
             theta[p] = w->res_host[2 * p];
             rho[p] = w->res_host[2 * p + 1];
+            pred[p] = w->res_host[2 * np + p];
             restarts[p] = j;
         }
     }

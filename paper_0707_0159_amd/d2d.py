@@ -63,7 +63,7 @@ class d2d_lanczos_stats(C.Structure):
     _fields_ = [("restarts", C.c_int), ("hv_count", C.c_int64 * D2D_NPREC), ("residual", C.c_double),
                 ("seconds", C.c_double), ("nlog", C.c_int), ("log_t", C.c_double * D2D_LOG_MAX),
                 ("log_theta", C.c_double * D2D_LOG_MAX), ("log_rho", C.c_double * D2D_LOG_MAX),
-                ("log_prec", C.c_int * D2D_LOG_MAX)]
+                ("log_prec", C.c_int * D2D_LOG_MAX), ("log_pred", C.c_double * D2D_LOG_MAX)]
 
 
 # name -> (restype, argtypes)
@@ -337,7 +337,7 @@ def d2d_lanczos(sb: int, opts: d2d_lanczos_opts, v0, psi=None):
     n = st.nlog
     stats = {"restarts": st.restarts, "hv_count": list(st.hv_count), "residual": st.residual,
              "seconds": st.seconds, "log_t": list(st.log_t[:n]), "log_theta": list(st.log_theta[:n]),
-             "log_rho": list(st.log_rho[:n]), "log_prec": list(st.log_prec[:n])}
+             "log_rho": list(st.log_rho[:n]), "log_prec": list(st.log_prec[:n]), "log_pred": list(st.log_pred[:n])}
     return s, e.value, stats
 
 
@@ -394,5 +394,5 @@ def d2d_batch_lanczos(b: int, opts: d2d_lanczos_opts, v0s, psis=None, n=None):
     per = [{"restarts": st.restarts, "hv_count": list(st.hv_count), "residual": st.residual,
             "seconds": st.seconds, "log_theta": list(st.log_theta[:st.nlog]),
             "log_rho": list(st.log_rho[:st.nlog]), "log_t": list(st.log_t[:st.nlog]),
-            "log_prec": list(st.log_prec[:st.nlog])} for st in stats]
+            "log_prec": list(st.log_prec[:st.nlog]), "log_pred": list(st.log_pred[:st.nlog])} for st in stats]
     return s, e, per
