@@ -236,13 +236,27 @@ d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[D2D_NPREC]);
  * that the first vector kernel of the step adds: same result bit for bit, one
  * launch less, the central term overlapping the GEMM's tail); d2d_hv always
  * returns the whole product.  Without a call (or after tile -1) FP32 and BF16
- * are fused, FP64 is not.  Returns D2D_EINVAL for an index out of range or a
- * shape not built for that precision. */
+ * are fused, FP64 is not.  A K-loop leaves out every K step whose operator
+ * tile (the output tile's rows of H_l[q_L], or its columns of H_r[q_R], times
+ * the step's BK columns) is zero: the sector operators are block sparse (a
+ * row run of column state i2 couples only to the runs of the column states
+ * that the column's Hamiltonian and bond operators reach), and a left-out
+ * step would add exact zeros.  D2D_TILE_DENSE runs every step instead (the
+ * same result bit for bit, except with D2D_TILE_SPLIT4, whose halves are cut
+ * in the list of steps run).  Returns D2D_EINVAL for an index out of range,
+ * a shape not built for that precision or an unknown flag. */
 #define D2D_TILE_SPLIT (1 << 16)
 #define D2D_TILE_FUSED (1 << 17)
 #define D2D_TILE_SPLIT4 (1 << 18)
 #define D2D_TILE_XCD (1 << 19)
+#define D2D_TILE_DENSE (1 << 20)
 d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile);
+/* Floating-point operations of one grouped-GEMM launch of precision prec
+ * under the superblock's current launch configuration: 2 per multiply-add
+ * over the K steps run, output tiles and steps clipped to the sector blocks
+ * (with D2D_TILE_DENSE this is sb_info's flops_exec).  Builds the work list
+ * if needed. */
+d2d_status d2d_sb_gemm_flops(d2d_sb* sb, int prec, double* flops);
 /* Autotuner: times every grouped-GEMM tile shape of precision prec on this
  * superblock, unsplit, with D2D_TILE_SPLIT and with D2D_TILE_SPLIT4, each with
  * and without D2D_TILE_FUSED and D2D_TILE_XCD (reps launches each, on internal scratch vectors, HIP events
@@ -370,6 +384,9 @@ d2d_status d2d_batch_set_tile(d2d_batch* b, int prec, int tile);
  * for a superblock (key: precision, problem count and every sector
  * dimension).  Synchronous.  On an error the previous configuration stays. */
 d2d_status d2d_batch_autotune(d2d_batch* b, int prec, int reps, int* best_tile, double* best_ms);
+/* As d2d_sb_gemm_flops, for one batched grouped-GEMM launch over every
+ * problem of the batch. */
+d2d_status d2d_batch_gemm_flops(d2d_batch* b, int prec, double* flops);
 /* Batched restarted Lanczos; v0[i] device start vectors (array or entries
  * nullable: seeded as for d2d_lanczos with seed opts.seed + i); energies host out
  * [n]; psi[i] device out (nullable array or entries); per_problem (nullable)

@@ -39,9 +39,9 @@ struct d2d_batch {
     int n_ptiles = 0, cap_ptiles = 0;
     bf16_t *d_vp = nullptr, *d_vt = nullptr;
     int64_t vp_len = 0, vt_len = 0;
-    // work_key(shape, split, xcd) -> (table, count), active problems only
-    std::map<int, std::pair<WorkItem*, int>> work;
-    std::map<int, int> work_cap;
+    // work_key(shape, split, xcd, dense) -> work list of the active problems
+    std::map<int, WorkList> work;
+    NzCells nz;                         // zero pattern of every pair's operators (owned by the superblocks)
     std::vector<int> active;
     int64_t hv_count[D2D_NPREC] = {0, 0, 0, 0};
     // launch configuration per precision (as on a single superblock)
@@ -49,6 +49,7 @@ struct d2d_batch {
     int split[D2D_NPREC] = {0, 0, 0, 0};          // K-loop split level
     int fuse[D2D_NPREC] = {0, 1, 1, 1};           // central term inside the GEMM launch (inner steps)
     int xcd[D2D_NPREC] = {0, 0, 0, 0};            // XCD-aware work order
+    int dense[D2D_NPREC] = {0, 0, 0, 0};          // every K step (no skipping of zero operator tiles)
     void* d_x[3] = {nullptr, nullptr, nullptr};   // ntot doubles each, partial outputs of split K-loops
     void* d_w2 = nullptr;               // ntot doubles, central-term part of fused launches
     void* stage_v = nullptr;
@@ -82,36 +83,21 @@ int batch_auto_tile(const d2d_batch* b, int prec) {
     return D <= 64 ? 17 : (D <= 512 ? 14 : 15);
 }
 
-int work_key(int shape, int split, int xcd) { return shape | split << 16 | xcd << 18; }
+int work_key(int shape, int split, int xcd, int dense) { return shape | split << 16 | xcd << 18 | dense << 19; }
 
 int batch_shape(const d2d_batch* b, int prec) {
     return b->tile_sel[prec] >= 0 ? b->tile_sel[prec] : batch_auto_tile(b, prec);
 }
 
-// Launch tables of the active problems (work list of one shape, split level and
-// order; central and pack tiles).
+// Launch tables of the active problems (work list of one shape, split level,
+// order and step choice; central and pack tiles).
 d2d_status build_work(d2d_batch* b, int key) {
     std::vector<int> keep(b->pairs.size());
     for (size_t p = 0; p < b->pairs.size(); ++p) keep[p] = b->active[b->pair_prob[p]];
-    std::vector<WorkItem> w;
-    make_work(b->pairs, &keep, tile_shape(key & 0xFFFF), (key >> 16) & 3, (key >> 18) & 1, w);
-    auto it = b->work.find(key);
-    if (it != b->work.end() && b->work_cap[key] < (int)w.size()) {
-        dfree(b->ctx, it->second.first, (size_t)b->work_cap[key]);
-        b->work.erase(it);
-        it = b->work.end();
-    }
-    if (it == b->work.end()) {
-        WorkItem* d = nullptr;
-        const size_t cap = std::max<size_t>(w.size(), 1);
-        D2D_CHECK(b->ctx->alloc((void**)&d, cap * sizeof(WorkItem)));
-        b->work[key] = {d, 0};
-        b->work_cap[key] = (int)cap;
-    }
-    auto& e = b->work[key];
-    if (!w.empty()) D2D_HIP(hipMemcpy(e.first, w.data(), w.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
-    e.second = (int)w.size();
-    return D2D_OK;
+    WorkHost h;
+    make_work(b->pairs, &keep, tile_shape(key & 0xFFFF), (key >> 16) & 3, (key >> 18) & 1,
+              ((key >> 19) & 1) ? nullptr : &b->nz, h);
+    return upload_work(b->ctx, h, b->work[key]);
 }
 
 d2d_status build_tiles(d2d_batch* b) {
@@ -178,9 +164,9 @@ HvTables tables_of(d2d_batch* b) {
 }
 
 // Work list of the precision's current launch configuration (built on first use).
-d2d_status batch_work(d2d_batch* b, int prec, int* shape, std::pair<WorkItem*, int>** wl) {
+d2d_status batch_work(d2d_batch* b, int prec, int* shape, const WorkList** wl) {
     *shape = batch_shape(b, prec);
-    const int key = work_key(*shape, b->split[prec], b->xcd[prec]);
+    const int key = work_key(*shape, b->split[prec], b->xcd[prec], b->dense[prec]);
     if (b->work.find(key) == b->work.end()) D2D_CHECK(build_work(b, key));
     *wl = &b->work[key];
     return D2D_OK;
@@ -192,7 +178,7 @@ d2d_status batch_hv(d2d_batch* b, int prec, const void* v, void* w, hipStream_t 
         return D2D_EINVAL;
     }
     int shape = 0;
-    std::pair<WorkItem*, int>* wl = nullptr;
+    const WorkList* wl = nullptr;
     D2D_CHECK(batch_work(b, prec, &shape, &wl));
     HvTables t = tables_of(b);
     for (int i = 0; i < split_parts(b->split[prec]); ++i) {
@@ -208,7 +194,7 @@ d2d_status batch_hv(d2d_batch* b, int prec, const void* v, void* w, hipStream_t 
         for (int i = 0; i < 3; ++i) parts->x[i] = t.x[i];
         parts->central = t.w2;
     }
-    return hv_launch(t, prec, shape, wl->first, wl->second, v, w, s);
+    return hv_launch(t, prec, shape, *wl, v, w, s);
 }
 
 struct BatchHv : HvOps {
@@ -220,7 +206,7 @@ struct BatchHv : HvOps {
     }
     d2d_status prepare(int prec) override {
         int shape = 0;
-        std::pair<WorkItem*, int>* wl = nullptr;
+        const WorkList* wl = nullptr;
         D2D_CHECK(batch_work(b, prec, &shape, &wl));
         for (int i = 0; i < split_parts(b->split[prec]); ++i)
             if (!b->d_x[i]) D2D_CHECK(b->ctx->alloc(&b->d_x[i], (size_t)b->ntot * 8));
@@ -265,7 +251,7 @@ d2d_batch::~d2d_batch() {
     dfree(ctx, d_ptiles, (size_t)cap_ptiles);
     dfree(ctx, d_vp, (size_t)vp_len * vparts);
     dfree(ctx, d_vt, (size_t)vt_len * vparts);
-    for (auto& kv : work) dfree(ctx, kv.second.first, (size_t)work_cap[kv.first]);
+    for (auto& kv : work) free_work(ctx, kv.second);
     for (auto& x : d_x)
         if (x) ctx->free(x, (size_t)ntot * 8);
     if (d_w2) ctx->free(d_w2, (size_t)ntot * 8);
@@ -297,8 +283,10 @@ extern "C" d2d_status d2d_batch_create(d2d_ctx* ctx, d2d_sb* const* sbs, int n, 
     for (int i = 0; i < n; ++i) {
         const d2d_sb* s = sbs[i];
         pbase[i] = (int)b->pairs.size();
-        for (const SectorDev& q0 : s->pairs) {
-            SectorDev q = q0;
+        for (size_t j = 0; j < s->pairs.size(); ++j) {
+            SectorDev q = s->pairs[j];
+            b->nz.L.push_back(s->nzL[j].data());
+            b->nz.R.push_back(s->nzR[j].data());
             q.off += voff;
             q.hl_off += hl;
             q.hr_off += hr;
@@ -488,6 +476,7 @@ extern "C" d2d_status d2d_batch_set_tile(d2d_batch* b, int prec, int tile) {
     b->split[prec] = tile < 0 ? (std::max(b->max_dl, b->max_dr) <= 768 ? 1 : 0) : t.split;
     b->fuse[prec] = t.fuse;
     b->xcd[prec] = t.xcd;
+    b->dense[prec] = t.dense;
     return D2D_OK;
 }
 
@@ -521,6 +510,7 @@ extern "C" d2d_status d2d_batch_autotune(d2d_batch* b, int prec, int reps, int* 
         b->split[prec] = c.split;
         b->fuse[prec] = c.fuse;
         b->xcd[prec] = c.xcd;
+        b->dense[prec] = c.dense;
     };
     const uint64_t key = batch_key(b, prec);
     TileSel sel;
@@ -529,7 +519,7 @@ extern "C" d2d_status d2d_batch_autotune(d2d_batch* b, int prec, int reps, int* 
         return D2D_OK;
     }
     hipStream_t s = b->ctx->stream;
-    const TileSel saved{b->tile_sel[prec], b->split[prec], b->fuse[prec], b->xcd[prec]};
+    const TileSel saved{b->tile_sel[prec], b->split[prec], b->fuse[prec], b->xcd[prec], b->dense[prec]};
     // every problem active, as at the start of a solve
     BatchHv ops(b);
     D2D_CHECK(ops.set_active(std::vector<int>(b->sbs.size(), 1), nullptr));
@@ -554,15 +544,33 @@ extern "C" d2d_status d2d_batch_autotune(d2d_batch* b, int prec, int reps, int* 
     // keep only the work lists still selected (set_active rebuilds every list held)
     std::vector<int> keys;
     for (int p = 0; p < D2D_NPREC; ++p)
-        if (b->HL[p]) keys.push_back(work_key(batch_shape(b, p), b->split[p], b->xcd[p]));
+        if (b->HL[p]) keys.push_back(work_key(batch_shape(b, p), b->split[p], b->xcd[p], b->dense[p]));
     for (auto it = b->work.begin(); it != b->work.end();) {
         if (std::find(keys.begin(), keys.end(), it->first) == keys.end()) {
-            dfree(b->ctx, it->second.first, (size_t)b->work_cap[it->first]);
-            b->work_cap.erase(it->first);
+            free_work(b->ctx, it->second);
             it = b->work.erase(it);
         } else {
             ++it;
         }
     }
     return st;
+}
+
+extern "C" d2d_status d2d_batch_gemm_flops(d2d_batch* b, int prec, double* flops) {
+    if (!b || !flops || prec < 0 || prec >= D2D_NPREC) {
+        set_error("d2d_batch_gemm_flops: bad argument");
+        return D2D_EINVAL;
+    }
+    if (!(b->prec_mask & (1u << prec)) || !b->HL[prec]) {
+        set_error("d2d_batch_gemm_flops: precision %d not kept by every superblock", prec);
+        return D2D_EINVAL;
+    }
+    // the figure is for every problem of the batch
+    BatchHv ops(b);
+    D2D_CHECK(ops.set_active(std::vector<int>(b->sbs.size(), 1), nullptr));
+    int shape = 0;
+    const WorkList* wl = nullptr;
+    D2D_CHECK(batch_work(b, prec, &shape, &wl));
+    *flops = wl->flops;
+    return D2D_OK;
 }

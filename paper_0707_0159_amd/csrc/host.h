@@ -133,11 +133,33 @@ struct HvTables {
     bf16_t* vp;
     bf16_t* vt;
 };
+// Zero pattern of the sector operators in cells of NZ_CELL x NZ_CELL: for
+// pair p, L[p] has ceil(dL/NZ_CELL)^2 bytes for the stored H_l (column-major,
+// cell (i, j) at j * ceil(dL/NZ_CELL) + i, nonzero when any element is), R[p]
+// likewise for the stored H_r^T.  Null pointers: treat as dense.
+constexpr int NZ_CELL = 16;
+struct NzCells {
+    std::vector<const uint8_t*> L, R;
+};
+// A work list on the host: items, their K-step table, the flops it executes.
+struct WorkHost {
+    std::vector<WorkItem> items;
+    std::vector<int32_t> ksteps;
+    double flops = 0;
+};
+// A work list on the device.
+struct WorkList {
+    WorkItem* items = nullptr;
+    int32_t* ksteps = nullptr;
+    int n = 0, nsteps = 0;
+    size_t cap_items = 0, cap_steps = 0;
+    double flops = 0;   // GEMM flops of one launch over the list
+};
 // stages of one Hv launch sequence (a whole product is all three)
 constexpr int HV_PACK = 1, HV_GEMM = 2, HV_CENTRAL = 4, HV_ALL = 7;
 // pack (BF16) + grouped GEMM + central term, the stages selected
-d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkItem* work, int nwork, const void* v,
-                     void* w, hipStream_t s, int stages = HV_ALL);
+d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkList& wl, const void* v, void* w,
+                     hipStream_t s, int stages = HV_ALL);
 
 // Output of a fused Hv left in parts: the product is
 // (((w + x0) + x1) + x2) + central, added in that order by the consumer (the
@@ -207,11 +229,13 @@ struct d2d_sb {
     std::vector<int32_t> h_src, h_rmap, h_cmap;
     std::vector<double> h_rc, h_cc;
     // work lists per tile shape
-    std::map<int, std::pair<d2d::WorkItem*, int>> work;
+    std::map<int, d2d::WorkList> work;             // key: shape | split << 16 | xcd << 18 | dense << 19
+    std::vector<std::vector<uint8_t>> nzL, nzR;    // zero pattern of each pair's operators (NzCells)
     int tile_sel[D2D_NPREC] = {-1, -1, -1, -1};   // shape index, or -1 = by size
     int split[D2D_NPREC] = {0, 0, 0, 0};          // 0 none, 1 two K-loops apart, 2 each K-loop halved too
     int fuse[D2D_NPREC] = {0, 1, 1, 1};           // inner Lanczos steps: central term inside the GEMM launch
     int xcd[D2D_NPREC] = {0, 0, 0, 0};            // XCD-aware work order
+    int dense[D2D_NPREC] = {0, 0, 0, 0};          // 1: run every K step (no skipping of zero operator tiles)
     void* d_x[3] = {nullptr, nullptr, nullptr};   // split-K partial outputs, N doubles each, on demand
     void* d_w2 = nullptr;               // N doubles, central-term part of fused launches
     int64_t hv_count[D2D_NPREC] = {0, 0, 0, 0};
@@ -238,7 +262,7 @@ int sb_auto_tile(const d2d_sb* sb, int prec);
 // a launch configuration: shape index (-1 = by size), K-loop split level, central
 // term fused into the GEMM launch, XCD-aware order
 struct TileSel {
-    int shape = -1, split = 0, fuse = 0, xcd = 0;
+    int shape = -1, split = 0, fuse = 0, xcd = 0, dense = 0;
 };
 // d2d_sb_set_tile's tile argument (shape | D2D_TILE_* flags, or -1) for precision
 // prec; false when it names no shape of that precision or unknown flags
@@ -252,7 +276,11 @@ d2d_status tune_configs(hipStream_t s, int prec, int reps, const std::function<d
 // D2D_TUNE_CACHE file (lines "key tile ms"): the first valid entry for key
 bool tune_cache_lookup(uint64_t key, int prec, TileSel* sel, int* tile, double* ms);
 void tune_cache_store(uint64_t key, int tile, double ms);
-d2d_status sb_work(d2d_sb* sb, int shape, int split, int xcd, WorkItem** w, int* nwork);
+// work list of a launch configuration (built on first use)
+d2d_status sb_work(d2d_sb* sb, int shape, int split, int xcd, int dense, const WorkList** wl);
+// upload a host work list into wl (reusing its buffers when large enough)
+d2d_status upload_work(d2d_ctx* ctx, const WorkHost& h, WorkList& wl);
+void free_work(d2d_ctx* ctx, WorkList& wl);
 // central-term launch table of the pairs with keep[p] != 0 (all when keep is null)
 void central_tiles(const std::vector<SectorDev>& pairs, const std::vector<int>* keep,
                    std::vector<CentralTile>& out);
@@ -264,7 +292,9 @@ inline int split_parts(int split) { return split == 0 ? 0 : (split == 1 ? 1 : 3)
 // work items of the pairs with keep[p] != 0 for a tile shape; split level 0:
 // one item per output tile, 1: one per K-loop, 2: one per half K-loop
 // xcd: the XCD-aware order (rectangles of each pair's tiles per XCD, interleaved, padded with p = -1)
+// nz: zero pattern of the operators (K steps whose operator tile is zero are
+// left out), or null for every step
 void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep, const TileShape& ts, int split, int xcd,
-               std::vector<WorkItem>& out);
+               const NzCells* nz, WorkHost& out);
 void free_lanczos(d2d_sb* sb);
 }  // namespace d2d

@@ -51,13 +51,16 @@ struct SectorDev {
 };
 
 // One output tile of the grouped GEMM: pair, tile row, tile column.
-// part: 0 = both K-loops into W; 1 = H_l V only into W; 2 = V H_r^T only into W1
-// (split K-loops: the central-term kernel adds W1 into W).
 // part: bits 0-1 K-loops (0 both, 1 H_l V only, 2 V H_r^T only); bits 2-3
 // output slot (0 W, s partial X[s-1]); bit 4 one half of the K-loop only,
 // bit 5 which half.
+// ks[f], kn[f]: the K steps of K-loop f (0: H_l V, 1: V H_r^T) are the kn[f]
+// step starts (multiples of BK, ascending) at ks[f] in the work list's step
+// table: every step whose operator tile (the item's rows or columns x the
+// step's BK columns of H_l or H_r) holds a nonzero, or every step.
 struct WorkItem {
     int32_t p, tm, tn, part;
+    int32_t ks[2], kn[2];
 };
 
 // Tile shapes built into the library.
@@ -109,6 +112,7 @@ hipError_t launch_full_pack(const SectorDev* sec, int npairs, int64_t max_elems,
 struct HvGemmArgs {
     const WorkItem* work;
     int nwork;
+    const int32_t* ksteps;     // K-step table of the work list
     const SectorDev* sec;
     const void* HL;
     const void* HR;

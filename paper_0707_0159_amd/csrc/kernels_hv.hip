@@ -14,11 +14,11 @@ namespace d2d {
 
 // ------------------------------------------------------------------ work items
 // WorkItem.part: bits 0-1 the K-loops it runs (0 both, 1 only H_l V, 2 only
-// V H_r^T); bits 2-3 its output slot (0: W, s: X[s-1]); bit 4 set: it runs
-// only one half of its K-loop, bit 5 which half.  A half is cut at a multiple
-// of BK, so no K step straddles the cut.
+// V H_r^T); bits 2-3 its output slot (0: W, s: X[s-1]).  Which K steps a
+// K-loop runs comes with the item (its list of step starts): the host leaves
+// out steps whose operator tile is zero and cuts halves of a K-loop there.
 struct ItemK {
-    int ph_lo, ph_hi, slot, halved, half;
+    int ph_lo, ph_hi, slot;
 };
 __device__ inline ItemK decode_item(int part) {
     ItemK d;
@@ -26,20 +26,52 @@ __device__ inline ItemK decode_item(int part) {
     d.ph_lo = ph == 2 ? 1 : 0;
     d.ph_hi = ph == 1 ? 1 : 2;
     d.slot = (part >> 2) & 3;
-    d.halved = (part >> 4) & 1;
-    d.half = (part >> 5) & 1;
     return d;
 }
-template <int BK>
-__device__ inline void k_range(const ItemK& d, int K, int& k_lo, int& k_hi) {
-    if (!d.halved) {
-        k_lo = 0;
-        k_hi = K;
-        return;
+
+// The K-loop of one item over its step list ks[0..n): double-buffered LDS,
+// PF steps' global loads in flight while a step is computed.  The step start
+// that the next load needs is read one step ahead.
+template <int PF, typename L0, typename L1, typename S0, typename S1, typename C>
+__device__ inline void k_steps(const int32_t* __restrict__ ks, int n, L0&& gload0, L1&& gload1, S0&& stage0,
+                               S1&& stage1, C&& compute) {
+    int buf = 0;
+    if constexpr (PF == 1) {
+        if (n > 0) gload0(ks[0]);
+        int knext = n > 1 ? ks[1] : 0;
+#pragma unroll 1
+        for (int i = 0; i < n; ++i) {
+            stage0(buf);
+            __syncthreads();
+            const int kafter = i + 2 < n ? ks[i + 2] : 0;
+            if (i + 1 < n) gload0(knext);
+            compute(buf);
+            buf ^= 1;
+            knext = kafter;
+        }
+    } else {
+        if (n > 0) gload0(ks[0]);
+        if (n > 1) gload1(ks[1]);
+        int kn0 = n > 2 ? ks[2] : 0, kn1 = n > 3 ? ks[3] : 0;
+#pragma unroll 1
+        for (int i = 0; i < n; i += 2) {
+            stage0(buf);
+            __syncthreads();
+            const int ka0 = i + 4 < n ? ks[i + 4] : 0;
+            if (i + 2 < n) gload0(kn0);
+            compute(buf);
+            buf ^= 1;
+            kn0 = ka0;
+            if (i + 1 >= n) break;
+            stage1(buf);
+            __syncthreads();
+            const int ka1 = i + 5 < n ? ks[i + 5] : 0;
+            if (i + 3 < n) gload1(kn1);
+            compute(buf);
+            buf ^= 1;
+            kn1 = ka1;
+        }
     }
-    const int cut = ((K + 1) / 2 + BK - 1) / BK * BK;
-    k_lo = d.half ? (cut < K ? cut : K) : 0;
-    k_hi = d.half ? K : (cut < K ? cut : K);
 }
 
 // ------------------------------------------------------------------ MFMA shapes
@@ -300,6 +332,7 @@ template <typename T>
 struct HvK {
     const WorkItem* work;
     int nwork;
+    const int32_t* ksteps;
     const SectorDev* sec;
     const T* HL;
     const T* HRt;
@@ -365,8 +398,6 @@ k_hv_gemm(const HvK<T> g) {
         const int64_t lda = dL;
         const int64_t ldb = phase == 0 ? dL : dR;
         const int K = phase == 0 ? dL : dR;
-        int k_lo, k_hi;
-        k_range<BK>(it, K, k_lo, k_hi);
 
         auto gload = [&](int k0, T (&xa)[EA], T (&xb)[EB]) {
 #pragma unroll
@@ -414,36 +445,21 @@ k_hv_gemm(const HvK<T> g) {
         // LDS is double-buffered: a step stores into one buffer while the
         // other was computed in the previous step, and the barrier after the
         // stores orders both.
-        int buf = 0;
-        if constexpr (PF == 1) {
-            if (k_lo < k_hi) gload(k_lo, ra, rb);
-#pragma unroll 1
-            for (int k0 = k_lo; k0 < k_hi; k0 += BK) {
-                stage(ra, rb, buf);
-                __syncthreads();
-                if (k0 + BK < k_hi) gload(k0 + BK, ra, rb);
-                compute(buf);
-                buf ^= 1;
-            }
-        } else {
-            T ra1[EA], rb1[EB];
-            if (k_lo < k_hi) gload(k_lo, ra, rb);
-            if (k_lo + BK < k_hi) gload(k_lo + BK, ra1, rb1);
-#pragma unroll 1
-            for (int k0 = k_lo; k0 < k_hi; k0 += 2 * BK) {
-                stage(ra, rb, buf);
-                __syncthreads();
-                if (k0 + 2 * BK < k_hi) gload(k0 + 2 * BK, ra, rb);
-                compute(buf);
-                buf ^= 1;
-                if (k0 + BK >= k_hi) break;
-                stage(ra1, rb1, buf);
-                __syncthreads();
-                if (k0 + 3 * BK < k_hi) gload(k0 + 3 * BK, ra1, rb1);
-                compute(buf);
-                buf ^= 1;
-            }
-        }
+        T ra1[PF == 2 ? EA : 1], rb1[PF == 2 ? EB : 1];
+        // (the item's fields are selected, not indexed by phase: a runtime
+        // index would put the item in scratch memory)
+        const int32_t* ks = g.ksteps + (phase == 0 ? wi.ks[0] : wi.ks[1]);
+        const int nks = phase == 0 ? wi.kn[0] : wi.kn[1];
+        k_steps<PF>(
+            ks, nks, [&](int k0) { gload(k0, ra, rb); },
+            [&](int k0) {
+                if constexpr (PF == 2) gload(k0, ra1, rb1);
+            },
+            [&](int buf) { stage(ra, rb, buf); },
+            [&](int buf) {
+                if constexpr (PF == 2) stage(ra1, rb1, buf);
+            },
+            compute);
         __syncthreads();
     }
 
@@ -488,7 +504,8 @@ struct LoOffsets {
 
 template <int BM, int BN, int BK, int WGM, int WGN, int PF, bool X3, bool CEN>
 __global__ void __launch_bounds__(64 * WGM * WGN)
-k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __restrict__ sec,
+k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const int32_t* __restrict__ ksteps,
+               const SectorDev* __restrict__ sec,
                const bf16_t* __restrict__ HL, const bf16_t* __restrict__ HRt, const bf16_t* __restrict__ VP,
                const bf16_t* __restrict__ VT, const OutPtrs out, const LoOffsets lo,
                const CentralK<typename std::conditional<X3, float, bf16_t>::type, float, float> cen) {
@@ -537,8 +554,6 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __
         const int64_t loA = phase == 0 ? lo.hl : lo.vt, loB = phase == 0 ? lo.vp : lo.hr;
         const int64_t ld = phase == 0 ? s.dLp : s.dRp;     // both operands share the K stride
         const int Kp = phase == 0 ? s.dLp : s.dRp;
-        int k_lo, k_hi;
-        k_range<BK>(it, Kp, k_lo, k_hi);
 
         auto gload = [&](int k0, uint4 (&xa)[NP][EA], uint4 (&xb)[NP][EB]) {
 #pragma unroll
@@ -599,36 +614,19 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const SectorDev* __
                     }
             }
         };
-        int buf = 0;
-        if constexpr (PF == 1) {
-            if (k_lo < k_hi) gload(k_lo, ra, rb);
-#pragma unroll 1
-            for (int k0 = k_lo; k0 < k_hi; k0 += BK) {
-                stage(ra, rb, buf);
-                __syncthreads();
-                if (k0 + BK < k_hi) gload(k0 + BK, ra, rb);
-                compute(buf);
-                buf ^= 1;
-            }
-        } else {
-            uint4 ra1[NP][EA], rb1[NP][EB];
-            if (k_lo < k_hi) gload(k_lo, ra, rb);
-            if (k_lo + BK < k_hi) gload(k_lo + BK, ra1, rb1);
-#pragma unroll 1
-            for (int k0 = k_lo; k0 < k_hi; k0 += 2 * BK) {
-                stage(ra, rb, buf);
-                __syncthreads();
-                if (k0 + 2 * BK < k_hi) gload(k0 + 2 * BK, ra, rb);
-                compute(buf);
-                buf ^= 1;
-                if (k0 + BK >= k_hi) break;
-                stage(ra1, rb1, buf);
-                __syncthreads();
-                if (k0 + 3 * BK < k_hi) gload(k0 + 3 * BK, ra1, rb1);
-                compute(buf);
-                buf ^= 1;
-            }
-        }
+        uint4 ra1[PF == 2 ? NP : 1][PF == 2 ? EA : 1], rb1[PF == 2 ? NP : 1][PF == 2 ? EB : 1];
+        const int32_t* ks = ksteps + (phase == 0 ? wi.ks[0] : wi.ks[1]);
+        const int nks = phase == 0 ? wi.kn[0] : wi.kn[1];
+        k_steps<PF>(
+            ks, nks, [&](int k0) { gload(k0, ra, rb); },
+            [&](int k0) {
+                if constexpr (PF == 2) gload(k0, ra1, rb1);
+            },
+            [&](int buf) { stage(ra, rb, buf); },
+            [&](int buf) {
+                if constexpr (PF == 2) stage(ra1, rb1, buf);
+            },
+            compute);
         __syncthreads();
     }
 
@@ -662,11 +660,11 @@ static void gemm_bf16_launch(const HvGemmArgs& a, const void* VT, hipStream_t st
     if (a.fuse) {
         const int extra = (a.fuse->ntiles + NW - 1) / NW;
         hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, PF, X3, true>), dim3(a.nwork + extra), dim3(64 * NW),
-                           0, st, a.work, a.nwork, a.sec, HL, HR, VP, V2, out, lo,
+                           0, st, a.work, a.nwork, a.ksteps, a.sec, HL, HR, VP, V2, out, lo,
                            central_args<TIc, float, float>(*a.fuse));
     } else {
         hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, PF, X3, false>), dim3(a.nwork), dim3(64 * NW), 0, st,
-                           a.work, a.nwork, a.sec, HL, HR, VP, V2, out, lo, CentralK<TIc, float, float>{});
+                           a.work, a.nwork, a.ksteps, a.sec, HL, HR, VP, V2, out, lo, CentralK<TIc, float, float>{});
     }
 }
 
@@ -889,6 +887,7 @@ static void gemm_launch(const HvGemmArgs& a, hipStream_t st) {
     HvK<T> g;
     g.work = a.work;
     g.nwork = a.nwork;
+    g.ksteps = a.ksteps;
     g.sec = a.sec;
     g.HL = (const T*)a.HL;
     g.HRt = (const T*)a.HR;

@@ -420,11 +420,10 @@ struct SbHv : HvOps {
         return sb_hv_parts(sb, prec, v, w, s, HV_ALL, parts);
     }
     d2d_status prepare(int prec) override {
-        WorkItem* d;
-        int n;
+        const WorkList* wl = nullptr;
         const int shape = sb->tile_sel[prec] >= 0 ? sb->tile_sel[prec] : sb_auto_tile(sb, prec);
         D2D_CHECK(sb_ensure_parts(sb, sb->split[prec], true));
-        return sb_work(sb, shape, sb->split[prec], sb->xcd[prec], &d, &n);
+        return sb_work(sb, shape, sb->split[prec], sb->xcd[prec], sb->dense[prec], &wl);
     }
     d2d_status set_active(const std::vector<int>&, bool* rebuilt) override {
         if (rebuilt) *rebuilt = false;

@@ -129,10 +129,7 @@ d2d_sb::~d2d_sb() {
     release(ctx, d_rowsL, (size_t)Drows);
     release(ctx, d_colsR, (size_t)Dcols);
     release(ctx, d_srcdl, np * K);
-    for (auto& kv : work) {
-        WorkItem* w = kv.second.first;
-        release(ctx, w, (size_t)kv.second.second);
-    }
+    for (auto& kv : work) free_work(ctx, kv.second);
     work.clear();
 }
 
@@ -182,33 +179,110 @@ void central_sources(const std::vector<SectorDev>& pairs, const std::vector<int3
         }
 }
 
-// Items of one pair: for every K-loop variant of the split level, the tiles in
-// raster order (rows fastest), with their K extents as costs.
-static void pair_items(int p, const SectorDev& sd, const TileShape& ts, int split, int i0, int i1, int j0, int j1,
-                       std::vector<std::pair<int, WorkItem>>& w) {
+// K-step lists of one pair for a tile shape: for every row tile the steps of
+// H_l V, for every column tile the steps of V H_r^T (appended to ks), and the
+// flops a step executes per output element of the tile.
+struct PairSteps {
+    std::vector<int32_t> row_off, row_n, col_off, col_n;
+};
+
+static PairSteps pair_steps(const SectorDev& sd, const TileShape& ts, const uint8_t* nzl, const uint8_t* nzr,
+                            std::vector<int32_t>& ks) {
+    PairSteps ps;
+    const bool b16 = ts.prec == D2D_BF16 || ts.prec == D2D_BF16X3;
     const int dL = sd.dL, dR = sd.dR;
-    const int hL = (dL + 1) / 2, hR = (dR + 1) / 2;
+    // the K-loops run over the padded lengths of the BF16 operands (zero padding)
+    const int KL = b16 ? sd.dLp : dL, KR = b16 ? sd.dRp : dR;
+    const int cl = (dL + NZ_CELL - 1) / NZ_CELL, cr = (dR + NZ_CELL - 1) / NZ_CELL;
+    // stored operator (column-major d x d): cell (i / NZ_CELL, j / NZ_CELL) at cells[j_cell * c + i_cell]
+    auto any = [](const uint8_t* cells, int c, int i0, int i1, int j0, int j1) {
+        for (int j = j0; j < j1; ++j)
+            for (int i = i0; i < i1; ++i)
+                if (cells[(size_t)j * c + i]) return true;
+        return false;
+    };
+    const int tm = (dL + ts.BM - 1) / ts.BM, tn = (dR + ts.BN - 1) / ts.BN;
+    for (int i = 0; i < tm; ++i) {
+        ps.row_off.push_back((int32_t)ks.size());
+        // H_l stored as (row r, column k): rows of the tile x columns of the step
+        const int r0 = i * ts.BM / NZ_CELL, r1 = (std::min((i + 1) * ts.BM, dL) + NZ_CELL - 1) / NZ_CELL;
+        for (int k0 = 0; k0 < KL; k0 += ts.BK) {
+            const int c0 = k0 / NZ_CELL, c1 = std::min((std::min(k0 + ts.BK, dL) + NZ_CELL - 1) / NZ_CELL, cl);
+            if (!nzl || (c0 < c1 && any(nzl, cl, r0, r1, c0, c1))) ks.push_back(k0);
+        }
+        ps.row_n.push_back((int32_t)ks.size() - ps.row_off.back());
+    }
+    for (int j = 0; j < tn; ++j) {
+        ps.col_off.push_back((int32_t)ks.size());
+        // H_r^T stored as (row k, column c): rows of the step x columns of the tile
+        const int q0 = j * ts.BN / NZ_CELL, q1 = (std::min((j + 1) * ts.BN, dR) + NZ_CELL - 1) / NZ_CELL;
+        for (int k0 = 0; k0 < KR; k0 += ts.BK) {
+            const int c0 = k0 / NZ_CELL, c1 = std::min((std::min(k0 + ts.BK, dR) + NZ_CELL - 1) / NZ_CELL, cr);
+            if (!nzr || (c0 < c1 && any(nzr, cr, c0, c1, q0, q1))) ks.push_back(k0);
+        }
+        ps.col_n.push_back((int32_t)ks.size() - ps.col_off.back());
+    }
+    return ps;
+}
+
+// flops of the steps ks[off .. off+n) of one K-loop for an output tile of
+// rows x cols, clipped to the true (unpadded) K extent d
+static double steps_flops(const std::vector<int32_t>& ks, int off, int n, int BK, int d, int rows, int cols) {
+    double f = 0;
+    for (int q = off; q < off + n; ++q) f += 2.0 * rows * cols * std::max(0, std::min(BK, d - ks[q]));
+    return f;
+}
+
+// Items of one pair: for every K-loop variant of the split level, the tiles
+// i0..i1 x j0..j1 in raster order (rows fastest), with their step counts as
+// costs.  Halves of a K-loop cut its step list in two.
+static void pair_items(int p, const SectorDev& sd, const TileShape& ts, const PairSteps& ps,
+                       const std::vector<int32_t>& ks, int split, int i0, int i1, int j0, int j1,
+                       std::vector<std::pair<int, WorkItem>>& w, double& flops) {
     const int nv = split == 2 ? 4 : (split == 1 ? 2 : 1);
     for (int v = 0; v < nv; ++v)
         for (int j = j0; j < j1; ++j)
             for (int i = i0; i < i1; ++i) {
+                const int rows = std::min(ts.BM, sd.dL - i * ts.BM), cols = std::min(ts.BN, sd.dR - j * ts.BN);
+                const int ro = ps.row_off[i], rn = ps.row_n[i], co = ps.col_off[j], cn = ps.col_n[j];
+                WorkItem it{(int32_t)p, i, j, 0, {ro, co}, {0, 0}};
                 if (split == 2) {
                     // slots: W (H_l V, 1st half), X0 (2nd half), X1 (V H_r^T, 1st half), X2 (2nd half)
-                    const int cost[4] = {hL, dL - hL, hR, dR - hR};
+                    const int rh = (rn + 1) / 2, ch = (cn + 1) / 2;
                     const int part[4] = {1 | (0 << 2) | (1 << 4) | (0 << 5), 1 | (1 << 2) | (1 << 4) | (1 << 5),
                                          2 | (2 << 2) | (1 << 4) | (0 << 5), 2 | (3 << 2) | (1 << 4) | (1 << 5)};
-                    w.push_back({cost[v], {(int32_t)p, i, j, part[v]}});
+                    it.part = part[v];
+                    if (v < 2) {
+                        it.ks[0] = v == 0 ? ro : ro + rh;
+                        it.kn[0] = v == 0 ? rh : rn - rh;
+                    } else {
+                        it.ks[1] = v == 2 ? co : co + ch;
+                        it.kn[1] = v == 2 ? ch : cn - ch;
+                    }
                 } else if (split == 1) {
-                    w.push_back({v == 0 ? dL : dR, {(int32_t)p, i, j, v == 0 ? (1 | (0 << 2)) : (2 | (1 << 2))}});
+                    it.part = v == 0 ? (1 | (0 << 2)) : (2 | (1 << 2));
+                    if (v == 0) it.kn[0] = rn;
+                    else it.kn[1] = cn;
                 } else {
-                    w.push_back({dL + dR, {(int32_t)p, i, j, 0}});
+                    it.kn[0] = rn;
+                    it.kn[1] = cn;
                 }
+                flops += steps_flops(ks, it.ks[0], it.kn[0], ts.BK, sd.dL, rows, cols) +
+                         steps_flops(ks, it.ks[1], it.kn[1], ts.BK, sd.dR, rows, cols);
+                w.push_back({it.kn[0] + it.kn[1], it});
             }
 }
 
 void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep, const TileShape& ts, int split,
-               int xcd, std::vector<WorkItem>& out) {
-    out.clear();
+               int xcd, const NzCells* nz, WorkHost& out) {
+    out.items.clear();
+    out.ksteps.clear();
+    out.flops = 0;
+    std::vector<PairSteps> ps(pairs.size());
+    for (size_t p = 0; p < pairs.size(); ++p) {
+        if (keep && !(*keep)[p]) continue;
+        ps[p] = pair_steps(pairs[p], ts, nz ? nz->L[p] : nullptr, nz ? nz->R[p] : nullptr, out.ksteps);
+    }
     if (xcd) {
         // XCD-aware order.  Work-groups go to the 8 XCDs round-robin by index,
         // and each XCD has its own L2: cut every pair's tile grid into 8
@@ -235,12 +309,13 @@ void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep
                 for (int x = 0; x < NX; ++x) {
                     const int rb = x / 4, cb = x % 4;
                     std::vector<std::pair<int, WorkItem>> w;
-                    pair_items(p, sd, ts, split, rb * tm / 2, (rb + 1) * tm / 2, cb * tn / 4, (cb + 1) * tn / 4, w);
+                    pair_items(p, sd, ts, ps[p], out.ksteps, split, rb * tm / 2, (rb + 1) * tm / 2, cb * tn / 4,
+                               (cb + 1) * tn / 4, w, out.flops);
                     for (auto& e : w) bins[x].push_back(e.second);
                 }
             } else {
                 std::vector<std::pair<int, WorkItem>> w;
-                pair_items(p, sd, ts, split, 0, tm, 0, tn, w);
+                pair_items(p, sd, ts, ps[p], out.ksteps, split, 0, tm, 0, tn, w, out.flops);
                 const size_t n = w.size();
                 for (int x = 0; x < NX; ++x)
                     for (size_t q = x * n / NX; q < (x + 1) * n / NX; ++q) bins[x].push_back(w[q].second);
@@ -249,46 +324,91 @@ void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep
         size_t len = 0;
         for (auto& b : bins) len = std::max(len, b.size());
         for (size_t j = 0; j < len; ++j)
-            for (int x = 0; x < NX; ++x) out.push_back(j < bins[x].size() ? bins[x][j] : WorkItem{-1, 0, 0, 0});
+            for (int x = 0; x < NX; ++x)
+                out.items.push_back(j < bins[x].size() ? bins[x][j] : WorkItem{-1, 0, 0, 0, {0, 0}, {0, 0}});
         return;
     }
     std::vector<std::pair<int, WorkItem>> w;
     for (size_t p = 0; p < pairs.size(); ++p) {
         if (keep && !(*keep)[p]) continue;
         const int tm = (pairs[p].dL + ts.BM - 1) / ts.BM, tn = (pairs[p].dR + ts.BN - 1) / ts.BN;
-        pair_items((int)p, pairs[p], ts, split, 0, tm, 0, tn, w);
+        pair_items((int)p, pairs[p], ts, ps[p], out.ksteps, split, 0, tm, 0, tn, w, out.flops);
     }
     // longest K-loops first
     std::stable_sort(w.begin(), w.end(), [](const std::pair<int, WorkItem>& a, const std::pair<int, WorkItem>& b) {
         return a.first > b.first;
     });
-    for (auto& x : w) out.push_back(x.second);
+    for (auto& x : w) out.items.push_back(x.second);
 }
 
-d2d_status sb_work(d2d_sb* sb, int shape, int split, int xcd, WorkItem** out, int* nwork) {
-    const int key = shape | (split << 16) | (xcd << 18);
-    auto it = sb->work.find(key);
-    if (it != sb->work.end()) {
-        *out = it->second.first;
-        *nwork = it->second.second;
-        return D2D_OK;
+d2d_status upload_work(d2d_ctx* ctx, const WorkHost& h, WorkList& wl) {
+    if (h.items.size() > wl.cap_items) {
+        if (wl.items) ctx->free(wl.items, wl.cap_items * sizeof(WorkItem));
+        wl.items = nullptr;
+        wl.cap_items = 0;
+        D2D_CHECK(ctx->alloc((void**)&wl.items, h.items.size() * sizeof(WorkItem)));
+        wl.cap_items = h.items.size();
     }
-    std::vector<WorkItem> w;
-    make_work(sb->pairs, nullptr, tile_shape(shape), split, xcd, w);
-    WorkItem* d = nullptr;
-    D2D_CHECK(upload(sb->ctx, w, &d));
-    sb->work[key] = {d, (int)w.size()};
-    *out = d;
-    *nwork = (int)w.size();
+    if (h.ksteps.size() > wl.cap_steps || !wl.ksteps) {
+        if (wl.ksteps) ctx->free(wl.ksteps, wl.cap_steps * sizeof(int32_t));
+        wl.ksteps = nullptr;
+        wl.cap_steps = 0;
+        const size_t cap = std::max<size_t>(h.ksteps.size(), 1);
+        D2D_CHECK(ctx->alloc((void**)&wl.ksteps, cap * sizeof(int32_t)));
+        wl.cap_steps = cap;
+    }
+    if (!h.items.empty())
+        D2D_HIP(hipMemcpy(wl.items, h.items.data(), h.items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+    if (!h.ksteps.empty())
+        D2D_HIP(hipMemcpy(wl.ksteps, h.ksteps.data(), h.ksteps.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    wl.n = (int)h.items.size();
+    wl.nsteps = (int)h.ksteps.size();
+    wl.flops = h.flops;
     return D2D_OK;
 }
 
-d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkItem* work, int nwork, const void* v,
-                     void* w, hipStream_t s, int stages) {
+void free_work(d2d_ctx* ctx, WorkList& wl) {
+    if (wl.items) ctx->free(wl.items, wl.cap_items * sizeof(WorkItem));
+    if (wl.ksteps) ctx->free(wl.ksteps, wl.cap_steps * sizeof(int32_t));
+    wl = WorkList{};
+}
+
+NzCells sb_nz(const d2d_sb* sb) {
+    NzCells nz;
+    for (size_t p = 0; p < sb->pairs.size(); ++p) {
+        nz.L.push_back(sb->nzL[p].data());
+        nz.R.push_back(sb->nzR[p].data());
+    }
+    return nz;
+}
+
+d2d_status sb_work(d2d_sb* sb, int shape, int split, int xcd, int dense, const WorkList** out) {
+    const int key = shape | (split << 16) | (xcd << 18) | (dense << 19);
+    auto it = sb->work.find(key);
+    if (it != sb->work.end()) {
+        *out = &it->second;
+        return D2D_OK;
+    }
+    WorkHost h;
+    const NzCells nz = sb_nz(sb);
+    make_work(sb->pairs, nullptr, tile_shape(shape), split, xcd, dense ? nullptr : &nz, h);
+    WorkList wl;
+    const d2d_status st = upload_work(sb->ctx, h, wl);
+    if (st != D2D_OK) {
+        free_work(sb->ctx, wl);
+        return st;
+    }
+    sb->work[key] = wl;
+    *out = &sb->work[key];
+    return D2D_OK;
+}
+
+d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkList& wl, const void* v, void* w,
+                     hipStream_t s, int stages) {
     // a split work list (passed together with its partial outputs x) writes
     // shares of the K-loops there; the central term adds them, or, fused,
     // leaves them to the consumer
-    HvGemmArgs g{work, nwork, t.sec, t.HL[prec], t.HR[prec], v, w, {t.x[0], t.x[1], t.x[2]}, nullptr};
+    HvGemmArgs g{wl.items, wl.n, wl.ksteps, t.sec, t.HL[prec], t.HR[prec], v, w, {t.x[0], t.x[1], t.x[2]}, nullptr};
     CentralArgs c{};
     c.tiles = t.ctiles;
     c.ntiles = t.n_ctiles;
@@ -376,9 +496,8 @@ d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t
     }
     const int shape = sb->tile_sel[prec] >= 0 ? sb->tile_sel[prec] : sb_auto_tile(sb, prec);
     const int split = sb->split[prec];
-    WorkItem* work = nullptr;
-    int nwork = 0;
-    D2D_CHECK(sb_work(sb, shape, split, sb->xcd[prec], &work, &nwork));
+    const WorkList* wl = nullptr;
+    D2D_CHECK(sb_work(sb, shape, split, sb->xcd[prec], sb->dense[prec], &wl));
     HvTables t = tables_of(sb);
     D2D_CHECK(sb_ensure_parts(sb, split, parts != nullptr));
     for (int i = 0; i < split_parts(split); ++i) t.x[i] = sb->d_x[i];
@@ -387,7 +506,7 @@ d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t
         for (int i = 0; i < 3; ++i) parts->x[i] = t.x[i];
         parts->central = t.w2;
     }
-    return hv_launch(t, prec, shape, work, nwork, v, w, s, stages);
+    return hv_launch(t, prec, shape, *wl, v, w, s, stages);
 }
 
 d2d_status sb_hv_nocount(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t s) {
@@ -525,11 +644,24 @@ extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d
         std::vector<double> h(hl), r(hr);
         D2D_HIP(hipMemcpy(h.data(), sb->HL[D2D_FP64], hl * 8, hipMemcpyDeviceToHost));
         D2D_HIP(hipMemcpy(r.data(), sb->HR[D2D_FP64], hr * 8, hipMemcpyDeviceToHost));
+        // and the zero pattern in cells, for the K steps the grouped GEMM can leave out
+        auto cells = [](const double* a, int d, std::vector<uint8_t>& out, int64_t& nnz) {
+            const int c = (d + NZ_CELL - 1) / NZ_CELL;
+            out.assign((size_t)c * c, 0);
+            for (int j = 0; j < d; ++j)
+                for (int i = 0; i < d; ++i)
+                    if (a[i + (int64_t)j * d] != 0.0) {
+                        out[(size_t)(j / NZ_CELL) * c + i / NZ_CELL] = 1;
+                        ++nnz;
+                    }
+        };
+        sb->nzL.resize(sb->pairs.size());
+        sb->nzR.resize(sb->pairs.size());
         for (size_t p = 0; p < sb->pairs.size(); ++p) {
             const SectorDev& s = sb->pairs[p];
             int64_t nl = 0, nr = 0;
-            for (int64_t i = 0; i < (int64_t)s.dL * s.dL; ++i) nl += h[s.hl_off + i] != 0.0;
-            for (int64_t i = 0; i < (int64_t)s.dR * s.dR; ++i) nr += r[s.hr_off + i] != 0.0;
+            cells(h.data() + s.hl_off, s.dL, sb->nzL[p], nl);
+            cells(r.data() + s.hr_off, s.dR, sb->nzR[p], nr);
             sb->flops_nnz += 2.0 * nl * s.dR + 2.0 * nr * s.dL;
         }
     }
@@ -827,9 +959,11 @@ bool decode_tile(int prec, int tile, TileSel* out) {
     t.split = tile < 0 ? 0 : ((tile & D2D_TILE_SPLIT4) ? 2 : ((tile & D2D_TILE_SPLIT) ? 1 : 0));
     t.fuse = tile >= 0 ? ((tile & D2D_TILE_FUSED) ? 1 : 0) : (prec != D2D_FP64 ? 1 : 0);
     t.xcd = tile >= 0 && (tile & D2D_TILE_XCD) ? 1 : 0;
+    t.dense = tile >= 0 && (tile & D2D_TILE_DENSE) ? 1 : 0;
     t.shape = tile < 0 ? -1 : (tile & 0xFFFF);
     if (t.shape >= tile_shape_count() || (t.shape >= 0 && tile_shape(t.shape).prec != prec) ||
-        (tile >= 0 && (tile & ~(0xFFFF | D2D_TILE_SPLIT | D2D_TILE_SPLIT4 | D2D_TILE_FUSED | D2D_TILE_XCD))) ||
+        (tile >= 0 &&
+         (tile & ~(0xFFFF | D2D_TILE_SPLIT | D2D_TILE_SPLIT4 | D2D_TILE_FUSED | D2D_TILE_XCD | D2D_TILE_DENSE))) ||
         (tile >= 0 && (tile & D2D_TILE_SPLIT) && (tile & D2D_TILE_SPLIT4)))
         return false;
     *out = t;
@@ -838,7 +972,7 @@ bool decode_tile(int prec, int tile, TileSel* out) {
 
 int encode_tile(const TileSel& t) {
     return t.shape | (t.split == 1 ? D2D_TILE_SPLIT : 0) | (t.split == 2 ? D2D_TILE_SPLIT4 : 0) |
-           (t.fuse ? D2D_TILE_FUSED : 0) | (t.xcd ? D2D_TILE_XCD : 0);
+           (t.fuse ? D2D_TILE_FUSED : 0) | (t.xcd ? D2D_TILE_XCD : 0) | (t.dense ? D2D_TILE_DENSE : 0);
 }
 
 }  // namespace d2d
@@ -857,6 +991,23 @@ extern "C" d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile) {
     sb->split[prec] = t.split;
     sb->fuse[prec] = t.fuse;
     sb->xcd[prec] = t.xcd;
+    sb->dense[prec] = t.dense;
+    return D2D_OK;
+}
+
+extern "C" d2d_status d2d_sb_gemm_flops(d2d_sb* sb, int prec, double* flops) {
+    if (!sb || !flops || prec < 0 || prec >= D2D_NPREC) {
+        set_error("d2d_sb_gemm_flops: bad argument");
+        return D2D_EINVAL;
+    }
+    if (!(sb->prec_mask & (1u << prec)) || !sb->HL[prec]) {
+        set_error("d2d_sb_gemm_flops: precision %d not kept by this superblock", prec);
+        return D2D_EINVAL;
+    }
+    const int shape = sb->tile_sel[prec] >= 0 ? sb->tile_sel[prec] : sb_auto_tile(sb, prec);
+    const WorkList* wl = nullptr;
+    D2D_CHECK(sb_work(sb, shape, sb->split[prec], sb->xcd[prec], sb->dense[prec], &wl));
+    *flops = wl->flops;
     return D2D_OK;
 }
 
@@ -1020,6 +1171,7 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
         sb->split[prec] = c.split;
         sb->fuse[prec] = c.fuse;
         sb->xcd[prec] = c.xcd;
+        sb->dense[prec] = c.dense;
     };
     const uint64_t key = sector_key(sb, prec);
     TileSel sel;
@@ -1038,7 +1190,7 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
         ctx->free(v, (size_t)sb->N * in_sz);
         return st;
     }
-    const TileSel saved{sb->tile_sel[prec], sb->split[prec], sb->fuse[prec], sb->xcd[prec]};
+    const TileSel saved{sb->tile_sel[prec], sb->split[prec], sb->fuse[prec], sb->xcd[prec], sb->dense[prec]};
     if (launch_fill(v, prec, sb->N, 0.5, s) != hipSuccess) {
         set_error("d2d_sb_autotune: HIP setup failed");
         st = D2D_EDEVICE;

@@ -25,6 +25,7 @@ D2D_TILE_SPLIT = 1 << 16
 D2D_TILE_FUSED = 1 << 17
 D2D_TILE_SPLIT4 = 1 << 18
 D2D_TILE_XCD = 1 << 19
+D2D_TILE_DENSE = 1 << 20
 
 _STATUS = {0: "D2D_OK", -1: "D2D_EINVAL", -2: "D2D_ENOMEM", -3: "D2D_EDEVICE", -4: "D2D_ENOCONV",
            -5: "D2D_ESTATE"}
@@ -88,6 +89,8 @@ _SIGS = {
     "d2d_hv_count": (C.c_int, [P, i64p]),
     "d2d_hv_profile": (C.c_int, [P, C.c_int, P, P, C.c_int, f64p, f64p]),
     "d2d_sb_set_tile": (C.c_int, [P, C.c_int, C.c_int]),
+    "d2d_sb_gemm_flops": (C.c_int, [P, C.c_int, f64p]),
+    "d2d_batch_gemm_flops": (C.c_int, [P, C.c_int, f64p]),
     "d2d_sb_autotune": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(C.c_int), f64p]),
     "d2d_tile_shapes": (C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "d2d_lanczos": (C.c_int, [P, C.POINTER(d2d_lanczos_opts), P, f64p, P, C.POINTER(d2d_lanczos_stats)]),
@@ -303,6 +306,18 @@ def d2d_hv_count(sb: int):
 
 def d2d_sb_set_tile(sb: int, prec: int, tile: int):
     _check(load().d2d_sb_set_tile(P(sb), int(prec), int(tile)))
+
+
+def d2d_sb_gemm_flops(sb: int, prec: int) -> float:
+    f = C.c_double()
+    _check(load().d2d_sb_gemm_flops(P(sb), int(prec), C.byref(f)))
+    return f.value
+
+
+def d2d_batch_gemm_flops(b: int, prec: int) -> float:
+    f = C.c_double()
+    _check(load().d2d_batch_gemm_flops(P(b), int(prec), C.byref(f)))
+    return f.value
 
 
 def d2d_sb_autotune(sb: int, prec: int, reps: int = 20):

@@ -258,3 +258,62 @@ def test_bf16x3_every_tile_shape(ctx, cfg):
             assert e2 <= 1e-4
     print("worst vs exact", worst)
     prob.close()
+
+
+def sector_step_flops(osb, BM, BN, BK, dense):
+    """The grouped GEMM's flops for one tile shape, from the oracle's dense
+    sector operators: per output tile and K step of BK, 2 x rows x columns x
+    (K columns in the step), every step (dense) or only the steps whose
+    operator tile holds a nonzero in 16 x 16 cells (the library's granularity)."""
+    total = 0.0
+    for (q, r, c, o), (hl, hr) in zip(osb.sectors, osb.dense_sectors()):
+        dL, dR = r.size, c.size
+        for H, d, dout, B in ((hl, dL, dR, BM), (hr, dR, dL, BN)):
+            # nonzero 16 x 16 cells of H (rows: output rows of the product, columns: K)
+            nc = -(-d // 16)
+            P = np.zeros((nc * 16, nc * 16), dtype=bool)
+            P[:d, :d] = H != 0
+            cells = P.reshape(nc, 16, nc, 16).any(axis=(1, 3))
+            for t0 in range(0, d, B):
+                rows = min(B, d - t0)
+                for k0 in range(0, d, BK):
+                    keep = dense or cells[t0 // 16:-(-min(t0 + B, d) // 16), k0 // 16:-(-min(k0 + BK, d) // 16)].any()
+                    if keep:
+                        # each tile's rows meet every output tile of the other dimension
+                        total += 2.0 * rows * min(BK, d - k0) * dout
+    return total
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+def test_skipped_k_steps_add_nothing(ctx, prec):
+    """K steps whose operator tile is zero are left out: the product is bit
+    for bit the one that runs every step (unhalved K-loops; every shape, with
+    split K-loops and the XCD order too), and the flops the library reports
+    for either are the oracle's count over the same steps."""
+    from paper_0707_0159_amd import d2d
+    wl = W.CONFIGS[2]
+    osb = oracle_superblock(wl)
+    prob = GpuProblem(ctx, wl, prec_mask=15)
+    v = W.random_vector(osb.N, 1200 + prec)
+    run = gpu_hv_bf16 if prec == d2d.D2D_BF16 else (lambda c, p, x: gpu_hv(c, p, prec, x))
+    fewer = 0
+    for i, s in enumerate(d2d.d2d_tile_shapes()):
+        if s[0] != prec:
+            continue
+        dense_f = sector_step_flops(osb, s[1], s[2], s[3], True)
+        skip_f = sector_step_flops(osb, s[1], s[2], s[3], False)
+        for sp in (0, d2d.D2D_TILE_SPLIT, d2d.D2D_TILE_XCD):
+            d2d.d2d_sb_set_tile(prob.sb, prec, i | sp | d2d.D2D_TILE_DENSE)
+            fd = d2d.d2d_sb_gemm_flops(prob.sb, prec)
+            wd = run(ctx, prob, v)
+            d2d.d2d_sb_set_tile(prob.sb, prec, i | sp)
+            fs = d2d.d2d_sb_gemm_flops(prob.sb, prec)
+            ws = run(ctx, prob, v)
+            print(f"prec {prec} shape {i} flags {sp:#x}: flops dense {fd:.4e} skipping {fs:.4e} ({fs / fd:.3f})")
+            assert np.array_equal(wd, ws)
+            assert abs(fd - dense_f) <= 1e-9 * dense_f and abs(fs - skip_f) <= 1e-9 * dense_f
+        assert abs(dense_f - prob.info["flops_exec"]) <= 1e-9 * dense_f
+        fewer += skip_f < dense_f
+    assert fewer >= 1
+    d2d.d2d_sb_set_tile(prob.sb, prec, -1)
+    prob.close()

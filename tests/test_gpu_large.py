@@ -77,6 +77,30 @@ def test_full_size_hv(ctx, problem):
     assert e3 <= 1e-4
 
 
+def test_full_size_skipped_k_steps(ctx, problem):
+    """At the real sizes the sector operators are block sparse: the K steps
+    left out remove a good share of the dense-sector flops, and the product
+    equals, bit for bit, the one that runs every step (in the autotuned
+    configuration, its K-loops unhalved)."""
+    from paper_0707_0159_amd import d2d
+    wl, osb, prob = problem
+    v = W.random_vector(osb.N, 1300)
+    for prec in (0, 1, 2, 3):
+        tile, _ = d2d.d2d_sb_autotune(prob.sb, prec, reps=3)
+        t = tile & ~d2d.D2D_TILE_SPLIT4 & ~d2d.D2D_TILE_DENSE
+        d2d.d2d_sb_set_tile(prob.sb, prec, t | d2d.D2D_TILE_DENSE)
+        fd = d2d.d2d_sb_gemm_flops(prob.sb, prec)
+        wd = hv(ctx, prob, prec, v)
+        d2d.d2d_sb_set_tile(prob.sb, prec, t)
+        fs = d2d.d2d_sb_gemm_flops(prob.sb, prec)
+        ws = hv(ctx, prob, prec, v)
+        d2d.d2d_sb_set_tile(prob.sb, prec, tile)
+        print(f"{wl.name} prec {prec} tile {t:#x}: flops {fs:.4e} of {fd:.4e} ({fs / fd:.3f})")
+        assert abs(fd - prob.info["flops_exec"]) <= 1e-9 * fd
+        assert np.array_equal(wd, ws)
+        assert fs <= 0.8 * fd
+
+
 @pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_full_size_energy(ctx, problem, prec):
     from paper_0707_0159_amd import d2d
