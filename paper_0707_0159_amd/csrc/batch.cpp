@@ -26,15 +26,13 @@ struct d2d_batch {
     size_t hl_bytes[D2D_NPREC] = {0, 0, 0, 0}, hr_bytes[D2D_NPREC] = {0, 0, 0, 0};
     int64_t h16_len = 0, r16_len = 0;   // BF16 operator lengths (the BF16x3 lo parts follow the hi parts)
     int vparts = 1;
-    int K = 0;
-    int64_t Drows = 0, Dcols = 0;
-    int32_t *d_src = nullptr, *d_rmap = nullptr, *d_cmap = nullptr;
-    double *d_rc64 = nullptr, *d_cc64 = nullptr;
-    float *d_rc32 = nullptr, *d_cc32 = nullptr;
-    CentralTile* d_ctiles = nullptr;
-    int n_ctiles = 0, cap_ctiles = 0;
-    int64_t* d_srcoff = nullptr;
-    int32_t* d_srcdl = nullptr;
+    // central term: every problem's units and terms, rebased; the launch table
+    // holds the units of the active problems
+    std::vector<CentralUnit> cunits;
+    std::vector<CentralTerm> cterms;
+    CentralTerm* d_cterms = nullptr;
+    CentralUnit* d_cunits = nullptr;
+    int n_cunits = 0, cap_cunits = 0;
     int4* d_ptiles = nullptr;
     int n_ptiles = 0, cap_ptiles = 0;
     bf16_t *d_vp = nullptr, *d_vt = nullptr;
@@ -101,21 +99,22 @@ d2d_status build_work(d2d_batch* b, int key) {
 }
 
 d2d_status build_tiles(d2d_batch* b) {
-    std::vector<CentralTile> ct;
+    std::vector<CentralUnit> ct;
     std::vector<int4> pt;
     std::vector<int> keep(b->pairs.size());
     for (size_t p = 0; p < b->pairs.size(); ++p) keep[p] = b->active[b->pair_prob[p]];
-    central_tiles(b->pairs, &keep, ct);
+    for (const CentralUnit& u : b->cunits)
+        if (keep[u.p]) ct.push_back(u);
     for (size_t p = 0; p < b->pairs.size(); ++p) {
         if (!keep[p]) continue;
         const int dL = b->pairs[p].dL, dR = b->pairs[p].dR;
         for (int j = 0; j < (dR + 63) / 64; ++j)
             for (int i = 0; i < (dL + 63) / 64; ++i) pt.push_back(make_int4((int)p, i, j, 0));
     }
-    if ((int)ct.size() > b->cap_ctiles) {
-        dfree(b->ctx, b->d_ctiles, (size_t)b->cap_ctiles);
-        b->cap_ctiles = (int)std::max<size_t>(ct.size(), 1);
-        D2D_CHECK(b->ctx->alloc((void**)&b->d_ctiles, (size_t)b->cap_ctiles * sizeof(CentralTile)));
+    if ((int)ct.size() > b->cap_cunits) {
+        dfree(b->ctx, b->d_cunits, (size_t)b->cap_cunits);
+        b->cap_cunits = (int)std::max<size_t>(ct.size(), 1);
+        D2D_CHECK(b->ctx->alloc((void**)&b->d_cunits, (size_t)b->cap_cunits * sizeof(CentralUnit)));
     }
     if ((int)pt.size() > b->cap_ptiles) {
         dfree(b->ctx, b->d_ptiles, (size_t)b->cap_ptiles);
@@ -123,9 +122,9 @@ d2d_status build_tiles(d2d_batch* b) {
         D2D_CHECK(b->ctx->alloc((void**)&b->d_ptiles, (size_t)b->cap_ptiles * sizeof(int4)));
     }
     if (!ct.empty())
-        D2D_HIP(hipMemcpy(b->d_ctiles, ct.data(), ct.size() * sizeof(CentralTile), hipMemcpyHostToDevice));
+        D2D_HIP(hipMemcpy(b->d_cunits, ct.data(), ct.size() * sizeof(CentralUnit), hipMemcpyHostToDevice));
     if (!pt.empty()) D2D_HIP(hipMemcpy(b->d_ptiles, pt.data(), pt.size() * sizeof(int4), hipMemcpyHostToDevice));
-    b->n_ctiles = (int)ct.size();
+    b->n_cunits = (int)ct.size();
     b->n_ptiles = (int)pt.size();
     return D2D_OK;
 }
@@ -142,20 +141,9 @@ HvTables tables_of(d2d_batch* b) {
     t.lo[1] = b->r16_len;
     t.lo[2] = b->vp_len;
     t.lo[3] = b->vt_len;
-    t.K = b->K;
-    t.src = b->d_src;
-    t.rmap = b->d_rmap;
-    t.cmap = b->d_cmap;
-    t.rcoef64 = b->d_rc64;
-    t.ccoef64 = b->d_cc64;
-    t.rcoef32 = b->d_rc32;
-    t.ccoef32 = b->d_cc32;
-    t.Drows = b->Drows;
-    t.Dcols = b->Dcols;
-    t.ctiles = b->d_ctiles;
-    t.n_ctiles = b->n_ctiles;
-    t.srcoff = b->d_srcoff;
-    t.srcdl = b->d_srcdl;
+    t.cunits = b->d_cunits;
+    t.n_cunits = b->n_cunits;
+    t.cterms = b->d_cterms;
     t.ptiles = b->d_ptiles;
     t.n_ptiles = b->n_ptiles;
     t.vp = b->d_vp;
@@ -238,16 +226,8 @@ d2d_batch::~d2d_batch() {
         if (HL[p]) ctx->free(HL[p], hl_bytes[p]);
         if (HR[p]) ctx->free(HR[p], hr_bytes[p]);
     }
-    dfree(ctx, d_src, np * K);
-    dfree(ctx, d_srcoff, np * K);
-    dfree(ctx, d_srcdl, np * K);
-    dfree(ctx, d_rmap, (size_t)K * Drows);
-    dfree(ctx, d_cmap, (size_t)K * Dcols);
-    dfree(ctx, d_rc64, (size_t)K * Drows);
-    dfree(ctx, d_cc64, (size_t)K * Dcols);
-    dfree(ctx, d_rc32, (size_t)K * Drows);
-    dfree(ctx, d_cc32, (size_t)K * Dcols);
-    dfree(ctx, d_ctiles, (size_t)cap_ctiles);
+    dfree(ctx, d_cterms, cterms.size());
+    dfree(ctx, d_cunits, (size_t)cap_cunits);
     dfree(ctx, d_ptiles, (size_t)cap_ptiles);
     dfree(ctx, d_vp, (size_t)vp_len * vparts);
     dfree(ctx, d_vt, (size_t)vt_len * vparts);
@@ -275,7 +255,6 @@ extern "C" d2d_status d2d_batch_create(d2d_ctx* ctx, d2d_sb* const* sbs, int n, 
         }
         b->sbs.push_back(sbs[i]);
         b->prec_mask &= sbs[i]->prec_mask;
-        b->K = std::max(b->K, sbs[i]->K);
     }
     // concatenation offsets
     int64_t voff = 0, hl = 0, hr = 0, h16 = 0, r16 = 0, vp = 0, vt = 0, rb = 0, cb = 0;
@@ -314,8 +293,6 @@ extern "C" d2d_status d2d_batch_create(d2d_ctx* ctx, d2d_sb* const* sbs, int n, 
         cb += s->Dcols;
     }
     b->ntot = voff;
-    b->Drows = rb;
-    b->Dcols = cb;
     b->vp_len = vp;
     b->vt_len = vt;
     D2D_CHECK(dupload(ctx, b->pairs, &b->d_sec));
@@ -354,48 +331,22 @@ extern "C" d2d_status d2d_batch_create(d2d_ctx* ctx, d2d_sb* const* sbs, int n, 
         D2D_HIP(hipMemset(b->d_vp, 0, (size_t)vp * 2 * b->vparts));
         D2D_HIP(hipMemset(b->d_vt, 0, (size_t)vt * 2 * b->vparts));
     }
-    // central tables padded to K terms, source pairs rebased
-    const int K = b->K;
-    const size_t np = b->pairs.size();
-    std::vector<int32_t> src(np * K, -1), rmap((size_t)K * rb, -1), cmap((size_t)K * cb, -1);
-    std::vector<double> rc((size_t)K * rb, 0.0), cc((size_t)K * cb, 0.0);
-    int64_t rbase = 0, cbase = 0;
+    // central units and terms of every problem, rebased
     for (int i = 0; i < n; ++i) {
         const d2d_sb* s = sbs[i];
-        const int Ki = s->K;
-        for (size_t p = 0; p < s->pairs.size(); ++p)
-            for (int k = 0; k < Ki; ++k) {
-                const int32_t q = s->h_src[p * Ki + k];
-                src[(pbase[i] + p) * K + k] = q >= 0 ? q + pbase[i] : -1;
-            }
-        for (int k = 0; k < Ki; ++k) {
-            for (int64_t r = 0; r < s->Drows; ++r) {
-                rmap[(size_t)k * rb + rbase + r] = s->h_rmap[(size_t)k * s->Drows + r];
-                rc[(size_t)k * rb + rbase + r] = s->h_rc[(size_t)k * s->Drows + r];
-            }
-            for (int64_t c = 0; c < s->Dcols; ++c) {
-                cmap[(size_t)k * cb + cbase + c] = s->h_cmap[(size_t)k * s->Dcols + c];
-                cc[(size_t)k * cb + cbase + c] = s->h_cc[(size_t)k * s->Dcols + c];
-            }
+        const int tbase = (int)b->cterms.size();
+        for (CentralTerm t : s->h_cterms) {
+            t.base += b->voff[i];
+            b->cterms.push_back(t);
         }
-        rbase += s->Drows;
-        cbase += s->Dcols;
+        for (CentralUnit u : s->h_cunits) {
+            u.off += b->voff[i];
+            u.tofs += tbase;
+            u.p += pbase[i];
+            b->cunits.push_back(u);
+        }
     }
-    std::vector<float> rc32(rc.begin(), rc.end()), cc32(cc.begin(), cc.end());
-    D2D_CHECK(dupload(ctx, src, &b->d_src));
-    {
-        std::vector<int64_t> so;
-        std::vector<int32_t> sd;
-        central_sources(b->pairs, src, K, so, sd);
-        D2D_CHECK(dupload(ctx, so, &b->d_srcoff));
-        D2D_CHECK(dupload(ctx, sd, &b->d_srcdl));
-    }
-    D2D_CHECK(dupload(ctx, rmap, &b->d_rmap));
-    D2D_CHECK(dupload(ctx, cmap, &b->d_cmap));
-    D2D_CHECK(dupload(ctx, rc, &b->d_rc64));
-    D2D_CHECK(dupload(ctx, cc, &b->d_cc64));
-    D2D_CHECK(dupload(ctx, rc32, &b->d_rc32));
-    D2D_CHECK(dupload(ctx, cc32, &b->d_cc32));
+    D2D_CHECK(dupload(ctx, b->cterms, &b->d_cterms));
     b->active.assign(n, 1);
     // every sector small: the GEMM is latency-bound, split its two K-loops
     const int split = std::max(b->max_dl, b->max_dr) <= 768 ? 1 : 0;

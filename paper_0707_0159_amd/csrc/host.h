@@ -115,19 +115,9 @@ struct HvTables {
     const void* HL[D2D_NPREC];
     const void* HR[D2D_NPREC];
     int64_t lo[4];            // BF16x3: elements from the hi to the lo parts of HL, HR, VP, VT
-    int K;
-    const int32_t* src;
-    const int32_t* rmap;
-    const int32_t* cmap;
-    const double* rcoef64;
-    const double* ccoef64;
-    const float* rcoef32;
-    const float* ccoef32;
-    int64_t Drows, Dcols;
-    const CentralTile* ctiles;
-    int n_ctiles;
-    const int64_t* srcoff;
-    const int32_t* srcdl;
+    const CentralUnit* cunits;   // central-term launch table
+    int n_cunits;
+    const CentralTerm* cterms;
     const int4* ptiles;
     int n_ptiles;
     bf16_t* vp;
@@ -203,20 +193,15 @@ struct d2d_sb {
     d2d::SectorDev* d_sec = nullptr;
     void* HL[D2D_NPREC] = {nullptr, nullptr, nullptr, nullptr};
     void* HR[D2D_NPREC] = {nullptr, nullptr, nullptr, nullptr};
-    int K = 0;
-    int32_t* d_src = nullptr;
-    int32_t* d_rmap = nullptr;
-    int32_t* d_cmap = nullptr;
-    double* d_rcoef64 = nullptr;
-    double* d_ccoef64 = nullptr;
-    float* d_rcoef32 = nullptr;
-    float* d_ccoef32 = nullptr;
+    int K = 0;                               // central bond terms
     int64_t max_elems = 0;
-    d2d::CentralTile* d_cblocks = nullptr;   // central-term launch table
-    int64_t* d_srcoff = nullptr;             // central source blocks per (pair, term)
+    // central term: work units and terms of every rectangle (host copies build batches)
+    std::vector<d2d::CentralUnit> h_cunits;
+    std::vector<d2d::CentralTerm> h_cterms;
+    d2d::CentralUnit* d_cunits = nullptr;
+    d2d::CentralTerm* d_cterms = nullptr;
     int32_t* d_rowsL = nullptr;              // [Drows] left half index of every packed row
     int32_t* d_colsR = nullptr;              // [Dcols] right half index of every packed column
-    int32_t* d_srcdl = nullptr;
     // BF16 operands and per-Hv padded copies of the input vector
     int64_t hl16_len = 0, hr16_len = 0, vp_len = 0, vt_len = 0;
     d2d::bf16_t* d_vp = nullptr;
@@ -224,10 +209,6 @@ struct d2d_sb {
     int vparts = 1;                    // 2 when VP / VT also hold BF16x3 lo parts
     int4* d_ptiles = nullptr;          // pack launch table (pair, 64-row tile, 64-column tile)
     int n_ptiles = 0;
-    int n_cblocks = 0;
-    // host copies of the central tables (used to build batches)
-    std::vector<int32_t> h_src, h_rmap, h_cmap;
-    std::vector<double> h_rc, h_cc;
     // work lists per tile shape
     std::map<int, d2d::WorkList> work;             // key: shape | split << 16 | xcd << 18 | dense << 19
     std::vector<std::vector<uint8_t>> nzL, nzR;    // zero pattern of each pair's operators (NzCells)
@@ -281,12 +262,6 @@ d2d_status sb_work(d2d_sb* sb, int shape, int split, int xcd, int dense, const W
 // upload a host work list into wl (reusing its buffers when large enough)
 d2d_status upload_work(d2d_ctx* ctx, const WorkHost& h, WorkList& wl);
 void free_work(d2d_ctx* ctx, WorkList& wl);
-// central-term launch table of the pairs with keep[p] != 0 (all when keep is null)
-void central_tiles(const std::vector<SectorDev>& pairs, const std::vector<int>* keep,
-                   std::vector<CentralTile>& out);
-// packed offset and row count of the source block of every (pair, term); -1 / 0 when none
-void central_sources(const std::vector<SectorDev>& pairs, const std::vector<int32_t>& src, int K,
-                     std::vector<int64_t>& off, std::vector<int32_t>& dl);
 // number of partial outputs of a split level (0, 1, 3)
 inline int split_parts(int split) { return split == 0 ? 0 : (split == 1 ? 1 : 3); }
 // work items of the pairs with keep[p] != 0 for a tile shape; split level 0:

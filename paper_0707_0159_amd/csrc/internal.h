@@ -72,32 +72,40 @@ int tile_shape_count();
 const TileShape& tile_shape(int i);
 
 // ---------------------------------------------------------------- launchers
-// Central term W += sum_k c_k a_k V b_k^T by gather tables.
-// One launch-table entry per output tile of 64 rows x 8 columns of one pair,
-// carrying everything the tile needs about its pair.
-struct CentralTile {
-    int64_t off;                 // packed offset of the output block
-    int64_t row_base, col_base;  // offsets of the pair's rows / columns in the map tables
-    int p;                       // sector pair
-    int r0, c0;                  // first row and column of the tile
-    int dL, dR;                  // dimensions of the output block
-    int pad;
+// Central term W += sum_k c_k A_k V B_k^T.  Every A_k (column 2) and B_k
+// (column 3) has at most one nonzero per row, so on the rectangle of a pair
+// block where the column-2 state i2 and the column-3 state i3 are fixed (a
+// run of block-1 rows x a run of block-4 columns) each term is one scalar
+// times the rectangle of a source pair block of the same shape.  The launch
+// table lists, per rectangle, its terms (those with a nonzero coefficient;
+// the terms that map the rectangle onto itself, such as S^z S^z, merged into
+// one), and cuts the rectangle into work units of one wave.
+// Unit: rows [ru, ru+nr) x columns [cu, cu+nc) of a rectangle whose element
+// (r, c) is W[off + r + c * ldw]; its terms are terms[tofs .. tofs+nt).
+struct CentralUnit {
+    int64_t off;
+    int32_t ldw;
+    int32_t ru, nr, cu, nc;
+    int32_t tofs, nt;
+    int32_t p;        // sector pair (host bookkeeping)
+};
+// Term: coefficient times the source rectangle, element (r, c) at V[base + r + c * ld].
+struct CentralTerm {
+    int64_t base;
+    int32_t ld, pad;
+    double c64;
+    float c32, pad2;
 };
 struct CentralArgs {
-    const CentralTile* tiles;  // [ntiles]
-    int ntiles;
-    int K;
-    const int64_t* srcoff;     // [npairs*K] packed offset of the source block of term k, or -1
-    const int32_t* srcdl;      // [npairs*K] row count of that source block
-    const int32_t* rmap;       // [K*Drows]
-    const int32_t* cmap;       // [K*Dcols]
-    const void* rcoef;         // [K*Drows] (double for FP64, float otherwise)
-    const void* ccoef;         // [K*Dcols]
-    int64_t Drows, Dcols;
+    const CentralUnit* units;  // [nunits]
+    int nunits;
+    const CentralTerm* terms;
     const void* V;
     void* W;
     const void* X[3];          // split-K partial outputs added into W first, in order (nullable)
 };
+// elements of a unit per lane (a unit has at most 64 * CENTRAL_CS elements)
+constexpr int CENTRAL_CS = 8;
 hipError_t launch_central(int prec, const CentralArgs& a, hipStream_t s);
 
 // packed <-> full space (dir 0: dst packed from full src; dir 1: dst full from packed src)

@@ -114,197 +114,144 @@ struct Mf<float> {
 __device__ inline float bf16_to_f32(bf16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
 
-static constexpr int CT = 8;
-static constexpr int KMAX = 16;
-
 // Central-term arguments in the element types of one precision.
 template <typename TI, typename TO, typename TC>
 struct CentralK {
-    const CentralTile* tiles;
-    int ntiles;
-    int K;
-    const int64_t* srcoff;
-    const int32_t* srcdl;
-    const int32_t* rmap;
-    const int32_t* cmap;
-    const TC* rcoef;
-    const TC* ccoef;
-    int64_t Drows, Dcols;
+    const CentralUnit* units;
+    int nunits;
+    const CentralTerm* terms;
     const TI* V;
     TO* W;
     const TO* X[3];   // split-K partial outputs added to W before the central term (nullable)
 };
 
-// Central term.  One wave per output tile of 64 rows x CT columns of one pair;
-// the NW waves of a block take tiles i0 .. i0+NW-1 (every wave of the block
-// must call this: it holds a block barrier).  The launch-table entry carries
-// the pair's offsets and dimensions, and the source block of every term comes
-// from a per-(pair, term) table, so all the loads the gathers depend on
-// (column maps and coefficients into shared memory; each lane's row maps and
-// coefficients of all K terms; the old W and the split-K partial W1) are
-// issued in one round.  Each lane owns one row r; runs of consecutive i1 map
-// to consecutive source rows, so a wave's gathers are coalesced.
-// ACCUM: W = (((W + X0) + X1) + X2) + central (the split-K partials that
-// are present).  Otherwise W is a separate output that receives the central
-// term alone, for a consumer that adds the parts in that order.
-template <typename TI, typename TO, typename TC, int NW, bool ACCUM>
-__device__ inline void central_tiles_block(const CentralK<TI, TO, TC>& c, int i0) {
-    __shared__ int64_t s_off2[NW][KMAX];
-    __shared__ int s_dl2[NW][KMAX];
-    __shared__ int s_cm[NW][KMAX][CT];
-    __shared__ TC s_cc[NW][KMAX][CT];
-    const int wv = NW == 1 ? 0 : (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int ti = i0 + wv;
-    const bool live = ti < c.ntiles;
-    const CentralTile t = c.tiles[live ? ti : 0];
-    const int K = live ? c.K : 0;
-    if (lane < K) {
-        s_off2[wv][lane] = c.srcoff[(int64_t)t.p * K + lane];
-        s_dl2[wv][lane] = c.srcdl[(int64_t)t.p * K + lane];
+template <typename TC>
+__device__ inline TC term_coef(const CentralTerm& t);
+template <>
+__device__ inline double term_coef<double>(const CentralTerm& t) { return t.c64; }
+template <>
+__device__ inline float term_coef<float>(const CentralTerm& t) { return t.c32; }
+
+// terms whose gathers are issued together
+static constexpr int CENTRAL_TG = 4;
+
+// Central term, one wave per unit (a unit never spans two rectangles, so each
+// of its terms is a scalar and a source base: the unit record and its term
+// records are wave-uniform loads).  Lane l takes row l % nrl of the unit
+// (nrl = min(nr, 64)) and, in step i, column l / nrl + i * (64 / nrl): a
+// short row run puts several columns in one step, and a column's rows stay
+// consecutive across lanes, so the gathers are coalesced.  Steps past the
+// unit's columns are skipped, loads inside a step are at clamped indices and
+// masked afterwards (a load under a lane condition whose value is selected
+// right at the join would make every load wait for the previous one).
+// ACCUM: W = (((W + X0) + X1) + X2) + central (the split-K partials that are
+// present).  Otherwise W is a separate output that receives the central term
+// alone, for a consumer that adds the parts in that order.
+// bf16 input: a gather reads the aligned 32-bit word holding the element and
+// keeps its half after the loads of the group are issued; an aligned word
+// never crosses a page, so the wider read stays inside the allocation that
+// holds the element.
+template <typename TI, typename TO, typename TC, bool ACCUM>
+__device__ inline void central_unit(const CentralK<TI, TO, TC>& c, int ui) {
+    constexpr int CS = CENTRAL_CS, TG = CENTRAL_TG;
+    constexpr bool NARROW = sizeof(TI) == 2;
+    const int lane = threadIdx.x & 63;
+    const CentralUnit u = c.units[ui];
+    const int nrl = u.nr < 64 ? u.nr : 64;
+    const int L = 64 / nrl;
+    const int lr = lane % nrl, lc = lane / nrl;
+    const int r = u.ru + lr;
+    const int nsteps = (u.nc + L - 1) / L;   // <= CS
+    int col[CS];
+    bool ok[CS];
+#pragma unroll
+    for (int i = 0; i < CS; ++i) {
+        ok[i] = lc < L && lc + i * L < u.nc;
+        col[i] = ok[i] ? u.cu + lc + i * L : u.cu;
     }
-    for (int q = lane; q < K * CT; q += 64) {
-        const int k = q / CT, cc = q % CT, col = t.c0 + cc;
-        const bool ok = col < t.dR;
-        s_cm[wv][k][cc] = ok ? c.cmap[k * c.Dcols + t.col_base + col] : -1;
-        s_cc[wv][k][cc] = ok ? c.ccoef[k * c.Dcols + t.col_base + col] : TC(0);
-    }
-    const int r = t.r0 + lane;
-    const bool rok = live && r < t.dL;
-    // Loads below are unconditional, at an index clamped into the tables (the
-    // element of row 0, or of column 0, of this tile's own block), and the
-    // out-of-range values are masked afterwards: a load under a condition whose
-    // value is selected right at the join would make every load wait for the
-    // previous one.
-    int rm[KMAX];
-    TC rc[KMAX];
-    TO wo[CT];
+    TO wo[CS];
+    TC acc[CS];
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        rm[k] = -1;
-        rc[k] = TC(0);
-    }
-#pragma unroll
-    for (int j = 0; j < CT; ++j) wo[j] = TO(0);
-    if (K > 0) {
-        const int rr = rok ? r : 0;
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            const int64_t i = (k < K ? k : 0) * c.Drows + t.row_base + rr;
-            rm[k] = c.rmap[i];
-            rc[k] = c.rcoef[i];
-        }
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-            if (!(rok && k < K)) {
-                rm[k] = -1;
-                rc[k] = TC(0);
-            }
+    for (int i = 0; i < CS; ++i) {
+        wo[i] = TO(0);
+        acc[i] = TC(0);
     }
     if constexpr (ACCUM) {
-        if (live) {
-            const int rr = rok ? r : 0;
 #pragma unroll
-            for (int j = 0; j < CT; ++j) {
-                const int cc = t.c0 + j < t.dR ? t.c0 + j : 0;
-                const int64_t e = t.off + rr + (int64_t)cc * t.dL;
-                TO x = c.W[e];
-                if (c.X[0]) x = x + c.X[0][e];
-                if (c.X[1]) x = x + c.X[1][e];
-                if (c.X[2]) x = x + c.X[2][e];
-                wo[j] = x;
-            }
+        for (int i = 0; i < CS; ++i) {
+            if (i >= nsteps) break;
+            const int64_t e = u.off + r + (int64_t)col[i] * u.ldw;
+            TO x = c.W[e];
+            if (c.X[0]) x = x + c.X[0][e];
+            if (c.X[1]) x = x + c.X[1][e];
+            if (c.X[2]) x = x + c.X[2][e];
+            wo[i] = x;
         }
     }
-    __syncthreads();
-    if (!rok) return;
-    TC acc[CT];
+    for (int t0 = 0; t0 < u.nt; t0 += TG) {
+        TC x[TG][CS];
+        uint32_t raw[NARROW ? TG : 1][NARROW ? CS : 1];
+        uint32_t hi[TG];   // bit i: element i is the word's upper half
+        TC cf[TG];
 #pragma unroll
-    for (int j = 0; j < CT; ++j) acc[j] = TC(0);
-    // Gather addressing: for term k and tile column j the source column
-    // V + so + cm * dl2 is the same for the whole wave, only the row map rm
-    // differs per lane, so a gather is a wave-uniform base plus a 32-bit
-    // per-lane byte offset (a source block is far below 4 GB), and the 8
-    // column gathers of one term share that offset.  bf16 input: a gather
-    // reads the aligned 32-bit word holding the element and keeps its half
-    // after all loads of the group are issued (16-bit loads into half
-    // registers, or converting right at the load, would make each gather wait
-    // for the previous one); an aligned word never crosses a page, so the
-    // wider read stays inside the allocation holding the element.
-    constexpr bool NARROW = sizeof(TI) == 2;
-    // gathers in groups of KG terms (all loads of a group, then its FMAs)
-    constexpr int KG = sizeof(TC) == 8 ? 4 : 8;
+        for (int q = 0; q < TG; ++q) {
+            cf[q] = TC(0);
+            hi[q] = 0;
+            if (t0 + q >= u.nt) continue;
+            const CentralTerm tm = c.terms[u.tofs + t0 + q];
+            cf[q] = term_coef<TC>(tm);
 #pragma unroll
-    for (int k0 = 0; k0 < KMAX; k0 += KG) {
-        if (k0 >= K) break;
-        TC x[KG][CT];
-        uint32_t raw[NARROW ? KG : 1][NARROW ? CT : 1];
-        uint64_t hi = 0;   // bit q*CT+j: the element is the word's upper half
-        static_assert(!NARROW || KG * CT <= 64, "half mask");
-#pragma unroll
-        for (int q = 0; q < KG; ++q) {
-            const int k = k0 + q < K ? k0 + q : 0;
-            const int64_t so = s_off2[wv][k];
-            const bool okr = k0 + q < K && rm[k0 + q] >= 0 && so >= 0;
-            const int64_t dl2 = s_dl2[wv][k];
-            const uint32_t rr = (uint32_t)rm[k0 + q];
-#pragma unroll
-            for (int j = 0; j < CT; ++j) {
-                const int cm = s_cm[wv][k][j];
-                const bool ok = okr && cm >= 0;
-                const TI* col = c.V + (so >= 0 ? so : 0) + (int64_t)(cm >= 0 ? cm : 0) * dl2;   // uniform
+            for (int i = 0; i < CS; ++i) {
+                if (i >= nsteps) break;
+                const int64_t idx = tm.base + r + (int64_t)col[i] * tm.ld;
                 if constexpr (NARROW) {
-                    const uint32_t shc = (uint32_t)(((uintptr_t)col >> 1) & 1);
-                    const char* wb = (const char*)(col - shc);                                      // 4-byte aligned
-                    const uint32_t pe = rr + shc;
-                    raw[q][j] = ok ? *(const uint32_t*)(wb + ((pe >> 1) << 2)) : 0u;
-                    hi |= (uint64_t)(pe & 1) << (q * CT + j);
+                    raw[q][i] = ((const uint32_t*)c.V)[idx >> 1];
+                    hi[q] |= (uint32_t)(idx & 1) << i;
                 } else {
-                    x[q][j] = ok ? (TC) * (const TI*)((const char*)col + rr * (uint32_t)sizeof(TI)) : TC(0);
+                    x[q][i] = (TC)c.V[idx];
                 }
             }
         }
-        if constexpr (NARROW) {
 #pragma unroll
-            for (int q = 0; q < KG; ++q)
+        for (int q = 0; q < TG; ++q) {
+            if (t0 + q >= u.nt) continue;
 #pragma unroll
-                for (int j = 0; j < CT; ++j)
-                    x[q][j] = __uint_as_float(((hi >> (q * CT + j)) & 1) ? (raw[q][j] & 0xffff0000u)
-                                                                        : (raw[q][j] << 16));
-        }
-#pragma unroll
-        for (int q = 0; q < KG; ++q) {
-            const int k = k0 + q < K ? k0 + q : 0;
-#pragma unroll
-            for (int j = 0; j < CT; ++j) acc[j] += rc[k0 + q] * s_cc[wv][k][j] * x[q][j];
+            for (int i = 0; i < CS; ++i) {
+                if (i >= nsteps) break;
+                TC v;
+                if constexpr (NARROW)
+                    v = __uint_as_float(((hi[q] >> i) & 1) ? (raw[q][i] & 0xffff0000u) : (raw[q][i] << 16));
+                else
+                    v = x[q][i];
+                acc[i] += cf[q] * v;
+            }
         }
     }
 #pragma unroll
-    for (int j = 0; j < CT; ++j)
-        if (t.c0 + j < t.dR) {
-            const int64_t e = t.off + r + (int64_t)(t.c0 + j) * t.dL;
-            c.W[e] = wo[j] + (TO)acc[j];
-        }
+    for (int i = 0; i < CS; ++i) {
+        if (i >= nsteps) break;
+        if (ok[i]) c.W[u.off + r + (int64_t)col[i] * u.ldw] = wo[i] + (TO)acc[i];
+    }
+}
+
+// NW waves of a block take units i0 .. i0+NW-1 (no block barrier).
+template <typename TI, typename TO, typename TC, int NW, bool ACCUM>
+__device__ inline void central_units_block(const CentralK<TI, TO, TC>& c, int i0) {
+    const int ui = i0 + (NW == 1 ? 0 : (int)(threadIdx.x >> 6));
+    if (ui < c.nunits) central_unit<TI, TO, TC, ACCUM>(c, ui);
 }
 
 template <typename TI, typename TO, typename TC>
 __global__ void __launch_bounds__(64) k_central(const CentralK<TI, TO, TC> c) {
-    central_tiles_block<TI, TO, TC, 1, true>(c, blockIdx.x);
+    central_units_block<TI, TO, TC, 1, true>(c, blockIdx.x);
 }
 
 template <typename TI, typename TO, typename TC>
 static CentralK<TI, TO, TC> central_args(const CentralArgs& a) {
     CentralK<TI, TO, TC> c;
-    c.tiles = a.tiles;
-    c.ntiles = a.ntiles;
-    c.K = a.K;
-    c.srcoff = a.srcoff;
-    c.srcdl = a.srcdl;
-    c.rmap = a.rmap;
-    c.cmap = a.cmap;
-    c.rcoef = (const TC*)a.rcoef;
-    c.ccoef = (const TC*)a.ccoef;
-    c.Drows = a.Drows;
-    c.Dcols = a.Dcols;
+    c.units = a.units;
+    c.nunits = a.nunits;
+    c.terms = a.terms;
     c.V = (const TI*)a.V;
     c.W = (TO*)a.W;
     for (int i = 0; i < 3; ++i) c.X[i] = (const TO*)a.X[i];
@@ -312,9 +259,8 @@ static CentralK<TI, TO, TC> central_args(const CentralArgs& a) {
 }
 
 hipError_t launch_central(int prec, const CentralArgs& a, hipStream_t st) {
-    if (a.ntiles == 0) return hipSuccess;
-    if (a.K > KMAX) return hipErrorInvalidValue;
-    dim3 grid(a.ntiles);
+    if (a.nunits == 0) return hipSuccess;
+    dim3 grid(a.nunits);
     if (prec == D2D_FP64)
         hipLaunchKernelGGL((k_central<double, double, double>), grid, dim3(64), 0, st,
                            central_args<double, double, double>(a));
@@ -349,7 +295,7 @@ __global__ void __launch_bounds__(64 * WGM * WGN)
 k_hv_gemm(const HvK<T> g) {
     if constexpr (CEN) {
         if ((int)blockIdx.x >= g.nwork) {
-            central_tiles_block<T, T, T, WGM * WGN, false>(g.cen, ((int)blockIdx.x - g.nwork) * WGM * WGN);
+            central_units_block<T, T, T, WGM * WGN, false>(g.cen, ((int)blockIdx.x - g.nwork) * WGM * WGN);
             return;
         }
     }
@@ -512,7 +458,7 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const int32_t* __re
     using TIc = typename std::conditional<X3, float, bf16_t>::type;
     if constexpr (CEN) {
         if ((int)blockIdx.x >= nwork) {
-            central_tiles_block<TIc, float, float, WGM * WGN, false>(cen, ((int)blockIdx.x - nwork) * WGM * WGN);
+            central_units_block<TIc, float, float, WGM * WGN, false>(cen, ((int)blockIdx.x - nwork) * WGM * WGN);
             return;
         }
     }
@@ -658,7 +604,7 @@ static void gemm_bf16_launch(const HvGemmArgs& a, const void* VT, hipStream_t st
     for (int i = 0; i < 3; ++i) out.X[i] = (float*)a.X[i];
     const LoOffsets lo{a.lo[0], a.lo[1], a.lo[2], a.lo[3]};
     if (a.fuse) {
-        const int extra = (a.fuse->ntiles + NW - 1) / NW;
+        const int extra = (a.fuse->nunits + NW - 1) / NW;
         hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, PF, X3, true>), dim3(a.nwork + extra), dim3(64 * NW),
                            0, st, a.work, a.nwork, a.ksteps, a.sec, HL, HR, VP, V2, out, lo,
                            central_args<TIc, float, float>(*a.fuse));
@@ -670,7 +616,6 @@ static void gemm_bf16_launch(const HvGemmArgs& a, const void* VT, hipStream_t st
 
 hipError_t launch_hv_gemm_bf16(int shape, const HvGemmArgs& a, const void* VT, hipStream_t st) {
     if (a.nwork <= 0) return hipSuccess;
-    if (a.fuse && a.fuse->K > KMAX) return hipErrorInvalidValue;
     switch (shape) {
         case 14: gemm_bf16_launch<64, 64, 32, 2, 2, 1, false>(a, VT, st); break;
         case 15: gemm_bf16_launch<128, 128, 32, 2, 2, 1, false>(a, VT, st); break;
@@ -896,7 +841,7 @@ static void gemm_launch(const HvGemmArgs& a, hipStream_t st) {
     for (int i = 0; i < 3; ++i) g.X[i] = (T*)a.X[i];
     if (a.fuse) {
         g.cen = central_args<T, T, T>(*a.fuse);
-        const int extra = (a.fuse->ntiles + NW - 1) / NW;
+        const int extra = (a.fuse->nunits + NW - 1) / NW;
         hipLaunchKernelGGL((k_hv_gemm<T, BM, BN, BK, WGM, WGN, PF, true>), dim3(a.nwork + extra), dim3(64 * NW), 0, st, g);
     } else {
         g.cen = CentralK<T, T, T>{};
@@ -906,7 +851,6 @@ static void gemm_launch(const HvGemmArgs& a, hipStream_t st) {
 
 hipError_t launch_hv_gemm(int shape, const HvGemmArgs& a, hipStream_t st) {
     if (a.nwork <= 0) return hipSuccess;
-    if (a.fuse && a.fuse->K > KMAX) return hipErrorInvalidValue;
     switch (shape) {
         case 0: gemm_launch<double, 32, 32, 16, 2, 2, 1>(a, st); break;
         case 1: gemm_launch<double, 64, 64, 16, 2, 2, 1>(a, st); break;

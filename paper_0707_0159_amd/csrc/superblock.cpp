@@ -117,18 +117,10 @@ d2d_sb::~d2d_sb() {
     release(ctx, d_vp, (size_t)vp_len * vparts);
     release(ctx, d_vt, (size_t)vt_len * vparts);
     release(ctx, d_ptiles, (size_t)n_ptiles);
-    release(ctx, d_src, np * K);
-    release(ctx, d_rmap, (size_t)K * Drows);
-    release(ctx, d_cmap, (size_t)K * Dcols);
-    release(ctx, d_rcoef64, (size_t)K * Drows);
-    release(ctx, d_ccoef64, (size_t)K * Dcols);
-    release(ctx, d_rcoef32, (size_t)K * Drows);
-    release(ctx, d_ccoef32, (size_t)K * Dcols);
-    release(ctx, d_cblocks, (size_t)n_cblocks);
-    release(ctx, d_srcoff, np * K);
+    release(ctx, d_cunits, h_cunits.size());
+    release(ctx, d_cterms, h_cterms.size());
     release(ctx, d_rowsL, (size_t)Drows);
     release(ctx, d_colsR, (size_t)Dcols);
-    release(ctx, d_srcdl, np * K);
     for (auto& kv : work) free_work(ctx, kv.second);
     work.clear();
 }
@@ -142,41 +134,6 @@ int sb_auto_tile(const d2d_sb* sb, int prec) {
     if (prec == D2D_BF16) return D <= 64 ? 17 : (D <= 512 ? 14 : 15);
     if (prec == D2D_BF16X3) return D <= 64 ? 30 : (D <= 512 ? 28 : 29);
     return -1;
-}
-
-void central_tiles(const std::vector<SectorDev>& pairs, const std::vector<int>* keep,
-                   std::vector<CentralTile>& out) {
-    out.clear();
-    for (size_t p = 0; p < pairs.size(); ++p) {
-        if (keep && !(*keep)[p]) continue;
-        const SectorDev& s = pairs[p];
-        for (int c0 = 0; c0 < s.dR; c0 += 8)
-            for (int r0 = 0; r0 < s.dL; r0 += 64) {
-                CentralTile t{};
-                t.off = s.off;
-                t.p = (int)p;
-                t.r0 = r0;
-                t.c0 = c0;
-                t.dL = s.dL;
-                t.dR = s.dR;
-                t.row_base = s.row_base;
-                t.col_base = s.col_base;
-                out.push_back(t);
-            }
-    }
-}
-
-void central_sources(const std::vector<SectorDev>& pairs, const std::vector<int32_t>& src, int K,
-                     std::vector<int64_t>& off, std::vector<int32_t>& dl) {
-    off.assign(pairs.size() * K, -1);
-    dl.assign(pairs.size() * K, 0);
-    for (size_t p = 0; p < pairs.size(); ++p)
-        for (int k = 0; k < K; ++k) {
-            const int32_t q = src[p * K + k];
-            if (q < 0) continue;
-            off[p * K + k] = pairs[q].off;
-            dl[p * K + k] = pairs[q].dL;
-        }
 }
 
 // K-step lists of one pair for a tile shape: for every row tile the steps of
@@ -410,17 +367,9 @@ d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkList& wl,
     // leaves them to the consumer
     HvGemmArgs g{wl.items, wl.n, wl.ksteps, t.sec, t.HL[prec], t.HR[prec], v, w, {t.x[0], t.x[1], t.x[2]}, nullptr};
     CentralArgs c{};
-    c.tiles = t.ctiles;
-    c.ntiles = t.n_ctiles;
-    c.K = t.K;
-    c.srcoff = t.srcoff;
-    c.srcdl = t.srcdl;
-    c.rmap = t.rmap;
-    c.cmap = t.cmap;
-    c.rcoef = prec == D2D_FP64 ? (const void*)t.rcoef64 : (const void*)t.rcoef32;
-    c.ccoef = prec == D2D_FP64 ? (const void*)t.ccoef64 : (const void*)t.ccoef32;
-    c.Drows = t.Drows;
-    c.Dcols = t.Dcols;
+    c.units = t.cunits;
+    c.nunits = t.n_cunits;
+    c.terms = t.cterms;
     c.V = v;   // the unpadded input in every precision
     if (t.w2) {
         c.W = t.w2;
@@ -460,20 +409,9 @@ static HvTables tables_of(d2d_sb* sb) {
     t.lo[1] = sb->hr16_len;
     t.lo[2] = sb->vp_len;
     t.lo[3] = sb->vt_len;
-    t.K = sb->K;
-    t.src = sb->d_src;
-    t.rmap = sb->d_rmap;
-    t.cmap = sb->d_cmap;
-    t.rcoef64 = sb->d_rcoef64;
-    t.ccoef64 = sb->d_ccoef64;
-    t.rcoef32 = sb->d_rcoef32;
-    t.ccoef32 = sb->d_ccoef32;
-    t.Drows = sb->Drows;
-    t.Dcols = sb->Dcols;
-    t.ctiles = sb->d_cblocks;
-    t.n_ctiles = sb->n_cblocks;
-    t.srcoff = sb->d_srcoff;
-    t.srcdl = sb->d_srcdl;
+    t.cunits = sb->d_cunits;
+    t.n_cunits = (int)sb->h_cunits.size();
+    t.cterms = sb->d_cterms;
     t.ptiles = sb->d_ptiles;
     t.n_ptiles = sb->n_ptiles;
     t.vp = sb->d_vp;
@@ -750,101 +688,164 @@ extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d
         for (size_t i = 0; i < kv.second.size(); ++i) posL[kv.second[i]] = (int32_t)i;
     for (auto& kv : right)
         for (size_t i = 0; i < kv.second.size(); ++i) posR[kv.second[i]] = (int32_t)i;
-    std::vector<int32_t> src((size_t)np * K, -1), rmap((size_t)K * rb, -1), cmap((size_t)K * cb, -1);
-    std::vector<double> rc((size_t)K * rb, 0.0), cc((size_t)K * cb, 0.0);
-    int64_t gathers = 0;
+    // the nonzero of every row of A_k and B_k, and the change of quantum numbers
+    struct TermMap {
+        std::vector<int> ra, rb;
+        std::vector<double> av, bv;
+        QN dA{0, 0};
+        bool live = false;
+    };
+    std::vector<TermMap> tmap(K);
     for (int k = 0; k < K; ++k) {
         const Mat& A = tc[k].A;
         const Mat& B = tc[k].B;
-        std::vector<int> ra(n, -1), rbm(n, -1);
-        std::vector<double> av(n, 0.0), bv(n, 0.0);
-        QN dA{0, 0}, dB{0, 0};
+        TermMap& t = tmap[k];
+        t.ra.assign(n, -1);
+        t.rb.assign(n, -1);
+        t.av.assign(n, 0.0);
+        t.bv.assign(n, 0.0);
+        QN dB{0, 0};
         bool seenA = false, seenB = false;
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) {
                 if (A(i, j) != 0.0) {
-                    if (ra[i] >= 0) {
+                    if (t.ra[i] >= 0) {
                         set_error("central operator with two nonzeros in a row");
                         return D2D_EINVAL;
                     }
-                    ra[i] = j;
-                    av[i] = A(i, j);
-                    dA = {col.qn[i].first - col.qn[j].first, col.qn[i].second - col.qn[j].second};
+                    t.ra[i] = j;
+                    t.av[i] = A(i, j);
+                    t.dA = {col.qn[i].first - col.qn[j].first, col.qn[i].second - col.qn[j].second};
                     seenA = true;
                 }
                 if (B(i, j) != 0.0) {
-                    if (rbm[i] >= 0) {
+                    if (t.rb[i] >= 0) {
                         set_error("central operator with two nonzeros in a row");
                         return D2D_EINVAL;
                     }
-                    rbm[i] = j;
-                    bv[i] = B(i, j);
+                    t.rb[i] = j;
+                    t.bv[i] = B(i, j);
                     dB = {col.qn[i].first - col.qn[j].first, col.qn[i].second - col.qn[j].second};
                     seenB = true;
                 }
             }
         if (!seenA || !seenB) continue;
-        if (dA.first + dB.first != 0 || dA.second + dB.second != 0) {
+        if (t.dA.first + dB.first != 0 || t.dA.second + dB.second != 0) {
             set_error("central term does not conserve the quantum numbers");
             return D2D_EINVAL;
         }
-        for (int p = 0; p < np; ++p) {
-            const QN qs{sb->pair_q[p].first - dA.first, sb->pair_q[p].second - dA.second};
-            auto it = pair_of.find(qs);
-            if (it == pair_of.end()) continue;
-            const int p2 = it->second;
-            src[(size_t)p * K + k] = p2;
-            const SectorDev& s = sb->pairs[p];
-            int64_t nr = 0, nc = 0;
-            for (int r = 0; r < s.dL; ++r) {
-                const int h = sb->rowsL[p][r], a = h / m, b = h % m;
-                if (ra[a] < 0) continue;
-                const int32_t pos = posL[(int64_t)ra[a] * m + b];
-                rmap[(size_t)k * rb + s.row_base + r] = pos;
-                rc[(size_t)k * rb + s.row_base + r] = tc[k].coef * av[a];
-                ++nr;
-            }
-            for (int c = 0; c < s.dR; ++c) {
-                const int h = sb->colsR[p][c], a = h / m, b = h % m;
-                if (rbm[a] < 0) continue;
-                const int32_t pos = posR[(int64_t)rbm[a] * m + b];
-                cmap[(size_t)k * cb + s.col_base + c] = pos;
-                cc[(size_t)k * cb + s.col_base + c] = bv[a];
-                ++nc;
-            }
-            gathers += nr * nc;
+        t.live = true;
+    }
+    // Rectangles: within a pair block, a run of rows with one column-2 state
+    // i2 times a run of columns with one column-3 state i3.  Term k maps the
+    // rectangle onto the rectangle of (A_k's column for i2, B_k's column for
+    // i3) in the pair shifted by its change of quantum numbers, with the same
+    // block-1 and block-4 states in the same order, times one coefficient.
+    struct Run {
+        int start, len, col, first;   // first packed index, length, column state, block state of the first
+    };
+    auto runs_of = [&](const std::vector<int32_t>& idx) {
+        std::vector<Run> out;
+        for (int i = 0; i < (int)idx.size(); ++i) {
+            const int a = idx[i] / m;
+            if (out.empty() || out.back().col != a) out.push_back({i, 0, a, idx[i] % m});
+            out.back().len++;
         }
+        return out;
+    };
+    std::vector<CentralUnit>& units = sb->h_cunits;
+    std::vector<CentralTerm>& terms = sb->h_cterms;
+    int64_t gathers = 0;
+    for (int p = 0; p < np; ++p) {
+        const SectorDev& s = sb->pairs[p];
+        const std::vector<Run> rr = runs_of(sb->rowsL[p]), cr = runs_of(sb->colsR[p]);
+        for (const Run& R : rr)
+            for (const Run& C : cr) {
+                std::vector<CentralTerm> list;
+                double self = 0.0;
+                for (int k = 0; k < K; ++k) {
+                    const TermMap& t = tmap[k];
+                    if (!t.live || t.ra[R.col] < 0 || t.rb[C.col] < 0) continue;
+                    auto it = pair_of.find(QN{sb->pair_q[p].first - t.dA.first, sb->pair_q[p].second - t.dA.second});
+                    if (it == pair_of.end()) continue;
+                    const int p2 = it->second;
+                    const double coef = tc[k].coef * t.av[R.col] * t.bv[C.col];
+                    if (coef == 0.0) continue;
+                    const int sr = posL[(int64_t)t.ra[R.col] * m + R.first];
+                    const int sc = posR[(int64_t)t.rb[C.col] * m + C.first];
+                    // the run maps onto consecutive rows / columns of the source block
+                    for (int i = 0; i < R.len; ++i)
+                        if (posL[(int64_t)t.ra[R.col] * m + sb->rowsL[p][R.start + i] % m] != sr + i) {
+                            set_error("central term: a row run does not map onto consecutive rows");
+                            return D2D_EINVAL;
+                        }
+                    for (int i = 0; i < C.len; ++i)
+                        if (posR[(int64_t)t.rb[C.col] * m + sb->colsR[p][C.start + i] % m] != sc + i) {
+                            set_error("central term: a column run does not map onto consecutive columns");
+                            return D2D_EINVAL;
+                        }
+                    gathers += (int64_t)R.len * C.len;
+                    const SectorDev& s2 = sb->pairs[p2];
+                    if (p2 == p && sr == R.start && sc == C.start) {
+                        self += coef;   // terms mapping the rectangle onto itself act as one
+                        continue;
+                    }
+                    CentralTerm e{};
+                    e.base = s2.off + sr + (int64_t)sc * s2.dL;
+                    e.ld = s2.dL;
+                    e.c64 = coef;
+                    e.c32 = (float)coef;
+                    list.push_back(e);
+                }
+                if (self != 0.0) {
+                    CentralTerm e{};
+                    e.base = s.off + R.start + (int64_t)C.start * s.dL;
+                    e.ld = s.dL;
+                    e.c64 = self;
+                    e.c32 = (float)self;
+                    list.insert(list.begin(), e);
+                }
+                const int tofs = (int)terms.size(), nt = (int)list.size();
+                terms.insert(terms.end(), list.begin(), list.end());
+                // work units of one wave: up to 64 rows x CENTRAL_CS * (64 / rows) columns
+                for (int ru = 0; ru < R.len; ru += 64) {
+                    const int nr = std::min(64, R.len - ru);
+                    const int span = CENTRAL_CS * (64 / nr);
+                    for (int cu = 0; cu < C.len; cu += span) {
+                        CentralUnit u{};
+                        u.off = s.off + R.start + (int64_t)C.start * s.dL;
+                        u.ldw = s.dL;
+                        u.ru = ru;
+                        u.nr = nr;
+                        u.cu = cu;
+                        u.nc = std::min(span, C.len - cu);
+                        u.tofs = tofs;
+                        u.nt = nt;
+                        u.p = p;
+                        units.push_back(u);
+                    }
+                }
+            }
     }
     sb->flops_central = 2.0 * (double)gathers;
-    std::vector<float> rc32(rc.begin(), rc.end()), cc32(cc.begin(), cc.end());
-    sb->h_src = src;
-    sb->h_rmap = rmap;
-    sb->h_cmap = cmap;
-    sb->h_rc = rc;
-    sb->h_cc = cc;
-    D2D_CHECK(upload(ctx, src, &sb->d_src));
-    D2D_CHECK(upload(ctx, rmap, &sb->d_rmap));
-    D2D_CHECK(upload(ctx, cmap, &sb->d_cmap));
-    D2D_CHECK(upload(ctx, rc, &sb->d_rcoef64));
-    D2D_CHECK(upload(ctx, cc, &sb->d_ccoef64));
-    D2D_CHECK(upload(ctx, rc32, &sb->d_rcoef32));
-    D2D_CHECK(upload(ctx, cc32, &sb->d_ccoef32));
-    // launch table of the central term: (pair, 64-row tile, 8-column tile)
-    if (K > 16) {
-        set_error("more than 16 central bond terms are not supported");
-        return D2D_EINVAL;
+    // every index a unit's wave forms (W and each term's source, at the
+    // unit's first and last row and column) inside the packed vector
+    for (const CentralUnit& u : units) {
+        const int64_t lo = u.ru + (int64_t)u.cu * u.ldw, hi = u.ru + u.nr - 1 + (int64_t)(u.cu + u.nc - 1) * u.ldw;
+        bool ok = u.nr >= 1 && u.nr <= 64 && u.nc >= 1 && u.nc <= CENTRAL_CS * (64 / u.nr) && u.off + lo >= 0 &&
+                  u.off + hi < sb->N && u.tofs >= 0 && u.tofs + u.nt <= (int)terms.size();
+        for (int t = 0; ok && t < u.nt; ++t) {
+            const CentralTerm& e = terms[u.tofs + t];
+            ok = e.base + u.ru + (int64_t)u.cu * e.ld >= 0 &&
+                 e.base + u.ru + u.nr - 1 + (int64_t)(u.cu + u.nc - 1) * e.ld < sb->N;
+        }
+        if (!ok) {
+            set_error("central term: a work unit reaches outside the vector");
+            return D2D_EINVAL;
+        }
     }
-    {
-        std::vector<CentralTile> cb;
-        central_tiles(sb->pairs, nullptr, cb);
-        sb->n_cblocks = (int)cb.size();
-        D2D_CHECK(upload(ctx, cb, &sb->d_cblocks));
-        std::vector<int64_t> so;
-        std::vector<int32_t> sd;
-        central_sources(sb->pairs, src, K, so, sd);
-        D2D_CHECK(upload(ctx, so, &sb->d_srcoff));
-        D2D_CHECK(upload(ctx, sd, &sb->d_srcdl));
-    }
+    D2D_CHECK(upload(ctx, units, &sb->d_cunits));
+    D2D_CHECK(upload(ctx, terms, &sb->d_cterms));
     {
         // half indices of the packed rows and columns (full-space conversion)
         std::vector<int32_t> hr, hc;
