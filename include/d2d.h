@@ -290,8 +290,11 @@ d2d_status d2d_tile_shapes(int* count, int* desc);
  * theta_j (1e-13 relative; exact arithmetic never raises it) or rho_{j+1} > 4
  * beta_k |y_k| (the true FP64 residual well above the one the Krylov
  * recurrence predicts).  Slow convergence of the Krylov space itself keeps
- * the precision.  A batch runs in one precision and raises it when any active
- * problem meets the condition.  k_in is capped at the problem dimension.
+ * the precision.  In a batch, a problem that meets the condition waits
+ * while the others go on converging at the current precision; when none is
+ * left, the waiting problems continue one precision higher (for one
+ * superblock this is plain escalation).  k_in is capped at the problem
+ * dimension.
  * Convergence: rho_j <= tol_res * |theta_j|, or, when tol_rel_e > 0, two
  * successive FP64 Rayleigh quotients with |theta_j - theta_{j-1}| <=
  * tol_rel_e * |theta_j|.
@@ -327,7 +330,9 @@ typedef struct {
 #define D2D_LOG_MAX 256
 typedef struct {
     int restarts;
-    int64_t hv_count[D2D_NPREC]; /* Hv applications per precision              */
+    int64_t hv_count[D2D_NPREC]; /* Hv applications to this problem per
+                                    precision (in a batch: the grouped launches
+                                    that included it)                          */
     double residual;          /* last rho                                      */
     double seconds;           /* wall time of the call                         */
     int nlog;                 /* entries in the per-restart log                */

@@ -482,7 +482,12 @@ extern "C" d2d_status d2d_batch_autotune(d2d_batch* b, int prec, int reps, int* 
     const d2d_status st = tune_configs(s, prec, reps, [&](const TileSel& c) {
         apply(c);
         HvParts parts{};
-        return batch_hv(b, prec, b->stage_v, b->stage_w, s, c.fuse ? &parts : nullptr);
+        D2D_CHECK(batch_hv(b, prec, b->stage_v, b->stage_w, s, c.fuse ? &parts : nullptr));
+        if (!c.fuse) return D2D_OK;
+        // a fused product leaves its parts to the consumer: charge reading them
+        const void* pp[4] = {parts.x[0], parts.x[1], parts.x[2], parts.central};
+        D2D_HIP(launch_read_parts(pp, prec, b->ntot, b->stage_w, s));
+        return D2D_OK;
     }, &sel, &bms);
     if (st != D2D_OK) {
         apply(saved);

@@ -171,6 +171,8 @@ hipError_t launch_cast_f64_f32(const double* x, float* y, int64_t n, hipStream_t
 hipError_t launch_cast_f64_bf16(const double* x, bf16_t* y, int64_t n, hipStream_t s);
 hipError_t launch_cast_f32_bf16(const float* x, bf16_t* y, int64_t n, hipStream_t s);
 hipError_t launch_fill(void* x, int prec, int64_t n, double v, hipStream_t s);
+// reads the (nullable) parts[0..4) of a fused product (FP64 for FP64, else FP32)
+hipError_t launch_read_parts(const void* const* parts, int prec, int64_t n, void* sink, hipStream_t s);
 hipError_t launch_check_finite(const void* x, int prec, int64_t n, int* flag, hipStream_t s);
 
 // ---------------------------------------------------------------- Lanczos kernels

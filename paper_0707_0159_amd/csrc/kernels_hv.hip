@@ -974,6 +974,35 @@ hipError_t launch_fill(void* x, int prec, int64_t n, double v, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Reads the parts of a fused product as the first Lanczos step kernel does
+// (autotuning charges a launch configuration for the partial outputs it leaves
+// to its consumer); stores nothing unless a sum hits an impossible value.
+template <typename T>
+__global__ void k_read_parts(const T* __restrict__ p0, const T* __restrict__ p1, const T* __restrict__ p2,
+                             const T* __restrict__ p3, int64_t n, T* sink) {
+    T acc = T(0);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (p0) acc += p0[i];
+        if (p1) acc += p1[i];
+        if (p2) acc += p2[i];
+        if (p3) acc += p3[i];
+    }
+    if (acc == T(-1.2345e-30)) sink[0] = acc;
+}
+
+hipError_t launch_read_parts(const void* const* parts, int prec, int64_t n, void* sink, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (prec == D2D_FP64)
+        hipLaunchKernelGGL(k_read_parts<double>, dim3(grid_for(n)), dim3(256), 0, s, (const double*)parts[0],
+                           (const double*)parts[1], (const double*)parts[2], (const double*)parts[3], n,
+                           (double*)sink);
+    else
+        hipLaunchKernelGGL(k_read_parts<float>, dim3(grid_for(n)), dim3(256), 0, s, (const float*)parts[0],
+                           (const float*)parts[1], (const float*)parts[2], (const float*)parts[3], n,
+                           (float*)sink);
+    return hipGetLastError();
+}
+
 // flag[0] set to 1 if any element is NaN or Inf
 template <typename T>
 __global__ void k_check_finite(const T* __restrict__ x, int64_t n, int* flag) {

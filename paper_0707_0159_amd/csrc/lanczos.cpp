@@ -16,7 +16,11 @@
 // A set of problems (a batch) runs in lockstep: their vectors are
 // concatenated, the vector kernels are segmented per problem, the Hv is one
 // grouped launch over all of them, and a converged problem leaves the launches
-// at the next restart.  One superblock is the set of one.
+// at the next restart.  A problem whose restarts fall short because of the
+// working precision waits until the others are done at that precision, and
+// the waiting problems then go on one precision higher.  One superblock is
+// the set of one.
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -273,8 +277,6 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
     std::vector<int> act(np, 1);
     D2D_CHECK(set_active_flags(w, act));
     D2D_CHECK(hv.set_active(act, nullptr));
-    int64_t cnt0[D2D_NPREC];
-    for (int i = 0; i < D2D_NPREC; ++i) cnt0[i] = hv.counter(i);
     for (int p = 0; p < np; ++p) {
         if (v0 && v0[p])
             D2D_HIP(hipMemcpyAsync(w->X + w->seg_off[p], v0[p], (size_t)len[p] * 8, hipMemcpyDeviceToDevice, s));
@@ -299,31 +301,37 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
     std::vector<int> have_prev(np, 0);
     std::vector<d2d_lanczos_stats> st(np);
     std::memset(st.data(), 0, sizeof(d2d_lanczos_stats) * np);
-    std::vector<int> done(np, 0), restarts(np, 0);
+    // deferred: the problem's restarts need a higher precision; it waits until
+    // the problems still converging at this precision are done
+    std::vector<int> done(np, 0), restarts(np, 0), deferred(np, 0);
+    // Hv applications to each problem by precision (the initial FP64 residual included)
+    std::vector<std::array<int64_t, D2D_NPREC>> hvc(np);
     for (int p = 0; p < np; ++p) {
         theta[p] = w->res_host[2 * p];
         rho[p] = w->res_host[2 * p + 1];
+        hvc[p].fill(0);
+        hvc[p][D2D_FP64] = 1;
     }
     int prec = opts->prec;
     int j = 0;
     d2d_status result = D2D_OK;
     for (;;) {
         const double tsec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        bool changed = false, escalate = false, any = false;
+        bool changed = false, any = false;
         for (int p = 0; p < np; ++p) {
-            if (done[p]) continue;
+            if (done[p] || deferred[p]) continue;
             if (!std::isfinite(theta[p]) || !std::isfinite(rho[p])) {
                 set_error("Lanczos: non-finite Rayleigh quotient (problem %d, restart %d)", p, j);
                 return D2D_EDEVICE;
             }
-            // Raise the precision only when the restart both made poor progress and
-            // shows the inner products' error: the Rayleigh quotient rose (exact
-            // arithmetic never lets it), or the true residual is well above the
-            // one the Krylov recurrence predicted.  Slow convergence of the
-            // Krylov space itself (the estimate matches) is left alone.
-            if (rho_prev[p] >= 0.0 && opts->escalate > 0.0 && rho[p] > opts->escalate * rho_prev[p] &&
-                (theta[p] > theta_prev[p] + 1e-13 * std::fabs(theta_prev[p]) || rho[p] > 4.0 * pred[p]))
-                escalate = true;
+            // A restart is short of what it should achieve because of the
+            // low-precision products when it both made poor progress and shows
+            // their error: the Rayleigh quotient rose (exact arithmetic never
+            // lets it), or the true residual is well above the one the Krylov
+            // recurrence predicted.  Slow convergence of the Krylov space itself
+            // (the estimate matches) keeps the precision.
+            const bool shortfall = rho_prev[p] >= 0.0 && opts->escalate > 0.0 && rho[p] > opts->escalate * rho_prev[p] &&
+                                   (theta[p] > theta_prev[p] + 1e-13 * std::fabs(theta_prev[p]) || rho[p] > 4.0 * pred[p]);
             d2d_lanczos_stats& sp = st[p];
             if (sp.nlog < D2D_LOG_MAX) {
                 sp.log_t[sp.nlog] = tsec;
@@ -342,18 +350,26 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
                 if (psi && psi[p])
                     D2D_HIP(hipMemcpyAsync(psi[p], w->X + w->seg_off[p], (size_t)len[p] * 8,
                                            hipMemcpyDeviceToDevice, s));
+            } else if (shortfall && prec != D2D_FP64) {
+                deferred[p] = 1;
+                changed = true;
             } else {
                 any = true;
             }
         }
-        if (escalate && prec != D2D_FP64) {
-            // BF16 -> BF16x3 (when kept) -> FP32 (when kept) -> FP64
+        if (!any) {
+            // nothing left at this precision: the deferred problems go on one
+            // step higher (BF16 -> BF16x3 when kept -> FP32 when kept -> FP64)
+            bool wait = false;
+            for (int p = 0; p < np; ++p) wait = wait || deferred[p];
+            if (!wait) break;
             int nxt = D2D_FP64;
             if (prec == D2D_BF16 && hv.has(D2D_BF16X3)) nxt = D2D_BF16X3;
             else if ((prec == D2D_BF16 || prec == D2D_BF16X3) && hv.has(D2D_FP32)) nxt = D2D_FP32;
             prec = nxt;
+            for (int p = 0; p < np; ++p) deferred[p] = 0;
+            changed = true;
         }
-        if (!any) break;
         if (j >= opts->max_restarts) {
             set_error("Lanczos: no convergence after %d restarts", j);
             result = D2D_ENOCONV;
@@ -363,9 +379,9 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
                                            hipMemcpyDeviceToDevice, s));
             break;
         }
+        std::vector<int> a(np);
+        for (int p = 0; p < np; ++p) a[p] = done[p] || deferred[p] ? 0 : 1;
         if (changed) {
-            std::vector<int> a(np);
-            for (int p = 0; p < np; ++p) a[p] = done[p] ? 0 : 1;
             D2D_HIP(hipStreamSynchronize(s));
             D2D_CHECK(set_active_flags(w, a));
             bool rebuilt = false;
@@ -374,17 +390,22 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
         }
         D2D_CHECK(restart(w, hv, prec, k, opts->reorth_window, opts->separate_central == 0, opts->plain_cgs2 != 0,
                           opts->use_graph != 0, s));
+        for (int p = 0; p < np; ++p)
+            if (a[p]) {
+                hvc[p][prec] += k - 1;
+                hvc[p][D2D_FP64] += 1;
+            }
         D2D_HIP(hipStreamSynchronize(s));
         ++j;
         for (int p = 0; p < np; ++p) {
-            if (done[p]) continue;
+            if (!a[p]) continue;
             rho_prev[p] = rho[p];
             theta_prev[p] = theta[p];
             have_prev[p] = 1;
             theta[p] = w->res_host[2 * p];
             rho[p] = w->res_host[2 * p + 1];
             pred[p] = w->res_host[2 * np + p];
-            restarts[p] = j;
+            restarts[p] += 1;   // the restarts that included the problem
         }
     }
     D2D_HIP(hipStreamSynchronize(s));
@@ -394,7 +415,7 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
         st[p].restarts = restarts[p];
         st[p].residual = rho[p];
         if (!done[p]) st[p].seconds = total;
-        for (int i = 0; i < D2D_NPREC; ++i) st[p].hv_count[i] = hv.counter(i) - cnt0[i];
+        for (int i = 0; i < D2D_NPREC; ++i) st[p].hv_count[i] = hvc[p][i];
         if (stats) stats[p] = st[p];
     }
     if (np == 1 && stats) stats[0].seconds = total;

@@ -1201,7 +1201,12 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
         st = tune_configs(s, prec, reps, [&](const TileSel& c) {
             apply(c);
             HvParts parts{};
-            return sb_hv_parts(sb, prec, v, w, s, HV_ALL, c.fuse ? &parts : nullptr);
+            D2D_CHECK(sb_hv_parts(sb, prec, v, w, s, HV_ALL, c.fuse ? &parts : nullptr));
+            if (!c.fuse) return D2D_OK;
+            // a fused product leaves its parts to the consumer: charge reading them
+            const void* pp[4] = {parts.x[0], parts.x[1], parts.x[2], parts.central};
+            D2D_HIP(launch_read_parts(pp, prec, sb->N, w, s));
+            return D2D_OK;
         }, &sel, &bms);
     ctx->free(v, (size_t)sb->N * in_sz);
     ctx->free(w, (size_t)sb->N * out_sz);

@@ -199,3 +199,44 @@ def test_config5_sampled_hv_against_oracle(ctx):
         done += 1
     print("config5 problems checked", done)
     assert done >= 16
+
+
+@pytest.fixture(scope="module")
+def config5_batch15(ctx):
+    from paper_0707_0159_amd import d2d
+    wls, refs = config5_or_skip()
+    probs = [GpuProblem(ctx, wl, prec_mask=15) for wl in wls]
+    b = d2d.d2d_batch_create(ctx, [p.sb for p in probs])
+    yield wls, refs, probs, b
+    d2d.d2d_batch_destroy(b)
+    for p in probs:
+        p.close()
+
+
+def test_config5_bf16_defers_only_the_problems_that_need_more(ctx, config5_batch15):
+    """BF16 batch of the 64 uneven superblocks: a problem whose BF16 restarts
+    fall short (the small ladders, whose energy rises) waits and finishes in
+    BF16x3 while the others stay in BF16 throughout; every energy within
+    1e-10, and each problem's Hv count is the launches that included it."""
+    from paper_0707_0159_amd import d2d
+    wls, refs, probs, b = config5_batch15
+    with torch.cuda.stream(ctx.stream):
+        v0 = [torch.as_tensor(W.random_vector(p.info["n"], wl.seed)).to("cuda") for p, wl in zip(probs, wls)]
+    ctx.stream.synchronize()
+    opts = d2d.lanczos_opts(prec=d2d.D2D_BF16, k_in=24, max_restarts=400, tol_res=1e-8, reorth_window=3)
+    st, e, per = d2d.d2d_batch_lanczos(b, opts, v0)
+    assert st == 0
+    dE = [abs(ei - refs[wl.name]) / abs(refs[wl.name]) for ei, wl in zip(e, wls)]
+    raised = [i for i, q in enumerate(per) if max(q["log_prec"]) > d2d.D2D_BF16]
+    kept = [i for i, q in enumerate(per) if set(q["log_prec"]) == {d2d.D2D_BF16}]
+    print(f"config5 bf16: max dE {max(dE):.2e}, raised {[(i, probs[i].info['n']) for i in raised]}, "
+          f"kept {len(kept)}")
+    assert max(dE) <= 1e-10
+    assert raised and kept
+    assert max(probs[i].info["n"] for i in kept) > 10 * max(probs[i].info["n"] for i in raised)
+    for q in per:
+        # one FP64 residual per restart plus the first; k_in - 1 inner products per restart
+        assert q["hv_count"][d2d.D2D_FP64] == q["restarts"] + 1
+        assert sum(q["hv_count"][1:]) == 23 * q["restarts"]
+    counts = {tuple(q["hv_count"]) for q in per}
+    assert len(counts) > 1
