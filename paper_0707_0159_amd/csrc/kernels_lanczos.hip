@@ -559,10 +559,14 @@ struct GramLayout {
     __host__ __device__ static constexpr int g(int j, int l) { return NQ + 1 + j * NQ - j * (j - 1) / 2 + (l - j); }
 };
 
+// First kernel of the Gram form: w = (((w + P0) + P1) + P2) + P3 in the Hv's
+// precision, stored back in place (in that precision: the FP32 sum is what
+// the second kernel upcasts) when there are parts; partials of c1 = Q^T w,
+// |w|^2 and the window's Gram matrix.
 template <int NQ, bool UPCAST>
 __global__ void __launch_bounds__(LZ_THREADS)
 k_lz_dots_gram(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int64_t ldq, int nq,
-               const double* w64in, const float* __restrict__ w32, const HvPartPtrs P, double* w64out,
+               typename std::conditional<UPCAST, float, double>::type* wio, const HvPartPtrs P,
                double* __restrict__ partial, int NB) {
     using GL = GramLayout<NQ>;
     constexpr int U = StepUnroll<NQ>::U;
@@ -574,7 +578,7 @@ k_lz_dots_gram(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int64
     for (int j = 0; j < GL::ROWS; ++j) acc[j] = 0.0;
     const int64_t st = blockDim.x;
     using TW = typename std::conditional<UPCAST, float, double>::type;
-    const TW* win = UPCAST ? (const TW*)w32 : (const TW*)w64in;
+    const TW* win = wio;
     for (int64_t e0 = sg.lo + threadIdx.x; e0 < sg.hi; e0 += U * st) {
         double x[U], q[U][NQ];
         TW wv[U], pv[4][U];
@@ -597,7 +601,7 @@ k_lz_dots_gram(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int64
             for (int i = 0; i < 4; ++i)
                 if (P.p[i]) f = f + pv[i][u];
             x[u] = ok ? (double)f : 0.0;
-            if ((UPCAST || any) && ok) w64out[e] = x[u];
+            if (any && ok) wio[e] = f;
 #pragma unroll
             for (int j = 0; j < NQ; ++j) q[u][j] = ok ? q[u][j] : 0.0;
 #pragma unroll
@@ -614,10 +618,11 @@ k_lz_dots_gram(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int64
 
 // Second kernel: d, alpha_i = d[nq-1], beta = |w - Q d| from the sums;
 // q_next = (w - Q d) / beta and its low-precision copy.
-template <int NQ>
+template <int NQ, bool UPCAST>
 __global__ void __launch_bounds__(LZ_THREADS)
 k_lz_update_gram(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int64_t ldq, int nq,
-                 const double* __restrict__ partial_in, int NB, const double* __restrict__ w,
+                 const double* __restrict__ partial_in, int NB,
+                 const typename std::conditional<UPCAST, float, double>::type* __restrict__ w,
                  double* __restrict__ qnext, void* __restrict__ lo, int lo_prec, double* __restrict__ scal, int i) {
     using GL = GramLayout<NQ>;
     const LzSeg sg = bt[blockIdx.x];
@@ -660,7 +665,7 @@ k_lz_update_gram(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int
         for (int u = 0; u < 4; ++u) {
             const int64_t e = e0 + u * st;
             const int64_t ec = e < sg.hi ? e : sg.lo;
-            x[u] = w[ec];
+            x[u] = (double)w[ec];
 #pragma unroll
             for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? Q[j * ldq + ec] : 0.0;
         }
@@ -683,16 +688,22 @@ static hipError_t lz_step_gram(const LzStepArgs& a, hipStream_t s) {
     const int NB = a.NB;
     HvPartPtrs P;
     for (int i = 0; i < 4; ++i) P.p[i] = a.wpart[i];
-    if (a.upcast)
+    // the low-precision product's sum stays in its FP32 buffer (the upcast is exact)
+    if (a.upcast) {
         hipLaunchKernelGGL((k_lz_dots_gram<NQ, true>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq,
-                           (const double*)nullptr, a.w32, P, a.w, a.partial, NB);
-    else
+                           (float*)a.w32, P, a.partial, NB);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_lz_update_gram<NQ, true>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq,
+                           a.partial, NB, (const float*)a.w32, a.qnext, a.lo, a.lo ? a.lo_prec : -1, a.scal, a.i);
+    } else {
         hipLaunchKernelGGL((k_lz_dots_gram<NQ, false>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq,
-                           a.w, (const float*)nullptr, P, a.w, a.partial, NB);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_lz_update_gram<NQ>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq, a.partial,
-                       NB, a.w, a.qnext, a.lo, a.lo ? a.lo_prec : -1, a.scal, a.i);
+                           a.w, P, a.partial, NB);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_lz_update_gram<NQ, false>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq,
+                           a.partial, NB, (const double*)a.w, a.qnext, a.lo, a.lo ? a.lo_prec : -1, a.scal, a.i);
+    }
     return hipGetLastError();
 }
 
