@@ -628,6 +628,9 @@ hipError_t launch_hv_gemm_bf16(int shape, const HvGemmArgs& a, const void* VT, h
         case 29: gemm_bf16_launch<128, 128, 32, 2, 2, 1, true>(a, VT, st); break;
         case 30: gemm_bf16_launch<32, 32, 32, 1, 1, 2, true>(a, VT, st); break;
         case 31: gemm_bf16_launch<64, 64, 32, 2, 2, 2, true>(a, VT, st); break;
+        case 32: gemm_bf16_launch<256, 128, 64, 4, 2, 1, false>(a, VT, st); break;
+        case 33: gemm_bf16_launch<128, 256, 64, 2, 4, 1, false>(a, VT, st); break;
+        case 34: gemm_bf16_launch<256, 128, 32, 4, 2, 1, true>(a, VT, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -821,6 +824,13 @@ static const TileShape kShapes[] = {
     {D2D_BF16X3, 128, 128, 32},   // 29
     {D2D_BF16X3, 32, 32, 32, 2},  // 30: 1 wave
     {D2D_BF16X3, 64, 64, 32, 2},  // 31
+    // 8 waves of 64x64: an output tile twice as large re-reads its operator
+    // and input panels half as often (large sectors)
+    {D2D_BF16, 256, 128, 64},     // 32
+    {D2D_BF16, 128, 256, 64},     // 33
+    {D2D_BF16X3, 256, 128, 32},   // 34
+    {D2D_FP32, 256, 128, 16},     // 35
+    {D2D_FP32, 128, 256, 16},     // 36
 };
 
 int tile_shape_count() { return (int)(sizeof(kShapes) / sizeof(kShapes[0])); }
@@ -873,6 +883,8 @@ hipError_t launch_hv_gemm(int shape, const HvGemmArgs& a, hipStream_t st) {
         case 22: gemm_launch<float, 32, 32, 16, 1, 1, 2>(a, st); break;
         case 23: gemm_launch<double, 64, 64, 16, 2, 2, 2>(a, st); break;
         case 24: gemm_launch<float, 128, 64, 16, 2, 2, 2>(a, st); break;
+        case 35: gemm_launch<float, 256, 128, 16, 4, 2, 1>(a, st); break;
+        case 36: gemm_launch<float, 128, 256, 16, 2, 4, 1>(a, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
