@@ -30,45 +30,56 @@ __device__ inline ItemK decode_item(int part) {
 }
 
 // The K-loop of one item over its step list ks[0..n): double-buffered LDS,
-// PF steps' global loads in flight while a step is computed.  The step start
-// that the next load needs is read one step ahead.
+// PF steps' global loads in flight while a step is computed.  Every
+// iteration issues the same loads (past the end of the list it reloads the
+// last step), so the compiler can wait for exactly the step being staged;
+// the step starts are scalar loads issued just before a barrier, whose wait
+// covers them, so no LDS wait has to wait for one.
+// stage(buf, k0) receives the start of the step its registers hold.
 template <int PF, typename L0, typename L1, typename S0, typename S1, typename C>
-__device__ inline void k_steps(const int32_t* __restrict__ ks, int n, L0&& gload0, L1&& gload1, S0&& stage0,
+__device__ __attribute__((always_inline)) inline void k_steps(const int32_t* __restrict__ ks, int n, L0&& gload0, L1&& gload1, S0&& stage0,
                                S1&& stage1, C&& compute) {
+    if (n <= 0) return;
+    auto at = [&](int i) { return ks[i < n ? i : n - 1]; };
     int buf = 0;
     if constexpr (PF == 1) {
-        if (n > 0) gload0(ks[0]);
-        int knext = n > 1 ? ks[1] : 0;
+        int kcur = at(0);
+        gload0(kcur);
+        int knext = at(1);
 #pragma unroll 1
         for (int i = 0; i < n; ++i) {
-            stage0(buf);
+            const int kafter = at(i + 2);
+            stage0(buf, kcur);
             __syncthreads();
-            const int kafter = i + 2 < n ? ks[i + 2] : 0;
-            if (i + 1 < n) gload0(knext);
+            gload0(knext);
             compute(buf);
             buf ^= 1;
+            kcur = knext;
             knext = kafter;
         }
     } else {
-        if (n > 0) gload0(ks[0]);
-        if (n > 1) gload1(ks[1]);
-        int kn0 = n > 2 ? ks[2] : 0, kn1 = n > 3 ? ks[3] : 0;
+        int kc0 = at(0), kc1 = at(1);
+        gload0(kc0);
+        gload1(kc1);
+        int kn0 = at(2), kn1 = at(3);
 #pragma unroll 1
         for (int i = 0; i < n; i += 2) {
-            stage0(buf);
+            const int ka0 = at(i + 4);
+            stage0(buf, kc0);
             __syncthreads();
-            const int ka0 = i + 4 < n ? ks[i + 4] : 0;
-            if (i + 2 < n) gload0(kn0);
+            gload0(kn0);
             compute(buf);
             buf ^= 1;
+            kc0 = kn0;
             kn0 = ka0;
             if (i + 1 >= n) break;
-            stage1(buf);
+            const int ka1 = at(i + 5);
+            stage1(buf, kc1);
             __syncthreads();
-            const int ka1 = i + 5 < n ? ks[i + 5] : 0;
-            if (i + 3 < n) gload1(kn1);
+            gload1(kn1);
             compute(buf);
             buf ^= 1;
+            kc1 = kn1;
             kn1 = ka1;
         }
     }
@@ -345,25 +356,32 @@ k_hv_gemm(const HvK<T> g) {
         const int64_t ldb = phase == 0 ? dL : dR;
         const int K = phase == 0 ? dL : dR;
 
-        auto gload = [&](int k0, T (&xa)[EA], T (&xb)[EB]) {
+        // Loads are unconditional, at indices clamped into the block: a load
+        // under a lane condition becomes a branch around it, which leaves the
+        // compiler no count of the loads in flight, so every step would wait
+        // for all of them (the prefetched step's included).  Rows and columns
+        // past the block only feed outputs that are not stored; K past the
+        // block is zeroed in the A tile when it is staged.
+        auto gload = [&](int k0, T (&xa)[EA], T (&xb)[EB]) __attribute__((always_inline)) {
 #pragma unroll
             for (int e = 0; e < EA; ++e) {
                 const int idx = t + NT * e, i = idx % BM, k = idx / BM;
                 const int r = row0 + i, kk = k0 + k;
-                xa[e] = (r < dL && kk < K) ? A[r + kk * lda] : T(0);
+                xa[e] = A[(r < dL ? r : dL - 1) + (int64_t)(kk < K ? kk : K - 1) * lda];
             }
 #pragma unroll
             for (int e = 0; e < EB; ++e) {
                 const int idx = t + NT * e, k = idx % BK, j = idx / BK;
                 const int c = col0 + j, kk = k0 + k;
-                xb[e] = (c < dR && kk < K) ? B[kk + c * ldb] : T(0);
+                xb[e] = B[(kk < K ? kk : K - 1) + (int64_t)(c < dR ? c : dR - 1) * ldb];
             }
         };
-        auto stage = [&](const T (&xa)[EA], const T (&xb)[EB], int buf) {
+        auto stage = [&](const T (&xa)[EA], const T (&xb)[EB], int buf, int k0) __attribute__((always_inline)) {
+            const bool tail = k0 + BK > K;   // wave-uniform: only the last step of a K-loop
 #pragma unroll
             for (int e = 0; e < EA; ++e) {
                 const int idx = t + NT * e;
-                As[buf][idx / BM][idx % BM] = xa[e];
+                As[buf][idx / BM][idx % BM] = tail && k0 + idx / BM >= K ? T(0) : xa[e];
             }
 #pragma unroll
             for (int e = 0; e < EB; ++e) {
@@ -371,20 +389,30 @@ k_hv_gemm(const HvK<T> g) {
                 Bs[buf][idx / BK][idx % BK] = xb[e];
             }
         };
-        auto compute = [&](int buf) {
+        // FP32: a step's operand fragments are read from LDS in groups of KG
+        // slices ahead of their MFMAs, so one wait covers a group (FP64 reads
+        // them slice by slice: the larger fragments would cost occupancy)
+        auto compute = [&](int buf) __attribute__((always_inline)) {
+            constexpr int NS = BK / M::MK, KG = sizeof(T) == 8 ? 1 : (NS < 8 ? NS : 8);
 #pragma unroll
-            for (int kk = 0; kk < BK; kk += M::MK) {
-                T a[FM], b[FN];
+            for (int g0 = 0; g0 < NS; g0 += KG) {
+                T a[KG][FM], b[KG][FN];
 #pragma unroll
-                for (int i = 0; i < FM; ++i)
-                    a[i] = As[buf][kk + lane / M::MN][wm * WM + i * M::MN + lane % M::MN];
+                for (int q = 0; q < KG; ++q) {
+                    const int kk = (g0 + q) * M::MK;
 #pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    b[j] = Bs[buf][wn * WN + j * M::MN + lane % M::MN][kk + lane / M::MN];
+                    for (int i = 0; i < FM; ++i)
+                        a[q][i] = As[buf][kk + lane / M::MN][wm * WM + i * M::MN + lane % M::MN];
 #pragma unroll
-                for (int i = 0; i < FM; ++i)
+                    for (int j = 0; j < FN; ++j)
+                        b[q][j] = Bs[buf][wn * WN + j * M::MN + lane % M::MN][kk + lane / M::MN];
+                }
 #pragma unroll
-                    for (int j = 0; j < FN; ++j) acc[i][j] = M::op(b[j], a[i], acc[i][j]);
+                for (int q = 0; q < KG; ++q)
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j) acc[i][j] = M::op(b[q][j], a[q][i], acc[i][j]);
             }
         };
 
@@ -397,13 +425,13 @@ k_hv_gemm(const HvK<T> g) {
         const int32_t* ks = g.ksteps + (phase == 0 ? wi.ks[0] : wi.ks[1]);
         const int nks = phase == 0 ? wi.kn[0] : wi.kn[1];
         k_steps<PF>(
-            ks, nks, [&](int k0) { gload(k0, ra, rb); },
-            [&](int k0) {
+            ks, nks, [&](int k0) __attribute__((always_inline)) { gload(k0, ra, rb); },
+            [&](int k0) __attribute__((always_inline)) {
                 if constexpr (PF == 2) gload(k0, ra1, rb1);
             },
-            [&](int buf) { stage(ra, rb, buf); },
-            [&](int buf) {
-                if constexpr (PF == 2) stage(ra1, rb1, buf);
+            [&](int buf, int k0) __attribute__((always_inline)) { stage(ra, rb, buf, k0); },
+            [&](int buf, int k0) __attribute__((always_inline)) {
+                if constexpr (PF == 2) stage(ra1, rb1, buf, k0);
             },
             compute);
         __syncthreads();
@@ -501,7 +529,7 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const int32_t* __re
         const int64_t ld = phase == 0 ? s.dLp : s.dRp;     // both operands share the K stride
         const int Kp = phase == 0 ? s.dLp : s.dRp;
 
-        auto gload = [&](int k0, uint4 (&xa)[NP][EA], uint4 (&xb)[NP][EB]) {
+        auto gload = [&](int k0, uint4 (&xa)[NP][EA], uint4 (&xb)[NP][EB]) __attribute__((always_inline)) {
 #pragma unroll
             for (int h = 0; h < NP; ++h) {
 #pragma unroll
@@ -520,7 +548,9 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const int32_t* __re
                 }
             }
         };
-        auto stage = [&](const uint4 (&xa)[NP][EA], const uint4 (&xb)[NP][EB], int buf) {
+        // (unconditional loads at clamped indices put the register sets in
+        // scratch memory here, so the loads keep their bounds conditions)
+        auto stage = [&](const uint4 (&xa)[NP][EA], const uint4 (&xb)[NP][EB], int buf, int) __attribute__((always_inline)) {
 #pragma unroll
             for (int h = 0; h < NP; ++h) {
 #pragma unroll
@@ -535,7 +565,7 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const int32_t* __re
                 }
             }
         };
-        auto compute = [&](int buf) {
+        auto compute = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 16) {
                 bf16x8 a[NP][FM], b[NP][FN];
@@ -564,13 +594,13 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const int32_t* __re
         const int32_t* ks = ksteps + (phase == 0 ? wi.ks[0] : wi.ks[1]);
         const int nks = phase == 0 ? wi.kn[0] : wi.kn[1];
         k_steps<PF>(
-            ks, nks, [&](int k0) { gload(k0, ra, rb); },
-            [&](int k0) {
+            ks, nks, [&](int k0) __attribute__((always_inline)) { gload(k0, ra, rb); },
+            [&](int k0) __attribute__((always_inline)) {
                 if constexpr (PF == 2) gload(k0, ra1, rb1);
             },
-            [&](int buf) { stage(ra, rb, buf); },
-            [&](int buf) {
-                if constexpr (PF == 2) stage(ra1, rb1, buf);
+            [&](int buf, int k0) __attribute__((always_inline)) { stage(ra, rb, buf, k0); },
+            [&](int buf, int k0) __attribute__((always_inline)) {
+                if constexpr (PF == 2) stage(ra1, rb1, buf, k0);
             },
             compute);
         __syncthreads();
