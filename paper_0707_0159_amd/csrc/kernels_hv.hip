@@ -461,6 +461,7 @@ k_hv_gemm(const HvK<T> g) {
 //   phase 1: A = V^T (column-major dR x dL, ld dRp), B = H_r^T (ld dRp)
 // K runs over the padded length; the padding of every operand is zero.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 struct OutPtrs {
     float* W;
     float* X[3];
@@ -519,7 +520,7 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const int32_t* __re
 #pragma unroll
             for (int v = 0; v < M::NV; ++v) acc[i][j][v] = 0.0f;
 
-    uint4 ra[NP][EA], rb[NP][EB];
+    u32x4 ra[NP][EA], rb[NP][EB];
     const ItemK it = decode_item(wi.part);
 #pragma unroll 1
     for (int phase = it.ph_lo; phase < it.ph_hi; ++phase) {
@@ -529,39 +530,42 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const int32_t* __re
         const int64_t ld = phase == 0 ? s.dLp : s.dRp;     // both operands share the K stride
         const int Kp = phase == 0 ? s.dLp : s.dRp;
 
-        auto gload = [&](int k0, uint4 (&xa)[NP][EA], uint4 (&xb)[NP][EB]) __attribute__((always_inline)) {
+        auto gload = [&](int k0, u32x4 (&xa)[NP][EA], u32x4 (&xb)[NP][EB]) __attribute__((always_inline)) {
 #pragma unroll
             for (int h = 0; h < NP; ++h) {
 #pragma unroll
                 for (int e = 0; e < EA; ++e) {
                     const int idx = t + NT * e, r = idx / KV, kv = idx % KV;
                     const int gr = row0 + r, kk = k0 + 8 * kv;
-                    xa[h][e] = (gr < dL && kk < Kp) ? *(const uint4*)(A + h * loA + gr * ld + kk)
-                                                    : make_uint4(0, 0, 0, 0);
+                    xa[h][e] = *(const u32x4*)(A + h * loA + (int64_t)::min(gr, dL - 1) * ld + ::min(kk, Kp - 8));
                 }
 #pragma unroll
                 for (int e = 0; e < EB; ++e) {
                     const int idx = t + NT * e, c = idx / KV, kv = idx % KV;
                     const int gc = col0 + c, kk = k0 + 8 * kv;
-                    xb[h][e] = (gc < dR && kk < Kp) ? *(const uint4*)(B + h * loB + gc * ld + kk)
-                                                    : make_uint4(0, 0, 0, 0);
+                    xb[h][e] = *(const u32x4*)(B + h * loB + (int64_t)::min(gc, dR - 1) * ld + ::min(kk, Kp - 8));
                 }
             }
         };
-        // (unconditional loads at clamped indices put the register sets in
-        // scratch memory here, so the loads keep their bounds conditions)
-        auto stage = [&](const uint4 (&xa)[NP][EA], const uint4 (&xb)[NP][EB], int buf, int) __attribute__((always_inline)) {
+        // Loads as in the FP32 kernel: unconditional at clamped indices, K past
+        // the padded length zeroed in the A tile when staged.  The register
+        // sets are native vectors (a struct type would put them in scratch
+        // memory once the loads are unconditional).
+        auto stage = [&](const u32x4 (&xa)[NP][EA], const u32x4 (&xb)[NP][EB], int buf, int k0) __attribute__((always_inline)) {
+            const bool tail = k0 + BK > Kp;   // wave-uniform: only the last step of a K-loop
 #pragma unroll
             for (int h = 0; h < NP; ++h) {
 #pragma unroll
                 for (int e = 0; e < EA; ++e) {
                     const int idx = t + NT * e;
-                    *(uint4*)&As[buf][h][idx / KV][8 * (idx % KV)] = xa[h][e];
+                    const u32x4 z = {0u, 0u, 0u, 0u};
+                    *(u32x4*)&As[buf][h][idx / KV][8 * (idx % KV)] =
+                        tail && k0 + 8 * (idx % KV) >= Kp ? z : xa[h][e];
                 }
 #pragma unroll
                 for (int e = 0; e < EB; ++e) {
                     const int idx = t + NT * e;
-                    *(uint4*)&Bs[buf][h][idx / KV][8 * (idx % KV)] = xb[h][e];
+                    *(u32x4*)&Bs[buf][h][idx / KV][8 * (idx % KV)] = xb[h][e];
                 }
             }
         };
@@ -590,7 +594,7 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const int32_t* __re
                     }
             }
         };
-        uint4 ra1[PF == 2 ? NP : 1][PF == 2 ? EA : 1], rb1[PF == 2 ? NP : 1][PF == 2 ? EB : 1];
+        u32x4 ra1[PF == 2 ? NP : 1][PF == 2 ? EA : 1], rb1[PF == 2 ? NP : 1][PF == 2 ? EB : 1];
         const int32_t* ks = ksteps + (phase == 0 ? wi.ks[0] : wi.ks[1]);
         const int nks = phase == 0 ? wi.kn[0] : wi.kn[1];
         k_steps<PF>(
