@@ -38,6 +38,10 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "bf16x3": 2.5e15 / 3, "hbm": 8.0e12}
 
 
+def basis_name(args):
+    return "FP64 at every precision" if args.basis_fp64 else "FP32 below FP64 (start vector in FP64)"
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     with open(os.path.join(ROOT, "paper_0707_0159_amd", "csrc", "kernels_hv.hip"), "rb") as f:
@@ -180,7 +184,7 @@ def bench_batch(args):
 
     def solve(prec):
         opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol, use_graph=1,
-                                reorth_window=args.window)
+                                reorth_window=args.window, basis_fp64=int(args.basis_fp64))
         st, e, per = d2d.d2d_batch_lanczos(b, opts, v0)
         if st != 0:
             raise RuntimeError("batched Lanczos did not converge")
@@ -246,7 +250,7 @@ def bench_batch(args):
                                f"{len(wls)} problems, 6 columns, m 64..512)",
                    "N_sb_total": sum(i["n"] for i in infos), "N_sb_max": max(i["n"] for i in infos),
                    "k_in": args.k_in, "reorth_window": args.window, "tol_res": args.tol,
-                   "parallelism": "none (1 GPU)"},
+                   "inner_basis": basis_name(args), "parallelism": "none (1 GPU)"},
         "time_to_energy": {"mixed_fp32": head, "mixed_bf16": bf16, "mixed_bf16x3": bf16x3, "fp64": fp64,
                            "speedup_fp32_vs_fp64": fp64["s_per_solve"] / head["s_per_solve"],
                            "speedup_bf16_vs_fp64": fp64["s_per_solve"] / bf16["s_per_solve"],
@@ -278,6 +282,8 @@ def main():
     ap.add_argument("--k-in", type=int, default=24)
     ap.add_argument("--window", type=int, default=3, help="reorthogonalisation window (0 = full)")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--basis-fp64", action="store_true",
+                    help="store the inner Krylov basis in FP64 at every precision (default: FP32 below FP64)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", choices=["hv", "copy"], default=None,
@@ -363,7 +369,7 @@ def main():
 
     def solve(prec):
         opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol, use_graph=1,
-                                reorth_window=args.window)
+                                reorth_window=args.window, basis_fp64=int(args.basis_fp64))
         st, e, stats = d2d.d2d_lanczos(sb, opts, v0, psi)
         if st != 0:
             raise RuntimeError(f"Lanczos did not converge: {stats['residual']}")
@@ -457,9 +463,11 @@ def main():
         "config": {"workload": wl.name, "description": wl.description, "N_sb": N,
                    "sector_pairs": info["npairs"], "m": info["m"], "column_dim": info["ncol"],
                    "central_terms": info["nterms"], "k_in": args.k_in, "reorth_window": args.window,
-                   "tol_res": args.tol, "tiles": tuned, "parallelism": "none (1 GPU)"},
-        "precision_schedule": "inner Hv FP32 MFMA (FP32 accumulate); FP64 Lanczos scalars, reorthogonalisation, "
-                              "tridiagonal solve and FP64-Hv residual at every restart",
+                   "tol_res": args.tol, "inner_basis": basis_name(args), "tiles": tuned,
+                   "parallelism": "none (1 GPU)"},
+        "precision_schedule": "inner Hv FP32 MFMA (FP32 accumulate); FP64 Lanczos scalars, reorthogonalisation "
+                              "arithmetic, tridiagonal solve and FP64-Hv residual at every restart; inner basis "
+                              f"stored {basis_name(args)}",
         "time_to_energy": {
             "E_oracle": E0,
             "mixed_fp32": head, "mixed_bf16": bf16, "mixed_bf16x3": bf16x3, "fp64": fp64,

@@ -281,9 +281,12 @@ d2d_status d2d_tile_shapes(int* count, int* desc);
  *   steps with Hv in precision prec_j, reorthogonalisation by classical
  *   Gram-Schmidt twice in FP64 (against all basis vectors, or the last
  *   reorth_window ones), the tridiagonal lowest eigenpair on the device, and
- *   x_{j+1} = Q y.
+ *   x_{j+1} = y_0 x_j + sum_{i>=1} y_i q_i.
  * All recurrences, dot products, the tridiagonal solve and the Ritz vector
- * are FP64 on the device; the host reads (theta_j, rho_j) once per restart.
+ * are FP64 arithmetic on the device; the host reads (theta_j, rho_j) once per
+ * restart.  Below FP64 the basis q_0..q_{k-1} is stored in FP32 (unless
+ * basis_fp64): x_j enters x_{j+1} in FP64, so the storage rounding only
+ * touches the correction sum_{i>=1} y_i q_i, which shrinks with the residual.
  * Precision schedule: start in opts.prec; the precision is raised (BF16 ->
  * BF16X3 when kept -> FP32 -> FP64) after a restart with rho_{j+1} > escalate
  * * rho_j whose shortfall is the low-precision products' doing: theta_{j+1} >
@@ -325,6 +328,9 @@ typedef struct {
                             second Gram-Schmidt pass and the norm follow from the
                             first pass's sums and the window's Gram matrix;
                             1: always two explicit passes (three kernels)     */
+    int basis_fp64;      /* 0: inner basis in FP32 when prec_j is below FP64 (the
+                            FP32 basis vector is the FP32/BF16x3 Hv input);
+                            1: FP64 basis at every precision                  */
 } d2d_lanczos_opts;
 
 #define D2D_LOG_MAX 256

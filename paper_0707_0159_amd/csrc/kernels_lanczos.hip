@@ -365,12 +365,20 @@ struct HvPartPtrs {
     const void* p[4];
 };
 
+// The next Hv's input copy of a basis vector: FP32 (FP32 and BF16x3 products)
+// or BF16 (round to nearest even); lo_prec -1 writes nothing (the product
+// reads the basis vector itself).
+__device__ inline void store_lo(void* __restrict__ lo, int lo_prec, int64_t e, double q) {
+    if (lo_prec == D2D_FP32 || lo_prec == D2D_BF16X3) ((float*)lo)[e] = (float)q;
+    else if (lo_prec == D2D_BF16) ((uint16_t*)lo)[e] = f32_bf16_rne((float)q);
+}
+
 // Step kernel 1: w = (((w + P0) + P1) + P2) + P3 in the Hv's precision (the
 // parts of a split or fused Hv, each nullable), upcast from FP32 when UPCAST,
 // stored as FP64 when it changed; partials of c1 = Q[0..nq)^T w.
-template <int NQ, bool UPCAST>
+template <int NQ, bool UPCAST, typename TQ>
 __global__ void __launch_bounds__(LZ_THREADS)
-k_lz_dots(const LzSeg* __restrict__ bt, const double* __restrict__ Q,
+k_lz_dots(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q,
           int64_t ldq, int nq, const double* w64in, const float* __restrict__ w32, const HvPartPtrs P,
           double* w64out, double* __restrict__ partial, int NB) {
     const bool any = P.p[0] || P.p[1] || P.p[2] || P.p[3];
@@ -387,6 +395,7 @@ k_lz_dots(const LzSeg* __restrict__ bt, const double* __restrict__ Q,
         // loads at an index clamped into the segment, issued together; the
         // lanes past the end are masked afterwards
         double x[U], q[U][NQ];
+        TQ qr[U][NQ];
         TW wv[U], pv[4][U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -396,8 +405,14 @@ k_lz_dots(const LzSeg* __restrict__ bt, const double* __restrict__ Q,
 #pragma unroll
             for (int i = 0; i < 4; ++i) pv[i][u] = P.p[i] ? ((const TW*)P.p[i])[ec] : TW(0);
 #pragma unroll
-            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? Q[j * ldq + ec] : 0.0;
+            for (int j = 0; j < NQ; ++j) qr[u][j] = Q[(j < nq ? j : nq - 1) * ldq + ec];
         }
+        // every window load is issued before any is waited for (rows past nq
+        // re-read row nq-1 and are zeroed here)
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? (double)qr[u][j] : 0.0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const bool ok = e0 + u * st < sg.hi;
@@ -424,9 +439,9 @@ k_lz_dots(const LzSeg* __restrict__ bt, const double* __restrict__ Q,
 
 // Step kernel 2: c1 from partial_in; w <- w - Q c1; partials of c2 = Q^T w
 // (rows 0..nq-1) and |w|^2 (row nq) into partial_out; alpha_i = c1[i].
-template <int NQ>
+template <int NQ, typename TQ>
 __global__ void __launch_bounds__(LZ_THREADS)
-k_lz_update_dots(const LzSeg* __restrict__ bt, const double* __restrict__ Q,
+k_lz_update_dots(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q,
                  int64_t ldq, int nq, const double* __restrict__ partial_in, double* __restrict__ w,
                  double* __restrict__ partial_out, int NB, double* __restrict__ scal, int i) {
     const LzSeg sg = bt[blockIdx.x];
@@ -443,14 +458,21 @@ k_lz_update_dots(const LzSeg* __restrict__ bt, const double* __restrict__ Q,
     const int64_t st = blockDim.x;
     for (int64_t e0 = sg.lo + threadIdx.x; e0 < sg.hi; e0 += U * st) {
         double x[U], q[U][NQ];
+        TQ qr[U][NQ];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t e = e0 + u * st;
             const int64_t ec = e < sg.hi ? e : sg.lo;
             x[u] = w[ec];
 #pragma unroll
-            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? Q[j * ldq + ec] : 0.0;
+            for (int j = 0; j < NQ; ++j) qr[u][j] = Q[(j < nq ? j : nq - 1) * ldq + ec];
         }
+        // every window load is issued before any is waited for (rows past nq
+        // re-read row nq-1 and are zeroed here)
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? (double)qr[u][j] : 0.0;
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (e0 + u * st >= sg.hi) {
@@ -494,11 +516,11 @@ k_lz_update_dots(const LzSeg* __restrict__ bt, const double* __restrict__ Q,
 // Step kernel 3: c2 and |w|^2 from partial_in; beta = sqrt(|w|^2 - |c2|^2);
 // q_next = (w - [need2] Q c2) / beta with need2 = |c2| > 1e-13 |w|;
 // lo = cast(q_next); the problem's first block writes alpha_i += c2[i], beta_{i+1}.
-template <int NQ>
+template <int NQ, typename TQ>
 __global__ void __launch_bounds__(LZ_THREADS)
-k_lz_next(const LzSeg* __restrict__ bt, const double* __restrict__ Q,
+k_lz_next(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q,
           int64_t ldq, int nq, const double* __restrict__ partial_in, int NB, const double* __restrict__ w,
-          double* __restrict__ qnext, void* __restrict__ lo, int lo_prec, double* __restrict__ scal, int i) {
+          TQ* __restrict__ qnext, void* __restrict__ lo, int lo_prec, double* __restrict__ scal, int i) {
     const LzSeg sg = bt[blockIdx.x];
     if (!sg.act) return;
     __shared__ double cs[NQ + 1];
@@ -520,14 +542,21 @@ k_lz_next(const LzSeg* __restrict__ bt, const double* __restrict__ Q,
     for (int64_t e0 = sg.lo + threadIdx.x; e0 < sg.hi; e0 += 4 * st) {
         // loads at an index clamped into the segment, issued together
         double x[4], q[4][NQ];
+        TQ qr[4][NQ];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t e = e0 + u * st;
             const int64_t ec = e < sg.hi ? e : sg.lo;
             x[u] = w[ec];
 #pragma unroll
-            for (int j = 0; j < NQ; ++j) q[u][j] = (corr && j < nq) ? Q[j * ldq + ec] : 0.0;
+            for (int j = 0; j < NQ; ++j) qr[u][j] = Q[(j < nq ? j : nq - 1) * ldq + ec];
         }
+        // every window load is issued before any is waited for (rows past nq
+        // re-read row nq-1 and are zeroed here)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) q[u][j] = (corr && j < nq) ? (double)qr[u][j] : 0.0;
         if (corr)
 #pragma unroll
             for (int j = 0; j < NQ; ++j)
@@ -539,9 +568,8 @@ k_lz_next(const LzSeg* __restrict__ bt, const double* __restrict__ Q,
             const int64_t e = e0 + u * st;
             if (e >= sg.hi) break;
             const double q = x[u] * inv;
-            qnext[e] = q;
-            if (lo_prec == D2D_FP32 || lo_prec == D2D_BF16X3) ((float*)lo)[e] = (float)q;
-            else if (lo_prec == D2D_BF16) ((uint16_t*)lo)[e] = f32_bf16_rne((float)q);
+            qnext[e] = (TQ)q;
+            store_lo(lo, lo_prec, e, q);
         }
     }
 }
@@ -552,6 +580,10 @@ k_lz_next(const LzSeg* __restrict__ bt, const double* __restrict__ Q,
 // read of the window: c2 = c1 - G c1, d = c1 + c2, and
 // |w - Q d|^2 = |w|^2 - 2 d.c1 + d^T G d.  Partial rows (fixed layout):
 // c1 in 0..NQ-1, |w|^2 in NQ, G_jl (j <= l) from NQ+1 on.
+// Elements a thread keeps in flight per round in the Gram kernels: with about
+// 2048 elements per block, a block covers its segment in one round of loads.
+static constexpr int GRAM_U = 8;
+
 template <int NQ>
 struct GramLayout {
     static constexpr int NG = NQ * (NQ + 1) / 2;
@@ -563,13 +595,13 @@ struct GramLayout {
 // precision, stored back in place (in that precision: the FP32 sum is what
 // the second kernel upcasts) when there are parts; partials of c1 = Q^T w,
 // |w|^2 and the window's Gram matrix.
-template <int NQ, bool UPCAST>
+template <int NQ, bool UPCAST, typename TQ>
 __global__ void __launch_bounds__(LZ_THREADS)
-k_lz_dots_gram(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int64_t ldq, int nq,
+k_lz_dots_gram(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q, int64_t ldq, int nq,
                typename std::conditional<UPCAST, float, double>::type* wio, const HvPartPtrs P,
                double* __restrict__ partial, int NB) {
     using GL = GramLayout<NQ>;
-    constexpr int U = StepUnroll<NQ>::U;
+    constexpr int U = GRAM_U;
     const LzSeg sg = bt[blockIdx.x];
     if (!sg.act) return;
     const bool any = P.p[0] || P.p[1] || P.p[2] || P.p[3];
@@ -581,6 +613,7 @@ k_lz_dots_gram(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int64
     const TW* win = wio;
     for (int64_t e0 = sg.lo + threadIdx.x; e0 < sg.hi; e0 += U * st) {
         double x[U], q[U][NQ];
+        TQ qr[U][NQ];
         TW wv[U], pv[4][U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -590,8 +623,14 @@ k_lz_dots_gram(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int64
 #pragma unroll
             for (int i = 0; i < 4; ++i) pv[i][u] = P.p[i] ? ((const TW*)P.p[i])[ec] : TW(0);
 #pragma unroll
-            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? Q[j * ldq + ec] : 0.0;
+            for (int j = 0; j < NQ; ++j) qr[u][j] = Q[(j < nq ? j : nq - 1) * ldq + ec];
         }
+        // every window load is issued before any is waited for (rows past nq
+        // re-read row nq-1 and are zeroed here)
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? (double)qr[u][j] : 0.0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t e = e0 + u * st;
@@ -618,12 +657,12 @@ k_lz_dots_gram(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int64
 
 // Second kernel: d, alpha_i = d[nq-1], beta = |w - Q d| from the sums;
 // q_next = (w - Q d) / beta and its low-precision copy.
-template <int NQ, bool UPCAST>
+template <int NQ, bool UPCAST, typename TQ>
 __global__ void __launch_bounds__(LZ_THREADS)
-k_lz_update_gram(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int64_t ldq, int nq,
+k_lz_update_gram(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q, int64_t ldq, int nq,
                  const double* __restrict__ partial_in, int NB,
                  const typename std::conditional<UPCAST, float, double>::type* __restrict__ w,
-                 double* __restrict__ qnext, void* __restrict__ lo, int lo_prec, double* __restrict__ scal, int i) {
+                 TQ* __restrict__ qnext, void* __restrict__ lo, int lo_prec, double* __restrict__ scal, int i) {
     using GL = GramLayout<NQ>;
     const LzSeg sg = bt[blockIdx.x];
     if (!sg.act) return;
@@ -657,85 +696,104 @@ k_lz_update_gram(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int
         sc[S_BETA + i + 1] = bb;
     }
     if (!qnext) return;
+    constexpr int U = GRAM_U;
     const double inv = bb > 0.0 ? 1.0 / bb : 0.0;
     const int64_t st = blockDim.x;
-    for (int64_t e0 = sg.lo + threadIdx.x; e0 < sg.hi; e0 += 4 * st) {
-        double x[4], q[4][NQ];
+    for (int64_t e0 = sg.lo + threadIdx.x; e0 < sg.hi; e0 += U * st) {
+        double x[U], q[U][NQ];
+        TQ qr[U][NQ];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int64_t e = e0 + u * st;
             const int64_t ec = e < sg.hi ? e : sg.lo;
             x[u] = (double)w[ec];
 #pragma unroll
-            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? Q[j * ldq + ec] : 0.0;
+            for (int j = 0; j < NQ; ++j) qr[u][j] = Q[(j < nq ? j : nq - 1) * ldq + ec];
         }
+        // every window load is issued before any is waited for (rows past nq
+        // re-read row nq-1 and are zeroed here)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? (double)qr[u][j] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
             const int64_t e = e0 + u * st;
             if (e >= sg.hi) break;
 #pragma unroll
             for (int j = 0; j < NQ; ++j) x[u] -= d[j] * q[u][j];
             const double qv = x[u] * inv;
-            qnext[e] = qv;
-            if (lo_prec == D2D_FP32 || lo_prec == D2D_BF16X3) ((float*)lo)[e] = (float)qv;
-            else if (lo_prec == D2D_BF16) ((uint16_t*)lo)[e] = f32_bf16_rne((float)qv);
+            qnext[e] = (TQ)qv;
+            store_lo(lo, lo_prec, e, qv);
         }
     }
 }
 
+template <typename TQ>
 static hipError_t lz_step_gram(const LzStepArgs& a, hipStream_t s) {
     constexpr int NQ = 4;
     const int NB = a.NB;
+    const TQ* Q = (const TQ*)a.Q;
+    TQ* qn = (TQ*)a.qnext;
+    const int lp = a.lo ? a.lo_prec : -1;
     HvPartPtrs P;
     for (int i = 0; i < 4; ++i) P.p[i] = a.wpart[i];
     // the low-precision product's sum stays in its FP32 buffer (the upcast is exact)
     if (a.upcast) {
-        hipLaunchKernelGGL((k_lz_dots_gram<NQ, true>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq,
+        hipLaunchKernelGGL((k_lz_dots_gram<NQ, true, TQ>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, Q, a.ldq, a.nq,
                            (float*)a.w32, P, a.partial, NB);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_lz_update_gram<NQ, true>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq,
-                           a.partial, NB, (const float*)a.w32, a.qnext, a.lo, a.lo ? a.lo_prec : -1, a.scal, a.i);
+        hipLaunchKernelGGL((k_lz_update_gram<NQ, true, TQ>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, Q, a.ldq,
+                           a.nq, a.partial, NB, (const float*)a.w32, qn, a.lo, lp, a.scal, a.i);
     } else {
-        hipLaunchKernelGGL((k_lz_dots_gram<NQ, false>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq,
-                           a.w, P, a.partial, NB);
+        hipLaunchKernelGGL((k_lz_dots_gram<NQ, false, TQ>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, Q, a.ldq,
+                           a.nq, a.w, P, a.partial, NB);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_lz_update_gram<NQ, false>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq,
-                           a.partial, NB, (const double*)a.w, a.qnext, a.lo, a.lo ? a.lo_prec : -1, a.scal, a.i);
+        hipLaunchKernelGGL((k_lz_update_gram<NQ, false, TQ>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, Q, a.ldq,
+                           a.nq, a.partial, NB, (const double*)a.w, qn, a.lo, lp, a.scal, a.i);
     }
     return hipGetLastError();
 }
 
-template <int NQ>
+template <int NQ, typename TQ>
 static hipError_t lz_step_nq(const LzStepArgs& a, hipStream_t s) {
     const int NB = a.NB;
+    const TQ* Q = (const TQ*)a.Q;
     HvPartPtrs P;
     for (int i = 0; i < 4; ++i) P.p[i] = a.wpart[i];
     if (a.upcast)
-        hipLaunchKernelGGL((k_lz_dots<NQ, true>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq,
+        hipLaunchKernelGGL((k_lz_dots<NQ, true, TQ>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, Q, a.ldq, a.nq,
                            (const double*)nullptr, a.w32, P, a.w, a.partial, NB);
     else
-        hipLaunchKernelGGL((k_lz_dots<NQ, false>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq,
+        hipLaunchKernelGGL((k_lz_dots<NQ, false, TQ>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, Q, a.ldq,
                            a.nq, a.w, (const float*)nullptr, P, a.w, a.partial, NB);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_lz_update_dots<NQ>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq,
+    hipLaunchKernelGGL((k_lz_update_dots<NQ, TQ>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, Q, a.ldq, a.nq,
                        a.partial, a.w, a.partial2, NB, a.scal, a.i);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_lz_next<NQ>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, a.Q, a.ldq, a.nq,
-                       a.partial2, NB, a.w, a.qnext, a.lo, a.lo ? a.lo_prec : -1, a.scal, a.i);
+    hipLaunchKernelGGL((k_lz_next<NQ, TQ>), dim3(NB), dim3(LZ_THREADS), 0, s, a.bt, Q, a.ldq, a.nq,
+                       a.partial2, NB, a.w, (TQ*)a.qnext, a.lo, a.lo ? a.lo_prec : -1, a.scal, a.i);
     return hipGetLastError();
 }
 
-hipError_t launch_lz_step(const LzStepArgs& a, hipStream_t s) {
-    if (a.gram && a.nq <= 4) return lz_step_gram(a, s);
-    if (a.nq <= 4) return lz_step_nq<4>(a, s);
-    if (a.nq <= 8) return lz_step_nq<8>(a, s);
-    if (a.nq <= 16) return lz_step_nq<16>(a, s);
-    if (a.nq <= 32) return lz_step_nq<32>(a, s);
+template <typename TQ>
+static hipError_t lz_step(const LzStepArgs& a, hipStream_t s) {
+    if (a.gram && a.nq <= 4) return lz_step_gram<TQ>(a, s);
+    if (a.nq <= 4) return lz_step_nq<4, TQ>(a, s);
+    if (a.nq <= 8) return lz_step_nq<8, TQ>(a, s);
+    if (a.nq <= 16) return lz_step_nq<16, TQ>(a, s);
+    if (a.nq <= 32) return lz_step_nq<32, TQ>(a, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_lz_step(const LzStepArgs& a, hipStream_t s) {
+    // an FP32 basis only with an FP32 product (the FP64 recurrence keeps an FP64 basis)
+    if (a.q32 && !a.upcast) return hipErrorInvalidValue;
+    return a.q32 ? lz_step<float>(a, s) : lz_step<double>(a, s);
 }
 
 // partials of x.w (row 0)
@@ -801,9 +859,12 @@ hipError_t launch_lz_residual(const LzSet& z, const double* x, double* w, hipStr
     return hipGetLastError();
 }
 
-// x = Q y (y of the problem); partials of |x|^2
+// x = y_0 x + sum_{j>=1} y_j Q[j] (y of the problem; Q[0] is x itself, or
+// its FP32 copy in an FP32 basis, so x enters in FP64 either way), in place;
+// partials of |x|^2
+template <typename TQ>
 __global__ void __launch_bounds__(LZ_THREADS)
-k_lz_ritz(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int64_t ldq,
+k_lz_ritz(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q, int64_t ldq,
           int k, const double* __restrict__ scal, double* __restrict__ x, double* __restrict__ partial, int NB) {
     const LzSeg sg = bt[blockIdx.x];
     if (!sg.act) return;
@@ -813,8 +874,8 @@ k_lz_ritz(const LzSeg* __restrict__ bt, const double* __restrict__ Q, int64_t ld
     __syncthreads();
     double acc[1] = {0.0};
     for (int64_t e = sg.lo + threadIdx.x; e < sg.hi; e += blockDim.x) {
-        double v = 0.0;
-        for (int j = 0; j < k; ++j) v += ys[j] * Q[j * ldq + e];
+        double v = ys[0] * x[e];
+        for (int j = 1; j < k; ++j) v += ys[j] * (double)Q[j * ldq + e];
         x[e] = v;
         acc[0] += v * v;
     }
@@ -833,10 +894,14 @@ k_lz_normalize(const LzSeg* __restrict__ bt, const double* __restrict__ partial,
     for (int64_t e = sg.lo + threadIdx.x; e < sg.hi; e += blockDim.x) dst[e] = src[e] * inv;
 }
 
-hipError_t launch_lz_ritz(const LzSet& z, const double* Q, int k, double* x, hipStream_t s) {
+hipError_t launch_lz_ritz(const LzSet& z, const void* Q, bool q32, int k, double* x, hipStream_t s) {
     if (k > 128) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_lz_ritz, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, Q, z.ntot, k, z.scal, x,
-                       z.partial, z.NB);
+    if (q32)
+        hipLaunchKernelGGL(k_lz_ritz<float>, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, (const float*)Q, z.ntot, k,
+                           z.scal, x, z.partial, z.NB);
+    else
+        hipLaunchKernelGGL(k_lz_ritz<double>, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, (const double*)Q, z.ntot,
+                           k, z.scal, x, z.partial, z.NB);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_lz_normalize, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, z.partial, z.NB,
@@ -870,19 +935,22 @@ hipError_t launch_lz_norms(const LzSet& z, const double* v, hipStream_t s) {
     return hipGetLastError();
 }
 
-// q_1 = r / beta_1 of each problem; lo = cast(q_1)
+// Q[0] = x, Q[1] = r / beta_1 of each problem (rounded to the basis type);
+// lo = cast(Q[1])
+template <typename TQ>
 __global__ void __launch_bounds__(LZ_THREADS)
-k_lz_first(const LzSeg* __restrict__ bt, const double* __restrict__ w,
-           const double* __restrict__ scal, double* __restrict__ q1, void* __restrict__ lo, int lo_prec) {
+k_lz_first(const LzSeg* __restrict__ bt, const double* __restrict__ x, const double* __restrict__ w,
+           const double* __restrict__ scal, TQ* __restrict__ q0, TQ* __restrict__ q1, void* __restrict__ lo,
+           int lo_prec) {
     const LzSeg sg = bt[blockIdx.x];
     if (!sg.act) return;
     const double b = scal[(int64_t)sg.prob * S_LEN + S_BETA + 1];
     const double inv = b > 0.0 ? 1.0 / b : 0.0;
     for (int64_t e = sg.lo + threadIdx.x; e < sg.hi; e += blockDim.x) {
         const double q = w[e] * inv;
-        q1[e] = q;
-        if (lo_prec == D2D_FP32 || lo_prec == D2D_BF16X3) ((float*)lo)[e] = (float)q;
-        else if (lo_prec == D2D_BF16) ((uint16_t*)lo)[e] = f32_bf16_rne((float)q);
+        q0[e] = (TQ)x[e];
+        q1[e] = (TQ)q;
+        store_lo(lo, lo_prec, e, q);
     }
 }
 
@@ -912,22 +980,14 @@ hipError_t launch_seeded_normal(double* x, int64_t n, uint64_t seed, hipStream_t
     return hipGetLastError();
 }
 
-// copy of the active problems' segments
-__global__ void __launch_bounds__(LZ_THREADS)
-k_lz_copy(const LzSeg* __restrict__ bt, const double* __restrict__ x,
-          double* __restrict__ y) {
-    const LzSeg sg = bt[blockIdx.x];
-    if (!sg.act) return;
-    for (int64_t e = sg.lo + threadIdx.x; e < sg.hi; e += blockDim.x) y[e] = x[e];
-}
-
-hipError_t launch_lz_first(const LzSet& z, const double* x, const double* w, double* Q, void* lo, int lo_prec,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(k_lz_copy, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, x, Q);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lz_first, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, w, z.scal, Q + z.ntot, lo,
-                       lo ? lo_prec : -1);
+hipError_t launch_lz_first(const LzSet& z, const double* x, const double* w, void* Q, bool q32, void* lo,
+                           int lo_prec, hipStream_t s) {
+    if (q32)
+        hipLaunchKernelGGL(k_lz_first<float>, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, x, w, z.scal, (float*)Q,
+                           (float*)Q + z.ntot, lo, lo ? lo_prec : -1);
+    else
+        hipLaunchKernelGGL(k_lz_first<double>, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, x, w, z.scal, (double*)Q,
+                           (double*)Q + z.ntot, lo, lo ? lo_prec : -1);
     return hipGetLastError();
 }
 

@@ -7,9 +7,10 @@
 // Inner:      Lanczos started from x_j: q_0 = x_j, alpha_0 = theta_j,
 //             beta_1 = rho_j, q_1 = r / rho_j (all FP64-exact), then k-1
 //             steps with Hv in the working precision (FP64 / FP32 / BF16
-//             inputs, FP32 accumulation), full reorthogonalisation by
-//             classical Gram-Schmidt twice in FP64, the lowest eigenpair of the
-//             k x k tridiagonal on the device, x_{j+1} = Q y / |Q y|.
+//             inputs, FP32 accumulation), reorthogonalisation by classical
+//             Gram-Schmidt twice in FP64, the lowest eigenpair of the k x k
+//             tridiagonal on the device, x_{j+1} = Q y / |Q y| with q_0 = x_j
+//             taken in FP64 (the basis is stored in FP32 below FP64).
 // The fixed point is an eigenvector of the FP64 operator because the residual
 // that drives every restart is computed with the FP64 Hv.
 //
@@ -155,17 +156,24 @@ d2d_status residual_step(LanczosWork* w, HvOps& hv, hipStream_t s) {
 }
 
 // One inner Lanczos of k vectors from X (after residual_step); X <- Ritz vector.
+// Below FP64 the basis is stored in FP32 unless basis64: X enters the Ritz
+// vector in FP64, so the rounding of the basis only touches the correction
+// sum_{j>=1} y_j q_j, which shrinks with the residual.  An FP32 basis vector
+// is the FP32 and BF16x3 products' input itself; BF16 reads its own copy.
 d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool fused, bool plain_cgs2,
-                      hipStream_t s) {
+                      bool basis64, hipStream_t s) {
     const LzSet z = set_of(w);
     const int64_t N = w->ntot;
-    void* lo = prec == D2D_FP64 ? nullptr : (void*)w->vlo;
-    D2D_HIP(launch_lz_first(z, w->X, w->W, w->Q, lo, prec, s));
+    const bool q32 = prec != D2D_FP64 && !basis64;
+    const size_t qs = q32 ? 4 : 8;
+    char* Q = (char*)w->Q;
+    void* lo = prec == D2D_FP64 || (q32 && prec != D2D_BF16) ? nullptr : (void*)w->vlo;
+    D2D_HIP(launch_lz_first(z, w->X, w->W, Q, q32, lo, prec, s));
     for (int i = 1; i < k; ++i) {
-        double* qi = w->Q + (int64_t)i * N;
+        const void* qi = Q + (size_t)i * N * qs;
         // fused GEMM + central launch; the step's first kernel adds the parts
         HvParts parts{};
-        const void* hin = prec == D2D_FP64 ? (const void*)qi : (const void*)w->vlo;
+        const void* hin = lo ? (const void*)lo : qi;
         void* hout = prec == D2D_FP64 ? (void*)w->W : (void*)w->wlo;
         if (fused) D2D_CHECK(hv.hv_fused(prec, hin, hout, s, &parts));
         else D2D_CHECK(hv.hv(prec, hin, hout, s));
@@ -173,7 +181,8 @@ d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bo
         a.bt = z.bt;
         // projection against q_{i-nq+1} .. q_i (all of them for full reorthogonalisation)
         const int nq = window >= 2 ? std::min(i + 1, window) : i + 1;
-        a.Q = w->Q + (int64_t)(i + 1 - nq) * N;
+        a.Q = Q + (size_t)(i + 1 - nq) * N * qs;
+        a.q32 = q32;
         a.ldq = N;
         a.nq = nq;
         a.i = i;
@@ -187,13 +196,13 @@ d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bo
         a.partial2 = z.partial2;
         a.NB = z.NB;
         a.scal = z.scal;
-        a.qnext = i + 1 < k ? w->Q + (int64_t)(i + 1) * N : nullptr;
+        a.qnext = i + 1 < k ? (void*)(Q + (size_t)(i + 1) * N * qs) : nullptr;
         a.lo = lo;
         a.lo_prec = prec;
         D2D_HIP(launch_lz_step(a, s));
     }
     D2D_HIP(launch_lz_tridiag(z, k, s));
-    D2D_HIP(launch_lz_ritz(z, w->Q, k, w->X, s));
+    D2D_HIP(launch_lz_ritz(z, Q, q32, k, w->X, s));
     return D2D_OK;
 }
 
@@ -207,9 +216,9 @@ void drop_graphs(LanczosWork* w) {
 }
 
 d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool fused, bool plain_cgs2,
-                   bool use_graph, hipStream_t s) {
+                   bool basis64, bool use_graph, hipStream_t s) {
     if (!use_graph || s == nullptr) {
-        D2D_CHECK(inner_loop(w, hv, prec, k, window, fused, plain_cgs2, s));
+        D2D_CHECK(inner_loop(w, hv, prec, k, window, fused, plain_cgs2, basis64, s));
         D2D_CHECK(residual_step(w, hv, s));
         hv.count(prec, k - 1);
         hv.count(D2D_FP64, 1);
@@ -223,7 +232,7 @@ d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool 
         D2D_CHECK(hv.prepare(prec));          // launch tables exist before capture
         D2D_CHECK(hv.prepare(D2D_FP64));
         D2D_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        d2d_status st = inner_loop(w, hv, prec, k, window, fused, plain_cgs2, s);
+        d2d_status st = inner_loop(w, hv, prec, k, window, fused, plain_cgs2, basis64, s);
         if (st == D2D_OK) st = residual_step(w, hv, s);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s, &g);
@@ -252,9 +261,10 @@ namespace d2d {
 d2d_status check_lanczos_opts(const d2d_lanczos_opts* o) {
     if (!o || o->k_in < 2 || o->k_in > 33 || o->max_restarts < 0 || !(o->tol_res > 0.0) || o->prec < 0 ||
         o->prec >= D2D_NPREC || o->reorth_window < 0 || o->reorth_window == 1 || o->separate_central < 0 ||
-        o->separate_central > 1 || !(o->tol_rel_e >= 0.0) || o->plain_cgs2 < 0 || o->plain_cgs2 > 1) {
+        o->separate_central > 1 || !(o->tol_rel_e >= 0.0) || o->plain_cgs2 < 0 || o->plain_cgs2 > 1 ||
+        o->basis_fp64 < 0 || o->basis_fp64 > 1) {
         set_error("Lanczos options: k_in 2..33, max_restarts >= 0, tol_res > 0, prec 0..3, reorth_window 0 or >= 2, "
-                  "separate_central 0 or 1, tol_rel_e >= 0, plain_cgs2 0 or 1");
+                  "separate_central 0 or 1, tol_rel_e >= 0, plain_cgs2 0 or 1, basis_fp64 0 or 1");
         return D2D_EINVAL;
     }
     return D2D_OK;
@@ -389,7 +399,7 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
             if (rebuilt) drop_graphs(w);
         }
         D2D_CHECK(restart(w, hv, prec, k, opts->reorth_window, opts->separate_central == 0, opts->plain_cgs2 != 0,
-                          opts->use_graph != 0, s));
+                          opts->basis_fp64 != 0, opts->use_graph != 0, s));
         for (int p = 0; p < np; ++p)
             if (a[p]) {
                 hvc[p][prec] += k - 1;

@@ -20,7 +20,7 @@ def ctx():
     d2d.d2d_ctx_destroy(c)
 
 
-def run(ctx, prob, prec, seed, k_in=24, graph=1, tol=1e-9, window=0, separate=0, plain=0):
+def run(ctx, prob, prec, seed, k_in=24, graph=1, tol=1e-9, window=0, separate=0, plain=0, basis64=0):
     from paper_0707_0159_amd import d2d
     n = prob.info["n"]
     with torch.cuda.stream(ctx.stream):
@@ -28,7 +28,8 @@ def run(ctx, prob, prec, seed, k_in=24, graph=1, tol=1e-9, window=0, separate=0,
         psi = torch.zeros_like(v0)
     ctx.stream.synchronize()
     opts = d2d.lanczos_opts(prec=prec, k_in=k_in, max_restarts=300, tol_res=tol, use_graph=graph,
-                            reorth_window=window, separate_central=separate, plain_cgs2=plain)
+                            reorth_window=window, separate_central=separate, plain_cgs2=plain,
+                            basis_fp64=basis64)
     st, e, stats = d2d.d2d_lanczos(prob.sb, opts, v0, psi)
     ctx.stream.synchronize()
     return st, e, stats, psi.cpu().numpy()
@@ -65,6 +66,38 @@ def test_config2_energy(ctx, prec, window, plain):
     assert st == 0
     assert abs(e - E0) <= 1e-10 * abs(E0)
     assert e >= E0 - 1e-10 * abs(E0)          # Rayleigh quotient is variational
+    prob.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2, 3])
+@pytest.mark.parametrize("window", [0, 3])
+def test_basis_storage_fp32_and_fp64(ctx, prec, window):
+    """The inner basis in FP32 (the default below FP64) and in FP64 both reach
+    the oracle's energy, and the FP32 basis's Ritz vector is an eigenvector of
+    the oracle's operator to the residual bar: the start vector enters the
+    Ritz vector in FP64, so the storage rounding only touches the correction."""
+    wl = W.CONFIGS[1]
+    prob = GpuProblem(ctx, wl, prec_mask=15)
+    E0 = reference_energy(wl.name)
+    osb = oracle_superblock(wl)
+    for basis64 in (0, 1):
+        st, e, stats, psi = run(ctx, prob, prec, wl.seed, window=window, basis64=basis64)
+        print("basis", prec, window, basis64, e, E0, stats["restarts"], stats["hv_count"])
+        assert st == 0
+        assert abs(e - E0) <= 1e-10 * abs(E0)
+        r = osb.hv_explicit(psi) - e * psi
+        assert np.linalg.norm(r) <= 1e-8 * abs(E0)
+    prob.close()
+
+
+def test_fp64_solve_ignores_basis_option(ctx):
+    """At FP64 the basis is FP64 whatever basis_fp64 says: identical iterates."""
+    wl = W.CONFIGS[1]
+    prob = GpuProblem(ctx, wl)
+    (s0, e0, st0, p0), (s1, e1, st1, p1) = [run(ctx, prob, 0, wl.seed, window=3, basis64=b) for b in (0, 1)]
+    assert s0 == 0 and s1 == 0 and e0 == e1
+    assert np.array_equal(np.asarray(st0["log_theta"]), np.asarray(st1["log_theta"]))
+    assert np.array_equal(p0, p1)
     prob.close()
 
 
@@ -158,10 +191,11 @@ def test_no_escalation_when_the_krylov_space_is_slow(ctx):
 
 
 def test_escalation_from_bf16_on_a_rising_energy(ctx):
-    """A 12-site ladder (dimension 924) in BF16: a restart's Ritz vector has a
-    higher FP64 Rayleigh quotient than its start, which only the BF16 error
-    can cause, so the precision moves on to BF16x3; the energy still meets
-    the bar."""
+    """A 12-site ladder (dimension 924) in BF16 with an FP64 inner basis: a
+    restart's Ritz vector has a higher FP64 Rayleigh quotient than its start,
+    which only the BF16 error can cause, so the precision moves on to BF16x3;
+    the energy still meets the bar.  (With the default FP32 basis this seed's
+    BF16 restarts happen not to rise, and the solve stays in BF16.)"""
     from paper_0707_0159_amd import d2d
     wl = W.config5()[15]
     prob = GpuProblem(ctx, wl, prec_mask=15)
@@ -169,7 +203,7 @@ def test_escalation_from_bf16_on_a_rising_energy(ctx):
     with torch.cuda.stream(ctx.stream):
         v0 = torch.as_tensor(W.random_vector(prob.info["n"], wl.seed)).to("cuda")
     ctx.stream.synchronize()
-    opts = d2d.lanczos_opts(prec=2, k_in=24, max_restarts=300, tol_res=1e-8, reorth_window=3)
+    opts = d2d.lanczos_opts(prec=2, k_in=24, max_restarts=300, tol_res=1e-8, reorth_window=3, basis_fp64=1)
     st, e, stats = d2d.d2d_lanczos(prob.sb, opts, v0)
     E0 = reference_energy(wl.name)
     seen = list(dict.fromkeys(stats["log_prec"]))
