@@ -42,6 +42,38 @@ def basis_name(args):
     return "FP64 at every precision" if args.basis_fp64 else "FP32 below FP64 (start vector in FP64)"
 
 
+PREC_NAMES = ("fp64", "fp32", "bf16", "bf16x3")
+
+
+def solve_time_bound(stats: dict, n: int, k_in: int, window: int, basis_fp64: bool, hv_flops: dict,
+                     hv_bytes: dict) -> dict:
+    """Time-to-energy roofline of one solve: every Hv at max(flops / MFMA peak,
+    minimum bytes / HBM peak) of its precision, plus the Lanczos vector
+    kernels' algorithmic bytes at HBM peak.  Per inner step with window w and
+    basis bytes bq (8 at FP64 or with an FP64 basis, else 4), product bytes
+    bw (8 at FP64, else 4): the two step kernels read the product twice and
+    the window twice and write the next basis vector (BF16 also its 2-byte
+    copy): N (2 bw + 2 w bq + bq [+ 2]).  Per restart (FP64 residual, Ritz
+    vector, normalisation, first basis vectors): N (88 + (k_in + 1) bq)."""
+    hv = stats["hv_count"]
+    restarts = stats["restarts"]
+    nq = window if window >= 2 else (k_in + 1) / 2.0
+    t_hv = t_step = 0.0
+    for p, name in enumerate(PREC_NAMES):
+        cnt = hv[p]
+        if cnt == 0:
+            continue
+        t_hv += cnt * max(hv_flops[name] / PEAK[name], hv_bytes[name] / PEAK["hbm"])
+        steps = cnt - (restarts + 1) if p == 0 else cnt     # FP64 counts include the residual products
+        bq = 8 if (p == 0 or basis_fp64) else 4
+        bw = 8 if p == 0 else 4
+        t_step += max(steps, 0) * n * (2 * bw + 2 * nq * bq + bq + (2 if name == "bf16" else 0)) / PEAK["hbm"]
+    bq_main = 8 if (basis_fp64 or sum(hv[1:]) == 0) else 4
+    t_restart = (restarts + 1) * n * (88 + (k_in + 1) * bq_main) / PEAK["hbm"]
+    t_min = t_hv + t_step + t_restart
+    return {"t_min_ms": t_min * 1e3, "hv_ms": t_hv * 1e3, "lanczos_vectors_ms": (t_step + t_restart) * 1e3}
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     with open(os.path.join(ROOT, "paper_0707_0159_amd", "csrc", "kernels_hv.hip"), "rb") as f:
@@ -184,7 +216,8 @@ def bench_batch(args):
 
     def solve(prec):
         opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol, use_graph=1,
-                                reorth_window=args.window, basis_fp64=int(args.basis_fp64))
+                                reorth_window=args.window, basis_fp64=int(args.basis_fp64),
+                                k_in_bf16=args.k_in_bf16)
         st, e, per = d2d.d2d_batch_lanczos(b, opts, v0)
         if st != 0:
             raise RuntimeError("batched Lanczos did not converge")
@@ -249,7 +282,8 @@ def bench_batch(args):
         "config": {"workload": f"batch of {len(wls)} uneven superblocks (2/3-leg Heisenberg and Hubbard, "
                                f"{len(wls)} problems, 6 columns, m 64..512)",
                    "N_sb_total": sum(i["n"] for i in infos), "N_sb_max": max(i["n"] for i in infos),
-                   "k_in": args.k_in, "reorth_window": args.window, "tol_res": args.tol,
+                   "k_in": args.k_in, "k_in_bf16": args.k_in_bf16, "reorth_window": args.window,
+                   "tol_res": args.tol,
                    "inner_basis": basis_name(args), "parallelism": "none (1 GPU)"},
         "time_to_energy": {"mixed_fp32": head, "mixed_bf16": bf16, "mixed_bf16x3": bf16x3, "fp64": fp64,
                            "speedup_fp32_vs_fp64": fp64["s_per_solve"] / head["s_per_solve"],
@@ -279,7 +313,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--k-in", type=int, default=24)
+    ap.add_argument("--k-in", type=int, default=48, help="Krylov dimension per restart")
+    ap.add_argument("--k-in-bf16", type=int, default=24, help="Krylov dimension of BF16 cycles (0: --k-in)")
     ap.add_argument("--window", type=int, default=3, help="reorthogonalisation window (0 = full)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--basis-fp64", action="store_true",
@@ -369,7 +404,8 @@ def main():
 
     def solve(prec):
         opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol, use_graph=1,
-                                reorth_window=args.window, basis_fp64=int(args.basis_fp64))
+                                reorth_window=args.window, basis_fp64=int(args.basis_fp64),
+                                k_in_bf16=args.k_in_bf16)
         st, e, stats = d2d.d2d_lanczos(sb, opts, v0, psi)
         if st != 0:
             raise RuntimeError(f"Lanczos did not converge: {stats['residual']}")
@@ -396,10 +432,15 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         e, st = last
+        k_path = args.k_in_bf16 if prec == d2d.D2D_BF16 and args.k_in_bf16 > 0 else args.k_in
+        bound = solve_time_bound(st, N, k_path, args.window, args.basis_fp64,
+                                 {k: v["gemm_flops"] for k, v in tuned.items()},
+                                 {k: info["bytes_min_" + k] for k in tuned})
+        bound["frac"] = bound["t_min_ms"] * 1e-3 / (wall / steps)
         return {"hv_per_s": hv / wall, "s_per_solve": wall / steps, "E": e,
                 "dE_rel": None if E0 is None else abs(e - E0) / abs(E0),
                 "first_within_1e-10_s": first_within(st), "restarts": st["restarts"],
-                "hv_count": st["hv_count"], "precision_log": st["log_prec"]}
+                "hv_count": st["hv_count"], "precision_log": st["log_prec"], "time_roofline": bound}
 
     # ---------------------------------------------------------------- timed: headline mixed path (FP32 MFMA)
     head = timed(d2d.D2D_FP32, args.steps, args.warmup)
@@ -462,7 +503,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "description": wl.description, "N_sb": N,
                    "sector_pairs": info["npairs"], "m": info["m"], "column_dim": info["ncol"],
-                   "central_terms": info["nterms"], "k_in": args.k_in, "reorth_window": args.window,
+                   "central_terms": info["nterms"], "k_in": args.k_in, "k_in_bf16": args.k_in_bf16,
+                   "reorth_window": args.window,
                    "tol_res": args.tol, "inner_basis": basis_name(args), "tiles": tuned,
                    "parallelism": "none (1 GPU)"},
         "precision_schedule": "inner Hv FP32 MFMA (FP32 accumulate); FP64 Lanczos scalars, reorthogonalisation "

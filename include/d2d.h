@@ -296,8 +296,8 @@ d2d_status d2d_tile_shapes(int* count, int* desc);
  * the precision.  In a batch, a problem that meets the condition waits
  * while the others go on converging at the current precision; when none is
  * left, the waiting problems continue one precision higher (for one
- * superblock this is plain escalation).  k_in is capped at the problem
- * dimension.
+ * superblock this is plain escalation).  k_in (k_in_bf16 for BF16 cycles)
+ * is capped at the smallest problem dimension.
  * Convergence: rho_j <= tol_res * |theta_j|, or, when tol_rel_e > 0, two
  * successive FP64 Rayleigh quotients with |theta_j - theta_{j-1}| <=
  * tol_rel_e * |theta_j|.
@@ -311,13 +311,14 @@ d2d_status d2d_tile_shapes(int* count, int* desc);
  * max_restarts is reached. */
 typedef struct {
     int prec;            /* Hv precision of the inner steps                    */
-    int k_in;            /* Krylov dimension per restart (2..33)               */
+    int k_in;            /* Krylov dimension per restart (2..128; 2..32 with
+                            full reorthogonalisation)                         */
     int max_restarts;
     double tol_res;      /* relative residual |r|/|theta|                      */
     double escalate;     /* precision raise threshold on rho_{j+1}/rho_j        */
     int use_graph;       /* capture the inner loop in a hipGraph and replay it */
     int reorth_window;   /* 0: reorthogonalise against every basis vector (full);
-                            w >= 2: only against the last w vectors (the FP64
+                            w in 2..32: only against the last w vectors (the FP64
                             restarts keep the fixed point exact either way)   */
     int separate_central; /* 0: inner-step Hv is one launch where the tile choice
                             says so (D2D_TILE_FUSED); 1: the central term always
@@ -331,6 +332,10 @@ typedef struct {
     int basis_fp64;      /* 0: inner basis in FP32 when prec_j is below FP64 (the
                             FP32 basis vector is the FP32/BF16x3 Hv input);
                             1: FP64 basis at every precision                  */
+    int k_in_bf16;       /* Krylov dimension of BF16 inner cycles (0: k_in);
+                            limits as k_in.  A BF16 cycle gains little past
+                            the point where the BF16 products' error stops
+                            it, so it may be shorter than the others        */
 } d2d_lanczos_opts;
 
 #define D2D_LOG_MAX 256

@@ -259,11 +259,18 @@ d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool 
 namespace d2d {
 
 d2d_status check_lanczos_opts(const d2d_lanczos_opts* o) {
-    if (!o || o->k_in < 2 || o->k_in > 33 || o->max_restarts < 0 || !(o->tol_res > 0.0) || o->prec < 0 ||
-        o->prec >= D2D_NPREC || o->reorth_window < 0 || o->reorth_window == 1 || o->separate_central < 0 ||
+    // the tridiagonal solve and the scalar layout take k <= 128; a projection
+    // covers at most 32 basis vectors (full reorthogonalisation: k <= 32)
+    const int kb = o ? (o->k_in_bf16 > 0 ? o->k_in_bf16 : o->k_in) : 0;
+    if (!o || o->k_in < 2 || o->k_in > 128 || (o->reorth_window == 0 && o->k_in > 32) || o->k_in_bf16 < 0 ||
+        kb < 2 || kb > 128 || (o->reorth_window == 0 && kb > 32) || o->max_restarts < 0 ||
+        !(o->tol_res > 0.0) || o->prec < 0 || o->prec >= D2D_NPREC || o->reorth_window < 0 ||
+        o->reorth_window == 1 || o->reorth_window > 32 || o->separate_central < 0 ||
         o->separate_central > 1 || !(o->tol_rel_e >= 0.0) || o->plain_cgs2 < 0 || o->plain_cgs2 > 1 ||
         o->basis_fp64 < 0 || o->basis_fp64 > 1) {
-        set_error("Lanczos options: k_in 2..33, max_restarts >= 0, tol_res > 0, prec 0..3, reorth_window 0 or >= 2, "
+        set_error("Lanczos options: k_in and k_in_bf16 (0 or) 2..128 (2..32 with full reorthogonalisation), "
+                  "max_restarts >= 0, "
+                  "tol_res > 0, prec 0..3, reorth_window 0 or 2..32, "
                   "separate_central 0 or 1, tol_rel_e >= 0, plain_cgs2 0 or 1, basis_fp64 0 or 1");
         return D2D_EINVAL;
     }
@@ -278,9 +285,14 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
     const int np = (int)len.size();
     int64_t nmin = len[0];
     for (int64_t n : len) nmin = std::min(nmin, n);
-    // Krylov size: at most the smallest problem's dimension (an exhausted space needs no more)
-    const int k = (int)std::min<int64_t>(opts->k_in, std::max<int64_t>(nmin, 2));
-    D2D_CHECK(ensure_lanczos_work(ctx, lw, len, std::max(k, 2)));
+    // Krylov size per precision (BF16 cycles may be shorter), at most the
+    // smallest problem's dimension (an exhausted space needs no more)
+    auto k_of = [&](int prec) {
+        const int kk = prec == D2D_BF16 && opts->k_in_bf16 > 0 ? opts->k_in_bf16 : opts->k_in;
+        return (int)std::min<int64_t>(kk, std::max<int64_t>(nmin, 2));
+    };
+    const int kmax = std::max(k_of(D2D_BF16), k_of(D2D_FP64));
+    D2D_CHECK(ensure_lanczos_work(ctx, lw, len, kmax));
     LanczosWork* w = lw;
     drop_graphs(w);
     const LzSet z = set_of(w);
@@ -353,7 +365,7 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
             }
             const bool e_stop = opts->tol_rel_e > 0.0 && have_prev[p] &&
                                 std::fabs(theta[p] - theta_prev[p]) <= opts->tol_rel_e * std::fabs(theta[p]);
-            if (rho[p] <= opts->tol_res * std::fabs(theta[p]) || rho[p] == 0.0 || k < 2 || e_stop) {
+            if (rho[p] <= opts->tol_res * std::fabs(theta[p]) || rho[p] == 0.0 || e_stop) {
                 done[p] = 1;
                 changed = true;
                 sp.seconds = tsec;
@@ -398,6 +410,7 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
             D2D_CHECK(hv.set_active(a, &rebuilt));
             if (rebuilt) drop_graphs(w);
         }
+        const int k = k_of(prec);
         D2D_CHECK(restart(w, hv, prec, k, opts->reorth_window, opts->separate_central == 0, opts->plain_cgs2 != 0,
                           opts->basis_fp64 != 0, opts->use_graph != 0, s));
         for (int p = 0; p < np; ++p)

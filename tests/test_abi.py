@@ -55,12 +55,31 @@ def test_splitmix64_known_answers():
     assert abs(z.mean()) < 0.01 and abs(z.std() - 1.0) < 0.01
 
 
-def test_lanczos_opts_layout():
-    """The binding's options struct has the C layout (offsets of the tail fields)."""
+def test_lanczos_opts_layout(tmp_path):
+    """The binding's options and stats structs have the layout a C compiler
+    gives the header's: every field offset and the size, printed by a small C
+    program built with gcc against include/d2d.h."""
     import ctypes as C
+    import shutil
+    import subprocess
     from paper_0707_0159_amd import d2d
-    o = d2d.d2d_lanczos_opts
-    assert o.tol_res.offset == 16 and o.escalate.offset == 24
-    assert o.separate_central.offset == 40 and o.tol_rel_e.offset == 48 and o.seed.offset == 56
-    assert o.plain_cgs2.offset == 64
-    assert C.sizeof(o) == 72
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"d2d_lanczos_opts": d2d.d2d_lanczos_opts, "d2d_lanczos_stats": d2d.d2d_lanczos_stats}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "d2d.h"', "int main(void) {"]
+    for name, py in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for name, py in structs.items():
+        assert got[(name, "size")] == C.sizeof(py), name
+        for f, _ in py._fields_:
+            assert got[(name, f)] == getattr(py, f).offset, (name, f)

@@ -90,6 +90,48 @@ def test_basis_storage_fp32_and_fp64(ctx, prec, window):
     prob.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_krylov_size_limits(ctx, prec):
+    """With a window, k_in runs up to 128 (here 64, window 3); full
+    reorthogonalisation projects on at most 32 basis vectors, so it takes k_in
+    up to 32.  k_in 33 with it, k_in 129, and a window of 33 are refused before
+    any launch."""
+    from paper_0707_0159_amd import d2d
+    wl = W.CONFIGS[2]
+    prob = GpuProblem(ctx, wl)
+    E0 = reference_energy(wl.name)
+    for k, win in ((64, 3), (32, 0)):
+        st, e, stats, _ = run(ctx, prob, prec, wl.seed, k_in=k, window=win, tol=1e-8)
+        print("k_in", prec, k, win, e, stats["restarts"], stats["hv_count"])
+        assert st == 0 and abs(e - E0) <= 1e-10 * abs(E0)
+    for k, win in ((33, 0), (129, 3), (24, 33)):
+        with pytest.raises(d2d.D2DError, match="k_in"):
+            run(ctx, prob, prec, wl.seed, k_in=k, window=win)
+    prob.close()
+
+
+def test_bf16_cycles_use_their_own_krylov_size(ctx):
+    """k_in_bf16 sets the length of the BF16 cycles only: every BF16 restart
+    adds k_in_bf16 - 1 products, any other precision k_in - 1, and the solve
+    reaches the oracle's energy."""
+    from paper_0707_0159_amd import d2d
+    wl = W.CONFIGS[2]
+    prob = GpuProblem(ctx, wl, prec_mask=15)
+    with torch.cuda.stream(ctx.stream):
+        v0 = torch.as_tensor(W.random_vector(prob.info["n"], wl.seed)).to("cuda")
+    ctx.stream.synchronize()
+    opts = d2d.lanczos_opts(prec=2, k_in=48, k_in_bf16=16, max_restarts=300, tol_res=1e-8, reorth_window=3)
+    st, e, stats = d2d.d2d_lanczos(prob.sb, opts, v0)
+    E0 = reference_energy(wl.name)
+    hv = stats["hv_count"]
+    print("k_in_bf16", e, stats["restarts"], hv, stats["log_prec"])
+    assert st == 0 and abs(e - E0) <= 1e-10 * abs(E0)
+    assert hv[2] > 0 and hv[2] % 15 == 0 and hv[1] % 47 == 0 and hv[3] % 47 == 0
+    assert hv[2] // 15 + hv[1] // 47 + hv[3] // 47 == stats["restarts"]
+    assert hv[0] == stats["restarts"] + 1
+    prob.close()
+
+
 def test_fp64_solve_ignores_basis_option(ctx):
     """At FP64 the basis is FP64 whatever basis_fp64 says: identical iterates."""
     wl = W.CONFIGS[1]
