@@ -336,6 +336,10 @@ typedef struct {
                             limits as k_in.  A BF16 cycle gains little past
                             the point where the BF16 products' error stops
                             it, so it may be shorter than the others        */
+    int fixed_cycles;    /* 0: a cycle stops early when the problems' previous
+                            cycle reduced the residual at a rate that meets
+                            tol_res in fewer steps (1.25 x those steps + 4);
+                            1: every cycle has k_in (k_in_bf16) vectors     */
 } d2d_lanczos_opts;
 
 #define D2D_LOG_MAX 256

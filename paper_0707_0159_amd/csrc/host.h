@@ -100,9 +100,11 @@ struct LanczosWork {
     std::vector<d2d::LzSeg> h_bt;   // host copy (its act flags follow the active set)
     int2* prange = nullptr;
     int* active = nullptr;
-    hipGraphExec_t exec[D2D_NPREC] = {nullptr, nullptr, nullptr, nullptr};
-    hipGraph_t graph[D2D_NPREC] = {nullptr, nullptr, nullptr, nullptr};
-    int graph_k[D2D_NPREC] = {0, 0, 0, 0};
+    // captured restarts, two per precision: index 2 prec + 0 for the full
+    // cycle, 2 prec + 1 for a shortened one; graph_k is the cycle length
+    hipGraphExec_t exec[2 * D2D_NPREC] = {};
+    hipGraph_t graph[2 * D2D_NPREC] = {};
+    int graph_k[2 * D2D_NPREC] = {};
 };
 
 namespace d2d {

@@ -34,7 +34,7 @@ namespace d2d {
 
 void free_lanczos_work(d2d_ctx* c, LanczosWork*& lw) {
     if (!lw) return;
-    for (int p = 0; p < D2D_NPREC; ++p) {
+    for (int p = 0; p < 2 * D2D_NPREC; ++p) {
         if (lw->exec[p]) (void)hipGraphExecDestroy(lw->exec[p]);
         if (lw->graph[p]) (void)hipGraphDestroy(lw->graph[p]);
     }
@@ -207,7 +207,7 @@ d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bo
 }
 
 void drop_graphs(LanczosWork* w) {
-    for (int p = 0; p < D2D_NPREC; ++p) {
+    for (int p = 0; p < 2 * D2D_NPREC; ++p) {
         if (w->exec[p]) (void)hipGraphExecDestroy(w->exec[p]);
         if (w->graph[p]) (void)hipGraphDestroy(w->graph[p]);
         w->exec[p] = nullptr;
@@ -215,8 +215,8 @@ void drop_graphs(LanczosWork* w) {
     }
 }
 
-d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool fused, bool plain_cgs2,
-                   bool basis64, bool use_graph, hipStream_t s) {
+d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, bool full, int window, bool fused,
+                   bool plain_cgs2, bool basis64, bool use_graph, hipStream_t s) {
     if (!use_graph || s == nullptr) {
         D2D_CHECK(inner_loop(w, hv, prec, k, window, fused, plain_cgs2, basis64, s));
         D2D_CHECK(residual_step(w, hv, s));
@@ -224,31 +224,32 @@ d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool 
         hv.count(D2D_FP64, 1);
         return D2D_OK;
     }
-    if (!w->exec[prec] || w->graph_k[prec] != k) {
-        if (w->exec[prec]) (void)hipGraphExecDestroy(w->exec[prec]);
-        if (w->graph[prec]) (void)hipGraphDestroy(w->graph[prec]);
-        w->exec[prec] = nullptr;
-        w->graph[prec] = nullptr;
+    const int g = 2 * prec + (full ? 0 : 1);
+    if (!w->exec[g] || w->graph_k[g] != k) {
+        if (w->exec[g]) (void)hipGraphExecDestroy(w->exec[g]);
+        if (w->graph[g]) (void)hipGraphDestroy(w->graph[g]);
+        w->exec[g] = nullptr;
+        w->graph[g] = nullptr;
         D2D_CHECK(hv.prepare(prec));          // launch tables exist before capture
         D2D_CHECK(hv.prepare(D2D_FP64));
         D2D_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         d2d_status st = inner_loop(w, hv, prec, k, window, fused, plain_cgs2, basis64, s);
         if (st == D2D_OK) st = residual_step(w, hv, s);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(s, &g);
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &gr);
         if (st != D2D_OK) {
-            if (g) (void)hipGraphDestroy(g);
+            if (gr) (void)hipGraphDestroy(gr);
             return st;
         }
         if (e != hipSuccess) {
             set_error("graph capture failed: %s", hipGetErrorString(e));
             return D2D_EDEVICE;
         }
-        w->graph[prec] = g;
-        D2D_HIP(hipGraphInstantiate(&w->exec[prec], g, nullptr, nullptr, 0));
-        w->graph_k[prec] = k;
+        w->graph[g] = gr;
+        D2D_HIP(hipGraphInstantiate(&w->exec[g], gr, nullptr, nullptr, 0));
+        w->graph_k[g] = k;
     }
-    D2D_HIP(hipGraphLaunch(w->exec[prec], s));
+    D2D_HIP(hipGraphLaunch(w->exec[g], s));
     hv.count(prec, k - 1);
     hv.count(D2D_FP64, 1);
     return D2D_OK;
@@ -267,11 +268,12 @@ d2d_status check_lanczos_opts(const d2d_lanczos_opts* o) {
         !(o->tol_res > 0.0) || o->prec < 0 || o->prec >= D2D_NPREC || o->reorth_window < 0 ||
         o->reorth_window == 1 || o->reorth_window > 32 || o->separate_central < 0 ||
         o->separate_central > 1 || !(o->tol_rel_e >= 0.0) || o->plain_cgs2 < 0 || o->plain_cgs2 > 1 ||
-        o->basis_fp64 < 0 || o->basis_fp64 > 1) {
+        o->basis_fp64 < 0 || o->basis_fp64 > 1 || o->fixed_cycles < 0 || o->fixed_cycles > 1) {
         set_error("Lanczos options: k_in and k_in_bf16 (0 or) 2..128 (2..32 with full reorthogonalisation), "
                   "max_restarts >= 0, "
                   "tol_res > 0, prec 0..3, reorth_window 0 or 2..32, "
-                  "separate_central 0 or 1, tol_rel_e >= 0, plain_cgs2 0 or 1, basis_fp64 0 or 1");
+                  "separate_central 0 or 1, tol_rel_e >= 0, plain_cgs2 0 or 1, basis_fp64 0 or 1, "
+                  "fixed_cycles 0 or 1");
         return D2D_EINVAL;
     }
     return D2D_OK;
@@ -321,6 +323,8 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
     D2D_HIP(hipStreamSynchronize(s));
     std::vector<double> theta(np), rho(np), rho_prev(np, -1.0), theta_prev(np, 0.0), pred(np, 0.0);
     std::vector<int> have_prev(np, 0);
+    // residual reduction per inner step of each problem's last cycle (log10; 0: unknown)
+    std::vector<double> rate(np, 0.0);
     std::vector<d2d_lanczos_stats> st(np);
     std::memset(st.data(), 0, sizeof(d2d_lanczos_stats) * np);
     // deferred: the problem's restarts need a higher precision; it waits until
@@ -410,9 +414,28 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
             D2D_CHECK(hv.set_active(a, &rebuilt));
             if (rebuilt) drop_graphs(w);
         }
-        const int k = k_of(prec);
-        D2D_CHECK(restart(w, hv, prec, k, opts->reorth_window, opts->separate_central == 0, opts->plain_cgs2 != 0,
-                          opts->basis_fp64 != 0, opts->use_graph != 0, s));
+        // Cycle length: k_of(prec), or shorter when every iterating problem's
+        // last cycle reduced the residual at a rate that reaches the residual
+        // bar in fewer steps (1.25 x the steps plus 4, for the slower start of
+        // a cycle); with an energy-change stop the cycles stay full.
+        const int kfull = k_of(prec);
+        int k = kfull;
+        if (!opts->fixed_cycles && opts->tol_rel_e == 0.0) {
+            int need = 2;
+            for (int p = 0; p < np && need < kfull; ++p) {
+                if (!a[p]) continue;
+                const double bar = opts->tol_res * std::fabs(theta[p]);
+                if (!(rate[p] > 0.0) || !(bar > 0.0)) {
+                    need = kfull;
+                    break;
+                }
+                const double steps = std::log10(rho[p] / bar) / rate[p];
+                need = std::max(need, (int)std::ceil(1.25 * steps) + 5);
+            }
+            k = std::min(kfull, need);
+        }
+        D2D_CHECK(restart(w, hv, prec, k, k == kfull, opts->reorth_window, opts->separate_central == 0,
+                          opts->plain_cgs2 != 0, opts->basis_fp64 != 0, opts->use_graph != 0, s));
         for (int p = 0; p < np; ++p)
             if (a[p]) {
                 hvc[p][prec] += k - 1;
@@ -429,6 +452,7 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
             rho[p] = w->res_host[2 * p + 1];
             pred[p] = w->res_host[2 * np + p];
             restarts[p] += 1;   // the restarts that included the problem
+            rate[p] = rho[p] > 0.0 && rho[p] < rho_prev[p] ? std::log10(rho_prev[p] / rho[p]) / (k - 1) : 0.0;
         }
     }
     D2D_HIP(hipStreamSynchronize(s));

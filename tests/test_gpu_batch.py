@@ -223,7 +223,8 @@ def test_config5_bf16_defers_only_the_problems_that_need_more(ctx, config5_batch
     with torch.cuda.stream(ctx.stream):
         v0 = [torch.as_tensor(W.random_vector(p.info["n"], wl.seed)).to("cuda") for p, wl in zip(probs, wls)]
     ctx.stream.synchronize()
-    opts = d2d.lanczos_opts(prec=d2d.D2D_BF16, k_in=24, max_restarts=400, tol_res=1e-8, reorth_window=3)
+    opts = d2d.lanczos_opts(prec=d2d.D2D_BF16, k_in=24, max_restarts=400, tol_res=1e-8, reorth_window=3,
+                            fixed_cycles=1)
     st, e, per = d2d.d2d_batch_lanczos(b, opts, v0)
     assert st == 0
     dE = [abs(ei - refs[wl.name]) / abs(refs[wl.name]) for ei, wl in zip(e, wls)]

@@ -120,7 +120,8 @@ def test_bf16_cycles_use_their_own_krylov_size(ctx):
     with torch.cuda.stream(ctx.stream):
         v0 = torch.as_tensor(W.random_vector(prob.info["n"], wl.seed)).to("cuda")
     ctx.stream.synchronize()
-    opts = d2d.lanczos_opts(prec=2, k_in=48, k_in_bf16=16, max_restarts=300, tol_res=1e-8, reorth_window=3)
+    opts = d2d.lanczos_opts(prec=2, k_in=48, k_in_bf16=16, max_restarts=300, tol_res=1e-8, reorth_window=3,
+                            fixed_cycles=1)
     st, e, stats = d2d.d2d_lanczos(prob.sb, opts, v0)
     E0 = reference_energy(wl.name)
     hv = stats["hv_count"]
@@ -129,6 +130,34 @@ def test_bf16_cycles_use_their_own_krylov_size(ctx):
     assert hv[2] > 0 and hv[2] % 15 == 0 and hv[1] % 47 == 0 and hv[3] % 47 == 0
     assert hv[2] // 15 + hv[1] // 47 + hv[3] // 47 == stats["restarts"]
     assert hv[0] == stats["restarts"] + 1
+    prob.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_last_cycle_fits_the_residual_bar(ctx, prec):
+    """With fixed_cycles 0 a cycle stops early when the previous cycle's
+    residual rate reaches the bar sooner: the solve meets the oracle's energy
+    with fewer products than full cycles, and the inner products are no
+    longer a multiple of k_in - 1; fixed_cycles 1 keeps every cycle full."""
+    from paper_0707_0159_amd import d2d
+    wl = W.CONFIGS[2]
+    prob = GpuProblem(ctx, wl)
+    E0 = reference_energy(wl.name)
+    with torch.cuda.stream(ctx.stream):
+        v0 = torch.as_tensor(W.random_vector(prob.info["n"], wl.seed)).to("cuda")
+    ctx.stream.synchronize()
+    out = {}
+    for fixed in (0, 1):
+        opts = d2d.lanczos_opts(prec=prec, k_in=64, max_restarts=300, tol_res=1e-8, reorth_window=3,
+                                fixed_cycles=fixed)
+        st, e, stats = d2d.d2d_lanczos(prob.sb, opts, v0)
+        inner = sum(stats["hv_count"]) - (stats["restarts"] + 1)
+        print("fixed_cycles", prec, fixed, e, stats["restarts"], stats["hv_count"], stats["log_rho"])
+        assert st == 0 and abs(e - E0) <= 1e-10 * abs(E0)
+        assert stats["residual"] <= 1e-8 * abs(e)
+        out[fixed] = (inner, stats["restarts"])
+    assert out[1][0] == 63 * out[1][1]
+    assert out[0][0] % 63 != 0 and out[0][0] < out[1][0]
     prob.close()
 
 
@@ -220,7 +249,8 @@ def test_no_escalation_when_the_krylov_space_is_slow(ctx):
     with torch.cuda.stream(ctx.stream):
         v0 = torch.as_tensor(W.random_vector(prob.info["n"], wl.seed)).to("cuda")
     ctx.stream.synchronize()
-    opts = d2d.lanczos_opts(prec=2, k_in=24, max_restarts=300, tol_res=1e-8, reorth_window=3, escalate=1e-6)
+    opts = d2d.lanczos_opts(prec=2, k_in=24, max_restarts=300, tol_res=1e-8, reorth_window=3, escalate=1e-6,
+                            fixed_cycles=1)
     st, e, stats = d2d.d2d_lanczos(prob.sb, opts, v0)
     E0 = reference_energy(wl.name)
     ratios = [r / max(p, 1e-300) for r, p in zip(stats["log_rho"][1:], stats["log_pred"][1:])]
@@ -245,7 +275,8 @@ def test_escalation_from_bf16_on_a_rising_energy(ctx):
     with torch.cuda.stream(ctx.stream):
         v0 = torch.as_tensor(W.random_vector(prob.info["n"], wl.seed)).to("cuda")
     ctx.stream.synchronize()
-    opts = d2d.lanczos_opts(prec=2, k_in=24, max_restarts=300, tol_res=1e-8, reorth_window=3, basis_fp64=1)
+    opts = d2d.lanczos_opts(prec=2, k_in=24, max_restarts=300, tol_res=1e-8, reorth_window=3, basis_fp64=1,
+                            fixed_cycles=1)
     st, e, stats = d2d.d2d_lanczos(prob.sb, opts, v0)
     E0 = reference_energy(wl.name)
     seen = list(dict.fromkeys(stats["log_prec"]))
