@@ -278,7 +278,8 @@ d2d_status d2d_tile_shapes(int* count, int* desc);
  *   restart j: w = H_64 x_j, theta_j = x_j.w, r = w - theta_j x_j,
  *   rho_j = |r|; stop if converged; else an inner Lanczos started from x_j
  *   (alpha_0 = theta_j, beta_1 = rho_j, q_1 = r/rho_j) runs k_in - 1 more
- *   steps with Hv in precision prec_j, reorthogonalisation by classical
+ *   steps (fewer in a cycle fitted to the residual bar, see fixed_cycles)
+ *   with Hv in precision prec_j, reorthogonalisation by classical
  *   Gram-Schmidt twice in FP64 (against all basis vectors, or the last
  *   reorth_window ones), the tridiagonal lowest eigenpair on the device, and
  *   x_{j+1} = y_0 x_j + sum_{i>=1} y_i q_i.
