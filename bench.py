@@ -45,33 +45,46 @@ def basis_name(args):
 PREC_NAMES = ("fp64", "fp32", "bf16", "bf16x3")
 
 
-def solve_time_bound(stats: dict, n: int, k_in: int, window: int, basis_fp64: bool, hv_flops: dict,
+def solve_time_parts(stats: dict, n: int, k_in: int, window: int, basis_fp64: bool, hv_flops: dict,
                      hv_bytes: dict) -> dict:
-    """Time-to-energy roofline of one solve: every Hv at max(flops / MFMA peak,
-    minimum bytes / HBM peak) of its precision, plus the Lanczos vector
-    kernels' algorithmic bytes at HBM peak.  Per inner step with window w and
-    basis bytes bq (8 at FP64 or with an FP64 basis, else 4), product bytes
-    bw (8 at FP64, else 4): the two step kernels read the product twice and
-    the window twice and write the next basis vector (BF16 also its 2-byte
-    copy): N (2 bw + 2 w bq + bq [+ 2]).  Per restart (FP64 residual, Ritz
-    vector, normalisation, first basis vectors): N (88 + (k_in + 1) bq)."""
+    """Lower-bound pieces of one problem's solve (seconds): every Hv at
+    max(flops / MFMA peak, minimum bytes / HBM peak) of its precision
+    ("hv_s"), the same flops and bytes summed separately ("hv_flop_s",
+    "hv_byte_s"), and the Lanczos vector kernels' algorithmic bytes at HBM peak
+    ("vec_s").  Per inner step with window w and basis bytes bq (8 at FP64 or
+    with an FP64 basis, else 4), product bytes bw (8 at FP64, else 4): the two
+    step kernels read the product twice and the window twice and write the
+    next basis vector (BF16 also its 2-byte copy): N (2 bw + 2 w bq + bq
+    [+ 2]).  Per restart (FP64 residual, Ritz vector, normalisation, first
+    basis vectors): N (88 + (k_in + 1) bq)."""
     hv = stats["hv_count"]
     restarts = stats["restarts"]
     nq = window if window >= 2 else (k_in + 1) / 2.0
-    t_hv = t_step = 0.0
+    t_hv = t_flop = t_byte = t_step = 0.0
     for p, name in enumerate(PREC_NAMES):
         cnt = hv[p]
         if cnt == 0:
             continue
-        t_hv += cnt * max(hv_flops[name] / PEAK[name], hv_bytes[name] / PEAK["hbm"])
+        tf, tb = hv_flops[name] / PEAK[name], hv_bytes[name] / PEAK["hbm"]
+        t_hv += cnt * max(tf, tb)
+        t_flop += cnt * tf
+        t_byte += cnt * tb
         steps = cnt - (restarts + 1) if p == 0 else cnt     # FP64 counts include the residual products
         bq = 8 if (p == 0 or basis_fp64) else 4
         bw = 8 if p == 0 else 4
         t_step += max(steps, 0) * n * (2 * bw + 2 * nq * bq + bq + (2 if name == "bf16" else 0)) / PEAK["hbm"]
     bq_main = 8 if (basis_fp64 or sum(hv[1:]) == 0) else 4
     t_restart = (restarts + 1) * n * (88 + (k_in + 1) * bq_main) / PEAK["hbm"]
-    t_min = t_hv + t_step + t_restart
-    return {"t_min_ms": t_min * 1e3, "hv_ms": t_hv * 1e3, "lanczos_vectors_ms": (t_step + t_restart) * 1e3}
+    return {"hv_s": t_hv, "hv_flop_s": t_flop, "hv_byte_s": t_byte, "vec_s": t_step + t_restart}
+
+
+def solve_time_bound(stats: dict, n: int, k_in: int, window: int, basis_fp64: bool, hv_flops: dict,
+                     hv_bytes: dict) -> dict:
+    """Time-to-energy roofline of one solve: its Hv products, each at the
+    bound of its precision, plus the Lanczos vector traffic."""
+    t = solve_time_parts(stats, n, k_in, window, basis_fp64, hv_flops, hv_bytes)
+    return {"t_min_ms": (t["hv_s"] + t["vec_s"]) * 1e3, "hv_ms": t["hv_s"] * 1e3,
+            "lanczos_vectors_ms": t["vec_s"] * 1e3}
 
 
 def kernel_source_hash() -> str:
@@ -213,6 +226,20 @@ def bench_batch(args):
     with torch.cuda.stream(s):
         v0 = [torch.as_tensor(W.random_vector(i["n"], wl.seed), device="cuda") for i, wl in zip(infos, wls)]
     s.synchronize()
+    # per problem: the flops its Hv executes on its own (default launch
+    # configuration) and the minimum bytes, per precision
+    prob_flops = [{n: d2d.d2d_sb_gemm_flops(sb, p) for p, n in enumerate(PREC_NAMES)} for sb in sbs]
+    prob_bytes = [{n: i["bytes_min_" + n] for n in PREC_NAMES} for i in infos]
+
+    def batch_time_bound(per, prec):
+        # the batch runs every problem's flops and bytes: time >= the larger of
+        # the summed flop and byte times, plus the vector kernels' bytes
+        k = args.k_in_bf16 if prec == d2d.D2D_BF16 and args.k_in_bf16 > 0 else args.k_in
+        parts = [solve_time_parts(st, i["n"], k, args.window, args.basis_fp64, f, by)
+                 for st, i, f, by in zip(per, infos, prob_flops, prob_bytes)]
+        t_hv = max(sum(x["hv_flop_s"] for x in parts), sum(x["hv_byte_s"] for x in parts))
+        t_vec = sum(x["vec_s"] for x in parts)
+        return {"t_min_ms": (t_hv + t_vec) * 1e3, "hv_ms": t_hv * 1e3, "lanczos_vectors_ms": t_vec * 1e3}
 
     def solve(prec):
         opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol, use_graph=1,
@@ -242,7 +269,9 @@ def bench_batch(args):
                 continue
             ft = next((t for t, th in zip(p["log_t"], p["log_theta"]) if abs(th - E0) <= 1e-10 * abs(E0)), None)
             firsts.append(ft)
-        return {"hv_per_s": hv / wall, "s_per_solve": wall / steps,
+        bound = batch_time_bound(per, prec)
+        bound["frac"] = bound["t_min_ms"] * 1e-3 / (wall / steps)
+        return {"hv_per_s": hv / wall, "s_per_solve": wall / steps, "time_roofline": bound,
                 "max_dE_rel": max(dE) if dE else None, "problems_with_reference": len(dE),
                 "all_within_1e-10_s": (max(firsts) if firsts and None not in firsts else None),
                 "restarts_max": max(p["restarts"] for p in per),
