@@ -38,25 +38,36 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "bf16x3": 2.5e15 / 3, "hbm": 8.0e12}
 
 
+BASIS_NAMES = {0: "the products' input precision (FP32; BF16 for BF16 products; start vector in FP64)",
+               1: "FP64 at every precision", 2: "FP32 below FP64 (start vector in FP64)"}
+
+
 def basis_name(args):
-    return "FP64 at every precision" if args.basis_fp64 else "FP32 below FP64 (start vector in FP64)"
+    return BASIS_NAMES[args.basis]
+
+
+def basis_bytes(p: int, basis: int) -> int:
+    """Bytes per inner basis element for precision index p (0 FP64, 1 FP32, 2 BF16, 3 BF16x3)."""
+    if p == 0 or basis == 1:
+        return 8
+    return 2 if (p == 2 and basis == 0) else 4
 
 
 PREC_NAMES = ("fp64", "fp32", "bf16", "bf16x3")
 
 
-def solve_time_parts(stats: dict, n: int, k_in: int, window: int, basis_fp64: bool, hv_flops: dict,
+def solve_time_parts(stats: dict, n: int, k_in: int, window: int, basis: int, hv_flops: dict,
                      hv_bytes: dict) -> dict:
     """Lower-bound pieces of one problem's solve (seconds): every Hv at
     max(flops / MFMA peak, minimum bytes / HBM peak) of its precision
     ("hv_s"), the same flops and bytes summed separately ("hv_flop_s",
     "hv_byte_s"), and the Lanczos vector kernels' algorithmic bytes at HBM peak
-    ("vec_s").  Per inner step with window w and basis bytes bq (8 at FP64 or
-    with an FP64 basis, else 4), product bytes bw (8 at FP64, else 4): the two
-    step kernels read the product twice and the window twice and write the
-    next basis vector (BF16 also its 2-byte copy): N (2 bw + 2 w bq + bq
-    [+ 2]).  Per restart (FP64 residual, Ritz vector, normalisation, first
-    basis vectors): N (88 + (k_in + 1) bq)."""
+    ("vec_s").  Per inner step with window w and basis bytes bq (basis_bytes),
+    product bytes bw (8 at FP64, else 4): the two step kernels read the
+    product twice and the window twice and write the next basis vector, and
+    an input copy where the basis is not in the input precision (ci bytes):
+    N (2 bw + 2 w bq + bq + ci).  Per restart (FP64 residual, Ritz vector,
+    normalisation, first basis vectors): N (88 + (k_in + 1) bq)."""
     hv = stats["hv_count"]
     restarts = stats["restarts"]
     nq = window if window >= 2 else (k_in + 1) / 2.0
@@ -70,19 +81,22 @@ def solve_time_parts(stats: dict, n: int, k_in: int, window: int, basis_fp64: bo
         t_flop += cnt * tf
         t_byte += cnt * tb
         steps = cnt - (restarts + 1) if p == 0 else cnt     # FP64 counts include the residual products
-        bq = 8 if (p == 0 or basis_fp64) else 4
+        bq = basis_bytes(p, basis)
         bw = 8 if p == 0 else 4
-        t_step += max(steps, 0) * n * (2 * bw + 2 * nq * bq + bq + (2 if name == "bf16" else 0)) / PEAK["hbm"]
-    bq_main = 8 if (basis_fp64 or sum(hv[1:]) == 0) else 4
+        bi = {0: 8, 1: 4, 2: 2, 3: 4}[p]
+        ci = 0 if bq == bi else bi
+        t_step += max(steps, 0) * n * (2 * bw + 2 * nq * bq + bq + ci) / PEAK["hbm"]
+    main = max(range(4), key=lambda q: hv[q] if q else hv[0] - (restarts + 1))
+    bq_main = basis_bytes(main, basis)
     t_restart = (restarts + 1) * n * (88 + (k_in + 1) * bq_main) / PEAK["hbm"]
     return {"hv_s": t_hv, "hv_flop_s": t_flop, "hv_byte_s": t_byte, "vec_s": t_step + t_restart}
 
 
-def solve_time_bound(stats: dict, n: int, k_in: int, window: int, basis_fp64: bool, hv_flops: dict,
+def solve_time_bound(stats: dict, n: int, k_in: int, window: int, basis: int, hv_flops: dict,
                      hv_bytes: dict) -> dict:
     """Time-to-energy roofline of one solve: its Hv products, each at the
     bound of its precision, plus the Lanczos vector traffic."""
-    t = solve_time_parts(stats, n, k_in, window, basis_fp64, hv_flops, hv_bytes)
+    t = solve_time_parts(stats, n, k_in, window, basis, hv_flops, hv_bytes)
     return {"t_min_ms": (t["hv_s"] + t["vec_s"]) * 1e3, "hv_ms": t["hv_s"] * 1e3,
             "lanczos_vectors_ms": t["vec_s"] * 1e3}
 
@@ -235,7 +249,7 @@ def bench_batch(args):
         # the batch runs every problem's flops and bytes: time >= the larger of
         # the summed flop and byte times, plus the vector kernels' bytes
         k = args.k_in_bf16 if prec == d2d.D2D_BF16 and args.k_in_bf16 > 0 else args.k_in
-        parts = [solve_time_parts(st, i["n"], k, args.window, args.basis_fp64, f, by)
+        parts = [solve_time_parts(st, i["n"], k, args.window, args.basis, f, by)
                  for st, i, f, by in zip(per, infos, prob_flops, prob_bytes)]
         t_hv = max(sum(x["hv_flop_s"] for x in parts), sum(x["hv_byte_s"] for x in parts))
         t_vec = sum(x["vec_s"] for x in parts)
@@ -243,7 +257,7 @@ def bench_batch(args):
 
     def solve(prec):
         opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol, use_graph=1,
-                                reorth_window=args.window, basis_fp64=int(args.basis_fp64),
+                                reorth_window=args.window, basis=args.basis,
                                 k_in_bf16=args.k_in_bf16, fixed_cycles=int(args.fixed_cycles))
         st, e, per = d2d.d2d_batch_lanczos(b, opts, v0)
         if st != 0:
@@ -349,8 +363,8 @@ def main():
                     help="every cycle full length (default: the last cycle fitted to the residual bar)")
     ap.add_argument("--window", type=int, default=3, help="reorthogonalisation window (0 = full)")
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--basis-fp64", action="store_true",
-                    help="store the inner Krylov basis in FP64 at every precision (default: FP32 below FP64)")
+    ap.add_argument("--basis", type=int, choices=[0, 1, 2], default=0,
+                    help="inner basis storage: 0 the products' input precision, 1 FP64, 2 FP32 below FP64")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", choices=["hv", "copy"], default=None,
@@ -436,7 +450,7 @@ def main():
 
     def solve(prec):
         opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol, use_graph=1,
-                                reorth_window=args.window, basis_fp64=int(args.basis_fp64),
+                                reorth_window=args.window, basis=args.basis,
                                 k_in_bf16=args.k_in_bf16, fixed_cycles=int(args.fixed_cycles))
         st, e, stats = d2d.d2d_lanczos(sb, opts, v0, psi)
         if st != 0:
@@ -465,7 +479,7 @@ def main():
         wall = time.perf_counter() - t0
         e, st = last
         k_path = args.k_in_bf16 if prec == d2d.D2D_BF16 and args.k_in_bf16 > 0 else args.k_in
-        bound = solve_time_bound(st, N, k_path, args.window, args.basis_fp64,
+        bound = solve_time_bound(st, N, k_path, args.window, args.basis,
                                  {k: v["gemm_flops"] for k, v in tuned.items()},
                                  {k: info["bytes_min_" + k] for k in tuned})
         bound["frac"] = bound["t_min_ms"] * 1e-3 / (wall / steps)

@@ -285,9 +285,10 @@ d2d_status d2d_tile_shapes(int* count, int* desc);
  *   x_{j+1} = y_0 x_j + sum_{i>=1} y_i q_i.
  * All recurrences, dot products, the tridiagonal solve and the Ritz vector
  * are FP64 arithmetic on the device; the host reads (theta_j, rho_j) once per
- * restart.  Below FP64 the basis q_0..q_{k-1} is stored in FP32 (unless
- * basis_fp64): x_j enters x_{j+1} in FP64, so the storage rounding only
- * touches the correction sum_{i>=1} y_i q_i, which shrinks with the residual.
+ * restart.  Below FP64 the basis q_0..q_{k-1} is stored in the products'
+ * input precision (see basis): x_j enters x_{j+1} in FP64, so the storage
+ * rounding only touches the correction sum_{i>=1} y_i q_i, which shrinks with
+ * the residual.
  * Precision schedule: start in opts.prec; the precision is raised (BF16 ->
  * BF16X3 when kept -> FP32 -> FP64) after a restart with rho_{j+1} > escalate
  * * rho_j whose shortfall is the low-precision products' doing: theta_{j+1} >
@@ -330,9 +331,11 @@ typedef struct {
                             second Gram-Schmidt pass and the norm follow from the
                             first pass's sums and the window's Gram matrix;
                             1: always two explicit passes (three kernels)     */
-    int basis_fp64;      /* 0: inner basis in FP32 when prec_j is below FP64 (the
-                            FP32 basis vector is the FP32/BF16x3 Hv input);
-                            1: FP64 basis at every precision                  */
+    int basis;           /* storage of the inner basis: 0: the products' input
+                            precision (FP64; FP32 for FP32 and BF16x3; BF16
+                            for BF16), so a basis vector is the Hv input
+                            itself; 1: FP64 at every precision; 2: FP32
+                            below FP64 (BF16 products read a BF16 copy)      */
     int k_in_bf16;       /* Krylov dimension of BF16 inner cycles (0: k_in);
                             limits as k_in.  A BF16 cycle gains little past
                             the point where the BF16 products' error stops

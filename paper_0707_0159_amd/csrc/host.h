@@ -87,7 +87,8 @@ struct LanczosWork {
     int kmax = 0, nprob = 0, NB = 0;
     int64_t ntot = 0;
     std::vector<int64_t> seg_off, seg_len;
-    double* Q = nullptr;         // (kmax+1) x ntot
+    int64_t ldq = 0;             // basis vector stride: ntot rounded up to 64 elements
+    double* Q = nullptr;         // (kmax+1) x ldq doubles (or as many FP32 / BF16 elements)
     double* X = nullptr;
     double* W = nullptr;
     float* wlo = nullptr;

@@ -207,15 +207,15 @@ struct LzSet {
 // upcast), w -= Q c1, c2 = Q^T w, alpha_i = c1[i] + c2[i],
 // beta_{i+1} = sqrt(|w|^2 - |c2|^2), and if qnext != null:
 // qnext = (w - [need2] Q c2) / beta_{i+1}, lo = cast(qnext).  The basis Q
-// (and qnext) is FP64, or FP32 when q32 (then upcast must hold); the
-// arithmetic is FP64 either way.
+// (and qnext) has qbytes per element: FP64 (8), FP32 (4) or BF16 (2; the
+// narrow ones with upcast only); the arithmetic is FP64 either way.
 struct LzStepArgs {
     const LzSeg* bt;
     const void* Q;
     int64_t ldq;
     int nq, i;
     bool upcast;
-    bool q32;
+    int qbytes;
     bool gram;              // two-kernel Gram form of the step (nq <= 4)
     const float* w32;
     double* w;
@@ -236,15 +236,16 @@ hipError_t launch_seeded_normal(double* x, int64_t n, uint64_t seed, hipStream_t
 hipError_t launch_lz_step(const LzStepArgs& a, hipStream_t s);
 // theta = x.w, w -= theta x, rho = |w|; alpha_0 = theta, beta_1 = rho, res = (theta, rho)
 hipError_t launch_lz_residual(const LzSet& z, const double* x, double* w, hipStream_t s);
-// x = (y_0 x + sum_{j>=1} y_j Q[j]) / |.| per problem (Q FP32 when q32, else FP64)
-hipError_t launch_lz_ritz(const LzSet& z, const void* Q, bool q32, int k, double* x, hipStream_t s);
+// x = (y_0 x + sum_{j>=1} y_j Q[j]) / |.| per problem (Q: qbytes per element, vectors ldq apart)
+hipError_t launch_lz_ritz(const LzSet& z, const void* Q, int qbytes, int64_t ldq, int k, double* x,
+                          hipStream_t s);
 // x = v / |v| per problem
 hipError_t launch_lz_normalize_into(const LzSet& z, const double* v, double* x, hipStream_t s);
 // res[2p] = |v_p|^2
 hipError_t launch_lz_norms(const LzSet& z, const double* v, hipStream_t s);
-// Q[0] = x, Q[1] = w / beta_1 (FP32 when q32, else FP64), lo = cast(Q[1])
-hipError_t launch_lz_first(const LzSet& z, const double* x, const double* w, void* Q, bool q32, void* lo,
-                           int lo_prec, hipStream_t s);
+// Q[0] = x, Q[1] = w / beta_1 (qbytes per element, ldq apart), lo = cast(Q[1])
+hipError_t launch_lz_first(const LzSet& z, const double* x, const double* w, void* Q, int qbytes, int64_t ldq,
+                           void* lo, int lo_prec, hipStream_t s);
 // lowest eigenpair of each problem's k x k tridiagonal (theta at S_THETA+1, y at S_Y)
 hipError_t launch_lz_tridiag(const LzSet& z, int k, hipStream_t s);
 

@@ -373,6 +373,23 @@ __device__ inline void store_lo(void* __restrict__ lo, int lo_prec, int64_t e, d
     else if (lo_prec == D2D_BF16) ((uint16_t*)lo)[e] = f32_bf16_rne((float)q);
 }
 
+// A basis element stored in BF16 (the bits; FP64 -> FP32 -> BF16, each to
+// nearest even, as every BF16 copy here).
+struct bf16q {
+    uint16_t b;
+};
+__device__ inline double q_to_f64(double x) { return x; }
+__device__ inline double q_to_f64(float x) { return (double)x; }
+__device__ inline double q_to_f64(bf16q x) { return (double)__uint_as_float((uint32_t)x.b << 16); }
+template <typename TQ>
+__device__ inline TQ q_from_f64(double q);
+template <>
+__device__ inline double q_from_f64<double>(double q) { return q; }
+template <>
+__device__ inline float q_from_f64<float>(double q) { return (float)q; }
+template <>
+__device__ inline bf16q q_from_f64<bf16q>(double q) { return bf16q{f32_bf16_rne((float)q)}; }
+
 // Step kernel 1: w = (((w + P0) + P1) + P2) + P3 in the Hv's precision (the
 // parts of a split or fused Hv, each nullable), upcast from FP32 when UPCAST,
 // stored as FP64 when it changed; partials of c1 = Q[0..nq)^T w.
@@ -412,7 +429,7 @@ k_lz_dots(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q,
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? (double)qr[u][j] : 0.0;
+            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? q_to_f64(qr[u][j]) : 0.0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const bool ok = e0 + u * st < sg.hi;
@@ -472,7 +489,7 @@ k_lz_update_dots(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q,
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? (double)qr[u][j] : 0.0;
+            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? q_to_f64(qr[u][j]) : 0.0;
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (e0 + u * st >= sg.hi) {
@@ -556,7 +573,7 @@ k_lz_next(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q,
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int j = 0; j < NQ; ++j) q[u][j] = (corr && j < nq) ? (double)qr[u][j] : 0.0;
+            for (int j = 0; j < NQ; ++j) q[u][j] = (corr && j < nq) ? q_to_f64(qr[u][j]) : 0.0;
         if (corr)
 #pragma unroll
             for (int j = 0; j < NQ; ++j)
@@ -568,7 +585,7 @@ k_lz_next(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q,
             const int64_t e = e0 + u * st;
             if (e >= sg.hi) break;
             const double q = x[u] * inv;
-            qnext[e] = (TQ)q;
+            qnext[e] = q_from_f64<TQ>(q);
             store_lo(lo, lo_prec, e, q);
         }
     }
@@ -630,7 +647,7 @@ k_lz_dots_gram(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q, int64_t l
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? (double)qr[u][j] : 0.0;
+            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? q_to_f64(qr[u][j]) : 0.0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t e = e0 + u * st;
@@ -715,7 +732,7 @@ k_lz_update_gram(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q, int64_t
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? (double)qr[u][j] : 0.0;
+            for (int j = 0; j < NQ; ++j) q[u][j] = j < nq ? q_to_f64(qr[u][j]) : 0.0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t e = e0 + u * st;
@@ -723,7 +740,7 @@ k_lz_update_gram(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q, int64_t
 #pragma unroll
             for (int j = 0; j < NQ; ++j) x[u] -= d[j] * q[u][j];
             const double qv = x[u] * inv;
-            qnext[e] = (TQ)qv;
+            qnext[e] = q_from_f64<TQ>(qv);
             store_lo(lo, lo_prec, e, qv);
         }
     }
@@ -791,9 +808,12 @@ static hipError_t lz_step(const LzStepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_lz_step(const LzStepArgs& a, hipStream_t s) {
-    // an FP32 basis only with an FP32 product (the FP64 recurrence keeps an FP64 basis)
-    if (a.q32 && !a.upcast) return hipErrorInvalidValue;
-    return a.q32 ? lz_step<float>(a, s) : lz_step<double>(a, s);
+    // a narrow basis only with a low-precision product (the FP64 recurrence keeps an FP64 basis)
+    if (a.qbytes != 8 && !a.upcast) return hipErrorInvalidValue;
+    if (a.qbytes == 8) return lz_step<double>(a, s);
+    if (a.qbytes == 4) return lz_step<float>(a, s);
+    if (a.qbytes == 2) return lz_step<bf16q>(a, s);
+    return hipErrorInvalidValue;
 }
 
 // partials of x.w (row 0)
@@ -875,7 +895,7 @@ k_lz_ritz(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q, int64_t ldq,
     double acc[1] = {0.0};
     for (int64_t e = sg.lo + threadIdx.x; e < sg.hi; e += blockDim.x) {
         double v = ys[0] * x[e];
-        for (int j = 1; j < k; ++j) v += ys[j] * (double)Q[j * ldq + e];
+        for (int j = 1; j < k; ++j) v += ys[j] * q_to_f64(Q[j * ldq + e]);
         x[e] = v;
         acc[0] += v * v;
     }
@@ -894,14 +914,20 @@ k_lz_normalize(const LzSeg* __restrict__ bt, const double* __restrict__ partial,
     for (int64_t e = sg.lo + threadIdx.x; e < sg.hi; e += blockDim.x) dst[e] = src[e] * inv;
 }
 
-hipError_t launch_lz_ritz(const LzSet& z, const void* Q, bool q32, int k, double* x, hipStream_t s) {
+hipError_t launch_lz_ritz(const LzSet& z, const void* Q, int qbytes, int64_t ldq, int k, double* x,
+                          hipStream_t s) {
     if (k > 128) return hipErrorInvalidValue;
-    if (q32)
-        hipLaunchKernelGGL(k_lz_ritz<float>, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, (const float*)Q, z.ntot, k,
+    if (qbytes == 2)
+        hipLaunchKernelGGL(k_lz_ritz<bf16q>, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, (const bf16q*)Q, ldq, k,
                            z.scal, x, z.partial, z.NB);
-    else
-        hipLaunchKernelGGL(k_lz_ritz<double>, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, (const double*)Q, z.ntot,
+    else if (qbytes == 4)
+        hipLaunchKernelGGL(k_lz_ritz<float>, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, (const float*)Q, ldq, k,
+                           z.scal, x, z.partial, z.NB);
+    else if (qbytes == 8)
+        hipLaunchKernelGGL(k_lz_ritz<double>, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, (const double*)Q, ldq,
                            k, z.scal, x, z.partial, z.NB);
+    else
+        return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_lz_normalize, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, z.partial, z.NB,
@@ -948,8 +974,8 @@ k_lz_first(const LzSeg* __restrict__ bt, const double* __restrict__ x, const dou
     const double inv = b > 0.0 ? 1.0 / b : 0.0;
     for (int64_t e = sg.lo + threadIdx.x; e < sg.hi; e += blockDim.x) {
         const double q = w[e] * inv;
-        q0[e] = (TQ)x[e];
-        q1[e] = (TQ)q;
+        q0[e] = q_from_f64<TQ>(x[e]);
+        q1[e] = q_from_f64<TQ>(q);
         store_lo(lo, lo_prec, e, q);
     }
 }
@@ -980,14 +1006,20 @@ hipError_t launch_seeded_normal(double* x, int64_t n, uint64_t seed, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_lz_first(const LzSet& z, const double* x, const double* w, void* Q, bool q32, void* lo,
-                           int lo_prec, hipStream_t s) {
-    if (q32)
+hipError_t launch_lz_first(const LzSet& z, const double* x, const double* w, void* Q, int qbytes, int64_t ldq,
+                           void* lo, int lo_prec, hipStream_t s) {
+    const int lp = lo ? lo_prec : -1;
+    if (qbytes == 2)
+        hipLaunchKernelGGL(k_lz_first<bf16q>, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, x, w, z.scal, (bf16q*)Q,
+                           (bf16q*)Q + ldq, lo, lp);
+    else if (qbytes == 4)
         hipLaunchKernelGGL(k_lz_first<float>, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, x, w, z.scal, (float*)Q,
-                           (float*)Q + z.ntot, lo, lo ? lo_prec : -1);
-    else
+                           (float*)Q + ldq, lo, lp);
+    else if (qbytes == 8)
         hipLaunchKernelGGL(k_lz_first<double>, dim3(z.NB), dim3(LZ_THREADS), 0, s, z.bt, x, w, z.scal, (double*)Q,
-                           (double*)Q + z.ntot, lo, lo ? lo_prec : -1);
+                           (double*)Q + ldq, lo, lp);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

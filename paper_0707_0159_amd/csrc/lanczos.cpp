@@ -10,7 +10,8 @@
 //             inputs, FP32 accumulation), reorthogonalisation by classical
 //             Gram-Schmidt twice in FP64, the lowest eigenpair of the k x k
 //             tridiagonal on the device, x_{j+1} = Q y / |Q y| with q_0 = x_j
-//             taken in FP64 (the basis is stored in FP32 below FP64).
+//             taken in FP64 (below FP64 the basis is stored in the products'
+//             input precision).
 // The fixed point is an eigenvector of the FP64 operator because the residual
 // that drives every restart is computed with the FP64 Hv.
 //
@@ -39,7 +40,7 @@ void free_lanczos_work(d2d_ctx* c, LanczosWork*& lw) {
         if (lw->graph[p]) (void)hipGraphDestroy(lw->graph[p]);
     }
     const size_t nt = (size_t)lw->ntot;
-    c->free(lw->Q, (size_t)(lw->kmax + 1) * nt * 8);
+    c->free(lw->Q, (size_t)(lw->kmax + 1) * lw->ldq * 8);
     c->free(lw->X, nt * 8);
     c->free(lw->W, nt * 8);
     c->free(lw->wlo, nt * 4);
@@ -99,7 +100,9 @@ d2d_status ensure_lanczos_work(d2d_ctx* c, LanczosWork*& lw, const std::vector<i
         off += len[p];
     }
     const size_t nt = (size_t)ntot;
-    D2D_CHECK(c->alloc((void**)&w->Q, (size_t)(kmax + 1) * nt * 8));
+    // every basis vector starts on a 128-byte boundary (64 elements of 2 bytes or more)
+    w->ldq = (ntot + 63) / 64 * 64;
+    D2D_CHECK(c->alloc((void**)&w->Q, (size_t)(kmax + 1) * w->ldq * 8));
     D2D_CHECK(c->alloc((void**)&w->X, nt * 8));
     D2D_CHECK(c->alloc((void**)&w->W, nt * 8));
     D2D_CHECK(c->alloc((void**)&w->wlo, nt * 4));
@@ -155,22 +158,32 @@ d2d_status residual_step(LanczosWork* w, HvOps& hv, hipStream_t s) {
     return D2D_OK;
 }
 
+// Bytes per basis element: basis 0 stores the basis in the products' input
+// precision (FP64, FP32 for FP32 and BF16x3, BF16 for BF16), 1 in FP64, 2 in
+// FP32 below FP64.
+int basis_bytes(int prec, int basis) {
+    if (prec == D2D_FP64 || basis == 1) return 8;
+    if (prec == D2D_BF16 && basis == 0) return 2;
+    return 4;
+}
+
 // One inner Lanczos of k vectors from X (after residual_step); X <- Ritz vector.
-// Below FP64 the basis is stored in FP32 unless basis64: X enters the Ritz
-// vector in FP64, so the rounding of the basis only touches the correction
-// sum_{j>=1} y_j q_j, which shrinks with the residual.  An FP32 basis vector
-// is the FP32 and BF16x3 products' input itself; BF16 reads its own copy.
+// X enters the Ritz vector in FP64, so the rounding of a narrow basis only
+// touches the correction sum_{j>=1} y_j q_j, which shrinks with the residual.
+// A basis vector in the products' input precision is the product's input
+// itself; otherwise the step writes an input copy (lo).
 d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool fused, bool plain_cgs2,
-                      bool basis64, hipStream_t s) {
+                      int basis, hipStream_t s) {
     const LzSet z = set_of(w);
-    const int64_t N = w->ntot;
-    const bool q32 = prec != D2D_FP64 && !basis64;
-    const size_t qs = q32 ? 4 : 8;
+    const int64_t ldq = w->ldq;
+    const int qb = basis_bytes(prec, basis);
+    const size_t qs = (size_t)qb;
     char* Q = (char*)w->Q;
-    void* lo = prec == D2D_FP64 || (q32 && prec != D2D_BF16) ? nullptr : (void*)w->vlo;
-    D2D_HIP(launch_lz_first(z, w->X, w->W, Q, q32, lo, prec, s));
+    const int in_bytes = prec == D2D_FP64 ? 8 : (prec == D2D_BF16 ? 2 : 4);
+    void* lo = qb == in_bytes ? nullptr : (void*)w->vlo;
+    D2D_HIP(launch_lz_first(z, w->X, w->W, Q, qb, ldq, lo, prec, s));
     for (int i = 1; i < k; ++i) {
-        const void* qi = Q + (size_t)i * N * qs;
+        const void* qi = Q + (size_t)i * ldq * qs;
         // fused GEMM + central launch; the step's first kernel adds the parts
         HvParts parts{};
         const void* hin = lo ? (const void*)lo : qi;
@@ -181,9 +194,9 @@ d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bo
         a.bt = z.bt;
         // projection against q_{i-nq+1} .. q_i (all of them for full reorthogonalisation)
         const int nq = window >= 2 ? std::min(i + 1, window) : i + 1;
-        a.Q = Q + (size_t)(i + 1 - nq) * N * qs;
-        a.q32 = q32;
-        a.ldq = N;
+        a.Q = Q + (size_t)(i + 1 - nq) * ldq * qs;
+        a.qbytes = qb;
+        a.ldq = ldq;
         a.nq = nq;
         a.i = i;
         a.upcast = prec != D2D_FP64;
@@ -196,13 +209,13 @@ d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bo
         a.partial2 = z.partial2;
         a.NB = z.NB;
         a.scal = z.scal;
-        a.qnext = i + 1 < k ? (void*)(Q + (size_t)(i + 1) * N * qs) : nullptr;
+        a.qnext = i + 1 < k ? (void*)(Q + (size_t)(i + 1) * ldq * qs) : nullptr;
         a.lo = lo;
         a.lo_prec = prec;
         D2D_HIP(launch_lz_step(a, s));
     }
     D2D_HIP(launch_lz_tridiag(z, k, s));
-    D2D_HIP(launch_lz_ritz(z, Q, q32, k, w->X, s));
+    D2D_HIP(launch_lz_ritz(z, Q, qb, ldq, k, w->X, s));
     return D2D_OK;
 }
 
@@ -216,9 +229,9 @@ void drop_graphs(LanczosWork* w) {
 }
 
 d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, bool full, int window, bool fused,
-                   bool plain_cgs2, bool basis64, bool use_graph, hipStream_t s) {
+                   bool plain_cgs2, int basis, bool use_graph, hipStream_t s) {
     if (!use_graph || s == nullptr) {
-        D2D_CHECK(inner_loop(w, hv, prec, k, window, fused, plain_cgs2, basis64, s));
+        D2D_CHECK(inner_loop(w, hv, prec, k, window, fused, plain_cgs2, basis, s));
         D2D_CHECK(residual_step(w, hv, s));
         hv.count(prec, k - 1);
         hv.count(D2D_FP64, 1);
@@ -233,7 +246,7 @@ d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, bool full, int wi
         D2D_CHECK(hv.prepare(prec));          // launch tables exist before capture
         D2D_CHECK(hv.prepare(D2D_FP64));
         D2D_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        d2d_status st = inner_loop(w, hv, prec, k, window, fused, plain_cgs2, basis64, s);
+        d2d_status st = inner_loop(w, hv, prec, k, window, fused, plain_cgs2, basis, s);
         if (st == D2D_OK) st = residual_step(w, hv, s);
         hipGraph_t gr = nullptr;
         hipError_t e = hipStreamEndCapture(s, &gr);
@@ -268,11 +281,11 @@ d2d_status check_lanczos_opts(const d2d_lanczos_opts* o) {
         !(o->tol_res > 0.0) || o->prec < 0 || o->prec >= D2D_NPREC || o->reorth_window < 0 ||
         o->reorth_window == 1 || o->reorth_window > 32 || o->separate_central < 0 ||
         o->separate_central > 1 || !(o->tol_rel_e >= 0.0) || o->plain_cgs2 < 0 || o->plain_cgs2 > 1 ||
-        o->basis_fp64 < 0 || o->basis_fp64 > 1 || o->fixed_cycles < 0 || o->fixed_cycles > 1) {
+        o->basis < 0 || o->basis > 2 || o->fixed_cycles < 0 || o->fixed_cycles > 1) {
         set_error("Lanczos options: k_in and k_in_bf16 (0 or) 2..128 (2..32 with full reorthogonalisation), "
                   "max_restarts >= 0, "
                   "tol_res > 0, prec 0..3, reorth_window 0 or 2..32, "
-                  "separate_central 0 or 1, tol_rel_e >= 0, plain_cgs2 0 or 1, basis_fp64 0 or 1, "
+                  "separate_central 0 or 1, tol_rel_e >= 0, plain_cgs2 0 or 1, basis 0..2, "
                   "fixed_cycles 0 or 1");
         return D2D_EINVAL;
     }
@@ -435,7 +448,7 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
             k = std::min(kfull, need);
         }
         D2D_CHECK(restart(w, hv, prec, k, k == kfull, opts->reorth_window, opts->separate_central == 0,
-                          opts->plain_cgs2 != 0, opts->basis_fp64 != 0, opts->use_graph != 0, s));
+                          opts->plain_cgs2 != 0, opts->basis, opts->use_graph != 0, s));
         for (int p = 0; p < np; ++p)
             if (a[p]) {
                 hvc[p][prec] += k - 1;

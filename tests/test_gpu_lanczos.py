@@ -20,7 +20,7 @@ def ctx():
     d2d.d2d_ctx_destroy(c)
 
 
-def run(ctx, prob, prec, seed, k_in=24, graph=1, tol=1e-9, window=0, separate=0, plain=0, basis64=0):
+def run(ctx, prob, prec, seed, k_in=24, graph=1, tol=1e-9, window=0, separate=0, plain=0, basis=0):
     from paper_0707_0159_amd import d2d
     n = prob.info["n"]
     with torch.cuda.stream(ctx.stream):
@@ -29,7 +29,7 @@ def run(ctx, prob, prec, seed, k_in=24, graph=1, tol=1e-9, window=0, separate=0,
     ctx.stream.synchronize()
     opts = d2d.lanczos_opts(prec=prec, k_in=k_in, max_restarts=300, tol_res=tol, use_graph=graph,
                             reorth_window=window, separate_central=separate, plain_cgs2=plain,
-                            basis_fp64=basis64)
+                            basis=basis)
     st, e, stats = d2d.d2d_lanczos(prob.sb, opts, v0, psi)
     ctx.stream.synchronize()
     return st, e, stats, psi.cpu().numpy()
@@ -71,22 +71,36 @@ def test_config2_energy(ctx, prec, window, plain):
 
 @pytest.mark.parametrize("prec", [1, 2, 3])
 @pytest.mark.parametrize("window", [0, 3])
-def test_basis_storage_fp32_and_fp64(ctx, prec, window):
-    """The inner basis in FP32 (the default below FP64) and in FP64 both reach
-    the oracle's energy, and the FP32 basis's Ritz vector is an eigenvector of
-    the oracle's operator to the residual bar: the start vector enters the
-    Ritz vector in FP64, so the storage rounding only touches the correction."""
+def test_basis_storage(ctx, prec, window):
+    """The inner basis in the products' input precision (the default: FP32,
+    BF16 for BF16 products), in FP64 and in FP32: every low precision reaches
+    the oracle's energy, and the Ritz vector is an eigenvector of the oracle's
+    operator to the residual bar (the start vector enters the Ritz vector in
+    FP64, so the storage rounding only touches the correction)."""
     wl = W.CONFIGS[1]
     prob = GpuProblem(ctx, wl, prec_mask=15)
     E0 = reference_energy(wl.name)
     osb = oracle_superblock(wl)
-    for basis64 in (0, 1):
-        st, e, stats, psi = run(ctx, prob, prec, wl.seed, window=window, basis64=basis64)
-        print("basis", prec, window, basis64, e, E0, stats["restarts"], stats["hv_count"])
+    for basis in (0, 1, 2):
+        st, e, stats, psi = run(ctx, prob, prec, wl.seed, window=window, basis=basis)
+        print("basis", prec, window, basis, e, E0, stats["restarts"], stats["hv_count"])
         assert st == 0
         assert abs(e - E0) <= 1e-10 * abs(E0)
         r = osb.hv_explicit(psi) - e * psi
         assert np.linalg.norm(r) <= 1e-8 * abs(E0)
+    prob.close()
+
+
+@pytest.mark.parametrize("basis", [0, 1, 2])
+def test_config2_bf16_basis(ctx, basis):
+    """Config 2 in BF16 with each basis storage: the oracle's energy, with
+    the default fitted cycles and the window of the benchmark."""
+    wl = W.CONFIGS[2]
+    prob = GpuProblem(ctx, wl, prec_mask=15)
+    E0 = reference_energy(wl.name)
+    st, e, stats, _ = run(ctx, prob, 2, wl.seed, window=3, tol=1e-8, basis=basis)
+    print("config2 bf16 basis", basis, e, stats["restarts"], stats["hv_count"], stats["log_prec"])
+    assert st == 0 and abs(e - E0) <= 1e-10 * abs(E0)
     prob.close()
 
 
@@ -162,13 +176,14 @@ def test_last_cycle_fits_the_residual_bar(ctx, prec):
 
 
 def test_fp64_solve_ignores_basis_option(ctx):
-    """At FP64 the basis is FP64 whatever basis_fp64 says: identical iterates."""
+    """At FP64 the basis is FP64 whatever the basis option says: identical iterates."""
     wl = W.CONFIGS[1]
     prob = GpuProblem(ctx, wl)
-    (s0, e0, st0, p0), (s1, e1, st1, p1) = [run(ctx, prob, 0, wl.seed, window=3, basis64=b) for b in (0, 1)]
-    assert s0 == 0 and s1 == 0 and e0 == e1
-    assert np.array_equal(np.asarray(st0["log_theta"]), np.asarray(st1["log_theta"]))
-    assert np.array_equal(p0, p1)
+    out = [run(ctx, prob, 0, wl.seed, window=3, basis=b) for b in (0, 1, 2)]
+    for s1, e1, st1, p1 in out:
+        assert s1 == 0 and e1 == out[0][1]
+        assert np.array_equal(np.asarray(st1["log_theta"]), np.asarray(out[0][2]["log_theta"]))
+        assert np.array_equal(p1, out[0][3])
     prob.close()
 
 
@@ -266,8 +281,8 @@ def test_escalation_from_bf16_on_a_rising_energy(ctx):
     """A 12-site ladder (dimension 924) in BF16 with an FP64 inner basis: a
     restart's Ritz vector has a higher FP64 Rayleigh quotient than its start,
     which only the BF16 error can cause, so the precision moves on to BF16x3;
-    the energy still meets the bar.  (With the default FP32 basis this seed's
-    BF16 restarts happen not to rise, and the solve stays in BF16.)"""
+    the energy still meets the bar.  (With an FP32 basis this seed's BF16
+    restarts happen not to rise, and the solve stays in BF16.)"""
     from paper_0707_0159_amd import d2d
     wl = W.config5()[15]
     prob = GpuProblem(ctx, wl, prec_mask=15)
@@ -275,7 +290,7 @@ def test_escalation_from_bf16_on_a_rising_energy(ctx):
     with torch.cuda.stream(ctx.stream):
         v0 = torch.as_tensor(W.random_vector(prob.info["n"], wl.seed)).to("cuda")
     ctx.stream.synchronize()
-    opts = d2d.lanczos_opts(prec=2, k_in=24, max_restarts=300, tol_res=1e-8, reorth_window=3, basis_fp64=1,
+    opts = d2d.lanczos_opts(prec=2, k_in=24, max_restarts=300, tol_res=1e-8, reorth_window=3, basis=1,
                             fixed_cycles=1)
     st, e, stats = d2d.d2d_lanczos(prob.sb, opts, v0)
     E0 = reference_energy(wl.name)
