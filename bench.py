@@ -256,7 +256,8 @@ def bench_batch(args):
         return {"t_min_ms": (t_hv + t_vec) * 1e3, "hv_ms": t_hv * 1e3, "lanczos_vectors_ms": t_vec * 1e3}
 
     def solve(prec):
-        opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol, use_graph=1,
+        opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol,
+                                use_graph=1 if args.graph else 0,
                                 reorth_window=args.window, basis=args.basis,
                                 k_in_bf16=args.k_in_bf16, fixed_cycles=int(args.fixed_cycles))
         st, e, per = d2d.d2d_batch_lanczos(b, opts, v0)
@@ -326,7 +327,8 @@ def bench_batch(args):
                                f"{len(wls)} problems, 6 columns, m 64..512)",
                    "N_sb_total": sum(i["n"] for i in infos), "N_sb_max": max(i["n"] for i in infos),
                    "k_in": args.k_in, "k_in_bf16": args.k_in_bf16,
-                   "fixed_cycles": bool(args.fixed_cycles), "reorth_window": args.window,
+                   "fixed_cycles": bool(args.fixed_cycles), "graphs": bool(args.graph),
+                   "reorth_window": args.window,
                    "tol_res": args.tol,
                    "inner_basis": basis_name(args), "parallelism": "none (1 GPU)"},
         "time_to_energy": {"mixed_fp32": head, "mixed_bf16": bf16, "mixed_bf16x3": bf16x3, "fp64": fp64,
@@ -359,6 +361,8 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--k-in", type=int, default=48, help="Krylov dimension per restart")
     ap.add_argument("--k-in-bf16", type=int, default=24, help="Krylov dimension of BF16 cycles (0: --k-in)")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture each restart in a hipGraph and replay it (default: direct launches)")
     ap.add_argument("--fixed-cycles", action="store_true",
                     help="every cycle full length (default: the last cycle fitted to the residual bar)")
     ap.add_argument("--window", type=int, default=3, help="reorthogonalisation window (0 = full)")
@@ -449,7 +453,8 @@ def main():
         return
 
     def solve(prec):
-        opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol, use_graph=1,
+        opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol,
+                                use_graph=1 if args.graph else 0,
                                 reorth_window=args.window, basis=args.basis,
                                 k_in_bf16=args.k_in_bf16, fixed_cycles=int(args.fixed_cycles))
         st, e, stats = d2d.d2d_lanczos(sb, opts, v0, psi)
@@ -550,7 +555,8 @@ def main():
         "config": {"workload": wl.name, "description": wl.description, "N_sb": N,
                    "sector_pairs": info["npairs"], "m": info["m"], "column_dim": info["ncol"],
                    "central_terms": info["nterms"], "k_in": args.k_in, "k_in_bf16": args.k_in_bf16,
-                   "fixed_cycles": bool(args.fixed_cycles), "reorth_window": args.window,
+                   "fixed_cycles": bool(args.fixed_cycles), "graphs": bool(args.graph),
+                   "reorth_window": args.window,
                    "tol_res": args.tol, "inner_basis": basis_name(args), "tiles": tuned,
                    "parallelism": "none (1 GPU)"},
         "precision_schedule": "inner Hv FP32 MFMA (FP32 accumulate); FP64 Lanczos scalars, reorthogonalisation "

@@ -318,7 +318,11 @@ typedef struct {
     int max_restarts;
     double tol_res;      /* relative residual |r|/|theta|                      */
     double escalate;     /* precision raise threshold on rho_{j+1}/rho_j        */
-    int use_graph;       /* capture the inner loop in a hipGraph and replay it */
+    int use_graph;       /* 1: capture each restart (its cycle and the FP64
+                            residual) in a hipGraph and replay it; 0: launch
+                            the kernels directly.  The capture is made anew
+                            in every call, so it pays only where the host's
+                            launches would not stay ahead of the device   */
     int reorth_window;   /* 0: reorthogonalise against every basis vector (full);
                             w in 2..32: only against the last w vectors (the FP64
                             restarts keep the fixed point exact either way)   */

@@ -337,7 +337,7 @@ def d2d_tile_shapes():
     return [tuple(desc[5 * i:5 * i + 5]) for i in range(n.value)]
 
 
-def lanczos_opts(prec=D2D_FP64, k_in=24, max_restarts=200, tol_res=1e-9, escalate=0.5, use_graph=1,
+def lanczos_opts(prec=D2D_FP64, k_in=24, max_restarts=200, tol_res=1e-9, escalate=0.5, use_graph=0,
                  reorth_window=0, separate_central=0, tol_rel_e=0.0, seed=0, plain_cgs2=0, basis=0,
                  k_in_bf16=0, fixed_cycles=0):
     return d2d_lanczos_opts(int(prec), int(k_in), int(max_restarts), float(tol_res), float(escalate),

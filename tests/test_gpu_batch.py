@@ -137,7 +137,8 @@ def test_batch_lanczos_energies(ctx, prec):
         for i, p in enumerate(probs):
             v0.append(torch.as_tensor(W.random_vector(p.info["n"], 100 + i)).to("cuda"))
     ctx.stream.synchronize()
-    st, e, per = d2d.d2d_batch_lanczos(b, d2d.lanczos_opts(prec=prec, k_in=24, tol_res=1e-9), v0)
+    # restarts captured in hipGraphs here (the other batch solves launch directly)
+    st, e, per = d2d.d2d_batch_lanczos(b, d2d.lanczos_opts(prec=prec, k_in=24, tol_res=1e-9, use_graph=1), v0)
     print("batch", prec, e, refs, [q["restarts"] for q in per])
     assert st == 0
     for ei, ri in zip(e, refs):
