@@ -1,4 +1,5 @@
-// FP64 Lanczos vector kernels and the tridiagonal eigensolver for gfx950.
+// Lanczos vector kernels (FP64 arithmetic on a basis stored in FP64, FP32 or
+// BF16) and the tridiagonal eigensolver for gfx950.
 //
 // Scalars (alpha, beta, projection coefficients, norms) stay in device memory
 // so that a Lanczos inner loop runs without any host round trip.
