@@ -91,6 +91,24 @@ def test_basis_storage(ctx, prec, window):
     prob.close()
 
 
+@pytest.mark.parametrize("prec", [1, 2, 3])
+def test_odd_length_basis(ctx, prec):
+    """An odd packed length (config 1's blocks in the 8-up sector, 495
+    states): basis vectors of 2 or 4 bytes start on padded strides, and the
+    BF16 central-term gathers read whole aligned words; the energy equals the
+    lowest eigenvalue of the oracle's explicit matrix of that sector."""
+    wl = W.CONFIGS[1]
+    tgt = (8, 0)
+    prob = GpuProblem(ctx, wl, target=tgt, prec_mask=15)
+    assert prob.info["n"] == 495
+    E0 = float(np.linalg.eigvalsh(oracle_superblock(wl, tgt).explicit().toarray())[0])
+    for basis in (0, 2):
+        st, e, stats, _ = run(ctx, prob, prec, wl.seed, window=3, tol=1e-9, basis=basis)
+        print("odd length", prec, basis, e, E0, stats["restarts"], stats["hv_count"])
+        assert st == 0 and abs(e - E0) <= 1e-10 * abs(E0)
+    prob.close()
+
+
 @pytest.mark.parametrize("basis", [0, 1, 2])
 def test_config2_bf16_basis(ctx, basis):
     """Config 2 in BF16 with each basis storage: the oracle's energy, with
