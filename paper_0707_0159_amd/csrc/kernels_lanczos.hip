@@ -279,14 +279,16 @@ int lz_step_blocks(int64_t n) {
 }
 
 // out_sh[j] = sum_{b in [b0,b1)} partial[j*NB + b], j < rows (shared result).
+// Always inlined: as a call it made every caller reserve the registers of its
+// unrolled loads (246, two waves per SIMD).
 // A problem has at most LZ_STEP_NB blocks, so a lane adds at most
 // LZ_STEP_NB / 64 partials of a row; all of them are loaded at once (index
 // clamped into the problem's range, the extra values masked afterwards), so
 // the sum costs one memory latency, not one per partial.
 // When the problem has at most 512 blocks, a wave loads the partials of up to
 // four of its rows together (8 per lane and row) before adding any.
-__device__ inline void reduce_rows(const double* __restrict__ partial, int rows, int NB, int b0, int b1,
-                                   double* out_sh) {
+__device__ __attribute__((always_inline)) inline void reduce_rows(const double* __restrict__ partial, int rows,
+                                                                  int NB, int b0, int b1, double* out_sh) {
     constexpr int R = LZ_STEP_NB / 64;
     constexpr int NW = LZ_THREADS / 64;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -598,9 +600,9 @@ k_lz_next(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q,
 // read of the window: c2 = c1 - G c1, d = c1 + c2, and
 // |w - Q d|^2 = |w|^2 - 2 d.c1 + d^T G d.  Partial rows (fixed layout):
 // c1 in 0..NQ-1, |w|^2 in NQ, G_jl (j <= l) from NQ+1 on.
-// Elements a thread keeps in flight per round in the Gram kernels: with about
-// 2048 elements per block, a block covers its segment in one round of loads.
-static constexpr int GRAM_U = 8;
+// Elements a thread keeps in flight per round in the Gram kernels (8 ran no
+// faster and cost the first kernel a wave of occupancy).
+static constexpr int GRAM_U = 4;
 
 template <int NQ>
 struct GramLayout {
