@@ -442,8 +442,9 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
                     need = kfull;
                     break;
                 }
+                // (capped before the conversion: a tiny rate gives a huge count)
                 const double steps = std::log10(rho[p] / bar) / rate[p];
-                need = std::max(need, (int)std::ceil(1.25 * steps) + 5);
+                need = std::max(need, (int)std::min<double>(kfull, std::ceil(1.25 * steps) + 5));
             }
             k = std::min(kfull, need);
         }
