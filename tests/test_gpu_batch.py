@@ -137,12 +137,20 @@ def test_batch_lanczos_energies(ctx, prec):
         for i, p in enumerate(probs):
             v0.append(torch.as_tensor(W.random_vector(p.info["n"], 100 + i)).to("cuda"))
     ctx.stream.synchronize()
-    # restarts captured in hipGraphs here (the other batch solves launch directly)
-    st, e, per = d2d.d2d_batch_lanczos(b, d2d.lanczos_opts(prec=prec, k_in=24, tol_res=1e-9, use_graph=1), v0)
-    print("batch", prec, e, refs, [q["restarts"] for q in per])
-    assert st == 0
-    for ei, ri in zip(e, refs):
-        assert abs(ei - ri) <= 1e-10 * abs(ri)
+    # restarts captured in hipGraphs here (the other batch solves launch
+    # directly); full cycles, then the last cycle fitted to the residual bar
+    # (its own graph): both meet every energy, the fitted one with no more
+    # products
+    total = {}
+    for fixed in (1, 0):
+        opts = d2d.lanczos_opts(prec=prec, k_in=24, tol_res=1e-9, use_graph=1, fixed_cycles=fixed)
+        st, e, per = d2d.d2d_batch_lanczos(b, opts, v0)
+        print("batch", prec, fixed, e, refs, [q["restarts"] for q in per], [sum(q["hv_count"]) for q in per])
+        assert st == 0
+        for ei, ri in zip(e, refs):
+            assert abs(ei - ri) <= 1e-10 * abs(ri)
+        total[fixed] = sum(sum(q["hv_count"]) for q in per)
+    assert total[0] <= total[1]
     d2d.d2d_batch_destroy(b)
     for p in probs:
         p.close()
