@@ -16,11 +16,14 @@ per precision; the roofline of the dominant kernel (the grouped GEMM, timed
 with HIP events on the stream it runs on) and of the BF16 GEMM; and the CPU
 oracle's Hv rate on the host cores.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME | --config I]
 
---config 5 runs the batch of 64 uneven superblocks instead (one grouped
-launch per Lanczos step over every problem; value = problem Hv applications
-per second, summed over the batch).
+The default workload is the 2x16 Hubbard ladder (m = 256).  --config indexes
+the benchmark set in its fixed order (1 heisenberg_2x6_m16, 2
+hubbard_2x16_U8_m256, 3 hubbard_3x12_U4_N33_m400, 4 heisenberg_4x16_m1000,
+5 batch64); batch64 runs the batch of 64 uneven superblocks instead (one
+grouped launch per Lanczos step over every problem; value = problem Hv
+applications per second, summed over the batch).
 """
 from __future__ import annotations
 
@@ -209,7 +212,7 @@ def bench_batch(args):
     import workloads as W
     from paper_0707_0159_amd import d2d
 
-    wls = W.config5()
+    wls = W.batch64()
     ref_path = os.path.join(ROOT, "tests", "golden", "reference_energies.json")
     refs = {}
     if os.path.exists(ref_path):
@@ -358,7 +361,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
+                    help="workload by its index in the benchmark set (see the module docstring)")
+    ap.add_argument("--workload", default=None,
+                    help="workload by name (overrides --config): a single superblock's name or batch64")
     ap.add_argument("--k-in", type=int, default=48, help="Krylov dimension per restart")
     ap.add_argument("--k-in-bf16", type=int, default=24, help="Krylov dimension of BF16 cycles (0: --k-in)")
     ap.add_argument("--graph", action="store_true",
@@ -398,10 +404,14 @@ def main():
         print(json.dumps({"profile": "copy", "bytes_read_per_launch": nbytes, "bytes_written_per_launch": nbytes}))
         return
 
-    if args.config == 5:
+    name = args.workload or W.BENCH_SET[args.config - 1]
+    if name == "batch64":
         bench_batch(args)
         return
-    wl = W.CONFIGS[args.config]
+    if name not in W.WORKLOADS:
+        print(f"unknown workload {name}; known: {', '.join(W.BENCH_SET)}", file=sys.stderr)
+        sys.exit(2)
+    wl = W.WORKLOADS[name]
     ref_path = os.path.join(ROOT, "tests", "golden", "reference_energies.json")
     E0 = None
     if os.path.exists(ref_path):

@@ -4,8 +4,8 @@ Runs the oracle's infinite-system growth (float64, CPU) and stores the final
 blocks 1 and 4 under ``workloads/blocks/<name>.npz`` together with a JSON log
 of every growth step.  Calls nothing outside ``oracle/`` and ``workloads``.
 
-    python -m oracle.make_blocks --config 2
-    python -m oracle.make_blocks --config 5 --problems 0-7
+    python -m oracle.make_blocks --workload hubbard_2x16_U8_m256
+    python -m oracle.make_blocks --workload batch64 --problems 0-7
 """
 from __future__ import annotations
 
@@ -48,12 +48,12 @@ def build(wl: W.Workload, tol=1e-10, verbose=True):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--config", type=int, required=True)
-    ap.add_argument("--problems", default=None, help="config 5 only: a-b range")
+    ap.add_argument("--workload", required=True, choices=sorted(W.WORKLOADS) + ["batch64"])
+    ap.add_argument("--problems", default=None, help="batch64 only: a-b range")
     ap.add_argument("--tol", type=float, default=1e-10)
     args = ap.parse_args()
-    if args.config == 5:
-        probs = W.config5()
+    if args.workload == "batch64":
+        probs = W.batch64()
         if args.problems:
             a, b = (int(x) for x in args.problems.split("-"))
             probs = probs[a:b + 1]
@@ -62,7 +62,7 @@ def main():
                 continue
             build(wl, tol=args.tol)
     else:
-        print(build(W.CONFIGS[args.config], tol=args.tol))
+        print(build(W.WORKLOADS[args.workload], tol=args.tol))
 
 
 if __name__ == "__main__":

@@ -11,7 +11,7 @@ with the oracle, and find its lowest eigenvalue in the target sector to about
 Writes ``tests/golden/reference_energies.json`` (merging with what is there).
 Calls only ``oracle/`` and ``workloads``.
 
-    python -m oracle.make_reference --config 1 2
+    python -m oracle.make_reference --workload heisenberg_2x6_m16 hubbard_2x16_U8_m256
 """
 from __future__ import annotations
 
@@ -61,14 +61,14 @@ def reference(wl: W.Workload, ncv=32):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--config", type=int, nargs="+", required=True)
+    ap.add_argument("--workload", nargs="+", required=True, choices=sorted(W.WORKLOADS) + ["batch64"])
     args = ap.parse_args()
     data = {}
     if os.path.exists(GOLDEN):
         with open(GOLDEN) as f:
             data = json.load(f)
-    for c in args.config:
-        wls = W.config5() if c == 5 else [W.CONFIGS[c]]
+    for name in args.workload:
+        wls = W.batch64() if name == "batch64" else [W.WORKLOADS[name]]
         for wl in wls:
             if wl.name in data and data[wl.name].get("block_hash") == W.block_file_hash(wl.name):
                 continue

@@ -22,10 +22,10 @@ def ctx():
 
 
 def mixed_problems(ctx):
-    return [GpuProblem(ctx, W.CONFIGS[1], prec_mask=15),
-            GpuProblem(ctx, W.CONFIGS[2], prec_mask=15),
-            GpuProblem(ctx, W.CONFIGS[1], target=(7, 0), prec_mask=15),
-            GpuProblem(ctx, W.CONFIGS[1], target=(2, 0), prec_mask=15)]
+    return [GpuProblem(ctx, W.HEISENBERG_2X6_M16, prec_mask=15),
+            GpuProblem(ctx, W.HUBBARD_2X16_M256, prec_mask=15),
+            GpuProblem(ctx, W.HEISENBERG_2X6_M16, target=(7, 0), prec_mask=15),
+            GpuProblem(ctx, W.HEISENBERG_2X6_M16, target=(2, 0), prec_mask=15)]
 
 
 def batch_vectors(ctx, probs, prec, seed):
@@ -107,7 +107,7 @@ def test_batch_autotune(ctx, prec):
     print("batch autotune", prec, hex(tile), ms)
     assert d2d.d2d_tile_shapes()[tile & 0xFFFF][0] == prec and ms > 0
     assert_batch_equals_single(ctx, b, probs, prec, tile, 700)
-    refs = [reference_energy(W.CONFIGS[1].name), reference_energy(W.CONFIGS[2].name)]
+    refs = [reference_energy(W.HEISENBERG_2X6_M16.name), reference_energy(W.HUBBARD_2X16_M256.name)]
     with torch.cuda.stream(ctx.stream):
         v0 = [torch.as_tensor(W.random_vector(p.info["n"], 100 + i)).to("cuda") for i, p in enumerate(probs)]
     ctx.stream.synchronize()
@@ -126,7 +126,7 @@ def test_batch_lanczos_energies(ctx, prec):
     probs = mixed_problems(ctx)
     b = d2d.d2d_batch_create(ctx, [p.sb for p in probs])
     refs = []
-    for p, wl, tgt in zip(probs, [W.CONFIGS[1], W.CONFIGS[2], W.CONFIGS[1], W.CONFIGS[1]],
+    for p, wl, tgt in zip(probs, [W.HEISENBERG_2X6_M16, W.HUBBARD_2X16_M256, W.HEISENBERG_2X6_M16, W.HEISENBERG_2X6_M16],
                           [None, None, (7, 0), (2, 0)]):
         if tgt is None:
             refs.append(reference_energy(wl.name))
@@ -156,13 +156,13 @@ def test_batch_lanczos_energies(ctx, prec):
         p.close()
 
 
-def config5_or_skip():
+def batch64_or_skip():
     import json
     import os
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "reference_energies.json")
     with open(path) as f:
         g = json.load(f)
-    wls = W.config5()
+    wls = W.batch64()
     missing = [wl.name for wl in wls if wl.name not in g]
     if missing:
         pytest.skip(f"reference energies not yet written for {len(missing)} batch problems")
@@ -170,11 +170,11 @@ def config5_or_skip():
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_config5_batch_energies(ctx, prec):
+def test_batch64_energies(ctx, prec):
     """64 uneven superblocks (2/3-leg Heisenberg and Hubbard, m 64..512) in one
     batch: every problem's ground energy within 1e-10 of the oracle's."""
     from paper_0707_0159_amd import d2d
-    wls, refs = config5_or_skip()
+    wls, refs = batch64_or_skip()
     probs = [GpuProblem(ctx, wl, prec_mask=7) for wl in wls]
     b = d2d.d2d_batch_create(ctx, [p.sb for p in probs])
     with torch.cuda.stream(ctx.stream):
@@ -183,7 +183,7 @@ def test_config5_batch_energies(ctx, prec):
     opts = d2d.lanczos_opts(prec=prec, k_in=24, max_restarts=400, tol_res=1e-8, reorth_window=3)
     st, e, per = d2d.d2d_batch_lanczos(b, opts, v0)
     dE = [abs(ei - refs[wl.name]) / abs(refs[wl.name]) for ei, wl in zip(e, wls)]
-    print(f"config5 prec {prec}: max dE {max(dE):.2e}, restarts max {max(q['restarts'] for q in per)}")
+    print(f"batch64 prec {prec}: max dE {max(dE):.2e}, restarts max {max(q['restarts'] for q in per)}")
     assert st == 0
     assert max(dE) <= 1e-10
     d2d.d2d_batch_destroy(b)
@@ -191,10 +191,10 @@ def test_config5_batch_energies(ctx, prec):
         p.close()
 
 
-def test_config5_sampled_hv_against_oracle(ctx):
+def test_batch64_sampled_hv_against_oracle(ctx):
     """Single-problem Hv of the smaller batch problems against the oracle (FP64 <= 1e-12)."""
     from test_gpu_hv import gpu_hv
-    wls = W.config5()
+    wls = W.batch64()
     done = 0
     for wl in wls:
         osb = oracle_superblock(wl)
@@ -206,14 +206,14 @@ def test_config5_sampled_hv_against_oracle(ctx):
         assert err <= 1e-12, (wl.name, err)
         prob.close()
         done += 1
-    print("config5 problems checked", done)
+    print("batch64 problems checked", done)
     assert done >= 16
 
 
 @pytest.fixture(scope="module")
-def config5_batch15(ctx):
+def batch64_fixture(ctx):
     from paper_0707_0159_amd import d2d
-    wls, refs = config5_or_skip()
+    wls, refs = batch64_or_skip()
     probs = [GpuProblem(ctx, wl, prec_mask=15) for wl in wls]
     b = d2d.d2d_batch_create(ctx, [p.sb for p in probs])
     yield wls, refs, probs, b
@@ -222,13 +222,13 @@ def config5_batch15(ctx):
         p.close()
 
 
-def test_config5_bf16_defers_only_the_problems_that_need_more(ctx, config5_batch15):
+def test_batch64_bf16_defers_only_the_problems_that_need_more(ctx, batch64_fixture):
     """BF16 batch of the 64 uneven superblocks: a problem whose BF16 restarts
     fall short (the small ladders, whose energy rises) waits and finishes in
     BF16x3 while the others stay in BF16 throughout; every energy within
     1e-10, and each problem's Hv count is the launches that included it."""
     from paper_0707_0159_amd import d2d
-    wls, refs, probs, b = config5_batch15
+    wls, refs, probs, b = batch64_fixture
     with torch.cuda.stream(ctx.stream):
         v0 = [torch.as_tensor(W.random_vector(p.info["n"], wl.seed)).to("cuda") for p, wl in zip(probs, wls)]
     ctx.stream.synchronize()
@@ -239,7 +239,7 @@ def test_config5_bf16_defers_only_the_problems_that_need_more(ctx, config5_batch
     dE = [abs(ei - refs[wl.name]) / abs(refs[wl.name]) for ei, wl in zip(e, wls)]
     raised = [i for i, q in enumerate(per) if max(q["log_prec"]) > d2d.D2D_BF16]
     kept = [i for i, q in enumerate(per) if set(q["log_prec"]) == {d2d.D2D_BF16}]
-    print(f"config5 bf16: max dE {max(dE):.2e}, raised {[(i, probs[i].info['n']) for i in raised]}, "
+    print(f"batch64 bf16: max dE {max(dE):.2e}, raised {[(i, probs[i].info['n']) for i in raised]}, "
           f"kept {len(kept)}")
     assert max(dE) <= 1e-10
     assert raised and kept

@@ -46,15 +46,15 @@ def gap_cut(spec, target):
     return target
 
 
-@pytest.mark.parametrize("cfg,target_m", [(1, 40), (2, 300)])
-def test_density_matrix_and_next_block(ctx, cfg, target_m):
+@pytest.mark.parametrize("name,target_m", [(W.HEISENBERG_2X6_M16.name, 40), (W.HUBBARD_2X16_M256.name, 300)])
+def test_density_matrix_and_next_block(ctx, name, target_m):
     from oracle.blockio import block_from_arrays
     from oracle.blocks import truncate_half
     from oracle.dmrg import reduced_density_matrices
     from oracle.superblock import Superblock
     from paper_0707_0159_amd import d2d
 
-    wl = W.CONFIGS[cfg]
+    wl = W.WORKLOADS[name]
     prob = GpuProblem(ctx, wl)
     osb = oracle_superblock(wl)
     psi = ground_state(ctx, prob, wl.seed)
@@ -88,8 +88,8 @@ def test_density_matrix_and_next_block(ctx, cfg, target_m):
     # next superblock (two more columns): same ground energy from either pair of blocks
     Q2 = wl.target_of_sites(wl.legs * (wl.length + 2))
     e_gpu = np.linalg.eigvalsh(Superblock(blocks[0][0], blocks[1][0], Q2).explicit().toarray())[0] \
-        if cfg == 1 else None
-    if cfg == 1:
+        if name == W.HEISENBERG_2X6_M16.name else None
+    if name == W.HEISENBERG_2X6_M16.name:
         e_or = np.linalg.eigvalsh(Superblock(blocks[0][1], blocks[1][1], Q2).explicit().toarray())[0]
         assert abs(e_gpu - e_or) <= 1e-10 * abs(e_or)
     prob.close()

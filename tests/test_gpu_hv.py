@@ -35,10 +35,10 @@ def gpu_hv(ctx, prob, prec, v):
     return wd.double().cpu().numpy()
 
 
-def test_config1_all_sectors_fp64_and_fp32(ctx):
+def test_heisenberg_2x6_all_sectors_fp64_and_fp32(ctx):
     """2x6 Heisenberg, exact m=16 blocks, every S_z sector of the 4096 space."""
     from paper_0707_0159_amd import d2d
-    wl = W.CONFIGS[1]
+    wl = W.HEISENBERG_2X6_M16
     worst = {0: 0.0, 1: 0.0}
     total = 0
     for nup in range(0, 13):
@@ -57,16 +57,16 @@ def test_config1_all_sectors_fp64_and_fp32(ctx):
                 worst[prec] = max(worst[prec], rel_err(gpu_hv(ctx, prob, prec, v), ref))
         total += nvec
         prob.close()
-    print("config1 worst rel err", worst)
+    print("heisenberg_2x6 worst rel err", worst)
     assert worst[0] <= 1e-12
     assert worst[1] <= 1e-5
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)])
-def test_config2_every_tile_shape(ctx, prec, tol):
+def test_hubbard_2x16_every_tile_shape(ctx, prec, tol):
     """2x16 Hubbard m=256: 47 sector pairs of ragged size, every tile shape."""
     from paper_0707_0159_amd import d2d
-    wl = W.CONFIGS[2]
+    wl = W.HUBBARD_2X16_M256
     osb = oracle_superblock(wl)
     prob = GpuProblem(ctx, wl)
     assert prob.info["n"] == osb.N
@@ -89,7 +89,7 @@ def test_config2_every_tile_shape(ctx, prec, tol):
 
 def test_sector_table_matches_oracle(ctx):
     from paper_0707_0159_amd import d2d
-    wl = W.CONFIGS[2]
+    wl = W.HUBBARD_2X16_M256
     osb = oracle_superblock(wl)
     prob = GpuProblem(ctx, wl)
     qL, dL, dR, off = d2d.d2d_sb_sectors(prob.sb)
@@ -102,7 +102,7 @@ def test_sector_table_matches_oracle(ctx):
 
 def test_repeatable_bitwise(ctx):
     """No atomics in the accumulation: repeated products are bit-identical."""
-    wl = W.CONFIGS[2]
+    wl = W.HUBBARD_2X16_M256
     prob = GpuProblem(ctx, wl)
     v = W.random_vector(prob.info["n"], 7)
     for prec in (0, 1):
@@ -179,12 +179,12 @@ def gpu_hv_bf16(ctx, prob, v):
     return wd.double().cpu().numpy()
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
-def test_bf16_every_tile_shape(ctx, cfg):
+@pytest.mark.parametrize("name", [W.HEISENBERG_2X6_M16.name, W.HUBBARD_2X16_M256.name])
+def test_bf16_every_tile_shape(ctx, name):
     """BF16 operands, FP32 accumulation: equal to the oracle on bf16-rounded
     operands up to FP32 accumulation (<= 1e-5), and within 2e-2 of the exact product."""
     from paper_0707_0159_amd import d2d
-    wl = W.CONFIGS[cfg]
+    wl = W.WORKLOADS[name]
     osb = oracle_superblock(wl)
     prob = GpuProblem(ctx, wl, prec_mask=7)
     shapes = [i | sp for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == d2d.D2D_BF16
@@ -200,19 +200,19 @@ def test_bf16_every_tile_shape(ctx, cfg):
             d2d.d2d_sb_set_tile(prob.sb, d2d.D2D_BF16, sh)
             w = gpu_hv_bf16(ctx, prob, v)
             e1, e2 = rel_err(w, ref_b), rel_err(w, ref)
-            print(f"config {cfg} bf16 shape {sh}: vs bf16-operand oracle {e1:.3e}, vs exact {e2:.3e}")
+            print(f"{name} bf16 shape {sh}: vs bf16-operand oracle {e1:.3e}, vs exact {e2:.3e}")
             assert e1 <= 1e-5
             assert e2 <= 2e-2
     prob.close()
 
 
-@pytest.mark.parametrize("cfg,target", [(1, (6, 0)), (1, (3, 0)), (2, None)])
-def test_pack_unpack_full_space(ctx, cfg, target):
+@pytest.mark.parametrize("name,target", [(W.HEISENBERG_2X6_M16.name, (6, 0)), (W.HEISENBERG_2X6_M16.name, (3, 0)), (W.HUBBARD_2X16_M256.name, None)])
+def test_pack_unpack_full_space(ctx, name, target):
     """d2d_pack / d2d_unpack against the oracle's index map of the paper's
     vector order (pure data movement: equal bit for bit; unpack zero-fills
     outside the target sector)."""
     from paper_0707_0159_amd import d2d
-    wl = W.CONFIGS[cfg]
+    wl = W.WORKLOADS[name]
     osb = oracle_superblock(wl, target)
     prob = GpuProblem(ctx, wl, target)
     D = osb.m * osb.n
@@ -231,13 +231,13 @@ def test_pack_unpack_full_space(ctx, cfg, target):
     prob.close()
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
-def test_bf16x3_every_tile_shape(ctx, cfg):
+@pytest.mark.parametrize("name", [W.HEISENBERG_2X6_M16.name, W.HUBBARD_2X16_M256.name])
+def test_bf16x3_every_tile_shape(ctx, name):
     """BF16x3 (hi/lo bf16 parts of FP32 operands, three products, FP32
     accumulation): equal to the oracle computing the same three products in
     float64 up to FP32 accumulation (<= 1e-5), and within 1e-4 of the exact product."""
     from paper_0707_0159_amd import d2d
-    wl = W.CONFIGS[cfg]
+    wl = W.WORKLOADS[name]
     osb = oracle_superblock(wl)
     prob = GpuProblem(ctx, wl, prec_mask=15)
     shapes = [i | sp for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == d2d.D2D_BF16X3
@@ -252,7 +252,7 @@ def test_bf16x3_every_tile_shape(ctx, cfg):
             d2d.d2d_sb_set_tile(prob.sb, d2d.D2D_BF16X3, sh)
             w = gpu_hv(ctx, prob, d2d.D2D_BF16X3, v)
             e1, e2 = rel_err(w, ref3), rel_err(w, ref)
-            print(f"config {cfg} bf16x3 shape {sh}: vs split-operand oracle {e1:.3e}, vs exact {e2:.3e}")
+            print(f"{name} bf16x3 shape {sh}: vs split-operand oracle {e1:.3e}, vs exact {e2:.3e}")
             worst = max(worst, e2)
             assert e1 <= 1e-5
             assert e2 <= 1e-4
@@ -291,7 +291,7 @@ def test_skipped_k_steps_add_nothing(ctx, prec):
     split K-loops and the XCD order too), and the flops the library reports
     for either are the oracle's count over the same steps."""
     from paper_0707_0159_amd import d2d
-    wl = W.CONFIGS[2]
+    wl = W.HUBBARD_2X16_M256
     osb = oracle_superblock(wl)
     prob = GpuProblem(ctx, wl, prec_mask=15)
     v = W.random_vector(osb.N, 1200 + prec)

@@ -37,12 +37,12 @@ def run(ctx, prob, prec, seed, k_in=24, graph=1, tol=1e-9, window=0, separate=0,
 
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("graph", [0, 1])
-def test_config1_energy(ctx, prec, graph):
-    wl = W.CONFIGS[1]
+def test_heisenberg_2x6_energy(ctx, prec, graph):
+    wl = W.HEISENBERG_2X6_M16
     prob = GpuProblem(ctx, wl)
     st, e, stats, psi = run(ctx, prob, prec, wl.seed, graph=graph)
     E0 = reference_energy(wl.name)
-    print("config1", prec, graph, e, E0, stats["restarts"], stats["hv_count"])
+    print("heisenberg_2x6", prec, graph, e, E0, stats["restarts"], stats["hv_count"])
     assert st == 0
     assert abs(e - E0) <= 1e-10 * abs(E0)
     # psi is an eigenvector of the oracle's operator
@@ -54,14 +54,14 @@ def test_config1_energy(ctx, prec, graph):
 
 @pytest.mark.parametrize("prec", [0, 1, 2, 3])
 @pytest.mark.parametrize("window,plain", [(0, 0), (3, 0), (3, 1), (2, 0), (4, 0)])
-def test_config2_energy(ctx, prec, window, plain):
+def test_hubbard_2x16_energy(ctx, prec, window, plain):
     """Full reorthogonalisation, and windows of 2..4 in the two-kernel Gram form
     and the three-kernel two-pass form."""
-    wl = W.CONFIGS[2]
+    wl = W.HUBBARD_2X16_M256
     prob = GpuProblem(ctx, wl, prec_mask=15)
     st, e, stats, psi = run(ctx, prob, prec, wl.seed, window=window, plain=plain)
     E0 = reference_energy(wl.name)
-    print("config2", prec, window, plain, e, E0, (e - E0) / abs(E0), stats["restarts"], stats["hv_count"],
+    print("hubbard_2x16", prec, window, plain, e, E0, (e - E0) / abs(E0), stats["restarts"], stats["hv_count"],
           stats["seconds"])
     assert st == 0
     assert abs(e - E0) <= 1e-10 * abs(E0)
@@ -77,7 +77,7 @@ def test_basis_storage(ctx, prec, window):
     the oracle's energy, and the Ritz vector is an eigenvector of the oracle's
     operator to the residual bar (the start vector enters the Ritz vector in
     FP64, so the storage rounding only touches the correction)."""
-    wl = W.CONFIGS[1]
+    wl = W.HEISENBERG_2X6_M16
     prob = GpuProblem(ctx, wl, prec_mask=15)
     E0 = reference_energy(wl.name)
     osb = oracle_superblock(wl)
@@ -93,11 +93,11 @@ def test_basis_storage(ctx, prec, window):
 
 @pytest.mark.parametrize("prec", [1, 2, 3])
 def test_odd_length_basis(ctx, prec):
-    """An odd packed length (config 1's blocks in the 8-up sector, 495
+    """An odd packed length (the 2x6 ladder's blocks in the 8-up sector, 495
     states): basis vectors of 2 or 4 bytes start on padded strides, and the
     BF16 central-term gathers read whole aligned words; the energy equals the
     lowest eigenvalue of the oracle's explicit matrix of that sector."""
-    wl = W.CONFIGS[1]
+    wl = W.HEISENBERG_2X6_M16
     tgt = (8, 0)
     prob = GpuProblem(ctx, wl, target=tgt, prec_mask=15)
     assert prob.info["n"] == 495
@@ -110,14 +110,14 @@ def test_odd_length_basis(ctx, prec):
 
 
 @pytest.mark.parametrize("basis", [0, 1, 2])
-def test_config2_bf16_basis(ctx, basis):
-    """Config 2 in BF16 with each basis storage: the oracle's energy, with
+def test_hubbard_2x16_bf16_basis(ctx, basis):
+    """The 2x16 Hubbard ladder in BF16 with each basis storage: the oracle's energy, with
     the default fitted cycles and the window of the benchmark."""
-    wl = W.CONFIGS[2]
+    wl = W.HUBBARD_2X16_M256
     prob = GpuProblem(ctx, wl, prec_mask=15)
     E0 = reference_energy(wl.name)
     st, e, stats, _ = run(ctx, prob, 2, wl.seed, window=3, tol=1e-8, basis=basis)
-    print("config2 bf16 basis", basis, e, stats["restarts"], stats["hv_count"], stats["log_prec"])
+    print("hubbard_2x16 bf16 basis", basis, e, stats["restarts"], stats["hv_count"], stats["log_prec"])
     assert st == 0 and abs(e - E0) <= 1e-10 * abs(E0)
     prob.close()
 
@@ -129,7 +129,7 @@ def test_krylov_size_limits(ctx, prec):
     up to 32.  k_in 33 with it, k_in 129, and a window of 33 are refused before
     any launch."""
     from paper_0707_0159_amd import d2d
-    wl = W.CONFIGS[2]
+    wl = W.HUBBARD_2X16_M256
     prob = GpuProblem(ctx, wl)
     E0 = reference_energy(wl.name)
     for k, win in ((64, 3), (32, 0)):
@@ -147,7 +147,7 @@ def test_bf16_cycles_use_their_own_krylov_size(ctx):
     adds k_in_bf16 - 1 products, any other precision k_in - 1, and the solve
     reaches the oracle's energy."""
     from paper_0707_0159_amd import d2d
-    wl = W.CONFIGS[2]
+    wl = W.HUBBARD_2X16_M256
     prob = GpuProblem(ctx, wl, prec_mask=15)
     with torch.cuda.stream(ctx.stream):
         v0 = torch.as_tensor(W.random_vector(prob.info["n"], wl.seed)).to("cuda")
@@ -172,7 +172,7 @@ def test_last_cycle_fits_the_residual_bar(ctx, prec):
     with fewer products than full cycles, and the inner products are no
     longer a multiple of k_in - 1; fixed_cycles 1 keeps every cycle full."""
     from paper_0707_0159_amd import d2d
-    wl = W.CONFIGS[2]
+    wl = W.HUBBARD_2X16_M256
     prob = GpuProblem(ctx, wl)
     E0 = reference_energy(wl.name)
     with torch.cuda.stream(ctx.stream):
@@ -195,7 +195,7 @@ def test_last_cycle_fits_the_residual_bar(ctx, prec):
 
 def test_fp64_solve_ignores_basis_option(ctx):
     """At FP64 the basis is FP64 whatever the basis option says: identical iterates."""
-    wl = W.CONFIGS[1]
+    wl = W.HEISENBERG_2X6_M16
     prob = GpuProblem(ctx, wl)
     out = [run(ctx, prob, 0, wl.seed, window=3, basis=b) for b in (0, 1, 2)]
     for s1, e1, st1, p1 in out:
@@ -213,7 +213,7 @@ def test_fused_central_is_bitwise_separate(ctx, prec, split):
     GEMM: same energies, restart logs and Ritz vector; for unsplit, split and
     halved K-loops."""
     from paper_0707_0159_amd import d2d
-    wl = W.CONFIGS[2]
+    wl = W.HUBBARD_2X16_M256
     prob = GpuProblem(ctx, wl, prec_mask=15)
     shape = next(i for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == prec)
     flag = [0, d2d.D2D_TILE_SPLIT, d2d.D2D_TILE_SPLIT4][split]
@@ -233,7 +233,7 @@ def test_seeded_start_vector(ctx):
     same vector generated on the host gives the same solve (same restarts,
     energies within rounding of the two log/cos implementations)."""
     from paper_0707_0159_amd import d2d
-    wl = W.CONFIGS[2]
+    wl = W.HUBBARD_2X16_M256
     prob = GpuProblem(ctx, wl)
     n = prob.info["n"]
     E0 = reference_energy(wl.name)
@@ -254,7 +254,7 @@ def test_seeded_start_vector(ctx):
 def test_energy_change_stop(ctx):
     """tol_rel_e: stop on successive FP64 Rayleigh quotients (residual bar out of reach)."""
     from paper_0707_0159_amd import d2d
-    wl = W.CONFIGS[2]
+    wl = W.HUBBARD_2X16_M256
     prob = GpuProblem(ctx, wl)
     E0 = reference_energy(wl.name)
     n = prob.info["n"]
@@ -277,7 +277,7 @@ def test_no_escalation_when_the_krylov_space_is_slow(ctx):
     lower the Rayleigh quotient and reach the residual the recurrence
     predicts, so BF16 is kept to the end."""
     from paper_0707_0159_amd import d2d
-    wl = W.CONFIGS[2]
+    wl = W.HUBBARD_2X16_M256
     prob = GpuProblem(ctx, wl, prec_mask=15)
     with torch.cuda.stream(ctx.stream):
         v0 = torch.as_tensor(W.random_vector(prob.info["n"], wl.seed)).to("cuda")
@@ -302,7 +302,7 @@ def test_escalation_from_bf16_on_a_rising_energy(ctx):
     the energy still meets the bar.  (With an FP32 basis this seed's BF16
     restarts happen not to rise, and the solve stays in BF16.)"""
     from paper_0707_0159_amd import d2d
-    wl = W.config5()[15]
+    wl = W.batch64()[15]
     prob = GpuProblem(ctx, wl, prec_mask=15)
     assert prob.info["n"] == 924
     with torch.cuda.stream(ctx.stream):
@@ -326,7 +326,7 @@ def test_escalation_from_bf16_on_a_rising_energy(ctx):
 
 def test_ferromagnetic_sector_breakdown(ctx):
     """1-dimensional sector: the start vector is an eigenvector, rho = 0 at once."""
-    wl = W.CONFIGS[1]
+    wl = W.HEISENBERG_2X6_M16
     prob = GpuProblem(ctx, wl, target=(12, 0))
     assert prob.info["n"] == 1
     st, e, stats, psi = run(ctx, prob, 0, 3)

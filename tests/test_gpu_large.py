@@ -26,9 +26,9 @@ def ctx():
     d2d.d2d_ctx_destroy(c)
 
 
-@pytest.fixture(scope="module", params=[3, 4])
+@pytest.fixture(scope="module", params=[W.HUBBARD_3X12_M400.name, W.HEISENBERG_4X16_M1000.name])
 def problem(request, ctx):
-    wl = W.CONFIGS[request.param]
+    wl = W.WORKLOADS[request.param]
     print(f"building {wl.name}", flush=True)
     osb = oracle_superblock(wl)
     prob = GpuProblem(ctx, wl, prec_mask=15)

@@ -24,7 +24,7 @@ from oracle.local import Model, make_column
 from oracle.superblock import Superblock
 
 CASES = [
-    (Model("heisenberg", 2, J=1.0), 2, (6, 0), 6),          # config 1 geometry
+    (Model("heisenberg", 2, J=1.0), 2, (6, 0), 6),          # the 2x6 ladder's geometry
     (Model("heisenberg", 2, J=1.0), 2, (7, 0), 6),
     (Model("heisenberg", 3, J=0.7), 1, (6, 0), 4),
     (Model("hubbard", 2, t=1.0, U=8.0), 1, (4, 4), 4),

@@ -100,7 +100,7 @@ class Workload:
         return (4 if self.kind == "hubbard" else 2) ** self.legs
 
 
-def _config5_problems():
+def _batch64_problems():
     """64 uneven superblocks: one default_rng(5) stream, drawn problem by problem."""
     rng = np.random.default_rng(5)
     out = []
@@ -110,32 +110,39 @@ def _config5_problems():
         m = int(rng.choice([64, 128, 256, 512]))
         U = float(rng.uniform(2.0, 10.0)) if kind == "hubbard" else 0.0
         tgt = _half_filling(legs) if kind == "hubbard" else _sz_zero(legs)
-        out.append(Workload(f"batch{i:02d}_{kind}_{legs}x{CONFIG5_LENGTH}_m{m}", kind, legs,
-                            CONFIG5_LENGTH, m, t=1.0, U=U, J=1.0, target_of_sites=tgt,
+        out.append(Workload(f"batch{i:02d}_{kind}_{legs}x{BATCH_LENGTH}_m{m}", kind, legs,
+                            BATCH_LENGTH, m, t=1.0, U=U, J=1.0, target_of_sites=tgt,
                             seed=100 + i))
     return out
 
 
-CONFIG5_LENGTH = 6
+BATCH_LENGTH = 6
 
-CONFIGS = {
-    1: Workload("heisenberg_2x6_m16", "heisenberg", 2, 6, 16, J=1.0, target_of_sites=_sz_zero(2),
-                description="2-leg Heisenberg ladder 2x6, exact blocks of two rungs (m=16), "
-                            "columns of dim 4, superblock dim 4096"),
-    2: Workload("hubbard_2x16_U8_m256", "hubbard", 2, 16, 256, t=1.0, U=8.0,
-                target_of_sites=_half_filling(2),
-                description="2-leg Hubbard ladder 2x16, t=1, U=8, half filling, m=256"),
-    3: Workload("hubbard_3x12_U4_N33_m400", "hubbard", 3, 12, 400, t=1.0, U=4.0,
-                target_of_sites=_doped_11_12,
-                description="3-leg Hubbard ladder 3x12, t=1, U=4, 33 electrons (17 up, 16 down), m=400"),
-    4: Workload("heisenberg_4x16_m1000", "heisenberg", 4, 16, 1000, J=1.0,
-                target_of_sites=_sz_zero(4),
-                description="4-leg Heisenberg ladder 4x16, J=1, S_z=0, m=1000"),
-}
+HEISENBERG_2X6_M16 = Workload("heisenberg_2x6_m16", "heisenberg", 2, 6, 16, J=1.0, target_of_sites=_sz_zero(2),
+                              description="2-leg Heisenberg ladder 2x6, exact blocks of two rungs (m=16), "
+                                          "columns of dim 4, superblock dim 4096")
+HUBBARD_2X16_M256 = Workload("hubbard_2x16_U8_m256", "hubbard", 2, 16, 256, t=1.0, U=8.0,
+                             target_of_sites=_half_filling(2),
+                             description="2-leg Hubbard ladder 2x16, t=1, U=8, half filling, m=256")
+HUBBARD_3X12_M400 = Workload("hubbard_3x12_U4_N33_m400", "hubbard", 3, 12, 400, t=1.0, U=4.0,
+                             target_of_sites=_doped_11_12,
+                             description="3-leg Hubbard ladder 3x12, t=1, U=4, 33 electrons (17 up, 16 down), m=400")
+HEISENBERG_4X16_M1000 = Workload("heisenberg_4x16_m1000", "heisenberg", 4, 16, 1000, J=1.0,
+                                 target_of_sites=_sz_zero(4),
+                                 description="4-leg Heisenberg ladder 4x16, J=1, S_z=0, m=1000")
+
+# the single-superblock workloads by name
+WORKLOADS = {w.name: w for w in (HEISENBERG_2X6_M16, HUBBARD_2X16_M256, HUBBARD_3X12_M400, HEISENBERG_4X16_M1000)}
+
+# the benchmark set in its fixed order (the benchmark's --config index 1..5;
+# 5 is the batch of 64 uneven superblocks)
+BENCH_SET = (HEISENBERG_2X6_M16.name, HUBBARD_2X16_M256.name, HUBBARD_3X12_M400.name,
+             HEISENBERG_4X16_M1000.name, "batch64")
 
 
-def config5():
-    return _config5_problems()
+def batch64():
+    """The 64 uneven superblocks of the batch workload."""
+    return _batch64_problems()
 
 
 def block_path(name: str) -> str:
