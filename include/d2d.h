@@ -348,6 +348,14 @@ typedef struct {
                             cycle reduced the residual at a rate that meets
                             tol_res in fewer steps (1.25 x those steps + 4);
                             1: every cycle has k_in (k_in_bf16) vectors     */
+    int one_kernel_step; /* 0: a step runs as its two kernels; 1: with a
+                            window of 2..4 and direct launches, a step runs as
+                            one cooperative kernel (sums, grid barrier, update
+                            from registers) where every block's share fits its
+                            registers and the grid fits the device.  Same
+                            result bit for bit; slower on MI355X, where a
+                            cooperative launch costs more than the launch and
+                            the re-read of the window it saves              */
 } d2d_lanczos_opts;
 
 #define D2D_LOG_MAX 256

@@ -88,6 +88,7 @@ struct LanczosWork {
     int64_t ntot = 0;
     std::vector<int64_t> seg_off, seg_len;
     int64_t ldq = 0;             // basis vector stride: ntot rounded up to 64 elements
+    int64_t max_seg = 0;         // longest block segment of the step kernels
     double* Q = nullptr;         // (kmax+1) x ldq doubles (or as many FP32 / BF16 elements)
     double* X = nullptr;
     double* W = nullptr;

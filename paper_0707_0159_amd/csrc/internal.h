@@ -216,6 +216,8 @@ struct LzStepArgs {
     int nq, i;
     bool upcast;
     int qbytes;
+    bool coop;              // the Gram step as one cooperative kernel (caller checked lz_coop_fits
+                            // and that no segment exceeds lz_coop_segment_max)
     bool gram;              // two-kernel Gram form of the step (nq <= 4)
     const float* w32;
     double* w;
@@ -231,6 +233,10 @@ struct LzStepArgs {
     int lo_prec;
 };
 int lz_step_blocks(int64_t n);
+// the one-kernel Gram step: elements of a block's segment it can hold, and
+// whether a grid of NB blocks of its kernel fits the device at once
+int lz_coop_segment_max();
+bool lz_coop_fits(int NB, bool upcast, int qbytes);
 // x[i] = N(0,1) sample i of the SplitMix64 stream seeded with seed (Box-Muller)
 hipError_t launch_seeded_normal(double* x, int64_t n, uint64_t seed, hipStream_t s);
 hipError_t launch_lz_step(const LzStepArgs& a, hipStream_t s);

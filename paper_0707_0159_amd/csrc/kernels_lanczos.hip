@@ -3,7 +3,14 @@
 //
 // Scalars (alpha, beta, projection coefficients, norms) stay in device memory
 // so that a Lanczos inner loop runs without any host round trip.
+#include <hip/hip_cooperative_groups.h>
+
 #include "internal.h"
+
+// Multiply-adds are fused only where one expression writes them (a += b * c),
+// never across statements: the fused and the two-kernel forms of a step then
+// round alike, whatever the scheduler does with their registers.
+#pragma clang fp contract(on)
 
 namespace d2d {
 
@@ -675,20 +682,13 @@ k_lz_dots_gram(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q, int64_t l
     write_partials<GL::ROWS>(acc, GL::ROWS, partial, NB, blockIdx.x);
 }
 
-// Second kernel: d, alpha_i = d[nq-1], beta = |w - Q d| from the sums;
-// q_next = (w - Q d) / beta and its low-precision copy.
-template <int NQ, bool UPCAST, typename TQ>
-__global__ void __launch_bounds__(LZ_THREADS)
-k_lz_update_gram(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q, int64_t ldq, int nq,
-                 const double* __restrict__ partial_in, int NB,
-                 const typename std::conditional<UPCAST, float, double>::type* __restrict__ w,
-                 TQ* __restrict__ qnext, void* __restrict__ lo, int lo_prec, double* __restrict__ scal, int i) {
+// d = c1 + (c1 - G c1) and beta = sqrt(|w|^2 - 2 d.c1 + d^T G d) from the
+// block's copy cs of the summed rows.
+template <int NQ>
+__device__ __attribute__((always_inline)) inline void gram_coeffs(const double* cs, int nq, double (&d)[NQ],
+                                                                  double& bb) {
     using GL = GramLayout<NQ>;
-    const LzSeg sg = bt[blockIdx.x];
-    if (!sg.act) return;
-    __shared__ double cs[GL::ROWS];
-    reduce_rows(partial_in, GL::ROWS, NB, sg.pb0, sg.pb1, cs);
-    double c1[NQ], d[NQ];
+    double c1[NQ];
 #pragma unroll
     for (int j = 0; j < NQ; ++j) c1[j] = j < nq ? cs[j] : 0.0;
     auto gram = [&](int j, int l) { return j <= l ? cs[GL::g(j, l)] : cs[GL::g(l, j)]; };
@@ -709,7 +709,24 @@ k_lz_update_gram(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q, int64_t
         dgd += d[j] * gd;
     }
     const double b2 = cs[NQ] - 2.0 * dc + dgd;
-    const double bb = sqrt(b2 > 0.0 ? b2 : 0.0);
+    bb = sqrt(b2 > 0.0 ? b2 : 0.0);
+}
+
+// Second kernel: d, alpha_i = d[nq-1], beta = |w - Q d| from the sums;
+// q_next = (w - Q d) / beta and its low-precision copy.
+template <int NQ, bool UPCAST, typename TQ>
+__global__ void __launch_bounds__(LZ_THREADS)
+k_lz_update_gram(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q, int64_t ldq, int nq,
+                 const double* __restrict__ partial_in, int NB,
+                 const typename std::conditional<UPCAST, float, double>::type* __restrict__ w,
+                 TQ* __restrict__ qnext, void* __restrict__ lo, int lo_prec, double* __restrict__ scal, int i) {
+    using GL = GramLayout<NQ>;
+    const LzSeg sg = bt[blockIdx.x];
+    if (!sg.act) return;
+    __shared__ double cs[GL::ROWS];
+    reduce_rows(partial_in, GL::ROWS, NB, sg.pb0, sg.pb1, cs);
+    double d[NQ], bb;
+    gram_coeffs<NQ>(cs, nq, d, bb);
     if ((int)blockIdx.x == sg.pb0 && threadIdx.x == 0) {
         double* sc = scal + (int64_t)sg.prob * S_LEN;
         sc[S_ALPHA + i] = d[nq - 1];
@@ -747,6 +764,156 @@ k_lz_update_gram(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q, int64_t
             store_lo(lo, lo_prec, e, qv);
         }
     }
+}
+
+// One-kernel Gram step for segments a block covers in COOP_ROUNDS rounds of
+// GRAM_U elements per thread: the first kernel's sums, a grid barrier, then
+// the second kernel's update from the product and window values still held in
+// registers (neither is read twice, and one launch is saved).  Launched
+// cooperatively only (every block of the grid resident at once), and every
+// block, active or not, reaches the barrier exactly once.  The arithmetic and
+// its order are the two kernels', so the result is the same bit for bit.
+static constexpr int COOP_ROUNDS = 2;
+
+template <int NQ, bool UPCAST, typename TQ>
+__global__ void __launch_bounds__(LZ_THREADS)
+k_lz_step_gram_coop(const LzSeg* __restrict__ bt, const TQ* __restrict__ Q, int64_t ldq, int nq,
+                    const typename std::conditional<UPCAST, float, double>::type* __restrict__ win,
+                    const HvPartPtrs P, double* __restrict__ partial, int NB, TQ* __restrict__ qnext,
+                    void* __restrict__ lo, int lo_prec, double* __restrict__ scal, int i) {
+    using GL = GramLayout<NQ>;
+    using TW = typename std::conditional<UPCAST, float, double>::type;
+    constexpr int U = GRAM_U, RR = COOP_ROUNDS;
+    const LzSeg sg = bt[blockIdx.x];
+    const bool act = sg.act != 0;
+    const int64_t st = blockDim.x;
+    double x[RR][U], q[RR][U][NQ];
+    if (act) {
+        double acc[GL::ROWS];
+#pragma unroll
+        for (int j = 0; j < GL::ROWS; ++j) acc[j] = 0.0;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+            const int64_t e0 = sg.lo + threadIdx.x + (int64_t)r * U * st;
+            TQ qr[U][NQ];
+            TW wv[U], pv[4][U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t e = e0 + u * st;
+                const int64_t ec = e < sg.hi ? e : sg.lo;
+                wv[u] = win[ec];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) pv[k][u] = P.p[k] ? ((const TW*)P.p[k])[ec] : TW(0);
+#pragma unroll
+                for (int j = 0; j < NQ; ++j) qr[u][j] = Q[(j < nq ? j : nq - 1) * ldq + ec];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int j = 0; j < NQ; ++j) q[r][u][j] = j < nq ? q_to_f64(qr[u][j]) : 0.0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = e0 + u * st < sg.hi;
+                TW f = wv[u];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (P.p[k]) f = f + pv[k][u];
+                x[r][u] = ok ? (double)f : 0.0;
+#pragma unroll
+                for (int j = 0; j < NQ; ++j) q[r][u][j] = ok ? q[r][u][j] : 0.0;
+            }
+            // a lane whose round starts past the segment adds nothing (as the
+            // two-kernel loop, which ends before that round)
+            if (e0 < sg.hi) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+#pragma unroll
+                    for (int j = 0; j < NQ; ++j) acc[j] += q[r][u][j] * x[r][u];
+                    acc[NQ] += x[r][u] * x[r][u];
+#pragma unroll
+                    for (int j = 0; j < NQ; ++j)
+#pragma unroll
+                        for (int l = j; l < NQ; ++l) acc[GL::g(j, l)] += q[r][u][j] * q[r][u][l];
+                }
+            }
+        }
+        write_partials<GL::ROWS>(acc, GL::ROWS, partial, NB, blockIdx.x);
+    }
+    __threadfence();
+    cooperative_groups::this_grid().sync();
+    if (!act) return;
+    __shared__ double cs[GL::ROWS];
+    reduce_rows(partial, GL::ROWS, NB, sg.pb0, sg.pb1, cs);
+    double d[NQ], bb;
+    gram_coeffs<NQ>(cs, nq, d, bb);
+    if ((int)blockIdx.x == sg.pb0 && threadIdx.x == 0) {
+        double* sc = scal + (int64_t)sg.prob * S_LEN;
+        sc[S_ALPHA + i] = d[nq - 1];
+        sc[S_BETA + i + 1] = bb;
+    }
+    if (!qnext) return;
+    const double inv = bb > 0.0 ? 1.0 / bb : 0.0;
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = sg.lo + threadIdx.x + (int64_t)r * U * st + u * st;
+            if (e >= sg.hi) continue;
+            double xv = x[r][u];
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) xv -= d[j] * q[r][u][j];
+            const double qv = xv * inv;
+            qnext[e] = q_from_f64<TQ>(qv);
+            store_lo(lo, lo_prec, e, qv);
+        }
+    }
+}
+
+// Elements of a segment the one-kernel step can hold (per block).
+int lz_coop_segment_max() { return COOP_ROUNDS * GRAM_U * LZ_THREADS; }
+
+template <bool UPCAST, typename TQ>
+static bool coop_fits_t(int NB) {
+    int dev = 0, cus = 0, per = 0, coop = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return false;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_lz_step_gram_coop<4, UPCAST, TQ>, LZ_THREADS, 0) !=
+        hipSuccess)
+        return false;
+    return (int64_t)per * cus >= NB;
+}
+
+bool lz_coop_fits(int NB, bool upcast, int qbytes) {
+    if (!upcast) return qbytes == 8 && coop_fits_t<false, double>(NB);
+    if (qbytes == 8) return coop_fits_t<true, double>(NB);
+    if (qbytes == 4) return coop_fits_t<true, float>(NB);
+    if (qbytes == 2) return coop_fits_t<true, bf16q>(NB);
+    return false;
+}
+
+template <typename TQ>
+static hipError_t lz_step_gram_coop(const LzStepArgs& a, hipStream_t s) {
+    HvPartPtrs P;
+    for (int k = 0; k < 4; ++k) P.p[k] = a.wpart[k];
+    const TQ* Q = (const TQ*)a.Q;
+    TQ* qn = (TQ*)a.qnext;
+    int64_t ldq = a.ldq;
+    int nq = a.nq, NB = a.NB, lp = a.lo ? a.lo_prec : -1, i = a.i;
+    double* partial = a.partial;
+    void* lo = a.lo;
+    double* scal = a.scal;
+    const LzSeg* bt = a.bt;
+    if (a.upcast) {
+        const float* win = a.w32;
+        void* args[] = {&bt, &Q, &ldq, &nq, &win, &P, &partial, &NB, &qn, &lo, &lp, &scal, &i};
+        return hipLaunchCooperativeKernel((const void*)k_lz_step_gram_coop<4, true, TQ>, dim3(NB), dim3(LZ_THREADS),
+                                          args, 0, s);
+    }
+    const double* win = a.w;
+    void* args[] = {&bt, &Q, &ldq, &nq, &win, &P, &partial, &NB, &qn, &lo, &lp, &scal, &i};
+    return hipLaunchCooperativeKernel((const void*)k_lz_step_gram_coop<4, false, TQ>, dim3(NB), dim3(LZ_THREADS),
+                                      args, 0, s);
 }
 
 template <typename TQ>
@@ -802,6 +969,7 @@ static hipError_t lz_step_nq(const LzStepArgs& a, hipStream_t s) {
 
 template <typename TQ>
 static hipError_t lz_step(const LzStepArgs& a, hipStream_t s) {
+    if (a.gram && a.nq <= 4 && a.coop) return lz_step_gram_coop<TQ>(a, s);
     if (a.gram && a.nq <= 4) return lz_step_gram<TQ>(a, s);
     if (a.nq <= 4) return lz_step_nq<4, TQ>(a, s);
     if (a.nq <= 8) return lz_step_nq<8, TQ>(a, s);

@@ -92,6 +92,7 @@ d2d_status ensure_lanczos_work(d2d_ctx* c, LanczosWork*& lw, const std::vector<i
     }
     w->NB = (int)bt.size();
     w->h_bt = bt;
+    for (const LzSeg& sg : bt) w->max_seg = std::max<int64_t>(w->max_seg, sg.hi - sg.lo);
     w->seg_off.resize(w->nprob);
     w->seg_len = len;
     off = 0;
@@ -172,11 +173,16 @@ int basis_bytes(int prec, int basis) {
 // touches the correction sum_{j>=1} y_j q_j, which shrinks with the residual.
 // A basis vector in the products' input precision is the product's input
 // itself; otherwise the step writes an input copy (lo).
+// coop: the Gram step may run as one cooperative kernel (not under capture);
+// it does where every block's segment fits the kernel's registers and the
+// grid fits the device at once.
 d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool fused, bool plain_cgs2,
-                      int basis, hipStream_t s) {
+                      int basis, bool coop, hipStream_t s) {
     const LzSet z = set_of(w);
     const int64_t ldq = w->ldq;
     const int qb = basis_bytes(prec, basis);
+    const bool one_kernel = coop && w->max_seg <= lz_coop_segment_max() &&
+                            lz_coop_fits(z.NB, prec != D2D_FP64, qb);
     const size_t qs = (size_t)qb;
     char* Q = (char*)w->Q;
     const int in_bytes = prec == D2D_FP64 ? 8 : (prec == D2D_BF16 ? 2 : 4);
@@ -201,6 +207,7 @@ d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bo
         a.i = i;
         a.upcast = prec != D2D_FP64;
         a.gram = !plain_cgs2 && window >= 2 && window <= 4;
+        a.coop = a.gram && one_kernel;
         a.w32 = w->wlo;
         a.w = w->W;
         for (int q = 0; q < 3; ++q) a.wpart[q] = parts.x[q];
@@ -229,9 +236,9 @@ void drop_graphs(LanczosWork* w) {
 }
 
 d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, bool full, int window, bool fused,
-                   bool plain_cgs2, int basis, bool use_graph, hipStream_t s) {
+                   bool plain_cgs2, int basis, bool coop, bool use_graph, hipStream_t s) {
     if (!use_graph || s == nullptr) {
-        D2D_CHECK(inner_loop(w, hv, prec, k, window, fused, plain_cgs2, basis, s));
+        D2D_CHECK(inner_loop(w, hv, prec, k, window, fused, plain_cgs2, basis, coop, s));
         D2D_CHECK(residual_step(w, hv, s));
         hv.count(prec, k - 1);
         hv.count(D2D_FP64, 1);
@@ -246,7 +253,7 @@ d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, bool full, int wi
         D2D_CHECK(hv.prepare(prec));          // launch tables exist before capture
         D2D_CHECK(hv.prepare(D2D_FP64));
         D2D_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        d2d_status st = inner_loop(w, hv, prec, k, window, fused, plain_cgs2, basis, s);
+        d2d_status st = inner_loop(w, hv, prec, k, window, fused, plain_cgs2, basis, false, s);
         if (st == D2D_OK) st = residual_step(w, hv, s);
         hipGraph_t gr = nullptr;
         hipError_t e = hipStreamEndCapture(s, &gr);
@@ -281,12 +288,13 @@ d2d_status check_lanczos_opts(const d2d_lanczos_opts* o) {
         !(o->tol_res > 0.0) || o->prec < 0 || o->prec >= D2D_NPREC || o->reorth_window < 0 ||
         o->reorth_window == 1 || o->reorth_window > 32 || o->separate_central < 0 ||
         o->separate_central > 1 || !(o->tol_rel_e >= 0.0) || o->plain_cgs2 < 0 || o->plain_cgs2 > 1 ||
-        o->basis < 0 || o->basis > 2 || o->fixed_cycles < 0 || o->fixed_cycles > 1) {
+        o->basis < 0 || o->basis > 2 || o->fixed_cycles < 0 || o->fixed_cycles > 1 || o->one_kernel_step < 0 ||
+        o->one_kernel_step > 1) {
         set_error("Lanczos options: k_in and k_in_bf16 (0 or) 2..128 (2..32 with full reorthogonalisation), "
                   "max_restarts >= 0, "
                   "tol_res > 0, prec 0..3, reorth_window 0 or 2..32, "
                   "separate_central 0 or 1, tol_rel_e >= 0, plain_cgs2 0 or 1, basis 0..2, "
-                  "fixed_cycles 0 or 1");
+                  "fixed_cycles 0 or 1, one_kernel_step 0 or 1");
         return D2D_EINVAL;
     }
     return D2D_OK;
@@ -449,7 +457,7 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
             k = std::min(kfull, need);
         }
         D2D_CHECK(restart(w, hv, prec, k, k == kfull, opts->reorth_window, opts->separate_central == 0,
-                          opts->plain_cgs2 != 0, opts->basis, opts->use_graph != 0, s));
+                          opts->plain_cgs2 != 0, opts->basis, opts->one_kernel_step != 0, opts->use_graph != 0, s));
         for (int p = 0; p < np; ++p)
             if (a[p]) {
                 hvc[p][prec] += k - 1;

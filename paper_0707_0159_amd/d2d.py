@@ -58,7 +58,7 @@ class d2d_lanczos_opts(C.Structure):
                 ("escalate", C.c_double), ("use_graph", C.c_int), ("reorth_window", C.c_int),
                 ("separate_central", C.c_int), ("tol_rel_e", C.c_double), ("seed", C.c_uint64),
                 ("plain_cgs2", C.c_int), ("basis", C.c_int), ("k_in_bf16", C.c_int),
-                ("fixed_cycles", C.c_int)]
+                ("fixed_cycles", C.c_int), ("one_kernel_step", C.c_int)]
 
 
 class d2d_lanczos_stats(C.Structure):
@@ -339,10 +339,11 @@ def d2d_tile_shapes():
 
 def lanczos_opts(prec=D2D_FP64, k_in=24, max_restarts=200, tol_res=1e-9, escalate=0.5, use_graph=0,
                  reorth_window=0, separate_central=0, tol_rel_e=0.0, seed=0, plain_cgs2=0, basis=0,
-                 k_in_bf16=0, fixed_cycles=0):
+                 k_in_bf16=0, fixed_cycles=0, one_kernel_step=0):
     return d2d_lanczos_opts(int(prec), int(k_in), int(max_restarts), float(tol_res), float(escalate),
                             int(use_graph), int(reorth_window), int(separate_central), float(tol_rel_e),
-                            int(seed), int(plain_cgs2), int(basis), int(k_in_bf16), int(fixed_cycles))
+                            int(seed), int(plain_cgs2), int(basis), int(k_in_bf16), int(fixed_cycles),
+                            int(one_kernel_step))
 
 
 def d2d_lanczos(sb: int, opts: d2d_lanczos_opts, v0, psi=None):

@@ -20,7 +20,7 @@ def ctx():
     d2d.d2d_ctx_destroy(c)
 
 
-def run(ctx, prob, prec, seed, k_in=24, graph=1, tol=1e-9, window=0, separate=0, plain=0, basis=0):
+def run(ctx, prob, prec, seed, k_in=24, graph=1, tol=1e-9, window=0, separate=0, plain=0, basis=0, one=0):
     from paper_0707_0159_amd import d2d
     n = prob.info["n"]
     with torch.cuda.stream(ctx.stream):
@@ -29,7 +29,7 @@ def run(ctx, prob, prec, seed, k_in=24, graph=1, tol=1e-9, window=0, separate=0,
     ctx.stream.synchronize()
     opts = d2d.lanczos_opts(prec=prec, k_in=k_in, max_restarts=300, tol_res=tol, use_graph=graph,
                             reorth_window=window, separate_central=separate, plain_cgs2=plain,
-                            basis=basis)
+                            basis=basis, one_kernel_step=one)
     st, e, stats = d2d.d2d_lanczos(prob.sb, opts, v0, psi)
     ctx.stream.synchronize()
     return st, e, stats, psi.cpu().numpy()
@@ -202,6 +202,28 @@ def test_fp64_solve_ignores_basis_option(ctx):
         assert s1 == 0 and e1 == out[0][1]
         assert np.array_equal(np.asarray(st1["log_theta"]), np.asarray(out[0][2]["log_theta"]))
         assert np.array_equal(p1, out[0][3])
+    prob.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+def test_one_kernel_step_is_bitwise_two_kernels(ctx, prec):
+    """The Gram step as one cooperative kernel (sums, grid barrier, update
+    from registers) against the two kernels, direct launches on the 2x16
+    Hubbard ladder (412 blocks of at most 2048 elements): the same iterates
+    bit for bit."""
+    wl = W.HUBBARD_2X16_M256
+    prob = GpuProblem(ctx, wl, prec_mask=15)
+    out = [run(ctx, prob, prec, wl.seed, k_in=48, graph=0, window=3, tol=1e-8, one=o) for o in (1, 0)]
+    (s0, e0, st0, p0), (s1, e1, st1, p1) = out
+    print("one kernel", prec, e0, e1, st0["restarts"], st0["hv_count"])
+    assert s0 == 0 and s1 == 0
+    assert e0 == e1
+    assert st0["hv_count"] == st1["hv_count"]
+    assert np.array_equal(np.asarray(st0["log_theta"]), np.asarray(st1["log_theta"]))
+    assert np.array_equal(np.asarray(st0["log_rho"]), np.asarray(st1["log_rho"]))
+    assert np.array_equal(p0, p1)
+    E0 = reference_energy(wl.name)
+    assert abs(e0 - E0) <= 1e-10 * abs(E0)
     prob.close()
 
 
