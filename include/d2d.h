@@ -353,9 +353,10 @@ typedef struct {
                             one cooperative kernel (sums, grid barrier, update
                             from registers) where every block's share fits its
                             registers and the grid fits the device.  Same
-                            result bit for bit; slower on MI355X, where a
-                            cooperative launch costs more than the launch and
-                            the re-read of the window it saves              */
+                            result bit for bit; slower on MI355X, where the
+                            cooperative launch and its grid barrier cost more
+                            than the launch and the re-read of the window
+                            they save                                       */
 } d2d_lanczos_opts;
 
 #define D2D_LOG_MAX 256
