@@ -45,6 +45,11 @@ BASIS_NAMES = {0: "the products' input precision (FP32; BF16 for BF16 products; 
                1: "FP64 at every precision", 2: "FP32 below FP64 (start vector in FP64)"}
 
 
+def step_reads(args) -> int:
+    """Reads of the product and the window per Lanczos step in the time model."""
+    return 1 if args.one_kernel_step else 2
+
+
 def basis_name(args):
     return BASIS_NAMES[args.basis]
 
@@ -60,7 +65,7 @@ PREC_NAMES = ("fp64", "fp32", "bf16", "bf16x3")
 
 
 def solve_time_parts(stats: dict, n: int, k_in: int, window: int, basis: int, hv_flops: dict,
-                     hv_bytes: dict) -> dict:
+                     hv_bytes: dict, step_reads: int = 2) -> dict:
     """Lower-bound pieces of one problem's solve (seconds): every Hv at
     max(flops / MFMA peak, minimum bytes / HBM peak) of its precision
     ("hv_s"), the same flops and bytes summed separately ("hv_flop_s",
@@ -69,7 +74,10 @@ def solve_time_parts(stats: dict, n: int, k_in: int, window: int, basis: int, hv
     product bytes bw (8 at FP64, else 4): the two step kernels read the
     product twice and the window twice and write the next basis vector, and
     an input copy where the basis is not in the input precision (ci bytes):
-    N (2 bw + 2 w bq + bq + ci).  Per restart (FP64 residual, Ritz vector,
+    N (2 bw + 2 w bq + bq + ci).  With step_reads = 1 (the one-kernel step,
+    which holds its elements in registers across its grid barrier) the product
+    and the window count once; that is also a lower bound for a run where some
+    steps fall back to the two kernels.  Per restart (FP64 residual, Ritz vector,
     normalisation, first basis vectors): N (88 + (k_in + 1) bq)."""
     hv = stats["hv_count"]
     restarts = stats["restarts"]
@@ -88,7 +96,7 @@ def solve_time_parts(stats: dict, n: int, k_in: int, window: int, basis: int, hv
         bw = 8 if p == 0 else 4
         bi = {0: 8, 1: 4, 2: 2, 3: 4}[p]
         ci = 0 if bq == bi else bi
-        t_step += max(steps, 0) * n * (2 * bw + 2 * nq * bq + bq + ci) / PEAK["hbm"]
+        t_step += max(steps, 0) * n * (step_reads * (bw + nq * bq) + bq + ci) / PEAK["hbm"]
     main = max(range(4), key=lambda q: hv[q] if q else hv[0] - (restarts + 1))
     bq_main = basis_bytes(main, basis)
     t_restart = (restarts + 1) * n * (88 + (k_in + 1) * bq_main) / PEAK["hbm"]
@@ -96,10 +104,10 @@ def solve_time_parts(stats: dict, n: int, k_in: int, window: int, basis: int, hv
 
 
 def solve_time_bound(stats: dict, n: int, k_in: int, window: int, basis: int, hv_flops: dict,
-                     hv_bytes: dict) -> dict:
+                     hv_bytes: dict, step_reads: int = 2) -> dict:
     """Time-to-energy roofline of one solve: its Hv products, each at the
     bound of its precision, plus the Lanczos vector traffic."""
-    t = solve_time_parts(stats, n, k_in, window, basis, hv_flops, hv_bytes)
+    t = solve_time_parts(stats, n, k_in, window, basis, hv_flops, hv_bytes, step_reads)
     return {"t_min_ms": (t["hv_s"] + t["vec_s"]) * 1e3, "hv_ms": t["hv_s"] * 1e3,
             "lanczos_vectors_ms": t["vec_s"] * 1e3}
 
@@ -252,7 +260,7 @@ def bench_batch(args):
         # the batch runs every problem's flops and bytes: time >= the larger of
         # the summed flop and byte times, plus the vector kernels' bytes
         k = args.k_in_bf16 if prec == d2d.D2D_BF16 and args.k_in_bf16 > 0 else args.k_in
-        parts = [solve_time_parts(st, i["n"], k, args.window, args.basis, f, by)
+        parts = [solve_time_parts(st, i["n"], k, args.window, args.basis, f, by, step_reads(args))
                  for st, i, f, by in zip(per, infos, prob_flops, prob_bytes)]
         t_hv = max(sum(x["hv_flop_s"] for x in parts), sum(x["hv_byte_s"] for x in parts))
         t_vec = sum(x["vec_s"] for x in parts)
@@ -262,7 +270,8 @@ def bench_batch(args):
         opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol,
                                 use_graph=1 if args.graph else 0,
                                 reorth_window=args.window, basis=args.basis,
-                                k_in_bf16=args.k_in_bf16, fixed_cycles=int(args.fixed_cycles))
+                                k_in_bf16=args.k_in_bf16, fixed_cycles=int(args.fixed_cycles),
+                                one_kernel_step=int(args.one_kernel_step))
         st, e, per = d2d.d2d_batch_lanczos(b, opts, v0)
         if st != 0:
             raise RuntimeError("batched Lanczos did not converge")
@@ -331,6 +340,7 @@ def bench_batch(args):
                    "N_sb_total": sum(i["n"] for i in infos), "N_sb_max": max(i["n"] for i in infos),
                    "k_in": args.k_in, "k_in_bf16": args.k_in_bf16,
                    "fixed_cycles": bool(args.fixed_cycles), "graphs": bool(args.graph),
+                   "one_kernel_step": bool(args.one_kernel_step),
                    "reorth_window": args.window,
                    "tol_res": args.tol,
                    "inner_basis": basis_name(args), "parallelism": "none (1 GPU)"},
@@ -371,6 +381,9 @@ def main():
                     help="capture each restart in a hipGraph and replay it (default: direct launches)")
     ap.add_argument("--fixed-cycles", action="store_true",
                     help="every cycle full length (default: the last cycle fitted to the residual bar)")
+    ap.add_argument("--one-kernel-step", action="store_true",
+                    help="each Lanczos step as one cooperative kernel where the grid fits "
+                         "(default: its two kernels)")
     ap.add_argument("--window", type=int, default=3, help="reorthogonalisation window (0 = full)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--basis", type=int, choices=[0, 1, 2], default=0,
@@ -466,7 +479,8 @@ def main():
         opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol,
                                 use_graph=1 if args.graph else 0,
                                 reorth_window=args.window, basis=args.basis,
-                                k_in_bf16=args.k_in_bf16, fixed_cycles=int(args.fixed_cycles))
+                                k_in_bf16=args.k_in_bf16, fixed_cycles=int(args.fixed_cycles),
+                                one_kernel_step=int(args.one_kernel_step))
         st, e, stats = d2d.d2d_lanczos(sb, opts, v0, psi)
         if st != 0:
             raise RuntimeError(f"Lanczos did not converge: {stats['residual']}")
@@ -496,7 +510,7 @@ def main():
         k_path = args.k_in_bf16 if prec == d2d.D2D_BF16 and args.k_in_bf16 > 0 else args.k_in
         bound = solve_time_bound(st, N, k_path, args.window, args.basis,
                                  {k: v["gemm_flops"] for k, v in tuned.items()},
-                                 {k: info["bytes_min_" + k] for k in tuned})
+                                 {k: info["bytes_min_" + k] for k in tuned}, step_reads(args))
         bound["frac"] = bound["t_min_ms"] * 1e-3 / (wall / steps)
         return {"hv_per_s": hv / wall, "s_per_solve": wall / steps, "E": e,
                 "dE_rel": None if E0 is None else abs(e - E0) / abs(E0),
@@ -566,6 +580,7 @@ def main():
                    "sector_pairs": info["npairs"], "m": info["m"], "column_dim": info["ncol"],
                    "central_terms": info["nterms"], "k_in": args.k_in, "k_in_bf16": args.k_in_bf16,
                    "fixed_cycles": bool(args.fixed_cycles), "graphs": bool(args.graph),
+                   "one_kernel_step": bool(args.one_kernel_step),
                    "reorth_window": args.window,
                    "tol_res": args.tol, "inner_basis": basis_name(args), "tiles": tuned,
                    "parallelism": "none (1 GPU)"},

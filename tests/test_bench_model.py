@@ -60,3 +60,16 @@ def test_bf16_step_bytes_follow_the_basis(bench, basis, bq, ci):
     t = bench.solve_time_parts(stats, n, k, 3, basis, f, f)
     expect = (8 * n * (2 * 4 + 2 * 3 * bq + bq + ci) + 3 * n * (88 + 6 * bq)) / bench.PEAK["hbm"]
     assert t["vec_s"] == pytest.approx(expect)
+
+
+def test_one_kernel_step_reads_product_and_window_once(bench):
+    # FP32 solve, window 3, FP32 basis: the one-kernel form reads the product
+    # (4 B) and the window (3 x 4 B) once instead of twice per step
+    n, k = 1000, 7
+    stats = {"hv_count": [2, 30, 0, 0], "restarts": 1}
+    f = {x: 0.0 for x in bench.PREC_NAMES}
+    two = bench.solve_time_parts(stats, n, k, 3, 0, f, f)
+    one = bench.solve_time_parts(stats, n, k, 3, 0, f, f, step_reads=1)
+    restart = 2 * n * (88 + 8 * 4) / bench.PEAK["hbm"]
+    assert two["vec_s"] == pytest.approx((30 * n * (2 * (4 + 12) + 4) / bench.PEAK["hbm"]) + restart)
+    assert one["vec_s"] == pytest.approx((30 * n * ((4 + 12) + 4) / bench.PEAK["hbm"]) + restart)
