@@ -18,7 +18,8 @@ oracle's Hv rate on the host cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME | --config I]
 
-The default workload is the 2x16 Hubbard ladder (m = 256).  --config indexes
+The default workload is the largest single superblock, the 4-leg Heisenberg
+ladder 4x16 (m = 1000, N = 4.2e7).  --config indexes
 the benchmark set in its fixed order (1 heisenberg_2x6_m16, 2
 hubbard_2x16_U8_m256, 3 hubbard_3x12_U4_N33_m400, 4 heisenberg_4x16_m1000,
 5 batch64); batch64 runs the batch of 64 uneven superblocks instead (one
@@ -158,12 +159,20 @@ def use_tune_cache():
     atexit.register(lambda: os.path.exists(path) and os.remove(path))
 
 
-def cpu_baseline(wl, seconds: float):
-    """The oracle's Hv (the paper's matrix form, float64, numpy/scipy) on the host."""
+def cpu_baseline(wl, seconds: float, iterations: int | None = None, E0=None):
+    """The oracle's Hv (the paper's matrix form, float64, numpy/scipy) on the
+    host, and the oracle's time to the ground energy: its Lanczos (full
+    reorthogonalisation, float64) run to its own stop where the vectors fit
+    a bounded run (N <= 2e6), else extrapolated from `iterations` products:
+    per iteration k the measured median Hv plus the reorthogonalisation of
+    CGS2 against k vectors at the measured time of one length-N dot product
+    (4k + 6 dot-equivalents)."""
+    import numpy as np
     from threadpoolctl import threadpool_info
 
     import workloads as W
     from oracle.blockio import block_from_arrays
+    from oracle.lanczos import ground_state
     from oracle.superblock import Superblock
 
     raw = W.load_blocks(wl.name)
@@ -171,17 +180,45 @@ def cpu_baseline(wl, seconds: float):
     v = W.random_vector(sb.N, 1000)
     sb.hv_factored(v)                      # builds the dense sectors and the V_c gather plan
     n = 0
+    times = []
     t0 = time.perf_counter()
     while True:
+        t1 = time.perf_counter()
         sb.hv_factored(v)
+        times.append(time.perf_counter() - t1)
         n += 1
         dt = time.perf_counter() - t0
         if dt >= seconds:
             break
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    return {"value": n / dt, "unit": "Hv/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n} oracle Hv (mode F: H_l V + V H_r^T + H_c V_c, float64) on {wl.name}, "
-                      f"N={sb.N}, {dt:.1f} s, BLAS threads {threads}, host cpus {len(os.sched_getaffinity(0))}"}
+    out = {"value": n / dt, "unit": "Hv/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{n} oracle Hv (mode F: H_l V + V H_r^T + H_c V_c, float64) on {wl.name}, "
+                     f"N={sb.N}, {dt:.1f} s, BLAS threads {threads}, host cpus {len(os.sched_getaffinity(0))}"}
+    t_hv = float(np.median(times))
+    if sb.N <= 2_000_000:
+        t1 = time.perf_counter()
+        e, _, inf = ground_state(sb.hv_factored, sb.N, v0=W.random_vector(sb.N, wl.seed), tol=1e-14,
+                                 max_iter=600)
+        out["time_to_energy"] = {"kind": "measured", "s": time.perf_counter() - t1, "iterations": inf["iterations"],
+                                 "dE_rel": None if E0 is None else abs(e - E0) / abs(E0),
+                                 "what": "oracle Lanczos, full reorthogonalisation, to its own stop (|dtheta| <= "
+                                         "1e-14 |theta|)"}
+    elif iterations:
+        a = W.random_vector(sb.N, 1)
+        b = W.random_vector(sb.N, 2)
+        t1 = time.perf_counter()
+        for _ in range(5):
+            float(a @ b)
+        t_dot = (time.perf_counter() - t1) / 5
+        k = np.arange(1, iterations + 1)
+        t = float(iterations * t_hv + np.sum(4 * k + 6) * t_dot)
+        out["time_to_energy"] = {"kind": "extrapolated", "s": t, "iterations": int(iterations),
+                                 "median_hv_s": t_hv, "dot_s": t_dot,
+                                 "what": "iterations = the GPU FP64 solve's product count to its stop (an "
+                                         "unrestarted Lanczos needs at most about as many); per iteration k: the "
+                                         "oracle's median Hv + (4k + 6) length-N dot products of CGS2 against k "
+                                         "vectors"}
+    return out
 
 
 def cpu_baseline_batch(wls, seconds: float):
@@ -210,6 +247,20 @@ def cpu_baseline_batch(wls, seconds: float):
     return {"value": n / dt, "unit": "problem-Hv/s", "cores": int(threads), "kind": "oracle",
             "sample": f"one oracle Hv (mode F, float64) on each of the first {n} problems of the batch, "
                       f"{dt:.1f} s of products, BLAS threads {threads}, host cpus {len(os.sched_getaffinity(0))}"}
+
+
+def batch_description(wls, infos) -> str:
+    """The batch workload in words, with the problems whose blocks hold fewer
+    states than their drawn m (blocks of few columns stay exact)."""
+    short = [wl.name for wl, i in zip(wls, infos) if i["m"] < wl.m]
+    L = wls[0].length
+    txt = (f"batch of {len(wls)} uneven superblocks (2/3-leg Heisenberg and Hubbard), {L}-column lattices, "
+           f"blocks of {(L - 2) // 2} columns, drawn m 64..512")
+    if short:
+        txt += f"; {len(short)} problems have blocks below their drawn m (exact blocks of fewer states)"
+    else:
+        txt += "; every problem's blocks truncated to its drawn m"
+    return txt
 
 
 def bench_batch(args):
@@ -251,9 +302,9 @@ def bench_batch(args):
     with torch.cuda.stream(s):
         v0 = [torch.as_tensor(W.random_vector(i["n"], wl.seed), device="cuda") for i, wl in zip(infos, wls)]
     s.synchronize()
-    # per problem: the flops its Hv executes on its own (default launch
-    # configuration) and the minimum bytes, per precision
-    prob_flops = [{n: d2d.d2d_sb_gemm_flops(sb, p) for p, n in enumerate(PREC_NAMES)} for sb in sbs]
+    # per problem: the method's flops of one Hv (F_nnz, central term included)
+    # and the minimum bytes, per precision
+    prob_flops = [{n: i["flops_nnz"] for n in PREC_NAMES} for i in infos]
     prob_bytes = [{n: i["bytes_min_" + n] for n in PREC_NAMES} for i in infos]
 
     def batch_time_bound(per, prec):
@@ -314,6 +365,7 @@ def bench_batch(args):
     # one batched Hv (pack + grouped GEMM + central term) per precision, HIP events on the context stream
     hv_ms = {}
     F = sum(i["flops_exec"] for i in infos)
+    Fn = sum(i["flops_nnz"] - i["flops_central"] for i in infos)
     Fx = d2d.d2d_batch_gemm_flops(b, d2d.D2D_FP32)
     for prec, name, dt in ((d2d.D2D_FP64, "fp64", torch.float64), (d2d.D2D_FP32, "fp32", torch.float32),
                            (d2d.D2D_BF16, "bf16", torch.bfloat16), (d2d.D2D_BF16X3, "bf16x3", torch.float32)):
@@ -335,8 +387,7 @@ def bench_batch(args):
         "value": head["hv_per_s"], "unit": "Hv/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": head["s_per_solve"] * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
-        "config": {"workload": f"batch of {len(wls)} uneven superblocks (2/3-leg Heisenberg and Hubbard, "
-                               f"{len(wls)} problems, 6 columns, m 64..512)",
+        "config": {"workload": batch_description(wls, infos),
                    "N_sb_total": sum(i["n"] for i in infos), "N_sb_max": max(i["n"] for i in infos),
                    "k_in": args.k_in, "k_in_bf16": args.k_in_bf16,
                    "fixed_cycles": bool(args.fixed_cycles), "graphs": bool(args.graph),
@@ -351,8 +402,11 @@ def bench_batch(args):
         "tiles": tiles,
         "batched_hv_ms": hv_ms,
         "flops_exec_per_batched_hv": F, "gemm_flops_run_fp32": Fx,
-        "roofline": {"bound": "mfma", "achieved": Fx / (hv_ms["fp32"] * 1e-3) / 1e12, "peak": PEAK["fp32"] / 1e12,
-                     "unit": "TFLOP/s", "frac": Fx / (hv_ms["fp32"] * 1e-3) / PEAK["fp32"], "traffic": None,
+        "roofline": {"bound": "mfma", "achieved": Fn / (hv_ms["fp32"] * 1e-3) / 1e12, "peak": PEAK["fp32"] / 1e12,
+                     "unit": "TFLOP/s", "frac": Fn / (hv_ms["fp32"] * 1e-3) / PEAK["fp32"], "traffic": None,
+                     "work": "F_nnz of every problem's Hv (GEMM part) per batched Hv",
+                     "executed_tflops": Fx / (hv_ms["fp32"] * 1e-3) / 1e12,
+                     "frac_exec": Fx / (hv_ms["fp32"] * 1e-3) / PEAK["fp32"],
                      "kernel": "batched Hv launch sequence (fp32 grouped GEMM + central term), latency-bound"},
     }
     if not args.no_cpu_baseline:
@@ -371,7 +425,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
+    ap.add_argument("--config", type=int, default=4, choices=[1, 2, 3, 4, 5],
                     help="workload by its index in the benchmark set (see the module docstring)")
     ap.add_argument("--workload", default=None,
                     help="workload by name (overrides --config): a single superblock's name or batch64")
@@ -509,7 +563,7 @@ def main():
         e, st = last
         k_path = args.k_in_bf16 if prec == d2d.D2D_BF16 and args.k_in_bf16 > 0 else args.k_in
         bound = solve_time_bound(st, N, k_path, args.window, args.basis,
-                                 {k: v["gemm_flops"] for k, v in tuned.items()},
+                                 {k: info["flops_nnz"] for k in tuned},
                                  {k: info["bytes_min_" + k] for k in tuned}, step_reads(args))
         bound["frac"] = bound["t_min_ms"] * 1e-3 / (wall / steps)
         return {"hv_per_s": hv / wall, "s_per_solve": wall / steps, "E": e,
@@ -546,14 +600,22 @@ def main():
         ms[name] = {"gemm_ms": g, "central_ms": c, "hv_ms": ev0.elapsed_time(ev1) / 50}
 
     F = info["flops_exec"]
+    F_nnz_gemm = info["flops_nnz"] - info["flops_central"]
 
     def roofline(name):
-        # executed flops: the K steps the launch runs (zero operator tiles left out)
+        # achieved: the method's work, 2 flops per nonzero of the H_l and H_r
+        # sector blocks times the other side's dimension (F_nnz, GEMM part),
+        # over the launch's duration; the flops the launch executes (every K
+        # step whose operator tile holds a nonzero) are reported beside it
         sec = ms[name]["gemm_ms"] * 1e-3
         fx = tuned[name]["gemm_flops"]
-        achieved = fx / sec
+        achieved = F_nnz_gemm / sec
         return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[name] / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK[name], "traffic": traffic_record(wl.name, name, tuned[name]),
+                "work": "F_nnz: 2 x nonzeros of the H_l, H_r sector blocks x the other dimension, per launch",
+                "flops_nnz_per_launch": F_nnz_gemm,
+                "executed_tflops": fx / sec / 1e12, "frac_exec": fx / sec / PEAK[name],
+                "executed_over_nnz": fx / F_nnz_gemm,
                 "kernel": f"grouped GEMM H_l V + V H_r^T ({name}, tile {tuned[name]['BMxBNxBK']}"
                           f"{', split K-loops' if tuned[name]['split_k_loops'] else ''}"
                           f"{' (halved)' if tuned[name]['split_k_loops'] == 'halves' else ''}"
@@ -602,7 +664,10 @@ def main():
         "roofline_fp64": roofline("fp64"),
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, iterations=int(fp64["hv_count"][0]), E0=E0)
+        if "time_to_energy" in line["cpu_baseline"]:
+            line["time_to_energy"]["speedup_fp32_vs_cpu_oracle"] = (
+                line["cpu_baseline"]["time_to_energy"]["s"] / head["s_per_solve"])
     d2d.d2d_sb_destroy(sb)
     d2d.d2d_block_destroy(b1)
     d2d.d2d_block_destroy(b4)

@@ -55,7 +55,9 @@ extern "C" {
 
 typedef int d2d_status;
 #define D2D_OK       0
-#define D2D_EINVAL  -1   /* bad argument (null, size, NaN input, empty target)  */
+#define D2D_EINVAL  -1   /* bad argument: null pointer, size, empty target, a
+                            non-finite block entry or model parameter, a zero
+                            or non-finite Lanczos start vector               */
 #define D2D_ENOMEM  -2   /* device allocation failed or context memory cap hit */
 #define D2D_EDEVICE -3   /* HIP runtime error                                  */
 #define D2D_ENOCONV -4   /* Lanczos did not reach the tolerance                */
@@ -205,7 +207,9 @@ d2d_status d2d_unpack(d2d_sb* sb, const double* packed, double* full);
 /* --------------------------------------------------------------------- Hv
  * w = H v in the packed layout, on the context stream, asynchronous.
  * prec D2D_FP64: v, w double.  D2D_FP32: v float, w float.  D2D_BF16: v
- * bfloat16 (uint16 storage), w float.  v and w must not overlap. */
+ * bfloat16 (uint16 storage), w float.  v and w must not overlap.  The entries
+ * of v are not inspected (the call does not wait for the device): non-finite
+ * entries give non-finite products, as in a BLAS routine. */
 d2d_status d2d_hv(d2d_sb* sb, int prec, const void* v, void* w);
 
 /* Kernel timing of Hv on the context stream: after one product, `reps`
@@ -250,6 +254,14 @@ d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[D2D_NPREC]);
 #define D2D_TILE_SPLIT4 (1 << 18)
 #define D2D_TILE_XCD (1 << 19)
 #define D2D_TILE_DENSE (1 << 20)
+/* D2D_TILE_ASYM: the two K-loops as separate work items in two launches,
+ * each in a tile that is narrow along the dimension its K-step list depends
+ * on and wide along the other: H_l V items in the shape given (e.g. 64 rows x
+ * 256 columns: the step list follows the 64 rows of H_l, the 256 columns
+ * share it), V H_r^T items in the next shape of the table, its transpose
+ * (256 x 64).  Valid only for shapes whose next entry is their transpose;
+ * one partial output, added as with D2D_TILE_SPLIT. */
+#define D2D_TILE_ASYM (1 << 21)
 d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile);
 /* Floating-point operations of one grouped-GEMM launch of precision prec
  * under the superblock's current launch configuration: 2 per multiply-add
@@ -320,9 +332,11 @@ typedef struct {
     double escalate;     /* precision raise threshold on rho_{j+1}/rho_j        */
     int use_graph;       /* 1: capture each restart (its cycle and the FP64
                             residual) in a hipGraph and replay it; 0: launch
-                            the kernels directly.  The capture is made anew
-                            in every call, so it pays only where the host's
-                            launches would not stay ahead of the device   */
+                            the kernels directly.  Captures are kept with the
+                            superblock's (batch's) Lanczos workspace and
+                            replayed by later calls while the cycle length,
+                            the options they depend on and the launch
+                            configuration hold (see graph_captures)         */
     int reorth_window;   /* 0: reorthogonalise against every basis vector (full);
                             w in 2..32: only against the last w vectors (the FP64
                             restarts keep the fixed point exact either way)   */
@@ -376,6 +390,13 @@ typedef struct {
     double log_pred[D2D_LOG_MAX];   /* residual the previous inner Lanczos
                                        predicted for its Ritz vector
                                        (beta_k |y_k|; 0 for the first entry)     */
+    int graph_captures;       /* restarts captured as hipGraphs in this call
+                                 (use_graph: a capture made by an earlier call
+                                 on the same superblock or batch is replayed
+                                 while the cycle length, options and launch
+                                 configuration it was made for hold)          */
+    int64_t coop_steps;       /* inner steps run as the one cooperative kernel
+                                 (one_kernel_step)                             */
 } d2d_lanczos_stats;
 
 d2d_status d2d_lanczos(d2d_sb* sb, const d2d_lanczos_opts* opts, const double* v0, double* energy,
@@ -395,6 +416,32 @@ d2d_status d2d_lanczos(d2d_sb* sb, const d2d_lanczos_opts* opts, const double* v
 d2d_status d2d_density_matrix(d2d_sb* sb, const double* psi, int side, int m_keep,
                               d2d_block** new_block, double* trunc_err, double* spectrum,
                               int64_t* spectrum_len);
+/* d2d_density_matrix with the wall time of its three phases in ms[3] (host
+ * out, milliseconds, the stream synchronised at each boundary), the paper's
+ * split of the step after the exact diagonalisation: ms[0] density-matrix
+ * formation (rho of every sector, one grouped FP64 matrix-core launch),
+ * ms[1] density-matrix diagonalisation (every sector's eigenpairs, the
+ * selection of the kept states), ms[2] renormalisation (kept eigenvectors,
+ * H' = U^T H U and the new edge operators on the device, the new block's
+ * host copy).  D2D_EINVAL when ms is NULL. */
+d2d_status d2d_density_matrix_timed(d2d_sb* sb, const double* psi, int side, int m_keep,
+                                    d2d_block** new_block, double* trunc_err, double* spectrum,
+                                    int64_t* spectrum_len, double ms[3]);
+
+/* -------------------------------------------------------------- observables
+ * Site densities <n_{y,sigma}> of a packed superblock state psi (device,
+ * FP64, unit norm) on the superblock's two explicit columns: the inputs of
+ * the hole density h(x,y) = 1 - <n_up + n_dn> and the staggered spin density
+ * s(x,y) = <n_up - n_dn> of the paper's stripe analysis (Eqs. (2) and (3);
+ * S(x) of Eq. (4) is the largest |s(x,y)| over the legs).  Column 2 is the
+ * lattice column right of block 1, column 3 the next one.  The density
+ * operators of a column are diagonal in its occupation basis, so
+ * <n_{y,sigma}> = sum over packed elements of psi^2 times the occupation of
+ * mode (y, sigma) in the element's column state.  Spin model: n_up = 1/2 +
+ * S^z, n_dn = 1/2 - S^z.  out (host, 4 * legs doubles):
+ * out[(c * legs + y) * 2 + sigma], c = 0 column 2, 1 column 3; sigma 0 up,
+ * 1 down.  Deterministic (partial sums added in a fixed order); synchronous. */
+d2d_status d2d_column_densities(d2d_sb* sb, const double* psi, double* out);
 
 /* -------------------------------------------------------------------- batch
  * Many independent superblocks advanced together: one grouped launch per

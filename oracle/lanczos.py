@@ -79,3 +79,32 @@ def ground_state_arpack(matvec, n, v0=None, tol=0.0, ncv=None):
     x = vecs[:, 0]
     r = matvec(x) - vals[0] * x
     return float(vals[0]), x, {"residual": float(np.linalg.norm(r))}
+
+
+def lowest_two_arpack(matvec, n, v0=None, tol=0.0, ncv=None):
+    """The two lowest eigenpairs by ARPACK, with their residual norms.
+
+    Returns ``(theta0, theta1, x0, rho0, rho1)``.  The second pair gives the
+    gap needed by the Kato-Temple bound on the first (see ``kato_temple_lower``).
+    """
+    from scipy.sparse.linalg import LinearOperator, eigsh
+    op = LinearOperator((n, n), matvec=matvec, dtype=np.float64)
+    vals, vecs = eigsh(op, k=2, which="SA", tol=tol, v0=v0, ncv=ncv)
+    order = np.argsort(vals)
+    vals, vecs = vals[order], vecs[:, order]
+    res = [float(np.linalg.norm(matvec(vecs[:, i]) - vals[i] * vecs[:, i])) for i in range(2)]
+    return float(vals[0]), float(vals[1]), vecs[:, 0], res[0], res[1]
+
+
+def kato_temple_lower(theta, rho, upper_gap_bound):
+    """Kato-Temple lower bound on the lowest eigenvalue of a symmetric operator.
+
+    For a unit vector with Rayleigh quotient ``theta`` and residual norm
+    ``rho``, and any ``b`` with ``theta < b <= lambda_1`` (the second
+    eigenvalue), ``lambda_0 >= theta - rho**2 / (b - theta)`` (Kato 1949,
+    Temple 1928).  ``upper_gap_bound`` is such a ``b``; None if it is not
+    above ``theta``.
+    """
+    if not upper_gap_bound > theta:
+        return None
+    return theta - rho * rho / (upper_gap_bound - theta)

@@ -5,7 +5,7 @@ blocks 1 and 4 under ``workloads/blocks/<name>.npz`` together with a JSON log
 of every growth step.  Calls nothing outside ``oracle/`` and ``workloads``.
 
     python -m oracle.make_blocks --workload hubbard_2x16_U8_m256
-    python -m oracle.make_blocks --workload batch64 --problems 0-7
+    python -m oracle.make_blocks --workload batch64 --problems 0-7 [--length 12]
 """
 from __future__ import annotations
 
@@ -40,7 +40,7 @@ def build(wl: W.Workload, tol=1e-10, verbose=True):
             "sectors": [len(L.sectors()), len(R.sectors())], "hash": W.block_file_hash(wl.name),
             "history": [{k: (float(v) if isinstance(v, (float, np.floating)) else v)
                          for k, v in h.items()} for h in hist],
-            "seconds": time.time() - t0}
+            "growth_tol": tol, "seconds": time.time() - t0}
     with open(path.replace(".npz", ".json"), "w") as f:
         json.dump(meta, f, indent=1)
     return meta
@@ -50,13 +50,17 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", required=True, choices=sorted(W.WORKLOADS) + ["batch64"])
     ap.add_argument("--problems", default=None, help="batch64 only: a-b range")
+    ap.add_argument("--length", type=int, default=None, help="batch64 only: lattice length (columns)")
+    ap.add_argument("--only", default=None, help="batch64 only: comma-separated problem indices")
     ap.add_argument("--tol", type=float, default=1e-10)
     args = ap.parse_args()
     if args.workload == "batch64":
-        probs = W.batch64()
+        probs = W.batch64(args.length)
         if args.problems:
             a, b = (int(x) for x in args.problems.split("-"))
             probs = probs[a:b + 1]
+        if args.only:
+            probs = [probs[int(i)] for i in args.only.split(",")]
         for wl in probs:
             if os.path.exists(W.block_path(wl.name)):
                 continue

@@ -137,14 +137,20 @@ class Superblock:
         i3 = idx // (m * m * n)
         return (i4 * m + i1) * (n * n) + i3 * n + i2
 
-    def explicit(self, full_space: bool = False) -> sp.csr_matrix:
-        """H as one sparse matrix (mode X), on the target or the full space."""
+    def explicit(self, full_space: bool = False, absolute: bool = False) -> sp.csr_matrix:
+        """H as one sparse matrix (mode X), on the target or the full space.
+
+        With ``absolute`` the three parts enter with the absolute values of
+        their entries, ``kron(|H_r|, I) + kron(I, |H_l|) + Pi^T kron(I, |H_c|) Pi``:
+        the sum of the magnitudes of the terms that make up each element of
+        ``H v`` (an upper bound of ``|H|`` entry by entry)."""
         m, n = self.m, self.n
         mn = m * n
         I_mn = sp.identity(mn, format="csr")
-        H = sp.kron(self.H_r, I_mn) + sp.kron(I_mn, self.H_l)
+        fix = abs if absolute else (lambda a: a)
+        H = sp.kron(fix(self.H_r), I_mn) + sp.kron(I_mn, fix(self.H_l))
         vc = self.vc_index_of_full()
-        Hc_big = sp.csr_matrix(sp.kron(sp.identity(m * m, format="csr"), self.H_c))
+        Hc_big = sp.csr_matrix(sp.kron(sp.identity(m * m, format="csr"), fix(self.H_c)))
         H = sp.csr_matrix(H + Hc_big[vc][:, vc])
         if full_space:
             return H
@@ -222,6 +228,23 @@ class Superblock:
             w[o:o + dL * dR] = W.T.reshape(-1)
         for hc, pidx in self.central_groups():
             w[pidx] += hc @ v[pidx]
+        return w
+
+    def hv_abs_bound(self, v: np.ndarray) -> np.ndarray:
+        """``|H_l| |V| + |V| |H_r|^T + unvec(|H_c| |V_c|)`` of ``|v|`` (mode F on
+        absolute values, packed).  Element i is the sum of the magnitudes of
+        every product term that enters ``(H v)_i`` in the matrix form of Eq. (1),
+        so any summation order of those terms in a precision with unit roundoff
+        u errs by at most about (number of terms) * u times it."""
+        a = np.abs(np.asarray(v, dtype=np.float64))
+        w = np.zeros_like(a)
+        for (q, r, c, o), (hl, hr) in zip(self.sectors, self.dense_sectors()):
+            dL, dR = r.size, c.size
+            V = a[o:o + dL * dR].reshape(dR, dL).T
+            W = np.abs(hl) @ V + V @ np.abs(hr).T
+            w[o:o + dL * dR] = W.T.reshape(-1)
+        for hc, pidx in self.central_groups():
+            w[pidx] += np.abs(hc) @ a[pidx]
         return w
 
     # ---------------------------------------------------------------- helpers

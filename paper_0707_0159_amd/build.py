@@ -17,7 +17,8 @@ LIB = os.path.join(HERE, "libd2d.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["core.cpp", "superblock.cpp", "lanczos.cpp", "density.cpp", "batch.cpp", "kernels_hv.hip", "kernels_lanczos.hip"]
+SOURCES = ["core.cpp", "superblock.cpp", "lanczos.cpp", "density.cpp", "batch.cpp", "kernels_hv.hip", "kernels_lanczos.hip",
+           "kernels_dmrg.hip", "observables.cpp"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",

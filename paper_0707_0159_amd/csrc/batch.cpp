@@ -52,6 +52,7 @@ struct d2d_batch {
     void* d_w2 = nullptr;               // ntot doubles, central-term part of fused launches
     void* stage_v = nullptr;
     void* stage_w = nullptr;
+    uint64_t builds = 0;                // work lists built so far (a rebuild reshapes the launches)
     LanczosWork* lz = nullptr;
     ~d2d_batch();
 };
@@ -90,11 +91,14 @@ int batch_shape(const d2d_batch* b, int prec) {
 // Launch tables of the active problems (work list of one shape, split level,
 // order and step choice; central and pack tiles).
 d2d_status build_work(d2d_batch* b, int key) {
+    b->builds++;
     std::vector<int> keep(b->pairs.size());
     for (size_t p = 0; p < b->pairs.size(); ++p) keep[p] = b->active[b->pair_prob[p]];
     WorkHost h;
-    make_work(b->pairs, &keep, tile_shape(key & 0xFFFF), (key >> 16) & 3, (key >> 18) & 1,
-              ((key >> 19) & 1) ? nullptr : &b->nz, h);
+    const int split = (key >> 16) & 3;
+    make_work(b->pairs, &keep, tile_shape(key & 0xFFFF), split, (key >> 18) & 1,
+              ((key >> 19) & 1) ? nullptr : &b->nz, h,
+              split == 3 ? &tile_shape(asym_partner(key & 0xFFFF)) : nullptr);
     return upload_work(b->ctx, h, b->work[key]);
 }
 
@@ -214,6 +218,9 @@ struct BatchHv : HvOps {
     bool has(int prec) override { return (b->prec_mask & (1u << prec)) && b->HL[prec]; }
     void count(int prec, int64_t n) override { b->hv_count[prec] += n; }
     int64_t counter(int prec) override { return b->hv_count[prec]; }
+    uint64_t fingerprint() override {
+        return config_fingerprint(b->tile_sel, b->split, b->fuse, b->xcd, b->dense, b->d_x, b->d_w2, b->builds);
+    }
 };
 
 }  // namespace

@@ -279,8 +279,15 @@ extern "C" d2d_status d2d_ctx_destroy(d2d_ctx* ctx) {
         set_error("d2d_ctx_destroy: %d live objects still use this context", ctx->children);
         return D2D_ESTATE;
     }
+    // work the context queued (asynchronous products, copies) ends before the
+    // context does: nothing of it may run on into the runtime's teardown
+    const hipError_t e = hipStreamSynchronize(ctx->stream);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
+    if (e != hipSuccess) {
+        set_error("d2d_ctx_destroy: work queued on the context's stream failed: %s", hipGetErrorString(e));
+        return D2D_EDEVICE;
+    }
     return D2D_OK;
 }
 

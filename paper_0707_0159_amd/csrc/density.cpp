@@ -1,19 +1,27 @@
 // Reduced density matrix of one half of the superblock state and the block
-// of the next DMRG step (the paper's density-matrix formation and
-// diagonalisation routines, DMF and DMD).
+// of the next DMRG step: the paper's density-matrix formation (DMF), its
+// diagonalisation (DMD), and the renormalisation of the enlarged half's
+// operators onto the kept states.
 //
 //   side 0: rho_L[q_L] = V[q] V[q]^T  over block 1 (x) column 2
 //   side 1: rho_R[q_R] = V[q]^T V[q]  over column 3 (x) block 4
 //
-// Each sector of rho is formed and diagonalised on the device (rocSOLVER
-// dsyevd, FP64).  The m_keep eigenvectors of largest weight are kept (ties:
-// sector ascending, then index in the sector ascending); the enlarged half's
-// Hamiltonian is projected on the device, H' = U^T H U, and the operators of
-// the new edge column (one nonzero per row) by a gather on the host.
+// DMF: every sector's rho is one problem of a grouped FP64 matrix-core GEMM
+// (one launch).  DMD: each sector is diagonalised on the device (rocSOLVER
+// dsyevd, FP64, all sectors queued back to back on the stream, one host
+// synchronisation); the m_keep eigenvectors of largest weight are kept (ties:
+// sector ascending, then index in the sector ascending).  Renormalisation:
+// the kept columns are gathered on the device with their sign fixed (entry of
+// largest modulus positive), H' = U^T (H U) per sector as two grouped GEMM
+// launches, and the new edge column's operators (one nonzero per row in the
+// half basis) as a row gather G = O U_from followed by E' = U_to^T G, one
+// grouped launch for all of them.  Only the small results (H', E') come back
+// to the host, where the block object lives.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <numeric>
 
@@ -23,24 +31,56 @@ using namespace d2d;
 
 namespace {
 
-struct DevVec {
+// A device buffer charged to the context, freed at scope exit.
+template <typename T>
+struct DevBuf {
     d2d_ctx* ctx;
-    double* p = nullptr;
+    T* p = nullptr;
     size_t n = 0;
-    explicit DevVec(d2d_ctx* c) : ctx(c) {}
+    explicit DevBuf(d2d_ctx* c) : ctx(c) {}
     d2d_status alloc(size_t count) {
-        n = count;
-        return ctx->alloc((void**)&p, n * 8);
+        n = std::max<size_t>(count, 1);
+        return ctx->alloc((void**)&p, n * sizeof(T));
     }
-    ~DevVec() {
-        if (p) ctx->free(p, n * 8);
+    d2d_status upload(const std::vector<T>& h) {
+        D2D_CHECK(alloc(h.size()));
+        if (!h.empty()) D2D_HIP(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+        return D2D_OK;
+    }
+    ~DevBuf() {
+        if (p) ctx->free(p, n * sizeof(T));
     }
 };
 
+// Tiles of a list of GEMM problems (64 x 64 output tiles, problem-major).
+std::vector<int4> gemm_tiles(const std::vector<GemmProb>& probs) {
+    std::vector<int4> t;
+    for (size_t i = 0; i < probs.size(); ++i)
+        for (int j = 0; j < (probs[i].N + 63) / 64; ++j)
+            for (int r = 0; r < (probs[i].M + 63) / 64; ++r) t.push_back(make_int4((int)i, r, j, 0));
+    return t;
+}
+
+d2d_status grouped_gemm(d2d_ctx* ctx, const std::vector<GemmProb>& probs, hipStream_t s) {
+    if (probs.empty()) return D2D_OK;
+    const std::vector<int4> tiles = gemm_tiles(probs);
+    DevBuf<GemmProb> dp(ctx);
+    DevBuf<int4> dt(ctx);
+    D2D_CHECK(dp.upload(probs));
+    D2D_CHECK(dt.upload(tiles));
+    D2D_HIP(launch_gemm_f64(dp.p, dt.p, (int)tiles.size(), s));
+    D2D_HIP(hipStreamSynchronize(s));   // the tables are freed at return
+    return D2D_OK;
+}
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
 }  // namespace
 
-extern "C" d2d_status d2d_density_matrix(d2d_sb* sb, const double* psi, int side, int m_keep, d2d_block** new_block,
-                                         double* trunc_err, double* spectrum, int64_t* spectrum_len) {
+static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_keep, d2d_block** new_block,
+                               double* trunc_err, double* spectrum, int64_t* spectrum_len, double* ms) {
     if (!sb || !psi || !new_block || !trunc_err || (side != 0 && side != 1) || m_keep < 1) {
         set_error("d2d_density_matrix: bad argument");
         return D2D_EINVAL;
@@ -49,6 +89,40 @@ extern "C" d2d_status d2d_density_matrix(d2d_sb* sb, const double* psi, int side
     d2d_ctx* ctx = sb->ctx;
     hipStream_t s = ctx->stream;
     const int np = (int)sb->pairs.size();
+    D2D_HIP(hipStreamSynchronize(s));   // phases are timed from here
+    auto t0 = std::chrono::steady_clock::now();
+
+    // ---- DMF: rho per sector, one grouped GEMM launch
+    std::vector<int> dim(np);
+    std::vector<int64_t> roff(np + 1, 0);
+    for (int p = 0; p < np; ++p) {
+        dim[p] = side == 0 ? sb->pairs[p].dL : sb->pairs[p].dR;
+        roff[p + 1] = roff[p] + (int64_t)dim[p] * dim[p];
+    }
+    DevBuf<double> rho(ctx), ev(ctx);
+    D2D_CHECK(rho.alloc((size_t)roff[np]));
+    {
+        std::vector<GemmProb> probs;
+        for (int p = 0; p < np; ++p) {
+            const SectorDev& q = sb->pairs[p];
+            GemmProb g{};
+            g.A = psi + q.off;
+            g.B = psi + q.off;
+            g.C = rho.p + roff[p];
+            g.M = g.N = dim[p];
+            g.K = side == 0 ? q.dR : q.dL;
+            g.lda = g.ldb = q.dL;
+            g.ldc = dim[p];
+            g.ta = side == 0 ? 0 : 1;   // side 0: V V^T; side 1: V^T V
+            g.tb = side == 0 ? 1 : 0;
+            probs.push_back(g);
+        }
+        D2D_CHECK(grouped_gemm(ctx, probs, s));
+    }
+    const double t_dmf = seconds_since(t0);
+    auto t1 = std::chrono::steady_clock::now();
+
+    // ---- DMD: eigenpairs of every sector (ascending eigenvalues, vectors in place)
     rocblas_handle h = nullptr;
     if (rocblas_create_handle(&h) != rocblas_status_success) {
         set_error("rocblas_create_handle failed");
@@ -59,50 +133,39 @@ extern "C" d2d_status d2d_density_matrix(d2d_sb* sb, const double* psi, int side
         ~HGuard() { rocblas_destroy_handle(h); }
     } hg{h};
     rocblas_set_stream(h, s);
-
-    // 1. rho per sector and its eigendecomposition (ascending eigenvalues)
-    std::vector<int> dim(np);
-    std::vector<size_t> roff(np + 1, 0);
-    for (int p = 0; p < np; ++p) {
-        dim[p] = side == 0 ? sb->pairs[p].dL : sb->pairs[p].dR;
-        roff[p + 1] = roff[p] + (size_t)dim[p] * dim[p];
-    }
-    int dmax = *std::max_element(dim.begin(), dim.end());
-    DevVec rho(ctx), ev(ctx), work(ctx);
-    D2D_CHECK(rho.alloc(roff[np]));
+    const int dmax = *std::max_element(dim.begin(), dim.end());
     size_t nev = 0;
-    for (int p = 0; p < np; ++p) nev += dim[p];
-    D2D_CHECK(ev.alloc(nev));
-    D2D_CHECK(work.alloc((size_t)dmax + 1));
-    rocblas_int* info = nullptr;
-    D2D_CHECK(ctx->alloc((void**)&info, sizeof(rocblas_int) * 4));
-    struct IGuard {
-        d2d_ctx* c;
-        rocblas_int* p;
-        ~IGuard() { c->free(p, sizeof(rocblas_int) * 4); }
-    } ig{ctx, info};
-    size_t eoff = 0;
     std::vector<size_t> evoff(np);
     for (int p = 0; p < np; ++p) {
-        const SectorDev& q = sb->pairs[p];
-        D2D_HIP(launch_syrk_f64(psi + q.off, q.dL, q.dR, side, rho.p + roff[p], s));
-        evoff[p] = eoff;
+        evoff[p] = nev;
+        nev += dim[p];
+    }
+    D2D_CHECK(ev.alloc(nev));
+    DevBuf<double> work(ctx);
+    D2D_CHECK(work.alloc((size_t)dmax + 1));
+    DevBuf<rocblas_int> info(ctx);
+    D2D_CHECK(info.alloc((size_t)np));
+    for (int p = 0; p < np; ++p)
         if (rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_lower, dim[p], rho.p + roff[p], dim[p],
-                             ev.p + eoff, work.p, info) != rocblas_status_success) {
+                             ev.p + evoff[p], work.p, info.p + p) != rocblas_status_success) {
             set_error("rocsolver_dsyevd failed on sector %d (dim %d)", p, dim[p]);
             return D2D_EDEVICE;
         }
-        eoff += dim[p];
-    }
     std::vector<double> evh(nev);
+    std::vector<rocblas_int> infoh(np);
     D2D_HIP(hipMemcpyAsync(evh.data(), ev.p, nev * 8, hipMemcpyDeviceToHost, s));
+    D2D_HIP(hipMemcpyAsync(infoh.data(), info.p, sizeof(rocblas_int) * np, hipMemcpyDeviceToHost, s));
     D2D_HIP(hipStreamSynchronize(s));
-
-    // 2. selection: descending weight, ties by (sector ascending, index ascending);
-    //    inside a sector rocSOLVER's order is ascending, so index i of the
-    //    descending list is column dim-1-i
-    // rank of each pair's half sector in ascending quantum number: pairs are in
-    // ascending q_L, so q_R = Q - q_L descends along them
+    for (int p = 0; p < np; ++p)
+        if (infoh[p] != 0) {
+            set_error("density-matrix eigensolve of sector %d (dim %d) did not converge (info %d)", p, dim[p],
+                      (int)infoh[p]);
+            return D2D_EDEVICE;
+        }
+    // selection: descending weight, ties by (sector ascending, index ascending);
+    // inside a sector rocSOLVER's order is ascending, so index i of the
+    // descending list is column dim-1-i.  Pairs are in ascending q_L, so on
+    // side 1 q_R = Q - q_L descends along them.
     std::vector<int> rank(np);
     for (int p = 0; p < np; ++p) rank[p] = side == 0 ? p : np - 1 - p;
     struct Cand {
@@ -132,13 +195,17 @@ extern "C" d2d_status d2d_density_matrix(d2d_sb* sb, const double* psi, int side
         wsum += cand[k].w;
     }
     *trunc_err = std::max(0.0, 1.0 - wsum);
-    // the half's sectors in ascending quantum number are the pairs in order (side 0)
-    // or in reverse order (side 1: q_R = Q - q_L descends as q_L ascends)
+    const double t_dmd = seconds_since(t1);
+    auto t2 = std::chrono::steady_clock::now();
+
+    // ---- renormalisation
+    // the half's sectors in ascending quantum number: the pairs in order (side
+    // 0) or in reverse order (side 1)
     std::vector<int> order(np);
     std::iota(order.begin(), order.end(), 0);
     if (side == 1) std::reverse(order.begin(), order.end());
-
-    // 3. U columns per kept sector (host copies), H' = U^T H U on the device
+    std::vector<int> start(np, 0), cnt(np, 0);
+    std::vector<int64_t> uoff(np + 1, 0), hoff(np + 1, 0);
     const Column col = make_column(sb->model);
     const int n = sb->n, m = sb->m;
     auto nb = std::make_unique<d2d_block>();
@@ -149,68 +216,96 @@ extern "C" d2d_status d2d_density_matrix(d2d_sb* sb, const double* psi, int side
     nb->H = Mat(keep, keep);
     nb->keys = col.keys;
     nb->ops.assign(col.keys.size(), Mat(keep, keep));
-    std::vector<int> start(np, 0), cnt(np, 0);
-    std::vector<std::vector<double>> U(np);     // dim x cnt, column-major
     int pos = 0;
+    std::vector<int4> sel;
+    std::vector<int64_t> seloff;
     for (int oi = 0; oi < np; ++oi) {
         const int p = order[oi];
         std::sort(kept[p].begin(), kept[p].end());
         start[p] = pos;
         cnt[p] = (int)kept[p].size();
-        if (cnt[p] == 0) continue;
-        const int d = dim[p];
-        std::vector<double> Z((size_t)d * d);
-        D2D_HIP(hipMemcpy(Z.data(), rho.p + roff[p], (size_t)d * d * 8, hipMemcpyDeviceToHost));
-        U[p].resize((size_t)d * cnt[p]);
-        for (int c = 0; c < cnt[p]; ++c) {
-            const int srccol = d - 1 - kept[p][c];
-            // sign: largest-modulus component positive
-            double best = 0.0;
-            int bi = 0;
-            for (int r = 0; r < d; ++r)
-                if (std::fabs(Z[(size_t)srccol * d + r]) > std::fabs(best)) {
-                    best = Z[(size_t)srccol * d + r];
-                    bi = r;
-                }
-            (void)bi;
-            const double sg = best < 0.0 ? -1.0 : 1.0;
-            for (int r = 0; r < d; ++r) U[p][(size_t)c * d + r] = sg * Z[(size_t)srccol * d + r];
-        }
+        pos += cnt[p];
         const QN q = side == 0 ? sb->pair_q[p] : QN{sb->Q[0] - sb->pair_q[p].first, sb->Q[1] - sb->pair_q[p].second};
         for (int c = 0; c < cnt[p]; ++c) nb->qn.push_back(q);
-        // H' block on the device: T = H U, H' = U^T T  (H_r is stored transposed; it is symmetric)
-        const double* Hd = side == 0 ? (const double*)sb->HL[0] + sb->pairs[p].hl_off
-                                     : (const double*)sb->HR[0] + sb->pairs[p].hr_off;
-        DevVec Ud(ctx), T(ctx), Hp(ctx);
-        D2D_CHECK(Ud.alloc((size_t)d * cnt[p]));
-        D2D_CHECK(T.alloc((size_t)d * cnt[p]));
-        D2D_CHECK(Hp.alloc((size_t)cnt[p] * cnt[p]));
-        D2D_HIP(hipMemcpy(Ud.p, U[p].data(), (size_t)d * cnt[p] * 8, hipMemcpyHostToDevice));
-        D2D_HIP(launch_gemm_nn_f64(Hd, d, Ud.p, d, T.p, d, d, cnt[p], d, side == 1 ? 1 : 0, s));
-        D2D_HIP(launch_gemm_nn_f64(Ud.p, d, T.p, d, Hp.p, cnt[p], cnt[p], cnt[p], d, 1, s));
-        std::vector<double> hp((size_t)cnt[p] * cnt[p]);
-        D2D_HIP(hipMemcpyAsync(hp.data(), Hp.p, hp.size() * 8, hipMemcpyDeviceToHost, s));
-        D2D_HIP(hipStreamSynchronize(s));
-        for (int j = 0; j < cnt[p]; ++j)
-            for (int i = 0; i < cnt[p]; ++i) nb->H(pos + i, pos + j) = hp[(size_t)j * cnt[p] + i];
-        pos += cnt[p];
     }
-    // 4. edge operators of the new block: the new column's site operators in the
-    //    half basis (left: c (x) P_block with the block's string; right: c (x) 1),
-    //    projected: E'[to, from] = U_to^T O U_from.  O has one nonzero per row.
+    for (int p = 0; p < np; ++p) {
+        uoff[p + 1] = uoff[p] + (int64_t)dim[p] * cnt[p];
+        hoff[p + 1] = hoff[p] + (int64_t)cnt[p] * cnt[p];
+        for (int c = 0; c < cnt[p]; ++c) {
+            sel.push_back(make_int4(dim[p], dim[p] - 1 - kept[p][c], (int)(seloff.size() / 2), 0));
+            seloff.push_back(roff[p]);
+            seloff.push_back(uoff[p] + (int64_t)c * dim[p]);
+        }
+    }
+    DevBuf<double> U(ctx), T(ctx), Hp(ctx);
+    D2D_CHECK(U.alloc((size_t)uoff[np]));
+    D2D_CHECK(T.alloc((size_t)uoff[np]));
+    D2D_CHECK(Hp.alloc((size_t)hoff[np]));
+    {
+        DevBuf<int4> dsel(ctx);
+        DevBuf<int64_t> doff(ctx);
+        D2D_CHECK(dsel.upload(sel));
+        D2D_CHECK(doff.upload(seloff));
+        D2D_HIP(launch_pick_columns(dsel.p, (int)sel.size(), doff.p, rho.p, U.p, s));
+        D2D_HIP(hipStreamSynchronize(s));
+    }
+    // H' = U^T (H U): H_l as stored (column-major), H_r through its stored transpose
+    {
+        std::vector<GemmProb> p1, p2;
+        for (int p = 0; p < np; ++p) {
+            if (!cnt[p]) continue;
+            const int d = dim[p];
+            GemmProb g{};
+            g.A = side == 0 ? (const double*)sb->HL[0] + sb->pairs[p].hl_off
+                            : (const double*)sb->HR[0] + sb->pairs[p].hr_off;
+            g.B = U.p + uoff[p];
+            g.C = T.p + uoff[p];
+            g.M = d;
+            g.N = cnt[p];
+            g.K = d;
+            g.lda = g.ldb = g.ldc = d;
+            g.ta = side;
+            g.tb = 0;
+            p1.push_back(g);
+            GemmProb g2{};
+            g2.A = U.p + uoff[p];
+            g2.B = T.p + uoff[p];
+            g2.C = Hp.p + hoff[p];
+            g2.M = g2.N = cnt[p];
+            g2.K = d;
+            g2.lda = g2.ldb = d;
+            g2.ldc = cnt[p];
+            g2.ta = 1;
+            g2.tb = 0;
+            p2.push_back(g2);
+        }
+        D2D_CHECK(grouped_gemm(ctx, p1, s));
+        D2D_CHECK(grouped_gemm(ctx, p2, s));
+    }
+    // edge operators: for operator o and target sector pt, G = O U_from (rows
+    // of the half basis gathered from the source sector pf with the
+    // operator's value, times the block parity for a left Hubbard block),
+    // then E'[pt, pf] = U_pt^T G
     const std::vector<int32_t>* halves = side == 0 ? sb->rowsL.data() : sb->colsR.data();
-    std::vector<std::vector<int32_t>> posin(np);
     std::vector<int> sector_of_half((size_t)m * n, -1), pos_of_half((size_t)m * n, -1);
     for (int p = 0; p < np; ++p)
         for (size_t i = 0; i < halves[p].size(); ++i) {
             sector_of_half[halves[p][i]] = p;
             pos_of_half[halves[p][i]] = (int)i;
         }
-    // parity of the block states of this half (block 1 for side 0)
     const std::vector<QN>& bq = side == 0 ? sb->qn1 : sb->qn4;
+    struct Entry {
+        int o, pt, pf;
+    };
+    std::vector<Entry> ents;
+    std::vector<int4> ent4;
+    std::vector<int64_t> eoffs;          // per entry: row map offset, U_from offset, G offset
+    std::vector<int32_t> rmap;
+    std::vector<double> rval;
+    std::vector<int64_t> goff(1, 0), eout(1, 0);
+    int64_t maxn = 0;
     for (size_t o = 0; o < col.keys.size(); ++o) {
         const Mat& cop = col.ops[o];
-        // row map of the column operator
         std::vector<int> src(n, -1);
         std::vector<double> val(n, 0.0);
         for (int a = 0; a < n; ++a)
@@ -219,30 +314,90 @@ extern "C" d2d_status d2d_density_matrix(d2d_sb* sb, const double* psi, int side
                     src[a] = a2;
                     val[a] = cop(a, a2);
                 }
-        Mat& E = nb->ops[o];
         for (int pt = 0; pt < np; ++pt) {
             if (!cnt[pt]) continue;
             const int dt = dim[pt];
-            // T[row, c] = O[row, :] U_from[:, c] for every source sector
+            // the source sectors the rows of pt reach (one, since the operator
+            // shifts the quantum numbers by a fixed amount; grouped anyway)
+            std::vector<int> rows_pf(dt, -1), rows_pos(dt, -1);
+            std::vector<double> rows_v(dt, 0.0);
+            std::vector<int> pfs;
             for (int r = 0; r < dt; ++r) {
                 const int hrow = halves[pt][r], a = hrow / m, b = hrow % m;
                 if (src[a] < 0) continue;
                 double v = val[a];
-                if (sb->model.kind == D2D_HUBBARD && side == 0)
-                    v *= ((bq[b].first + bq[b].second) & 1) ? -1.0 : 1.0;
+                if (sb->model.kind == D2D_HUBBARD && side == 0) v *= ((bq[b].first + bq[b].second) & 1) ? -1.0 : 1.0;
                 const int hsrc = src[a] * m + b;
                 const int pf = sector_of_half[hsrc];
                 if (pf < 0 || !cnt[pf]) continue;
-                const int rf = pos_of_half[hsrc];
-                // E'[start[pt]+i, start[pf]+j] += U_to[r, i] * v * U_from[rf, j]
-                for (int i = 0; i < cnt[pt]; ++i) {
-                    const double ut = U[pt][(size_t)i * dt + r] * v;
-                    if (ut == 0.0) continue;
-                    for (int j = 0; j < cnt[pf]; ++j)
-                        E(start[pt] + i, start[pf] + j) += ut * U[pf][(size_t)j * dim[pf] + rf];
+                rows_pf[r] = pf;
+                rows_pos[r] = pos_of_half[hsrc];
+                rows_v[r] = v;
+                if (std::find(pfs.begin(), pfs.end(), pf) == pfs.end()) pfs.push_back(pf);
+            }
+            for (int pf : pfs) {
+                const int64_t mo = (int64_t)rmap.size();
+                for (int r = 0; r < dt; ++r) {
+                    rmap.push_back(rows_pf[r] == pf ? rows_pos[r] : -1);
+                    rval.push_back(rows_pf[r] == pf ? rows_v[r] : 0.0);
                 }
+                const int e = (int)ents.size();
+                ents.push_back({(int)o, pt, pf});
+                ent4.push_back(make_int4(dt, cnt[pf], e, dim[pf]));
+                eoffs.push_back(mo);
+                eoffs.push_back(uoff[pf]);
+                eoffs.push_back(goff.back());
+                maxn = std::max<int64_t>(maxn, (int64_t)dt * cnt[pf]);
+                goff.push_back(goff.back() + (int64_t)dt * cnt[pf]);
+                eout.push_back(eout.back() + (int64_t)cnt[pt] * cnt[pf]);
             }
         }
+    }
+    DevBuf<double> G(ctx), E(ctx);
+    D2D_CHECK(G.alloc((size_t)goff.back()));
+    D2D_CHECK(E.alloc((size_t)eout.back()));
+    {
+        DevBuf<int4> dent(ctx);
+        DevBuf<int64_t> doffs(ctx);
+        DevBuf<int32_t> dmap(ctx);
+        DevBuf<double> dval(ctx);
+        D2D_CHECK(dent.upload(ent4));
+        D2D_CHECK(doffs.upload(eoffs));
+        D2D_CHECK(dmap.upload(rmap));
+        D2D_CHECK(dval.upload(rval));
+        D2D_HIP(launch_gather_rows(dent.p, (int)ent4.size(), maxn, doffs.p, dmap.p, dval.p, U.p, G.p, s));
+        std::vector<GemmProb> pe;
+        for (size_t e = 0; e < ents.size(); ++e) {
+            const Entry& x = ents[e];
+            GemmProb g{};
+            g.A = U.p + uoff[x.pt];
+            g.B = G.p + goff[e];
+            g.C = E.p + eout[e];
+            g.M = cnt[x.pt];
+            g.N = cnt[x.pf];
+            g.K = dim[x.pt];
+            g.lda = g.ldb = dim[x.pt];
+            g.ldc = cnt[x.pt];
+            g.ta = 1;
+            g.tb = 0;
+            pe.push_back(g);
+        }
+        D2D_CHECK(grouped_gemm(ctx, pe, s));
+    }
+    // results to the host block
+    std::vector<double> hh((size_t)hoff[np]), eh((size_t)eout.back());
+    if (!hh.empty()) D2D_HIP(hipMemcpyAsync(hh.data(), Hp.p, hh.size() * 8, hipMemcpyDeviceToHost, s));
+    if (!eh.empty()) D2D_HIP(hipMemcpyAsync(eh.data(), E.p, eh.size() * 8, hipMemcpyDeviceToHost, s));
+    D2D_HIP(hipStreamSynchronize(s));
+    for (int p = 0; p < np; ++p)
+        for (int j = 0; j < cnt[p]; ++j)
+            for (int i = 0; i < cnt[p]; ++i) nb->H(start[p] + i, start[p] + j) = hh[hoff[p] + (int64_t)j * cnt[p] + i];
+    for (size_t e = 0; e < ents.size(); ++e) {
+        const Entry& x = ents[e];
+        Mat& M = nb->ops[x.o];
+        for (int j = 0; j < cnt[x.pf]; ++j)
+            for (int i = 0; i < cnt[x.pt]; ++i)
+                M(start[x.pt] + i, start[x.pf] + j) += eh[eout[e] + (int64_t)j * cnt[x.pt] + i];
     }
     // sectors of the new block
     for (int i = 0; i < nb->m; ++i) {
@@ -254,7 +409,28 @@ extern "C" d2d_status d2d_density_matrix(d2d_sb* sb, const double* psi, int side
         nb->sec_dim.back()++;
     }
     nb->ncols = (side == 0 ? sb->ncols1 : sb->ncols4) + 1;
+    const double t_ren = seconds_since(t2);
+    if (ms) {
+        ms[0] = t_dmf * 1e3;
+        ms[1] = t_dmd * 1e3;
+        ms[2] = t_ren * 1e3;
+    }
     ctx->children++;
     *new_block = nb.release();
     return D2D_OK;
+}
+
+extern "C" d2d_status d2d_density_matrix(d2d_sb* sb, const double* psi, int side, int m_keep, d2d_block** new_block,
+                                         double* trunc_err, double* spectrum, int64_t* spectrum_len) {
+    return density_impl(sb, psi, side, m_keep, new_block, trunc_err, spectrum, spectrum_len, nullptr);
+}
+
+extern "C" d2d_status d2d_density_matrix_timed(d2d_sb* sb, const double* psi, int side, int m_keep,
+                                               d2d_block** new_block, double* trunc_err, double* spectrum,
+                                               int64_t* spectrum_len, double ms[3]) {
+    if (!ms) {
+        set_error("d2d_density_matrix_timed: ms is NULL");
+        return D2D_EINVAL;
+    }
+    return density_impl(sb, psi, side, m_keep, new_block, trunc_err, spectrum, spectrum_len, ms);
 }

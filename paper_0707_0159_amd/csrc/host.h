@@ -103,10 +103,10 @@ struct LanczosWork {
     int2* prange = nullptr;
     int* active = nullptr;
     // captured restarts, two per precision: index 2 prec + 0 for the full
-    // cycle, 2 prec + 1 for a shortened one; graph_k is the cycle length
+    // cycle, 2 prec + 1 for a shortened one
     hipGraphExec_t exec[2 * D2D_NPREC] = {};
     hipGraph_t graph[2 * D2D_NPREC] = {};
-    int graph_k[2 * D2D_NPREC] = {};
+    uint64_t graph_key[2 * D2D_NPREC] = {};   // what the capture was made for (see restart)
 };
 
 namespace d2d {
@@ -140,6 +140,7 @@ struct WorkHost {
     std::vector<WorkItem> items;
     std::vector<int32_t> ksteps;
     double flops = 0;
+    int n0 = -1;   // asymmetric split: items [0, n0) in the lead shape, the rest in its partner
 };
 // A work list on the device.
 struct WorkList {
@@ -148,6 +149,7 @@ struct WorkList {
     int n = 0, nsteps = 0;
     size_t cap_items = 0, cap_steps = 0;
     double flops = 0;   // GEMM flops of one launch over the list
+    int n0 = -1;        // asymmetric split: items of the lead shape (the rest: its partner)
 };
 // stages of one Hv launch sequence (a whole product is all three)
 constexpr int HV_PACK = 1, HV_GEMM = 2, HV_CENTRAL = 4, HV_ALL = 7;
@@ -174,7 +176,33 @@ struct HvOps {
     virtual bool has(int prec) = 0;
     virtual void count(int prec, int64_t n) = 0;
     virtual int64_t counter(int prec) = 0;
+    // fingerprint of everything a captured launch sequence depends on beyond
+    // the Lanczos workspace: launch configuration per precision, partial-output
+    // buffers, work-list builds; a captured restart is replayed only while it holds
+    virtual uint64_t fingerprint() = 0;
 };
+// FNV-1a over 64-bit words (launch-configuration fingerprints)
+inline uint64_t fnv_mix(uint64_t h, uint64_t x) {
+    for (int i = 0; i < 8; ++i) {
+        h ^= (x >> (8 * i)) & 0xffu;
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+inline uint64_t config_fingerprint(const int* tile, const int* split, const int* fuse, const int* xcd,
+                                   const int* dense, void* const* parts, const void* w2, uint64_t builds) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (int p = 0; p < D2D_NPREC; ++p) {
+        h = fnv_mix(h, (uint64_t)(int64_t)tile[p]);
+        h = fnv_mix(h, (uint64_t)split[p]);
+        h = fnv_mix(h, (uint64_t)fuse[p]);
+        h = fnv_mix(h, (uint64_t)xcd[p]);
+        h = fnv_mix(h, (uint64_t)dense[p]);
+    }
+    for (int i = 0; i < 3; ++i) h = fnv_mix(h, (uint64_t)(uintptr_t)parts[i]);
+    h = fnv_mix(h, (uint64_t)(uintptr_t)w2);
+    return fnv_mix(h, builds);
+}
 }  // namespace d2d
 
 struct d2d_sb {
@@ -266,14 +294,16 @@ d2d_status sb_work(d2d_sb* sb, int shape, int split, int xcd, int dense, const W
 // upload a host work list into wl (reusing its buffers when large enough)
 d2d_status upload_work(d2d_ctx* ctx, const WorkHost& h, WorkList& wl);
 void free_work(d2d_ctx* ctx, WorkList& wl);
-// number of partial outputs of a split level (0, 1, 3)
-inline int split_parts(int split) { return split == 0 ? 0 : (split == 1 ? 1 : 3); }
+// number of partial outputs of a split level (0 none, 1 two K-loops, 2 halves,
+// 3 two K-loops in asymmetric tiles): 0, 1, 3, 1
+inline int split_parts(int split) { return split == 0 ? 0 : (split == 2 ? 3 : 1); }
 // work items of the pairs with keep[p] != 0 for a tile shape; split level 0:
 // one item per output tile, 1: one per K-loop, 2: one per half K-loop
 // xcd: the XCD-aware order (rectangles of each pair's tiles per XCD, interleaved, padded with p = -1)
 // nz: zero pattern of the operators (K steps whose operator tile is zero are
 // left out), or null for every step
+// split 3: the V H_r^T items in shape ts1 (the partner of ts), after the H_l V items
 void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep, const TileShape& ts, int split, int xcd,
-               const NzCells* nz, WorkHost& out);
+               const NzCells* nz, WorkHost& out, const TileShape* ts1 = nullptr);
 void free_lanczos(d2d_sb* sb);
 }  // namespace d2d

@@ -70,6 +70,9 @@ struct TileShape {
 };
 int tile_shape_count();
 const TileShape& tile_shape(int i);
+// the shape of the V H_r^T items when shape i leads an asymmetric split (the
+// next entry of the table, i's transpose), or -1
+int asym_partner(int i);
 
 // ---------------------------------------------------------------- launchers
 // Central term W += sum_k c_k A_k V B_k^T.  Every A_k (column 2) and B_k
@@ -173,7 +176,6 @@ hipError_t launch_cast_f32_bf16(const float* x, bf16_t* y, int64_t n, hipStream_
 hipError_t launch_fill(void* x, int prec, int64_t n, double v, hipStream_t s);
 // reads the (nullable) parts[0..4) of a fused product (FP64 for FP64, else FP32)
 hipError_t launch_read_parts(const void* const* parts, int prec, int64_t n, void* sink, hipStream_t s);
-hipError_t launch_check_finite(const void* x, int prec, int64_t n, int* flag, hipStream_t s);
 
 // ---------------------------------------------------------------- Lanczos kernels
 
@@ -255,10 +257,29 @@ hipError_t launch_lz_first(const LzSet& z, const double* x, const double* w, voi
 // lowest eigenpair of each problem's k x k tridiagonal (theta at S_THETA+1, y at S_Y)
 hipError_t launch_lz_tridiag(const LzSet& z, int k, hipStream_t s);
 
-// density matrix: rho = V V^T (side 0) or V^T V (side 1) of a dL x dR block
-hipError_t launch_syrk_f64(const double* V, int dL, int dR, int side, double* rho, hipStream_t s);
-// out (rows x k) = A (rows x rows, col-major) * B (rows x k)
-hipError_t launch_gemm_nn_f64(const double* A, int lda, const double* B, int ldb, double* C, int ldc,
-                              int M, int N, int K, int transA, hipStream_t s);
+// Column densities (kernels_dmrg.hip): per column 2 and 3, DENS_SLOTS - 1
+// occupation-bit sums and the total weight of psi^2; gx blocks per pair, sums
+// in partial[(p * gx + x) * 2 * DENS_SLOTS + slot]
+constexpr int DENS_SLOTS = 9;
+hipError_t launch_col_dens(const SectorDev* sec, int npairs, int gx, const int32_t* rowsL, const int32_t* colsR, int m,
+                           int nbits, const double* psi, double* partial, hipStream_t s);
+
+// Grouped FP64 GEMM on the matrix cores: C = op(A) op(B), column-major, one
+// 64 x 64 tile per work-group; tiles[i] = (problem, tile row, tile column, 0)
+struct GemmProb {
+    const double* A;
+    const double* B;
+    double* C;
+    int M, N, K, lda, ldb, ldc;
+    int ta, tb;   // 1: the operand is used transposed
+};
+hipError_t launch_gemm_f64(const GemmProb* probs, const int4* tiles, int ntiles, hipStream_t s);
+// kept density-matrix eigenvectors: sel[j] = (rows, source column, offsets index, 0),
+// offs[2i] source matrix offset in Z, offs[2i+1] destination of the column in U
+hipError_t launch_pick_columns(const int4* sel, int ncols, const int64_t* offs, const double* Z, double* U,
+                               hipStream_t s);
+// G = O U_from row gathers: ent[e] = (rows, columns, offsets index, U_from leading dim)
+hipError_t launch_gather_rows(const int4* ent, int nent, int64_t maxn, const int64_t* offs, const int32_t* src,
+                              const double* val, const double* U, double* G, hipStream_t s);
 
 }  // namespace d2d

@@ -665,6 +665,10 @@ hipError_t launch_hv_gemm_bf16(int shape, const HvGemmArgs& a, const void* VT, h
         case 32: gemm_bf16_launch<256, 128, 64, 4, 2, 1, false>(a, VT, st); break;
         case 33: gemm_bf16_launch<128, 256, 64, 2, 4, 1, false>(a, VT, st); break;
         case 34: gemm_bf16_launch<256, 128, 32, 4, 2, 1, true>(a, VT, st); break;
+        case 41: gemm_bf16_launch<64, 256, 32, 2, 2, 1, false>(a, VT, st); break;
+        case 42: gemm_bf16_launch<256, 64, 32, 2, 2, 1, false>(a, VT, st); break;
+        case 43: gemm_bf16_launch<64, 256, 32, 2, 2, 1, true>(a, VT, st); break;
+        case 44: gemm_bf16_launch<256, 64, 32, 2, 2, 1, true>(a, VT, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -865,10 +869,26 @@ static const TileShape kShapes[] = {
     {D2D_BF16X3, 256, 128, 32},   // 34
     {D2D_FP32, 256, 128, 16},     // 35
     {D2D_FP32, 128, 256, 16},     // 36
+    // pairs for the asymmetric K-loop split (D2D_TILE_ASYM): H_l V items in a
+    // tile of few rows (its K-step list follows them) and many columns, V H_r^T
+    // items in the transposed tile (few columns, many rows)
+    {D2D_FP32, 64, 256, 16, 2},   // 37: 4 waves of 32x128
+    {D2D_FP32, 256, 64, 16, 2},   // 38: 4 waves of 128x32
+    {D2D_FP64, 64, 128, 16, 2},   // 39: 4 waves of 32x64
+    {D2D_FP64, 128, 64, 16, 2},   // 40
+    {D2D_BF16, 64, 256, 32},      // 41: 4 waves of 32x128
+    {D2D_BF16, 256, 64, 32},      // 42
+    {D2D_BF16X3, 64, 256, 32},    // 43
+    {D2D_BF16X3, 256, 64, 32},    // 44
 };
 
 int tile_shape_count() { return (int)(sizeof(kShapes) / sizeof(kShapes[0])); }
 const TileShape& tile_shape(int i) { return kShapes[i]; }
+int asym_partner(int i) {
+    if (i < 0 || i + 1 >= tile_shape_count()) return -1;
+    const TileShape &a = kShapes[i], &b = kShapes[i + 1];
+    return a.prec == b.prec && a.BM == b.BN && a.BN == b.BM && a.BK == b.BK && a.PF == b.PF ? i + 1 : -1;
+}
 
 template <typename T, int BM, int BN, int BK, int WGM, int WGN, int PF>
 static void gemm_launch(const HvGemmArgs& a, hipStream_t st) {
@@ -919,6 +939,10 @@ hipError_t launch_hv_gemm(int shape, const HvGemmArgs& a, hipStream_t st) {
         case 24: gemm_launch<float, 128, 64, 16, 2, 2, 2>(a, st); break;
         case 35: gemm_launch<float, 256, 128, 16, 4, 2, 1>(a, st); break;
         case 36: gemm_launch<float, 128, 256, 16, 2, 4, 1>(a, st); break;
+        case 37: gemm_launch<float, 64, 256, 16, 2, 2, 2>(a, st); break;
+        case 38: gemm_launch<float, 256, 64, 16, 2, 2, 2>(a, st); break;
+        case 39: gemm_launch<double, 64, 128, 16, 2, 2, 2>(a, st); break;
+        case 40: gemm_launch<double, 128, 64, 16, 2, 2, 2>(a, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1046,30 +1070,6 @@ hipError_t launch_read_parts(const void* const* parts, int prec, int64_t n, void
         hipLaunchKernelGGL(k_read_parts<float>, dim3(grid_for(n)), dim3(256), 0, s, (const float*)parts[0],
                            (const float*)parts[1], (const float*)parts[2], (const float*)parts[3], n,
                            (float*)sink);
-    return hipGetLastError();
-}
-
-// flag[0] set to 1 if any element is NaN or Inf
-template <typename T>
-__global__ void k_check_finite(const T* __restrict__ x, int64_t n, int* flag) {
-    int bad = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        float f;
-        if constexpr (sizeof(T) == 2) f = bf16_to_f32(x[i]);
-        else f = (float)x[i];
-        if constexpr (sizeof(T) == 8) { if (!isfinite((double)x[i])) bad = 1; }
-        else if (!isfinite(f)) bad = 1;
-    }
-    if (bad) atomicOr(flag, 1);
-}
-
-hipError_t launch_check_finite(const void* x, int prec, int64_t n, int* flag, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    int g = grid_for(n);
-    if (g > 1024) g = 1024;
-    if (prec == D2D_FP64) hipLaunchKernelGGL(k_check_finite<double>, dim3(g), dim3(256), 0, s, (const double*)x, n, flag);
-    else if (prec == D2D_FP32) hipLaunchKernelGGL(k_check_finite<float>, dim3(g), dim3(256), 0, s, (const float*)x, n, flag);
-    else hipLaunchKernelGGL(k_check_finite<bf16_t>, dim3(g), dim3(256), 0, s, (const bf16_t*)x, n, flag);
     return hipGetLastError();
 }
 

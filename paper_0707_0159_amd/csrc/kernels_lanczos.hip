@@ -212,51 +212,6 @@ __device__ void tridiag_body(const double* __restrict__ alpha, const double* __r
     if (l == 0) *pred_out = fabs(beta[k] * y[k - 1] * scale_s);
 }
 
-// ------------------------------------------------------------------ density matrix helpers
-// rho = V V^T (side 0, dL x dL) or V^T V (side 1, dR x dR); V column-major dL x dR.
-__global__ void k_syrk(const double* __restrict__ V, int dL, int dR, int side, double* __restrict__ rho) {
-    const int d = side == 0 ? dL : dR;
-    const int64_t dd = (int64_t)d * d;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < dd; e += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(e % d), j = (int)(e / d);
-        double s = 0.0;
-        if (side == 0)
-            for (int c = 0; c < dR; ++c) s += V[i + (int64_t)c * dL] * V[j + (int64_t)c * dL];
-        else
-            for (int r = 0; r < dL; ++r) s += V[r + (int64_t)i * dL] * V[r + (int64_t)j * dL];
-        rho[e] = s;
-    }
-}
-
-hipError_t launch_syrk_f64(const double* V, int dL, int dR, int side, double* rho, hipStream_t s) {
-    const int d = side == 0 ? dL : dR;
-    hipLaunchKernelGGL(k_syrk, dim3(ew_grid((int64_t)d * d)), dim3(LZ_THREADS), 0, s, V, dL, dR, side, rho);
-    return hipGetLastError();
-}
-
-// C (M x N) = op(A) (M x K) * B (K x N), column-major; op(A) = A or A^T.
-__global__ void k_gemm_nn(const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
-                          double* __restrict__ C, int ldc, int M, int N, int K, int transA) {
-    const int64_t mn = (int64_t)M * N;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < mn; e += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(e % M), j = (int)(e / M);
-        double s = 0.0;
-        if (transA)
-            for (int k = 0; k < K; ++k) s += A[k + (int64_t)i * lda] * B[k + (int64_t)j * ldb];
-        else
-            for (int k = 0; k < K; ++k) s += A[i + (int64_t)k * lda] * B[k + (int64_t)j * ldb];
-        C[i + (int64_t)j * ldc] = s;
-    }
-}
-
-hipError_t launch_gemm_nn_f64(const double* A, int lda, const double* B, int ldb, double* C, int ldc, int M, int N,
-                              int K, int transA, hipStream_t s) {
-    if ((int64_t)M * N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gemm_nn, dim3(ew_grid((int64_t)M * N)), dim3(LZ_THREADS), 0, s, A, lda, B, ldb, C, ldc, M,
-                       N, K, transA);
-    return hipGetLastError();
-}
-
 }  // namespace d2d
 
 // ====================================================================== segmented step kernels

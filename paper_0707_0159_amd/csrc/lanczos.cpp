@@ -176,8 +176,14 @@ int basis_bytes(int prec, int basis) {
 // coop: the Gram step may run as one cooperative kernel (not under capture);
 // it does where every block's segment fits the kernel's registers and the
 // grid fits the device at once.
+// what a call did besides its products (reported in the statistics)
+struct RunCounters {
+    int captures = 0;          // restarts captured as graphs
+    int64_t coop_steps = 0;    // steps run as the one-kernel (cooperative) step
+};
+
 d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bool fused, bool plain_cgs2,
-                      int basis, bool coop, hipStream_t s) {
+                      int basis, bool coop, hipStream_t s, RunCounters* rc) {
     const LzSet z = set_of(w);
     const int64_t ldq = w->ldq;
     const int qb = basis_bytes(prec, basis);
@@ -220,6 +226,7 @@ d2d_status inner_loop(LanczosWork* w, HvOps& hv, int prec, int k, int window, bo
         a.lo = lo;
         a.lo_prec = prec;
         D2D_HIP(launch_lz_step(a, s));
+        if (a.coop && rc) rc->coop_steps++;
     }
     D2D_HIP(launch_lz_tridiag(z, k, s));
     D2D_HIP(launch_lz_ritz(z, Q, qb, ldq, k, w->X, s));
@@ -235,25 +242,35 @@ void drop_graphs(LanczosWork* w) {
     }
 }
 
+// A restart (its inner Lanczos and the FP64 residual) launched directly, or
+// captured once as a hipGraph and replayed.  A capture stays valid, across
+// calls too, while the workspace lives and nothing it recorded changes: the
+// precision, cycle length, window, fusion, Gram form and basis storage, the
+// launch stream and the operator's launch configuration (its fingerprint).
 d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, bool full, int window, bool fused,
-                   bool plain_cgs2, int basis, bool coop, bool use_graph, hipStream_t s) {
+                   bool plain_cgs2, int basis, bool coop, bool use_graph, hipStream_t s, RunCounters* rc) {
     if (!use_graph || s == nullptr) {
-        D2D_CHECK(inner_loop(w, hv, prec, k, window, fused, plain_cgs2, basis, coop, s));
+        D2D_CHECK(inner_loop(w, hv, prec, k, window, fused, plain_cgs2, basis, coop, s, rc));
         D2D_CHECK(residual_step(w, hv, s));
         hv.count(prec, k - 1);
         hv.count(D2D_FP64, 1);
         return D2D_OK;
     }
     const int g = 2 * prec + (full ? 0 : 1);
-    if (!w->exec[g] || w->graph_k[g] != k) {
+    D2D_CHECK(hv.prepare(prec));          // launch tables exist before the fingerprint and any capture
+    D2D_CHECK(hv.prepare(D2D_FP64));
+    uint64_t key = hv.fingerprint();
+    for (uint64_t x : {(uint64_t)k, (uint64_t)window, (uint64_t)fused, (uint64_t)plain_cgs2, (uint64_t)basis,
+                       (uint64_t)(uintptr_t)s})
+        key = fnv_mix(key, x);
+    if (!w->exec[g] || w->graph_key[g] != key) {
         if (w->exec[g]) (void)hipGraphExecDestroy(w->exec[g]);
         if (w->graph[g]) (void)hipGraphDestroy(w->graph[g]);
         w->exec[g] = nullptr;
         w->graph[g] = nullptr;
-        D2D_CHECK(hv.prepare(prec));          // launch tables exist before capture
-        D2D_CHECK(hv.prepare(D2D_FP64));
+        w->graph_key[g] = 0;
         D2D_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        d2d_status st = inner_loop(w, hv, prec, k, window, fused, plain_cgs2, basis, false, s);
+        d2d_status st = inner_loop(w, hv, prec, k, window, fused, plain_cgs2, basis, false, s, nullptr);
         if (st == D2D_OK) st = residual_step(w, hv, s);
         hipGraph_t gr = nullptr;
         hipError_t e = hipStreamEndCapture(s, &gr);
@@ -267,7 +284,8 @@ d2d_status restart(LanczosWork* w, HvOps& hv, int prec, int k, bool full, int wi
         }
         w->graph[g] = gr;
         D2D_HIP(hipGraphInstantiate(&w->exec[g], gr, nullptr, nullptr, 0));
-        w->graph_k[g] = k;
+        w->graph_key[g] = key;
+        if (rc) rc->captures++;
     }
     D2D_HIP(hipGraphLaunch(w->exec[g], s));
     hv.count(prec, k - 1);
@@ -317,11 +335,16 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
     const int kmax = std::max(k_of(D2D_BF16), k_of(D2D_FP64));
     D2D_CHECK(ensure_lanczos_work(ctx, lw, len, kmax));
     LanczosWork* w = lw;
-    drop_graphs(w);
     const LzSet z = set_of(w);
     std::vector<int> act(np, 1);
     D2D_CHECK(set_active_flags(w, act));
-    D2D_CHECK(hv.set_active(act, nullptr));
+    {
+        // restarts captured by an earlier call are replayed while they hold
+        // (see restart); a rebuilt work list invalidates them
+        bool rebuilt = false;
+        D2D_CHECK(hv.set_active(act, &rebuilt));
+        if (rebuilt) drop_graphs(w);
+    }
     for (int p = 0; p < np; ++p) {
         if (v0 && v0[p])
             D2D_HIP(hipMemcpyAsync(w->X + w->seg_off[p], v0[p], (size_t)len[p] * 8, hipMemcpyDeviceToDevice, s));
@@ -362,6 +385,7 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
     int prec = opts->prec;
     int j = 0;
     d2d_status result = D2D_OK;
+    RunCounters rc;
     for (;;) {
         const double tsec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         bool changed = false, any = false;
@@ -457,7 +481,8 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
             k = std::min(kfull, need);
         }
         D2D_CHECK(restart(w, hv, prec, k, k == kfull, opts->reorth_window, opts->separate_central == 0,
-                          opts->plain_cgs2 != 0, opts->basis, opts->one_kernel_step != 0, opts->use_graph != 0, s));
+                          opts->plain_cgs2 != 0, opts->basis, opts->one_kernel_step != 0, opts->use_graph != 0, s,
+                          &rc));
         for (int p = 0; p < np; ++p)
             if (a[p]) {
                 hvc[p][prec] += k - 1;
@@ -485,6 +510,8 @@ d2d_status run_lanczos(d2d_ctx* ctx, LanczosWork*& lw, HvOps& hv, const d2d_lanc
         st[p].residual = rho[p];
         if (!done[p]) st[p].seconds = total;
         for (int i = 0; i < D2D_NPREC; ++i) st[p].hv_count[i] = hvc[p][i];
+        st[p].graph_captures = rc.captures;
+        st[p].coop_steps = rc.coop_steps;
         if (stats) stats[p] = st[p];
     }
     if (np == 1 && stats) stats[0].seconds = total;
@@ -522,6 +549,9 @@ struct SbHv : HvOps {
     bool has(int prec) override { return (sb->prec_mask & (1u << prec)) && sb->HL[prec]; }
     void count(int prec, int64_t n) override { sb->hv_count[prec] += n; }
     int64_t counter(int prec) override { return sb->hv_count[prec]; }
+    uint64_t fingerprint() override {
+        return config_fingerprint(sb->tile_sel, sb->split, sb->fuse, sb->xcd, sb->dense, sb->d_x, sb->d_w2, 0);
+    }
 };
 
 }  // namespace

@@ -231,10 +231,46 @@ static void pair_items(int p, const SectorDev& sd, const TileShape& ts, const Pa
 }
 
 void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep, const TileShape& ts, int split,
-               int xcd, const NzCells* nz, WorkHost& out) {
+               int xcd, const NzCells* nz, WorkHost& out, const TileShape* ts1) {
     out.items.clear();
     out.ksteps.clear();
     out.flops = 0;
+    out.n0 = -1;
+    if (split == 3) {
+        // Asymmetric split: the H_l V items in ts (their K-step lists follow
+        // the tile's BM rows), then the V H_r^T items in ts1 (lists follow its
+        // BN columns); each part longest K-loops first.
+        std::vector<std::pair<int, WorkItem>> w0, w1;
+        for (size_t p = 0; p < pairs.size(); ++p) {
+            if (keep && !(*keep)[p]) continue;
+            const SectorDev& sd = pairs[p];
+            const uint8_t* nl = nz ? nz->L[p] : nullptr;
+            const uint8_t* nr = nz ? nz->R[p] : nullptr;
+            const PairSteps p0 = pair_steps(sd, ts, nl, nr, out.ksteps);
+            const PairSteps p1 = pair_steps(sd, *ts1, nl, nr, out.ksteps);
+            for (int j = 0; j < (sd.dR + ts.BN - 1) / ts.BN; ++j)
+                for (int i = 0; i < (sd.dL + ts.BM - 1) / ts.BM; ++i) {
+                    WorkItem it{(int32_t)p, i, j, 1 | (0 << 2), {p0.row_off[i], 0}, {p0.row_n[i], 0}};
+                    const int rows = std::min(ts.BM, sd.dL - i * ts.BM), cols = std::min(ts.BN, sd.dR - j * ts.BN);
+                    out.flops += steps_flops(out.ksteps, it.ks[0], it.kn[0], ts.BK, sd.dL, rows, cols);
+                    w0.push_back({it.kn[0], it});
+                }
+            for (int j = 0; j < (sd.dR + ts1->BN - 1) / ts1->BN; ++j)
+                for (int i = 0; i < (sd.dL + ts1->BM - 1) / ts1->BM; ++i) {
+                    WorkItem it{(int32_t)p, i, j, 2 | (1 << 2), {0, p1.col_off[j]}, {0, p1.col_n[j]}};
+                    const int rows = std::min(ts1->BM, sd.dL - i * ts1->BM), cols = std::min(ts1->BN, sd.dR - j * ts1->BN);
+                    out.flops += steps_flops(out.ksteps, it.ks[1], it.kn[1], ts1->BK, sd.dR, rows, cols);
+                    w1.push_back({it.kn[1], it});
+                }
+        }
+        auto lpt = [](const std::pair<int, WorkItem>& a, const std::pair<int, WorkItem>& b) { return a.first > b.first; };
+        std::stable_sort(w0.begin(), w0.end(), lpt);
+        std::stable_sort(w1.begin(), w1.end(), lpt);
+        for (auto& x : w0) out.items.push_back(x.second);
+        out.n0 = (int)out.items.size();
+        for (auto& x : w1) out.items.push_back(x.second);
+        return;
+    }
     std::vector<PairSteps> ps(pairs.size());
     for (size_t p = 0; p < pairs.size(); ++p) {
         if (keep && !(*keep)[p]) continue;
@@ -321,6 +357,7 @@ d2d_status upload_work(d2d_ctx* ctx, const WorkHost& h, WorkList& wl) {
     wl.n = (int)h.items.size();
     wl.nsteps = (int)h.ksteps.size();
     wl.flops = h.flops;
+    wl.n0 = h.n0;
     return D2D_OK;
 }
 
@@ -348,7 +385,8 @@ d2d_status sb_work(d2d_sb* sb, int shape, int split, int xcd, int dense, const W
     }
     WorkHost h;
     const NzCells nz = sb_nz(sb);
-    make_work(sb->pairs, nullptr, tile_shape(shape), split, xcd, dense ? nullptr : &nz, h);
+    make_work(sb->pairs, nullptr, tile_shape(shape), split, xcd, dense ? nullptr : &nz, h,
+              split == 3 ? &tile_shape(asym_partner(shape)) : nullptr);
     WorkList wl;
     const d2d_status st = upload_work(sb->ctx, h, wl);
     if (st != D2D_OK) {
@@ -389,9 +427,30 @@ d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkList& wl,
         g.V = t.vp;
         if (prec == D2D_BF16X3)
             for (int i = 0; i < 4; ++i) g.lo[i] = t.lo[i];
-        if (stages & HV_GEMM) D2D_HIP(launch_hv_gemm_bf16(shape, g, t.vt, s));
-    } else {
-        if (stages & HV_GEMM) D2D_HIP(launch_hv_gemm(shape, g, s));
+    }
+    if (stages & HV_GEMM) {
+        const bool b16 = prec == D2D_BF16 || prec == D2D_BF16X3;
+        if (wl.n0 >= 0) {
+            // asymmetric split: the H_l V items in the lead shape, then the
+            // V H_r^T items in its partner (the fused central term rides on the second)
+            HvGemmArgs g0 = g, g1 = g;
+            g0.nwork = wl.n0;
+            g0.fuse = nullptr;
+            g1.work = wl.items + wl.n0;
+            g1.nwork = wl.n - wl.n0;
+            const int shape1 = asym_partner(shape);
+            if (b16) {
+                D2D_HIP(launch_hv_gemm_bf16(shape, g0, t.vt, s));
+                D2D_HIP(launch_hv_gemm_bf16(shape1, g1, t.vt, s));
+            } else {
+                D2D_HIP(launch_hv_gemm(shape, g0, s));
+                D2D_HIP(launch_hv_gemm(shape1, g1, s));
+            }
+        } else if (b16) {
+            D2D_HIP(launch_hv_gemm_bf16(shape, g, t.vt, s));
+        } else {
+            D2D_HIP(launch_hv_gemm(shape, g, s));
+        }
     }
     if (!t.w2 && (stages & HV_CENTRAL)) D2D_HIP(launch_central(prec, c, s));
     return D2D_OK;
@@ -856,6 +915,12 @@ extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d
         D2D_CHECK(upload(ctx, hr, &sb->d_rowsL));
         D2D_CHECK(upload(ctx, hc, &sb->d_colsR));
     }
+    // work lists of the default launch configuration of every kept precision
+    for (int p = 0; p < D2D_NPREC; ++p) {
+        if (!(prec_mask & (1u << p)) || !sb->HL[p]) continue;
+        const WorkList* wl = nullptr;
+        D2D_CHECK(sb_work(sb.get(), sb_auto_tile(sb.get(), p), 0, 0, 0, &wl));
+    }
     D2D_HIP(hipStreamSynchronize(ctx->stream));
     *out = sb.release();
     return D2D_OK;
@@ -957,15 +1022,18 @@ namespace d2d {
 
 bool decode_tile(int prec, int tile, TileSel* out) {
     TileSel t;
-    t.split = tile < 0 ? 0 : ((tile & D2D_TILE_SPLIT4) ? 2 : ((tile & D2D_TILE_SPLIT) ? 1 : 0));
+    t.split = tile < 0 ? 0
+                       : ((tile & D2D_TILE_ASYM) ? 3 : ((tile & D2D_TILE_SPLIT4) ? 2 : ((tile & D2D_TILE_SPLIT) ? 1 : 0)));
     t.fuse = tile >= 0 ? ((tile & D2D_TILE_FUSED) ? 1 : 0) : (prec != D2D_FP64 ? 1 : 0);
     t.xcd = tile >= 0 && (tile & D2D_TILE_XCD) ? 1 : 0;
     t.dense = tile >= 0 && (tile & D2D_TILE_DENSE) ? 1 : 0;
     t.shape = tile < 0 ? -1 : (tile & 0xFFFF);
     if (t.shape >= tile_shape_count() || (t.shape >= 0 && tile_shape(t.shape).prec != prec) ||
-        (tile >= 0 &&
-         (tile & ~(0xFFFF | D2D_TILE_SPLIT | D2D_TILE_SPLIT4 | D2D_TILE_FUSED | D2D_TILE_XCD | D2D_TILE_DENSE))) ||
-        (tile >= 0 && (tile & D2D_TILE_SPLIT) && (tile & D2D_TILE_SPLIT4)))
+        (tile >= 0 && (tile & ~(0xFFFF | D2D_TILE_SPLIT | D2D_TILE_SPLIT4 | D2D_TILE_FUSED | D2D_TILE_XCD |
+                                D2D_TILE_DENSE | D2D_TILE_ASYM))) ||
+        (tile >= 0 && (tile & D2D_TILE_SPLIT) && (tile & D2D_TILE_SPLIT4)) ||
+        // the asymmetric split: a shape with a partner, no other split, plain order
+        (t.split == 3 && (asym_partner(t.shape) < 0 || (tile & (D2D_TILE_SPLIT | D2D_TILE_SPLIT4 | D2D_TILE_XCD)))))
         return false;
     *out = t;
     return true;
@@ -973,6 +1041,7 @@ bool decode_tile(int prec, int tile, TileSel* out) {
 
 int encode_tile(const TileSel& t) {
     return t.shape | (t.split == 1 ? D2D_TILE_SPLIT : 0) | (t.split == 2 ? D2D_TILE_SPLIT4 : 0) |
+           (t.split == 3 ? D2D_TILE_ASYM : 0) |
            (t.fuse ? D2D_TILE_FUSED : 0) | (t.xcd ? D2D_TILE_XCD : 0) | (t.dense ? D2D_TILE_DENSE : 0);
 }
 
@@ -993,6 +1062,12 @@ extern "C" d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile) {
     sb->fuse[prec] = t.fuse;
     sb->xcd[prec] = t.xcd;
     sb->dense[prec] = t.dense;
+    // the work list of the configuration is built here, so that products in
+    // it need no allocation
+    if ((sb->prec_mask & (1u << prec)) && sb->HL[prec]) {
+        const WorkList* wl = nullptr;
+        D2D_CHECK(sb_work(sb, t.shape >= 0 ? t.shape : sb_auto_tile(sb, prec), t.split, t.xcd, t.dense, &wl));
+    }
     return D2D_OK;
 }
 
@@ -1125,13 +1200,14 @@ d2d_status tune_configs(hipStream_t s, int prec, int reps, const std::function<d
     bool any = false;
     double bms = 1e300;
     const int nsh = tile_shape_count();
-    for (int tt = 0; tt < 12 * nsh && st == D2D_OK; ++tt) {
+    for (int tt = 0; tt < 16 * nsh && st == D2D_OK; ++tt) {
         TileSel c;
         c.shape = tt % nsh;
-        c.split = (tt / nsh) % 3;
-        c.fuse = (tt / (3 * nsh)) % 2;
-        c.xcd = tt / (6 * nsh);
+        c.split = (tt / nsh) % 4;
+        c.fuse = (tt / (4 * nsh)) % 2;
+        c.xcd = tt / (8 * nsh);
         if (tile_shape(c.shape).prec != prec) continue;
+        if (c.split == 3 && (asym_partner(c.shape) < 0 || c.xcd)) continue;
         st = run(c);   // warm-up (also builds the work list)
         if (st != D2D_OK) break;
         if (hipEventRecord(e0, s) != hipSuccess) st = D2D_EDEVICE;

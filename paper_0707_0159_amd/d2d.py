@@ -26,6 +26,7 @@ D2D_TILE_FUSED = 1 << 17
 D2D_TILE_SPLIT4 = 1 << 18
 D2D_TILE_XCD = 1 << 19
 D2D_TILE_DENSE = 1 << 20
+D2D_TILE_ASYM = 1 << 21
 
 _STATUS = {0: "D2D_OK", -1: "D2D_EINVAL", -2: "D2D_ENOMEM", -3: "D2D_EDEVICE", -4: "D2D_ENOCONV",
            -5: "D2D_ESTATE"}
@@ -65,7 +66,8 @@ class d2d_lanczos_stats(C.Structure):
     _fields_ = [("restarts", C.c_int), ("hv_count", C.c_int64 * D2D_NPREC), ("residual", C.c_double),
                 ("seconds", C.c_double), ("nlog", C.c_int), ("log_t", C.c_double * D2D_LOG_MAX),
                 ("log_theta", C.c_double * D2D_LOG_MAX), ("log_rho", C.c_double * D2D_LOG_MAX),
-                ("log_prec", C.c_int * D2D_LOG_MAX), ("log_pred", C.c_double * D2D_LOG_MAX)]
+                ("log_prec", C.c_int * D2D_LOG_MAX), ("log_pred", C.c_double * D2D_LOG_MAX),
+                ("graph_captures", C.c_int), ("coop_steps", C.c_int64)]
 
 
 # name -> (restype, argtypes)
@@ -96,6 +98,8 @@ _SIGS = {
     "d2d_tile_shapes": (C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "d2d_lanczos": (C.c_int, [P, C.POINTER(d2d_lanczos_opts), P, f64p, P, C.POINTER(d2d_lanczos_stats)]),
     "d2d_density_matrix": (C.c_int, [P, P, C.c_int, C.c_int, C.POINTER(P), f64p, f64p, i64p]),
+    "d2d_column_densities": (C.c_int, [P, P, f64p]),
+    "d2d_density_matrix_timed": (C.c_int, [P, P, C.c_int, C.c_int, C.POINTER(P), f64p, f64p, i64p, f64p]),
     "d2d_batch_create": (C.c_int, [P, C.POINTER(P), C.c_int, C.POINTER(P)]),
     "d2d_batch_destroy": (C.c_int, [P]),
     "d2d_batch_hv": (C.c_int, [P, C.c_int, C.POINTER(P), C.POINTER(P)]),
@@ -355,7 +359,8 @@ def d2d_lanczos(sb: int, opts: d2d_lanczos_opts, v0, psi=None):
     n = st.nlog
     stats = {"restarts": st.restarts, "hv_count": list(st.hv_count), "residual": st.residual,
              "seconds": st.seconds, "log_t": list(st.log_t[:n]), "log_theta": list(st.log_theta[:n]),
-             "log_rho": list(st.log_rho[:n]), "log_prec": list(st.log_prec[:n]), "log_pred": list(st.log_pred[:n])}
+             "log_rho": list(st.log_rho[:n]), "log_prec": list(st.log_prec[:n]), "log_pred": list(st.log_pred[:n]),
+             "graph_captures": st.graph_captures, "coop_steps": st.coop_steps}
     return s, e.value, stats
 
 
@@ -368,6 +373,27 @@ def d2d_density_matrix(sb: int, psi, side: int, m_keep: int, spectrum_cap: int =
                                      spec.ctypes.data_as(f64p) if spectrum_cap else None,
                                      n.ctypes.data_as(i64p)))
     return blk.value, te.value, (spec[: int(n[0])] if spectrum_cap else None)
+
+
+def d2d_density_matrix_timed(sb: int, psi, side: int, m_keep: int, spectrum_cap: int = 0):
+    """As d2d_density_matrix, plus the milliseconds of its three phases (formation,
+    diagonalisation, renormalisation)."""
+    blk = P()
+    te = C.c_double()
+    spec = np.zeros(max(spectrum_cap, 1))
+    n = np.array([spectrum_cap], dtype=np.int64)
+    ms = np.zeros(3)
+    _check(load().d2d_density_matrix_timed(P(sb), P(_ptr(psi)), int(side), int(m_keep), C.byref(blk), C.byref(te),
+                                           spec.ctypes.data_as(f64p) if spectrum_cap else None,
+                                           n.ctypes.data_as(i64p), ms.ctypes.data_as(f64p)))
+    return blk.value, te.value, (spec[: int(n[0])] if spectrum_cap else None), ms
+
+
+def d2d_column_densities(sb: int, psi, legs: int):
+    """<n_{y,sigma}> on columns 2 and 3: array (2, legs, 2) [column][leg][up, down]."""
+    out = np.zeros(4 * legs)
+    _check(load().d2d_column_densities(P(sb), P(_ptr(psi)), out.ctypes.data_as(f64p)))
+    return out.reshape(2, legs, 2)
 
 
 def d2d_batch_create(ctx: Ctx, sbs) -> int:
@@ -412,5 +438,6 @@ def d2d_batch_lanczos(b: int, opts: d2d_lanczos_opts, v0s, psis=None, n=None):
     per = [{"restarts": st.restarts, "hv_count": list(st.hv_count), "residual": st.residual,
             "seconds": st.seconds, "log_theta": list(st.log_theta[:st.nlog]),
             "log_rho": list(st.log_rho[:st.nlog]), "log_t": list(st.log_t[:st.nlog]),
-            "log_prec": list(st.log_prec[:st.nlog]), "log_pred": list(st.log_pred[:st.nlog])} for st in stats]
+            "log_prec": list(st.log_prec[:st.nlog]), "log_pred": list(st.log_pred[:st.nlog]),
+            "graph_captures": st.graph_captures, "coop_steps": st.coop_steps} for st in stats]
     return s, e, per

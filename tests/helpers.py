@@ -53,3 +53,74 @@ def rel_err(w, ref):
     w = np.asarray(w, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     return float(np.linalg.norm(w - ref) / np.linalg.norm(ref))
+
+
+def sector_rel_errs(w, ref, sectors, scale=None):
+    """2-norm error of every sector block (sectors = [(q, dL, dR, offset)])
+    relative to the reference block's norm, or to scale's block norm."""
+    w = np.asarray(w, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = ref if scale is None else np.asarray(scale, dtype=np.float64)
+    out = []
+    for _, dL, dR, o in sectors:
+        a, b = w[o:o + dL * dR], ref[o:o + dL * dR]
+        nb = np.linalg.norm(den[o:o + dL * dR])
+        e = np.linalg.norm(a - b)
+        out.append(float(e / nb) if nb > 0 else (np.inf if e > 0 else 0.0))
+    return out
+
+
+def parity(w, ref, bound, tol, sectors=None):
+    """Element-wise parity of a product with the oracle's.
+
+    Every element must satisfy |w_i - ref_i| <= tol * bound_i, where bound is
+    the oracle's sum of the magnitudes of the terms of element i
+    (``Superblock.hv_abs_bound`` of the same input): a summation of those
+    terms in any order errs by at most about (number of terms) x (unit
+    roundoff) x bound_i, so a tol above that figure passes every correct
+    product and a wrong element of any size relative to its own terms fails.
+    Where bound_i is 0 every term is 0 and w_i must be exactly ref_i.
+    With ``sectors`` every sector block's 2-norm error must be <= tol times
+    the block's norm of the bound (the sector-level form of the same bar; the
+    error relative to the block's own norm, reported as well, is not gated:
+    in a sector whose products cancel, rounding the inputs alone exceeds tol
+    of the result).  Returns the worst element ratio |w - ref| / (tol *
+    bound), the global relative 2-norm error (reported, not gated), and the
+    worst sector errors."""
+    w = np.asarray(w, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    bound = np.asarray(bound, dtype=np.float64)
+    assert w.shape == ref.shape == bound.shape
+    assert np.all(np.isfinite(w)), "non-finite output"
+    d = np.abs(w - ref)
+    lim = tol * bound
+    bad = d > lim
+    worst_i = int(np.argmax(np.where(lim > 0, d / np.where(lim > 0, lim, 1.0), np.where(d > 0, np.inf, 0.0))))
+    ratio = float(d[worst_i] / lim[worst_i]) if lim[worst_i] > 0 else (np.inf if d[worst_i] > 0 else 0.0)
+    sec = sector_rel_errs(w, ref, sectors, scale=bound) if sectors is not None else []
+    sec_rel = sector_rel_errs(w, ref, sectors) if sectors is not None else []
+    rep = {"worst_ratio": ratio, "worst_index": worst_i, "n_bad": int(bad.sum()), "rel_norm": rel_err(w, ref),
+           "worst_sector": max(sec) if sec else None, "worst_sector_rel": max(sec_rel) if sec_rel else None}
+    return rep
+
+
+def assert_parity(w, ref, bound, tol, sectors=None, label=""):
+    rep = parity(w, ref, bound, tol, sectors)
+    print(f"{label}: elementwise worst {rep['worst_ratio']:.3g} of the bar (tol {tol:g}), "
+          f"{rep['n_bad']} elements over, rel norm {rep['rel_norm']:.3e}, "
+          f"worst sector {rep['worst_sector'] if rep['worst_sector'] is None else format(rep['worst_sector'], '.3e')} "
+          f"of its bound ({rep['worst_sector_rel'] if rep['worst_sector_rel'] is None else format(rep['worst_sector_rel'], '.3e')} "
+          f"of its own norm)")
+    assert rep["n_bad"] == 0, f"{label}: {rep['n_bad']} elements beyond tol x bound (worst at {rep['worst_index']})"
+    if sectors is not None:
+        assert rep["worst_sector"] <= tol, f"{label}: a sector's error {rep['worst_sector']:.3e} of its bound > {tol:g}"
+    return rep
+
+
+def asym_shapes(d2d, prec):
+    """Tile shapes of prec that lead an asymmetric split (D2D_TILE_ASYM): the
+    next table entry is their transpose (same precision, K step and prefetch)."""
+    t = d2d.d2d_tile_shapes()
+    return [i for i in range(len(t) - 1)
+            if t[i][0] == prec and t[i + 1][0] == prec and t[i][1] == t[i + 1][2] and t[i][2] == t[i + 1][1]
+            and t[i][3] == t[i + 1][3] and t[i][4] == t[i + 1][4]]

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from helpers import GpuProblem, oracle_superblock, reference_energy, rel_err
+from helpers import GpuProblem, assert_parity, oracle_superblock, reference_energy
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -82,10 +82,12 @@ def test_batch_set_tile_equals_single(ctx, prec):
     probs = mixed_problems(ctx)
     b = d2d.d2d_batch_create(ctx, [p.sb for p in probs])
     shapes = [i for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == prec]
-    for k, sh in enumerate(shapes):
-        flags = (d2d.D2D_TILE_SPLIT4 | d2d.D2D_TILE_XCD) if k % 2 else 0
-        d2d.d2d_batch_set_tile(b, prec, sh | flags)
-        assert_batch_equals_single(ctx, b, probs, prec, sh | flags, 600 + k)
+    from helpers import asym_shapes
+    cfgs = [sh | ((d2d.D2D_TILE_SPLIT4 | d2d.D2D_TILE_XCD) if k % 2 else 0) for k, sh in enumerate(shapes)]
+    cfgs += [sh | d2d.D2D_TILE_ASYM for sh in asym_shapes(d2d, prec)]
+    for k, cfg in enumerate(cfgs):
+        d2d.d2d_batch_set_tile(b, prec, cfg)
+        assert_batch_equals_single(ctx, b, probs, prec, cfg, 600 + k)
     with pytest.raises(RuntimeError):
         d2d.d2d_batch_set_tile(b, prec, len(d2d.d2d_tile_shapes()))
     with pytest.raises(RuntimeError):
@@ -192,7 +194,8 @@ def test_batch64_energies(ctx, prec):
 
 
 def test_batch64_sampled_hv_against_oracle(ctx):
-    """Single-problem Hv of the smaller batch problems against the oracle (FP64 <= 1e-12)."""
+    """Single-problem Hv of the smaller batch problems against the oracle,
+    element by element and per sector (FP64 1e-12, FP32 1e-5)."""
     from test_gpu_hv import gpu_hv
     wls = W.batch64()
     done = 0
@@ -202,8 +205,9 @@ def test_batch64_sampled_hv_against_oracle(ctx):
             continue
         prob = GpuProblem(ctx, wl)
         v = W.random_vector(osb.N, 900)
-        err = rel_err(gpu_hv(ctx, prob, 0, v), osb.hv_factored(v))
-        assert err <= 1e-12, (wl.name, err)
+        ref, bound, secs = osb.hv_factored(v), osb.hv_abs_bound(v), osb.sector_table()
+        assert_parity(gpu_hv(ctx, prob, 0, v), ref, bound, 1e-12, secs, f"{wl.name} fp64")
+        assert_parity(gpu_hv(ctx, prob, 1, v), ref, bound, 1e-5, secs, f"{wl.name} fp32")
         prob.close()
         done += 1
     print("batch64 problems checked", done)

@@ -46,7 +46,9 @@ def gap_cut(spec, target):
     return target
 
 
-@pytest.mark.parametrize("name,target_m", [(W.HEISENBERG_2X6_M16.name, 40), (W.HUBBARD_2X16_M256.name, 300)])
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name,target_m", [(W.HEISENBERG_2X6_M16.name, 40), (W.HUBBARD_2X16_M256.name, 300),
+                                           (W.HUBBARD_3X12_M400.name, 400), (W.HEISENBERG_4X16_M1000.name, 1000)])
 def test_density_matrix_and_next_block(ctx, name, target_m):
     from oracle.blockio import block_from_arrays
     from oracle.blocks import truncate_half
@@ -64,7 +66,9 @@ def test_density_matrix_and_next_block(ctx, name, target_m):
     m_keep = gap_cut(spec_o, min(target_m, spec_o.size - 1))
     blocks = {}
     for side, rho, idx, half in ((0, rhoL, rows_of, osb.left), (1, rhoR, cols_of, osb.right)):
-        blk, te, spec = d2d.d2d_density_matrix(prob.sb, psi, side, m_keep, spectrum_cap=100000)
+        blk, te, spec, ms = d2d.d2d_density_matrix_timed(prob.sb, psi, side, m_keep, spectrum_cap=200000)
+        print(f"{name} side {side} m_keep {m_keep}: formation {ms[0]:.2f} ms, diagonalisation {ms[1]:.2f} ms, "
+              f"renormalisation {ms[2]:.2f} ms", flush=True)
         ob, kept_w, te_o, spec_or, _ = truncate_half(half, rho, idx, m_keep)
         assert spec.size == spec_or.size
         assert np.max(np.abs(spec - spec_or)) <= 1e-12

@@ -215,8 +215,9 @@ def test_one_kernel_step_is_bitwise_two_kernels(ctx, prec):
     prob = GpuProblem(ctx, wl, prec_mask=15)
     out = [run(ctx, prob, prec, wl.seed, k_in=48, graph=0, window=3, tol=1e-8, one=o) for o in (1, 0)]
     (s0, e0, st0, p0), (s1, e1, st1, p1) = out
-    print("one kernel", prec, e0, e1, st0["restarts"], st0["hv_count"])
+    print("one kernel", prec, e0, e1, st0["restarts"], st0["hv_count"], "cooperative steps", st0["coop_steps"])
     assert s0 == 0 and s1 == 0
+    assert st0["coop_steps"] > 0 and st1["coop_steps"] == 0   # the cooperative path ran, and only when asked
     assert e0 == e1
     assert st0["hv_count"] == st1["hv_count"]
     assert np.array_equal(np.asarray(st0["log_theta"]), np.asarray(st1["log_theta"]))
@@ -228,17 +229,21 @@ def test_one_kernel_step_is_bitwise_two_kernels(ctx, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2, 3])
-@pytest.mark.parametrize("split", [0, 1, 2])
+@pytest.mark.parametrize("split", [0, 1, 2, 3])
 def test_fused_central_is_bitwise_separate(ctx, prec, split):
     """One launch for GEMM + central term (parts added by the first step kernel)
     gives the same iterates bit for bit as the central term launched after the
-    GEMM: same energies, restart logs and Ritz vector; for unsplit, split and
-    halved K-loops."""
+    GEMM: same energies, restart logs and Ritz vector; for unsplit, split,
+    halved and asymmetric K-loops (two GEMM launches, the central term on the
+    second)."""
     from paper_0707_0159_amd import d2d
     wl = W.HUBBARD_2X16_M256
     prob = GpuProblem(ctx, wl, prec_mask=15)
     shape = next(i for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == prec)
-    flag = [0, d2d.D2D_TILE_SPLIT, d2d.D2D_TILE_SPLIT4][split]
+    if split == 3:
+        from helpers import asym_shapes
+        shape = asym_shapes(d2d, prec)[0]
+    flag = [0, d2d.D2D_TILE_SPLIT, d2d.D2D_TILE_SPLIT4, d2d.D2D_TILE_ASYM][split]
     d2d.d2d_sb_set_tile(prob.sb, prec, shape | flag | d2d.D2D_TILE_FUSED)
     out = [run(ctx, prob, prec, wl.seed, window=3, tol=1e-8, separate=sep) for sep in (0, 1)]
     (s0, e0, st0, p0), (s1, e1, st1, p1) = out
@@ -354,3 +359,33 @@ def test_ferromagnetic_sector_breakdown(ctx):
     st, e, stats, psi = run(ctx, prob, 0, 3)
     assert st == 0 and abs(e - 4.0) < 1e-13        # J * 16 bonds / 4
     prob.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_graphs_replayed_across_calls(ctx, prec):
+    """Restarts captured as hipGraphs by one d2d_lanczos call are replayed by
+    the next calls on the same superblock (no new capture), with iterates bit
+    for bit those of direct launches; a new launch configuration (another
+    tile) is captured anew and still meets the energy."""
+    from paper_0707_0159_amd import d2d
+    wl = W.HUBBARD_2X16_M256
+    prob = GpuProblem(ctx, wl, prec_mask=15)
+    try:
+        direct = run(ctx, prob, prec, wl.seed, k_in=48, graph=0, window=3, tol=1e-8)
+        calls = [run(ctx, prob, prec, wl.seed, k_in=48, graph=1, window=3, tol=1e-8) for _ in range(3)]
+        caps = [c[2]["graph_captures"] for c in calls]
+        print("graph captures per call", prec, caps, "restarts", direct[2]["restarts"])
+        assert caps[0] >= 1 and caps[1] == 0 and caps[2] == 0
+        for st, e, stats, psi in calls:
+            assert st == 0 and e == direct[1]
+            assert np.array_equal(np.asarray(stats["log_theta"]), np.asarray(direct[2]["log_theta"]))
+            assert np.array_equal(psi, direct[3])
+        shape = [i for i, sh in enumerate(d2d.d2d_tile_shapes()) if sh[0] == prec][-1]
+        d2d.d2d_sb_set_tile(prob.sb, prec, shape)
+        st, e, stats, _ = run(ctx, prob, prec, wl.seed, k_in=48, graph=1, window=3, tol=1e-8)
+        assert st == 0 and stats["graph_captures"] >= 1
+        E0 = reference_energy(wl.name)
+        assert abs(e - E0) <= 1e-10 * abs(E0)
+    finally:
+        d2d.d2d_sb_set_tile(prob.sb, prec, -1)
+        prob.close()

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from helpers import GpuProblem, oracle_superblock, reference_energy, rel_err
+from helpers import GpuProblem, assert_parity, oracle_superblock, reference_energy
 from test_gpu_hv import bf16_bits, oracle_hv_bf16_operands
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(1200)]
@@ -62,19 +62,18 @@ def test_full_size_hv(ctx, problem):
         d2d.d2d_sb_autotune(prob.sb, prec, reps=3)
     v = W.random_vector(osb.N, 1000)
     ref = osb.hv_factored(v)
-    e64 = rel_err(hv(ctx, prob, 0, v), ref)
-    e32 = rel_err(hv(ctx, prob, 1, v), ref)
+    bound = osb.hv_abs_bound(v)
+    secs = osb.sector_table()
+    print(f"{wl.name}: N={osb.N}", flush=True)
+    assert_parity(hv(ctx, prob, 0, v), ref, bound, 1e-12, secs, f"{wl.name} fp64")
+    assert_parity(hv(ctx, prob, 1, v), ref, bound, 1e-5, secs, f"{wl.name} fp32")
     w16 = hv(ctx, prob, 2, v)
-    e16 = rel_err(w16, ref)
-    e16b = rel_err(w16, oracle_hv_bf16_operands(osb, v))
-    e3 = rel_err(hv(ctx, prob, 3, v), ref)
-    print(f"{wl.name}: N={osb.N} fp64 {e64:.3e} fp32 {e32:.3e} bf16 {e16:.3e} (vs bf16-operand oracle {e16b:.3e}) "
-          f"bf16x3 {e3:.3e}")
-    assert e64 <= 1e-12
-    assert e32 <= 1e-5
-    assert e16b <= 1e-5
-    assert e16 <= 2e-2
-    assert e3 <= 1e-4
+    assert_parity(w16, ref, bound, 2e-2, None, f"{wl.name} bf16 vs exact")
+    ref_b = oracle_hv_bf16_operands(osb, v)
+    bound_b = oracle_hv_bf16_operands(osb, v, absolute=True)
+    assert_parity(w16, ref_b, bound_b, 1e-5, secs, f"{wl.name} bf16 vs bf16-operand oracle")
+    del ref_b, bound_b, w16
+    assert_parity(hv(ctx, prob, 3, v), ref, bound, 1e-4, secs, f"{wl.name} bf16x3 vs exact")
 
 
 def test_full_size_skipped_k_steps(ctx, problem):

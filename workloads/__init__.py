@@ -100,8 +100,9 @@ class Workload:
         return (4 if self.kind == "hubbard" else 2) ** self.legs
 
 
-def _batch64_problems():
-    """64 uneven superblocks: one default_rng(5) stream, drawn problem by problem."""
+def _batch64_problems(length):
+    """64 uneven superblocks: one default_rng(5) stream, drawn problem by problem
+    (the draws do not depend on the lattice length)."""
     rng = np.random.default_rng(5)
     out = []
     for i in range(64):
@@ -110,13 +111,19 @@ def _batch64_problems():
         m = int(rng.choice([64, 128, 256, 512]))
         U = float(rng.uniform(2.0, 10.0)) if kind == "hubbard" else 0.0
         tgt = _half_filling(legs) if kind == "hubbard" else _sz_zero(legs)
-        out.append(Workload(f"batch{i:02d}_{kind}_{legs}x{BATCH_LENGTH}_m{m}", kind, legs,
-                            BATCH_LENGTH, m, t=1.0, U=U, J=1.0, target_of_sites=tgt,
+        out.append(Workload(f"batch{i:02d}_{kind}_{legs}x{length}_m{m}", kind, legs,
+                            length, m, t=1.0, U=U, J=1.0, target_of_sites=tgt,
                             seed=100 + i))
     return out
 
 
+# Lattice length of the batch problems.  At 12 columns the blocks have 5
+# columns, more states than any drawn m, so every problem truncates to its m.
+# 6 columns (blocks of 2 columns) is the short variant: the blocks of the
+# 2-leg and 3-leg Heisenberg problems (16 and 64 states) and of the 2-leg
+# Hubbard problems (256 states) stay below the larger drawn m.
 BATCH_LENGTH = 6
+BATCH_LENGTH_DRAWN = 12
 
 HEISENBERG_2X6_M16 = Workload("heisenberg_2x6_m16", "heisenberg", 2, 6, 16, J=1.0, target_of_sites=_sz_zero(2),
                               description="2-leg Heisenberg ladder 2x6, exact blocks of two rungs (m=16), "
@@ -140,9 +147,10 @@ BENCH_SET = (HEISENBERG_2X6_M16.name, HUBBARD_2X16_M256.name, HUBBARD_3X12_M400.
              HEISENBERG_4X16_M1000.name, "batch64")
 
 
-def batch64():
-    """The 64 uneven superblocks of the batch workload."""
-    return _batch64_problems()
+def batch64(length: int | None = None):
+    """The 64 uneven superblocks of the batch workload on ``length`` columns
+    (default ``BATCH_LENGTH``)."""
+    return _batch64_problems(BATCH_LENGTH if length is None else length)
 
 
 def block_path(name: str) -> str:
