@@ -212,6 +212,26 @@ d2d_status d2d_unpack(d2d_sb* sb, const double* packed, double* full);
  * entries give non-finite products, as in a BLAS routine. */
 d2d_status d2d_hv(d2d_sb* sb, int prec, const void* v, void* w);
 
+/* Hv for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * product as d2d_hv, bit for bit (same kernels, same launch configuration),
+ * with the partial outputs of split K-loops (see D2D_TILE_SPLIT) in a
+ * file-scope device array of D2D_NOALLOC_SCRATCH_BYTES that every GPU the
+ * library runs on holds until the process ends, instead of buffers the
+ * superblock allocates on first use.  The call allocates nothing and does not
+ * wait for the device.  Requirements:
+ *   - the grouped-GEMM work list of prec's current launch configuration is
+ *     built: d2d_sb_create builds the default configuration's, d2d_sb_set_tile
+ *     and d2d_sb_autotune the one they select; otherwise D2D_ESTATE;
+ *   - (partial outputs of the split level: 0, 1 or 3) x n x (8 bytes for
+ *     D2D_FP64, else 4) <= D2D_NOALLOC_SCRATCH_BYTES; otherwise D2D_EINVAL.
+ * Arguments and errors otherwise as d2d_hv.  All calls on one GPU share the
+ * array, whose contents stay from the last call (every element a call reads
+ * it writes first): calls that overlap on one GPU (several streams or
+ * threads) race. */
+#define D2D_NOALLOC_SCRATCH_BYTES (64u << 20)
+d2d_status d2d_hv_noalloc(d2d_sb* sb, int prec, const void* v, void* w);
+
 /* Kernel timing of Hv on the context stream: after one product, `reps`
  * grouped-GEMM launches back to back and then `reps` central-term launches
  * back to back, each group between two HIP events; returns the average

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <numeric>
 
 #include "host.h"
@@ -1009,6 +1010,88 @@ extern "C" d2d_status d2d_hv(d2d_sb* sb, int prec, const void* v, void* w) {
     return sb_hv(sb, prec, v, w, sb->ctx->stream);
 }
 
+// ------------------------------------------------------------------ Hv without allocation
+// Partial outputs of split K-loops for d2d_hv_noalloc: a file-scope device
+// array, one copy per GPU, held until the process ends.  In host code its
+// name stands for a host-side shadow, not a device address: the address on a
+// device comes from hipGetSymbolAddress with that device current, and only
+// that address is ever passed to a kernel.
+static __device__ __align__(256) unsigned char scratch[D2D_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on `device` (looked up once per device)
+d2d_status scratch_on(int device, void** out) {
+    if (device < 0 || device >= kMaxDevices) {
+        set_error("d2d_hv_noalloc: device %d out of range", device);
+        return D2D_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int prev = 0;
+        D2D_HIP(hipGetDevice(&prev));
+        D2D_HIP(hipSetDevice(device));
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        (void)hipSetDevice(prev);
+        if (e != hipSuccess || !ptr) {
+            set_error("d2d_hv_noalloc: hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+            return D2D_EDEVICE;
+        }
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return D2D_OK;
+}
+}  // namespace
+
+extern "C" d2d_status d2d_hv_noalloc(d2d_sb* sb, int prec, const void* v, void* w) {
+    if (!sb || !v || !w) {
+        set_error("d2d_hv_noalloc: NULL argument");
+        return D2D_EINVAL;
+    }
+    if (v == w) {
+        set_error("d2d_hv_noalloc: v and w must not overlap");
+        return D2D_EINVAL;
+    }
+    if (prec < 0 || prec >= D2D_NPREC || !(sb->prec_mask & (1u << prec)) || !sb->HL[prec]) {
+        set_error("d2d_hv_noalloc: precision %d not available on this superblock", prec);
+        return D2D_EINVAL;
+    }
+    const int shape = sb->tile_sel[prec] >= 0 ? sb->tile_sel[prec] : sb_auto_tile(sb, prec);
+    const int split = sb->split[prec];
+    const int key = shape | (split << 16) | (sb->xcd[prec] << 18) | (sb->dense[prec] << 19);
+    auto it = sb->work.find(key);
+    if (it == sb->work.end()) {
+        set_error("d2d_hv_noalloc: the work list of the launch configuration of precision %d is not built "
+                  "(d2d_sb_create, d2d_sb_set_tile and d2d_sb_autotune build it)", prec);
+        return D2D_ESTATE;
+    }
+    // the partial outputs, in the product's output type, one after the other
+    const int nparts = split_parts(split);
+    const size_t elem = prec == D2D_FP64 ? 8 : 4;
+    const size_t need = (size_t)nparts * (size_t)sb->N * elem;
+    if (need > (size_t)D2D_NOALLOC_SCRATCH_BYTES) {
+        set_error("d2d_hv_noalloc: %d partial outputs of %lld elements need %zu bytes, more than the %u bytes "
+                  "of scratch", nparts, (long long)sb->N, need, (unsigned)D2D_NOALLOC_SCRATCH_BYTES);
+        return D2D_EINVAL;
+    }
+    HvTables t = tables_of(sb);
+    if (nparts > 0) {
+        void* base = nullptr;
+        D2D_CHECK(scratch_on(sb->ctx->device, &base));
+        // every split work item stores every element of its tile into its
+        // slot, so the parts need no clearing
+        for (int i = 0; i < nparts; ++i) t.x[i] = (char*)base + (size_t)i * sb->N * elem;
+    }
+    D2D_CHECK(hv_launch(t, prec, shape, it->second, v, w, sb->ctx->stream));
+    sb->hv_count[prec]++;
+    return D2D_OK;
+}
+
 extern "C" d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[D2D_NPREC]) {
     if (!sb || !counts) {
         set_error("d2d_hv_count: NULL argument");
@@ -1063,7 +1146,7 @@ extern "C" d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile) {
     sb->xcd[prec] = t.xcd;
     sb->dense[prec] = t.dense;
     // the work list of the configuration is built here, so that products in
-    // it need no allocation
+    // it (d2d_hv_noalloc among them) need no allocation
     if ((sb->prec_mask & (1u << prec)) && sb->HL[prec]) {
         const WorkList* wl = nullptr;
         D2D_CHECK(sb_work(sb, t.shape >= 0 ? t.shape : sb_auto_tile(sb, prec), t.split, t.xcd, t.dense, &wl));

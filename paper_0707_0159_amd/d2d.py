@@ -89,6 +89,7 @@ _SIGS = {
     "d2d_pack": (C.c_int, [P, P, P]),
     "d2d_unpack": (C.c_int, [P, P, P]),
     "d2d_hv": (C.c_int, [P, C.c_int, P, P]),
+    "d2d_hv_noalloc": (C.c_int, [P, C.c_int, P, P]),
     "d2d_hv_count": (C.c_int, [P, i64p]),
     "d2d_hv_profile": (C.c_int, [P, C.c_int, P, P, C.c_int, f64p, f64p]),
     "d2d_sb_set_tile": (C.c_int, [P, C.c_int, C.c_int]),
@@ -294,6 +295,15 @@ def d2d_hv(sb: int, prec: int, v, w):
     """w = H v on the context stream; v, w torch tensors on the device."""
     _check(load().d2d_hv(P(sb), int(prec), P(_ptr(v)), P(_ptr(w))))
     return w
+
+
+def d2d_hv_noalloc(sb: int, prec: int, v, w):
+    """w = H v as d2d_hv, with the library's static scratch instead of any allocation."""
+    _check(load().d2d_hv_noalloc(P(sb), int(prec), P(_ptr(v)), P(_ptr(w))))
+    return w
+
+
+D2D_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def d2d_hv_profile(sb: int, prec: int, v, w, reps: int = 20):
