@@ -448,6 +448,9 @@ def main():
                     help="profiling runs for rocprofv3: 'hv' = only Hv launches of --prec, "
                          "'copy' = a plain device copy of known size (counter calibration)")
     ap.add_argument("--prec", choices=["fp64", "fp32", "bf16", "bf16x3"], default="fp32")
+    ap.add_argument("--dmrg-step", action="store_true",
+                    help="time the routines of one DMRG step on the workload (the paper's split: exact "
+                         "diagonalisation, density-matrix formation, diagonalisation, renormalisation)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path "
@@ -539,6 +542,35 @@ def main():
         if st != 0:
             raise RuntimeError(f"Lanczos did not converge: {stats['residual']}")
         return e, stats
+
+    if args.dmrg_step:
+        # One DMRG step's routines on this superblock (the paper's performance
+        # split): HMED = the ground-state solve (each path, median of steps),
+        # then DMF / DMD / renormalisation of both halves for m kept states.
+        out = {"workload": wl.name, "N_sb": N, "m_keep": wl.m}
+        for prec, nm in ((d2d.D2D_FP64, "fp64"), (d2d.D2D_FP32, "mixed_fp32"), (d2d.D2D_BF16, "mixed_bf16")):
+            solve(prec)
+            ts = []
+            for _ in range(max(1, args.steps)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                solve(prec)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            out["hmed_ms_" + nm] = float(np.median(ts)) * 1e3
+        solve(d2d.D2D_FP64)                      # psi: the FP64 ground state
+        torch.cuda.synchronize()
+        for side in (0, 1):
+            for rep in range(2):                 # the first call loads the eigensolver's code
+                blk, te, _, ms = d2d.d2d_density_matrix_timed(sb, psi, side, wl.m)
+                d2d.d2d_block_destroy(blk)
+            out[f"side{side}"] = {"dmf_ms": ms[0], "dmd_ms": ms[1], "renorm_ms": ms[2], "trunc_err": te}
+        print(json.dumps({"dmrg_step": out}))
+        d2d.d2d_sb_destroy(sb)
+        d2d.d2d_block_destroy(b1)
+        d2d.d2d_block_destroy(b4)
+        d2d.d2d_ctx_destroy(ctx)
+        return
 
     def first_within(stats, tol=1e-10):
         if E0 is None:

@@ -46,6 +46,28 @@ def build(wl: W.Workload, tol=1e-10, verbose=True):
     return meta
 
 
+def identical_done(wl: W.Workload, pool) -> W.Workload | None:
+    """A problem of the pool with the same model, legs, length and m whose
+    block file exists: the growth is deterministic, so its blocks are this
+    problem's blocks (the batch draws repeat Heisenberg problems)."""
+    for o in pool:
+        if (o.name != wl.name and (o.kind, o.legs, o.length, o.m, o.t, o.U, o.J) ==
+                (wl.kind, wl.legs, wl.length, wl.m, wl.t, wl.U, wl.J) and os.path.exists(W.block_path(o.name))):
+            return o
+    return None
+
+
+def copy_blocks(src: W.Workload, dst: W.Workload):
+    import shutil
+    shutil.copyfile(W.block_path(src.name), W.block_path(dst.name))
+    with open(W.block_path(src.name).replace(".npz", ".json")) as f:
+        meta = json.load(f)
+    meta.update(name=dst.name, copied_from=src.name)
+    with open(W.block_path(dst.name).replace(".npz", ".json"), "w") as f:
+        json.dump(meta, f, indent=1)
+    print(f"{dst.name}: blocks of {src.name} (identical problem)", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", required=True, choices=sorted(W.WORKLOADS) + ["batch64"])
@@ -63,6 +85,10 @@ def main():
             probs = [probs[int(i)] for i in args.only.split(",")]
         for wl in probs:
             if os.path.exists(W.block_path(wl.name)):
+                continue
+            twin = identical_done(wl, W.batch64(args.length))
+            if twin is not None:
+                copy_blocks(twin, wl)
                 continue
             build(wl, tol=args.tol)
     else:

@@ -104,6 +104,15 @@ def main():
                 continue
             if wl.name in data and data[wl.name].get("block_hash") == W.block_file_hash(wl.name):
                 continue
+            pool = W.batch64(args.length) if name == "batch64" else wls
+            twin = next((o for o in pool if o.name != wl.name and o.name in data and o.target == wl.target
+                         and data[o.name].get("block_hash") == W.block_file_hash(wl.name)), None)
+            if twin is not None:
+                # the same blocks and target: the same superblock, the same reference
+                rec = dict(data[twin.name], name=wl.name, copied_from=twin.name)
+                print(f"{wl.name}: reference of {twin.name} (identical superblock)", flush=True)
+                store(wl.name, rec)
+                continue
             rec = reference(wl)
             print(rec, flush=True)
             store(wl.name, rec)

@@ -96,9 +96,10 @@ d2d_status build_work(d2d_batch* b, int key) {
     for (size_t p = 0; p < b->pairs.size(); ++p) keep[p] = b->active[b->pair_prob[p]];
     WorkHost h;
     const int split = (key >> 16) & 3;
+    const bool dense = (key >> 19) & 1;
     make_work(b->pairs, &keep, tile_shape(key & 0xFFFF), split, (key >> 18) & 1,
-              ((key >> 19) & 1) ? nullptr : &b->nz, h,
-              split == 3 ? &tile_shape(asym_partner(key & 0xFFFF)) : nullptr);
+              (dense && split != 3) ? nullptr : &b->nz, h,
+              split == 3 ? &tile_shape(asym_partner(key & 0xFFFF)) : nullptr, dense);
     return upload_work(b->ctx, h, b->work[key]);
 }
 
@@ -273,6 +274,10 @@ extern "C" d2d_status d2d_batch_create(d2d_ctx* ctx, d2d_sb* const* sbs, int n, 
             SectorDev q = s->pairs[j];
             b->nz.L.push_back(s->nzL[j].data());
             b->nz.R.push_back(s->nzR[j].data());
+            b->nz.rowL.push_back(s->nzRowL[j].data());
+            b->nz.colR.push_back(s->nzColR[j].data());
+            b->nz.runsL.push_back(&s->runsL[j]);
+            b->nz.runsR.push_back(&s->runsR[j]);
             q.off += voff;
             q.hl_off += hl;
             q.hr_off += hr;

@@ -134,6 +134,13 @@ struct HvTables {
 constexpr int NZ_CELL = 16;
 struct NzCells {
     std::vector<const uint8_t*> L, R;
+    // Row-exact patterns for the asymmetric split: rowL[p][r * cL + j] != 0
+    // when row r of H_l[q_L] has a nonzero in columns [16 j, 16 j + 16);
+    // colR[p][c * cR + j] likewise for column c of the stored H_r^T (rows
+    // [16 j, 16 j + 16)); runsL[p] / runsR[p]: start of every run of rows
+    // (columns) with one column state, then d_L (d_R).  Empty: not known.
+    std::vector<const uint8_t*> rowL, colR;
+    std::vector<const std::vector<int>*> runsL, runsR;
 };
 // A work list on the host: items, their K-step table, the flops it executes.
 struct WorkHost {
@@ -244,6 +251,8 @@ struct d2d_sb {
     // work lists per tile shape
     std::map<int, d2d::WorkList> work;             // key: shape | split << 16 | xcd << 18 | dense << 19
     std::vector<std::vector<uint8_t>> nzL, nzR;    // zero pattern of each pair's operators (NzCells)
+    std::vector<std::vector<uint8_t>> nzRowL, nzColR;   // row-exact patterns (NzCells::rowL, colR)
+    std::vector<std::vector<int>> runsL, runsR;         // run starts (NzCells::runsL, runsR)
     int tile_sel[D2D_NPREC] = {-1, -1, -1, -1};   // shape index, or -1 = by size
     int split[D2D_NPREC] = {0, 0, 0, 0};          // 0 none, 1 two K-loops apart, 2 each K-loop halved too
     int fuse[D2D_NPREC] = {0, 1, 1, 1};           // inner Lanczos steps: central term inside the GEMM launch
@@ -302,8 +311,10 @@ inline int split_parts(int split) { return split == 0 ? 0 : (split == 2 ? 3 : 1)
 // xcd: the XCD-aware order (rectangles of each pair's tiles per XCD, interleaved, padded with p = -1)
 // nz: zero pattern of the operators (K steps whose operator tile is zero are
 // left out), or null for every step
-// split 3: the V H_r^T items in shape ts1 (the partner of ts), after the H_l V items
+// split 3: the V H_r^T items in shape ts1 (the partner of ts), after the H_l V
+// items; with run boundaries in nz the items are run-aligned (see make_work);
+// all_steps: every K step (the zero pattern then only places the runs)
 void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep, const TileShape& ts, int split, int xcd,
-               const NzCells* nz, WorkHost& out, const TileShape* ts1 = nullptr);
+               const NzCells* nz, WorkHost& out, const TileShape* ts1 = nullptr, bool all_steps = false);
 void free_lanczos(d2d_sb* sb);
 }  // namespace d2d

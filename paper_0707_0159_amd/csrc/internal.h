@@ -53,7 +53,10 @@ struct SectorDev {
 // One output tile of the grouped GEMM: pair, tile row, tile column.
 // part: bits 0-1 K-loops (0 both, 1 H_l V only, 2 V H_r^T only); bits 2-3
 // output slot (0 W, s partial X[s-1]); bit 4 one half of the K-loop only,
-// bit 5 which half.
+// bit 5 which half; bit 6 (ITEM_ALIGNED) a run-aligned item of one K-loop:
+// an H_l V item covers rows [tm, tm + kn[1]) (tm a row, not a tile index),
+// a V H_r^T item columns [tn, tn + kn[0]); the unused K-loop's count holds
+// the extent.
 // ks[f], kn[f]: the K steps of K-loop f (0: H_l V, 1: V H_r^T) are the kn[f]
 // step starts (multiples of BK, ascending) at ks[f] in the work list's step
 // table: every step whose operator tile (the item's rows or columns x the
@@ -62,6 +65,7 @@ struct WorkItem {
     int32_t p, tm, tn, part;
     int32_t ks[2], kn[2];
 };
+constexpr int ITEM_ALIGNED = 64;
 
 // Tile shapes built into the library.
 struct TileShape {

@@ -58,13 +58,20 @@ __device__ __attribute__((always_inline)) inline void k_steps(const int32_t* __r
             knext = kafter;
         }
     } else {
+        // Pairs of steps, then the odd last one after the loop: the loop's
+        // back edge is then reached only with both register sets refilled, so
+        // the wait at the top of a pair covers exactly the set being staged
+        // (with a break inside the pair, the back edge also merged a path
+        // whose second set was never consumed, and the compiler waited for
+        // every load in flight before reusing registers).
         int kc0 = at(0), kc1 = at(1);
         gload0(kc0);
         gload1(kc1);
         int kn0 = at(2), kn1 = at(3);
+        int i = 0;
 #pragma unroll 1
-        for (int i = 0; i < n; i += 2) {
-            const int ka0 = at(i + 4);
+        for (; i + 1 < n; i += 2) {
+            const int ka0 = at(i + 4), ka1 = at(i + 5);
             stage0(buf, kc0);
             __syncthreads();
             gload0(kn0);
@@ -72,8 +79,6 @@ __device__ __attribute__((always_inline)) inline void k_steps(const int32_t* __r
             buf ^= 1;
             kc0 = kn0;
             kn0 = ka0;
-            if (i + 1 >= n) break;
-            const int ka1 = at(i + 5);
             stage1(buf, kc1);
             __syncthreads();
             gload1(kn1);
@@ -81,6 +86,11 @@ __device__ __attribute__((always_inline)) inline void k_steps(const int32_t* __r
             buf ^= 1;
             kc1 = kn1;
             kn1 = ka1;
+        }
+        if (i < n) {
+            stage0(buf, kc0);
+            __syncthreads();
+            compute(buf);
         }
     }
 }
@@ -333,8 +343,14 @@ k_hv_gemm(const HvK<T> g) {
     const SectorDev s = sec[wi.p];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave % WGM, wn = wave / WGM;
-    const int row0 = wi.tm * BM, col0 = wi.tn * BN;
     const int dL = s.dL, dR = s.dR;
+    const ItemK it = decode_item(wi.part);
+    // a run-aligned item covers rows [row0, rlim) (H_l V) or columns [col0, clim) (V H_r^T)
+    const bool al = (wi.part & ITEM_ALIGNED) != 0;
+    const int row0 = al && it.ph_lo == 0 ? wi.tm : wi.tm * BM, col0 = al && it.ph_lo == 1 ? wi.tn : wi.tn * BN;
+    const int rlim = al && it.ph_lo == 0 ? row0 + wi.kn[1] : dL, clim = al && it.ph_lo == 1 ? col0 + wi.kn[0] : dR;
+    // a wave whose rows or columns all lie past the item's issues no MFMA (it still stages its loads)
+    const bool idle = row0 + wm * WM >= rlim || col0 + wn * WN >= clim;
 
     typename M::vec acc[FM][FN];
 #pragma unroll
@@ -345,7 +361,6 @@ k_hv_gemm(const HvK<T> g) {
             for (int v = 0; v < M::NV; ++v) acc[i][j][v] = T(0);
 
     T ra[EA], rb[EB];
-    const ItemK it = decode_item(wi.part);
 #pragma unroll 1
     for (int phase = it.ph_lo; phase < it.ph_hi; ++phase) {
         // phase 0: A = H_l[q_L] (dL x dL), B = V (dL x dR), K = dL
@@ -393,6 +408,7 @@ k_hv_gemm(const HvK<T> g) {
         // slices ahead of their MFMAs, so one wait covers a group (FP64 reads
         // them slice by slice: the larger fragments would cost occupancy)
         auto compute = [&](int buf) __attribute__((always_inline)) {
+            if (idle) return;
             constexpr int NS = BK / M::MK, KG = sizeof(T) == 8 ? 1 : (NS < 8 ? NS : 8);
 #pragma unroll
             for (int g0 = 0; g0 < NS; g0 += KG) {
@@ -446,7 +462,7 @@ k_hv_gemm(const HvK<T> g) {
 #pragma unroll
             for (int v = 0; v < M::NV; ++v) {
                 const int c = col0 + wn * WN + j * M::MN + M::col_of(lane, v);
-                if (r < dL && c < dR) Wp[r + (int64_t)c * dL] = acc[i][j][v];
+                if (r < rlim && c < clim) Wp[r + (int64_t)c * dL] = acc[i][j][v];
             }
         }
     }
@@ -509,8 +525,13 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const int32_t* __re
     const SectorDev s = sec[wi.p];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave % WGM, wn = wave / WGM;
-    const int row0 = wi.tm * BM, col0 = wi.tn * BN;
     const int dL = s.dL, dR = s.dR;
+    const ItemK it = decode_item(wi.part);
+    // run-aligned items and idle waves as in the FP32 / FP64 kernel
+    const bool al = (wi.part & ITEM_ALIGNED) != 0;
+    const int row0 = al && it.ph_lo == 0 ? wi.tm : wi.tm * BM, col0 = al && it.ph_lo == 1 ? wi.tn : wi.tn * BN;
+    const int rlim = al && it.ph_lo == 0 ? row0 + wi.kn[1] : dL, clim = al && it.ph_lo == 1 ? col0 + wi.kn[0] : dR;
+    const bool idle = row0 + wm * WM >= rlim || col0 + wn * WN >= clim;
 
     typename M::vec acc[FM][FN];
 #pragma unroll
@@ -521,7 +542,6 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const int32_t* __re
             for (int v = 0; v < M::NV; ++v) acc[i][j][v] = 0.0f;
 
     u32x4 ra[NP][EA], rb[NP][EB];
-    const ItemK it = decode_item(wi.part);
 #pragma unroll 1
     for (int phase = it.ph_lo; phase < it.ph_hi; ++phase) {
         const bf16_t* A = phase == 0 ? HL + s.hl16_off : VT + s.vt_off;
@@ -570,6 +590,7 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const int32_t* __re
             }
         };
         auto compute = [&](int buf) __attribute__((always_inline)) {
+            if (idle) return;
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 16) {
                 bf16x8 a[NP][FM], b[NP][FN];
@@ -619,7 +640,7 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const int32_t* __re
 #pragma unroll
             for (int v = 0; v < M::NV; ++v) {
                 const int c = col0 + wn * WN + j * 32 + M::col_of(lane, v);
-                if (r < dL && c < dR) Wp[r + (int64_t)c * dL] = acc[i][j][v];
+                if (r < rlim && c < clim) Wp[r + (int64_t)c * dL] = acc[i][j][v];
             }
         }
     }

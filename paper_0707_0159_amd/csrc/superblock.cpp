@@ -232,36 +232,86 @@ static void pair_items(int p, const SectorDev& sd, const TileShape& ts, const Pa
 }
 
 void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep, const TileShape& ts, int split,
-               int xcd, const NzCells* nz, WorkHost& out, const TileShape* ts1) {
+               int xcd, const NzCells* nz, WorkHost& out, const TileShape* ts1, bool all_steps) {
     out.items.clear();
     out.ksteps.clear();
     out.flops = 0;
     out.n0 = -1;
     if (split == 3) {
-        // Asymmetric split: the H_l V items in ts (their K-step lists follow
-        // the tile's BM rows), then the V H_r^T items in ts1 (lists follow its
-        // BN columns); each part longest K-loops first.
+        // Asymmetric split: the H_l V items in ts, then the V H_r^T items in
+        // ts1; each part longest K-loops first.  With the operators' runs
+        // known, an H_l V item covers a segment of at most BM rows inside one
+        // run of rows with one column-2 state, and its K steps are those
+        // whose BK columns hold a nonzero in exactly those rows (row-exact
+        // pattern); a V H_r^T item likewise covers a segment of at most BN
+        // columns inside one run of column-3 states.  The rows of a run couple
+        // only to the runs of the column states its column Hamiltonian and
+        // bond operators reach, so an aligned segment runs only those K steps.
         std::vector<std::pair<int, WorkItem>> w0, w1;
+        const bool runs = nz && !nz->runsL.empty();
+        // steps of BK columns over a K extent KL (padded for BF16) whose
+        // 16-column cells are set in any of the rows [r0, r1) of mask (nc cells per row)
+        auto seg_steps = [&](const uint8_t* mask, int nc, int r0, int r1, int KL, int BK) {
+            const int off = (int)out.ksteps.size();
+            for (int k0 = 0; k0 < KL; k0 += BK) {
+                bool any = all_steps || !mask;
+                const int c0 = k0 / NZ_CELL, c1 = std::min((k0 + BK + NZ_CELL - 1) / NZ_CELL, nc);
+                for (int r = r0; r < r1 && !any; ++r)
+                    for (int c = c0; c < c1 && !any; ++c) any = mask[(size_t)r * nc + c] != 0;
+                if (any) out.ksteps.push_back(k0);
+            }
+            return std::make_pair(off, (int)out.ksteps.size() - off);
+        };
         for (size_t p = 0; p < pairs.size(); ++p) {
             if (keep && !(*keep)[p]) continue;
             const SectorDev& sd = pairs[p];
-            const uint8_t* nl = nz ? nz->L[p] : nullptr;
-            const uint8_t* nr = nz ? nz->R[p] : nullptr;
-            const PairSteps p0 = pair_steps(sd, ts, nl, nr, out.ksteps);
-            const PairSteps p1 = pair_steps(sd, *ts1, nl, nr, out.ksteps);
-            for (int j = 0; j < (sd.dR + ts.BN - 1) / ts.BN; ++j)
-                for (int i = 0; i < (sd.dL + ts.BM - 1) / ts.BM; ++i) {
-                    WorkItem it{(int32_t)p, i, j, 1 | (0 << 2), {p0.row_off[i], 0}, {p0.row_n[i], 0}};
-                    const int rows = std::min(ts.BM, sd.dL - i * ts.BM), cols = std::min(ts.BN, sd.dR - j * ts.BN);
-                    out.flops += steps_flops(out.ksteps, it.ks[0], it.kn[0], ts.BK, sd.dL, rows, cols);
-                    w0.push_back({it.kn[0], it});
+            const bool b16 = ts.prec == D2D_BF16 || ts.prec == D2D_BF16X3;
+            const int KL = b16 ? sd.dLp : sd.dL, KR = b16 ? sd.dRp : sd.dR;
+            if (!runs) {
+                const uint8_t* nl = nz && !all_steps ? nz->L[p] : nullptr;
+                const uint8_t* nr = nz && !all_steps ? nz->R[p] : nullptr;
+                const PairSteps p0 = pair_steps(sd, ts, nl, nr, out.ksteps);
+                const PairSteps p1 = pair_steps(sd, *ts1, nl, nr, out.ksteps);
+                for (int j = 0; j < (sd.dR + ts.BN - 1) / ts.BN; ++j)
+                    for (int i = 0; i < (sd.dL + ts.BM - 1) / ts.BM; ++i) {
+                        WorkItem it{(int32_t)p, i, j, 1 | (0 << 2), {p0.row_off[i], 0}, {p0.row_n[i], 0}};
+                        const int rows = std::min(ts.BM, sd.dL - i * ts.BM), cols = std::min(ts.BN, sd.dR - j * ts.BN);
+                        out.flops += steps_flops(out.ksteps, it.ks[0], it.kn[0], ts.BK, sd.dL, rows, cols);
+                        w0.push_back({it.kn[0], it});
+                    }
+                for (int j = 0; j < (sd.dR + ts1->BN - 1) / ts1->BN; ++j)
+                    for (int i = 0; i < (sd.dL + ts1->BM - 1) / ts1->BM; ++i) {
+                        WorkItem it{(int32_t)p, i, j, 2 | (1 << 2), {0, p1.col_off[j]}, {0, p1.col_n[j]}};
+                        const int rows = std::min(ts1->BM, sd.dL - i * ts1->BM), cols = std::min(ts1->BN, sd.dR - j * ts1->BN);
+                        out.flops += steps_flops(out.ksteps, it.ks[1], it.kn[1], ts1->BK, sd.dR, rows, cols);
+                        w1.push_back({it.kn[1], it});
+                    }
+                continue;
+            }
+            const int cL = (sd.dL + NZ_CELL - 1) / NZ_CELL, cR = (sd.dR + NZ_CELL - 1) / NZ_CELL;
+            const std::vector<int>& rl = *nz->runsL[p];
+            for (size_t q = 0; q + 1 < rl.size(); ++q)
+                for (int t0 = rl[q]; t0 < rl[q + 1]; t0 += ts.BM) {
+                    const int t1 = std::min(rl[q + 1], t0 + ts.BM);
+                    const auto st = seg_steps(nz->rowL[p], cL, t0, t1, KL, ts.BK);
+                    for (int j = 0; j < (sd.dR + ts.BN - 1) / ts.BN; ++j) {
+                        WorkItem it{(int32_t)p, t0, j, 1 | (0 << 2) | ITEM_ALIGNED, {st.first, 0}, {st.second, t1 - t0}};
+                        const int cols = std::min(ts.BN, sd.dR - j * ts.BN);
+                        out.flops += steps_flops(out.ksteps, it.ks[0], it.kn[0], ts.BK, sd.dL, t1 - t0, cols);
+                        w0.push_back({it.kn[0], it});
+                    }
                 }
-            for (int j = 0; j < (sd.dR + ts1->BN - 1) / ts1->BN; ++j)
-                for (int i = 0; i < (sd.dL + ts1->BM - 1) / ts1->BM; ++i) {
-                    WorkItem it{(int32_t)p, i, j, 2 | (1 << 2), {0, p1.col_off[j]}, {0, p1.col_n[j]}};
-                    const int rows = std::min(ts1->BM, sd.dL - i * ts1->BM), cols = std::min(ts1->BN, sd.dR - j * ts1->BN);
-                    out.flops += steps_flops(out.ksteps, it.ks[1], it.kn[1], ts1->BK, sd.dR, rows, cols);
-                    w1.push_back({it.kn[1], it});
+            const std::vector<int>& rr = *nz->runsR[p];
+            for (size_t q = 0; q + 1 < rr.size(); ++q)
+                for (int t0 = rr[q]; t0 < rr[q + 1]; t0 += ts1->BN) {
+                    const int t1 = std::min(rr[q + 1], t0 + ts1->BN);
+                    const auto st = seg_steps(nz->colR[p], cR, t0, t1, KR, ts1->BK);
+                    for (int i = 0; i < (sd.dL + ts1->BM - 1) / ts1->BM; ++i) {
+                        WorkItem it{(int32_t)p, i, t0, 2 | (1 << 2) | ITEM_ALIGNED, {0, st.first}, {t1 - t0, st.second}};
+                        const int rows = std::min(ts1->BM, sd.dL - i * ts1->BM);
+                        out.flops += steps_flops(out.ksteps, it.ks[1], it.kn[1], ts1->BK, sd.dR, rows, t1 - t0);
+                        w1.push_back({it.kn[1], it});
+                    }
                 }
         }
         auto lpt = [](const std::pair<int, WorkItem>& a, const std::pair<int, WorkItem>& b) { return a.first > b.first; };
@@ -373,6 +423,10 @@ NzCells sb_nz(const d2d_sb* sb) {
     for (size_t p = 0; p < sb->pairs.size(); ++p) {
         nz.L.push_back(sb->nzL[p].data());
         nz.R.push_back(sb->nzR[p].data());
+        nz.rowL.push_back(sb->nzRowL[p].data());
+        nz.colR.push_back(sb->nzColR[p].data());
+        nz.runsL.push_back(&sb->runsL[p]);
+        nz.runsR.push_back(&sb->runsR[p]);
     }
     return nz;
 }
@@ -386,8 +440,9 @@ d2d_status sb_work(d2d_sb* sb, int shape, int split, int xcd, int dense, const W
     }
     WorkHost h;
     const NzCells nz = sb_nz(sb);
-    make_work(sb->pairs, nullptr, tile_shape(shape), split, xcd, dense ? nullptr : &nz, h,
-              split == 3 ? &tile_shape(asym_partner(shape)) : nullptr);
+    // the asymmetric split places its items on the runs even when it runs every step
+    make_work(sb->pairs, nullptr, tile_shape(shape), split, xcd, (dense && split != 3) ? nullptr : &nz, h,
+              split == 3 ? &tile_shape(asym_partner(shape)) : nullptr, dense != 0);
     WorkList wl;
     const d2d_status st = upload_work(sb->ctx, h, wl);
     if (st != D2D_OK) {
@@ -653,13 +708,41 @@ extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d
                         ++nnz;
                     }
         };
-        sb->nzL.resize(sb->pairs.size());
-        sb->nzR.resize(sb->pairs.size());
-        for (size_t p = 0; p < sb->pairs.size(); ++p) {
+        // row-exact patterns: per row of H_l (per column of the stored H_r^T)
+        // the 16-wide cells of the other index that hold a nonzero
+        auto lines = [](const double* a, int d, bool by_row, std::vector<uint8_t>& out) {
+            const int c = (d + NZ_CELL - 1) / NZ_CELL;
+            out.assign((size_t)d * c, 0);
+            for (int j = 0; j < d; ++j)
+                for (int i = 0; i < d; ++i)
+                    if (a[i + (int64_t)j * d] != 0.0) {
+                        if (by_row) out[(size_t)i * c + j / NZ_CELL] = 1;
+                        else out[(size_t)j * c + i / NZ_CELL] = 1;
+                    }
+        };
+        // starts of the runs of one column state (half index / m) along a sector
+        auto run_starts = [m](const std::vector<int32_t>& idx, std::vector<int>& out) {
+            out.clear();
+            for (size_t i = 0; i < idx.size(); ++i)
+                if (i == 0 || idx[i] / m != idx[i - 1] / m) out.push_back((int)i);
+            out.push_back((int)idx.size());
+        };
+        const size_t npp = sb->pairs.size();
+        sb->nzL.resize(npp);
+        sb->nzR.resize(npp);
+        sb->nzRowL.resize(npp);
+        sb->nzColR.resize(npp);
+        sb->runsL.resize(npp);
+        sb->runsR.resize(npp);
+        for (size_t p = 0; p < npp; ++p) {
             const SectorDev& s = sb->pairs[p];
             int64_t nl = 0, nr = 0;
             cells(h.data() + s.hl_off, s.dL, sb->nzL[p], nl);
             cells(r.data() + s.hr_off, s.dR, sb->nzR[p], nr);
+            lines(h.data() + s.hl_off, s.dL, true, sb->nzRowL[p]);
+            lines(r.data() + s.hr_off, s.dR, false, sb->nzColR[p]);
+            run_starts(sb->rowsL[p], sb->runsL[p]);
+            run_starts(sb->colsR[p], sb->runsR[p]);
             sb->flops_nnz += 2.0 * nl * s.dR + 2.0 * nr * s.dL;
         }
     }

@@ -303,6 +303,43 @@ def sector_step_flops(osb, BM, BN, BK, dense):
     return total
 
 
+def aligned_step_flops(osb, shape0, shape1, dense, padded):
+    """The asymmetric split's flops from the oracle's dense sector operators:
+    H_l V items on segments of at most BM0 rows inside each run of one
+    column-2 state, every BN0 columns; V H_r^T items on segments of at most
+    BN1 columns inside each run of one column-3 state, every BM1 rows; a K
+    step of BK runs when its 16-column cells hold a nonzero in the segment's
+    own rows (columns) of the operator (every step with dense); 2 x segment
+    x other extent x the step's K columns inside the block.  K runs over the
+    length padded to a multiple of 8 for the BF16 operands (padded)."""
+    (BM0, BN0, BK), (BM1, BN1, _) = shape0, shape1
+    m = osb.m
+    total = 0.0
+    for (q, r, c, o), (hl, hr) in zip(osb.sectors, osb.dense_sectors()):
+        dL, dR = r.size, c.size
+        for H, idx, dout, SEG, OTHER in ((hl, r, dR, BM0, BN0), (hr, c, dL, BN1, BM1)):
+            d = idx.size
+            KL = -(-d // 8) * 8 if padded else d
+            nc = -(-d // 16)
+            P = np.zeros((d, nc * 16), dtype=bool)
+            P[:, :d] = H != 0
+            cells = P.reshape(d, nc, 16).any(axis=2)          # per row of H: its nonzero 16-column cells
+            a = idx // m
+            starts = [0] + [i for i in range(1, d) if a[i] != a[i - 1]] + [d]
+            ntiles = -(-dout // OTHER)
+            for s0, s1 in zip(starts[:-1], starts[1:]):
+                for t0 in range(s0, s1, SEG):
+                    t1 = min(s1, t0 + SEG)
+                    rows = cells[t0:t1].any(axis=0)
+                    for k0 in range(0, KL, BK):
+                        c0, c1 = k0 // 16, min(-(-(k0 + BK) // 16), nc)
+                        if dense or (c0 < c1 and rows[c0:c1].any()):
+                            kk = max(0, min(BK, d - k0))
+                            for j in range(ntiles):
+                                total += 2.0 * (t1 - t0) * min(OTHER, dout - j * OTHER) * kk
+    return total
+
+
 @pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_skipped_k_steps_add_nothing(ctx, prec):
     """K steps whose operator tile is zero are left out: the product is bit
@@ -323,13 +360,23 @@ def test_skipped_k_steps_add_nothing(ctx, prec):
         skip_f = sector_step_flops(osb, s[1], s[2], s[3], False)
         for sp in (0, d2d.D2D_TILE_SPLIT, d2d.D2D_TILE_XCD) + ((d2d.D2D_TILE_ASYM,) if i in asym_shapes(d2d, prec) else ()):
             if sp == d2d.D2D_TILE_ASYM:
-                # the two launches in their own shapes: the dense flop count is
-                # the lead shape's H_l V steps plus the partner's V H_r^T steps
+                # run-aligned items in the lead shape and its transposed partner:
+                # every step and only the nonzero ones agree bit for bit, and
+                # the library's flops are the oracle's count of the same steps
+                sh0, sh1 = d2d.d2d_tile_shapes()[i][1:4], d2d.d2d_tile_shapes()[i + 1][1:4]
+                padded = prec in (d2d.D2D_BF16, d2d.D2D_BF16X3)
                 d2d.d2d_sb_set_tile(prob.sb, prec, i | sp | d2d.D2D_TILE_DENSE)
+                fd = d2d.d2d_sb_gemm_flops(prob.sb, prec)
                 wd = run(ctx, prob, v)
                 d2d.d2d_sb_set_tile(prob.sb, prec, i | sp)
+                fs = d2d.d2d_sb_gemm_flops(prob.sb, prec)
                 ws = run(ctx, prob, v)
+                ad = aligned_step_flops(osb, sh0, sh1, True, padded)
+                asf = aligned_step_flops(osb, sh0, sh1, False, padded)
+                print(f"prec {prec} shape {i} asym: flops every step {fd:.4e}, skipping {fs:.4e} "
+                      f"({fs / prob.info['flops_nnz']:.3f} of F_nnz)")
                 assert np.array_equal(wd, ws)
+                assert abs(fd - ad) <= 1e-9 * ad and abs(fs - asf) <= 1e-9 * ad
                 continue
             d2d.d2d_sb_set_tile(prob.sb, prec, i | sp | d2d.D2D_TILE_DENSE)
             fd = d2d.d2d_sb_gemm_flops(prob.sb, prec)
