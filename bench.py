@@ -123,6 +123,26 @@ def kernel_source_hash() -> str:
 TILE_KEYS = ("BMxBNxBK", "prefetch_depth", "split_k_loops", "xcd_order")
 
 
+def tile_desc(t: int, shapes) -> dict:
+    """Launch configuration of a d2d_sb_set_tile value: the tile shape (with the
+    asymmetric split, the H_l V shape and its transposed partner for V H_r^T),
+    the K-loop split and the flags."""
+    sh = t & 0xFFFF
+    if t & d2d.D2D_TILE_ASYM:
+        split = "asymmetric"
+        dims = "x".join(str(x) for x in shapes[sh][1:4]) + " + " + "x".join(str(x) for x in shapes[sh + 1][1:4])
+    else:
+        split = "halves" if t & d2d.D2D_TILE_SPLIT4 else bool(t & d2d.D2D_TILE_SPLIT)
+        dims = "x".join(str(x) for x in shapes[sh][1:4])
+    return {"tile": sh, "split_k_loops": split, "central_in_gemm_launch": bool(t & d2d.D2D_TILE_FUSED),
+            "xcd_order": bool(t & d2d.D2D_TILE_XCD), "BMxBNxBK": dims, "prefetch_depth": shapes[sh][4]}
+
+
+def split_words(split) -> str:
+    return {True: ", split K-loops", "halves": ", split K-loops (halved)",
+            "asymmetric": ", asymmetric split (H_l V and V H_r^T in transposed tiles)"}.get(split, "")
+
+
 def traffic_record(workload: str, prec: str, tile: dict):
     """HBM bytes per launch of the grouped GEMM from the committed rocprofv3
     counter summary, if it was taken on the current kernel source and in the
@@ -291,14 +311,12 @@ def bench_batch(args):
     infos = [d2d.d2d_sb_info(sb) for sb in sbs]
     b = d2d.d2d_batch_create(ctx, sbs)
     # launch configuration of the batch's grouped launches, per precision
+    shapes = d2d.d2d_tile_shapes()
     tiles = {}
     for prec, name in ((d2d.D2D_FP64, "fp64"), (d2d.D2D_FP32, "fp32"), (d2d.D2D_BF16, "bf16"),
                        (d2d.D2D_BF16X3, "bf16x3")):
         t, ms_t = d2d.d2d_batch_autotune(b, prec, 2)
-        tiles[name] = {"shape": t & 0xFFFF, "split_k_loops": {0: False, 1: True, 2: "halves"}[
-            1 if t & d2d.D2D_TILE_SPLIT else (2 if t & d2d.D2D_TILE_SPLIT4 else 0)],
-            "central_in_gemm_launch": bool(t & d2d.D2D_TILE_FUSED), "xcd_order": bool(t & d2d.D2D_TILE_XCD),
-            "tuned_ms": ms_t}
+        tiles[name] = dict(tile_desc(t, shapes), tuned_ms=ms_t)
     with torch.cuda.stream(s):
         v0 = [torch.as_tensor(W.random_vector(i["n"], wl.seed), device="cuda") for i, wl in zip(infos, wls)]
     s.synchronize()
@@ -502,13 +520,7 @@ def main():
     tuned = {}
     for prec, name in names.items():
         t, ms_t = d2d.d2d_sb_autotune(sb, prec, reps=10)
-        tuned[name] = {"tile": t & 0xFFFF,
-                       "split_k_loops": "halves" if t & d2d.D2D_TILE_SPLIT4 else bool(t & d2d.D2D_TILE_SPLIT),
-                       "central_in_gemm_launch": bool(t & d2d.D2D_TILE_FUSED),
-                       "xcd_order": bool(t & d2d.D2D_TILE_XCD),
-                       "BMxBNxBK": "x".join(str(x) for x in shapes[t & 0xFFFF][1:4]),
-                       "prefetch_depth": shapes[t & 0xFFFF][4], "ms": ms_t,
-                       "gemm_flops": d2d.d2d_sb_gemm_flops(sb, prec)}
+        tuned[name] = dict(tile_desc(t, shapes), ms=ms_t, gemm_flops=d2d.d2d_sb_gemm_flops(sb, prec))
     with torch.cuda.stream(s):
         v0 = torch.as_tensor(W.random_vector(N, wl.seed), device="cuda")
         psi = torch.zeros_like(v0)
@@ -649,9 +661,7 @@ def main():
                 "executed_tflops": fx / sec / 1e12, "frac_exec": fx / sec / PEAK[name],
                 "executed_over_nnz": fx / F_nnz_gemm,
                 "kernel": f"grouped GEMM H_l V + V H_r^T ({name}, tile {tuned[name]['BMxBNxBK']}"
-                          f"{', split K-loops' if tuned[name]['split_k_loops'] else ''}"
-                          f"{' (halved)' if tuned[name]['split_k_loops'] == 'halves' else ''}"
-                          f", zero operator tiles skipped)",
+                          f"{split_words(tuned[name]['split_k_loops'])}, zero operator tiles skipped)",
                 "flops_per_launch": fx, "dense_sector_flops": F,
                 "dense_equivalent_tflops": F / sec / 1e12, "launch_ms": ms[name]["gemm_ms"],
                 "hbm_bytes_min_per_launch": info["bytes_min_" + name],
