@@ -125,8 +125,9 @@ TILE_KEYS = ("BMxBNxBK", "prefetch_depth", "split_k_loops", "xcd_order")
 
 def tile_desc(t: int, shapes) -> dict:
     """Launch configuration of a d2d_sb_set_tile value: the tile shape (with the
-    asymmetric split, the H_l V shape and its transposed partner for V H_r^T),
-    the K-loop split and the flags."""
+    asymmetric split, the H_l V shape and its transposed partner for V H_r^T,
+    the next entry of the table), the K-loop split and the flags."""
+    from paper_0707_0159_amd import d2d
     sh = t & 0xFFFF
     if t & d2d.D2D_TILE_ASYM:
         split = "asymmetric"
@@ -135,7 +136,8 @@ def tile_desc(t: int, shapes) -> dict:
         split = "halves" if t & d2d.D2D_TILE_SPLIT4 else bool(t & d2d.D2D_TILE_SPLIT)
         dims = "x".join(str(x) for x in shapes[sh][1:4])
     return {"tile": sh, "split_k_loops": split, "central_in_gemm_launch": bool(t & d2d.D2D_TILE_FUSED),
-            "xcd_order": bool(t & d2d.D2D_TILE_XCD), "BMxBNxBK": dims, "prefetch_depth": shapes[sh][4]}
+            "xcd_order": bool(t & d2d.D2D_TILE_XCD), "persistent": bool(t & d2d.D2D_TILE_PERSIST),
+            "BMxBNxBK": dims, "prefetch_depth": shapes[sh][4]}
 
 
 def split_words(split) -> str:

@@ -282,6 +282,17 @@ d2d_status d2d_hv_count(const d2d_sb* sb, int64_t counts[D2D_NPREC]);
  * (256 x 64).  Valid only for shapes whose next entry is their transpose;
  * one partial output, added as with D2D_TILE_SPLIT. */
 #define D2D_TILE_ASYM (1 << 21)
+/* D2D_TILE_PERSIST: a persistent grouped launch.  The grid holds only the
+ * work-groups the device runs at once (occupancy per compute unit times the
+ * compute units); each takes work items, longest K-loop first, from a device
+ * counter kept with the work list until none is left, and the last to finish
+ * clears the counter, so consecutive launches (and launches replayed from a
+ * captured graph) need no reset.  The same items and the same arithmetic per
+ * item as the plain launch: the result is identical bit for bit.  Launches
+ * of one superblock (or batch) on streams that overlap share the counter and
+ * must not run at the same time.  Not with D2D_TILE_XCD (an XCD order steers
+ * work-groups by index, which a persistent launch does not use). */
+#define D2D_TILE_PERSIST (1 << 22)
 d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile);
 /* Floating-point operations of one grouped-GEMM launch of precision prec
  * under the superblock's current launch configuration: 2 per multiply-add

@@ -48,6 +48,7 @@ struct d2d_batch {
     int fuse[D2D_NPREC] = {0, 1, 1, 1};           // central term inside the GEMM launch (inner steps)
     int xcd[D2D_NPREC] = {0, 0, 0, 0};            // XCD-aware work order
     int dense[D2D_NPREC] = {0, 0, 0, 0};          // every K step (no skipping of zero operator tiles)
+    int persist[D2D_NPREC] = {0, 0, 0, 0};        // persistent grouped launch
     void* d_x[3] = {nullptr, nullptr, nullptr};   // ntot doubles each, partial outputs of split K-loops
     void* d_w2 = nullptr;               // ntot doubles, central-term part of fused launches
     void* stage_v = nullptr;
@@ -187,6 +188,7 @@ d2d_status batch_hv(d2d_batch* b, int prec, const void* v, void* w, hipStream_t 
         for (int i = 0; i < 3; ++i) parts->x[i] = t.x[i];
         parts->central = t.w2;
     }
+    t.persist = b->persist[prec];
     return hv_launch(t, prec, shape, *wl, v, w, s);
 }
 
@@ -220,7 +222,7 @@ struct BatchHv : HvOps {
     void count(int prec, int64_t n) override { b->hv_count[prec] += n; }
     int64_t counter(int prec) override { return b->hv_count[prec]; }
     uint64_t fingerprint() override {
-        return config_fingerprint(b->tile_sel, b->split, b->fuse, b->xcd, b->dense, b->d_x, b->d_w2, b->builds);
+        return config_fingerprint(b->tile_sel, b->split, b->fuse, b->xcd, b->dense, b->persist, b->d_x, b->d_w2, b->builds);
     }
 };
 
@@ -440,6 +442,7 @@ extern "C" d2d_status d2d_batch_set_tile(d2d_batch* b, int prec, int tile) {
     b->fuse[prec] = t.fuse;
     b->xcd[prec] = t.xcd;
     b->dense[prec] = t.dense;
+    b->persist[prec] = t.persist;
     return D2D_OK;
 }
 
@@ -474,6 +477,7 @@ extern "C" d2d_status d2d_batch_autotune(d2d_batch* b, int prec, int reps, int* 
         b->fuse[prec] = c.fuse;
         b->xcd[prec] = c.xcd;
         b->dense[prec] = c.dense;
+        b->persist[prec] = c.persist;
     };
     const uint64_t key = batch_key(b, prec);
     TileSel sel;
@@ -482,7 +486,8 @@ extern "C" d2d_status d2d_batch_autotune(d2d_batch* b, int prec, int reps, int* 
         return D2D_OK;
     }
     hipStream_t s = b->ctx->stream;
-    const TileSel saved{b->tile_sel[prec], b->split[prec], b->fuse[prec], b->xcd[prec], b->dense[prec]};
+    const TileSel saved{b->tile_sel[prec], b->split[prec], b->fuse[prec], b->xcd[prec], b->dense[prec],
+                        b->persist[prec]};
     // every problem active, as at the start of a solve
     BatchHv ops(b);
     D2D_CHECK(ops.set_active(std::vector<int>(b->sbs.size(), 1), nullptr));

@@ -282,6 +282,7 @@ extern "C" d2d_status d2d_ctx_destroy(d2d_ctx* ctx) {
     // work the context queued (asynchronous products, copies) ends before the
     // context does: nothing of it may run on into the runtime's teardown
     const hipError_t e = hipStreamSynchronize(ctx->stream);
+    free_eig_lanes(ctx);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     if (e != hipSuccess) {

@@ -8,8 +8,11 @@
 //
 // DMF: every sector's rho is one problem of a grouped FP64 matrix-core GEMM
 // (one launch).  DMD: each sector is diagonalised on the device (rocSOLVER
-// dsyevd, FP64, all sectors queued back to back on the stream, one host
-// synchronisation); the m_keep eigenvectors of largest weight are kept (ties:
+// dsyevd, FP64).  Its tridiagonal reduction and divide and conquer are long
+// chains of small dependent launches, so the sectors are spread over a few
+// streams of their own (largest first, each to the least loaded stream by
+// d^3), which run concurrently and join the context's stream before one host
+// synchronisation; the m_keep eigenvectors of largest weight are kept (ties:
 // sector ascending, then index in the sector ascending).  Renormalisation:
 // the kept columns are gathered on the device with their sign fixed (entry of
 // largest modulus positive), H' = U^T (H U) per sector as two grouped GEMM
@@ -79,6 +82,60 @@ double seconds_since(std::chrono::steady_clock::time_point t0) {
 
 }  // namespace
 
+// Streams of the density-matrix eigensolver, owned by the context: each with
+// its rocBLAS handle, a device workspace of the library's own that the handle
+// uses (sized before any work is queued, so that no call allocates while
+// others run) and an event that joins it back to the context's stream.
+struct EigLanes {
+    int n = 0;
+    hipStream_t s[EIG_LANES] = {};
+    rocblas_handle h[EIG_LANES] = {};
+    hipEvent_t done[EIG_LANES] = {};
+    hipEvent_t start = nullptr;
+    void* ws[EIG_LANES] = {};
+    size_t ws_bytes[EIG_LANES] = {};
+};
+
+void free_eig_lanes(d2d_ctx* ctx) {
+    EigLanes* L = ctx->eig;
+    if (!L) return;
+    for (int i = 0; i < L->n; ++i) {
+        if (L->s[i]) (void)hipStreamSynchronize(L->s[i]);
+        if (L->h[i]) rocblas_destroy_handle(L->h[i]);
+        if (L->ws[i]) ctx->free(L->ws[i], L->ws_bytes[i]);
+        if (L->done[i]) (void)hipEventDestroy(L->done[i]);
+        if (L->s[i]) (void)hipStreamDestroy(L->s[i]);
+    }
+    if (L->start) (void)hipEventDestroy(L->start);
+    delete L;
+    ctx->eig = nullptr;
+}
+
+static d2d_status eig_lanes(d2d_ctx* ctx, EigLanes** out) {
+    if (!ctx->eig) {
+        EigLanes* L = new EigLanes();
+        ctx->eig = L;
+        if (hipEventCreateWithFlags(&L->start, hipEventDisableTiming) != hipSuccess) {
+            set_error("hipEventCreateWithFlags failed");
+            return D2D_EDEVICE;
+        }
+        for (int i = 0; i < EIG_LANES; ++i) {
+            // default priority, like every stream of the library
+            if (hipStreamCreateWithFlags(&L->s[i], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&L->done[i], hipEventDisableTiming) != hipSuccess ||
+                rocblas_create_handle(&L->h[i]) != rocblas_status_success ||
+                rocblas_set_stream(L->h[i], L->s[i]) != rocblas_status_success) {
+                L->n = i + 1;
+                set_error("density-matrix eigensolver streams: creation failed");
+                return D2D_EDEVICE;
+            }
+            L->n = i + 1;
+        }
+    }
+    *out = ctx->eig;
+    return D2D_OK;
+}
+
 static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_keep, d2d_block** new_block,
                                double* trunc_err, double* spectrum, int64_t* spectrum_len, double* ms) {
     if (!sb || !psi || !new_block || !trunc_err || (side != 0 && side != 1) || m_keep < 1) {
@@ -123,17 +180,8 @@ static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_ke
     auto t1 = std::chrono::steady_clock::now();
 
     // ---- DMD: eigenpairs of every sector (ascending eigenvalues, vectors in place)
-    rocblas_handle h = nullptr;
-    if (rocblas_create_handle(&h) != rocblas_status_success) {
-        set_error("rocblas_create_handle failed");
-        return D2D_EDEVICE;
-    }
-    struct HGuard {
-        rocblas_handle h;
-        ~HGuard() { rocblas_destroy_handle(h); }
-    } hg{h};
-    rocblas_set_stream(h, s);
-    const int dmax = *std::max_element(dim.begin(), dim.end());
+    EigLanes* lanes = nullptr;
+    D2D_CHECK(eig_lanes(ctx, &lanes));
     size_t nev = 0;
     std::vector<size_t> evoff(np);
     for (int p = 0; p < np; ++p) {
@@ -141,16 +189,75 @@ static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_ke
         nev += dim[p];
     }
     D2D_CHECK(ev.alloc(nev));
-    DevBuf<double> work(ctx);
-    D2D_CHECK(work.alloc((size_t)dmax + 1));
+    DevBuf<double> offd(ctx);   // each sector's off-diagonal workspace, at its eigenvalues' offset
+    D2D_CHECK(offd.alloc(nev));
     DevBuf<rocblas_int> info(ctx);
     D2D_CHECK(info.alloc((size_t)np));
-    for (int p = 0; p < np; ++p)
-        if (rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_lower, dim[p], rho.p + roff[p], dim[p],
-                             ev.p + evoff[p], work.p, info.p + p) != rocblas_status_success) {
-            set_error("rocsolver_dsyevd failed on sector %d (dim %d)", p, dim[p]);
+    // sectors to lanes: largest first, each to the lane with the least d^3 so far
+    std::vector<int> by_size(np), lane_of(np, 0);
+    std::iota(by_size.begin(), by_size.end(), 0);
+    std::stable_sort(by_size.begin(), by_size.end(), [&](int a, int b) { return dim[a] > dim[b]; });
+    double load[EIG_LANES] = {};
+    int big[EIG_LANES] = {};
+    const int nl = std::min(lanes->n, std::max(np, 1));
+    for (int p : by_size) {
+        const int l = (int)(std::min_element(load, load + nl) - load);
+        lane_of[p] = l;
+        load[l] += (double)dim[p] * dim[p] * dim[p];
+        big[l] = std::max(big[l], dim[p]);
+    }
+    auto syevd = [&](int p) {
+        return rocsolver_dsyevd(lanes->h[lane_of[p]], rocblas_evect_original, rocblas_fill_lower, dim[p],
+                                rho.p + roff[p], dim[p], ev.p + evoff[p], offd.p + evoff[p], info.p + p);
+    };
+    // each lane's workspace, for the largest sector it gets, before any work is queued
+    for (int l = 0; l < nl; ++l) {
+        int p0 = -1;
+        for (int p : by_size)
+            if (lane_of[p] == l) {
+                p0 = p;
+                break;
+            }
+        if (p0 < 0) continue;
+        rocblas_handle h = lanes->h[l];
+        if (rocblas_start_device_memory_size_query(h) != rocblas_status_success) {
+            set_error("rocblas_start_device_memory_size_query failed");
             return D2D_EDEVICE;
         }
+        const rocblas_status q = syevd(p0);
+        size_t need = 0;
+        if ((q != rocblas_status_size_increased && q != rocblas_status_size_unchanged &&
+             q != rocblas_status_success) ||
+            rocblas_stop_device_memory_size_query(h, &need) != rocblas_status_success) {
+            set_error("rocsolver_dsyevd workspace query failed (dim %d)", big[l]);
+            return D2D_EDEVICE;
+        }
+        if (need > lanes->ws_bytes[l] || !lanes->ws[l]) {
+            // the lane is idle here: the previous call ended with a host synchronisation
+            if (lanes->ws[l]) ctx->free(lanes->ws[l], lanes->ws_bytes[l]);
+            lanes->ws[l] = nullptr;
+            lanes->ws_bytes[l] = 0;
+            const size_t bytes = std::max<size_t>(need, 256);
+            D2D_CHECK(ctx->alloc(&lanes->ws[l], bytes));
+            lanes->ws_bytes[l] = bytes;
+            if (rocblas_set_workspace(h, lanes->ws[l], bytes) != rocblas_status_success) {
+                set_error("rocblas_set_workspace(%zu bytes) failed", bytes);
+                return D2D_EDEVICE;
+            }
+        }
+    }
+    D2D_HIP(hipEventRecord(lanes->start, s));   // rho is formed
+    for (int l = 0; l < nl; ++l) D2D_HIP(hipStreamWaitEvent(lanes->s[l], lanes->start, 0));
+    for (int p : by_size)
+        if (syevd(p) != rocblas_status_success) {
+            set_error("rocsolver_dsyevd failed on sector %d (dim %d)", p, dim[p]);
+            for (int l = 0; l < nl; ++l) (void)hipStreamSynchronize(lanes->s[l]);
+            return D2D_EDEVICE;
+        }
+    for (int l = 0; l < nl; ++l) {
+        D2D_HIP(hipEventRecord(lanes->done[l], lanes->s[l]));
+        D2D_HIP(hipStreamWaitEvent(s, lanes->done[l], 0));
+    }
     std::vector<double> evh(nev);
     std::vector<rocblas_int> infoh(np);
     D2D_HIP(hipMemcpyAsync(evh.data(), ev.p, nev * 8, hipMemcpyDeviceToHost, s));

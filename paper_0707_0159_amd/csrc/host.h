@@ -58,6 +58,10 @@ std::vector<OpKey> edge_keys(const d2d_model& model);
 
 }  // namespace d2d
 
+// streams of the density-matrix eigensolver (created on first use)
+struct EigLanes;
+constexpr int EIG_LANES = 4;
+
 struct d2d_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -65,9 +69,11 @@ struct d2d_ctx {
     size_t mem_cap = 0;
     size_t bytes = 0;
     int children = 0;
+    EigLanes* eig = nullptr;
     d2d_status alloc(void** p, size_t bytes);
     void free(void* p, size_t bytes);
 };
+void free_eig_lanes(d2d_ctx* ctx);
 
 struct d2d_block {
     d2d_ctx* ctx = nullptr;
@@ -126,6 +132,7 @@ struct HvTables {
     int n_ptiles;
     bf16_t* vp;
     bf16_t* vt;
+    int persist;              // persistent grouped launch (the work list's counters)
 };
 // Zero pattern of the sector operators in cells of NZ_CELL x NZ_CELL: for
 // pair p, L[p] has ceil(dL/NZ_CELL)^2 bytes for the stored H_l (column-major,
@@ -157,6 +164,7 @@ struct WorkList {
     size_t cap_items = 0, cap_steps = 0;
     double flops = 0;   // GEMM flops of one launch over the list
     int n0 = -1;        // asymmetric split: items of the lead shape (the rest: its partner)
+    int* ctr = nullptr; // persistent launches: two counters per launch (next item, groups done), zero between launches
 };
 // stages of one Hv launch sequence (a whole product is all three)
 constexpr int HV_PACK = 1, HV_GEMM = 2, HV_CENTRAL = 4, HV_ALL = 7;
@@ -197,7 +205,8 @@ inline uint64_t fnv_mix(uint64_t h, uint64_t x) {
     return h;
 }
 inline uint64_t config_fingerprint(const int* tile, const int* split, const int* fuse, const int* xcd,
-                                   const int* dense, void* const* parts, const void* w2, uint64_t builds) {
+                                   const int* dense, const int* persist, void* const* parts, const void* w2,
+                                   uint64_t builds) {
     uint64_t h = 0xcbf29ce484222325ull;
     for (int p = 0; p < D2D_NPREC; ++p) {
         h = fnv_mix(h, (uint64_t)(int64_t)tile[p]);
@@ -205,6 +214,7 @@ inline uint64_t config_fingerprint(const int* tile, const int* split, const int*
         h = fnv_mix(h, (uint64_t)fuse[p]);
         h = fnv_mix(h, (uint64_t)xcd[p]);
         h = fnv_mix(h, (uint64_t)dense[p]);
+        h = fnv_mix(h, (uint64_t)persist[p]);
     }
     for (int i = 0; i < 3; ++i) h = fnv_mix(h, (uint64_t)(uintptr_t)parts[i]);
     h = fnv_mix(h, (uint64_t)(uintptr_t)w2);
@@ -258,6 +268,7 @@ struct d2d_sb {
     int fuse[D2D_NPREC] = {0, 1, 1, 1};           // inner Lanczos steps: central term inside the GEMM launch
     int xcd[D2D_NPREC] = {0, 0, 0, 0};            // XCD-aware work order
     int dense[D2D_NPREC] = {0, 0, 0, 0};          // 1: run every K step (no skipping of zero operator tiles)
+    int persist[D2D_NPREC] = {0, 0, 0, 0};        // 1: persistent grouped launch (work items from a counter)
     void* d_x[3] = {nullptr, nullptr, nullptr};   // split-K partial outputs, N doubles each, on demand
     void* d_w2 = nullptr;               // N doubles, central-term part of fused launches
     int64_t hv_count[D2D_NPREC] = {0, 0, 0, 0};
@@ -284,7 +295,7 @@ int sb_auto_tile(const d2d_sb* sb, int prec);
 // a launch configuration: shape index (-1 = by size), K-loop split level, central
 // term fused into the GEMM launch, XCD-aware order
 struct TileSel {
-    int shape = -1, split = 0, fuse = 0, xcd = 0, dense = 0;
+    int shape = -1, split = 0, fuse = 0, xcd = 0, dense = 0, persist = 0;
 };
 // d2d_sb_set_tile's tile argument (shape | D2D_TILE_* flags, or -1) for precision
 // prec; false when it names no shape of that precision or unknown flags

@@ -136,6 +136,8 @@ struct HvGemmArgs {
     void* X[3];                // partial outputs of split work items (slot s -> X[s-1]; nullable)
     const CentralArgs* fuse;   // nullable
     int64_t lo[4];             // BF16x3: element offsets of the lo parts of HL, HR, VP, VT
+    int* ctr;                  // non-null: persistent launch with these counters (next item, groups done),
+                               // zero on entry and left zero by the launch
 };
 hipError_t launch_hv_gemm(int shape, const HvGemmArgs& a, hipStream_t s);
 // BF16: HvGemmArgs.V is the padded copy VP, VT its padded transpose.

@@ -249,10 +249,8 @@ __device__ inline void central_unit(const CentralK<TI, TO, TC>& c, int ui) {
         }
     }
 #pragma unroll
-    for (int i = 0; i < CS; ++i) {
-        if (i >= nsteps) break;
-        if (ok[i]) c.W[u.off + r + (int64_t)col[i] * u.ldw] = wo[i] + (TO)acc[i];
-    }
+    for (int i = 0; i < CS; ++i)
+        if (i < nsteps && ok[i]) c.W[u.off + r + (int64_t)col[i] * u.ldw] = wo[i] + (TO)acc[i];
 }
 
 // NW waves of a block take units i0 .. i0+NW-1 (no block barrier).
@@ -309,14 +307,53 @@ struct HvK {
     CentralK<T, T, T> cen;
 };
 
+// Persistent grouped launch: a grid sized to what the device holds at once
+// takes the work items (in the list's longest-first order) from a counter,
+// one at a time per work-group, until the list is exhausted.  The last
+// work-group to finish clears the counters (ctr[0] next item, ctr[1] groups
+// done) for the next launch on the stream, so the launch needs no memset and
+// may be captured in a graph.
+// The thread index as a value the compiler cannot see through: inside the
+// persistent loop, index arithmetic derived from it is then recomputed per
+// item instead of being hoisted out of the loop and held in registers across
+// the whole item (which costs the plain kernel's occupancy).
+__device__ __attribute__((always_inline)) inline int opaque_tid() {
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+template <typename F>
+__device__ __attribute__((always_inline)) inline void persistent_loop(int total, int* ctr, F&& body) {
+    __shared__ int next;
+    for (;;) {
+        __syncthreads();   // every thread has read `next` and left the previous item
+        if (threadIdx.x == 0) next = atomicAdd(&ctr[0], 1);
+        __syncthreads();
+        // uniform over the block: held in a scalar register, so that the item's
+        // record and everything derived from it stay scalar as with blockIdx
+        const int i = __builtin_amdgcn_readfirstlane(next);
+        if (i >= total) break;
+        body(i);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&ctr[1], 1) == (int)gridDim.x - 1) {
+            atomicExch(&ctr[0], 0);
+            atomicExch(&ctr[1], 0);
+        }
+    }
+}
+
 // PF: K steps whose global loads are in flight while a step is computed (1 or
 // 2; two register sets for 2, the loop unrolled by two so the sets stay static).
+// One work item (bid) of the grouped launch: a GEMM tile, or with CEN a group
+// of central-term units past the GEMM items.
 template <typename T, int BM, int BN, int BK, int WGM, int WGN, int PF, bool CEN>
-__global__ void __launch_bounds__(64 * WGM * WGN)
-k_hv_gemm(const HvK<T> g) {
+__device__ __attribute__((always_inline)) inline void hv_gemm_item(const HvK<T>& g, const int bid, const int tid) {
     if constexpr (CEN) {
-        if ((int)blockIdx.x >= g.nwork) {
-            central_units_block<T, T, T, WGM * WGN, false>(g.cen, ((int)blockIdx.x - g.nwork) * WGM * WGN);
+        if (bid >= g.nwork) {
+            central_units_block<T, T, T, WGM * WGN, false>(g.cen, (bid - g.nwork) * WGM * WGN);
             return;
         }
     }
@@ -338,10 +375,11 @@ k_hv_gemm(const HvK<T> g) {
     __shared__ T As[2][BK][BM + PA];
     __shared__ T Bs[2][BN][BK + PB];
 
-    const WorkItem wi = work[blockIdx.x];
+    const WorkItem wi = work[bid];
     if (wi.p < 0) return;   // padding of an XCD-ordered work list
     const SectorDev s = sec[wi.p];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int t = tid, lane = t & 63, wave = t >> 6;
+    __builtin_assume(t >= 0 && t < 64 * WGM * WGN);
     const int wm = wave % WGM, wn = wave / WGM;
     const int dL = s.dL, dR = s.dR;
     const ItemK it = decode_item(wi.part);
@@ -468,6 +506,16 @@ k_hv_gemm(const HvK<T> g) {
     }
 }
 
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int PF, bool CEN>
+__global__ void __launch_bounds__(64 * WGM * WGN) k_hv_gemm(const HvK<T> g) {
+    hv_gemm_item<T, BM, BN, BK, WGM, WGN, PF, CEN>(g, (int)blockIdx.x, (int)threadIdx.x);
+}
+
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int PF, bool CEN>
+__global__ void __launch_bounds__(64 * WGM * WGN) k_hv_gemm_persist(const HvK<T> g, int* ctr, int total) {
+    persistent_loop(total, ctr, [&](int bid) { hv_gemm_item<T, BM, BN, BK, WGM, WGN, PF, CEN>(g, bid, opaque_tid()); });
+}
+
 // ------------------------------------------------------------------ BF16 GEMM
 // Same tile algorithm with v_mfma_f32_32x32x16_bf16 (lane l holds A[l%32][8(l/32)..+7]
 // and B[8(l/32)..+7][l%32]; results as the 32x32x2 f32 form, checked on the
@@ -493,17 +541,34 @@ struct LoOffsets {
     int64_t hl, hr, vp, vt;
 };
 
+// Arguments of the BF16 kernels (by value).
+template <bool X3>
+struct HvK16 {
+    const WorkItem* work;
+    int nwork;
+    const int32_t* ksteps;
+    const SectorDev* sec;
+    const bf16_t *HL, *HRt, *VP, *VT;
+    OutPtrs out;
+    LoOffsets lo;
+    CentralK<typename std::conditional<X3, float, bf16_t>::type, float, float> cen;
+};
+
 template <int BM, int BN, int BK, int WGM, int WGN, int PF, bool X3, bool CEN>
-__global__ void __launch_bounds__(64 * WGM * WGN)
-k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const int32_t* __restrict__ ksteps,
-               const SectorDev* __restrict__ sec,
-               const bf16_t* __restrict__ HL, const bf16_t* __restrict__ HRt, const bf16_t* __restrict__ VP,
-               const bf16_t* __restrict__ VT, const OutPtrs out, const LoOffsets lo,
-               const CentralK<typename std::conditional<X3, float, bf16_t>::type, float, float> cen) {
+__device__ __attribute__((always_inline)) inline void hv_gemm_bf16_item(const HvK16<X3>& g, const int bid, const int tid) {
     using TIc = typename std::conditional<X3, float, bf16_t>::type;
+    const WorkItem* __restrict__ work = g.work;
+    const int32_t* __restrict__ ksteps = g.ksteps;
+    const SectorDev* __restrict__ sec = g.sec;
+    const bf16_t* __restrict__ HL = g.HL;
+    const bf16_t* __restrict__ HRt = g.HRt;
+    const bf16_t* __restrict__ VP = g.VP;
+    const bf16_t* __restrict__ VT = g.VT;
+    const OutPtrs& out = g.out;
+    const LoOffsets& lo = g.lo;
     if constexpr (CEN) {
-        if ((int)blockIdx.x >= nwork) {
-            central_units_block<TIc, float, float, WGM * WGN, false>(cen, ((int)blockIdx.x - nwork) * WGM * WGN);
+        if (bid >= g.nwork) {
+            central_units_block<TIc, float, float, WGM * WGN, false>(g.cen, (bid - g.nwork) * WGM * WGN);
             return;
         }
     }
@@ -520,10 +585,11 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const int32_t* __re
     __shared__ __attribute__((aligned(16))) bf16_t As[2][NP][BM][LD];
     __shared__ __attribute__((aligned(16))) bf16_t Bs[2][NP][BN][LD];
 
-    const WorkItem wi = work[blockIdx.x];
+    const WorkItem wi = work[bid];
     if (wi.p < 0) return;   // padding of an XCD-ordered work list
     const SectorDev s = sec[wi.p];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int t = tid, lane = t & 63, wave = t >> 6;
+    __builtin_assume(t >= 0 && t < 64 * WGM * WGN);
     const int wm = wave % WGM, wn = wave / WGM;
     const int dL = s.dL, dR = s.dR;
     const ItemK it = decode_item(wi.part);
@@ -646,31 +712,79 @@ k_hv_gemm_bf16(const WorkItem* __restrict__ work, int nwork, const int32_t* __re
     }
 }
 
+template <int BM, int BN, int BK, int WGM, int WGN, int PF, bool X3, bool CEN>
+__global__ void __launch_bounds__(64 * WGM * WGN) k_hv_gemm_bf16(const HvK16<X3> g) {
+    hv_gemm_bf16_item<BM, BN, BK, WGM, WGN, PF, X3, CEN>(g, (int)blockIdx.x, (int)threadIdx.x);
+}
+
+template <int BM, int BN, int BK, int WGM, int WGN, int PF, bool X3, bool CEN>
+__global__ void __launch_bounds__(64 * WGM * WGN) k_hv_gemm_bf16_persist(const HvK16<X3> g, int* ctr, int total) {
+    persistent_loop(total, ctr,
+                    [&](int bid) { hv_gemm_bf16_item<BM, BN, BK, WGM, WGN, PF, X3, CEN>(g, bid, opaque_tid()); });
+}
+
+// Work-groups of kernel k the device holds at once: occupancy per compute
+// unit times the compute units.
+static int resident_groups(const void* k, int threads) {
+    int dev = 0, cus = 0, per = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        cus = prop.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, threads, 0) != hipSuccess || per < 1) per = 1;
+    return per * cus;
+}
+
+// Launch of a persistent kernel k over total items: a grid of the resident
+// work-groups (looked up once per kernel: `resident` is the caller's cache),
+// at most one per item.
+template <typename K, typename... Args>
+static void launch_persistent(K k, int& resident, int threads, hipStream_t st, int total, Args... args) {
+    if (resident == 0) resident = resident_groups((const void*)k, threads);
+    hipLaunchKernelGGL(k, dim3(std::max(1, std::min(total, resident))), dim3(threads), 0, st, args..., total);
+}
+
 template <int BM, int BN, int BK, int WGM, int WGN, int PF, bool X3>
 static void gemm_bf16_launch(const HvGemmArgs& a, const void* VT, hipStream_t st) {
     using TIc = typename std::conditional<X3, float, bf16_t>::type;
     constexpr int NW = WGM * WGN;
-    const bf16_t* HL = (const bf16_t*)a.HL;
-    const bf16_t* HR = (const bf16_t*)a.HR;
-    const bf16_t* VP = (const bf16_t*)a.V;
-    const bf16_t* V2 = (const bf16_t*)VT;
-    OutPtrs out;
-    out.W = (float*)a.W;
-    for (int i = 0; i < 3; ++i) out.X[i] = (float*)a.X[i];
-    const LoOffsets lo{a.lo[0], a.lo[1], a.lo[2], a.lo[3]};
+    HvK16<X3> g;
+    g.work = a.work;
+    g.nwork = a.nwork;
+    g.ksteps = a.ksteps;
+    g.sec = a.sec;
+    g.HL = (const bf16_t*)a.HL;
+    g.HRt = (const bf16_t*)a.HR;
+    g.VP = (const bf16_t*)a.V;
+    g.VT = (const bf16_t*)VT;
+    g.out.W = (float*)a.W;
+    for (int i = 0; i < 3; ++i) g.out.X[i] = (float*)a.X[i];
+    g.lo = LoOffsets{a.lo[0], a.lo[1], a.lo[2], a.lo[3]};
+    const int extra = a.fuse ? (a.fuse->nunits + NW - 1) / NW : 0;
+    const int total = a.nwork + extra;
     if (a.fuse) {
-        const int extra = (a.fuse->nunits + NW - 1) / NW;
-        hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, PF, X3, true>), dim3(a.nwork + extra), dim3(64 * NW),
-                           0, st, a.work, a.nwork, a.ksteps, a.sec, HL, HR, VP, V2, out, lo,
-                           central_args<TIc, float, float>(*a.fuse));
+        g.cen = central_args<TIc, float, float>(*a.fuse);
+        if (a.ctr) {
+            static int resident = 0;
+            launch_persistent(k_hv_gemm_bf16_persist<BM, BN, BK, WGM, WGN, PF, X3, true>, resident, 64 * NW, st, total,
+                              g, a.ctr);
+        } else {
+            hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, PF, X3, true>), dim3(total), dim3(64 * NW), 0, st, g);
+        }
     } else {
-        hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, PF, X3, false>), dim3(a.nwork), dim3(64 * NW), 0, st,
-                           a.work, a.nwork, a.ksteps, a.sec, HL, HR, VP, V2, out, lo, CentralK<TIc, float, float>{});
+        g.cen = CentralK<TIc, float, float>{};
+        if (a.ctr) {
+            static int resident = 0;
+            launch_persistent(k_hv_gemm_bf16_persist<BM, BN, BK, WGM, WGN, PF, X3, false>, resident, 64 * NW, st, total,
+                              g, a.ctr);
+        } else {
+            hipLaunchKernelGGL((k_hv_gemm_bf16<BM, BN, BK, WGM, WGN, PF, X3, false>), dim3(total), dim3(64 * NW), 0, st, g);
+        }
     }
 }
 
 hipError_t launch_hv_gemm_bf16(int shape, const HvGemmArgs& a, const void* VT, hipStream_t st) {
-    if (a.nwork <= 0) return hipSuccess;
+    if (a.nwork <= 0 && !(a.fuse && a.fuse->nunits > 0)) return hipSuccess;
     switch (shape) {
         case 14: gemm_bf16_launch<64, 64, 32, 2, 2, 1, false>(a, VT, st); break;
         case 15: gemm_bf16_launch<128, 128, 32, 2, 2, 1, false>(a, VT, st); break;
@@ -924,18 +1038,31 @@ static void gemm_launch(const HvGemmArgs& a, hipStream_t st) {
     g.V = (const T*)a.V;
     g.W = (T*)a.W;
     for (int i = 0; i < 3; ++i) g.X[i] = (T*)a.X[i];
+    const int extra = a.fuse ? (a.fuse->nunits + NW - 1) / NW : 0;
+    const int total = a.nwork + extra;
     if (a.fuse) {
         g.cen = central_args<T, T, T>(*a.fuse);
-        const int extra = (a.fuse->nunits + NW - 1) / NW;
-        hipLaunchKernelGGL((k_hv_gemm<T, BM, BN, BK, WGM, WGN, PF, true>), dim3(a.nwork + extra), dim3(64 * NW), 0, st, g);
+        if (a.ctr) {
+            static int resident = 0;
+            launch_persistent(k_hv_gemm_persist<T, BM, BN, BK, WGM, WGN, PF, true>, resident, 64 * NW, st, total, g,
+                              a.ctr);
+        } else {
+            hipLaunchKernelGGL((k_hv_gemm<T, BM, BN, BK, WGM, WGN, PF, true>), dim3(total), dim3(64 * NW), 0, st, g);
+        }
     } else {
         g.cen = CentralK<T, T, T>{};
-        hipLaunchKernelGGL((k_hv_gemm<T, BM, BN, BK, WGM, WGN, PF, false>), dim3(a.nwork), dim3(64 * NW), 0, st, g);
+        if (a.ctr) {
+            static int resident = 0;
+            launch_persistent(k_hv_gemm_persist<T, BM, BN, BK, WGM, WGN, PF, false>, resident, 64 * NW, st, total, g,
+                              a.ctr);
+        } else {
+            hipLaunchKernelGGL((k_hv_gemm<T, BM, BN, BK, WGM, WGN, PF, false>), dim3(total), dim3(64 * NW), 0, st, g);
+        }
     }
 }
 
 hipError_t launch_hv_gemm(int shape, const HvGemmArgs& a, hipStream_t st) {
-    if (a.nwork <= 0) return hipSuccess;
+    if (a.nwork <= 0 && !(a.fuse && a.fuse->nunits > 0)) return hipSuccess;
     switch (shape) {
         case 0: gemm_launch<double, 32, 32, 16, 2, 2, 1>(a, st); break;
         case 1: gemm_launch<double, 64, 64, 16, 2, 2, 1>(a, st); break;

@@ -550,7 +550,7 @@ struct SbHv : HvOps {
     void count(int prec, int64_t n) override { sb->hv_count[prec] += n; }
     int64_t counter(int prec) override { return sb->hv_count[prec]; }
     uint64_t fingerprint() override {
-        return config_fingerprint(sb->tile_sel, sb->split, sb->fuse, sb->xcd, sb->dense, sb->d_x, sb->d_w2, 0);
+        return config_fingerprint(sb->tile_sel, sb->split, sb->fuse, sb->xcd, sb->dense, sb->persist, sb->d_x, sb->d_w2, 0);
     }
 };
 

@@ -401,6 +401,11 @@ d2d_status upload_work(d2d_ctx* ctx, const WorkHost& h, WorkList& wl) {
         D2D_CHECK(ctx->alloc((void**)&wl.ksteps, cap * sizeof(int32_t)));
         wl.cap_steps = cap;
     }
+    if (!wl.ctr) {
+        // counters of persistent launches: each launch leaves them zero
+        D2D_CHECK(ctx->alloc((void**)&wl.ctr, 4 * sizeof(int)));
+        D2D_HIP(hipMemset(wl.ctr, 0, 4 * sizeof(int)));
+    }
     if (!h.items.empty())
         D2D_HIP(hipMemcpy(wl.items, h.items.data(), h.items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
     if (!h.ksteps.empty())
@@ -415,6 +420,7 @@ d2d_status upload_work(d2d_ctx* ctx, const WorkHost& h, WorkList& wl) {
 void free_work(d2d_ctx* ctx, WorkList& wl) {
     if (wl.items) ctx->free(wl.items, wl.cap_items * sizeof(WorkItem));
     if (wl.ksteps) ctx->free(wl.ksteps, wl.cap_steps * sizeof(int32_t));
+    if (wl.ctr) ctx->free(wl.ctr, 4 * sizeof(int));
     wl = WorkList{};
 }
 
@@ -460,6 +466,13 @@ d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkList& wl,
     // shares of the K-loops there; the central term adds them, or, fused,
     // leaves them to the consumer
     HvGemmArgs g{wl.items, wl.n, wl.ksteps, t.sec, t.HL[prec], t.HR[prec], v, w, {t.x[0], t.x[1], t.x[2]}, nullptr};
+    if (t.persist) {
+        if (!wl.ctr) {
+            set_error("persistent launch without the work list's counters");
+            return D2D_ESTATE;
+        }
+        g.ctr = wl.ctr;
+    }
     CentralArgs c{};
     c.units = t.cunits;
     c.nunits = t.n_cunits;
@@ -494,6 +507,7 @@ d2d_status hv_launch(const HvTables& t, int prec, int shape, const WorkList& wl,
             g0.fuse = nullptr;
             g1.work = wl.items + wl.n0;
             g1.nwork = wl.n - wl.n0;
+            if (g.ctr) g1.ctr = g.ctr + 2;   // the second launch counts on its own pair
             const int shape1 = asym_partner(shape);
             if (b16) {
                 D2D_HIP(launch_hv_gemm_bf16(shape, g0, t.vt, s));
@@ -552,6 +566,7 @@ d2d_status sb_hv_parts(d2d_sb* sb, int prec, const void* v, void* w, hipStream_t
     const WorkList* wl = nullptr;
     D2D_CHECK(sb_work(sb, shape, split, sb->xcd[prec], sb->dense[prec], &wl));
     HvTables t = tables_of(sb);
+    t.persist = sb->persist[prec];
     D2D_CHECK(sb_ensure_parts(sb, split, parts != nullptr));
     for (int i = 0; i < split_parts(split); ++i) t.x[i] = sb->d_x[i];
     if (parts) {
@@ -1163,6 +1178,7 @@ extern "C" d2d_status d2d_hv_noalloc(d2d_sb* sb, int prec, const void* v, void* 
         return D2D_EINVAL;
     }
     HvTables t = tables_of(sb);
+    t.persist = sb->persist[prec];
     if (nparts > 0) {
         void* base = nullptr;
         D2D_CHECK(scratch_on(sb->ctx->device, &base));
@@ -1193,11 +1209,14 @@ bool decode_tile(int prec, int tile, TileSel* out) {
     t.fuse = tile >= 0 ? ((tile & D2D_TILE_FUSED) ? 1 : 0) : (prec != D2D_FP64 ? 1 : 0);
     t.xcd = tile >= 0 && (tile & D2D_TILE_XCD) ? 1 : 0;
     t.dense = tile >= 0 && (tile & D2D_TILE_DENSE) ? 1 : 0;
+    t.persist = tile >= 0 && (tile & D2D_TILE_PERSIST) ? 1 : 0;
     t.shape = tile < 0 ? -1 : (tile & 0xFFFF);
     if (t.shape >= tile_shape_count() || (t.shape >= 0 && tile_shape(t.shape).prec != prec) ||
         (tile >= 0 && (tile & ~(0xFFFF | D2D_TILE_SPLIT | D2D_TILE_SPLIT4 | D2D_TILE_FUSED | D2D_TILE_XCD |
-                                D2D_TILE_DENSE | D2D_TILE_ASYM))) ||
+                                D2D_TILE_DENSE | D2D_TILE_ASYM | D2D_TILE_PERSIST))) ||
         (tile >= 0 && (tile & D2D_TILE_SPLIT) && (tile & D2D_TILE_SPLIT4)) ||
+        // a persistent launch takes items in list order, which an XCD order cannot steer
+        (t.persist && t.xcd) ||
         // the asymmetric split: a shape with a partner, no other split, plain order
         (t.split == 3 && (asym_partner(t.shape) < 0 || (tile & (D2D_TILE_SPLIT | D2D_TILE_SPLIT4 | D2D_TILE_XCD)))))
         return false;
@@ -1208,7 +1227,8 @@ bool decode_tile(int prec, int tile, TileSel* out) {
 int encode_tile(const TileSel& t) {
     return t.shape | (t.split == 1 ? D2D_TILE_SPLIT : 0) | (t.split == 2 ? D2D_TILE_SPLIT4 : 0) |
            (t.split == 3 ? D2D_TILE_ASYM : 0) |
-           (t.fuse ? D2D_TILE_FUSED : 0) | (t.xcd ? D2D_TILE_XCD : 0) | (t.dense ? D2D_TILE_DENSE : 0);
+           (t.fuse ? D2D_TILE_FUSED : 0) | (t.xcd ? D2D_TILE_XCD : 0) | (t.dense ? D2D_TILE_DENSE : 0) |
+           (t.persist ? D2D_TILE_PERSIST : 0);
 }
 
 }  // namespace d2d
@@ -1228,6 +1248,7 @@ extern "C" d2d_status d2d_sb_set_tile(d2d_sb* sb, int prec, int tile) {
     sb->fuse[prec] = t.fuse;
     sb->xcd[prec] = t.xcd;
     sb->dense[prec] = t.dense;
+    sb->persist[prec] = t.persist;
     // the work list of the configuration is built here, so that products in
     // it (d2d_hv_noalloc among them) need no allocation
     if ((sb->prec_mask & (1u << prec)) && sb->HL[prec]) {
@@ -1366,14 +1387,16 @@ d2d_status tune_configs(hipStream_t s, int prec, int reps, const std::function<d
     bool any = false;
     double bms = 1e300;
     const int nsh = tile_shape_count();
-    for (int tt = 0; tt < 16 * nsh && st == D2D_OK; ++tt) {
+    for (int tt = 0; tt < 32 * nsh && st == D2D_OK; ++tt) {
         TileSel c;
         c.shape = tt % nsh;
         c.split = (tt / nsh) % 4;
         c.fuse = (tt / (4 * nsh)) % 2;
-        c.xcd = tt / (8 * nsh);
+        c.xcd = (tt / (8 * nsh)) % 2;
+        c.persist = tt / (16 * nsh);
         if (tile_shape(c.shape).prec != prec) continue;
         if (c.split == 3 && (asym_partner(c.shape) < 0 || c.xcd)) continue;
+        if (c.persist && c.xcd) continue;
         st = run(c);   // warm-up (also builds the work list)
         if (st != D2D_OK) break;
         if (hipEventRecord(e0, s) != hipSuccess) st = D2D_EDEVICE;
@@ -1415,6 +1438,7 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
         sb->fuse[prec] = c.fuse;
         sb->xcd[prec] = c.xcd;
         sb->dense[prec] = c.dense;
+        sb->persist[prec] = c.persist;
     };
     const uint64_t key = sector_key(sb, prec);
     TileSel sel;
@@ -1433,7 +1457,8 @@ extern "C" d2d_status d2d_sb_autotune(d2d_sb* sb, int prec, int reps, int* best_
         ctx->free(v, (size_t)sb->N * in_sz);
         return st;
     }
-    const TileSel saved{sb->tile_sel[prec], sb->split[prec], sb->fuse[prec], sb->xcd[prec], sb->dense[prec]};
+    const TileSel saved{sb->tile_sel[prec], sb->split[prec], sb->fuse[prec], sb->xcd[prec], sb->dense[prec],
+                        sb->persist[prec]};
     if (launch_fill(v, prec, sb->N, 0.5, s) != hipSuccess) {
         set_error("d2d_sb_autotune: HIP setup failed");
         st = D2D_EDEVICE;

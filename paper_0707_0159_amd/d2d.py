@@ -27,6 +27,7 @@ D2D_TILE_SPLIT4 = 1 << 18
 D2D_TILE_XCD = 1 << 19
 D2D_TILE_DENSE = 1 << 20
 D2D_TILE_ASYM = 1 << 21
+D2D_TILE_PERSIST = 1 << 22
 
 _STATUS = {0: "D2D_OK", -1: "D2D_EINVAL", -2: "D2D_ENOMEM", -3: "D2D_EDEVICE", -4: "D2D_ENOCONV",
            -5: "D2D_ESTATE"}

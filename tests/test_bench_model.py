@@ -73,3 +73,17 @@ def test_one_kernel_step_reads_product_and_window_once(bench):
     restart = 2 * n * (88 + 8 * 4) / bench.PEAK["hbm"]
     assert two["vec_s"] == pytest.approx((30 * n * (2 * (4 + 12) + 4) / bench.PEAK["hbm"]) + restart)
     assert one["vec_s"] == pytest.approx((30 * n * ((4 + 12) + 4) / bench.PEAK["hbm"]) + restart)
+
+
+def test_tile_desc(bench):
+    """The bench line's description of a launch configuration (host only: a
+    made-up shape table of (precision, BM, BN, BK, prefetch depth) rows)."""
+    from paper_0707_0159_amd import d2d
+    shapes = [(1, 64, 64, 16, 2), (1, 64, 256, 16, 2), (1, 256, 64, 16, 2)]
+    d = bench.tile_desc(1 | d2d.D2D_TILE_ASYM, shapes)
+    assert d["split_k_loops"] == "asymmetric" and d["BMxBNxBK"] == "64x256x16 + 256x64x16"
+    d = bench.tile_desc(0 | d2d.D2D_TILE_SPLIT4 | d2d.D2D_TILE_PERSIST, shapes)
+    assert d["split_k_loops"] == "halves" and d["persistent"] and d["BMxBNxBK"] == "64x64x16"
+    d = bench.tile_desc(0 | d2d.D2D_TILE_SPLIT | d2d.D2D_TILE_XCD | d2d.D2D_TILE_FUSED, shapes)
+    assert d["split_k_loops"] is True and d["xcd_order"] and d["central_in_gemm_launch"] and not d["persistent"]
+    assert bench.split_words("asymmetric").startswith(", asymmetric")

@@ -85,6 +85,9 @@ def test_batch_set_tile_equals_single(ctx, prec):
     from helpers import asym_shapes
     cfgs = [sh | ((d2d.D2D_TILE_SPLIT4 | d2d.D2D_TILE_XCD) if k % 2 else 0) for k, sh in enumerate(shapes)]
     cfgs += [sh | d2d.D2D_TILE_ASYM for sh in asym_shapes(d2d, prec)]
+    # persistent launches (one counter pair per launch, left zero for the next)
+    cfgs += [shapes[0] | d2d.D2D_TILE_PERSIST, shapes[-1] | d2d.D2D_TILE_PERSIST | d2d.D2D_TILE_SPLIT4]
+    cfgs += [sh | d2d.D2D_TILE_ASYM | d2d.D2D_TILE_PERSIST for sh in asym_shapes(d2d, prec)[:1]]
     for k, cfg in enumerate(cfgs):
         d2d.d2d_batch_set_tile(b, prec, cfg)
         assert_batch_equals_single(ctx, b, probs, prec, cfg, 600 + k)

@@ -100,6 +100,54 @@ def test_hubbard_2x16_every_tile_shape(ctx, prec, tol):
     prob.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+def test_persistent_launch_is_bitwise_plain(ctx, prec):
+    """D2D_TILE_PERSIST: a grid of resident work-groups taking the work items
+    from a counter gives the plain launch's product bit for bit, for every
+    tile shape of the precision, unsplit, split, halved and asymmetric; the
+    counters the last work-group clears make back-to-back persistent launches
+    (and plain ones in between) agree too.  Checked against the oracle as
+    well (2x16 Hubbard m=256, 47 sector pairs of ragged size)."""
+    from paper_0707_0159_amd import d2d
+    wl = W.HUBBARD_2X16_M256
+    osb = oracle_superblock(wl)
+    prob = GpuProblem(ctx, wl, prec_mask=15)
+    cfgs = [i | sp for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == prec
+            for sp in (0, d2d.D2D_TILE_SPLIT, d2d.D2D_TILE_SPLIT4)]
+    cfgs += [i | d2d.D2D_TILE_ASYM for i in asym_shapes(d2d, prec)]
+    v = W.random_vector(osb.N, 77)
+    # FP64 and FP32 also against the oracle (the BF16 forms have their own parity tests)
+    ref = osb.hv_factored(v) if prec in (0, 1) else None
+    bound = osb.hv_abs_bound(v) if prec in (0, 1) else None
+    secs = osb.sector_table()
+    for cfg in cfgs:
+        d2d.d2d_sb_set_tile(prob.sb, prec, cfg)
+        plain = gpu_hv_prec(ctx, prob, prec, v)
+        d2d.d2d_sb_set_tile(prob.sb, prec, cfg | d2d.D2D_TILE_PERSIST)
+        first = gpu_hv_prec(ctx, prob, prec, v)
+        second = gpu_hv_prec(ctx, prob, prec, v)
+        assert np.array_equal(first, plain), f"cfg {cfg}"
+        assert np.array_equal(second, plain), f"cfg {cfg} second launch"
+        if ref is not None:
+            assert_parity(first, ref, bound, 1e-12 if prec == 0 else 1e-5, secs, f"persistent prec {prec} cfg {cfg}")
+    with pytest.raises(RuntimeError):   # a persistent launch takes no XCD order
+        d2d.d2d_sb_set_tile(prob.sb, prec, cfgs[0] | d2d.D2D_TILE_PERSIST | d2d.D2D_TILE_XCD)
+    prob.close()
+
+
+def gpu_hv_prec(ctx, prob, prec, v):
+    """d2d_hv with the input in the precision's storage type (BF16 inputs are
+    the FP32 values rounded by torch)."""
+    from paper_0707_0159_amd import d2d
+    dt = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16, 3: torch.float32}[prec]
+    with torch.cuda.stream(ctx.stream):
+        vd = torch.as_tensor(np.asarray(v, dtype=np.float64)).to("cuda").to(dt)
+        wd = torch.full(vd.shape, float("nan"), dtype=torch.float64 if prec == 0 else torch.float32, device="cuda")
+        d2d.d2d_hv(prob.sb, prec, vd, wd)
+    ctx.stream.synchronize()
+    return wd.double().cpu().numpy()
+
+
 def test_sector_table_matches_oracle(ctx):
     from paper_0707_0159_amd import d2d
     wl = W.HUBBARD_2X16_M256

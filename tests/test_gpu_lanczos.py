@@ -389,3 +389,34 @@ def test_graphs_replayed_across_calls(ctx, prec):
     finally:
         d2d.d2d_sb_set_tile(prob.sb, prec, -1)
         prob.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+def test_persistent_launch_in_captured_graphs(ctx, prec):
+    """The inner steps' grouped launch as a persistent launch (D2D_TILE_PERSIST,
+    central term fused, split K-loops) inside captured graphs replayed across
+    calls: its counters are left zero by every launch, so every replay takes
+    every work item, and the solve is bit for bit the plain launch's (same
+    energy, restart log and Ritz vector)."""
+    from paper_0707_0159_amd import d2d
+    wl = W.HUBBARD_2X16_M256
+    prob = GpuProblem(ctx, wl, prec_mask=15)
+    try:
+        shape = [i for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == prec][0]
+        cfg = shape | d2d.D2D_TILE_SPLIT | d2d.D2D_TILE_FUSED
+        d2d.d2d_sb_set_tile(prob.sb, prec, cfg)
+        plain = run(ctx, prob, prec, wl.seed, k_in=48, graph=0, window=3, tol=1e-8)
+        d2d.d2d_sb_set_tile(prob.sb, prec, cfg | d2d.D2D_TILE_PERSIST)
+        calls = [run(ctx, prob, prec, wl.seed, k_in=48, graph=g, window=3, tol=1e-8) for g in (0, 1, 1)]
+        print("persistent", prec, "restarts", plain[2]["restarts"], "captures",
+              [c[2]["graph_captures"] for c in calls])
+        assert calls[1][2]["graph_captures"] >= 1 and calls[2][2]["graph_captures"] == 0
+        for st, e, stats, psi in calls:
+            assert st == 0 and e == plain[1]
+            assert np.array_equal(np.asarray(stats["log_theta"]), np.asarray(plain[2]["log_theta"]))
+            assert np.array_equal(psi, plain[3])
+        E0 = reference_energy(wl.name)
+        assert abs(plain[1] - E0) <= 1e-10 * abs(E0)
+    finally:
+        d2d.d2d_sb_set_tile(prob.sb, prec, -1)
+        prob.close()
