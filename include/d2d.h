@@ -136,6 +136,7 @@ typedef struct {
     const int64_t* op_off;
     const double* op_data;
     int64_t op_data_len;   /* number of doubles in op_data (bounds check) */
+    int64_t H_len;         /* number of doubles in H: the sum of sec_dim[s]^2 (bounds check) */
 } d2d_block_desc;
 
 d2d_status d2d_block_import(d2d_ctx* ctx, const d2d_model* model, const d2d_block_desc* desc,

@@ -394,6 +394,12 @@ extern "C" d2d_status d2d_block_import(d2d_ctx* ctx, const d2d_model* model, con
         set_error("block of %lld states exceeds the supported 16384", (long long)m);
         return D2D_EINVAL;
     }
+    int64_t hlen = 0;
+    for (int s = 0; s < d->nsec; ++s) hlen += d->sec_dim[s] * d->sec_dim[s];
+    if (d->H_len != hlen) {
+        set_error("H holds %lld doubles, the sectors' blocks need %lld", (long long)d->H_len, (long long)hlen);
+        return D2D_EINVAL;
+    }
     auto b = std::make_unique<d2d_block>();
     b->ctx = ctx;
     b->model = *model;

@@ -2,6 +2,7 @@
 // layout, device assembly of the dense sector operators, central-term gather
 // tables, grouped-GEMM work lists and the Hv entry point.
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -247,7 +248,15 @@ void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep
         // columns inside one run of column-3 states.  The rows of a run couple
         // only to the runs of the column states its column Hamiltonian and
         // bond operators reach, so an aligned segment runs only those K steps.
-        std::vector<std::pair<int, WorkItem>> w0, w1;
+        // each item with its place in its sector's item grid: for H_l V items
+        // a = row segment (operator panel), b = column tile (input panel);
+        // for V H_r^T items a = column segment, b = row tile
+        struct Ent {
+            int klen;
+            WorkItem it;
+            int a, b;
+        };
+        std::vector<Ent> w0, w1;
         const bool runs = nz && !nz->runsL.empty();
         // steps of BK columns over a K extent KL (padded for BF16) whose
         // 16-column cells are set in any of the rows [r0, r1) of mask (nc cells per row)
@@ -277,49 +286,103 @@ void make_work(const std::vector<SectorDev>& pairs, const std::vector<int>* keep
                         WorkItem it{(int32_t)p, i, j, 1 | (0 << 2), {p0.row_off[i], 0}, {p0.row_n[i], 0}};
                         const int rows = std::min(ts.BM, sd.dL - i * ts.BM), cols = std::min(ts.BN, sd.dR - j * ts.BN);
                         out.flops += steps_flops(out.ksteps, it.ks[0], it.kn[0], ts.BK, sd.dL, rows, cols);
-                        w0.push_back({it.kn[0], it});
+                        w0.push_back({it.kn[0], it, i, j});
                     }
                 for (int j = 0; j < (sd.dR + ts1->BN - 1) / ts1->BN; ++j)
                     for (int i = 0; i < (sd.dL + ts1->BM - 1) / ts1->BM; ++i) {
                         WorkItem it{(int32_t)p, i, j, 2 | (1 << 2), {0, p1.col_off[j]}, {0, p1.col_n[j]}};
                         const int rows = std::min(ts1->BM, sd.dL - i * ts1->BM), cols = std::min(ts1->BN, sd.dR - j * ts1->BN);
                         out.flops += steps_flops(out.ksteps, it.ks[1], it.kn[1], ts1->BK, sd.dR, rows, cols);
-                        w1.push_back({it.kn[1], it});
+                        w1.push_back({it.kn[1], it, j, i});
                     }
                 continue;
             }
             const int cL = (sd.dL + NZ_CELL - 1) / NZ_CELL, cR = (sd.dR + NZ_CELL - 1) / NZ_CELL;
             const std::vector<int>& rl = *nz->runsL[p];
+            int seg = 0;
             for (size_t q = 0; q + 1 < rl.size(); ++q)
-                for (int t0 = rl[q]; t0 < rl[q + 1]; t0 += ts.BM) {
+                for (int t0 = rl[q]; t0 < rl[q + 1]; t0 += ts.BM, ++seg) {
                     const int t1 = std::min(rl[q + 1], t0 + ts.BM);
                     const auto st = seg_steps(nz->rowL[p], cL, t0, t1, KL, ts.BK);
                     for (int j = 0; j < (sd.dR + ts.BN - 1) / ts.BN; ++j) {
                         WorkItem it{(int32_t)p, t0, j, 1 | (0 << 2) | ITEM_ALIGNED, {st.first, 0}, {st.second, t1 - t0}};
                         const int cols = std::min(ts.BN, sd.dR - j * ts.BN);
                         out.flops += steps_flops(out.ksteps, it.ks[0], it.kn[0], ts.BK, sd.dL, t1 - t0, cols);
-                        w0.push_back({it.kn[0], it});
+                        w0.push_back({it.kn[0], it, seg, j});
                     }
                 }
             const std::vector<int>& rr = *nz->runsR[p];
+            seg = 0;
             for (size_t q = 0; q + 1 < rr.size(); ++q)
-                for (int t0 = rr[q]; t0 < rr[q + 1]; t0 += ts1->BN) {
+                for (int t0 = rr[q]; t0 < rr[q + 1]; t0 += ts1->BN, ++seg) {
                     const int t1 = std::min(rr[q + 1], t0 + ts1->BN);
                     const auto st = seg_steps(nz->colR[p], cR, t0, t1, KR, ts1->BK);
                     for (int i = 0; i < (sd.dL + ts1->BM - 1) / ts1->BM; ++i) {
                         WorkItem it{(int32_t)p, i, t0, 2 | (1 << 2) | ITEM_ALIGNED, {0, st.first}, {t1 - t0, st.second}};
                         const int rows = std::min(ts1->BM, sd.dL - i * ts1->BM);
                         out.flops += steps_flops(out.ksteps, it.ks[1], it.kn[1], ts1->BK, sd.dR, rows, t1 - t0);
-                        w1.push_back({it.kn[1], it});
+                        w1.push_back({it.kn[1], it, seg, i});
                     }
                 }
         }
-        auto lpt = [](const std::pair<int, WorkItem>& a, const std::pair<int, WorkItem>& b) { return a.first > b.first; };
+        if (xcd) {
+            // XCD-aware order per launch (work-group b runs on XCD b mod 8):
+            // each sector's item grid is cut into 8 rectangles, 2 bands of
+            // a (operator segments) x 4 bands of b (input panels) when the
+            // grid allows, else 8 runs of its a-major order; XCD x takes
+            // rectangle x of every sector, sectors in order of decreasing
+            // work, each rectangle a-major so that an XCD's work-groups in
+            // flight share their operator segments and input panels in its
+            // L2.  Lists are padded with empty items (p = -1) to one length.
+            auto order_xcd = [&](std::vector<Ent>& w) {
+                constexpr int NX = 8;
+                std::vector<std::vector<WorkItem>> bins(NX);
+                std::map<int, std::vector<Ent>> by_p;
+                for (auto& e : w) by_p[e.it.p].push_back(e);
+                std::vector<std::pair<double, int>> ps;
+                for (auto& kv : by_p) {
+                    double work = 0;
+                    for (auto& e : kv.second) work += e.klen;
+                    ps.push_back({work, kv.first});
+                }
+                std::stable_sort(ps.begin(), ps.end(), [](const std::pair<double, int>& x, const std::pair<double, int>& y) {
+                    return x.first > y.first;
+                });
+                for (auto& pw : ps) {
+                    std::vector<Ent>& v = by_p[pw.second];
+                    int na = 0, nb = 0;
+                    for (auto& e : v) {
+                        na = std::max(na, e.a + 1);
+                        nb = std::max(nb, e.b + 1);
+                    }
+                    std::stable_sort(v.begin(), v.end(), [](const Ent& x, const Ent& y) {
+                        return x.a != y.a ? x.a < y.a : x.b < y.b;
+                    });
+                    if (na >= 2 && nb >= 4) {
+                        for (auto& e : v) bins[(e.a * 2 / na) * 4 + e.b * 4 / nb].push_back(e.it);
+                    } else {
+                        const size_t n = v.size();
+                        for (int x = 0; x < NX; ++x)
+                            for (size_t q = x * n / NX; q < (x + 1) * n / NX; ++q) bins[x].push_back(v[q].it);
+                    }
+                }
+                size_t len = 0;
+                for (auto& b : bins) len = std::max(len, b.size());
+                for (size_t j = 0; j < len; ++j)
+                    for (int x = 0; x < NX; ++x)
+                        out.items.push_back(j < bins[x].size() ? bins[x][j] : WorkItem{-1, 0, 0, 0, {0, 0}, {0, 0}});
+            };
+            order_xcd(w0);
+            out.n0 = (int)out.items.size();
+            order_xcd(w1);
+            return;
+        }
+        auto lpt = [](const Ent& a, const Ent& b) { return a.klen > b.klen; };
         std::stable_sort(w0.begin(), w0.end(), lpt);
         std::stable_sort(w1.begin(), w1.end(), lpt);
-        for (auto& x : w0) out.items.push_back(x.second);
+        for (auto& x : w0) out.items.push_back(x.it);
         out.n0 = (int)out.items.size();
-        for (auto& x : w1) out.items.push_back(x.second);
+        for (auto& x : w1) out.items.push_back(x.it);
         return;
     }
     std::vector<PairSteps> ps(pairs.size());
@@ -1217,8 +1280,8 @@ bool decode_tile(int prec, int tile, TileSel* out) {
         (tile >= 0 && (tile & D2D_TILE_SPLIT) && (tile & D2D_TILE_SPLIT4)) ||
         // a persistent launch takes items in list order, which an XCD order cannot steer
         (t.persist && t.xcd) ||
-        // the asymmetric split: a shape with a partner, no other split, plain order
-        (t.split == 3 && (asym_partner(t.shape) < 0 || (tile & (D2D_TILE_SPLIT | D2D_TILE_SPLIT4 | D2D_TILE_XCD)))))
+        // the asymmetric split: a shape with a partner, no other split
+        (t.split == 3 && (asym_partner(t.shape) < 0 || (tile & (D2D_TILE_SPLIT | D2D_TILE_SPLIT4)))))
         return false;
     *out = t;
     return true;
@@ -1395,7 +1458,7 @@ d2d_status tune_configs(hipStream_t s, int prec, int reps, const std::function<d
         c.xcd = (tt / (8 * nsh)) % 2;
         c.persist = tt / (16 * nsh);
         if (tile_shape(c.shape).prec != prec) continue;
-        if (c.split == 3 && (asym_partner(c.shape) < 0 || c.xcd)) continue;
+        if (c.split == 3 && asym_partner(c.shape) < 0) continue;
         if (c.persist && c.xcd) continue;
         st = run(c);   // warm-up (also builds the work list)
         if (st != D2D_OK) break;

@@ -44,7 +44,8 @@ class d2d_model(C.Structure):
 class d2d_block_desc(C.Structure):
     _fields_ = [("side", C.c_int), ("ncols", C.c_int), ("nsec", C.c_int), ("sec_qn", i64p), ("sec_dim", i64p),
                 ("H", f64p), ("nops", C.c_int), ("op_key", i64p), ("nblk", C.c_int), ("op_blk", i64p),
-                ("op_off", i64p), ("op_data", f64p), ("op_data_len", C.c_int64)]
+                ("op_off", i64p), ("op_data", f64p), ("op_data_len", C.c_int64),
+                ("H_len", C.c_int64)]
 
 
 class d2d_sb_info_t(C.Structure):
@@ -214,6 +215,7 @@ def d2d_block_import(ctx: Ctx, model: d2d_model, arrays: dict) -> int:
     d.op_off = keep["op_off"].ctypes.data_as(i64p)
     d.op_data = keep["op_data"].ctypes.data_as(f64p)
     d.op_data_len = int(keep["op_data"].size)
+    d.H_len = int(keep["H"].size)
     h = P()
     _check(load().d2d_block_import(P(ctx.handle), C.byref(model), C.byref(d), C.byref(h)))
     return h.value

@@ -84,7 +84,7 @@ def test_batch_set_tile_equals_single(ctx, prec):
     shapes = [i for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == prec]
     from helpers import asym_shapes
     cfgs = [sh | ((d2d.D2D_TILE_SPLIT4 | d2d.D2D_TILE_XCD) if k % 2 else 0) for k, sh in enumerate(shapes)]
-    cfgs += [sh | d2d.D2D_TILE_ASYM for sh in asym_shapes(d2d, prec)]
+    cfgs += [sh | d2d.D2D_TILE_ASYM | x for sh in asym_shapes(d2d, prec) for x in (0, d2d.D2D_TILE_XCD)]
     # persistent launches (one counter pair per launch, left zero for the next)
     cfgs += [shapes[0] | d2d.D2D_TILE_PERSIST, shapes[-1] | d2d.D2D_TILE_PERSIST | d2d.D2D_TILE_SPLIT4]
     cfgs += [sh | d2d.D2D_TILE_ASYM | d2d.D2D_TILE_PERSIST for sh in asym_shapes(d2d, prec)[:1]]

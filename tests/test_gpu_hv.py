@@ -86,7 +86,7 @@ def test_hubbard_2x16_every_tile_shape(ctx, prec, tol):
               for sp in (0, d2d.D2D_TILE_SPLIT, d2d.D2D_TILE_SPLIT4,
                          d2d.D2D_TILE_XCD, d2d.D2D_TILE_SPLIT | d2d.D2D_TILE_XCD,
                          d2d.D2D_TILE_SPLIT4 | d2d.D2D_TILE_XCD)]
-    shapes += [i | d2d.D2D_TILE_ASYM for i in asym_shapes(d2d, prec)]
+    shapes += [i | d2d.D2D_TILE_ASYM | x for i in asym_shapes(d2d, prec) for x in (0, d2d.D2D_TILE_XCD)]
     assert any(sh & d2d.D2D_TILE_ASYM for sh in shapes)
     secs = osb.sector_table()
     for k in range(3):
@@ -255,7 +255,7 @@ def test_bf16_every_tile_shape(ctx, name):
               for sp in (0, d2d.D2D_TILE_SPLIT, d2d.D2D_TILE_SPLIT4,
                          d2d.D2D_TILE_XCD, d2d.D2D_TILE_SPLIT | d2d.D2D_TILE_XCD,
                          d2d.D2D_TILE_SPLIT4 | d2d.D2D_TILE_XCD)]
-    shapes += [i | d2d.D2D_TILE_ASYM for i in asym_shapes(d2d, d2d.D2D_BF16)]
+    shapes += [i | d2d.D2D_TILE_ASYM | x for i in asym_shapes(d2d, d2d.D2D_BF16) for x in (0, d2d.D2D_TILE_XCD)]
     assert shapes
     secs = osb.sector_table()
     for k in range(2):
@@ -308,7 +308,7 @@ def test_bf16x3_every_tile_shape(ctx, name):
     prob = GpuProblem(ctx, wl, prec_mask=15)
     shapes = [i | sp for i, s in enumerate(d2d.d2d_tile_shapes()) if s[0] == d2d.D2D_BF16X3
               for sp in (0, d2d.D2D_TILE_SPLIT, d2d.D2D_TILE_SPLIT4, d2d.D2D_TILE_XCD)]
-    shapes += [i | d2d.D2D_TILE_ASYM for i in asym_shapes(d2d, d2d.D2D_BF16X3)]
+    shapes += [i | d2d.D2D_TILE_ASYM | x for i in asym_shapes(d2d, d2d.D2D_BF16X3) for x in (0, d2d.D2D_TILE_XCD)]
     assert shapes
     worst = 0.0
     secs = osb.sector_table()
@@ -425,6 +425,10 @@ def test_skipped_k_steps_add_nothing(ctx, prec):
                       f"({fs / prob.info['flops_nnz']:.3f} of F_nnz)")
                 assert np.array_equal(wd, ws)
                 assert abs(fd - ad) <= 1e-9 * ad and abs(fs - asf) <= 1e-9 * ad
+                # the XCD order moves the same items: same product, same flops
+                d2d.d2d_sb_set_tile(prob.sb, prec, i | sp | d2d.D2D_TILE_XCD)
+                assert d2d.d2d_sb_gemm_flops(prob.sb, prec) == fs
+                assert np.array_equal(run(ctx, prob, v), ws)
                 continue
             d2d.d2d_sb_set_tile(prob.sb, prec, i | sp | d2d.D2D_TILE_DENSE)
             fd = d2d.d2d_sb_gemm_flops(prob.sb, prec)
