@@ -440,6 +440,67 @@ def bench_batch(args):
     print(json.dumps(line))
 
 
+SWEEP_CASES = [
+    # Fig. 3a: 5-leg x 10 Heisenberg ladder, S_z = 0; Fig. 3b: 3-leg x 10
+    # Hubbard ladder, U/t = 10, 28 fermions (14 up, 14 down); smaller lattices
+    # of the infinite phase at the same filling
+    {"name": "heisenberg_5x10", "kind": "heisenberg", "legs": 5, "L": 10, "t": 1.0, "U": 0.0,
+     "m": [32, 128], "target": lambda ns: (ns // 2, 0)},
+    {"name": "hubbard_3x10_U10_N28", "kind": "hubbard", "legs": 3, "L": 10, "t": 1.0, "U": 10.0,
+     "m": [64, 256], "target": lambda ns: (int(round(14 * ns / 30)), int(round(14 * ns / 30)))},
+]
+
+
+def bench_sweeps(args):
+    """Finite-system sweeps on the lattices of Fig. 3: the ground energy at
+    the middle position after each sweep, every step's products with the
+    transformed start vector and from a random one, and wall times."""
+    import numpy as np
+    import torch
+
+    from paper_0707_0159_amd import d2d
+    from paper_0707_0159_amd.sweep import finite_sweeps
+
+    ctx = d2d.d2d_ctx_create(0)
+    out = []
+    nsw = max(1, min(args.steps, 4)) if args.steps else 2
+    for case in SWEEP_CASES:
+        model = d2d.make_model(case["kind"], case["legs"], case["t"], case["U"], 1.0)
+        n_col = 2 ** case["legs"] if case["kind"] == "heisenberg" else 4 ** case["legs"]
+        for m in case["m"]:
+            # turn where the blocks reach m states (exact below when m is a power of the column dimension)
+            l_min = 1
+            while n_col ** l_min < m:
+                l_min += 1
+            t0 = time.perf_counter()
+            inf, recs = finite_sweeps(ctx, model, case["L"], m, case["target"], l_min, nsw, prec=d2d.D2D_FP32,
+                                      compare_random=True,
+                                      log=lambda r: print(json.dumps({k: v for k, v in r.items()
+                                                                      if not isinstance(v, list)}), flush=True))
+            wall = time.perf_counter() - t0
+            mid = [r for r in recs if r["position"] == case["L"] // 2 - 1 and r["direction"] != 1]
+            per_sweep = [r["energy"] for r in mid]
+            steps = recs[1:]
+            out.append({
+                "lattice": case["name"], "m": m, "l_min": l_min, "sweeps": nsw,
+                "N_middle": recs[0]["N"], "energy_infinite": inf[-1]["energy"],
+                "energy_middle_per_sweep": per_sweep,
+                "energy_lowest": min(r["energy"] for r in recs),
+                "products_transformed_start": int(sum(sum(r["hv_count"]) for r in steps)),
+                "products_random_start": int(sum(sum(r["hv_count_random"]) for r in steps)),
+                "ms_solve_transformed_start": float(np.sum([r["ms_solve"] for r in steps])),
+                "ms_solve_random_start": float(np.sum([r["ms_solve_random"] for r in steps])),
+                "ms_density_matrix": float(np.sum([r.get("ms_dm", 0.0) for r in steps])),
+                "ms_transform": float(np.sum([r.get("ms_transform", 0.0) for r in steps])),
+                "steps": len(recs), "wall_s": wall,
+                "truncation_max": max(r["trunc"] for r in recs),
+            })
+            print(json.dumps(out[-1]), flush=True)
+    d2d.d2d_ctx_destroy(ctx)
+    print(json.dumps({"sweeps": out, "precision": "FP32-mixed Hv, FP64 residual restarts",
+                      "data": "synthetic (no inputs: blocks grown from exact one-column blocks)"}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -471,6 +532,9 @@ def main():
     ap.add_argument("--dmrg-step", action="store_true",
                     help="time the routines of one DMRG step on the workload (the paper's split: exact "
                          "diagonalisation, density-matrix formation, diagonalisation, renormalisation)")
+    ap.add_argument("--sweeps", action="store_true",
+                    help="finite-system sweeps on the two lattices of Fig. 3 (energy per sweep, the products the "
+                         "wavefunction transformation saves, time per step)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path "
@@ -483,6 +547,10 @@ def main():
 
     import workloads as W
     from paper_0707_0159_amd import d2d
+
+    if args.sweeps:
+        bench_sweeps(args)
+        return
 
     if args.profile == "copy":
         nbytes = 1 << 30

@@ -460,6 +460,29 @@ d2d_status d2d_density_matrix_timed(d2d_sb* sb, const double* psi, int side, int
                                     d2d_block** new_block, double* trunc_err, double* spectrum,
                                     int64_t* spectrum_len, double ms[3]);
 
+/* Wavefunction transformation: the initial guess of the next superblock of
+ * a finite-system sweep (the sweeps whose energies Fig. 3 follows).  A block
+ * returned by d2d_density_matrix remembers the enlarged half it was made
+ * from (its parent block plus one column) and its transformation U, the
+ * kept density-matrix eigenvectors in that half's basis.  Moving the
+ * superblock one column right (direction 0), `to`'s block 1 is the new block
+ * made from `from`'s left half, and `from`'s block 4 was made from `to`'s
+ * right half:
+ *   psi_to[(i3, j1), (j3, j4)] = sum over i1, i2, i4 of
+ *       U1[(i2, i1), j1] psi_from[(i2, i1), (i3, i4)] U4[(j3, j4), i4]
+ * with U1 the transformation of to's block 1 and U4 that of from's block 4
+ * (indices as in the packed layout: column state, then block state).
+ * Direction 1 (moving left) is the mirror image: to's block 4 was made from
+ * from's right half, from's block 1 from to's left half.  psi_from and
+ * psi_to are packed device FP64 vectors of the two superblocks (lengths
+ * their N); the result is the projection of psi_from onto the kept states,
+ * not normalised.  Computed on the device (full-space form, grouped FP64
+ * GEMMs).  D2D_EINVAL when the superblocks' blocks are not one step apart in
+ * that direction (imported and exact blocks carry no transformation).
+ * Synchronous. */
+d2d_status d2d_wavefunction_transform(d2d_sb* from, const double* psi_from, d2d_sb* to, double* psi_to,
+                                      int direction);
+
 /* -------------------------------------------------------------- observables
  * Site densities <n_{y,sigma}> of a packed superblock state psi (device,
  * FP64, unit norm) on the superblock's two explicit columns: the inputs of

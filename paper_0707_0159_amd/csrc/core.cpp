@@ -1,5 +1,6 @@
 // Errors, context, dense host matrices, columns and blocks of libd2d.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -8,6 +9,11 @@
 #include "host.h"
 
 namespace d2d {
+
+uint64_t new_block_id() {
+    static std::atomic<uint64_t> next{1};
+    return next.fetch_add(1);
+}
 
 static thread_local std::string g_err;
 
@@ -402,6 +408,7 @@ extern "C" d2d_status d2d_block_import(d2d_ctx* ctx, const d2d_model* model, con
     }
     auto b = std::make_unique<d2d_block>();
     b->ctx = ctx;
+    b->id = new_block_id();
     b->model = *model;
     b->side = d->side;
     b->ncols = d->ncols;
@@ -519,6 +526,7 @@ extern "C" d2d_status d2d_block_exact(d2d_ctx* ctx, const d2d_model* model, int 
     }
     auto b = std::make_unique<d2d_block>();
     b->ctx = ctx;
+    b->id = new_block_id();
     b->model = *model;
     b->side = side;
     b->ncols = 1;

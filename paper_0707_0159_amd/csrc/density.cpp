@@ -356,6 +356,27 @@ static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_ke
         D2D_HIP(launch_pick_columns(dsel.p, (int)sel.size(), doff.p, rho.p, U.p, s));
         D2D_HIP(hipStreamSynchronize(s));
     }
+    // the block keeps its transformation from the enlarged half (sector by
+    // sector, rows in the sector's half indices) and its lineage, for the
+    // wavefunction transformation of finite-system sweeps
+    {
+        std::vector<double> uh((size_t)uoff[np]);
+        if (uoff[np] > 0) D2D_HIP(hipMemcpy(uh.data(), U.p, (size_t)uoff[np] * 8, hipMemcpyDeviceToHost));
+        const std::vector<int32_t>* hv = side == 0 ? sb->rowsL.data() : sb->colsR.data();
+        for (int oi = 0; oi < np; ++oi) {
+            const int p = order[oi];
+            if (!cnt[p]) continue;
+            USector u;
+            u.rows = hv[p];
+            u.col0 = start[p];
+            u.ncols = cnt[p];
+            u.v.assign(uh.begin() + uoff[p], uh.begin() + uoff[p + 1]);
+            nb->U.push_back(std::move(u));
+        }
+        nb->id = new_block_id();
+        nb->parent = side == 0 ? sb->id1 : sb->id4;
+        nb->u_dim = (int64_t)n * m;
+    }
     // H' = U^T (H U): H_l as stored (column-major), H_r through its stored transpose
     {
         std::vector<GemmProb> p1, p2;
@@ -540,4 +561,120 @@ extern "C" d2d_status d2d_density_matrix_timed(d2d_sb* sb, const double* psi, in
         return D2D_EINVAL;
     }
     return density_impl(sb, psi, side, m_keep, new_block, trunc_err, spectrum, spectrum_len, ms);
+}
+
+// ---------------------------------------------------------------- wavefunction transformation
+namespace {
+
+// Dense column-major rows x cols matrix of a block's transformation (its
+// sectors scattered into the enlarged half's full basis).
+std::vector<double> dense_u(const std::vector<USector>& U, int64_t rows, int cols) {
+    std::vector<double> out((size_t)rows * cols, 0.0);
+    for (const USector& u : U) {
+        const size_t d = u.rows.size();
+        for (int c = 0; c < u.ncols; ++c)
+            for (size_t i = 0; i < d; ++i) out[(size_t)u.rows[i] + (size_t)(u.col0 + c) * rows] = u.v[c * d + i];
+    }
+    return out;
+}
+
+}  // namespace
+
+extern "C" d2d_status d2d_wavefunction_transform(d2d_sb* from, const double* psi_from, d2d_sb* to, double* psi_to,
+                                                 int direction) {
+    if (!from || !psi_from || !to || !psi_to || (direction != 0 && direction != 1)) {
+        set_error("d2d_wavefunction_transform: bad argument");
+        return D2D_EINVAL;
+    }
+    if (from->ctx != to->ctx || from->n != to->n || from->model.kind != to->model.kind ||
+        from->model.legs != to->model.legs) {
+        set_error("d2d_wavefunction_transform: superblocks of different contexts or models");
+        return D2D_EINVAL;
+    }
+    const int n = from->n, m = from->m, m2 = to->m;
+    const int64_t D = (int64_t)n * m, D2 = (int64_t)n * m2;
+    // direction 0: to's block 1 grew from from's left half, and from's block 4
+    // from to's right half; direction 1: the mirror image
+    const bool ok = direction == 0
+                        ? (to->parent1 == from->id1 && to->u_dim1 == D && from->parent4 == to->id4 && from->u_dim4 == D2)
+                        : (to->parent4 == from->id4 && to->u_dim4 == D && from->parent1 == to->id1 && from->u_dim1 == D2);
+    if (!ok) {
+        set_error("d2d_wavefunction_transform: the superblocks' blocks are not one sweep step apart in direction %d",
+                  direction);
+        return D2D_EINVAL;
+    }
+    d2d_ctx* ctx = from->ctx;
+    hipStream_t s = ctx->stream;
+    // the new block's transformation (D x m2) and the old neighbour's (D2 x m)
+    const std::vector<double> Unew = dense_u(direction == 0 ? to->U1 : to->U4, D, m2);
+    const std::vector<double> Uold = dense_u(direction == 0 ? from->U4 : from->U1, D2, m);
+    DevBuf<double> full(ctx), mid(ctx), out(ctx), un(ctx), uo(ctx);
+    D2D_CHECK(full.alloc((size_t)(D * D)));
+    D2D_CHECK(mid.alloc((size_t)(m2 * D)));
+    D2D_CHECK(out.alloc((size_t)(D2 * D2)));
+    D2D_CHECK(un.upload(Unew));
+    D2D_CHECK(uo.upload(Uold));
+    D2D_CHECK(d2d_unpack(from, psi_from, full.p));
+    std::vector<GemmProb> first, second;
+    GemmProb g{};
+    if (direction == 0) {
+        // X = Unew^T Psi (m2 x D): rows the new block's states, columns (i3, i4)
+        g.A = un.p;
+        g.B = full.p;
+        g.C = mid.p;
+        g.M = m2;
+        g.N = (int)D;
+        g.K = (int)D;
+        g.lda = (int)D;
+        g.ldb = (int)D;
+        g.ldc = m2;
+        g.ta = 1;
+        first.push_back(g);
+        // Psi'[(i3, j1), (j3, j4)] = sum_i4 X[j1, (i3, i4)] Uold[(j3, j4), i4], one problem per i3
+        for (int i3 = 0; i3 < n; ++i3) {
+            GemmProb h{};
+            h.A = mid.p + (int64_t)i3 * m * m2;
+            h.B = uo.p;
+            h.C = out.p + (int64_t)i3 * m2;
+            h.M = m2;
+            h.N = (int)D2;
+            h.K = m;
+            h.lda = m2;
+            h.ldb = (int)D2;
+            h.ldc = (int)D2;
+            h.tb = 1;
+            second.push_back(h);
+        }
+    } else {
+        // Y = Psi Unew (D x m2): rows (i2, i1), columns the new block's states
+        g.A = full.p;
+        g.B = un.p;
+        g.C = mid.p;
+        g.M = (int)D;
+        g.N = m2;
+        g.K = (int)D;
+        g.lda = (int)D;
+        g.ldb = (int)D;
+        g.ldc = (int)D;
+        first.push_back(g);
+        // Psi'[(j2, j1), (i2, j4)] = sum_i1 Uold[(j2, j1), i1] Y[(i2, i1), j4], one problem per i2
+        for (int i2 = 0; i2 < n; ++i2) {
+            GemmProb h{};
+            h.A = uo.p;
+            h.B = mid.p + (int64_t)i2 * m;
+            h.C = out.p + (int64_t)i2 * m2 * D2;
+            h.M = (int)D2;
+            h.N = m2;
+            h.K = m;
+            h.lda = (int)D2;
+            h.ldb = (int)D;
+            h.ldc = (int)D2;
+            second.push_back(h);
+        }
+    }
+    D2D_CHECK(grouped_gemm(ctx, first, s));
+    D2D_CHECK(grouped_gemm(ctx, second, s));
+    D2D_CHECK(d2d_pack(to, out.p, psi_to));
+    D2D_HIP(hipStreamSynchronize(s));   // the work buffers are freed at return
+    return D2D_OK;
 }

@@ -75,10 +75,29 @@ struct d2d_ctx {
 };
 void free_eig_lanes(d2d_ctx* ctx);
 
+namespace d2d {
+// One sector of a block's transformation: the enlarged half's basis states
+// `rows` (half indices: column state * m_parent + parent state) onto the
+// block's states col0 .. col0 + ncols - 1, dense column-major rows x ncols.
+struct USector {
+    std::vector<int32_t> rows;
+    int col0 = 0, ncols = 0;
+    std::vector<double> v;
+};
+// a fresh block id (never 0)
+uint64_t new_block_id();
+}  // namespace d2d
+
 struct d2d_block {
     d2d_ctx* ctx = nullptr;
     d2d_model model{};
     int side = 0, ncols = 0, m = 0;
+    // Lineage for the wavefunction transformation: the block was made from
+    // the enlarged half (parent block + one column) by the transformation U;
+    // parent 0 and no U for imported and exact blocks.
+    uint64_t id = 0, parent = 0;
+    int64_t u_dim = 0;                    // dimension of that enlarged half (0: no transformation)
+    std::vector<d2d::USector> U;
     std::vector<d2d::QN> qn;           // per state, sorted
     std::vector<d2d::QN> sec_qn;
     std::vector<int64_t> sec_dim, sec_start;
@@ -230,6 +249,10 @@ struct d2d_sb {
     unsigned prec_mask = 0;
     std::vector<d2d::QN> qn1, qn4;     // block-state quantum numbers (block 1, block 4)
     int ncols1 = 0, ncols4 = 0;
+    // the blocks' lineage and transformations (copies; see d2d_block)
+    uint64_t id1 = 0, parent1 = 0, id4 = 0, parent4 = 0;
+    int64_t u_dim1 = 0, u_dim4 = 0;
+    std::vector<d2d::USector> U1, U4;
     // sector pairs
     std::vector<d2d::QN> pair_q;
     std::vector<d2d::SectorDev> pairs;

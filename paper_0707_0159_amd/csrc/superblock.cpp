@@ -696,6 +696,14 @@ extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d
     sb->qn4 = b4->qn;
     sb->ncols1 = b1->ncols;
     sb->ncols4 = b4->ncols;
+    sb->id1 = b1->id;
+    sb->parent1 = b1->parent;
+    sb->u_dim1 = b1->u_dim;
+    sb->U1 = b1->U;
+    sb->id4 = b4->id;
+    sb->parent4 = b4->parent;
+    sb->u_dim4 = b4->u_dim;
+    sb->U4 = b4->U;
     ctx->children++;   // undone by the destructor path below on failure
     struct Guard {
         std::unique_ptr<d2d_sb>* p;

@@ -103,6 +103,7 @@ _SIGS = {
     "d2d_density_matrix": (C.c_int, [P, P, C.c_int, C.c_int, C.POINTER(P), f64p, f64p, i64p]),
     "d2d_column_densities": (C.c_int, [P, P, f64p]),
     "d2d_density_matrix_timed": (C.c_int, [P, P, C.c_int, C.c_int, C.POINTER(P), f64p, f64p, i64p, f64p]),
+    "d2d_wavefunction_transform": (C.c_int, [P, P, P, P, C.c_int]),
     "d2d_batch_create": (C.c_int, [P, C.POINTER(P), C.c_int, C.POINTER(P)]),
     "d2d_batch_destroy": (C.c_int, [P]),
     "d2d_batch_hv": (C.c_int, [P, C.c_int, C.POINTER(P), C.POINTER(P)]),
@@ -400,6 +401,12 @@ def d2d_density_matrix_timed(sb: int, psi, side: int, m_keep: int, spectrum_cap:
                                            spec.ctypes.data_as(f64p) if spectrum_cap else None,
                                            n.ctypes.data_as(i64p), ms.ctypes.data_as(f64p)))
     return blk.value, te.value, (spec[: int(n[0])] if spectrum_cap else None), ms
+
+
+def d2d_wavefunction_transform(sb_from: int, psi_from, sb_to: int, psi_to, direction: int):
+    """Initial guess of the next sweep position: psi_to from psi_from (device FP64)."""
+    _check(load().d2d_wavefunction_transform(P(sb_from), P(_ptr(psi_from)), P(sb_to), P(_ptr(psi_to)),
+                                             int(direction)))
 
 
 def d2d_column_densities(sb: int, psi, legs: int):

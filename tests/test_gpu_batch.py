@@ -161,7 +161,9 @@ def test_batch_lanczos_energies(ctx, prec):
         p.close()
 
 
-def batch64_or_skip():
+def batch64_references():
+    """The batch problems and their stored reference energies; a missing
+    record fails the test (the references are part of the repository)."""
     import json
     import os
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "reference_energies.json")
@@ -169,8 +171,7 @@ def batch64_or_skip():
         g = json.load(f)
     wls = W.batch64()
     missing = [wl.name for wl in wls if wl.name not in g]
-    if missing:
-        pytest.skip(f"reference energies not yet written for {len(missing)} batch problems")
+    assert not missing, f"reference energies missing for {len(missing)} batch problems: {missing[:4]}"
     return wls, {wl.name: float(g[wl.name]["E0"]) for wl in wls}
 
 
@@ -179,7 +180,7 @@ def test_batch64_energies(ctx, prec):
     """64 uneven superblocks (2/3-leg Heisenberg and Hubbard, m 64..512) in one
     batch: every problem's ground energy within 1e-10 of the oracle's."""
     from paper_0707_0159_amd import d2d
-    wls, refs = batch64_or_skip()
+    wls, refs = batch64_references()
     probs = [GpuProblem(ctx, wl, prec_mask=7) for wl in wls]
     b = d2d.d2d_batch_create(ctx, [p.sb for p in probs])
     with torch.cuda.stream(ctx.stream):
@@ -220,7 +221,7 @@ def test_batch64_sampled_hv_against_oracle(ctx):
 @pytest.fixture(scope="module")
 def batch64_fixture(ctx):
     from paper_0707_0159_amd import d2d
-    wls, refs = batch64_or_skip()
+    wls, refs = batch64_references()
     probs = [GpuProblem(ctx, wl, prec_mask=15) for wl in wls]
     b = d2d.d2d_batch_create(ctx, [p.sb for p in probs])
     yield wls, refs, probs, b

@@ -329,7 +329,7 @@ def test_escalation_from_bf16_on_a_rising_energy(ctx):
     the energy still meets the bar.  (With an FP32 basis this seed's BF16
     restarts happen not to rise, and the solve stays in BF16.)"""
     from paper_0707_0159_amd import d2d
-    wl = W.batch64()[15]
+    wl = W.batch64(6)[15]       # the 6-column variant of batch problem 15: 924 states
     prob = GpuProblem(ctx, wl, prec_mask=15)
     assert prob.info["n"] == 924
     with torch.cuda.stream(ctx.stream):
