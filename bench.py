@@ -512,8 +512,9 @@ def main():
                     help="workload by name (overrides --config): a single superblock's name or batch64")
     ap.add_argument("--k-in", type=int, default=48, help="Krylov dimension per restart")
     ap.add_argument("--k-in-bf16", type=int, default=24, help="Krylov dimension of BF16 cycles (0: --k-in)")
-    ap.add_argument("--graph", action="store_true",
-                    help="capture each restart in a hipGraph and replay it (default: direct launches)")
+    ap.add_argument("--graph", dest="graph", action="store_true", default=True,
+                    help="capture each restart in a hipGraph once and replay it in later solves (the default)")
+    ap.add_argument("--no-graph", dest="graph", action="store_false", help="direct launches")
     ap.add_argument("--fixed-cycles", action="store_true",
                     help="every cycle full length (default: the last cycle fitted to the residual bar)")
     ap.add_argument("--one-kernel-step", action="store_true",

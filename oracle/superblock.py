@@ -163,13 +163,33 @@ class Superblock:
         return self._Hx @ v
 
     # ---------------------------------------------------------------- mode F
-    def dense_sectors(self):
-        """``H_l`` and ``H_r`` restricted to each sector, as dense FP64 blocks."""
-        if self._dense is None:
-            HL = sp.csr_matrix(self.H_l)
-            HR = sp.csr_matrix(self.H_r)
-            self._dense = [(HL[r][:, r].toarray(), HR[c][:, c].toarray()) for _, r, c, _ in self.sectors]
-        return self._dense
+    def dense_sectors(self, column_offdiagonal: bool = True):
+        """``H_l`` and ``H_r`` restricted to each sector, as dense FP64 blocks.
+
+        With ``column_offdiagonal=False``, without the explicit column's own
+        off-diagonal terms (``1 (x) offdiag(h_col)`` on the half index
+        ``column state * m + block state``): the part of each half that acts
+        on the column alone and moves it to another state, which a product
+        may apply as scaled copies of rectangles of ``V`` instead (the
+        sectors' sum is unchanged: those terms conserve the column's quantum
+        numbers)."""
+        if column_offdiagonal:
+            if self._dense is None:
+                HL = sp.csr_matrix(self.H_l)
+                HR = sp.csr_matrix(self.H_r)
+                self._dense = [(HL[r][:, r].toarray(), HR[c][:, c].toarray()) for _, r, c, _ in self.sectors]
+            return self._dense
+        off = sp.csr_matrix(self.col.H) - sp.diags(sp.csr_matrix(self.col.H).diagonal())
+        part = sp.csr_matrix(sp.kron(off, sp.identity(self.m, format="csr")))
+        HL = sp.csr_matrix(self.H_l - part)
+        HR = sp.csr_matrix(self.H_r - part)
+        return [(HL[r][:, r].toarray(), HR[c][:, c].toarray()) for _, r, c, _ in self.sectors]
+
+    def column_offdiagonal_part(self) -> sp.csr_matrix:
+        """``1 (x) offdiag(h_col)`` on either half's index (the same matrix for
+        both halves: column state slow, block state fast)."""
+        off = sp.csr_matrix(self.col.H) - sp.diags(sp.csr_matrix(self.col.H).diagonal())
+        return sp.csr_matrix(sp.kron(off, sp.identity(self.m, format="csr")))
 
     def central_groups(self):
         """Gather plan for ``H_c V_c``, one group per central sector.

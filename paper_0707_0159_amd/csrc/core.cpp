@@ -189,6 +189,28 @@ static const Mat& find_op(const std::vector<OpKey>& keys, const std::vector<Mat>
 
 // Hubbard: c_x^dag c_y = (c_x^dag P_X) (x) c_y and c_y^dag c_x = (P_X c_x) (x) c_y^dag, coefficient -t.
 // Heisenberg: J [S^z S^z + (S^+ S^- + S^- S^+)/2].
+// The column Hamiltonian's off-diagonal part (the terms between the
+// column's own sites: rung hops, rung spin flips) as matrices with at most
+// one nonzero per row.  They act on one column and leave the other and both
+// blocks alone, so the product applies them as the central term's gathers
+// (scaled copies of rectangles of V) instead of as diagonal lines inside the
+// dense sector operators, where every such line fills whole 16 x 16 cells
+// of the K-loop.
+std::vector<Mat> offdiagonal_pieces(const Mat& h) {
+    const int n = h.rows;
+    std::vector<std::vector<std::pair<int, double>>> rows(n);
+    size_t pieces = 0;
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j)
+            if (i != j && h(i, j) != 0.0) rows[i].push_back({j, h(i, j)});
+        pieces = std::max(pieces, rows[i].size());
+    }
+    std::vector<Mat> out(pieces, Mat(n, n));
+    for (int i = 0; i < n; ++i)
+        for (size_t t = 0; t < rows[i].size(); ++t) out[t](i, rows[i][t].first) = rows[i][t].second;
+    return out;
+}
+
 std::vector<BondTerm> bond_terms(const d2d_model& model, const std::vector<OpKey>& kx, const std::vector<Mat>& ox,
                                  const std::vector<double>& px, const std::vector<OpKey>& ky,
                                  const std::vector<Mat>& oy) {

@@ -413,7 +413,10 @@ static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_ke
     // edge operators: for operator o and target sector pt, G = O U_from (rows
     // of the half basis gathered from the source sector pf with the
     // operator's value, times the block parity for a left Hubbard block),
-    // then E'[pt, pf] = U_pt^T G
+    // then E'[pt, pf] = U_pt^T G.  The same gathers carry the half
+    // Hamiltonian's part that the stored sector operators leave out, the
+    // column's off-diagonal terms (pieces of one nonzero per row, even in
+    // the fermions: no parity), into H'.
     const std::vector<int32_t>* halves = side == 0 ? sb->rowsL.data() : sb->colsR.data();
     std::vector<int> sector_of_half((size_t)m * n, -1), pos_of_half((size_t)m * n, -1);
     for (int p = 0; p < np; ++p)
@@ -432,8 +435,11 @@ static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_ke
     std::vector<double> rval;
     std::vector<int64_t> goff(1, 0), eout(1, 0);
     int64_t maxn = 0;
-    for (size_t o = 0; o < col.keys.size(); ++o) {
-        const Mat& cop = col.ops[o];
+    const std::vector<Mat> hops = offdiagonal_pieces(col.H);
+    const size_t nedge = col.keys.size();
+    for (size_t o = 0; o < nedge + hops.size(); ++o) {
+        const bool edge = o < nedge;
+        const Mat& cop = edge ? col.ops[o] : hops[o - nedge];
         std::vector<int> src(n, -1);
         std::vector<double> val(n, 0.0);
         for (int a = 0; a < n; ++a)
@@ -454,7 +460,8 @@ static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_ke
                 const int hrow = halves[pt][r], a = hrow / m, b = hrow % m;
                 if (src[a] < 0) continue;
                 double v = val[a];
-                if (sb->model.kind == D2D_HUBBARD && side == 0) v *= ((bq[b].first + bq[b].second) & 1) ? -1.0 : 1.0;
+                if (edge && sb->model.kind == D2D_HUBBARD && side == 0)
+                    v *= ((bq[b].first + bq[b].second) & 1) ? -1.0 : 1.0;
                 const int hsrc = src[a] * m + b;
                 const int pf = sector_of_half[hsrc];
                 if (pf < 0 || !cnt[pf]) continue;
@@ -522,7 +529,7 @@ static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_ke
             for (int i = 0; i < cnt[p]; ++i) nb->H(start[p] + i, start[p] + j) = hh[hoff[p] + (int64_t)j * cnt[p] + i];
     for (size_t e = 0; e < ents.size(); ++e) {
         const Entry& x = ents[e];
-        Mat& M = nb->ops[x.o];
+        Mat& M = x.o < (int)nedge ? nb->ops[x.o] : nb->H;   // a column off-diagonal piece adds to H'
         for (int j = 0; j < cnt[x.pf]; ++j)
             for (int i = 0; i < cnt[x.pt]; ++i)
                 M(start[x.pt] + i, start[x.pf] + j) += eh[eout[e] + (int64_t)j * cnt[x.pt] + i];

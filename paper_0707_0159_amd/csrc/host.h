@@ -44,6 +44,9 @@ struct Column {
     const Mat& op(const OpKey& k) const;
 };
 Column make_column(const d2d_model& m);
+// the off-diagonal part of a column operator as matrices with at most one
+// nonzero per row (their sum is the operator minus its diagonal)
+std::vector<Mat> offdiagonal_pieces(const Mat& h);
 
 // A bond term coef * (A on the part whose modes come first) (x) (B on the other).
 struct BondTerm {

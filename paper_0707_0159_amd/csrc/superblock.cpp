@@ -776,8 +776,14 @@ extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d
     D2D_CHECK(ctx->alloc(&sb->HR[D2D_FP64], (size_t)hr * 8));
     const std::vector<BondTerm> tl = bond_terms(*model, b1->keys, b1->ops, b1->parity(), col.keys, col.ops);
     const std::vector<BondTerm> tr = bond_terms(*model, col.keys, col.ops, col.parity, b4->keys, b4->ops);
-    D2D_CHECK(assemble_half(sb.get(), b1, col, tl, true, (double*)sb->HL[D2D_FP64]));
-    D2D_CHECK(assemble_half(sb.get(), b4, col, tr, false, (double*)sb->HR[D2D_FP64]));
+    // the dense sector operators carry the column Hamiltonian's diagonal
+    // only; its off-diagonal part joins the central term (a5 below)
+    Column cdiag = col;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            if (i != j) cdiag.H(i, j) = 0.0;
+    D2D_CHECK(assemble_half(sb.get(), b1, cdiag, tl, true, (double*)sb->HL[D2D_FP64]));
+    D2D_CHECK(assemble_half(sb.get(), b4, cdiag, tr, false, (double*)sb->HR[D2D_FP64]));
     // nonzero count of the sector operators (the method's sparse flop count)
     {
         std::vector<double> h(hl), r(hr);
@@ -907,10 +913,19 @@ extern "C" d2d_status d2d_sb_create(d2d_ctx* ctx, const d2d_block* b1, const d2d
         D2D_CHECK(upload(ctx, pt, &sb->d_ptiles));
     }
 
-    // a5: central bond terms sum_k c_k A_k (x) B_k, A_k on column 2, B_k on column 3
-    const std::vector<BondTerm> tc = bond_terms(*model, col.keys, col.ops, col.parity, col.keys, col.ops);
+    // a5: central bond terms sum_k c_k A_k (x) B_k, A_k on column 2, B_k on column 3,
+    // then the columns' own off-diagonal terms: piece (x) 1 for column 2
+    // (part of H_l) and 1 (x) piece for column 3 (part of H_r)
+    std::vector<BondTerm> tc = bond_terms(*model, col.keys, col.ops, col.parity, col.keys, col.ops);
     sb->K = (int)tc.size();
-    const int K = sb->K, np = (int)sb->pairs.size();
+    {
+        const Mat id = mat_identity(n);
+        for (const Mat& pc : offdiagonal_pieces(col.H)) {
+            tc.push_back({1.0, pc, id});
+            tc.push_back({1.0, id, pc});
+        }
+    }
+    const int K = (int)tc.size(), np = (int)sb->pairs.size();
     // position of every half index inside its sector
     std::vector<int32_t> posL(mn, -1), posR(mn, -1);
     for (auto& kv : left)

@@ -331,9 +331,11 @@ def sector_step_flops(osb, BM, BN, BK, dense):
     """The grouped GEMM's flops for one tile shape, from the oracle's dense
     sector operators: per output tile and K step of BK, 2 x rows x columns x
     (K columns in the step), every step (dense) or only the steps whose
-    operator tile holds a nonzero in 16 x 16 cells (the library's granularity)."""
+    operator tile holds a nonzero in 16 x 16 cells (the library's granularity).
+    The sector operators the grouped GEMM carries are the halves without the
+    explicit columns' own off-diagonal terms (those go with the central term)."""
     total = 0.0
-    for (q, r, c, o), (hl, hr) in zip(osb.sectors, osb.dense_sectors()):
+    for (q, r, c, o), (hl, hr) in zip(osb.sectors, osb.dense_sectors(column_offdiagonal=False)):
         dL, dR = r.size, c.size
         for H, d, dout, B in ((hl, dL, dR, BM), (hr, dR, dL, BN)):
             # nonzero 16 x 16 cells of H (rows: output rows of the product, columns: K)
@@ -363,7 +365,7 @@ def aligned_step_flops(osb, shape0, shape1, dense, padded):
     (BM0, BN0, BK), (BM1, BN1, _) = shape0, shape1
     m = osb.m
     total = 0.0
-    for (q, r, c, o), (hl, hr) in zip(osb.sectors, osb.dense_sectors()):
+    for (q, r, c, o), (hl, hr) in zip(osb.sectors, osb.dense_sectors(column_offdiagonal=False)):
         dL, dR = r.size, c.size
         for H, idx, dout, SEG, OTHER in ((hl, r, dR, BM0, BN0), (hr, c, dL, BN1, BM1)):
             d = idx.size

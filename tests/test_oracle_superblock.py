@@ -236,3 +236,43 @@ def test_mutation_wrong_hopping_sign_in_column_is_caught(monkeypatch):
 
     monkeypatch.setattr(ol, "hubbard_column", bad)
     assert _eq1_mismatch(Model("hubbard", 2, t=1.0, U=4.0), 1, (3, 4), 4) > 0.5
+
+
+@pytest.mark.parametrize("model,k,Q,length", CASES[:1] + CASES[3:5] + CASES[6:])
+def test_column_offdiagonal_part_as_gathers(model, k, Q, length):
+    """The halves without the explicit columns' off-diagonal terms, plus those
+    terms applied as scaled copies of V's rectangles (row runs of one
+    column-2 state moved to another, column runs of one column-3 state
+    likewise, the weights read from the column Hamiltonian itself), give
+    H_l V + V H_r^T; the removed part of each sector is exactly the column
+    Hamiltonian's off-diagonal entries between states with equal block
+    states, and it conserves the sectors."""
+    L, R = exact_block(model, k, "L"), exact_block(model, k, "R")
+    sb = Superblock(L, R, Q)
+    m, n = sb.m, sb.n
+    hcol = sb.col.H.toarray()
+    v = np.random.default_rng(4).standard_normal(sb.N)
+    w_lr, w_split = np.zeros(sb.N), np.zeros(sb.N)
+    for (q, r, c, o), (hl, hr), (hl0, hr0) in zip(sb.sectors, sb.dense_sectors(),
+                                                 sb.dense_sectors(column_offdiagonal=False)):
+        Vs = v[o:o + r.size * c.size].reshape(c.size, r.size).T
+        w_lr[o:o + r.size * c.size] = (hl @ Vs + Vs @ hr.T).T.reshape(-1)
+        W = hl0 @ Vs + Vs @ hr0.T
+        # the removed part, element by element from the column Hamiltonian
+        for idx, H, H0 in ((r, hl, hl0), (c, hr, hr0)):
+            a, b = idx // m, idx % m
+            want = np.where((b[:, None] == b[None, :]) & (a[:, None] != a[None, :]), hcol[a[:, None], a[None, :]], 0.0)
+            assert np.array_equal(H - H0, want)
+        # the same part as gathers over rows (column 2) and columns (column 3)
+        a_r, b_r = r // m, r % m
+        a_c, b_c = c // m, c % m
+        for i in range(r.size):
+            for j in range(r.size):
+                if b_r[i] == b_r[j] and a_r[i] != a_r[j] and hcol[a_r[i], a_r[j]] != 0:
+                    W[i, :] += hcol[a_r[i], a_r[j]] * Vs[j, :]
+        for i in range(c.size):
+            for j in range(c.size):
+                if b_c[i] == b_c[j] and a_c[i] != a_c[j] and hcol[a_c[i], a_c[j]] != 0:
+                    W[:, i] += hcol[a_c[i], a_c[j]] * Vs[:, j]
+        w_split[o:o + r.size * c.size] = W.T.reshape(-1)
+    assert np.abs(w_split - w_lr).max() <= 1e-13 * max(1.0, np.abs(w_lr).max())
