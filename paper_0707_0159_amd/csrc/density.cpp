@@ -11,8 +11,8 @@
 // dsyevd, FP64).  Its tridiagonal reduction and divide and conquer are long
 // chains of small dependent launches, so the sectors are spread over a few
 // streams of their own (largest first, each to the least loaded stream by
-// d^3), which run concurrently and join the context's stream before one host
-// synchronisation; the m_keep eigenvectors of largest weight are kept (ties:
+// d^3), each fed by a host thread of its own, which run concurrently and
+// join the context's stream before one host synchronisation; the m_keep eigenvectors of largest weight are kept (ties:
 // sector ascending, then index in the sector ascending).  Renormalisation:
 // the kept columns are gathered on the device with their sign fixed (entry of
 // largest modulus positive), H' = U^T (H U) per sector as two grouped GEMM
@@ -27,6 +27,7 @@
 #include <chrono>
 #include <cmath>
 #include <numeric>
+#include <thread>
 
 #include "host.h"
 
@@ -248,10 +249,34 @@ static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_ke
     }
     D2D_HIP(hipEventRecord(lanes->start, s));   // rho is formed
     for (int l = 0; l < nl; ++l) D2D_HIP(hipStreamWaitEvent(lanes->s[l], lanes->start, 0));
-    for (int p : by_size)
-        if (syevd(p) != rocblas_status_success) {
-            set_error("rocsolver_dsyevd failed on sector %d (dim %d)", p, dim[p]);
-            for (int l = 0; l < nl; ++l) (void)hipStreamSynchronize(lanes->s[l]);
+    // Every lane's sectors are queued by a host thread of its own.  The
+    // eigensolver issues several kernels per matrix column, most of them a few
+    // microseconds long, so one thread queuing all sectors in turn keeps the
+    // device waiting on the host's launch rate.  (The error message is kept
+    // per thread, so the workers only record which sector failed.)
+    std::vector<int> failed(nl, -1);
+    auto run_lane = [&](int l) {
+        if (hipSetDevice(ctx->device) != hipSuccess) {
+            failed[l] = np;
+            return;
+        }
+        for (int p : by_size)
+            if (lane_of[p] == l && syevd(p) != rocblas_status_success) {
+                failed[l] = p;
+                return;
+            }
+    };
+    {
+        std::vector<std::thread> workers;
+        for (int l = 1; l < nl; ++l) workers.emplace_back(run_lane, l);
+        run_lane(0);
+        for (auto& w : workers) w.join();
+    }
+    for (int l = 0; l < nl; ++l)
+        if (failed[l] >= 0) {
+            if (failed[l] == np) set_error("hipSetDevice(%d) failed in an eigensolver thread", ctx->device);
+            else set_error("rocsolver_dsyevd failed on sector %d (dim %d)", failed[l], dim[failed[l]]);
+            for (int k = 0; k < nl; ++k) (void)hipStreamSynchronize(lanes->s[k]);
             return D2D_EDEVICE;
         }
     for (int l = 0; l < nl; ++l) {
