@@ -337,24 +337,6 @@ def bench_batch(args):
         t_vec = sum(x["vec_s"] for x in parts)
         return {"t_min_ms": (t_hv + t_vec) * 1e3, "hv_ms": t_hv * 1e3, "lanczos_vectors_ms": t_vec * 1e3}
 
-    if args.profile == "density":
-        # the density-matrix call's kernels (formation, the eigensolver's, renormalisation)
-        opts = d2d.lanczos_opts(prec=d2d.D2D_FP32, k_in=args.k_in, max_restarts=500, tol_res=args.tol,
-                                reorth_window=args.window)
-        st, e, _ = d2d.d2d_lanczos(sb, opts, v0, psi)
-        if st != 0:
-            raise RuntimeError("Lanczos did not converge")
-        out = {"profile": "density", "workload": wl.name, "energy": e}
-        for side in (0, 1):
-            for rep in range(2):
-                blk, te, _, ms = d2d.d2d_density_matrix_timed(sb, psi, side, wl.m)
-                d2d.d2d_block_destroy(blk)
-                out[f"side{side}_rep{rep}_ms"] = [float(x) for x in ms]
-                out[f"side{side}_trunc_err"] = te
-        torch.cuda.synchronize()
-        print(json.dumps(out))
-        return
-
     def solve(prec):
         opts = d2d.lanczos_opts(prec=prec, k_in=args.k_in, max_restarts=500, tol_res=args.tol,
                                 use_graph=1 if args.graph else 0,
@@ -632,6 +614,24 @@ def main():
         print(json.dumps({"profile": "hv", "prec": args.prec, "workload": wl.name, "launches": args.steps,
                           "tile": tuned[args.prec], "flops_exec": tuned[args.prec]["gemm_flops"],
                           "bytes_min": info["bytes_min_" + args.prec]}))
+        return
+
+    if args.profile == "density":
+        # the density-matrix call's kernels (formation, the eigensolver's, renormalisation)
+        opts = d2d.lanczos_opts(prec=d2d.D2D_FP32, k_in=args.k_in, max_restarts=500, tol_res=args.tol,
+                                reorth_window=args.window)
+        st, e, _ = d2d.d2d_lanczos(sb, opts, v0, psi)
+        if st != 0:
+            raise RuntimeError("Lanczos did not converge")
+        out = {"profile": "density", "workload": wl.name, "energy": e}
+        for side in (0, 1):
+            for rep in range(2):
+                blk, te, _, ms = d2d.d2d_density_matrix_timed(sb, psi, side, wl.m)
+                d2d.d2d_block_destroy(blk)
+                out[f"side{side}_rep{rep}_ms"] = [float(x) for x in ms]
+                out[f"side{side}_trunc_err"] = te
+        torch.cuda.synchronize()
+        print(json.dumps(out))
         return
 
     def solve(prec):
