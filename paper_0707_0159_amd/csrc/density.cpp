@@ -267,9 +267,19 @@ static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_ke
             }
     };
     {
+        // a lane whose thread cannot be started is queued by this thread
+        // (nothing may throw across the C interface)
         std::vector<std::thread> workers;
-        for (int l = 1; l < nl; ++l) workers.emplace_back(run_lane, l);
+        std::vector<int> inline_lanes;
+        for (int l = 1; l < nl; ++l) {
+            try {
+                workers.emplace_back(run_lane, l);
+            } catch (...) {
+                inline_lanes.push_back(l);
+            }
+        }
         run_lane(0);
+        for (int l : inline_lanes) run_lane(l);
         for (auto& w : workers) w.join();
     }
     for (int l = 0; l < nl; ++l)
