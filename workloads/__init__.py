@@ -119,10 +119,12 @@ def _batch64_problems(length):
 
 # Lattice length of the batch problems.  At 12 columns the blocks have 5
 # columns, more states than any drawn m, so every problem truncates to its m.
-# 6 columns (blocks of 2 columns) is the short variant: the blocks of the
-# 2-leg and 3-leg Heisenberg problems (16 and 64 states) and of the 2-leg
-# Hubbard problems (256 states) stay below the larger drawn m.
-BATCH_LENGTH = 6
+# 6 columns (blocks of 2 columns) is the short variant, kept as test input:
+# the blocks of its 2-leg and 3-leg Heisenberg problems (16 and 64 states)
+# and of its 2-leg Hubbard problems (256 states) are exact, below the larger
+# drawn m, so their superblocks are whole lattices that exact
+# diagonalisation checks.
+BATCH_LENGTH = 12
 BATCH_LENGTH_DRAWN = 12
 
 HEISENBERG_2X6_M16 = Workload("heisenberg_2x6_m16", "heisenberg", 2, 6, 16, J=1.0, target_of_sites=_sz_zero(2),
