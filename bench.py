@@ -427,7 +427,7 @@ def bench_batch(args):
                      "work": "F_nnz of every problem's Hv (GEMM part) per batched Hv",
                      "executed_tflops": Fx / (hv_ms["fp32"] * 1e-3) / 1e12,
                      "frac_exec": Fx / (hv_ms["fp32"] * 1e-3) / PEAK["fp32"],
-                     "kernel": "batched Hv launch sequence (fp32 grouped GEMM + central term), latency-bound"},
+                     "kernel": "batched Hv launch sequence (fp32 grouped GEMM + central term)"},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_batch(wls, args.cpu_seconds)
