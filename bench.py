@@ -667,6 +667,12 @@ def main():
                 blk, te, _, ms = d2d.d2d_density_matrix_timed(sb, psi, side, wl.m)
                 d2d.d2d_block_destroy(blk)
             out[f"side{side}"] = {"dmf_ms": ms[0], "dmd_ms": ms[1], "renorm_ms": ms[2], "trunc_err": te}
+        # both halves in one call (their sectors' eigensolves share the streams)
+        for rep in range(2):
+            bl, br, te2, ms = d2d.d2d_density_matrix_both(sb, psi, wl.m)
+            d2d.d2d_block_destroy(bl)
+            d2d.d2d_block_destroy(br)
+        out["both_halves"] = {"dmf_ms": ms[0], "dmd_ms": ms[1], "renorm_ms": ms[2], "trunc_err": list(te2)}
         print(json.dumps({"dmrg_step": out}))
         d2d.d2d_sb_destroy(sb)
         d2d.d2d_block_destroy(b1)

@@ -460,6 +460,18 @@ d2d_status d2d_density_matrix_timed(d2d_sb* sb, const double* psi, int side, int
                                     d2d_block** new_block, double* trunc_err, double* spectrum,
                                     int64_t* spectrum_len, double ms[3]);
 
+/* Both halves of one state at once, as in a step of the infinite-system
+ * algorithm (Fig. 1a: blocks 1 and 4 both grow by a column): the results of
+ * d2d_density_matrix for side 0 (*new_left, trunc_err[0]) and side 1
+ * (*new_right, trunc_err[1]), bit for bit, with the two halves' sectors
+ * diagonalised together on the context's eigensolver streams, so that the
+ * two halves' longest eigensolves overlap.  ms (host, nullable) receives the
+ * wall times of the three phases over both halves (formation,
+ * diagonalisation with the selections, renormalisation).  On failure no
+ * block is returned. */
+d2d_status d2d_density_matrix_both(d2d_sb* sb, const double* psi, int m_keep, d2d_block** new_left,
+                                   d2d_block** new_right, double trunc_err[2], double ms[3]);
+
 /* Wavefunction transformation: the initial guess of the next superblock of
  * a finite-system sweep (the sweeps whose energies Fig. 3 follows).  A block
  * returned by d2d_density_matrix remembers the enlarged half it was made

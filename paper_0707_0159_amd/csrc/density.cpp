@@ -137,95 +137,113 @@ static d2d_status eig_lanes(d2d_ctx* ctx, EigLanes** out) {
     return D2D_OK;
 }
 
-static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_keep, d2d_block** new_block,
-                               double* trunc_err, double* spectrum, int64_t* spectrum_len, double* ms) {
-    if (!sb || !psi || !new_block || !trunc_err || (side != 0 && side != 1) || m_keep < 1) {
-        set_error("d2d_density_matrix: bad argument");
-        return D2D_EINVAL;
-    }
-    *new_block = nullptr;
-    d2d_ctx* ctx = sb->ctx;
-    hipStream_t s = ctx->stream;
-    const int np = (int)sb->pairs.size();
-    D2D_HIP(hipStreamSynchronize(s));   // phases are timed from here
-    auto t0 = std::chrono::steady_clock::now();
+namespace {
 
-    // ---- DMF: rho per sector, one grouped GEMM launch
-    std::vector<int> dim(np);
-    std::vector<int64_t> roff(np + 1, 0);
+// One half's density matrix between the phases: its sectors' rho (then
+// their eigenvectors, in place), eigenvalues and the selection.
+struct Half {
+    d2d_sb* sb;
+    int side, np;
+    std::vector<int> dim;
+    std::vector<int64_t> roff;
+    std::vector<size_t> evoff;
+    size_t nev = 0;
+    DevBuf<double> rho, ev, offd;
+    DevBuf<rocblas_int> info;
+    std::vector<double> evh;
+    std::vector<std::vector<int>> kept;
+    int keep = 0;
+    Half(d2d_sb* s, int sd)
+        : sb(s), side(sd), np((int)s->pairs.size()), rho(s->ctx), ev(s->ctx), offd(s->ctx), info(s->ctx) {}
+};
+
+// DMF: rho of every sector of the half, one grouped GEMM launch.
+d2d_status half_rho(Half& h, const double* psi) {
+    d2d_sb* sb = h.sb;
+    const int np = h.np, side = h.side;
+    h.dim.assign(np, 0);
+    h.roff.assign(np + 1, 0);
+    h.evoff.assign(np, 0);
+    h.nev = 0;
     for (int p = 0; p < np; ++p) {
-        dim[p] = side == 0 ? sb->pairs[p].dL : sb->pairs[p].dR;
-        roff[p + 1] = roff[p] + (int64_t)dim[p] * dim[p];
+        h.dim[p] = side == 0 ? sb->pairs[p].dL : sb->pairs[p].dR;
+        h.roff[p + 1] = h.roff[p] + (int64_t)h.dim[p] * h.dim[p];
+        h.evoff[p] = h.nev;
+        h.nev += h.dim[p];
     }
-    DevBuf<double> rho(ctx), ev(ctx);
-    D2D_CHECK(rho.alloc((size_t)roff[np]));
-    {
-        std::vector<GemmProb> probs;
-        for (int p = 0; p < np; ++p) {
-            const SectorDev& q = sb->pairs[p];
-            GemmProb g{};
-            g.A = psi + q.off;
-            g.B = psi + q.off;
-            g.C = rho.p + roff[p];
-            g.M = g.N = dim[p];
-            g.K = side == 0 ? q.dR : q.dL;
-            g.lda = g.ldb = q.dL;
-            g.ldc = dim[p];
-            g.ta = side == 0 ? 0 : 1;   // side 0: V V^T; side 1: V^T V
-            g.tb = side == 0 ? 1 : 0;
-            probs.push_back(g);
-        }
-        D2D_CHECK(grouped_gemm(ctx, probs, s));
+    D2D_CHECK(h.rho.alloc((size_t)h.roff[np]));
+    std::vector<GemmProb> probs;
+    for (int p = 0; p < np; ++p) {
+        const SectorDev& q = sb->pairs[p];
+        GemmProb g{};
+        g.A = psi + q.off;
+        g.B = psi + q.off;
+        g.C = h.rho.p + h.roff[p];
+        g.M = g.N = h.dim[p];
+        g.K = side == 0 ? q.dR : q.dL;
+        g.lda = g.ldb = q.dL;
+        g.ldc = h.dim[p];
+        g.ta = side == 0 ? 0 : 1;   // side 0: V V^T; side 1: V^T V
+        g.tb = side == 0 ? 1 : 0;
+        probs.push_back(g);
     }
-    const double t_dmf = seconds_since(t0);
-    auto t1 = std::chrono::steady_clock::now();
+    return grouped_gemm(sb->ctx, probs, sb->ctx->stream);
+}
 
-    // ---- DMD: eigenpairs of every sector (ascending eigenvalues, vectors in place)
+// DMD: the eigenpairs of every sector of the given halves (ascending
+// eigenvalues, vectors in place of rho), all sectors of all halves spread over
+// the context's eigensolver streams together; the eigenvalues come back to
+// the host.
+d2d_status halves_eig(d2d_ctx* ctx, const std::vector<Half*>& hs) {
+    hipStream_t s = ctx->stream;
     EigLanes* lanes = nullptr;
     D2D_CHECK(eig_lanes(ctx, &lanes));
-    size_t nev = 0;
-    std::vector<size_t> evoff(np);
-    for (int p = 0; p < np; ++p) {
-        evoff[p] = nev;
-        nev += dim[p];
+    struct Job {
+        Half* h;
+        int p, d;
+    };
+    std::vector<Job> jobs;
+    for (Half* h : hs) {
+        D2D_CHECK(h->ev.alloc(h->nev));
+        D2D_CHECK(h->offd.alloc(h->nev));   // each sector's off-diagonal workspace, at its eigenvalues' offset
+        D2D_CHECK(h->info.alloc((size_t)h->np));
+        for (int p = 0; p < h->np; ++p) jobs.push_back({h, p, h->dim[p]});
     }
-    D2D_CHECK(ev.alloc(nev));
-    DevBuf<double> offd(ctx);   // each sector's off-diagonal workspace, at its eigenvalues' offset
-    D2D_CHECK(offd.alloc(nev));
-    DevBuf<rocblas_int> info(ctx);
-    D2D_CHECK(info.alloc((size_t)np));
+    const int nj = (int)jobs.size();
     // sectors to lanes: largest first, each to the lane with the least d^3 so far
-    std::vector<int> by_size(np), lane_of(np, 0);
-    std::iota(by_size.begin(), by_size.end(), 0);
-    std::stable_sort(by_size.begin(), by_size.end(), [&](int a, int b) { return dim[a] > dim[b]; });
+    std::stable_sort(jobs.begin(), jobs.end(), [](const Job& x, const Job& y) { return x.d > y.d; });
+    std::vector<int> lane_of(nj, 0);
     double load[EIG_LANES] = {};
     int big[EIG_LANES] = {};
-    const int nl = std::min(lanes->n, std::max(np, 1));
-    for (int p : by_size) {
+    const int nl = std::min(lanes->n, std::max(nj, 1));
+    for (int j = 0; j < nj; ++j) {
         const int l = (int)(std::min_element(load, load + nl) - load);
-        lane_of[p] = l;
-        load[l] += (double)dim[p] * dim[p] * dim[p];
-        big[l] = std::max(big[l], dim[p]);
+        lane_of[j] = l;
+        load[l] += (double)jobs[j].d * jobs[j].d * jobs[j].d;
+        big[l] = std::max(big[l], jobs[j].d);
     }
-    auto syevd = [&](int p) {
-        return rocsolver_dsyevd(lanes->h[lane_of[p]], rocblas_evect_original, rocblas_fill_lower, dim[p],
-                                rho.p + roff[p], dim[p], ev.p + evoff[p], offd.p + evoff[p], info.p + p);
+    auto syevd = [&](int j) {
+        Half& h = *jobs[j].h;
+        const int p = jobs[j].p;
+        return rocsolver_dsyevd(lanes->h[lane_of[j]], rocblas_evect_original, rocblas_fill_lower, h.dim[p],
+                                h.rho.p + h.roff[p], h.dim[p], h.ev.p + h.evoff[p], h.offd.p + h.evoff[p],
+                                h.info.p + p);
     };
     // each lane's workspace, for the largest sector it gets, before any work is queued
     for (int l = 0; l < nl; ++l) {
-        int p0 = -1;
-        for (int p : by_size)
-            if (lane_of[p] == l) {
-                p0 = p;
+        int j0 = -1;
+        for (int j = 0; j < nj; ++j)
+            if (lane_of[j] == l) {
+                j0 = j;
                 break;
             }
-        if (p0 < 0) continue;
+        if (j0 < 0) continue;
         rocblas_handle h = lanes->h[l];
         if (rocblas_start_device_memory_size_query(h) != rocblas_status_success) {
             set_error("rocblas_start_device_memory_size_query failed");
             return D2D_EDEVICE;
         }
-        const rocblas_status q = syevd(p0);
+        const rocblas_status q = syevd(j0);
         size_t need = 0;
         if ((q != rocblas_status_size_increased && q != rocblas_status_size_unchanged &&
              q != rocblas_status_success) ||
@@ -257,12 +275,12 @@ static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_ke
     std::vector<int> failed(nl, -1);
     auto run_lane = [&](int l) {
         if (hipSetDevice(ctx->device) != hipSuccess) {
-            failed[l] = np;
+            failed[l] = nj;
             return;
         }
-        for (int p : by_size)
-            if (lane_of[p] == l && syevd(p) != rocblas_status_success) {
-                failed[l] = p;
+        for (int j = 0; j < nj; ++j)
+            if (lane_of[j] == l && syevd(j) != rocblas_status_success) {
+                failed[l] = j;
                 return;
             }
     };
@@ -284,8 +302,9 @@ static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_ke
     }
     for (int l = 0; l < nl; ++l)
         if (failed[l] >= 0) {
-            if (failed[l] == np) set_error("hipSetDevice(%d) failed in an eigensolver thread", ctx->device);
-            else set_error("rocsolver_dsyevd failed on sector %d (dim %d)", failed[l], dim[failed[l]]);
+            if (failed[l] == nj) set_error("hipSetDevice(%d) failed in an eigensolver thread", ctx->device);
+            else
+                set_error("rocsolver_dsyevd failed on sector %d (dim %d)", jobs[failed[l]].p, jobs[failed[l]].d);
             for (int k = 0; k < nl; ++k) (void)hipStreamSynchronize(lanes->s[k]);
             return D2D_EDEVICE;
         }
@@ -293,31 +312,41 @@ static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_ke
         D2D_HIP(hipEventRecord(lanes->done[l], lanes->s[l]));
         D2D_HIP(hipStreamWaitEvent(s, lanes->done[l], 0));
     }
-    std::vector<double> evh(nev);
-    std::vector<rocblas_int> infoh(np);
-    D2D_HIP(hipMemcpyAsync(evh.data(), ev.p, nev * 8, hipMemcpyDeviceToHost, s));
-    D2D_HIP(hipMemcpyAsync(infoh.data(), info.p, sizeof(rocblas_int) * np, hipMemcpyDeviceToHost, s));
+    std::vector<std::vector<rocblas_int>> infoh(hs.size());
+    for (size_t k = 0; k < hs.size(); ++k) {
+        Half& h = *hs[k];
+        h.evh.assign(h.nev, 0.0);
+        infoh[k].assign(h.np, 0);
+        D2D_HIP(hipMemcpyAsync(h.evh.data(), h.ev.p, h.nev * 8, hipMemcpyDeviceToHost, s));
+        D2D_HIP(hipMemcpyAsync(infoh[k].data(), h.info.p, sizeof(rocblas_int) * h.np, hipMemcpyDeviceToHost, s));
+    }
     D2D_HIP(hipStreamSynchronize(s));
-    for (int p = 0; p < np; ++p)
-        if (infoh[p] != 0) {
-            set_error("density-matrix eigensolve of sector %d (dim %d) did not converge (info %d)", p, dim[p],
-                      (int)infoh[p]);
-            return D2D_EDEVICE;
-        }
-    // selection: descending weight, ties by (sector ascending, index ascending);
-    // inside a sector rocSOLVER's order is ascending, so index i of the
-    // descending list is column dim-1-i.  Pairs are in ascending q_L, so on
-    // side 1 q_R = Q - q_L descends along them.
+    for (size_t k = 0; k < hs.size(); ++k)
+        for (int p = 0; p < hs[k]->np; ++p)
+            if (infoh[k][p] != 0) {
+                set_error("density-matrix eigensolve of sector %d (dim %d) did not converge (info %d)", p,
+                          hs[k]->dim[p], (int)infoh[k][p]);
+                return D2D_EDEVICE;
+            }
+    return D2D_OK;
+}
+
+// The kept states of a half: the m_keep eigenvectors of largest weight, ties
+// by (sector ascending, index ascending); inside a sector rocSOLVER's order is
+// ascending, so index i of the descending list is column dim-1-i.  Pairs are
+// in ascending q_L, so on side 1 q_R = Q - q_L descends along them.
+void half_select(Half& h, int m_keep, double* trunc_err, double* spectrum, int64_t* spectrum_len) {
+    const int np = h.np;
     std::vector<int> rank(np);
-    for (int p = 0; p < np; ++p) rank[p] = side == 0 ? p : np - 1 - p;
+    for (int p = 0; p < np; ++p) rank[p] = h.side == 0 ? p : np - 1 - p;
     struct Cand {
         double w;
         int p, i;
     };
     std::vector<Cand> cand;
-    cand.reserve(nev);
+    cand.reserve(h.nev);
     for (int p = 0; p < np; ++p)
-        for (int i = 0; i < dim[p]; ++i) cand.push_back({evh[evoff[p] + dim[p] - 1 - i], p, i});
+        for (int i = 0; i < h.dim[p]; ++i) cand.push_back({h.evh[h.evoff[p] + h.dim[p] - 1 - i], p, i});
     std::stable_sort(cand.begin(), cand.end(), [&](const Cand& a, const Cand& b) {
         if (a.w != b.w) return a.w > b.w;
         if (a.p != b.p) return rank[a.p] < rank[b.p];
@@ -329,17 +358,26 @@ static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_ke
             for (int64_t i = 0; i < cap && i < (int64_t)cand.size(); ++i) spectrum[i] = cand[i].w;
         *spectrum_len = (int64_t)cand.size();
     }
-    const int keep = (int)std::min<size_t>((size_t)m_keep, cand.size());
-    std::vector<std::vector<int>> kept(np);
+    h.keep = (int)std::min<size_t>((size_t)m_keep, cand.size());
+    h.kept.assign(np, {});
     double wsum = 0.0;
-    for (int k = 0; k < keep; ++k) {
-        kept[cand[k].p].push_back(cand[k].i);
+    for (int k = 0; k < h.keep; ++k) {
+        h.kept[cand[k].p].push_back(cand[k].i);
         wsum += cand[k].w;
     }
     *trunc_err = std::max(0.0, 1.0 - wsum);
-    const double t_dmd = seconds_since(t1);
-    auto t2 = std::chrono::steady_clock::now();
+}
 
+// Renormalisation: the new block of a half from its kept eigenvectors.
+d2d_status half_block(Half& h, d2d_block** new_block) {
+    d2d_sb* sb = h.sb;
+    d2d_ctx* ctx = sb->ctx;
+    hipStream_t s = ctx->stream;
+    const int side = h.side, np = h.np, keep = h.keep;
+    const std::vector<int>& dim = h.dim;
+    const std::vector<int64_t>& roff = h.roff;
+    DevBuf<double>& rho = h.rho;
+    std::vector<std::vector<int>>& kept = h.kept;
     // ---- renormalisation
     // the half's sectors in ascending quantum number: the pairs in order (side
     // 0) or in reverse order (side 1)
@@ -579,14 +617,70 @@ static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_ke
         nb->sec_dim.back()++;
     }
     nb->ncols = (side == 0 ? sb->ncols1 : sb->ncols4) + 1;
-    const double t_ren = seconds_since(t2);
+    ctx->children++;
+    *new_block = nb.release();
+    return D2D_OK;
+}
+
+}  // namespace
+
+static d2d_status density_impl(d2d_sb* sb, const double* psi, int side, int m_keep, d2d_block** new_block,
+                               double* trunc_err, double* spectrum, int64_t* spectrum_len, double* ms) {
+    if (!sb || !psi || !new_block || !trunc_err || (side != 0 && side != 1) || m_keep < 1) {
+        set_error("d2d_density_matrix: bad argument");
+        return D2D_EINVAL;
+    }
+    *new_block = nullptr;
+    D2D_HIP(hipStreamSynchronize(sb->ctx->stream));   // phases are timed from here
+    auto t0 = std::chrono::steady_clock::now();
+    Half h(sb, side);
+    D2D_CHECK(half_rho(h, psi));
+    const double t_dmf = seconds_since(t0);
+    auto t1 = std::chrono::steady_clock::now();
+    D2D_CHECK(halves_eig(sb->ctx, {&h}));
+    half_select(h, m_keep, trunc_err, spectrum, spectrum_len);
+    const double t_dmd = seconds_since(t1);
+    auto t2 = std::chrono::steady_clock::now();
+    D2D_CHECK(half_block(h, new_block));
     if (ms) {
         ms[0] = t_dmf * 1e3;
         ms[1] = t_dmd * 1e3;
-        ms[2] = t_ren * 1e3;
+        ms[2] = seconds_since(t2) * 1e3;
     }
-    ctx->children++;
-    *new_block = nb.release();
+    return D2D_OK;
+}
+
+extern "C" d2d_status d2d_density_matrix_both(d2d_sb* sb, const double* psi, int m_keep, d2d_block** new_left,
+                                              d2d_block** new_right, double trunc_err[2], double ms[3]) {
+    if (!sb || !psi || !new_left || !new_right || !trunc_err || m_keep < 1) {
+        set_error("d2d_density_matrix_both: bad argument");
+        return D2D_EINVAL;
+    }
+    *new_left = *new_right = nullptr;
+    D2D_HIP(hipStreamSynchronize(sb->ctx->stream));
+    auto t0 = std::chrono::steady_clock::now();
+    Half h0(sb, 0), h1(sb, 1);
+    D2D_CHECK(half_rho(h0, psi));
+    D2D_CHECK(half_rho(h1, psi));
+    const double t_dmf = seconds_since(t0);
+    auto t1 = std::chrono::steady_clock::now();
+    D2D_CHECK(halves_eig(sb->ctx, {&h0, &h1}));
+    half_select(h0, m_keep, &trunc_err[0], nullptr, nullptr);
+    half_select(h1, m_keep, &trunc_err[1], nullptr, nullptr);
+    const double t_dmd = seconds_since(t1);
+    auto t2 = std::chrono::steady_clock::now();
+    D2D_CHECK(half_block(h0, new_left));
+    const d2d_status st = half_block(h1, new_right);
+    if (st != D2D_OK) {
+        d2d_block_destroy(*new_left);
+        *new_left = nullptr;
+        return st;
+    }
+    if (ms) {
+        ms[0] = t_dmf * 1e3;
+        ms[1] = t_dmd * 1e3;
+        ms[2] = seconds_since(t2) * 1e3;
+    }
     return D2D_OK;
 }
 

@@ -103,6 +103,7 @@ _SIGS = {
     "d2d_density_matrix": (C.c_int, [P, P, C.c_int, C.c_int, C.POINTER(P), f64p, f64p, i64p]),
     "d2d_column_densities": (C.c_int, [P, P, f64p]),
     "d2d_density_matrix_timed": (C.c_int, [P, P, C.c_int, C.c_int, C.POINTER(P), f64p, f64p, i64p, f64p]),
+    "d2d_density_matrix_both": (C.c_int, [P, P, C.c_int, C.POINTER(P), C.POINTER(P), f64p, f64p]),
     "d2d_wavefunction_transform": (C.c_int, [P, P, P, P, C.c_int]),
     "d2d_batch_create": (C.c_int, [P, C.POINTER(P), C.c_int, C.POINTER(P)]),
     "d2d_batch_destroy": (C.c_int, [P]),
@@ -387,6 +388,17 @@ def d2d_density_matrix(sb: int, psi, side: int, m_keep: int, spectrum_cap: int =
                                      spec.ctypes.data_as(f64p) if spectrum_cap else None,
                                      n.ctypes.data_as(i64p)))
     return blk.value, te.value, (spec[: int(n[0])] if spectrum_cap else None)
+
+
+def d2d_density_matrix_both(sb: int, psi, m_keep: int):
+    """Both halves' new blocks at once: (left block, right block, truncation
+    errors (2,), milliseconds of the three phases (3,))."""
+    bl, br = P(), P()
+    te = np.zeros(2)
+    ms = np.zeros(3)
+    _check(load().d2d_density_matrix_both(P(sb), P(_ptr(psi)), int(m_keep), C.byref(bl), C.byref(br),
+                                          te.ctypes.data_as(f64p), ms.ctypes.data_as(f64p)))
+    return bl.value, br.value, te, ms
 
 
 def d2d_density_matrix_timed(sb: int, psi, side: int, m_keep: int, spectrum_cap: int = 0):

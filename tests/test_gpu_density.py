@@ -97,3 +97,31 @@ def test_density_matrix_and_next_block(ctx, name, target_m):
         e_or = np.linalg.eigvalsh(Superblock(blocks[0][1], blocks[1][1], Q2).explicit().toarray())[0]
         assert abs(e_gpu - e_or) <= 1e-10 * abs(e_or)
     prob.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", [W.HUBBARD_2X16_M256.name, W.HEISENBERG_4X16_M1000.name])
+def test_both_halves_equal_two_calls(ctx, name):
+    """d2d_density_matrix_both gives both halves' blocks and truncation errors
+    bit for bit as two d2d_density_matrix calls (the eigensolves of the two
+    halves share the streams; each sector's is the same computation)."""
+    from paper_0707_0159_amd import d2d
+    wl = W.WORKLOADS[name]
+    prob = GpuProblem(ctx, wl)
+    psi = ground_state(ctx, prob, wl.seed)
+    single = []
+    for side in (0, 1):
+        blk, te, _ = d2d.d2d_density_matrix(prob.sb, psi, side, wl.m)
+        single.append((d2d.d2d_block_export(blk), te))
+        d2d.d2d_block_destroy(blk)
+    bl, br, te2, ms = d2d.d2d_density_matrix_both(prob.sb, psi, wl.m)
+    print(f"{name}: both halves in {ms[0]:.2f} + {ms[1]:.2f} + {ms[2]:.2f} ms")
+    for side, blk in ((0, bl), (1, br)):
+        ex = d2d.d2d_block_export(blk)
+        ref, te = single[side]
+        assert te2[side] == te
+        assert set(ex) == set(ref)
+        for k in ref:
+            assert np.array_equal(np.asarray(ex[k]), np.asarray(ref[k])), (side, k)
+        d2d.d2d_block_destroy(blk)
+    prob.close()
