@@ -8,7 +8,7 @@ calls and keeps the blocks.
   the superblock of two k-column blocks and two columns is solved for the
   target of its 2k + 2 columns (d2d_lanczos from the library's seeded start
   vector) and both enlarged halves become the next blocks
-  (d2d_density_matrix, m_keep states).
+  (d2d_density_matrix_both, m_keep states).
 * Finite phase on L columns, position l = the left block's columns: solve
   (started from the transformed state of the previous position), make the
   block on the side the sweep moves to, create the next superblock and carry
@@ -82,8 +82,9 @@ def finite_sweeps(ctx, model, L: int, m_keep: int, target_of_sites, l_min: int, 
             with torch.cuda.stream(s):
                 psi = torch.zeros(N, dtype=torch.float64, device="cuda")
             st, e, stats = d2d.d2d_lanczos(sb, opts, None, psi)
-            left[k + 1], tl, _ = d2d.d2d_density_matrix(sb, psi, 0, m_keep)
-            right[k + 1], tr, _ = d2d.d2d_density_matrix(sb, psi, 1, m_keep)
+            # both halves grow: one call, their eigensolves sharing the streams
+            left[k + 1], right[k + 1], te, _ = d2d.d2d_density_matrix_both(sb, psi, m_keep)
+            tl, tr = float(te[0]), float(te[1])
             blocks += [left[k + 1], right[k + 1]]
             inf_recs.append(dict(block_cols=k, N=N, energy=e, trunc_left=tl, trunc_right=tr,
                                  hv_count=list(stats["hv_count"]), status=st))
