@@ -114,6 +114,8 @@ def test_both_halves_equal_two_calls(ctx, name):
         blk, te, _ = d2d.d2d_density_matrix(prob.sb, psi, side, wl.m)
         single.append((d2d.d2d_block_export(blk), te))
         d2d.d2d_block_destroy(blk)
+    with pytest.raises(RuntimeError):
+        d2d.d2d_density_matrix_both(prob.sb, psi, 0)      # m_keep < 1: D2D_EINVAL, no block made
     bl, br, te2, ms = d2d.d2d_density_matrix_both(prob.sb, psi, wl.m)
     print(f"{name}: both halves in {ms[0]:.2f} + {ms[1]:.2f} + {ms[2]:.2f} ms")
     for side, blk in ((0, bl), (1, br)):
